@@ -1,0 +1,236 @@
+/*
+ * fastergs.h -- C ABI of the MI355X (gfx950) training-step library for 3D
+ * Gaussian Splatting: differentiable tile-based rasterization (forward and
+ * backward) and a fused Adam update, after Faster-GS (Hahlbohm et al.,
+ * arXiv 2602.09999).
+ *
+ * Conventions (all entry points):
+ *  - Every pointer is a DEVICE pointer unless marked (host).  All buffers
+ *    belong to the caller.  The library allocates no device memory and keeps
+ *    no state between calls; the workspace is a caller-owned byte buffer.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t, NULL = the
+ *    default stream).  fgs_rasterize_forward alone synchronises `stream` once
+ *    to read the instance count (see there).
+ *  - Arguments are validated before anything is launched; an invalid call
+ *    returns FGS_ERR_INVALID_ARGUMENT (or FGS_ERR_UNSUPPORTED for a valid
+ *    but unimplemented option) and enqueues nothing.  HIP runtime failures
+ *    return FGS_ERR_HIP.  fgs_last_error() gives a thread-local message.
+ *  - Layouts are structure-of-arrays, float32, index i of Gaussian i in
+ *    every plane ("[k][n]" = k planes of n floats, plane-major).
+ *  - Entry points are re-entrant; calls that share a workspace must not
+ *    overlap.  No exception crosses the ABI.
+ */
+#ifndef FASTERGS_H
+#define FASTERGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FGS_ABI_VERSION 1
+
+typedef enum fgs_status {
+  FGS_OK = 0,
+  FGS_ERR_INVALID_ARGUMENT = 1,
+  FGS_ERR_CAPACITY = 2,    /* instance buffers too small; see fgs_rasterize_forward */
+  FGS_ERR_HIP = 3,
+  FGS_ERR_UNSUPPORTED = 4
+} fgs_status;
+
+typedef enum fgs_dtype { FGS_F32 = 0, FGS_BF16 = 1 } fgs_dtype;
+
+/* The Gaussian parameters of Sec. 2.1 ("3D Gaussian Splatting"): mean mu,
+ * log-scales (scale = exp, "Activation Functions"), rotation quaternion
+ * (w, x, y, z; normalised before use), opacity logit (opacity = sigmoid) and
+ * degree-3 SH colour coefficients, with the DC band and the 15 higher bands
+ * in separate buffers (Sec. 3.2, "Rasterization Kernel Fusion").
+ *   means          [3][n]   world-space x, y, z planes
+ *   log_scales     [3][n]
+ *   quats          [4][n]   w, x, y, z planes (need not be normalised)
+ *   opacity_logits [n]
+ *   sh_dc          [3][n]   plane c = colour channel c
+ *   sh_rest        [45][n]  plane (k-1)*3 + c for SH index k = 1..15
+ * sh_dtype must be FGS_F32; sh_degree in 0..3 (planes beyond the degree are
+ * not read). n may be 0.                                                    */
+typedef struct fgs_gaussians {
+  int64_t n;
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opacity_logits;
+  const void* sh_dc;
+  const void* sh_rest;
+  int32_t sh_dtype;
+  int32_t sh_degree;
+} fgs_gaussians;
+
+/* Gradient planes with the layout of fgs_gaussians (all written in full). */
+typedef struct fgs_gaussian_grads {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* opacity_logits;
+  void* sh_dc;
+  void* sh_rest;
+} fgs_gaussian_grads;
+
+/* Pinhole camera of Eq. (1)-(2).  (host struct)
+ * world_to_cam: W, row-major 4x4 (only rows 0-2 are used).  fx, fy, cx, cy:
+ * intrinsics in pixels; pixel (i, j) is sampled at (i + 0.5, j + 0.5).
+ * near_z: Gaussians with camera-space z below it are not rendered.
+ * bg: background colour c_bg of Eq. (4).                                    */
+typedef struct fgs_camera {
+  float world_to_cam[16];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float near_z;
+  float bg[3];
+} fgs_camera;
+
+/* Thresholds (host struct).  Defaults from fgs_default_settings:
+ *   tile 16 (16x16 pixel tiles, Sec. 3.1)
+ *   alpha_min 1/255  (skip fragments below it, Sec. 3.2 "Splat Bounding")
+ *   alpha_max 0.99   (alpha cap, App. B.1)
+ *   t_min 1e-4       (stop once the transmittance falls below it, App. B.1)
+ *   dilation 0.3     (Sigma2D + 0.3 I, App. C.2)
+ *   quat_min 1e-4, det_min 1e-6 (degenerate-Gaussian guard, App. B.1)
+ * Only tile = 16 is implemented (others: FGS_ERR_UNSUPPORTED).              */
+typedef struct fgs_settings {
+  int32_t tile;
+  float alpha_min;
+  float alpha_max;
+  float t_min;
+  float dilation;
+  float quat_min;
+  float det_min;
+  uint32_t flags; /* reserved: must be 0 */
+} fgs_settings;
+
+/* Filled by fgs_rasterize_forward when non-NULL (host struct). */
+typedef struct fgs_forward_stats {
+  int64_t n_visible;    /* Gaussians with at least one tile instance        */
+  int64_t n_instances;  /* (tile, Gaussian) instances I                     */
+  int64_t tiles_x, tiles_y;
+} fgs_forward_stats;
+
+/* Byte offsets of the workspace regions (host struct), for inspection.
+ * All regions are 256-byte aligned.  The forward pass leaves there:
+ *   rec        float4[3*n]  per-Gaussian splat record, Gaussian order:
+ *                           {mu2D.x, mu2D.y, opacity, 2 ln(opacity/alpha_min)},
+ *                           {conic a, b, c (inverse of the dilated Sigma2D
+ *                            [[a,b],[b,c]]), camera z}, {r, g, b, flags}
+ *   rect       uint32[2*n]  tile rectangle: (tx0 | ty0<<16, tx1 | ty1<<16)
+ *   n_tiles    uint32[n]    instances per Gaussian (0 = not rendered)
+ *   depth_key  uint32[n]    bits of the FP32 camera z
+ *   counters   uint32[16]   [0] visible count, [1] instance count I
+ *   vis_ids    uint32[n] x2 ping-pong; sorted visible ids in vis_ids[vis_final]
+ *   inst_keys  uint32[cap] x2, inst_vals uint32[cap] x2: tile ids and
+ *                           Gaussian ids; sorted in [inst_final]
+ *   ranges     uint32[2*tiles] [start, end) of each tile's list
+ *   accum      float[9][n]  backward: dL/d(mu2D.x, mu2D.y, a, b, c, opacity, r, g, b) */
+typedef struct fgs_layout {
+  size_t rec, rect, n_tiles, depth_key, counters;
+  size_t vis_keys[2], vis_ids[2];
+  size_t inst_offsets;
+  size_t inst_keys[2], inst_vals[2];
+  size_t ranges, accum, scratch, total;
+  int32_t vis_final, inst_final;
+  int32_t tiles_x, tiles_y;
+  int64_t instance_capacity;
+} fgs_layout;
+
+/* One Adam parameter group (host struct). param, exp_avg and exp_avg_sq are
+ * float32 [numel]; grad is float32 [numel].  lr: this group's learning rate. */
+typedef struct fgs_adam_group {
+  float* param;
+  const float* grad;
+  float* exp_avg;
+  float* exp_avg_sq;
+  int64_t numel;
+  float lr;
+  int32_t dtype; /* FGS_F32 */
+} fgs_adam_group;
+
+int32_t fgs_abi_version(void);
+const char* fgs_status_string(fgs_status s);
+/* Message of the last failing call on this thread ("" if none). */
+const char* fgs_last_error(void);
+
+/* Fills *out (host) with the defaults listed at fgs_settings. */
+fgs_status fgs_default_settings(fgs_settings* out);
+
+/* Workspace size in bytes (host *bytes) for n Gaussians, one camera, and
+ * room for `instance_capacity` (tile, Gaussian) instances. */
+fgs_status fgs_workspace_size(int64_t n, const fgs_camera* cam, const fgs_settings* st,
+                              int64_t instance_capacity, size_t* bytes);
+
+/* Region offsets of that workspace (host *out). */
+fgs_status fgs_workspace_layout(int64_t n, const fgs_camera* cam, const fgs_settings* st,
+                                int64_t instance_capacity, fgs_layout* out);
+
+/* Forward rasterization of one view (Sec. 2.1 Eq. (1)-(4); Sec. 3.2 "Splat
+ * Bounding", "Tile-based Culling", "Sorting"; App. B.1-B.2):
+ *  1. per Gaussian: activations, EWA projection to the dilated 2D conic,
+ *     SH colour (clipped at 0), culling, opacity-aware tile rectangle, exact
+ *     per-tile test, depth key;
+ *  2. compaction of the visible Gaussians and a 32-bit radix sort by depth
+ *     (stable, so depth ties keep index order);
+ *  3. duplication into (tile, Gaussian) instances and a stable radix sort by
+ *     tile -- per-tile lists in (depth key, index) order -- and tile ranges;
+ *  4. per tile, front-to-back blending with the 0.99 alpha cap, the
+ *     alpha_min skip and termination once T < t_min (blend, then check).
+ * Outputs (caller-allocated):
+ *   image   float[3][height][width]  colour incl. T_final * bg, not clipped
+ *   t_final float[height][width]     transmittance after the last fragment (nullable)
+ *   last    uint32[height][width]    1 + position, in the pixel's tile list, of
+ *                                    the last blended fragment (0 = none);
+ *                                    required by fgs_rasterize_backward
+ *   stats   (host, nullable)
+ * The workspace must hold fgs_workspace_size(n, cam, st, instance_capacity)
+ * bytes and is read again by fgs_rasterize_backward.  The call synchronises
+ * `stream` once, after the depth sort, to read I.  If I > instance_capacity
+ * it returns FGS_ERR_CAPACITY with stats->n_instances = I, having written no
+ * image; grow the workspace and call again. */
+fgs_status fgs_rasterize_forward(const fgs_gaussians* g, const fgs_camera* cam,
+                                 const fgs_settings* st, void* workspace, size_t workspace_bytes,
+                                 int64_t instance_capacity, float* image, float* t_final,
+                                 uint32_t* last, fgs_forward_stats* stats, void* stream);
+
+/* Backward pass of fgs_rasterize_forward (Sec. 3.2 "Per-Gaussian Backward",
+ * App. B.1 front-to-back gradients, App. B.3): each tile is walked again in
+ * the same order up to its last blended fragment, per-fragment gradients of
+ * the loss w.r.t. mu2D, the conic, opacity and colour are reduced across the
+ * pixels of a wavefront and accumulated per Gaussian, then chained back to
+ * the raw parameters through the activations (Sec. 3.2 "Rasterization Kernel
+ * Fusion").  Inputs: the same g, cam, st and workspace as the forward call
+ * (unchanged since), its `image` and `last`, and dl_dimage float[3][h][w].
+ * Output: every plane of *grads (host struct of device pointers) is written
+ * in full; Gaussians that received no gradient get zeros. */
+fgs_status fgs_rasterize_backward(const fgs_gaussians* g, const fgs_camera* cam,
+                                  const fgs_settings* st, void* workspace, size_t workspace_bytes,
+                                  int64_t instance_capacity, const float* image,
+                                  const uint32_t* last, const float* dl_dimage,
+                                  const fgs_gaussian_grads* grads, void* stream);
+
+/* Fused Adam over several parameter groups in one launch (Sec. 3.3
+ * "Parameter Updates"; hyperparameters App. A): for every element,
+ *   m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2;
+ *   p <- p - lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps),
+ * including elements whose gradient is zero.  groups: host array of
+ * n_groups (1..16) descriptors; step t >= 1. */
+fgs_status fgs_adam_step(const fgs_adam_group* groups, int32_t n_groups, int64_t step,
+                         float beta1, float beta2, float eps, void* stream);
+
+/* L1 loss term of Sec. 2.1 / App. A: dl_dimage[i] = sign(image[i] - target[i]) / n
+ * (sign(0) = 0) for i < n; when loss (device double, nullable) is given, it
+ * receives mean |image - target| reduced in float64. */
+fgs_status fgs_l1_loss_backward(const float* image, const float* target, int64_t n,
+                                float* dl_dimage, double* loss, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FASTERGS_H */

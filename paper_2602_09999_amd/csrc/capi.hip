@@ -1,0 +1,371 @@
+// C ABI entry points (include/fastergs.h): argument validation, workspace
+// layout and the launch sequence of one forward / backward rasterization.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "fgs_internal.h"
+
+using namespace fgs;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fgs_status fail(fgs_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+fgs_status fail(fgs_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+fgs_status hip_fail(hipError_t e, const char* where) {
+  return fail(FGS_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define FGS_HIP(expr, where)                     \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
+
+int tile_key_bits(uint64_t tiles) {
+  int b = 1;
+  while (b < 32 && (uint64_t(1) << b) < tiles) ++b;
+  return b;
+}
+
+fgs_status check_camera(const fgs_camera* cam) {
+  if (!cam) return fail(FGS_ERR_INVALID_ARGUMENT, "camera is NULL");
+  if (cam->width <= 0 || cam->height <= 0)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "image size %dx%d must be positive", cam->width, cam->height);
+  if ((int64_t)cam->width * cam->height > (int64_t(1) << 30))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "image of %dx%d pixels exceeds 2^30 pixels", cam->width, cam->height);
+  if (!finite_pos(cam->fx) || !finite_pos(cam->fy))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "focal lengths must be finite and positive");
+  if (!std::isfinite(cam->cx) || !std::isfinite(cam->cy) || !std::isfinite(cam->near_z))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "principal point and near plane must be finite");
+  for (int k = 0; k < 12; ++k)
+    if (!std::isfinite(cam->world_to_cam[k]))
+      return fail(FGS_ERR_INVALID_ARGUMENT, "world_to_cam[%d] is not finite", k);
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(cam->bg[k])) return fail(FGS_ERR_INVALID_ARGUMENT, "bg[%d] is not finite", k);
+  return FGS_OK;
+}
+
+fgs_status check_settings(const fgs_settings* st) {
+  if (!st) return fail(FGS_ERR_INVALID_ARGUMENT, "settings is NULL");
+  if (st->tile != 8 && st->tile != 16 && st->tile != 32)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "tile must be 8, 16 or 32 (got %d)", st->tile);
+  if (st->tile != 16) return fail(FGS_ERR_UNSUPPORTED, "tile %d is not implemented; use 16", st->tile);
+  if (st->flags != 0) return fail(FGS_ERR_INVALID_ARGUMENT, "settings.flags must be 0");
+  if (!(st->alpha_min > 0.0f && st->alpha_min < st->alpha_max && st->alpha_max <= 1.0f))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "need 0 < alpha_min < alpha_max <= 1");
+  if (!(st->t_min > 0.0f && st->t_min < 1.0f)) return fail(FGS_ERR_INVALID_ARGUMENT, "need 0 < t_min < 1");
+  if (!(st->dilation >= 0.0f && std::isfinite(st->dilation)))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "dilation must be finite and >= 0");
+  if (!(st->quat_min >= 0.0f && std::isfinite(st->quat_min)) || !(st->det_min >= 0.0f && std::isfinite(st->det_min)))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "quat_min and det_min must be finite and >= 0");
+  return FGS_OK;
+}
+
+fgs_status check_gaussians(const fgs_gaussians* g) {
+  if (!g) return fail(FGS_ERR_INVALID_ARGUMENT, "gaussians is NULL");
+  if (g->n < 0 || g->n > INT32_MAX) return fail(FGS_ERR_INVALID_ARGUMENT, "n = %lld out of range", (long long)g->n);
+  if (g->sh_dtype != FGS_F32 && g->sh_dtype != FGS_BF16)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "unknown sh_dtype %d", g->sh_dtype);
+  if (g->sh_dtype != FGS_F32) return fail(FGS_ERR_UNSUPPORTED, "only float32 SH coefficients are implemented");
+  if (g->sh_degree < 0 || g->sh_degree > 3)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "sh_degree %d not in 0..3", g->sh_degree);
+  if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh_dc ||
+                   (g->sh_degree > 0 && !g->sh_rest)))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "a parameter pointer is NULL");
+  return FGS_OK;
+}
+
+fgs_status make_layout(int64_t n, const fgs_camera* cam, const fgs_settings* st, int64_t cap, fgs_layout* L) {
+  if (n < 0 || n > INT32_MAX) return fail(FGS_ERR_INVALID_ARGUMENT, "n = %lld out of range", (long long)n);
+  if (cap < 0 || cap > (int64_t)UINT32_MAX - 1)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "instance_capacity = %lld out of range", (long long)cap);
+  fgs_status s = check_camera(cam);
+  if (s != FGS_OK) return s;
+  s = check_settings(st);
+  if (s != FGS_OK) return s;
+  const int t = st->tile;
+  const int64_t tx = (cam->width + t - 1) / t, ty = (cam->height + t - 1) / t;
+  if (tx > 65535 || ty > 65535) return fail(FGS_ERR_INVALID_ARGUMENT, "tile grid too large");
+  std::memset(L, 0, sizeof(*L));
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  const size_t un = (size_t)n, uc = (size_t)cap, tiles = (size_t)(tx * ty);
+  L->rec = take(un * 48);
+  L->rect = take(un * 8);
+  L->n_tiles = take(un * 4);
+  L->depth_key = take(un * 4);
+  L->counters = take(64);
+  L->vis_keys[0] = take(un * 4);
+  L->vis_keys[1] = take(un * 4);
+  L->vis_ids[0] = take(un * 4);
+  L->vis_ids[1] = take(un * 4);
+  L->inst_offsets = take((un + 1) * 4);
+  L->inst_keys[0] = take(uc * 4);
+  L->inst_keys[1] = take(uc * 4);
+  L->inst_vals[0] = take(uc * 4);
+  L->inst_vals[1] = take(uc * 4);
+  L->ranges = take(tiles * 8);
+  L->accum = take(un * 9 * 4);
+  size_t words = scan_scratch_words(un);
+  words = std::max(words, radix_scratch_words(un));
+  words = std::max(words, radix_scratch_words(uc));
+  L->scratch = take(words * 4 + 256);
+  L->total = off;
+  L->vis_final = 0;  // the 32-bit depth sort takes 4 passes
+  L->inst_final = ((tile_key_bits((uint64_t)tiles) + kRadixBits - 1) / kRadixBits) & 1;
+  L->tiles_x = (int32_t)tx;
+  L->tiles_y = (int32_t)ty;
+  L->instance_capacity = cap;
+  return FGS_OK;
+}
+
+CamDev make_cam(const fgs_camera* c, const fgs_layout& L) {
+  CamDev d;
+  for (int k = 0; k < 12; ++k) d.w[k] = c->world_to_cam[k];
+  // camera centre -W3^T t, computed in double and rounded once
+  for (int k = 0; k < 3; ++k) {
+    double v = 0.0;
+    for (int r = 0; r < 3; ++r) v -= (double)c->world_to_cam[4 * r + k] * (double)c->world_to_cam[4 * r + 3];
+    d.campos[k] = (float)v;
+  }
+  d.fx = c->fx; d.fy = c->fy; d.cx = c->cx; d.cy = c->cy;
+  d.width = c->width; d.height = c->height;
+  d.tiles_x = L.tiles_x; d.tiles_y = L.tiles_y;
+  d.near_z = c->near_z;
+  for (int k = 0; k < 3; ++k) d.bg[k] = c->bg[k];
+  return d;
+}
+
+SetDev make_set(const fgs_settings* s) {
+  return SetDev{s->alpha_min, s->alpha_max, s->t_min, s->dilation, s->quat_min, s->det_min};
+}
+
+GaussDev make_gauss(const fgs_gaussians* g) {
+  GaussDev d;
+  d.means = g->means;
+  d.log_scales = g->log_scales;
+  d.quats = g->quats;
+  d.logits = g->opacity_logits;
+  d.sh_dc = static_cast<const float*>(g->sh_dc);
+  d.sh_rest = static_cast<const float*>(g->sh_rest);
+  d.n = (uint32_t)g->n;
+  d.sh_coeffs = (g->sh_degree + 1) * (g->sh_degree + 1);
+  return d;
+}
+
+template <typename T>
+T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t fgs_abi_version(void) { return FGS_ABI_VERSION; }
+
+const char* fgs_status_string(fgs_status s) {
+  switch (s) {
+    case FGS_OK: return "ok";
+    case FGS_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case FGS_ERR_CAPACITY: return "instance capacity exceeded";
+    case FGS_ERR_HIP: return "HIP runtime error";
+    case FGS_ERR_UNSUPPORTED: return "unsupported option";
+  }
+  return "unknown status";
+}
+
+const char* fgs_last_error(void) { return g_last_error.c_str(); }
+
+fgs_status fgs_default_settings(fgs_settings* out) {
+  if (!out) return fail(FGS_ERR_INVALID_ARGUMENT, "out is NULL");
+  out->tile = 16;
+  out->alpha_min = 1.0f / 255.0f;
+  out->alpha_max = 0.99f;
+  out->t_min = 1e-4f;
+  out->dilation = 0.3f;
+  out->quat_min = 1e-4f;
+  out->det_min = 1e-6f;
+  out->flags = 0;
+  return FGS_OK;
+}
+
+fgs_status fgs_workspace_size(int64_t n, const fgs_camera* cam, const fgs_settings* st, int64_t instance_capacity,
+                              size_t* bytes) {
+  if (!bytes) return fail(FGS_ERR_INVALID_ARGUMENT, "bytes is NULL");
+  fgs_layout L;
+  fgs_status s = make_layout(n, cam, st, instance_capacity, &L);
+  if (s != FGS_OK) return s;
+  *bytes = L.total;
+  return FGS_OK;
+}
+
+fgs_status fgs_workspace_layout(int64_t n, const fgs_camera* cam, const fgs_settings* st, int64_t instance_capacity,
+                                fgs_layout* out) {
+  if (!out) return fail(FGS_ERR_INVALID_ARGUMENT, "out is NULL");
+  return make_layout(n, cam, st, instance_capacity, out);
+}
+
+fgs_status fgs_rasterize_forward(const fgs_gaussians* g, const fgs_camera* cam, const fgs_settings* st,
+                                 void* workspace, size_t workspace_bytes, int64_t instance_capacity, float* image,
+                                 float* t_final, uint32_t* last, fgs_forward_stats* stats, void* stream) {
+  fgs_status s = check_gaussians(g);
+  if (s != FGS_OK) return s;
+  fgs_layout L;
+  s = make_layout(g->n, cam, st, instance_capacity, &L);
+  if (s != FGS_OK) return s;
+  if (!workspace) return fail(FGS_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (workspace_bytes < L.total)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "workspace holds %zu bytes, %zu needed", workspace_bytes, L.total);
+  if (!image || !last) return fail(FGS_ERR_INVALID_ARGUMENT, "image and last are required");
+
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const GaussDev gd = make_gauss(g);
+  const CamDev cd = make_cam(cam, L);
+  const SetDev sd = make_set(st);
+  const uint32_t n = gd.n;
+  float4* rec = at<float4>(workspace, L.rec);
+  uint2* rect = at<uint2>(workspace, L.rect);
+  uint32_t* n_tiles = at<uint32_t>(workspace, L.n_tiles);
+  uint32_t* depth_key = at<uint32_t>(workspace, L.depth_key);
+  uint32_t* counters = at<uint32_t>(workspace, L.counters);
+  uint32_t* vis_keys[2] = {at<uint32_t>(workspace, L.vis_keys[0]), at<uint32_t>(workspace, L.vis_keys[1])};
+  uint32_t* vis_ids[2] = {at<uint32_t>(workspace, L.vis_ids[0]), at<uint32_t>(workspace, L.vis_ids[1])};
+  uint32_t* offsets = at<uint32_t>(workspace, L.inst_offsets);
+  uint32_t* ikeys[2] = {at<uint32_t>(workspace, L.inst_keys[0]), at<uint32_t>(workspace, L.inst_keys[1])};
+  uint32_t* ivals[2] = {at<uint32_t>(workspace, L.inst_vals[0]), at<uint32_t>(workspace, L.inst_vals[1])};
+  uint2* ranges = at<uint2>(workspace, L.ranges);
+  uint32_t* scratch = at<uint32_t>(workspace, L.scratch);
+
+  uint32_t host_counts[2] = {0, 0};
+  if (n > 0) {
+    FGS_HIP(launch_preprocess(gd, cd, sd, st->tile, rec, rect, n_tiles, depth_key, hs), "preprocess");
+    // visible compaction (prefix sum, so index order is kept) and the depth sort
+    FGS_HIP(scan_u32(SCAN_NONZERO, n_tiles, nullptr, nullptr, offsets, n, counters + 0, scratch, hs), "scan");
+    FGS_HIP(launch_compact_visible(n_tiles, depth_key, n, offsets, vis_keys[0], vis_ids[0], hs), "compact");
+    int vis_final = 0;
+    FGS_HIP(radix_sort_pairs(vis_keys, vis_ids, n, counters + 0, 0, 32, scratch, &vis_final, hs), "depth sort");
+    if (vis_final != L.vis_final) return fail(FGS_ERR_HIP, "internal: depth sort buffer mismatch");
+    // instance offsets in depth order; I = total
+    FGS_HIP(scan_u32(SCAN_GATHER, n_tiles, vis_ids[vis_final], counters + 0, offsets, n, counters + 1, scratch, hs),
+            "offset scan");
+    FGS_HIP(hipMemcpyAsync(host_counts, counters, sizeof(host_counts), hipMemcpyDeviceToHost, hs), "count copy");
+    FGS_HIP(hipStreamSynchronize(hs), "count sync");
+  }
+  const uint32_t nvis = host_counts[0], inst = host_counts[1];
+  if (stats) {
+    stats->n_visible = nvis;
+    stats->n_instances = inst;
+    stats->tiles_x = L.tiles_x;
+    stats->tiles_y = L.tiles_y;
+  }
+  if ((int64_t)inst > instance_capacity)
+    return fail(FGS_ERR_CAPACITY, "%u instances exceed the capacity of %lld", inst, (long long)instance_capacity);
+
+  const size_t tiles = (size_t)L.tiles_x * L.tiles_y;
+  FGS_HIP(hipMemsetAsync(ranges, 0, tiles * sizeof(uint2), hs), "ranges clear");
+  if (inst > 0) {
+    FGS_HIP(launch_duplicate(vis_ids[L.vis_final], counters + 0, n, offsets, rec, rect, n_tiles, cd, st->tile,
+                             (uint32_t)instance_capacity, ikeys[0], ivals[0], hs),
+            "duplicate");
+    int inst_final = 0;
+    FGS_HIP(radix_sort_pairs(ikeys, ivals, inst, nullptr, 0, tile_key_bits(tiles), scratch, &inst_final, hs),
+            "tile sort");
+    if (inst_final != L.inst_final) return fail(FGS_ERR_HIP, "internal: tile sort buffer mismatch");
+    FGS_HIP(launch_tile_ranges(ikeys[inst_final], inst, (uint32_t)tiles, ranges, hs), "tile ranges");
+  }
+  FGS_HIP(launch_blend_forward(ranges, ivals[L.inst_final], rec, cd, sd, image, t_final, last, hs), "blend");
+  return FGS_OK;
+}
+
+fgs_status fgs_rasterize_backward(const fgs_gaussians* g, const fgs_camera* cam, const fgs_settings* st,
+                                  void* workspace, size_t workspace_bytes, int64_t instance_capacity,
+                                  const float* image, const uint32_t* last, const float* dl_dimage,
+                                  const fgs_gaussian_grads* grads, void* stream) {
+  fgs_status s = check_gaussians(g);
+  if (s != FGS_OK) return s;
+  fgs_layout L;
+  s = make_layout(g->n, cam, st, instance_capacity, &L);
+  if (s != FGS_OK) return s;
+  if (!workspace) return fail(FGS_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (workspace_bytes < L.total)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "workspace holds %zu bytes, %zu needed", workspace_bytes, L.total);
+  if (!image || !last || !dl_dimage) return fail(FGS_ERR_INVALID_ARGUMENT, "image, last and dl_dimage are required");
+  if (!grads) return fail(FGS_ERR_INVALID_ARGUMENT, "grads is NULL");
+  if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits ||
+                   !grads->sh_dc || !grads->sh_rest))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "a gradient pointer is NULL");
+  if (g->n == 0) return FGS_OK;
+
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const GaussDev gd = make_gauss(g);
+  const CamDev cd = make_cam(cam, L);
+  const SetDev sd = make_set(st);
+  float4* rec = at<float4>(workspace, L.rec);
+  uint2* ranges = at<uint2>(workspace, L.ranges);
+  uint32_t* ivals = at<uint32_t>(workspace, L.inst_vals[L.inst_final]);
+  float* accum = at<float>(workspace, L.accum);
+  FGS_HIP(hipMemsetAsync(accum, 0, (size_t)gd.n * 9 * sizeof(float), hs), "accum clear");
+  FGS_HIP(launch_blend_backward(ranges, ivals, rec, cd, sd, image, last, dl_dimage, accum, gd.n, hs), "blend bwd");
+  GradDev gr;
+  gr.means = grads->means;
+  gr.log_scales = grads->log_scales;
+  gr.quats = grads->quats;
+  gr.logits = grads->opacity_logits;
+  gr.sh_dc = static_cast<float*>(grads->sh_dc);
+  gr.sh_rest = static_cast<float*>(grads->sh_rest);
+  FGS_HIP(launch_preprocess_backward(gd, cd, sd, rec, accum, gr, hs), "preprocess bwd");
+  return FGS_OK;
+}
+
+fgs_status fgs_adam_step(const fgs_adam_group* groups, int32_t n_groups, int64_t step, float beta1, float beta2,
+                         float eps, void* stream) {
+  if (!groups) return fail(FGS_ERR_INVALID_ARGUMENT, "groups is NULL");
+  if (n_groups < 1 || n_groups > 16) return fail(FGS_ERR_INVALID_ARGUMENT, "n_groups %d not in 1..16", n_groups);
+  if (step < 1) return fail(FGS_ERR_INVALID_ARGUMENT, "step must be >= 1");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "betas must lie in [0, 1)");
+  if (!(eps >= 0.0f) || !std::isfinite(eps)) return fail(FGS_ERR_INVALID_ARGUMENT, "eps must be finite, >= 0");
+  for (int k = 0; k < n_groups; ++k) {
+    const fgs_adam_group& G = groups[k];
+    if (G.numel < 0) return fail(FGS_ERR_INVALID_ARGUMENT, "group %d: numel < 0", k);
+    if (G.dtype != FGS_F32) return fail(FGS_ERR_UNSUPPORTED, "group %d: only float32 parameters", k);
+    if (G.numel > 0 && (!G.param || !G.grad || !G.exp_avg || !G.exp_avg_sq))
+      return fail(FGS_ERR_INVALID_ARGUMENT, "group %d: NULL pointer", k);
+    if (!std::isfinite(G.lr)) return fail(FGS_ERR_INVALID_ARGUMENT, "group %d: lr not finite", k);
+  }
+  FGS_HIP(launch_adam(groups, n_groups, step, beta1, beta2, eps, static_cast<hipStream_t>(stream)), "adam");
+  return FGS_OK;
+}
+
+fgs_status fgs_l1_loss_backward(const float* image, const float* target, int64_t n, float* dl_dimage, double* loss,
+                                void* stream) {
+  if (n < 0 || n > UINT32_MAX) return fail(FGS_ERR_INVALID_ARGUMENT, "n out of range");
+  if (n > 0 && (!image || !target || !dl_dimage)) return fail(FGS_ERR_INVALID_ARGUMENT, "NULL pointer");
+  FGS_HIP(launch_l1_backward(image, target, (uint32_t)n, dl_dimage, loss, static_cast<hipStream_t>(stream)), "l1");
+  return FGS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,211 @@
+// Internal declarations shared by the HIP translation units of libfastergs.
+// Device helpers here are header-only so that every kernel that needs the same
+// decision (tile test, alpha) runs the identical instruction sequence.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fastergs.h"
+
+namespace fgs {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
+constexpr int kWave = 64;
+constexpr int kScanItems = 16;       // items per thread in scan / radix kernels
+constexpr int kScanTile = kBlock * kScanItems;
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kNumXcd = 8;           // MI355X: 8 XCDs, workgroups dealt round-robin
+
+// Camera as the kernels see it.
+struct CamDev {
+  float w[12];        // rows 0..2 of the world-to-camera matrix, row-major 3x4
+  float campos[3];    // camera centre in world space, -W3^T t
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  int32_t tiles_x, tiles_y;
+  float near_z;
+  float bg[3];
+};
+
+struct SetDev {
+  float alpha_min, alpha_max, t_min, dilation, quat_min, det_min;
+};
+
+struct GaussDev {
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* logits;
+  const float* sh_dc;
+  const float* sh_rest;
+  uint32_t n;
+  int32_t sh_coeffs;  // (degree + 1)^2
+};
+
+struct GradDev {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* logits;
+  float* sh_dc;
+  float* sh_rest;
+};
+
+// ----------------------------------------------------------------------------
+// Workgroup -> tile mapping.  Workgroups are dealt to the 8 XCDs round-robin
+// (workgroup b runs on XCD b % 8).  Giving each XCD a contiguous band of
+// tiles keeps the splat records that neighbouring tiles share in one L2.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nb) {
+  const uint32_t xcd = b % kNumXcd;
+  const uint32_t local = b / kNumXcd;
+  const uint32_t base = nb / kNumXcd, rem = nb % kNumXcd;
+  // XCD x owns tiles [start(x), start(x) + base + (x < rem)).
+  const uint32_t start = xcd * base + (xcd < rem ? xcd : rem);
+  return start + local;
+}
+
+// ----------------------------------------------------------------------------
+// Exact tile test (FP32, fixed operation order, no contraction).
+// Keeps a tile when the minimum of d^T [[a,b],[b,c]] d over the tile's
+// pixel-centre hull (clipped to the image) is <= thr = 2 ln(o / alpha_min).
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ float edge_min_q(float a, float b, float c, float dfix, float m_other,
+                                            float lo, float hi, bool fix_is_x) {
+#pragma clang fp contract(off)
+  float t = fix_is_x ? (-(b * dfix)) / c : (-(b * dfix)) / a;
+  float p = fminf(fmaxf(m_other + t, lo), hi);
+  float dvar = p - m_other;
+  float dx = fix_is_x ? dfix : dvar;
+  float dy = fix_is_x ? dvar : dfix;
+  return ((a * dx) * dx + ((b + b) * dx) * dy) + (c * dy) * dy;
+}
+
+__device__ __forceinline__ bool tile_keep(float mx, float my, float a, float b, float c, float thr,
+                                          int tx, int ty, int tile, int width, int height) {
+#pragma clang fp contract(off)
+  const float x0 = (float)(tx * tile) + 0.5f;
+  const float x1 = (float)min(tx * tile + tile - 1, width - 1) + 0.5f;
+  const float y0 = (float)(ty * tile) + 0.5f;
+  const float y1 = (float)min(ty * tile + tile - 1, height - 1) + 0.5f;
+  const bool left = mx < x0, right = mx > x1, top = my < y0, bottom = my > y1;
+  if (!(left || right || top || bottom)) return true;  // min is 0 inside the hull
+  float q = __builtin_huge_valf();
+  if (left) q = fminf(q, edge_min_q(a, b, c, x0 - mx, my, y0, y1, true));
+  if (right) q = fminf(q, edge_min_q(a, b, c, x1 - mx, my, y0, y1, true));
+  if (top) q = fminf(q, edge_min_q(a, b, c, y0 - my, mx, x0, x1, false));
+  if (bottom) q = fminf(q, edge_min_q(a, b, c, y1 - my, mx, x0, x1, false));
+  return q <= thr;
+}
+
+// Decode the packed tile rectangle.
+__device__ __forceinline__ void unpack_rect(uint2 r, int& tx0, int& ty0, int& tx1, int& ty1) {
+  tx0 = (int)(r.x & 0xffffu);
+  ty0 = (int)(r.x >> 16);
+  tx1 = (int)(r.y & 0xffffu);
+  ty1 = (int)(r.y >> 16);
+}
+
+// ----------------------------------------------------------------------------
+// Alpha of one fragment (Eq. (3) with the dilated conic, capped at alpha_max).
+// Shared by the forward and backward blend so both take identical decisions.
+// Returns alpha; g receives exp(power) and `power` the exponent.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ float splat_alpha(float dx, float dy, float a, float b, float c, float o,
+                                             float alpha_max, float& g) {
+#pragma clang fp contract(off)
+  const float quad = __builtin_fmaf(a * dx, dx, __builtin_fmaf(c * dy, dy, (b + b) * (dx * dy)));
+  g = __expf(-0.5f * quad);
+  return fminf(alpha_max, o * g);
+}
+
+// ----------------------------------------------------------------------------
+// Wave / block primitives (wave64, 256-thread blocks).
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    uint32_t y = __shfl_up(v, d, kWave);
+    if (lane >= d) v += y;
+  }
+  return v;
+}
+
+// Exclusive scan across the 256 threads of a block; *total gets the block sum.
+// `lds` must hold kBlock / kWave words.  Contains two barriers.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* lds, uint32_t* total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  uint32_t inc = wave_inclusive_scan(v, lane);
+  if (lane == kWave - 1) lds[wave] = inc;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / kWave; ++w) {
+    uint32_t s = lds[w];
+    pre += (w < wave) ? s : 0u;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + inc - v;
+}
+
+__device__ __forceinline__ uint32_t block_reduce_sum(uint32_t v, uint32_t* lds) {
+  uint32_t t;
+  block_exclusive_scan(v, lds, &t);
+  return t;
+}
+
+inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+// ----------------------------------------------------------------------------
+// Host-side launchers (each .hip file owns its kernels).
+// ----------------------------------------------------------------------------
+enum ScanMode { SCAN_IDENTITY = 0, SCAN_NONZERO = 1, SCAN_GATHER = 2 };
+
+// Scratch words needed by scan_u32 for n items.
+size_t scan_scratch_words(uint64_t n);
+// Exclusive scan of x[i] for i < n where x[i] = in[i] (IDENTITY), in[i] != 0
+// (NONZERO) or, for i < *d_count, in[idx[i]] (GATHER; 0 beyond the count).
+// Writes out[0..n) and, when d_total != NULL, the grand total to *d_total.
+hipError_t scan_u32(ScanMode mode, const uint32_t* in, const uint32_t* idx, const uint32_t* d_count,
+                    uint32_t* out, uint32_t n, uint32_t* d_total, uint32_t* scratch, hipStream_t s);
+
+size_t radix_scratch_words(uint64_t n);
+// Stable LSD radix sort of (key, value) pairs on bits [begin_bit, end_bit).
+// Items: n (host) or *d_count (device, <= n) when d_count != NULL.  Data
+// starts in keys[0]/vals[0]; returns (in *final_buf) the buffer holding the result.
+hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
+                            int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s);
+
+hipError_t launch_preprocess(const GaussDev& g, const CamDev& cam, const SetDev& st, int tile,
+                             float4* rec, uint2* rect, uint32_t* n_tiles, uint32_t* depth_key,
+                             hipStream_t s);
+hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth_key, uint32_t n,
+                                  const uint32_t* pos, uint32_t* vis_keys, uint32_t* vis_ids,
+                                  hipStream_t s);
+hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uint32_t n,
+                            const uint32_t* offsets, const float4* rec, const uint2* rect,
+                            const uint32_t* n_tiles, const CamDev& cam, int tile, uint32_t cap,
+                            uint32_t* keys, uint32_t* vals, hipStream_t s);
+hipError_t launch_tile_ranges(const uint32_t* keys, uint32_t count, uint32_t tiles, uint2* ranges,
+                              hipStream_t s);
+hipError_t launch_blend_forward(const uint2* ranges, const uint32_t* vals, const float4* rec,
+                                const CamDev& cam, const SetDev& st, float* image, float* t_final,
+                                uint32_t* last, hipStream_t s);
+hipError_t launch_blend_backward(const uint2* ranges, const uint32_t* vals, const float4* rec,
+                                 const CamDev& cam, const SetDev& st, const float* image,
+                                 const uint32_t* last, const float* dl_dimage, float* accum,
+                                 uint32_t n, hipStream_t s);
+hipError_t launch_preprocess_backward(const GaussDev& g, const CamDev& cam, const SetDev& st,
+                                      const float4* rec, const float* accum, const GradDev& gr,
+                                      hipStream_t s);
+hipError_t launch_adam(const fgs_adam_group* groups, int n_groups, int64_t step, float beta1,
+                       float beta2, float eps, hipStream_t s);
+hipError_t launch_l1_backward(const float* image, const float* target, uint32_t n, float* dl,
+                              double* loss, hipStream_t s);
+
+}  // namespace fgs

@@ -1,0 +1,253 @@
+// Per-Gaussian preprocess, visible compaction, instance duplication and tile
+// ranges (Sec. 2.1 Eq. (1)-(2) and activations; Sec. 3.2 "Splat Bounding",
+// "Tile-based Culling", "Sorting"; App. B.1 degenerate-Gaussian guard; App. B.2
+// compaction of visible indices only -- the per-Gaussian record stays in
+// Gaussian order so the backward pass needs no indirection).
+//
+// One thread per Gaussian; every plane is read with unit stride across the
+// wavefront (structure-of-arrays).  The key-deciding arithmetic (projection,
+// conic, threshold, rectangle, tile test) is evaluated in FP32 one operation
+// at a time in a fixed order with contraction disabled, so the instance keys
+// are reproducible bit for bit.
+#include "fgs_internal.h"
+
+namespace fgs {
+
+// Degree-3 real SH basis along unit direction (x, y, z) (Sec. 2.1).
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y) {
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[0] = 0.28209479177387814f;
+  Y[1] = -0.4886025119029199f * y;
+  Y[2] = 0.4886025119029199f * z;
+  Y[3] = -0.4886025119029199f * x;
+  Y[4] = 1.0925484305920792f * (x * y);
+  Y[5] = -1.0925484305920792f * (y * z);
+  Y[6] = 0.31539156525252005f * (2.0f * zz - xx - yy);
+  Y[7] = -1.0925484305920792f * (x * z);
+  Y[8] = 0.5462742152960396f * (xx - yy);
+  Y[9] = -0.5900435899266435f * y * (3.0f * xx - yy);
+  Y[10] = 2.890611442640554f * (x * y) * z;
+  Y[11] = -0.4570457994644658f * y * (4.0f * zz - xx - yy);
+  Y[12] = 0.3731763325901154f * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+  Y[13] = -0.4570457994644658f * x * (4.0f * zz - xx - yy);
+  Y[14] = 1.445305721320277f * z * (xx - yy);
+  Y[15] = -0.5900435899266435f * x * (xx - 3.0f * yy);
+}
+
+// View-dependent colour: sum_k coeff_k Y_k(dir) + 0.5, clipped at 0 per channel.
+// Returns the clip flags (bit c set when channel c was clipped).
+__device__ __forceinline__ uint32_t sh_colour(const GaussDev& g, uint32_t i, float px, float py, float pz,
+                                              const CamDev& cam, float* rgb) {
+  float dx = px - cam.campos[0], dy = py - cam.campos[1], dz = pz - cam.campos[2];
+  const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+  dx *= inv; dy *= inv; dz *= inv;
+  float Y[16];
+  sh_basis(dx, dy, dz, Y);
+  const size_t n = g.n;
+  float c0 = Y[0] * g.sh_dc[i], c1 = Y[0] * g.sh_dc[n + i], c2 = Y[0] * g.sh_dc[2 * n + i];
+  for (int k = 1; k < g.sh_coeffs; ++k) {
+    const float* p = g.sh_rest + (size_t)(3 * (k - 1)) * n + i;
+    c0 = fmaf(Y[k], p[0], c0);
+    c1 = fmaf(Y[k], p[n], c1);
+    c2 = fmaf(Y[k], p[2 * n], c2);
+  }
+  c0 += 0.5f; c1 += 0.5f; c2 += 0.5f;
+  uint32_t flags = (c0 < 0.0f ? 1u : 0u) | (c1 < 0.0f ? 2u : 0u) | (c2 < 0.0f ? 4u : 0u);
+  rgb[0] = fmaxf(c0, 0.0f);
+  rgb[1] = fmaxf(c1, 0.0f);
+  rgb[2] = fmaxf(c2, 0.0f);
+  return flags;
+}
+
+__global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, CamDev cam, SetDev st, int tile,
+                                                       float4* __restrict__ rec, uint2* __restrict__ rect,
+                                                       uint32_t* __restrict__ n_tiles,
+                                                       uint32_t* __restrict__ depth_key) {
+#pragma clang fp contract(off)
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= g.n) return;
+  const size_t n = g.n;
+  const float* W = cam.w;
+
+  const float mu0 = g.means[i], mu1 = g.means[n + i], mu2 = g.means[2 * n + i];
+  const float X = ((W[0] * mu0 + W[1] * mu1) + W[2] * mu2) + W[3];
+  const float Yc = ((W[4] * mu0 + W[5] * mu1) + W[6] * mu2) + W[7];
+  const float Z = ((W[8] * mu0 + W[9] * mu1) + W[10] * mu2) + W[11];
+  depth_key[i] = __float_as_uint(Z);
+
+  // activations: normalised quaternion, exp scales, sigmoid opacity
+  const float qw0 = g.quats[i], qx0 = g.quats[n + i], qy0 = g.quats[2 * n + i], qz0 = g.quats[3 * n + i];
+  const float n2 = ((qw0 * qw0 + qx0 * qx0) + qy0 * qy0) + qz0 * qz0;
+  const float qn = sqrtf(n2);
+  const float w = qw0 / qn, x = qx0 / qn, y = qy0 / qn, z = qz0 / qn;
+  const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
+  const float wx = w * x, wy = w * y, wz = w * z;
+  const float r00 = 1.0f - 2.0f * (yy + zz), r01 = 2.0f * (xy - wz), r02 = 2.0f * (xz + wy);
+  const float r10 = 2.0f * (xy + wz), r11 = 1.0f - 2.0f * (xx + zz), r12 = 2.0f * (yz - wx);
+  const float r20 = 2.0f * (xz - wy), r21 = 2.0f * (yz + wx), r22 = 1.0f - 2.0f * (xx + yy);
+  const float s0 = expf(g.log_scales[i]), s1 = expf(g.log_scales[n + i]), s2 = expf(g.log_scales[2 * n + i]);
+  const float m00 = r00 * s0, m01 = r01 * s1, m02 = r02 * s2;
+  const float m10 = r10 * s0, m11 = r11 * s1, m12 = r12 * s2;
+  const float m20 = r20 * s0, m21 = r21 * s1, m22 = r22 * s2;
+  // Sigma = M M^T
+  const float S00 = (m00 * m00 + m01 * m01) + m02 * m02;
+  const float S01 = (m00 * m10 + m01 * m11) + m02 * m12;
+  const float S02 = (m00 * m20 + m01 * m21) + m02 * m22;
+  const float S11 = (m10 * m10 + m11 * m11) + m12 * m12;
+  const float S12 = (m10 * m20 + m11 * m21) + m12 * m22;
+  const float S22 = (m20 * m20 + m21 * m21) + m22 * m22;
+
+  // Eq. (1): mean projection with the intrinsics
+  const float iz = 1.0f / Z;
+  const float u = X * iz, v = Yc * iz;
+  const float mx = cam.fx * u + cam.cx;
+  const float my = cam.fy * v + cam.cy;
+  // Eq. (2): T = J W3, Sigma2D = T Sigma T^T
+  const float j00 = cam.fx * iz, j11 = cam.fy * iz;
+  const float j02 = -(j00 * u), j12 = -(j11 * v);
+  const float T00 = j00 * W[0] + j02 * W[8], T01 = j00 * W[1] + j02 * W[9], T02 = j00 * W[2] + j02 * W[10];
+  const float T10 = j11 * W[4] + j12 * W[8], T11 = j11 * W[5] + j12 * W[9], T12 = j11 * W[6] + j12 * W[10];
+  const float U00 = (T00 * S00 + T01 * S01) + T02 * S02;
+  const float U01 = (T00 * S01 + T01 * S11) + T02 * S12;
+  const float U02 = (T00 * S02 + T01 * S12) + T02 * S22;
+  const float U10 = (T10 * S00 + T11 * S01) + T12 * S02;
+  const float U11 = (T10 * S01 + T11 * S11) + T12 * S12;
+  const float U12 = (T10 * S02 + T11 * S12) + T12 * S22;
+  const float c00 = (U00 * T00 + U01 * T01) + U02 * T02;
+  const float c01 = (U00 * T10 + U01 * T11) + U02 * T12;
+  const float c11 = (U10 * T10 + U11 * T11) + U12 * T12;
+  const float det = c00 * c11 - c01 * c01;
+  // dilation (2D low-pass filter) and conic
+  const float h00 = c00 + st.dilation, h11 = c11 + st.dilation, h01 = c01;
+  const float deth = h00 * h11 - h01 * h01;
+  const float ca = h11 / deth, cb = -h01 / deth, cc = h00 / deth;
+  const float o = 1.0f / (1.0f + expf(-g.logits[i]));
+
+  bool ok = (qn >= st.quat_min) && (Z >= cam.near_z) && (det >= st.det_min) && (o > st.alpha_min);
+  // opacity-aware extent: alpha reaches alpha_min out to d^T Sigma^-1 d = 2 ln(o / alpha_min)
+  const float thr = 2.0f * logf(o / st.alpha_min);
+  const float ext_x = sqrtf(thr * h00), ext_y = sqrtf(thr * h11);
+  ok = ok && (ext_x >= 0.0f) && (ext_y >= 0.0f) && isfinite(mx) && isfinite(my) && isfinite(ca) &&
+       isfinite(cb) && isfinite(cc);
+
+  // rectangle in pixel-centre indices, then tiles
+  const float lx = (mx - ext_x) - 0.5f, hx = (mx + ext_x) - 0.5f;
+  const float ly = (my - ext_y) - 0.5f, hy = (my + ext_y) - 0.5f;
+  const float wm1 = (float)(cam.width - 1), hm1 = (float)(cam.height - 1);
+  bool nonempty = ok && (hx >= 0.0f) && (lx <= wm1) && (hy >= 0.0f) && (ly <= hm1);
+  uint32_t count = 0;
+  if (nonempty) {
+    const int i0 = (lx <= 0.0f) ? 0 : (int)ceilf(lx);
+    const int i1 = (hx >= wm1) ? cam.width - 1 : (int)floorf(hx);
+    const int k0 = (ly <= 0.0f) ? 0 : (int)ceilf(ly);
+    const int k1 = (hy >= hm1) ? cam.height - 1 : (int)floorf(hy);
+    if (i0 <= i1 && k0 <= k1) {
+      const int tx0 = i0 / tile, tx1 = i1 / tile, ty0 = k0 / tile, ty1 = k1 / tile;
+      for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx)
+          count += tile_keep(mx, my, ca, cb, cc, thr, tx, ty, tile, cam.width, cam.height) ? 1u : 0u;
+      rect[i] = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
+    }
+  }
+  n_tiles[i] = count;
+  if (count == 0) return;
+
+  float rgb[3];
+  const uint32_t clip = sh_colour(g, i, mu0, mu1, mu2, cam, rgb);
+  rec[3 * (size_t)i + 0] = make_float4(mx, my, o, thr);
+  rec[3 * (size_t)i + 1] = make_float4(ca, cb, cc, Z);
+  rec[3 * (size_t)i + 2] = make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(clip | 8u));
+}
+
+hipError_t launch_preprocess(const GaussDev& g, const CamDev& cam, const SetDev& st, int tile, float4* rec,
+                             uint2* rect, uint32_t* n_tiles, uint32_t* depth_key, hipStream_t s) {
+  if (g.n == 0) return hipSuccess;
+  k_preprocess<<<ceil_div(g.n, kBlock), kBlock, 0, s>>>(g, cam, st, tile, rec, rect, n_tiles, depth_key);
+  return hipGetLastError();
+}
+
+// Writes (depth key, index) of every Gaussian with at least one instance at its
+// prefix-sum position: index order is kept, which the stable depth sort turns
+// into the (depth, index) tie-break.
+__global__ __launch_bounds__(kBlock) void k_compact(const uint32_t* __restrict__ n_tiles,
+                                                    const uint32_t* __restrict__ depth_key, uint32_t n,
+                                                    const uint32_t* __restrict__ pos,
+                                                    uint32_t* __restrict__ vis_keys,
+                                                    uint32_t* __restrict__ vis_ids) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n || n_tiles[i] == 0) return;
+  const uint32_t p = pos[i];
+  vis_keys[p] = depth_key[i];
+  vis_ids[p] = i;
+}
+
+hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth_key, uint32_t n,
+                                  const uint32_t* pos, uint32_t* vis_keys, uint32_t* vis_ids, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_compact<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n_tiles, depth_key, n, pos, vis_keys, vis_ids);
+  return hipGetLastError();
+}
+
+// Each visible Gaussian, in depth order, writes its kept tiles (row-major in
+// its rectangle) at its offset; writes never pass its own count nor `cap`.
+__global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict__ vis_ids,
+                                                      const uint32_t* __restrict__ d_nvis, uint32_t n,
+                                                      const uint32_t* __restrict__ offsets,
+                                                      const float4* __restrict__ rec,
+                                                      const uint2* __restrict__ rect,
+                                                      const uint32_t* __restrict__ n_tiles, CamDev cam,
+                                                      int tile, uint32_t cap, uint32_t* __restrict__ keys,
+                                                      uint32_t* __restrict__ vals) {
+  const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= min(*d_nvis, n)) return;
+  const uint32_t gid = vis_ids[p];
+  uint32_t off = offsets[p];
+  const uint32_t end = min(off + n_tiles[gid], cap);
+  const float4 r0 = rec[3 * (size_t)gid + 0];
+  const float4 r1 = rec[3 * (size_t)gid + 1];
+  int tx0, ty0, tx1, ty1;
+  unpack_rect(rect[gid], tx0, ty0, tx1, ty1);
+  for (int ty = ty0; ty <= ty1 && off < end; ++ty) {
+    for (int tx = tx0; tx <= tx1 && off < end; ++tx) {
+      if (tile_keep(r0.x, r0.y, r1.x, r1.y, r1.z, r0.w, tx, ty, tile, cam.width, cam.height)) {
+        keys[off] = (uint32_t)(ty * cam.tiles_x + tx);
+        vals[off] = gid;
+        ++off;
+      }
+    }
+  }
+  // The test above repeats the preprocess count on the same stored values, so
+  // this loop never runs; it keeps every slot defined (an out-of-range tile id
+  // that the range kernel ignores) should the two ever disagree.
+  for (; off < end; ++off) {
+    keys[off] = (uint32_t)(cam.tiles_x * cam.tiles_y);
+    vals[off] = gid;
+  }
+}
+
+hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uint32_t n, const uint32_t* offsets,
+                            const float4* rec, const uint2* rect, const uint32_t* n_tiles, const CamDev& cam,
+                            int tile, uint32_t cap, uint32_t* keys, uint32_t* vals, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_duplicate<<<ceil_div(n, kBlock), kBlock, 0, s>>>(vis_ids, d_nvis, n, offsets, rec, rect, n_tiles, cam, tile,
+                                                     cap, keys, vals);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t count,
+                                                        uint32_t tiles, uint2* __restrict__ ranges) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= count) return;
+  const uint32_t k = keys[i];
+  if (k >= tiles) return;
+  if (i == 0 || keys[i - 1] != k) ranges[k].x = i;
+  if (i == count - 1 || keys[i + 1] != k) ranges[k].y = i + 1;
+}
+
+hipError_t launch_tile_ranges(const uint32_t* keys, uint32_t count, uint32_t tiles, uint2* ranges, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  k_tile_ranges<<<ceil_div(count, kBlock), kBlock, 0, s>>>(keys, count, tiles, ranges);
+  return hipGetLastError();
+}
+
+}  // namespace fgs

@@ -1,0 +1,139 @@
+"""The C ABI without a GPU: the library loads, exports every symbol the header
+declares, and rejects invalid arguments before launching anything."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2602_09999_amd import _lib as L
+from paper_2602_09999_amd import binding as B
+import synthetic as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fastergs.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fgs_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.load()
+
+
+def test_every_declared_symbol_is_exported_and_bound(lib):
+    names = declared_functions()
+    assert len(names) >= 9
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in L.SIGNATURES, name
+    assert lib.fgs_abi_version() == 1
+
+
+def test_default_settings_match_the_paper(lib):
+    s = B.default_settings()
+    assert s.tile == 16
+    assert s.alpha_min == pytest.approx(1 / 255, rel=1e-7)
+    assert s.alpha_max == pytest.approx(0.99, rel=1e-7)
+    assert s.t_min == pytest.approx(1e-4, rel=1e-7)
+    assert s.dilation == pytest.approx(0.3, rel=1e-7)
+    assert s.quat_min == pytest.approx(1e-4, rel=1e-7) and s.det_min == pytest.approx(1e-6, rel=1e-7)
+
+
+def test_workspace_size_and_layout(lib):
+    cam = S.workload_camera("c1")
+    a = B.workspace_size(10_000, cam, instance_capacity=100_000)
+    b = B.workspace_size(10_000, cam, instance_capacity=200_000)
+    assert b - a >= 4 * 4 * 100_000
+    lay = B.workspace_layout(10_000, cam, instance_capacity=100_000)
+    offs = [lay.rec, lay.rect, lay.n_tiles, lay.depth_key, lay.counters, lay.vis_keys[0], lay.vis_ids[0],
+            lay.inst_offsets, lay.inst_keys[0], lay.inst_vals[0], lay.ranges, lay.accum, lay.scratch]
+    assert all(o % 256 == 0 for o in offs)
+    assert lay.total == a and lay.tiles_x == 16 and lay.tiles_y == 16
+    assert lay.inst_final == 1  # 256 tiles -> 8 key bits -> one radix pass
+    lay2 = B.workspace_layout(10, S.workload_camera("c3"), instance_capacity=10)
+    assert (lay2.tiles_x, lay2.tiles_y) == (100, 67) and lay2.inst_final == 0
+
+
+def _status(fn, *args):
+    return fn(*args)
+
+
+def test_invalid_arguments_are_rejected_without_launching(lib):
+    cam = B.make_camera(S.workload_camera("c1"))
+    st = B.default_settings()
+    size = ctypes.c_size_t()
+    assert lib.fgs_workspace_size(-1, ctypes.byref(cam), ctypes.byref(st), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
+    assert b"out of range" in lib.fgs_last_error()
+    bad = B.make_camera(S.workload_camera("c1"))
+    bad.width = 0
+    assert lib.fgs_workspace_size(10, ctypes.byref(bad), ctypes.byref(st), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
+    bad = B.make_camera(S.workload_camera("c1"))
+    bad.fx = float("nan")
+    assert lib.fgs_workspace_size(10, ctypes.byref(bad), ctypes.byref(st), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
+    st8 = B.default_settings(tile=8)
+    assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(st8), 0, ctypes.byref(size)) == L.FGS_ERR_UNSUPPORTED
+    st7 = B.default_settings(tile=7)
+    assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(st7), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
+    stb = B.default_settings(alpha_min=0.995)
+    assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(stb), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
+
+    g = L.Gaussians()
+    g.n = 5
+    g.sh_dtype = L.FGS_F32
+    g.sh_degree = 3
+    stats = L.ForwardStats()
+    # NULL parameter pointers
+    r = lib.fgs_rasterize_forward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), None, 0, 0, None, None, None,
+                                  ctypes.byref(stats), None)
+    assert r == L.FGS_ERR_INVALID_ARGUMENT
+    # bf16 SH is a valid option that is not implemented yet
+    fake = 1 << 20
+    for f in ("means", "log_scales", "quats", "opacity_logits", "sh_dc", "sh_rest"):
+        setattr(g, f, fake)
+    g.sh_dtype = L.FGS_BF16
+    r = lib.fgs_rasterize_forward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), fake, 1 << 30, 0, fake, None,
+                                  fake, ctypes.byref(stats), None)
+    assert r == L.FGS_ERR_UNSUPPORTED
+    g.sh_dtype = L.FGS_F32
+    g.sh_degree = 4
+    r = lib.fgs_rasterize_forward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), fake, 1 << 30, 0, fake, None,
+                                  fake, ctypes.byref(stats), None)
+    assert r == L.FGS_ERR_INVALID_ARGUMENT
+    g.sh_degree = 3
+    # workspace too small
+    r = lib.fgs_rasterize_forward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), fake, 16, 0, fake, None, fake,
+                                  ctypes.byref(stats), None)
+    assert r == L.FGS_ERR_INVALID_ARGUMENT and b"needed" in lib.fgs_last_error()
+    # missing outputs
+    r = lib.fgs_rasterize_forward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), fake, 1 << 30, 0, None, None,
+                                  None, ctypes.byref(stats), None)
+    assert r == L.FGS_ERR_INVALID_ARGUMENT
+    # backward without dl_dimage
+    gr = L.GaussianGrads()
+    r = lib.fgs_rasterize_backward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), fake, 1 << 30, 0, fake, fake,
+                                   None, ctypes.byref(gr), None)
+    assert r == L.FGS_ERR_INVALID_ARGUMENT
+    # Adam argument checks
+    arr = (L.AdamGroup * 1)()
+    assert lib.fgs_adam_step(arr, 0, 1, 0.9, 0.999, 1e-15, None) == L.FGS_ERR_INVALID_ARGUMENT
+    assert lib.fgs_adam_step(arr, 1, 0, 0.9, 0.999, 1e-15, None) == L.FGS_ERR_INVALID_ARGUMENT
+    arr[0].numel = 4
+    assert lib.fgs_adam_step(arr, 1, 1, 0.9, 0.999, 1e-15, None) == L.FGS_ERR_INVALID_ARGUMENT
+    assert lib.fgs_adam_step(arr, 1, 1, 1.5, 0.999, 1e-15, None) == L.FGS_ERR_INVALID_ARGUMENT
+    assert lib.fgs_l1_loss_backward(None, None, 10, None, None, None) == L.FGS_ERR_INVALID_ARGUMENT
+    assert lib.fgs_status_string(2) == b"instance capacity exceeded"
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    with pytest.raises(FileNotFoundError):
+        L._lib_backup = L._lib
+        try:
+            L._lib = None
+            L.load(str(tmp_path / "nope.so"))
+        finally:
+            L._lib = L._lib_backup
