@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured with rocprofv3 counters (optional)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="run one device copy of this many MiB first (reference kernel for counters)")
     return ap.parse_args()
 
 
@@ -59,6 +61,26 @@ def algorithmic_bytes(n, n_touched, i_proc, pixels):
     return {"adam": adam, "bwd": blend_bwd + pre_bwd, "blend_bwd": blend_bwd, "pre_bwd": pre_bwd}
 
 
+def source_digest(path: str) -> str:
+    import hashlib
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(path: str, kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, or None when
+    missing or taken on a different version of the kernel's source file."""
+    if not os.path.exists(path):
+        return None
+    try:
+        ent = json.load(open(path))["kernels"][kernel][workload]
+        src = os.path.join(ROOT, "paper_2602_09999_amd", "csrc", ent["source"])
+        if source_digest(src) != ent["source_sha256_16"]:
+            return None
+        return float(ent["bytes_per_launch"])
+    except (KeyError, ValueError, OSError, TypeError):
+        return None
+
+
 def cpu_baseline(workload: str, seed: int, budget_s: float):
     """FP64 oracle on a bounded sample of the workload, extrapolated to one step."""
     import oracle as O
@@ -70,9 +92,8 @@ def cpu_baseline(workload: str, seed: int, budget_s: float):
     cx, cy = w.width // 2, w.height // 2
     crop = (cx - 16, cy - 16, cx + 16, cy + 16)
     dl = S.make_dl_dimage(32, 32, seed=1)
-    t0 = time.perf_counter()
-    O.render64(scene, cam, crop=crop, dl_dimage=dl)
-    t_crop = time.perf_counter() - t0            # includes the FP64 preprocess of all N for culling
+    r = O.render64(scene, cam, crop=crop, dl_dimage=dl)
+    t_crop = r["seconds_compositing"]            # per-pixel compositing fwd+bwd of the crop only
     # per-Gaussian preprocess + its backward on a subset
     m = min(w.n, 200_000)
     sub = S.subset(scene, slice(0, m))
@@ -130,6 +151,13 @@ def main():
     last = torch.empty(w.height, w.width, dtype=torch.int32, device=dev)
     dl = torch.empty_like(image)
     grads = {k: torch.empty_like(v) for k, v in params.items()}
+    if args.calibrate_copy_mib > 0:
+        src = torch.ones(args.calibrate_copy_mib << 18, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calibrate_copy_mib} MiB read + {args.calibrate_copy_mib} MiB written")
+        del src, dst
     torch.cuda.synchronize()
 
     def step(ev=None):
@@ -181,15 +209,7 @@ def main():
     adam_gbs = byt["adam"] / (adam_ms * 1e-3) / 1e9
     bwd_gbs = byt["bwd"] / (float(ph[2]) * 1e-3) / 1e9
 
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        try:
-            tj = json.load(open(args.traffic_json))
-            ent = tj.get("kernels", {}).get("k_adam", {}).get(args.workload)
-            if ent and ent.get("source_hash") == tj.get("current_hash"):
-                traffic = ent.get("bytes_per_launch")
-        except Exception:  # malformed file: report no traffic
-            traffic = None
+    traffic = measured_traffic(args.traffic_json, "k_adam", args.workload)
 
     out = {
         "metric": "train steps/s (fwd+bwd+Adam) at 3M Gaussians 1600x1060; bwd HBM GB/s",

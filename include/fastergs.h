@@ -220,9 +220,11 @@ fgs_status fgs_rasterize_backward(const fgs_gaussians* g, const fgs_camera* cam,
  *   m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2;
  *   p <- p - lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps),
  * including elements whose gradient is zero.  groups: host array of
- * n_groups (1..16) descriptors; step t >= 1. */
+ * n_groups (1..16) descriptors; step t >= 1.  The hyperparameters are taken
+ * in double so that 1 - beta and the bias corrections are formed before
+ * rounding to float32, as PyTorch does. */
 fgs_status fgs_adam_step(const fgs_adam_group* groups, int32_t n_groups, int64_t step,
-                         float beta1, float beta2, float eps, void* stream);
+                         double beta1, double beta2, double eps, void* stream);
 
 /* L1 loss term of Sec. 2.1 / App. A: dl_dimage[i] = sign(image[i] - target[i]) / n
  * (sign(0) = 0) for i < n; when loss (device double, nullable) is given, it

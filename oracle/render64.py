@@ -338,6 +338,8 @@ def render64(scene: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
         myk = np.abs(ys - my) <= float(e2[1]) + 1.0
         border |= torch.as_tensor(myk[:, None] & mxk[None, :])
 
+    import time as _time
+    t_blend0 = _time.perf_counter()
     for by in range(y0, y1, block_px):
         for bx in range(x0, x1, block_px):
             ex, ey = min(bx + block_px, x1), min(by + block_px, y1)
@@ -368,7 +370,9 @@ def render64(scene: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
                 g = dl_dimage[:, by - y0:ey - y0, bx - x0:ex - x0].to(F64).reshape(3, -1).T
                 (Cc * g).sum().backward()
 
+    t_blend = _time.perf_counter() - t_blend0
     out: Dict[str, object] = {
+        "seconds_compositing": t_blend,
         "image": image, "t_final": tfin, "last_id": last_id, "borderline": border,
         "n_blended": nblend, "order": order, "n_valid": int(len(order)),
         "n_cull_border": int(cb.numel()),

@@ -72,7 +72,8 @@ SIGNATURES = {
     "fgs_rasterize_backward": (c_int32, [ctypes.POINTER(Gaussians), ctypes.POINTER(Camera), ctypes.POINTER(Settings),
                                          c_void_p, c_size_t, c_int64, c_void_p, c_void_p, c_void_p,
                                          ctypes.POINTER(GaussianGrads), c_void_p]),
-    "fgs_adam_step": (c_int32, [ctypes.POINTER(AdamGroup), c_int32, c_int64, c_float, c_float, c_float, c_void_p]),
+    "fgs_adam_step": (c_int32, [ctypes.POINTER(AdamGroup), c_int32, c_int64, c_double, c_double, c_double,
+                                c_void_p]),
     "fgs_l1_loss_backward": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
 }
 

@@ -68,17 +68,17 @@ __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a, uint64_t total_vec)
   }
 }
 
-hipError_t launch_adam(const fgs_adam_group* groups, int n_groups, int64_t step, float beta1, float beta2,
-                       float eps, hipStream_t s) {
+hipError_t launch_adam(const fgs_adam_group* groups, int n_groups, int64_t step, double beta1, double beta2,
+                       double eps, hipStream_t s) {
   AdamArgs a = {};
   a.n_groups = n_groups;
-  const double bc1 = 1.0 - std::pow((double)beta1, (double)step);
-  const double bc2 = 1.0 - std::pow((double)beta2, (double)step);
-  a.one_minus_b1 = (float)(1.0 - (double)beta1);
-  a.beta2 = beta2;
-  a.one_minus_b2 = (float)(1.0 - (double)beta2);
+  const double bc1 = 1.0 - std::pow(beta1, (double)step);
+  const double bc2 = 1.0 - std::pow(beta2, (double)step);
+  a.one_minus_b1 = (float)(1.0 - beta1);
+  a.beta2 = (float)beta2;
+  a.one_minus_b2 = (float)(1.0 - beta2);
   a.inv_sqrt_bc2 = (float)(1.0 / std::sqrt(bc2));
-  a.eps = eps;
+  a.eps = (float)eps;
   uint64_t vec = 0;
   for (int k = 0; k < n_groups; ++k) {
     AdamGroupDev& G = a.grp[k];

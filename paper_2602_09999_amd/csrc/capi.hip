@@ -340,14 +340,14 @@ fgs_status fgs_rasterize_backward(const fgs_gaussians* g, const fgs_camera* cam,
   return FGS_OK;
 }
 
-fgs_status fgs_adam_step(const fgs_adam_group* groups, int32_t n_groups, int64_t step, float beta1, float beta2,
-                         float eps, void* stream) {
+fgs_status fgs_adam_step(const fgs_adam_group* groups, int32_t n_groups, int64_t step, double beta1, double beta2,
+                         double eps, void* stream) {
   if (!groups) return fail(FGS_ERR_INVALID_ARGUMENT, "groups is NULL");
   if (n_groups < 1 || n_groups > 16) return fail(FGS_ERR_INVALID_ARGUMENT, "n_groups %d not in 1..16", n_groups);
   if (step < 1) return fail(FGS_ERR_INVALID_ARGUMENT, "step must be >= 1");
-  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f))
+  if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0))
     return fail(FGS_ERR_INVALID_ARGUMENT, "betas must lie in [0, 1)");
-  if (!(eps >= 0.0f) || !std::isfinite(eps)) return fail(FGS_ERR_INVALID_ARGUMENT, "eps must be finite, >= 0");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(FGS_ERR_INVALID_ARGUMENT, "eps must be finite, >= 0");
   for (int k = 0; k < n_groups; ++k) {
     const fgs_adam_group& G = groups[k];
     if (G.numel < 0) return fail(FGS_ERR_INVALID_ARGUMENT, "group %d: numel < 0", k);

@@ -203,8 +203,8 @@ hipError_t launch_blend_backward(const uint2* ranges, const uint32_t* vals, cons
 hipError_t launch_preprocess_backward(const GaussDev& g, const CamDev& cam, const SetDev& st,
                                       const float4* rec, const float* accum, const GradDev& gr,
                                       hipStream_t s);
-hipError_t launch_adam(const fgs_adam_group* groups, int n_groups, int64_t step, float beta1,
-                       float beta2, float eps, hipStream_t s);
+hipError_t launch_adam(const fgs_adam_group* groups, int n_groups, int64_t step, double beta1,
+                       double beta2, double eps, hipStream_t s);
 hipError_t launch_l1_backward(const float* image, const float* target, uint32_t n, float* dl,
                               double* loss, hipStream_t s);
 
