@@ -200,7 +200,13 @@ def main():
     ranges = rz.view("ranges", 2 * tiles).view(torch.int32).view(tiles, 2)
     lp = torch.zeros(lay.tiles_y * 16, lay.tiles_x * 16, dtype=torch.int64, device=dev)
     lp[:w.height, :w.width] = last.long()
-    i_proc = int(lp.view(lay.tiles_y, 16, lay.tiles_x, 16).amax(dim=(1, 3)).sum())
+    walks = lp.view(lay.tiles_y, 16, lay.tiles_x, 16).amax(dim=(1, 3)).flatten()
+    i_proc = int(walks.sum())
+    lens = (ranges[:, 1] - ranges[:, 0]).long()
+    q = torch.tensor([0.5, 0.9, 0.99, 1.0], device=dev)
+    log("tile walk p50/p90/p99/max", [int(x) for x in torch.quantile(walks.double(), q.double())],
+        "list length p50/p90/p99/max", [int(x) for x in torch.quantile(lens.double(), q.double())],
+        "tiles walking their whole list", int(((walks == lens) & (lens > 0)).sum()))
     accum = rz.view("accum", 9 * n, dtype=torch.float32).view(9, n)
     n_touched = int((accum != 0).any(0).sum())
     pixels = w.width * w.height

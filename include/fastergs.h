@@ -125,8 +125,11 @@ typedef struct fgs_forward_stats {
  *   rect       uint32[2*n]  tile rectangle: (tx0 | ty0<<16, tx1 | ty1<<16)
  *   n_tiles    uint32[n]    instances per Gaussian (0 = not rendered)
  *   depth_key  uint32[n]    bits of the FP32 camera z
- *   counters   uint32[16]   [0] visible count, [1] instance count I
- *   vis_ids    uint32[n] x2 ping-pong; sorted visible ids in vis_ids[vis_final]
+ *   counters   uint32[16]   [0] visible count, [1] smallest and [2] largest
+ *                           visible depth key, [3] index of the ping-pong buffer
+ *                           holding the depth-sorted visible ids, [4..5] the
+ *                           instance count I (uint64)
+ *   vis_ids    uint32[n] x2 ping-pong (see counters[3])
  *   inst_keys  uint32[cap] x2, inst_vals uint32[cap] x2: tile ids and
  *                           Gaussian ids; sorted in [inst_final]
  *   ranges     uint32[2*tiles] [start, end) of each tile's list
@@ -137,7 +140,8 @@ typedef struct fgs_layout {
   size_t inst_offsets;
   size_t inst_keys[2], inst_vals[2];
   size_t ranges, accum, scratch, total;
-  int32_t vis_final, inst_final;
+  int32_t inst_final;
+  int32_t reserved;
   int32_t tiles_x, tiles_y;
   int64_t instance_capacity;
 } fgs_layout;
@@ -177,7 +181,8 @@ fgs_status fgs_workspace_layout(int64_t n, const fgs_camera* cam, const fgs_sett
  *     SH colour (clipped at 0), culling, opacity-aware tile rectangle, exact
  *     per-tile test, depth key;
  *  2. compaction of the visible Gaussians and a 32-bit radix sort by depth
- *     (stable, so depth ties keep index order);
+ *     (stable, so depth ties keep index order; digit passes on bits that all
+ *     visible keys share are skipped);
  *  3. duplication into (tile, Gaussian) instances and a stable radix sort by
  *     tile -- per-tile lists in (depth key, index) order -- and tile ranges;
  *  4. per tile, front-to-back blending with the 0.99 alpha cap, the
@@ -191,7 +196,7 @@ fgs_status fgs_workspace_layout(int64_t n, const fgs_camera* cam, const fgs_sett
  *   stats   (host, nullable)
  * The workspace must hold fgs_workspace_size(n, cam, st, instance_capacity)
  * bytes and is read again by fgs_rasterize_backward.  The call synchronises
- * `stream` once, after the depth sort, to read I.  If I > instance_capacity
+ * `stream` once, after the preprocess, to read I.  If I > instance_capacity
  * it returns FGS_ERR_CAPACITY with stats->n_instances = I, having written no
  * image; grow the workspace and call again. */
 fgs_status fgs_rasterize_forward(const fgs_gaussians* g, const fgs_camera* cam,

@@ -37,33 +37,68 @@ __device__ __forceinline__ void adam_elem(float& p, float g, float& m, float& v,
   p = p - step * (m / denom);
 }
 
-__global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a, uint64_t total_vec) {
-  const uint64_t slot = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (slot >= total_vec) return;
+constexpr int kAdamSlots = 2;  // float4 slots per thread (more loads in flight)
+
+typedef float vf4 __attribute__((ext_vector_type(4)));
+// Streaming load of a gradient that is read exactly once.
+__device__ __forceinline__ float4 load_once4(const float* p) {
+  const vf4 v = __builtin_nontemporal_load(reinterpret_cast<const vf4*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ int adam_group(const AdamArgs& a, uint64_t slot) {
   int gi = 0;
 #pragma unroll 1
   while (gi + 1 < a.n_groups && slot >= a.grp[gi + 1].vec_begin) ++gi;
-  const AdamGroupDev& G = a.grp[gi];
-  const uint64_t e0 = (slot - G.vec_begin) * 4;
-  if (G.vec4 && e0 + 4 <= G.numel) {
-    float4 p = *reinterpret_cast<const float4*>(G.p + e0);
-    const float4 g = *reinterpret_cast<const float4*>(G.g + e0);
-    float4 m = *reinterpret_cast<const float4*>(G.m + e0);
-    float4 v = *reinterpret_cast<const float4*>(G.v + e0);
-    adam_elem(p.x, g.x, m.x, v.x, a, G.step_size);
-    adam_elem(p.y, g.y, m.y, v.y, a, G.step_size);
-    adam_elem(p.z, g.z, m.z, v.z, a, G.step_size);
-    adam_elem(p.w, g.w, m.w, v.w, a, G.step_size);
-    *reinterpret_cast<float4*>(G.p + e0) = p;
-    *reinterpret_cast<float4*>(G.m + e0) = m;
-    *reinterpret_cast<float4*>(G.v + e0) = v;
-  } else {
-    for (uint64_t e = e0; e < e0 + 4 && e < G.numel; ++e) {
-      float p = G.p[e], m = G.m[e], v = G.v[e];
-      adam_elem(p, G.g[e], m, v, a, G.step_size);
-      G.p[e] = p;
-      G.m[e] = m;
-      G.v[e] = v;
+  return gi;
+}
+
+// Each workgroup covers kAdamSlots * 256 consecutive float4 slots; thread t
+// takes slots t and t + 256 so that every load instruction is coalesced.
+__global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a, uint64_t total_vec) {
+  const uint64_t base = (uint64_t)blockIdx.x * (kBlock * kAdamSlots) + threadIdx.x;
+  float4 p[kAdamSlots], g[kAdamSlots], m[kAdamSlots], v[kAdamSlots];
+  int gi[kAdamSlots];
+  bool vec[kAdamSlots];
+#pragma unroll
+  for (int u = 0; u < kAdamSlots; ++u) {
+    const uint64_t slot = base + (uint64_t)u * kBlock;
+    vec[u] = false;
+    gi[u] = 0;
+    if (slot >= total_vec) continue;
+    gi[u] = adam_group(a, slot);
+    const AdamGroupDev& G = a.grp[gi[u]];
+    const uint64_t e0 = (slot - G.vec_begin) * 4;
+    vec[u] = G.vec4 && e0 + 4 <= G.numel;
+    if (vec[u]) {
+      p[u] = *reinterpret_cast<const float4*>(G.p + e0);
+      g[u] = load_once4(G.g + e0);
+      m[u] = *reinterpret_cast<const float4*>(G.m + e0);
+      v[u] = *reinterpret_cast<const float4*>(G.v + e0);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kAdamSlots; ++u) {
+    const uint64_t slot = base + (uint64_t)u * kBlock;
+    if (slot >= total_vec) continue;
+    const AdamGroupDev& G = a.grp[gi[u]];
+    const uint64_t e0 = (slot - G.vec_begin) * 4;
+    if (vec[u]) {
+      adam_elem(p[u].x, g[u].x, m[u].x, v[u].x, a, G.step_size);
+      adam_elem(p[u].y, g[u].y, m[u].y, v[u].y, a, G.step_size);
+      adam_elem(p[u].z, g[u].z, m[u].z, v[u].z, a, G.step_size);
+      adam_elem(p[u].w, g[u].w, m[u].w, v[u].w, a, G.step_size);
+      *reinterpret_cast<float4*>(G.p + e0) = p[u];
+      *reinterpret_cast<float4*>(G.m + e0) = m[u];
+      *reinterpret_cast<float4*>(G.v + e0) = v[u];
+    } else {
+      for (uint64_t e = e0; e < e0 + 4 && e < G.numel; ++e) {
+        float pe = G.p[e], me = G.m[e], ve = G.v[e];
+        adam_elem(pe, G.g[e], me, ve, a, G.step_size);
+        G.p[e] = pe;
+        G.m[e] = me;
+        G.v[e] = ve;
+      }
     }
   }
 }
@@ -94,7 +129,8 @@ hipError_t launch_adam(const fgs_adam_group* groups, int n_groups, int64_t step,
     vec += (G.numel + 3) / 4;
   }
   if (vec == 0) return hipSuccess;
-  k_adam<<<(uint32_t)((vec + kBlock - 1) / kBlock), kBlock, 0, s>>>(a, vec);
+  const uint64_t per_block = (uint64_t)kBlock * kAdamSlots;
+  k_adam<<<(uint32_t)((vec + per_block - 1) / per_block), kBlock, 0, s>>>(a, vec);
   return hipGetLastError();
 }
 

@@ -2,84 +2,147 @@
 // App. B.1: alpha cap 0.99, stop once T < 1e-4, front-to-back gradients;
 // Sec. 3.2 "Per-Gaussian Backward" / App. B.3 on reducing gradient atomics).
 //
-// One workgroup of 256 threads per 16x16 tile, one pixel per thread.  Splat
-// records of the tile's list are gathered 256 at a time into LDS and then
-// read by every pixel of the tile (LDS broadcast, no bank conflicts).
+// One wave64 per 16x16 tile; lane l owns the four pixels (l % 16, l / 16 + 4r),
+// r = 0..3.  The tile's list is read in batches of 64 entries: lane i gathers
+// entry i's 48-byte splat record with vector loads (the next batch is in flight
+// while the current one is used) and each fragment is broadcast to the wave with
+// v_readlane -- no LDS traffic and no barriers.  The x-terms of the quadratic
+// are shared by a lane's four pixels and the conic is pre-scaled so that alpha
+// takes one v_exp_f32.  A wave stops as soon as its 256 pixels are done.
 //
-// Backward: every pixel replays its own walk in the same order up to its last
-// blended fragment.  Per fragment, the nine per-pixel gradient terms are
-// summed over the 64 pixels of a wavefront with a transpose butterfly (16
-// cross-lane steps for 9 values instead of 54), the four wavefront partials
-// are combined through LDS, and one float atomic per value per (Gaussian,
-// tile) goes to the accumulators.
+// Backward: the wave replays the walk up to the tile's last blended fragment.
+// Per fragment, each lane sums the nine gradient terms of its four pixels,
+// the wave sums them over its 64 lanes on the VALU with a transpose butterfly
+// (16 cross-lane steps for 9 values: DPP within rows, gfx950 permlane swaps
+// across rows), and nine lanes issue one float atomic each per (Gaussian, tile).
 #include "fgs_internal.h"
 
 namespace fgs {
 
 constexpr int kTile = 16;
+constexpr int kRows = 4;  // pixels per lane
 
-__global__ __launch_bounds__(kBlock) void k_blend_fwd(const uint2* __restrict__ ranges,
-                                                      const uint32_t* __restrict__ vals,
-                                                      const float4* __restrict__ rec, CamDev cam, SetDev st,
-                                                      float* __restrict__ image, float* __restrict__ t_final,
-                                                      uint32_t* __restrict__ last) {
-  __shared__ float4 s_geo[kBlock];  // mu2D.x, mu2D.y, opacity
-  __shared__ float4 s_con[kBlock];  // conic a, b, c
-  __shared__ float4 s_col[kBlock];  // r, g, b
+// A batch of up to 64 consecutive list entries: lane i holds entry base + i.
+struct Batch {
+  uint32_t gid;
+  float4 r0, r1, r2;  // splat record: {mu2D, o, -}, {a, b, c, -}, {r, g, b, flags}
+};
+
+__device__ __forceinline__ void load_batch(const uint32_t* __restrict__ vals, const float4* __restrict__ rec,
+                                           uint32_t base, uint32_t end, int lane, Batch& b) {
+  const uint32_t j = base + (uint32_t)lane;
+  if (j < end) {
+    b.gid = vals[j];
+    b.r0 = rec[3 * (size_t)b.gid + 0];
+    b.r1 = rec[3 * (size_t)b.gid + 1];
+    b.r2 = rec[3 * (size_t)b.gid + 2];
+  }
+}
+
+__device__ __forceinline__ float bcast(float v, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+
+// Splat k of a batch, broadcast to the wave, with the conic pre-scaled so that
+// alpha = min(alpha_max, o * 2^(a2 dx^2 + b2 dx dy + c2 dy^2)).
+struct Splat {
+  float mx, my, o, a, b, c, a2, b2, c2;
+};
+constexpr float kHalfLog2e = 0.72134752044448170368f;  // log2(e) / 2
+
+__device__ __forceinline__ Splat splat_of(const Batch& B, int k) {
+  Splat s;
+  s.mx = bcast(B.r0.x, k);
+  s.my = bcast(B.r0.y, k);
+  s.o = bcast(B.r0.z, k);
+  s.a = bcast(B.r1.x, k);
+  s.b = bcast(B.r1.y, k);
+  s.c = bcast(B.r1.z, k);
+  s.a2 = -kHalfLog2e * s.a;
+  s.b2 = -2.0f * kHalfLog2e * s.b;
+  s.c2 = -kHalfLog2e * s.c;
+  return s;
+}
+
+// Alpha of Eq. (3) for one pixel, given the terms of the lane's column:
+// ax = a2 dx^2 and bx = b2 dx.  The forward and the backward call exactly
+// this sequence, so they take identical skip decisions.
+__device__ __forceinline__ float pixel_alpha(const Splat& s, float ax, float bx, float dy, float alpha_max,
+                                             float& G) {
+  G = __builtin_amdgcn_exp2f(fmaf(fmaf(s.c2, dy, bx), dy, ax));
+  return fminf(alpha_max, s.o * G);
+}
+
+__global__ __launch_bounds__(kWave) void k_blend_fwd(const uint2* __restrict__ ranges,
+                                                     const uint32_t* __restrict__ vals,
+                                                     const float4* __restrict__ rec, CamDev cam, SetDev st,
+                                                     float* __restrict__ image, float* __restrict__ t_final,
+                                                     uint32_t* __restrict__ last) {
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const int tx = (int)(tile % (uint32_t)cam.tiles_x), ty = (int)(tile / (uint32_t)cam.tiles_x);
-  const int px = tx * kTile + (int)(threadIdx.x % kTile);
-  const int py = ty * kTile + (int)(threadIdx.x / kTile);
-  const bool inside = px < cam.width && py < cam.height;
-  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  const int lane = threadIdx.x;
+  const int px = tx * kTile + (lane % kTile);
+  const float fx = (float)px + 0.5f;
+  float fy[kRows], T[kRows], C0[kRows], C1[kRows], C2[kRows];
+  uint32_t lpos[kRows];
+  bool live[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int py = ty * kTile + lane / kTile + 4 * r;
+    fy[r] = (float)py + 0.5f;
+    T[r] = 1.0f; C0[r] = C1[r] = C2[r] = 0.0f;
+    lpos[r] = 0;
+    live[r] = px < cam.width && py < cam.height;
+  }
   const uint2 range = ranges[tile];
-
-  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-  uint32_t last_pos = 0;
-  bool done = !inside;
-  for (uint32_t start = range.x; start < range.y; start += kBlock) {
-    if (__syncthreads_count(done ? 1 : 0) == kBlock) break;  // also guards LDS reuse
-    const uint32_t j = start + threadIdx.x;
-    if (j < range.y) {
-      const uint32_t gid = vals[j];
-      const float4 r0 = rec[3 * (size_t)gid + 0];
-      const float4 r1 = rec[3 * (size_t)gid + 1];
-      const float4 r2 = rec[3 * (size_t)gid + 2];
-      s_geo[threadIdx.x] = r0;
-      s_con[threadIdx.x] = r1;
-      s_col[threadIdx.x] = r2;
-    }
-    __syncthreads();
-    const int cnt = (int)min((uint32_t)kBlock, range.y - start);
-    if (!done) {
-      for (int k = 0; k < cnt; ++k) {
-        const float4 geo = s_geo[k];
-        const float4 con = s_con[k];
-        float g;
-        const float alpha = splat_alpha(fx - geo.x, fy - geo.y, con.x, con.y, con.z, geo.z, st.alpha_max, g);
-        if (alpha < st.alpha_min) continue;
-        const float4 col = s_col[k];
-        const float wgt = alpha * T;
-        C0 = fmaf(wgt, col.x, C0);
-        C1 = fmaf(wgt, col.y, C1);
-        C2 = fmaf(wgt, col.z, C2);
-        T = T * (1.0f - alpha);
-        last_pos = start - range.x + (uint32_t)k + 1u;
-        if (T < st.t_min) {
-          done = true;
-          break;
-        }
+  const uint32_t beg = __builtin_amdgcn_readfirstlane(range.x);
+  const uint32_t end = __builtin_amdgcn_readfirstlane(range.y);
+  Batch cur = {}, nxt = {};
+  load_batch(vals, rec, beg, end, lane, cur);
+  bool running = beg < end;
+  for (uint32_t base = beg; running && base < end; base += kWave) {
+    if (base + kWave < end) load_batch(vals, rec, base + kWave, end, lane, nxt);
+    const int cnt = (int)min((uint32_t)kWave, end - base);
+    for (int k = 0; k < cnt; ++k) {
+      const Splat sp = splat_of(cur, k);
+      const float dx = fx - sp.mx;
+      const float ax = sp.a2 * dx * dx, bx = sp.b2 * dx;
+      const float cr = bcast(cur.r2.x, k), cg = bcast(cur.r2.y, k), cb = bcast(cur.r2.z, k);
+      bool any = false;
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) {  // branch-free: a skipped fragment has alpha 0
+        float G;
+        const float alpha = pixel_alpha(sp, ax, bx, fy[r] - sp.my, st.alpha_max, G);
+        const bool blend = live[r] && alpha >= st.alpha_min;
+        const float a = blend ? alpha : 0.0f;
+        const float wgt = a * T[r];
+        C0[r] = fmaf(wgt, cr, C0[r]);
+        C1[r] = fmaf(wgt, cg, C1[r]);
+        C2[r] = fmaf(wgt, cb, C2[r]);
+        T[r] = T[r] * (1.0f - a);
+        lpos[r] = blend ? base - beg + (uint32_t)k + 1u : lpos[r];
+        live[r] = live[r] && !(T[r] < st.t_min);
+        any |= live[r];
+      }
+      if (__ballot(any) == 0ull) {
+        running = false;
+        break;
       }
     }
+    cur = nxt;
   }
-  if (inside) {
-    const size_t hw = (size_t)cam.width * cam.height;
-    const size_t pix = (size_t)py * cam.width + px;
-    image[pix] = fmaf(T, cam.bg[0], C0);
-    image[hw + pix] = fmaf(T, cam.bg[1], C1);
-    image[2 * hw + pix] = fmaf(T, cam.bg[2], C2);
-    if (t_final) t_final[pix] = T;
-    last[pix] = last_pos;
+  const size_t hw = (size_t)cam.width * cam.height;
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int py = ty * kTile + lane / kTile + 4 * r;
+    if (px < cam.width && py < cam.height) {
+      const size_t pix = (size_t)py * cam.width + px;
+      image[pix] = fmaf(T[r], cam.bg[0], C0[r]);
+      image[hw + pix] = fmaf(T[r], cam.bg[1], C1[r]);
+      image[2 * hw + pix] = fmaf(T[r], cam.bg[2], C2[r]);
+      if (t_final) t_final[pix] = T[r];
+      last[pix] = lpos[r];
+    }
   }
 }
 
@@ -87,163 +150,173 @@ hipError_t launch_blend_forward(const uint2* ranges, const uint32_t* vals, const
                                 const SetDev& st, float* image, float* t_final, uint32_t* last, hipStream_t s) {
   const uint32_t tiles = (uint32_t)cam.tiles_x * (uint32_t)cam.tiles_y;
   if (tiles == 0) return hipSuccess;
-  k_blend_fwd<<<tiles, kBlock, 0, s>>>(ranges, vals, rec, cam, st, image, t_final, last);
+  k_blend_fwd<<<tiles, kWave, 0, s>>>(ranges, vals, rec, cam, st, image, t_final, last);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Sum of v[0..7] over the 64 lanes: on return, lane l holds the total of value
-// 4*b0 + 2*b1 + b2 where b0, b1, b2 are the low bits of l.
+// Cross-lane sums on the VALU (no LDS round trip): DPP quad_perm / row_ror /
+// row_shr within 16-lane rows, and the gfx950 permlane swaps across rows
+// (called with the same register twice, the two outputs hold a lane's value
+// and its partner's, so their sum is the pair sum).
+template <int CTRL, bool BOUND_ZERO = false>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, BOUND_ZERO));
+}
+constexpr int kQuadXor1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kRowRor4 = 0x124;
+constexpr int kRowRor8 = 0x128;   // within a 16-lane row: lane l <- l ^ 8
+constexpr int kRowShr4 = 0x114;   // lane l <- l - 4 (0 for the first 4 lanes of a row)
+
+__device__ __forceinline__ float pair16(float x) {
+  const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+__device__ __forceinline__ float pair32(float x) {
+  const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+
+// Sum of v[0..7] over the 64 lanes by a transpose butterfly: each exchange
+// halves the values a lane carries.  On return, lanes with bit 2 set (l % 8 >= 4)
+// hold the total of value 4*b0 + 2*b1 + b3 (b = bits of the lane index).
 __device__ __forceinline__ float wave_reduce8(const float* v, int lane) {
-  const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
+  const bool b0 = lane & 1, b1 = lane & 2, b3 = lane & 8;
   float r4[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const float send = b0 ? v[j] : v[j + 4];
     const float keep = b0 ? v[j + 4] : v[j];
-    r4[j] = keep + __shfl_xor(send, 1, kWave);
+    r4[j] = keep + dpp<kQuadXor1>(send);
   }
   float r2[2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const float send = b1 ? r4[j] : r4[j + 2];
     const float keep = b1 ? r4[j + 2] : r4[j];
-    r2[j] = keep + __shfl_xor(send, 2, kWave);
+    r2[j] = keep + dpp<kQuadXor2>(send);
   }
-  float r1 = (b2 ? r2[1] : r2[0]) + __shfl_xor(b2 ? r2[0] : r2[1], 4, kWave);
-  r1 += __shfl_xor(r1, 8, kWave);
-  r1 += __shfl_xor(r1, 16, kWave);
-  r1 += __shfl_xor(r1, 32, kWave);
-  return r1;
+  float r1 = (b3 ? r2[1] : r2[0]) + dpp<kRowRor8>(b3 ? r2[0] : r2[1]);
+  r1 += dpp<kRowShr4, true>(r1);  // complete in lanes with bit 2 set
+  r1 = pair16(r1);
+  return pair32(r1);
 }
 
-__device__ __forceinline__ float wave_reduce1(float v) {
-#pragma unroll
-  for (int m = 1; m < kWave; m <<= 1) v += __shfl_xor(v, m, kWave);
-  return v;
+__device__ __forceinline__ float wave_reduce1(float x) {
+  x += dpp<kQuadXor1>(x);
+  x += dpp<kQuadXor2>(x);
+  x += dpp<kRowRor4>(x);
+  x += dpp<kRowRor8>(x);
+  x = pair16(x);
+  return pair32(x);
 }
 
 constexpr int kGrad = 9;  // dL/d(mu2D.x, mu2D.y, a, b, c, opacity, r, g, b)
 
-__global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* __restrict__ ranges,
-                                                      const uint32_t* __restrict__ vals,
-                                                      const float4* __restrict__ rec, CamDev cam, SetDev st,
-                                                      const float* __restrict__ image,
-                                                      const uint32_t* __restrict__ last,
-                                                      const float* __restrict__ dl_dimage,
-                                                      float* __restrict__ accum, uint32_t n) {
-  constexpr int kWaves = kBlock / kWave;
-  __shared__ float4 s_geo[kBlock];
-  __shared__ float4 s_con[kBlock];
-  __shared__ float4 s_col[kBlock];
-  __shared__ uint32_t s_id[kBlock];
-  __shared__ float s_red[kWaves][kBlock][kGrad];
-  __shared__ uint32_t s_max[kWaves];
-
+__global__ __launch_bounds__(kWave) void k_blend_bwd(const uint2* __restrict__ ranges,
+                                                     const uint32_t* __restrict__ vals,
+                                                     const float4* __restrict__ rec, CamDev cam, SetDev st,
+                                                     const float* __restrict__ image,
+                                                     const uint32_t* __restrict__ last,
+                                                     const float* __restrict__ dl_dimage,
+                                                     float* __restrict__ accum, uint32_t n) {
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const int tx = (int)(tile % (uint32_t)cam.tiles_x), ty = (int)(tile / (uint32_t)cam.tiles_x);
-  const int px = tx * kTile + (int)(threadIdx.x % kTile);
-  const int py = ty * kTile + (int)(threadIdx.x / kTile);
-  const bool inside = px < cam.width && py < cam.height;
-  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const uint2 range = ranges[tile];
-
+  const int lane = threadIdx.x;
+  const int px = tx * kTile + (lane % kTile);
+  const float fx = (float)px + 0.5f;
   const size_t hw = (size_t)cam.width * cam.height;
-  const size_t pix = inside ? (size_t)py * cam.width + px : 0;
-  const uint32_t my_last = inside ? last[pix] : 0u;
-  float g0 = 0.f, g1 = 0.f, g2 = 0.f, F0 = 0.f, F1 = 0.f, F2 = 0.f;
-  if (inside) {
-    g0 = dl_dimage[pix]; g1 = dl_dimage[hw + pix]; g2 = dl_dimage[2 * hw + pix];
-    F0 = image[pix]; F1 = image[hw + pix]; F2 = image[2 * hw + pix];
-  }
-  // longest walk in the tile
-  uint32_t m = my_last;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, kWave));
-  if (lane == 0) s_max[wave] = m;
-  __syncthreads();
+  float fy[kRows], gc0[kRows], gc1[kRows], gc2[kRows], gF[kRows];
+  float T[kRows], gS[kRows];
+  uint32_t my_last[kRows];
   uint32_t walk = 0;
 #pragma unroll
-  for (int w = 0; w < kWaves; ++w) walk = max(walk, s_max[w]);
-  const uint32_t end = min(range.x + walk, range.y);
+  for (int r = 0; r < kRows; ++r) {
+    const int py = ty * kTile + lane / kTile + 4 * r;
+    fy[r] = (float)py + 0.5f;
+    T[r] = 1.0f;
+    gS[r] = 0.0f;  // g . S_i, the upstream gradient dotted with the colour blended so far
+    gc0[r] = gc1[r] = gc2[r] = gF[r] = 0.0f;
+    my_last[r] = 0;
+    if (px < cam.width && py < cam.height) {
+      const size_t pix = (size_t)py * cam.width + px;
+      my_last[r] = last[pix];
+      gc0[r] = dl_dimage[pix]; gc1[r] = dl_dimage[hw + pix]; gc2[r] = dl_dimage[2 * hw + pix];
+      // g . C with C the final pixel colour (including T_final * bg)
+      gF[r] = gc0[r] * image[pix] + gc1[r] * image[hw + pix] + gc2[r] * image[2 * hw + pix];
+    }
+    walk = max(walk, my_last[r]);
+  }
+  // longest walk of the tile (wave max)
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) walk = max(walk, (uint32_t)__shfl_xor((int)walk, d, kWave));
+  const uint32_t beg = __builtin_amdgcn_readfirstlane(ranges[tile].x);
+  const uint32_t lim = __builtin_amdgcn_readfirstlane(ranges[tile].y);
+  const uint32_t end = min(beg + __builtin_amdgcn_readfirstlane(walk), lim);
+  // lanes that publish the wave sums: l % 8 >= 4 of the first row hold value 4*b0 + 2*b1 + b3
+  const bool writer = lane < 16 && (lane & 4);
+  const int wq = ((lane & 1) << 2) | (lane & 2) | ((lane >> 3) & 1);
 
-  float T = 1.0f, S0 = 0.f, S1 = 0.f, S2 = 0.f;
-  for (uint32_t start = range.x; start < end; start += kBlock) {
-    __syncthreads();  // the previous batch's LDS is no longer read
-    const uint32_t j = start + threadIdx.x;
-    if (j < end) {
-      const uint32_t gid = vals[j];
-      s_id[threadIdx.x] = gid;
-      s_geo[threadIdx.x] = rec[3 * (size_t)gid + 0];
-      s_con[threadIdx.x] = rec[3 * (size_t)gid + 1];
-      s_col[threadIdx.x] = rec[3 * (size_t)gid + 2];
-    }
-    __syncthreads();
-    const int cnt = (int)min((uint32_t)kBlock, end - start);
+  Batch cur = {}, nxt = {};
+  load_batch(vals, rec, beg, end, lane, cur);
+  for (uint32_t base = beg; base < end; base += kWave) {
+    if (base + kWave < end) load_batch(vals, rec, base + kWave, end, lane, nxt);
+    const int cnt = (int)min((uint32_t)kWave, end - base);
     for (int k = 0; k < cnt; ++k) {
-      const uint32_t pos = start - range.x + (uint32_t)k;
-      const float4 geo = s_geo[k];
-      const float4 con = s_con[k];
-      const float dx = fx - geo.x, dy = fy - geo.y;
-      float G;
-      const float alpha = splat_alpha(dx, dy, con.x, con.y, con.z, geo.z, st.alpha_max, G);
-      const bool contrib = (pos < my_last) && (alpha >= st.alpha_min);
-      float v[kGrad];
-#pragma unroll
-      for (int q = 0; q < kGrad; ++q) v[q] = 0.0f;
-      if (contrib) {
-        const float4 col = s_col[k];
-        const float wgt = alpha * T;
-        v[6] = wgt * g0;
-        v[7] = wgt * g1;
-        v[8] = wgt * g2;
-        S0 = fmaf(wgt, col.x, S0);
-        S1 = fmaf(wgt, col.y, S1);
-        S2 = fmaf(wgt, col.z, S2);
-        const float inv1m = 1.0f / (1.0f - alpha);
-        // dC/dalpha_i = T_i c_i - (C - S_i) / (1 - alpha_i), C including T_final * bg
-        const float dalpha = g0 * (T * col.x - (F0 - S0) * inv1m) + g1 * (T * col.y - (F1 - S1) * inv1m) +
-                             g2 * (T * col.z - (F2 - S2) * inv1m);
-        T = T * (1.0f - alpha);
-        const bool capped = geo.z * G > st.alpha_max;
-        const float dG = capped ? 0.0f : dalpha * geo.z;
-        v[5] = capped ? 0.0f : dalpha * G;
-        const float dpow = dG * G;  // power = -(a dx^2 + 2 b dx dy + c dy^2) / 2
-        v[0] = dpow * (con.x * dx + con.y * dy);
-        v[1] = dpow * (con.y * dx + con.z * dy);
-        v[2] = -0.5f * dpow * dx * dx;
-        v[3] = -dpow * dx * dy;
-        v[4] = -0.5f * dpow * dy * dy;
-      }
-      if (__ballot(contrib) != 0ull) {
-        const float r8 = wave_reduce8(v, lane);
-        const float r1 = wave_reduce1(v[8]);
-        if (lane < 8) s_red[wave][k][((lane & 1) << 2) | (lane & 2) | ((lane >> 2) & 1)] = r8;
-        if (lane == 0) s_red[wave][k][8] = r1;
-      } else if (lane < kGrad) {
-        s_red[wave][k][lane] = 0.0f;
-      }
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < cnt) {
-      const uint32_t gid = s_id[threadIdx.x];
-      float acc[kGrad];
+      const uint32_t pos = base - beg + (uint32_t)k;
+      const Splat sp = splat_of(cur, k);
+      const float cr = bcast(cur.r2.x, k), cg = bcast(cur.r2.y, k), cb = bcast(cur.r2.z, k);
+      const float dx = fx - sp.mx;
+      const float ax = sp.a2 * dx * dx, bx = sp.b2 * dx;
+      // per lane, summed over its four pixels: dL/dG * o (= dL/dpower) times
+      // dx, dy, dx^2, dx dy, dy^2; dL/dG * G (= dL/do); and the colour weights
+      float sP = 0.f, sQ = 0.f, sXX = 0.f, sXY = 0.f, sYY = 0.f, sO = 0.f, w0 = 0.f, w1 = 0.f, w2 = 0.f;
       bool any = false;
+      const float dxx = dx * dx;
 #pragma unroll
-      for (int q = 0; q < kGrad; ++q) {
-        float a = 0.0f;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) a += s_red[w][threadIdx.x][q];
-        acc[q] = a;
-        any |= (a != 0.0f);
+      for (int r = 0; r < kRows; ++r) {  // branch-free: a fragment that is not blended has alpha 0
+        const float dy = fy[r] - sp.my;
+        float G;
+        const float alpha = pixel_alpha(sp, ax, bx, dy, st.alpha_max, G);
+        const bool blend = pos < my_last[r] && alpha >= st.alpha_min;
+        any |= blend;
+        const float a = blend ? alpha : 0.0f;
+        const float wgt = a * T[r];
+        w0 = fmaf(wgt, gc0[r], w0);
+        w1 = fmaf(wgt, gc1[r], w1);
+        w2 = fmaf(wgt, gc2[r], w2);
+        const float gcol = gc0[r] * cr + gc1[r] * cg + gc2[r] * cb;
+        gS[r] = fmaf(wgt, gcol, gS[r]);
+        // dC/dalpha_i . g = T_i (g . c_i) - (g . C - g . S_i) / (1 - alpha_i)
+        const float dalpha = fmaf(-(gF[r] - gS[r]), __builtin_amdgcn_rcpf(1.0f - alpha), T[r] * gcol);
+        T[r] = T[r] * (1.0f - a);
+        // a capped alpha carries no gradient to o or G
+        const float dGG = (blend && !(sp.o * G > st.alpha_max)) ? dalpha * G : 0.0f;
+        sO += dGG;
+        const float dpow = dGG * sp.o;  // dL/dpower, power = -(a dx^2 + 2 b dx dy + c dy^2) / 2
+        sP = fmaf(dpow, dx, sP);
+        sQ = fmaf(dpow, dy, sQ);
+        sXX = fmaf(dpow, dxx, sXX);
+        sXY = fmaf(dpow, dx * dy, sXY);
+        sYY = fmaf(dpow, dy * dy, sYY);
       }
-      if (any) {
-#pragma unroll
-        for (int q = 0; q < kGrad; ++q)
-          if (acc[q] != 0.0f) unsafeAtomicAdd(accum + (size_t)q * n + gid, acc[q]);
-      }
+      float v[kGrad];
+      v[0] = sp.a * sP + sp.b * sQ;   // dL/dmu2D.x
+      v[1] = sp.b * sP + sp.c * sQ;   // dL/dmu2D.y
+      v[2] = -0.5f * sXX;             // dL/da
+      v[3] = -sXY;                    // dL/db
+      v[4] = -0.5f * sYY;             // dL/dc
+      v[5] = sO;                      // dL/do
+      v[6] = w0; v[7] = w1; v[8] = w2;
+      if (__ballot(any) == 0ull) continue;  // no pixel of the tile blends this fragment
+      const float r8 = wave_reduce8(v, lane);
+      const float r1 = wave_reduce1(v[8]);
+      const uint32_t gid = (uint32_t)__builtin_amdgcn_readlane((int)cur.gid, k);
+      if (writer && r8 != 0.0f) unsafeAtomicAdd(accum + (size_t)wq * n + gid, r8);
+      if (lane == 0 && r1 != 0.0f) unsafeAtomicAdd(accum + (size_t)8 * n + gid, r1);
     }
+    cur = nxt;
   }
 }
 
@@ -252,7 +325,7 @@ hipError_t launch_blend_backward(const uint2* ranges, const uint32_t* vals, cons
                                  float* accum, uint32_t n, hipStream_t s) {
   const uint32_t tiles = (uint32_t)cam.tiles_x * (uint32_t)cam.tiles_y;
   if (tiles == 0 || n == 0) return hipSuccess;
-  k_blend_bwd<<<tiles, kBlock, 0, s>>>(ranges, vals, rec, cam, st, image, last, dl_dimage, accum, n);
+  k_blend_bwd<<<tiles, kWave, 0, s>>>(ranges, vals, rec, cam, st, image, last, dl_dimage, accum, n);
   return hipGetLastError();
 }
 

@@ -133,7 +133,6 @@ fgs_status make_layout(int64_t n, const fgs_camera* cam, const fgs_settings* st,
   words = std::max(words, radix_scratch_words(uc));
   L->scratch = take(words * 4 + 256);
   L->total = off;
-  L->vis_final = 0;  // the 32-bit depth sort takes 4 passes
   L->inst_final = ((tile_key_bits((uint64_t)tiles) + kRadixBits - 1) / kRadixBits) & 1;
   L->tiles_x = (int32_t)tx;
   L->tiles_y = (int32_t)ty;
@@ -259,36 +258,50 @@ fgs_status fgs_rasterize_forward(const fgs_gaussians* g, const fgs_camera* cam, 
   uint2* ranges = at<uint2>(workspace, L.ranges);
   uint32_t* scratch = at<uint32_t>(workspace, L.scratch);
 
-  uint32_t host_counts[2] = {0, 0};
+  // One host synchronisation, right after the preprocess: the visible count,
+  // the instance count I and the depth-key range size every later launch.
+  uint32_t stats_host[8] = {0, 0xffffffffu, 0, 0, 0, 0, 0, 0};
   if (n > 0) {
     FGS_HIP(launch_preprocess(gd, cd, sd, st->tile, rec, rect, n_tiles, depth_key, hs), "preprocess");
-    // visible compaction (prefix sum, so index order is kept) and the depth sort
-    FGS_HIP(scan_u32(SCAN_NONZERO, n_tiles, nullptr, nullptr, offsets, n, counters + 0, scratch, hs), "scan");
-    FGS_HIP(launch_compact_visible(n_tiles, depth_key, n, offsets, vis_keys[0], vis_ids[0], hs), "compact");
-    int vis_final = 0;
-    FGS_HIP(radix_sort_pairs(vis_keys, vis_ids, n, counters + 0, 0, 32, scratch, &vis_final, hs), "depth sort");
-    if (vis_final != L.vis_final) return fail(FGS_ERR_HIP, "internal: depth sort buffer mismatch");
-    // instance offsets in depth order; I = total
-    FGS_HIP(scan_u32(SCAN_GATHER, n_tiles, vis_ids[vis_final], counters + 0, offsets, n, counters + 1, scratch, hs),
-            "offset scan");
-    FGS_HIP(hipMemcpyAsync(host_counts, counters, sizeof(host_counts), hipMemcpyDeviceToHost, hs), "count copy");
-    FGS_HIP(hipStreamSynchronize(hs), "count sync");
+    FGS_HIP(launch_stats(n_tiles, depth_key, n, counters, hs), "stats");
+    FGS_HIP(hipMemcpyAsync(stats_host, counters, sizeof(stats_host), hipMemcpyDeviceToHost, hs), "stats copy");
+    FGS_HIP(hipStreamSynchronize(hs), "stats sync");
   }
-  const uint32_t nvis = host_counts[0], inst = host_counts[1];
+  const uint32_t nvis = stats_host[kStatVisible];
+  uint64_t inst64 = 0;
+  std::memcpy(&inst64, stats_host + kStatInstances, sizeof(inst64));
   if (stats) {
     stats->n_visible = nvis;
-    stats->n_instances = inst;
+    stats->n_instances = (int64_t)inst64;
     stats->tiles_x = L.tiles_x;
     stats->tiles_y = L.tiles_y;
   }
-  if ((int64_t)inst > instance_capacity)
-    return fail(FGS_ERR_CAPACITY, "%u instances exceed the capacity of %lld", inst, (long long)instance_capacity);
+  if (inst64 > (uint64_t)instance_capacity)
+    return fail(FGS_ERR_CAPACITY, "%llu instances exceed the capacity of %lld", (unsigned long long)inst64,
+                (long long)instance_capacity);
+  const uint32_t inst = (uint32_t)inst64;
+
+  int vis_final = 0;
+  if (nvis > 0) {
+    // visible compaction (prefix sum, so index order is kept) and the depth
+    // sort over the key bits that vary among the visible Gaussians
+    FGS_HIP(scan_u32(SCAN_NONZERO, n_tiles, nullptr, nullptr, offsets, n, nullptr, scratch, hs), "scan");
+    FGS_HIP(launch_compact_visible(n_tiles, depth_key, n, offsets, vis_keys[0], vis_ids[0], hs), "compact");
+    const uint32_t diff = stats_host[kStatKeyMin] ^ stats_host[kStatKeyMax];
+    const int depth_bits = diff ? 32 - __builtin_clz(diff) : 0;
+    FGS_HIP(radix_sort_pairs(vis_keys, vis_ids, nvis, nullptr, 0, depth_bits, scratch, &vis_final, hs),
+            "depth sort");
+    FGS_HIP(launch_set_word(counters + kStatDepthBuf, (uint32_t)vis_final, hs), "depth buffer note");
+    // instance offsets in depth order
+    FGS_HIP(scan_u32(SCAN_GATHER, n_tiles, vis_ids[vis_final], counters + kStatVisible, offsets, nvis, nullptr,
+                     scratch, hs), "offset scan");
+  }
 
   const size_t tiles = (size_t)L.tiles_x * L.tiles_y;
   FGS_HIP(hipMemsetAsync(ranges, 0, tiles * sizeof(uint2), hs), "ranges clear");
   if (inst > 0) {
-    FGS_HIP(launch_duplicate(vis_ids[L.vis_final], counters + 0, n, offsets, rec, rect, n_tiles, cd, st->tile,
-                             (uint32_t)instance_capacity, ikeys[0], ivals[0], hs),
+    FGS_HIP(launch_duplicate(vis_ids[vis_final], counters + kStatVisible, nvis, offsets, rec, rect, n_tiles, cd,
+                             st->tile, (uint32_t)instance_capacity, ikeys[0], ivals[0], hs),
             "duplicate");
     int inst_final = 0;
     FGS_HIP(radix_sort_pairs(ikeys, ivals, inst, nullptr, 0, tile_key_bits(tiles), scratch, &inst_final, hs),

@@ -1,6 +1,6 @@
 // Internal declarations shared by the HIP translation units of libfastergs.
 // Device helpers here are header-only so that every kernel that needs the same
-// decision (tile test, alpha) runs the identical instruction sequence.
+// decision (the tile test) runs the identical instruction sequence.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -91,13 +91,17 @@ __device__ __forceinline__ bool tile_keep(float mx, float my, float a, float b, 
   const float y0 = (float)(ty * tile) + 0.5f;
   const float y1 = (float)min(ty * tile + tile - 1, height - 1) + 0.5f;
   const bool left = mx < x0, right = mx > x1, top = my < y0, bottom = my > y1;
-  if (!(left || right || top || bottom)) return true;  // min is 0 inside the hull
-  float q = __builtin_huge_valf();
-  if (left) q = fminf(q, edge_min_q(a, b, c, x0 - mx, my, y0, y1, true));
-  if (right) q = fminf(q, edge_min_q(a, b, c, x1 - mx, my, y0, y1, true));
-  if (top) q = fminf(q, edge_min_q(a, b, c, y0 - my, mx, x0, x1, false));
-  if (bottom) q = fminf(q, edge_min_q(a, b, c, y1 - my, mx, x0, x1, false));
-  return q <= thr;
+  // All four edges are evaluated and the facing ones selected (no divergent
+  // branches); the minimum is 0 inside the hull.
+  const float qL = edge_min_q(a, b, c, x0 - mx, my, y0, y1, true);
+  const float qR = edge_min_q(a, b, c, x1 - mx, my, y0, y1, true);
+  const float qT = edge_min_q(a, b, c, y0 - my, mx, x0, x1, false);
+  const float qB = edge_min_q(a, b, c, y1 - my, mx, x0, x1, false);
+  const float inf = __builtin_huge_valf();
+  float q = fminf(left ? qL : inf, right ? qR : inf);
+  q = fminf(q, fminf(top ? qT : inf, bottom ? qB : inf));
+  const bool inside = !(left || right || top || bottom);
+  return inside || q <= thr;
 }
 
 // Decode the packed tile rectangle.
@@ -106,19 +110,6 @@ __device__ __forceinline__ void unpack_rect(uint2 r, int& tx0, int& ty0, int& tx
   ty0 = (int)(r.x >> 16);
   tx1 = (int)(r.y & 0xffffu);
   ty1 = (int)(r.y >> 16);
-}
-
-// ----------------------------------------------------------------------------
-// Alpha of one fragment (Eq. (3) with the dilated conic, capped at alpha_max).
-// Shared by the forward and backward blend so both take identical decisions.
-// Returns alpha; g receives exp(power) and `power` the exponent.
-// ----------------------------------------------------------------------------
-__device__ __forceinline__ float splat_alpha(float dx, float dy, float a, float b, float c, float o,
-                                             float alpha_max, float& g) {
-#pragma clang fp contract(off)
-  const float quad = __builtin_fmaf(a * dx, dx, __builtin_fmaf(c * dy, dy, (b + b) * (dx * dy)));
-  g = __expf(-0.5f * quad);
-  return fminf(alpha_max, o * g);
 }
 
 // ----------------------------------------------------------------------------
@@ -159,6 +150,83 @@ __device__ __forceinline__ uint32_t block_reduce_sum(uint32_t v, uint32_t* lds) 
   return t;
 }
 
+// ----------------------------------------------------------------------------
+// Load-balanced walk over candidate tiles (wave64).  Each lane holds one
+// Gaussian and its candidate tiles (the tile rectangle, row-major).  The wave
+// visits all candidates of its 64 Gaussians 64 at a time, in (lane, tile)
+// order, so every lane tests one candidate per step whatever the rectangle
+// sizes.  Every step calls emit(owner_lane, rank, tx, ty, keep) in all lanes
+// (uniform control flow, so emit may use cross-lane shuffles); for a kept tile
+// rank is its index among the owner's kept tiles, so consecutive kept tiles of
+// the wave map to consecutive output slots.  Returns,
+// in each lane, the number of kept tiles of its own Gaussian.
+// `owner_at` is 64 words of LDS private to the wave.
+// ----------------------------------------------------------------------------
+struct CandLane {
+  float mx, my, a, b, c, thr;
+  int tx0, ty0, w;  // rectangle origin and width in tiles
+  uint32_t cand;    // candidate tiles (0: none)
+};
+
+__device__ __forceinline__ uint32_t udiv_small(uint32_t r, uint32_t w) {
+  uint32_t q = (uint32_t)((float)r * __builtin_amdgcn_rcpf((float)w));
+  if (q * w > r) --q;
+  if ((q + 1) * w <= r) ++q;
+  return q;
+}
+
+template <typename Emit>
+__device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, volatile uint32_t* owner_at, int tile,
+                                                   int width, int height, Emit emit) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t incl = wave_inclusive_scan(me.cand, lane);
+  const uint32_t cstart = incl - me.cand;
+  const uint32_t total = __shfl(incl, kWave - 1, kWave);
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const uint64_t upto = below | (1ull << lane);
+  uint32_t kept = 0;
+  uint32_t tag = 0;
+  owner_at[lane] = 0xffffffffu;  // no step tag matches
+  for (uint32_t c0 = 0; c0 < total; c0 += kWave, tag += 0x100u) {
+    // the Gaussian whose candidates start in (or run into) this step claims its first slot
+    const bool claims = me.cand > 0 && cstart < c0 + kWave && cstart + me.cand > c0;
+    const uint32_t slot = cstart > c0 ? cstart - c0 : 0u;
+    if (claims) owner_at[slot] = tag | (uint32_t)lane;
+    const uint32_t mine = owner_at[lane];
+    const uint64_t claimed = __ballot((mine & ~0xffu) == tag);
+    const uint64_t m = claimed & upto;
+    const int src_slot = m ? 63 - __clzll(m) : 0;
+    const int owner = (int)(owner_at[src_slot] & 0xffu);
+    const uint32_t pos = c0 + (uint32_t)lane;
+    const bool valid = pos < total;
+    const uint32_t o_cstart = __shfl(cstart, owner, kWave);
+    const uint32_t o_kept = __shfl(kept, owner, kWave);
+    const int o_w = __shfl(me.w, owner, kWave);
+    const uint32_t r = pos - o_cstart;
+    const uint32_t ry = udiv_small(r, (uint32_t)o_w);
+    const int tx = __shfl(me.tx0, owner, kWave) + (int)(r - ry * (uint32_t)o_w);
+    const int ty = __shfl(me.ty0, owner, kWave) + (int)ry;
+    // Every cross-lane read happens with all lanes active: a lane past the
+    // end of the candidates may still own the Gaussian another lane reads.
+    const float o_mx = __shfl(me.mx, owner, kWave), o_my = __shfl(me.my, owner, kWave);
+    const float o_a = __shfl(me.a, owner, kWave), o_b = __shfl(me.b, owner, kWave);
+    const float o_c = __shfl(me.c, owner, kWave), o_thr = __shfl(me.thr, owner, kWave);
+    const bool keep = tile_keep(o_mx, o_my, o_a, o_b, o_c, o_thr, tx, ty, tile, width, height) & valid;
+    const uint64_t kb = __ballot(keep);
+    const uint32_t first = o_cstart > c0 ? o_cstart - c0 : 0u;
+    const uint64_t from_first = first >= 64 ? 0ull : ~((first == 0) ? 0ull : (~0ull >> (64 - first)));
+    emit(owner, o_kept + (uint32_t)__popcll(kb & below & from_first), tx, ty, keep);  // uniform call
+    // this lane's Gaussian: add the kept tiles of its segment in this step
+    if (claims) {
+      const uint32_t lo = slot;
+      const uint32_t hi = min(cstart + me.cand - c0, (uint32_t)kWave);  // exclusive
+      const uint64_t seg = (hi >= 64 ? ~0ull : ((1ull << hi) - 1ull)) & ~((lo == 0) ? 0ull : ((1ull << lo) - 1ull));
+      kept += (uint32_t)__popcll(kb & seg);
+    }
+  }
+  return kept;
+}
+
 inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 // ----------------------------------------------------------------------------
@@ -184,6 +252,15 @@ hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], uint32_t n, co
 hipError_t launch_preprocess(const GaussDev& g, const CamDev& cam, const SetDev& st, int tile,
                              float4* rec, uint2* rect, uint32_t* n_tiles, uint32_t* depth_key,
                              hipStream_t s);
+// Slots of the workspace counters (uint32 words).
+constexpr int kStatVisible = 0;    // visible Gaussians
+constexpr int kStatKeyMin = 1;     // smallest visible depth key
+constexpr int kStatKeyMax = 2;     // largest visible depth key
+constexpr int kStatDepthBuf = 3;   // ping-pong buffer holding the depth-sorted visible ids
+constexpr int kStatInstances = 4;  // instance count I, uint64 at words 4-5
+hipError_t launch_set_word(uint32_t* p, uint32_t v, hipStream_t s);
+hipError_t launch_stats(const uint32_t* n_tiles, const uint32_t* depth_key, uint32_t n, uint32_t* counters,
+                        hipStream_t s);
 hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth_key, uint32_t n,
                                   const uint32_t* pos, uint32_t* vis_keys, uint32_t* vis_ids,
                                   hipStream_t s);

@@ -64,8 +64,10 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, CamDev cam, S
                                                        uint32_t* __restrict__ n_tiles,
                                                        uint32_t* __restrict__ depth_key) {
 #pragma clang fp contract(off)
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= g.n) return;
+  __shared__ uint32_t s_owner[kBlock / kWave][kWave];
+  const uint32_t i0 = blockIdx.x * kBlock + threadIdx.x;
+  const bool in_range = i0 < g.n;
+  const uint32_t i = in_range ? i0 : g.n - 1;  // lanes past the end mirror the last Gaussian, then drop it
   const size_t n = g.n;
   const float* W = cam.w;
 
@@ -73,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, CamDev cam, S
   const float X = ((W[0] * mu0 + W[1] * mu1) + W[2] * mu2) + W[3];
   const float Yc = ((W[4] * mu0 + W[5] * mu1) + W[6] * mu2) + W[7];
   const float Z = ((W[8] * mu0 + W[9] * mu1) + W[10] * mu2) + W[11];
-  depth_key[i] = __float_as_uint(Z);
+  if (in_range) depth_key[i] = __float_as_uint(Z);
 
   // activations: normalised quaternion, exp scales, sigmoid opacity
   const float qw0 = g.quats[i], qx0 = g.quats[n + i], qy0 = g.quats[2 * n + i], qz0 = g.quats[3 * n + i];
@@ -134,21 +136,26 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, CamDev cam, S
   const float lx = (mx - ext_x) - 0.5f, hx = (mx + ext_x) - 0.5f;
   const float ly = (my - ext_y) - 0.5f, hy = (my + ext_y) - 0.5f;
   const float wm1 = (float)(cam.width - 1), hm1 = (float)(cam.height - 1);
-  bool nonempty = ok && (hx >= 0.0f) && (lx <= wm1) && (hy >= 0.0f) && (ly <= hm1);
-  uint32_t count = 0;
+  bool nonempty = in_range && ok && (hx >= 0.0f) && (lx <= wm1) && (hy >= 0.0f) && (ly <= hm1);
+  CandLane me = {mx, my, ca, cb, cc, thr, 0, 0, 1, 0u};
   if (nonempty) {
-    const int i0 = (lx <= 0.0f) ? 0 : (int)ceilf(lx);
-    const int i1 = (hx >= wm1) ? cam.width - 1 : (int)floorf(hx);
+    const int i0x = (lx <= 0.0f) ? 0 : (int)ceilf(lx);
+    const int i1x = (hx >= wm1) ? cam.width - 1 : (int)floorf(hx);
     const int k0 = (ly <= 0.0f) ? 0 : (int)ceilf(ly);
     const int k1 = (hy >= hm1) ? cam.height - 1 : (int)floorf(hy);
-    if (i0 <= i1 && k0 <= k1) {
-      const int tx0 = i0 / tile, tx1 = i1 / tile, ty0 = k0 / tile, ty1 = k1 / tile;
-      for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx)
-          count += tile_keep(mx, my, ca, cb, cc, thr, tx, ty, tile, cam.width, cam.height) ? 1u : 0u;
+    if (i0x <= i1x && k0 <= k1) {
+      const int tx0 = i0x / tile, tx1 = i1x / tile, ty0 = k0 / tile, ty1 = k1 / tile;
+      me.tx0 = tx0;
+      me.ty0 = ty0;
+      me.w = tx1 - tx0 + 1;
+      me.cand = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
       rect[i] = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
     }
   }
+  // exact per-tile test of every candidate tile, load-balanced over the wave
+  const uint32_t count = wave_tile_walk(me, s_owner[threadIdx.x / kWave], tile, cam.width, cam.height,
+                                        [](int, uint32_t, int, int, bool) {});
+  if (!in_range) return;
   n_tiles[i] = count;
   if (count == 0) return;
 
@@ -163,6 +170,80 @@ hipError_t launch_preprocess(const GaussDev& g, const CamDev& cam, const SetDev&
                              uint2* rect, uint32_t* n_tiles, uint32_t* depth_key, hipStream_t s) {
   if (g.n == 0) return hipSuccess;
   k_preprocess<<<ceil_div(g.n, kBlock), kBlock, 0, s>>>(g, cam, st, tile, rec, rect, n_tiles, depth_key);
+  return hipGetLastError();
+}
+
+// Statistics the host needs to size the rest of the pass: visible count,
+// instance count I (= the sum of the per-Gaussian counts, independent of the
+// depth order) and the range of the visible depth keys.
+__global__ void k_init_stats(uint32_t* __restrict__ c) {
+  if (threadIdx.x == 0) {
+    c[kStatVisible] = 0u;
+    c[kStatKeyMin] = 0xffffffffu;
+    c[kStatKeyMax] = 0u;
+    c[kStatDepthBuf] = 0u;
+    reinterpret_cast<unsigned long long*>(c + kStatInstances)[0] = 0ull;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_stats(const uint32_t* __restrict__ n_tiles,
+                                                  const uint32_t* __restrict__ depth_key, uint32_t n,
+                                                  uint32_t* __restrict__ c) {
+  __shared__ uint32_t s_vis[kBlock / kWave], s_min[kBlock / kWave], s_max[kBlock / kWave];
+  __shared__ unsigned long long s_sum[kBlock / kWave];
+  uint32_t vis = 0, kmin = 0xffffffffu, kmax = 0u;
+  unsigned long long sum = 0;
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const uint32_t t = n_tiles[i];
+    if (t != 0) {
+      const uint32_t k = depth_key[i];
+      ++vis;
+      sum += t;
+      kmin = min(kmin, k);
+      kmax = max(kmax, k);
+    }
+  }
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    vis += __shfl_xor(vis, d, kWave);
+    sum += __shfl_xor(sum, d, kWave);
+    kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, d, kWave));
+    kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, d, kWave));
+  }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  if (lane == 0) {
+    s_vis[wave] = vis; s_min[wave] = kmin; s_max[wave] = kmax; s_sum[wave] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / kWave; ++w) {
+      vis += s_vis[w]; sum += s_sum[w]; kmin = min(kmin, s_min[w]); kmax = max(kmax, s_max[w]);
+    }
+    if (vis) {
+      atomicAdd(c + kStatVisible, vis);
+      atomicMin(c + kStatKeyMin, kmin);
+      atomicMax(c + kStatKeyMax, kmax);
+      atomicAdd(reinterpret_cast<unsigned long long*>(c + kStatInstances), sum);
+    }
+  }
+}
+
+__global__ void k_set_word(uint32_t* __restrict__ p, uint32_t v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+hipError_t launch_set_word(uint32_t* p, uint32_t v, hipStream_t s) {
+  k_set_word<<<1, kWave, 0, s>>>(p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats(const uint32_t* n_tiles, const uint32_t* depth_key, uint32_t n, uint32_t* counters,
+                        hipStream_t s) {
+  k_init_stats<<<1, kWave, 0, s>>>(counters);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n == 0) return e;
+  const uint32_t blocks = min(ceil_div(n, kBlock * 8), 2048u);
+  k_stats<<<blocks, kBlock, 0, s>>>(n_tiles, depth_key, n, counters);
   return hipGetLastError();
 }
 
@@ -188,8 +269,11 @@ hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth
   return hipGetLastError();
 }
 
-// Each visible Gaussian, in depth order, writes its kept tiles (row-major in
-// its rectangle) at its offset; writes never pass its own count nor `cap`.
+// Each visible Gaussian, in depth order, writes its kept tiles at its offset.
+// A wave handles 64 consecutive Gaussians and spreads their candidate tiles
+// over its lanes (load-balanced walk), so the wave's kept tiles are written as
+// one contiguous, coalesced run.  Writes never pass a Gaussian's own count nor
+// `cap`.
 __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict__ vis_ids,
                                                       const uint32_t* __restrict__ d_nvis, uint32_t n,
                                                       const uint32_t* __restrict__ offsets,
@@ -198,30 +282,42 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
                                                       const uint32_t* __restrict__ n_tiles, CamDev cam,
                                                       int tile, uint32_t cap, uint32_t* __restrict__ keys,
                                                       uint32_t* __restrict__ vals) {
+  __shared__ uint32_t s_owner[kBlock / kWave][kWave];
   const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
-  if (p >= min(*d_nvis, n)) return;
-  const uint32_t gid = vis_ids[p];
-  uint32_t off = offsets[p];
-  const uint32_t end = min(off + n_tiles[gid], cap);
-  const float4 r0 = rec[3 * (size_t)gid + 0];
-  const float4 r1 = rec[3 * (size_t)gid + 1];
-  int tx0, ty0, tx1, ty1;
-  unpack_rect(rect[gid], tx0, ty0, tx1, ty1);
-  for (int ty = ty0; ty <= ty1 && off < end; ++ty) {
-    for (int tx = tx0; tx <= tx1 && off < end; ++tx) {
-      if (tile_keep(r0.x, r0.y, r1.x, r1.y, r1.z, r0.w, tx, ty, tile, cam.width, cam.height)) {
-        keys[off] = (uint32_t)(ty * cam.tiles_x + tx);
-        vals[off] = gid;
-        ++off;
-      }
-    }
+  const uint32_t nv = min(*d_nvis, n);
+  if (blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1)) >= nv) return;  // whole wave idle
+  CandLane me = {};
+  uint32_t gid = 0, off = 0, end = 0;
+  if (p < nv) {
+    gid = vis_ids[p];
+    off = offsets[p];
+    end = min(off + n_tiles[gid], cap);
+    const float4 r0 = rec[3 * (size_t)gid + 0];
+    const float4 r1 = rec[3 * (size_t)gid + 1];
+    int tx0, ty0, tx1, ty1;
+    unpack_rect(rect[gid], tx0, ty0, tx1, ty1);
+    me = CandLane{r0.x, r0.y, r1.x, r1.y, r1.z, r0.w, tx0, ty0, tx1 - tx0 + 1,
+                  n_tiles[gid] ? (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1)) : 0u};
   }
-  // The test above repeats the preprocess count on the same stored values, so
-  // this loop never runs; it keeps every slot defined (an out-of-range tile id
+  const uint32_t tiles = (uint32_t)(cam.tiles_x * cam.tiles_y);
+  const uint32_t written = wave_tile_walk(
+      me, s_owner[threadIdx.x / kWave], tile, cam.width, cam.height,
+      [&](int owner, uint32_t rank, int tx, int ty, bool keep) {
+        const uint32_t o_off = __shfl(off, owner, kWave);
+        const uint32_t o_end = __shfl(end, owner, kWave);
+        const uint32_t o_gid = __shfl(gid, owner, kWave);
+        const uint32_t slot = o_off + rank;
+        if (keep && slot < o_end) {
+          keys[slot] = (uint32_t)(ty * cam.tiles_x + tx);
+          vals[slot] = o_gid;
+        }
+      });
+  // The walk repeats the preprocess count on the same stored values, so this
+  // loop never runs; it keeps every slot defined (an out-of-range tile id
   // that the range kernel ignores) should the two ever disagree.
-  for (; off < end; ++off) {
-    keys[off] = (uint32_t)(cam.tiles_x * cam.tiles_y);
-    vals[off] = gid;
+  for (uint32_t slot = off + written; p < nv && slot < end; ++slot) {
+    keys[slot] = tiles;
+    vals[slot] = gid;
   }
 }
 

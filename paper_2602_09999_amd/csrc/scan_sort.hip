@@ -7,7 +7,8 @@
 // kernel.  The scatter ranks keys stably inside a workgroup with wave64
 // ballots: the 64 lanes of a wave find the lanes sharing their digit with 8
 // ballots, count the ones below them, and keep a running per-digit counter
-// per wave in LDS; wave offsets are then prefixed in wave order.
+// per wave in LDS; wave offsets are then prefixed in wave order.  The ranked
+// block is staged in LDS in digit order and written out in coalesced runs.
 #include "fgs_internal.h"
 
 namespace fgs {
@@ -125,6 +126,10 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restric
   hist[(size_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
+// Scatter of one radix pass.  Each workgroup ranks its 4096 keys stably
+// (wave ballots + per-wave digit counters), places them in LDS in
+// (digit, input order) order, and then writes them out so that consecutive
+// threads store consecutive addresses of each digit's run.
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __restrict__ keys_in,
                                                           const uint32_t* __restrict__ vals_in,
                                                           uint32_t* __restrict__ keys_out,
@@ -134,15 +139,20 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
                                                           uint32_t nb) {
   constexpr int kWaves = kBlock / kWave;
   __shared__ uint32_t wcnt[kWaves][kRadix];
-  __shared__ uint32_t gbase[kRadix];
+  __shared__ uint32_t gdelta[kRadix];  // global start of the digit minus its block-local start (mod 2^32)
+  __shared__ uint32_t lstart[kRadix];  // block-local start of each digit
+  __shared__ uint32_t s_key[kScanTile];
+  __shared__ uint32_t s_val[kScanTile];
+  __shared__ uint32_t scan_lds[kBlock / kWave];
   const uint32_t count = d_count ? min(*d_count, n) : n;
   const uint32_t base = blockIdx.x * kScanTile;
   if (base >= count) return;  // uniform for the whole workgroup
+  const uint32_t in_block = min((uint32_t)kScanTile, count - base);
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) wcnt[w][threadIdx.x] = 0;
-  gbase[threadIdx.x] = hist_scan[(size_t)threadIdx.x * nb + blockIdx.x];
+  const uint32_t gbase = hist_scan[(size_t)threadIdx.x * nb + blockIdx.x];
   __syncthreads();
 
   // Wave w owns items [base + w*1024, base + (w+1)*1024), visited 64 at a time
@@ -173,6 +183,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
   }
   __syncthreads();
   {
+    // thread t = digit t: prefix over waves, block-local digit start, global offset
     uint32_t run = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) {
@@ -180,6 +191,10 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
       wcnt[w][threadIdx.x] = run;
       run += t;
     }
+    uint32_t tot;
+    const uint32_t ls = block_exclusive_scan(run, scan_lds, &tot);
+    lstart[threadIdx.x] = ls;
+    gdelta[threadIdx.x] = gbase - ls;
   }
   __syncthreads();
 #pragma unroll
@@ -187,9 +202,21 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
     const uint32_t i = wbase + k * kWave + lane;
     if (i < count) {
       const uint32_t d = (key[k] >> shift) & (kRadix - 1);
-      const uint32_t pos = gbase[d] + wcnt[wave][d] + rank[k];
-      keys_out[pos] = key[k];
-      vals_out[pos] = val[k];
+      const uint32_t lp = lstart[d] + wcnt[wave][d] + rank[k];
+      s_key[lp] = key[k];
+      s_val[lp] = val[k];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint32_t j = k * kBlock + threadIdx.x;
+    if (j < in_block) {
+      const uint32_t kk = s_key[j];
+      const uint32_t d = (kk >> shift) & (kRadix - 1);
+      const uint32_t pos = gdelta[d] + j;  // = gbase[d] + (j - lstart[d])
+      keys_out[pos] = kk;
+      vals_out[pos] = s_val[j];
     }
   }
 }
