@@ -61,20 +61,23 @@ def algorithmic_bytes(n, n_touched, i_proc, pixels):
     return {"adam": adam, "bwd": blend_bwd + pre_bwd, "blend_bwd": blend_bwd, "pre_bwd": pre_bwd}
 
 
-def source_digest(path: str) -> str:
+def source_digest(files) -> str:
     import hashlib
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_2602_09999_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(path: str, kernel: str, workload: str):
-    """HBM bytes per launch from the committed counter summary, or None when
-    missing or taken on a different version of the kernel's source file."""
+    """HBM bytes per launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE, each scaled by a calibration kernel of known traffic), or None
+    when missing or taken on a different version of the kernel's sources."""
     if not os.path.exists(path):
         return None
     try:
         ent = json.load(open(path))["kernels"][kernel][workload]
-        src = os.path.join(ROOT, "paper_2602_09999_amd", "csrc", ent["source"])
-        if source_digest(src) != ent["source_sha256_16"]:
+        if source_digest(ent["source"]) != ent["source_sha256_16"]:
             return None
         return float(ent["bytes_per_launch"])
     except (KeyError, ValueError, OSError, TypeError):
@@ -152,11 +155,13 @@ def main():
     dl = torch.empty_like(image)
     grads = {k: torch.empty_like(v) for k, v in params.items()}
     if args.calibrate_copy_mib > 0:
+        # a plain elementwise kernel (torch.neg) of known traffic: it reads and
+        # writes exactly calibrate_copy_mib MiB, so HBM counters can be scaled
         src = torch.ones(args.calibrate_copy_mib << 18, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.neg(src, out=dst)
         torch.cuda.synchronize()
-        log(f"calibration copy: {args.calibrate_copy_mib} MiB read + {args.calibrate_copy_mib} MiB written")
+        log(f"calibration kernel (neg): {args.calibrate_copy_mib} MiB read + {args.calibrate_copy_mib} MiB written")
         del src, dst
     torch.cuda.synchronize()
 
