@@ -4,14 +4,23 @@
 A step is the whole hot path on one view: forward rasterization (preprocess,
 compaction, depth sort, duplication, tile sort, ranges, blend), the L1 loss
 gradient, the backward pass (blend backward, preprocess backward) and the
-fused Adam update of all 59 parameters of every Gaussian.  Inputs are seeded
+Adam update of all 59 parameters of every Gaussian.  Inputs are seeded
 synthetic scenes resident in HBM before timing starts.
 
+Variants: the backward pass fused with Adam (Sec. 3.3: gradients chained and
+applied without a gradient buffer, the zero-gradient step streamed) or
+followed by the separate Adam kernel; float32 or bfloat16 SH coefficients;
+the Gaussians in z-order (the layout training keeps them in, re-sorted every
+few thousand iterations; Sec. 3.3) or in the generator's random order.  The
+first variant (default: fused, float32, z-ordered) gives the reported value;
+all are listed, with the cost of the layout step.
+
 Prints ONE JSON line.  Per-phase times come from HIP events recorded on the
-stream the kernels are launched on; the roofline block reports the dominant
-kernel (the fused Adam launch, one kernel per step) against the 8 TB/s HBM
-peak.  The CPU baseline times the FP64 oracle on a bounded sample of the same
-workload on the host cores and extrapolates to one step.
+stream the kernels are launched on; the dominant kernel's own duration comes
+from events the library records around it (fgs_time_next_launch), and the
+roofline block relates its algorithmic bytes to the 8 TB/s HBM peak.  The CPU
+baseline times the FP64 oracle on a bounded sample of the same workload on
+the host cores and extrapolates to one step.
 """
 from __future__ import annotations
 
@@ -45,7 +54,9 @@ def parse():
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured with rocprofv3 counters (optional)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
-                    help="run one device copy of this many MiB first (reference kernel for counters)")
+                    help="run one elementwise kernel over this many MiB first (reference for counters)")
+    ap.add_argument("--variants", default=",".join(VARIANTS),
+                    help="comma-separated variants to time; the first is the reported value")
     return ap.parse_args()
 
 
@@ -127,6 +138,137 @@ def cpu_baseline(workload: str, seed: int, budget_s: float):
             "seconds_per_step_extrapolated": sec}
 
 
+# name: (backward fused with Adam, SH element type, z-ordered layout); the
+# first is the headline
+VARIANTS = {
+    "fused_f32": (True, torch.float32, True),
+    "unfused_f32": (False, torch.float32, True),
+    "fused_bf16sh": (True, torch.bfloat16, True),
+    "unfused_bf16sh": (False, torch.bfloat16, True),
+    "fused_f32_unordered": (True, torch.float32, False),
+}
+ZORDER_EVERY = 5000  # iterations between z-order re-layouts (Sec. 3.3)
+# the step each variant times live with the library's timing hook, and the kernel it is
+TIMED = {True: ("adam_untouched", "k_adam_untouched"), False: ("adam", "k_adam")}
+
+
+def fused_bytes(n, n_touched, sh_bf16):
+    """Algorithmic bytes of the fused backward + Adam kernels.  'touched': the
+    nine accumulators of every Gaussian, the 1-bit marks, and for each Gaussian
+    with a gradient its record plus read and write of p, m, v of its 59
+    parameters.  'untouched': the zero-gradient step, i.e. read and write of
+    p, m, v of every parameter of all other Gaussians (SH planes at 2 bytes per
+    parameter when bfloat16) and the marks."""
+    sh = 48 * (2 * 2 + 16) if sh_bf16 else 48 * 24
+    per = 11 * 24 + sh
+    touched = n * 36 + n // 4 + n_touched * (48 + per)
+    untouched = (n - n_touched) * per + n // 4
+    return {"touched": touched, "untouched": untouched}
+
+
+def adam_bytes(n, sh_bf16):
+    """Algorithmic bytes of the separate Adam kernel: read p, g, m, v; write p, m, v."""
+    sh = 48 * (3 * 2 + 16 + 0) if sh_bf16 else 48 * 28
+    return n * (11 * 28 + sh)
+
+
+def run_variant(name, args, scene, cam, target, dev, w):
+    import paper_2602_09999_amd as P
+    from paper_2602_09999_amd import binding as B
+    fused, shd, zorder = VARIANTS[name]
+    params = {k: v.to(dev) for k, v in scene.items()}
+    for k in ("sh_dc", "sh_rest"):
+        params[k] = params[k].to(shd).contiguous()
+    rz = B.Rasterizer(cam, device=dev)
+    opt = P.FusedAdam(params, S.ADAM_LR)
+    zorder_ms = None
+    if zorder:
+        # the layout step of training (outside the timed region): parameters
+        # and moments re-sorted in Morton order of the means
+        B.apply_zorder(params, opt)  # first call warms up the kernels
+        z0, z1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        z0.record()
+        B.apply_zorder(params, opt)
+        z1.record()
+        torch.cuda.synchronize()
+        zorder_ms = z0.elapsed_time(z1)
+    stream = torch.cuda.current_stream()
+    image = torch.empty(3, w.height, w.width, device=dev)
+    t_final = torch.empty(w.height, w.width, device=dev)
+    last = torch.empty(w.height, w.width, dtype=torch.int32, device=dev)
+    dl = torch.empty_like(image)
+    grads = None if fused else {k: torch.empty_like(v) for k, v in params.items()}
+    step_name, kernel = TIMED[fused]
+
+    def step(ev=None, kev=None):
+        if kev is not None:
+            B.time_next_launch(step_name, kev[0], kev[1])
+        if ev is not None:
+            ev[0].record(stream)
+        rz.forward(params, image, t_final, last)
+        if ev is not None:
+            ev[1].record(stream)
+        B.l1_loss_backward(image, target, dl)
+        if ev is not None:
+            ev[2].record(stream)
+        if fused:
+            rz.backward_adam(params, image, last, dl, opt)
+        else:
+            rz.backward(params, image, last, dl, grads)
+            if ev is not None:
+                ev[3].record(stream)
+            opt.step(grads)
+        if ev is not None:
+            if fused:
+                ev[3].record(stream)
+            ev[4].record(stream)
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    kevs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    for pair in kevs:  # torch creates events lazily: record each once so the hook can use it
+        for e in pair:
+            e.record(stream)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"{name}: warmup done; N_vis={rz.last_stats.get('n_visible')} I={rz.last_stats.get('n_instances')}")
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k], kevs[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ph = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(4)] for k in range(args.steps)]).mean(0)
+    kms = float(np.mean([kevs[k][0].elapsed_time(kevs[k][1]) for k in range(args.steps)]))
+    ms_step = 1000.0 * elapsed / args.steps
+    names = ("forward", "l1", "backward+adam", "-") if fused else ("forward", "l1", "backward", "adam")
+    phases = {names[j]: float(ph[j]) for j in range(4) if names[j] != "-"}
+    log(f"{name}: ms/step {ms_step:.3f}; " + " ".join(f"{k} {v:.3f}" for k, v in phases.items()) +
+        f"; {kernel} {kms:.3f} ms")
+    return {"steps": args.steps, "elapsed": elapsed, "ms_per_step": ms_step, "steps_per_s": args.steps / elapsed,
+            "phase_ms": phases, "kernel": kernel, "kernel_ms": kms, "rz": rz, "params": params, "last": last,
+            "fused": fused, "sh_bf16": shd == torch.bfloat16, "zorder": zorder, "zorder_ms": zorder_ms}
+
+
+def workload_counts(r, w, dev):
+    """Instance and gradient counts of a finished run (outside any timed region)."""
+    rz, last = r["rz"], r["last"]
+    lay = rz.layout()
+    n = w.n
+    tiles = lay.tiles_x * lay.tiles_y
+    ranges = rz.view("ranges", 2 * tiles).view(torch.int32).view(tiles, 2)
+    lp = torch.zeros(lay.tiles_y * 16, lay.tiles_x * 16, dtype=torch.int64, device=dev)
+    lp[:w.height, :w.width] = last.long()
+    walks = lp.view(lay.tiles_y, 16, lay.tiles_x, 16).amax(dim=(1, 3)).flatten()
+    lens = (ranges[:, 1] - ranges[:, 0]).long()
+    q = torch.tensor([0.5, 0.9, 0.99, 1.0], device=dev).double()
+    log("tile walk p50/p90/p99/max", [int(x) for x in torch.quantile(walks.double(), q)],
+        "list length p50/p90/p99/max", [int(x) for x in torch.quantile(lens.double(), q)],
+        "tiles walking their whole list", int(((walks == lens) & (lens > 0)).sum()))
+    accum = rz.view("accum", 9 * n, dtype=torch.float32).view(9, n)
+    return {"i_proc": int(walks.sum()), "n_touched": int((accum != 0).any(0).sum()),
+            "visible": rz.last_stats.get("n_visible"), "instances": rz.last_stats.get("n_instances")}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -136,24 +278,12 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(2)
-    import paper_2602_09999_amd as P
-    from paper_2602_09999_amd import binding as B
-
     w = S.WORKLOADS[args.workload]
     log(f"workload {w.name}: {w.description}")
     scene = S.make_scene(w.n, seed=args.seed)
     cam = S.workload_camera(args.workload)
     dev = torch.device("cuda", 0)
-    params = {k: v.to(dev) for k, v in scene.items()}
     target = S.make_target(w.height, w.width, seed=args.seed).to(dev)
-    rz = B.Rasterizer(cam, device=dev)
-    opt = P.FusedAdam(params, S.ADAM_LR)
-    stream = torch.cuda.current_stream()
-    image = torch.empty(3, w.height, w.width, device=dev)
-    t_final = torch.empty(w.height, w.width, device=dev)
-    last = torch.empty(w.height, w.width, dtype=torch.int32, device=dev)
-    dl = torch.empty_like(image)
-    grads = {k: torch.empty_like(v) for k, v in params.items()}
     if args.calibrate_copy_mib > 0:
         # a plain elementwise kernel (torch.neg) of known traffic: it reads and
         # writes exactly calibrate_copy_mib MiB, so HBM counters can be scaled
@@ -163,93 +293,77 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration kernel (neg): {args.calibrate_copy_mib} MiB read + {args.calibrate_copy_mib} MiB written")
         del src, dst
-    torch.cuda.synchronize()
-
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
-        rz.forward(params, image, t_final, last)
-        if ev is not None:
-            ev[1].record(stream)
-        B.l1_loss_backward(image, target, dl)
-        if ev is not None:
-            ev[2].record(stream)
-        rz.backward(params, image, last, dl, grads)
-        if ev is not None:
-            ev[3].record(stream)
-        opt.step(grads)
-        if ev is not None:
-            ev[4].record(stream)
-
-    for i in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"warmup done; N_vis={rz.last_stats.get('n_visible')} I={rz.last_stats.get('n_instances')}")
-
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(evs[k])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    phases = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(4)] for k in range(args.steps)])
-    ph = phases.mean(0)  # ms: forward, l1, backward, adam
-    ms_step = 1000.0 * elapsed / args.steps
-    log(f"ms/step {ms_step:.3f}; forward {ph[0]:.3f} l1 {ph[1]:.3f} backward {ph[2]:.3f} adam {ph[3]:.3f} ms")
-
-    # workload counts for the algorithmic-byte model (outside the timed region)
-    lay = rz.layout()
-    n = w.n
-    tiles = lay.tiles_x * lay.tiles_y
-    ranges = rz.view("ranges", 2 * tiles).view(torch.int32).view(tiles, 2)
-    lp = torch.zeros(lay.tiles_y * 16, lay.tiles_x * 16, dtype=torch.int64, device=dev)
-    lp[:w.height, :w.width] = last.long()
-    walks = lp.view(lay.tiles_y, 16, lay.tiles_x, 16).amax(dim=(1, 3)).flatten()
-    i_proc = int(walks.sum())
-    lens = (ranges[:, 1] - ranges[:, 0]).long()
-    q = torch.tensor([0.5, 0.9, 0.99, 1.0], device=dev)
-    log("tile walk p50/p90/p99/max", [int(x) for x in torch.quantile(walks.double(), q.double())],
-        "list length p50/p90/p99/max", [int(x) for x in torch.quantile(lens.double(), q.double())],
-        "tiles walking their whole list", int(((walks == lens) & (lens > 0)).sum()))
-    accum = rz.view("accum", 9 * n, dtype=torch.float32).view(9, n)
-    n_touched = int((accum != 0).any(0).sum())
-    pixels = w.width * w.height
-    byt = algorithmic_bytes(n, n_touched, i_proc, pixels)
-    adam_ms = float(ph[3])
-    adam_gbs = byt["adam"] / (adam_ms * 1e-3) / 1e9
-    bwd_gbs = byt["bwd"] / (float(ph[2]) * 1e-3) / 1e9
-
-    traffic = measured_traffic(args.traffic_json, "k_adam", args.workload)
-
+    names = [v for v in args.variants.split(",") if v]
+    for v in names:
+        if v not in VARIANTS:
+            raise SystemExit(f"unknown variant {v}; choose from {', '.join(VARIANTS)}")
+    head = names[0]
+    results, counts = {}, None
+    for v in names:
+        r = run_variant(v, args, scene, cam, target, dev, w)
+        if v == head:
+            counts = workload_counts(r, w, dev)
+        for k in ("rz", "params", "last"):
+            r.pop(k)
+        results[v] = r
+        torch.cuda.empty_cache()
+    hr = results[head]
+    n, pixels = w.n, w.width * w.height
+    bwd_blend = n * 36 + counts["i_proc"] * (4 + 48) + pixels * 28
+    if hr["fused"]:
+        fb = fused_bytes(n, counts["n_touched"], hr["sh_bf16"])
+        kbytes = fb["untouched"]
+        bwd_bytes, bwd_ms = bwd_blend + fb["touched"] + fb["untouched"], hr["phase_ms"]["backward+adam"]
+    else:
+        kbytes = adam_bytes(n, hr["sh_bf16"])
+        bwd_bytes = bwd_blend + algorithmic_bytes(n, counts["n_touched"], counts["i_proc"], pixels)["pre_bwd"]
+        bwd_ms = hr["phase_ms"]["backward"]
+    k_gbs = kbytes / (hr["kernel_ms"] * 1e-3) / 1e9
+    bwd_gbs = bwd_bytes / (bwd_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.traffic_json, hr["kernel"], args.workload)
+    variants = {}
+    for v, r in results.items():
+        kb = fused_bytes(n, counts["n_touched"], r["sh_bf16"])["untouched"] if r["fused"] else adam_bytes(n, r["sh_bf16"])
+        variants[v] = {"steps_per_s": r["steps_per_s"], "ms_per_step": r["ms_per_step"], "phase_ms": r["phase_ms"],
+                       "sh": "bf16" if r["sh_bf16"] else "f32", "backward_fused_with_adam": r["fused"],
+                       "zorder_layout": r["zorder"],
+                       "timed_kernel": {"name": r["kernel"], "avg_launch_ms": r["kernel_ms"],
+                                        "algorithmic_bytes": kb,
+                                        "GB_per_s": kb / (r["kernel_ms"] * 1e-3) / 1e9}}
     out = {
         "metric": "train steps/s (fwd+bwd+Adam) at 3M Gaussians 1600x1060; bwd HBM GB/s",
-        "value": args.steps / elapsed,
+        "value": hr["steps_per_s"],
         "unit": "steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": hr["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded scene, random uniform target)",
         "config": {"workload": f"{w.name}: {w.description}", "gaussians": n, "width": w.width,
-                   "height": w.height, "tile": 16, "sh_degree": 3, "seed": args.seed,
-                   "visible": rz.last_stats.get("n_visible"), "instances": rz.last_stats.get("n_instances"),
-                   "instances_walked": i_proc, "gaussians_with_gradient": n_touched},
-        "roofline": {"bound": "hbm", "kernel": "k_adam", "achieved": adam_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": adam_gbs / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes": byt["adam"], "avg_launch_ms": adam_ms},
+                   "height": w.height, "tile": 16, "sh_degree": 3, "seed": args.seed, "variant": head,
+                   "visible": counts["visible"], "instances": counts["instances"],
+                   "instances_walked": counts["i_proc"], "gaussians_with_gradient": counts["n_touched"]},
+        "roofline": {"bound": "hbm", "kernel": hr["kernel"], "achieved": k_gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": k_gbs / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes": kbytes, "avg_launch_ms": hr["kernel_ms"]},
         "bwd_hbm": {"achieved": bwd_gbs, "unit": "GB/s", "frac": bwd_gbs / HBM_PEAK_GBS,
-                    "algorithmic_bytes": byt["bwd"], "ms": float(ph[2])},
-        "phase_ms": {"forward": float(ph[0]), "l1": float(ph[1]), "backward": float(ph[2]),
-                     "adam": float(ph[3])},
+                    "algorithmic_bytes": bwd_bytes, "ms": bwd_ms,
+                    "covers": "blend backward + " + ("preprocess backward fused with Adam (both kernels)"
+                                                     if hr["fused"] else "preprocess backward")},
+        "phase_ms": hr["phase_ms"],
+        "zorder": None if hr["zorder_ms"] is None else {
+            "layout_ms": hr["zorder_ms"], "every_iterations": ZORDER_EVERY,
+            "amortized_ms_per_step": hr["zorder_ms"] / ZORDER_EVERY,
+            "covers": "Morton permutation of the means + gather of all parameters and both Adam moments"},
+        "variants": variants,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.seed, args.cpu_budget_s)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out))
 
 
 if __name__ == "__main__":

@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define FGS_ABI_VERSION 1
+#define FGS_ABI_VERSION 4
 
 typedef enum fgs_status {
   FGS_OK = 0,
@@ -41,6 +41,13 @@ typedef enum fgs_status {
 } fgs_status;
 
 typedef enum fgs_dtype { FGS_F32 = 0, FGS_BF16 = 1 } fgs_dtype;
+
+/* fgs_settings.flags bits.
+ * FGS_FLAG_FP64_CONIC: the precision form's float64 path for the
+ *   near-degenerate 2x2 covariance: the determinant guard and the inverse of
+ *   the dilated matrix are formed in float64 from the float32 entries and the
+ *   conic is rounded to float32 (everything else stays float32). */
+#define FGS_FLAG_FP64_CONIC 1u
 
 /* The Gaussian parameters of Sec. 2.1 ("3D Gaussian Splatting"): mean mu,
  * log-scales (scale = exp, "Activation Functions"), rotation quaternion
@@ -53,8 +60,10 @@ typedef enum fgs_dtype { FGS_F32 = 0, FGS_BF16 = 1 } fgs_dtype;
  *   opacity_logits [n]
  *   sh_dc          [3][n]   plane c = colour channel c
  *   sh_rest        [45][n]  plane (k-1)*3 + c for SH index k = 1..15
- * sh_dtype must be FGS_F32; sh_degree in 0..3 (planes beyond the degree are
- * not read). n may be 0.                                                    */
+ * sh_dtype: FGS_F32, or FGS_BF16 for the precision form (SH coefficients
+ * and their gradients stored as bfloat16; everything else, including all
+ * blending, transmittance and gradient accumulation, stays float32).
+ * sh_degree in 0..3 (planes beyond the degree are not read). n may be 0.   */
 typedef struct fgs_gaussians {
   int64_t n;
   const float* means;
@@ -67,7 +76,8 @@ typedef struct fgs_gaussians {
   int32_t sh_degree;
 } fgs_gaussians;
 
-/* Gradient planes with the layout of fgs_gaussians (all written in full). */
+/* Gradient planes with the layout of fgs_gaussians (all written in full);
+ * sh_dc and sh_rest have the element type of the SH coefficients. */
 typedef struct fgs_gaussian_grads {
   float* means;
   float* log_scales;
@@ -106,7 +116,7 @@ typedef struct fgs_settings {
   float dilation;
   float quat_min;
   float det_min;
-  uint32_t flags; /* reserved: must be 0 */
+  uint32_t flags; /* FGS_FLAG_* bits; others must be 0 */
 } fgs_settings;
 
 /* Filled by fgs_rasterize_forward when non-NULL (host struct). */
@@ -118,11 +128,12 @@ typedef struct fgs_forward_stats {
 
 /* Byte offsets of the workspace regions (host struct), for inspection.
  * All regions are 256-byte aligned.  The forward pass leaves there:
- *   rec        float4[3*n]  per-Gaussian splat record, Gaussian order:
+ *   rec        float4[4*n]  per-Gaussian splat record (64 bytes), Gaussian order:
  *                           {mu2D.x, mu2D.y, opacity, 2 ln(opacity/alpha_min)},
  *                           {conic a, b, c (inverse of the dilated Sigma2D
- *                            [[a,b],[b,c]]), camera z}, {r, g, b, flags}
- *   rect       uint32[2*n]  tile rectangle: (tx0 | ty0<<16, tx1 | ty1<<16)
+ *                            [[a,b],[b,c]]), camera z}, {r, g, b, flags},
+ *                           {tile rectangle (tx0 | ty0<<16, tx1 | ty1<<16) and
+ *                            instance count, as uint32 bits; 0}
  *   n_tiles    uint32[n]    instances per Gaussian (0 = not rendered)
  *   depth_key  uint32[n]    bits of the FP32 camera z
  *   counters   uint32[16]   [0] visible count, [1] smallest and [2] largest
@@ -133,30 +144,44 @@ typedef struct fgs_forward_stats {
  *   inst_keys  uint32[cap] x2, inst_vals uint32[cap] x2: tile ids and
  *                           Gaussian ids; sorted in [inst_final]
  *   ranges     uint32[2*tiles] [start, end) of each tile's list
- *   accum      float[9][n]  backward: dL/d(mu2D.x, mu2D.y, a, b, c, opacity, r, g, b) */
+ *   accum      float[9][n]  backward: dL/d(mu2D.x, mu2D.y, a, b, c, opacity, r, g, b)
+ *   touched    uint8[ceil(n/4)]  fused backward + Adam: bit j of byte k set when
+ *                           Gaussian 4k+j received a gradient */
 typedef struct fgs_layout {
-  size_t rec, rect, n_tiles, depth_key, counters;
+  size_t rec, n_tiles, depth_key, counters;
   size_t vis_keys[2], vis_ids[2];
   size_t inst_offsets;
   size_t inst_keys[2], inst_vals[2];
-  size_t ranges, accum, scratch, total;
+  size_t ranges, accum, touched, scratch, total;
   int32_t inst_final;
   int32_t reserved;
   int32_t tiles_x, tiles_y;
   int64_t instance_capacity;
 } fgs_layout;
 
-/* One Adam parameter group (host struct). param, exp_avg and exp_avg_sq are
- * float32 [numel]; grad is float32 [numel].  lr: this group's learning rate. */
+/* One Adam parameter group (host struct).  param and grad: [numel] of
+ * `dtype` (FGS_F32, or FGS_BF16: widened, updated in float32 and rounded back
+ * to nearest-even); exp_avg and exp_avg_sq: float32 [numel] in both cases.
+ * lr: this group's learning rate. */
 typedef struct fgs_adam_group {
-  float* param;
-  const float* grad;
+  void* param;
+  const void* grad;
   float* exp_avg;
   float* exp_avg_sq;
   int64_t numel;
   float lr;
-  int32_t dtype; /* FGS_F32 */
+  int32_t dtype;
 } fgs_adam_group;
+
+/* Optimizer state for fgs_rasterize_backward_adam (host struct of device
+ * pointers).  Index order: means, log_scales, quats, opacity_logits, sh_dc,
+ * sh_rest.  exp_avg[k] and exp_avg_sq[k] are float32 planes shaped like
+ * parameter k (sh_rest: all 45 planes); lr[k] is its learning rate. */
+typedef struct fgs_adam_moments {
+  float* exp_avg[6];
+  float* exp_avg_sq[6];
+  float lr[6];
+} fgs_adam_moments;
 
 int32_t fgs_abi_version(void);
 const char* fgs_status_string(fgs_status s);
@@ -220,6 +245,26 @@ fgs_status fgs_rasterize_backward(const fgs_gaussians* g, const fgs_camera* cam,
                                   const uint32_t* last, const float* dl_dimage,
                                   const fgs_gaussian_grads* grads, void* stream);
 
+/* Backward pass fused with the Adam step (Sec. 3.3 "Fusing Backward and
+ * Optimizer"): the blend backward of fgs_rasterize_backward; then, for each
+ * Gaussian that received a gradient, one kernel chains its accumulated 2D
+ * gradients to the raw parameters and immediately applies Adam with the
+ * moments of *opt (no gradient buffer is written), and marks it; a streaming
+ * kernel then applies the zero-gradient Adam step to every parameter of all
+ * other Gaussians.  Every parameter is updated, also those whose gradient is
+ * zero, so the result equals fgs_rasterize_backward followed by
+ * fgs_adam_step over the six groups (with bfloat16 SH, the SH gradient is
+ * rounded to bfloat16 first, as a stored gradient would be).  The parameter
+ * planes *g points to are updated in place and must be writable; sh_rest must
+ * hold all 45 planes (planes beyond sh_degree get a zero gradient).  Other
+ * arguments as for fgs_rasterize_backward and fgs_adam_step. */
+fgs_status fgs_rasterize_backward_adam(const fgs_gaussians* g, const fgs_camera* cam,
+                                       const fgs_settings* st, void* workspace, size_t workspace_bytes,
+                                       int64_t instance_capacity, const float* image,
+                                       const uint32_t* last, const float* dl_dimage,
+                                       const fgs_adam_moments* opt, int64_t step, double beta1,
+                                       double beta2, double eps, void* stream);
+
 /* Fused Adam over several parameter groups in one launch (Sec. 3.3
  * "Parameter Updates"; hyperparameters App. A): for every element,
  *   m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2;
@@ -236,6 +281,39 @@ fgs_status fgs_adam_step(const fgs_adam_group* groups, int32_t n_groups, int64_t
  * receives mean |image - target| reduced in float64. */
 fgs_status fgs_l1_loss_backward(const float* image, const float* target, int64_t n,
                                 float* dl_dimage, double* loss, void* stream);
+
+/* Z-order layout (Sec. 3.3 "Locality-preserving Densification"): re-sorting
+ * the Gaussians in Morton order of their means places Gaussians that are
+ * close in 3D close in memory, which the gathers of the rasterizer and the
+ * scattered updates of the fused backward + Adam benefit from; the paper
+ * applies it every few thousand iterations.  Conventions: bounding cube of
+ * the means with side the largest per-axis extent; 10 bits per axis,
+ * q = min(1023, floor((x - min) * (1024 / side))) in float32; codes interleave
+ * the bits with x in bit 0; ties keep the index order (stable).
+ * fgs_zorder_workspace_size: device scratch bytes for n Gaussians (host *bytes).
+ * fgs_zorder_permutation: perm[k] (device uint32[n]) = index of the Gaussian at
+ *   position k; means float32 [3][n] (finite); workspace 256-byte aligned. */
+fgs_status fgs_zorder_workspace_size(int64_t n, size_t* bytes);
+fgs_status fgs_zorder_permutation(const float* means, int64_t n, void* workspace, size_t workspace_bytes,
+                                  uint32_t* perm, void* stream);
+/* Gather of `planes` planes of n elements of elem_bytes (2 or 4) bytes:
+ * dst[p][k] = src[p][perm[k]] (apply a z-order permutation to parameters and
+ * optimizer moments alike).  src and dst must not overlap. */
+fgs_status fgs_permute_planes(const void* src, void* dst, int64_t n, int32_t planes, int32_t elem_bytes,
+                              const uint32_t* perm, void* stream);
+
+/* Timing hook for measurement: arms a one-shot timer on the calling thread.
+ * The next time this thread's library calls run `step`, start_event is
+ * recorded on the call's stream just before it and stop_event just after it
+ * (hipEvent_t handles created by the caller); the hook is then disarmed.
+ * Steps (one kernel each unless noted): "preprocess", "duplicate",
+ * "tile_sort" (all passes of the tile radix sort), "blend_forward",
+ * "blend_backward", "preprocess_backward", and for
+ * fgs_rasterize_backward_adam "preprocess_backward_adam" (gradients and Adam
+ * of the Gaussians with a gradient) and "adam_untouched" (the zero-gradient
+ * step of all others), "adam".  step = NULL
+ * disarms.  An unknown name returns FGS_ERR_INVALID_ARGUMENT. */
+fgs_status fgs_time_next_launch(const char* step, void* start_event, void* stop_event);
 
 #ifdef __cplusplus
 }

@@ -16,6 +16,8 @@ keys32     FP32 emulation of the (tile, depth) instance keys: opacity-aware
            rectangle, exact per-tile test, canonical (tile, depth, id) order
            and tile ranges, with borderline bands.
 adam64     Adam in FP64 with the paper's hyperparameters.
+zorder32   Morton (z-order) permutation of the means: FP32 quantisation,
+           bit interleave, stable order.
 
 Pins (tests/test_oracle_*.py) tie each function to closed forms, invariants,
 finite differences, library special cases and brute force; see those tests.
@@ -25,4 +27,5 @@ from .render64 import (  # noqa: F401
     composite64, render64, l1_loss_grad64, camera_center64,
 )
 from .adam64 import adam64  # noqa: F401
-from .keys32 import keys_ref, keys_ref_banded, depth_key32, tile_lists_for  # noqa: F401
+from .keys32 import keys_ref, keys_ref_banded, depth_key32, tile_lists_for, record32, tile_rect  # noqa: F401
+from . import zorder32  # noqa: F401

@@ -62,12 +62,14 @@ def depth_key32(means, cam) -> np.ndarray:
 
 def record32(scene: Dict[str, torch.Tensor], cam, *, thr_scale: float = 1.0,
              cull_slack: float = 0.0, dilation=DILATION, tau=TAU_ALPHA,
-             det_min=DET_MIN, quat_min=QUAT_MIN) -> Dict[str, np.ndarray]:
+             det_min=DET_MIN, quat_min=QUAT_MIN, fp64_conic: bool = False) -> Dict[str, np.ndarray]:
     """FP32 per-Gaussian quantities that decide the instance keys.
 
     thr_scale multiplies the truncation threshold (used for the borderline
     band); cull_slack > 0 loosens, < 0 tightens each cull comparison by that
-    relative amount.
+    relative amount.  fp64_conic: the precision form's determinant and 2x2
+    inverse in float64 from the float32 entries (products exact, one rounding
+    per subtraction and per division), the conic rounded to float32.
     """
     with np.errstate(all="ignore"):
         mu = _np32(scene["means"])
@@ -118,15 +120,23 @@ def record32(scene: Dict[str, torch.Tensor], cam, *, thr_scale: float = 1.0,
         h00 = c00 + dilation
         h11 = c11 + dilation
         h01 = c01
-        deth = h00 * h11 - h01 * h01
-        ca = h11 / deth
-        cb = -h01 / deth
-        cc = h00 / deth
+        if fp64_conic:
+            d = np.float64
+            det_d = c00.astype(d) * c11.astype(d) - c01.astype(d) * c01.astype(d)
+            deth_d = h00.astype(d) * h11.astype(d) - h01.astype(d) * h01.astype(d)
+            ca = (h11.astype(d) / deth_d).astype(np.float32)
+            cb = (-h01.astype(d) / deth_d).astype(np.float32)
+            cc = (h00.astype(d) / deth_d).astype(np.float32)
+        else:
+            deth = h00 * h11 - h01 * h01
+            ca = h11 / deth
+            cb = -h01 / deth
+            cc = h00 / deth
         o = one / (one + np.exp(-logit))
 
         lo, hi = f32(1.0 - cull_slack), f32(1.0 + cull_slack)
-        valid = ((qn >= quat_min * lo) & (Z >= near * lo) & (det >= det_min * lo)
-                 & (o > tau * lo))
+        det_ok = (det_d >= np.float64(det_min * lo)) if fp64_conic else (det >= det_min * lo)
+        valid = ((qn >= quat_min * lo) & (Z >= near * lo) & det_ok & (o > tau * lo))
         thr = (two * np.log(o / tau)) * f32(thr_scale)
         ext_x = np.sqrt(thr * h00)
         ext_y = np.sqrt(thr * h11)
@@ -252,10 +262,10 @@ def _sort_instances(gid, tid, depth, n_tiles_total):
 
 
 def keys_ref(scene: Dict[str, torch.Tensor], cam, tile: int = 16, thr_scale: float = 1.0,
-             cull_slack: float = 0.0) -> Dict[str, np.ndarray]:
+             cull_slack: float = 0.0, fp64_conic: bool = False) -> Dict[str, np.ndarray]:
     """Sorted instance keys (tile id), values (Gaussian index), tile ranges [tiles, 2],
     per-Gaussian tile counts and the FP32 record they were derived from."""
-    rec = record32(scene, cam, thr_scale=thr_scale, cull_slack=cull_slack)
+    rec = record32(scene, cam, thr_scale=thr_scale, cull_slack=cull_slack, fp64_conic=fp64_conic)
     w, h = int(cam.width), int(cam.height)
     gid, tid = _instances(rec, w, h, tile)  # the extents already carry thr_scale
     tiles = ((w + tile - 1) // tile) * ((h + tile - 1) // tile)
@@ -267,14 +277,14 @@ def keys_ref(scene: Dict[str, torch.Tensor], cam, tile: int = 16, thr_scale: flo
             "tiles_y": (h + tile - 1) // tile}
 
 
-def keys_ref_banded(scene, cam, tile: int = 16, delta: float = 1e-3):
+def keys_ref_banded(scene, cam, tile: int = 16, delta: float = 1e-3, fp64_conic: bool = False):
     """Nominal instances plus the borderline pairs: those present with every
     threshold loosened by ``delta`` (relative) but absent with every threshold
     tightened by ``delta``.  Returns (nominal, borderline_pairs) where
     borderline_pairs is a set of (tile, gaussian) tuples."""
-    nom = keys_ref(scene, cam, tile)
-    loose = keys_ref(scene, cam, tile, thr_scale=1.0 + delta, cull_slack=delta)
-    tight = keys_ref(scene, cam, tile, thr_scale=1.0 - delta, cull_slack=-delta)
+    nom = keys_ref(scene, cam, tile, fp64_conic=fp64_conic)
+    loose = keys_ref(scene, cam, tile, thr_scale=1.0 + delta, cull_slack=delta, fp64_conic=fp64_conic)
+    tight = keys_ref(scene, cam, tile, thr_scale=1.0 - delta, cull_slack=-delta, fp64_conic=fp64_conic)
     lo_pairs = set(zip(tight["keys"].tolist(), tight["vals"].tolist()))
     hi_pairs = set(zip(loose["keys"].tolist(), loose["vals"].tolist()))
     return nom, hi_pairs - lo_pairs

@@ -43,10 +43,11 @@ class ForwardStats(ctypes.Structure):
 
 
 class Layout(ctypes.Structure):
-    _fields_ = [("rec", c_size_t), ("rect", c_size_t), ("n_tiles", c_size_t), ("depth_key", c_size_t),
+    _fields_ = [("rec", c_size_t), ("n_tiles", c_size_t), ("depth_key", c_size_t),
                 ("counters", c_size_t), ("vis_keys", c_size_t * 2), ("vis_ids", c_size_t * 2),
                 ("inst_offsets", c_size_t), ("inst_keys", c_size_t * 2), ("inst_vals", c_size_t * 2),
-                ("ranges", c_size_t), ("accum", c_size_t), ("scratch", c_size_t), ("total", c_size_t),
+                ("ranges", c_size_t), ("accum", c_size_t), ("touched", c_size_t), ("scratch", c_size_t),
+                ("total", c_size_t),
                 ("inst_final", c_int32), ("reserved", c_int32), ("tiles_x", c_int32), ("tiles_y", c_int32),
                 ("instance_capacity", c_int64)]
 
@@ -54,6 +55,10 @@ class Layout(ctypes.Structure):
 class AdamGroup(ctypes.Structure):
     _fields_ = [("param", c_void_p), ("grad", c_void_p), ("exp_avg", c_void_p), ("exp_avg_sq", c_void_p),
                 ("numel", c_int64), ("lr", c_float), ("dtype", c_int32)]
+
+
+class AdamMoments(ctypes.Structure):
+    _fields_ = [("exp_avg", c_void_p * 6), ("exp_avg_sq", c_void_p * 6), ("lr", c_float * 6)]
 
 
 # name -> (restype, argtypes); every symbol the header declares
@@ -72,9 +77,17 @@ SIGNATURES = {
     "fgs_rasterize_backward": (c_int32, [ctypes.POINTER(Gaussians), ctypes.POINTER(Camera), ctypes.POINTER(Settings),
                                          c_void_p, c_size_t, c_int64, c_void_p, c_void_p, c_void_p,
                                          ctypes.POINTER(GaussianGrads), c_void_p]),
+    "fgs_rasterize_backward_adam": (c_int32, [ctypes.POINTER(Gaussians), ctypes.POINTER(Camera),
+                                              ctypes.POINTER(Settings), c_void_p, c_size_t, c_int64, c_void_p,
+                                              c_void_p, c_void_p, ctypes.POINTER(AdamMoments), c_int64, c_double,
+                                              c_double, c_double, c_void_p]),
     "fgs_adam_step": (c_int32, [ctypes.POINTER(AdamGroup), c_int32, c_int64, c_double, c_double, c_double,
                                 c_void_p]),
     "fgs_l1_loss_backward": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
+    "fgs_time_next_launch": (c_int32, [ctypes.c_char_p, c_void_p, c_void_p]),
+    "fgs_zorder_workspace_size": (c_int32, [c_int64, ctypes.POINTER(c_size_t)]),
+    "fgs_zorder_permutation": (c_int32, [c_void_p, c_int64, c_void_p, c_size_t, c_void_p, c_void_p]),
+    "fgs_permute_planes": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p, c_void_p]),
 }
 
 _lib = None

@@ -44,7 +44,9 @@ def rasterize(params: Dict[str, torch.Tensor], rasterizer: B.Rasterizer):
 class FusedAdam:
     """Adam over the six Gaussian parameter groups in one kernel launch
     (beta1 = 0.9, beta2 = 0.999, eps = 1e-15 by default).  Moments are float32
-    tensors owned by this object; step(grads) updates params in place."""
+    tensors owned by this object; step(grads) updates params in place.
+    Rasterizer.backward_adam(params, ..., optimizer) instead fuses the step
+    into the backward pass (no gradient tensors)."""
 
     def __init__(self, params: Dict[str, torch.Tensor], lrs: Dict[str, float], betas=(0.9, 0.999),
                  eps: float = 1e-15):
@@ -52,8 +54,9 @@ class FusedAdam:
         self.lrs = dict(lrs)
         self.betas = betas
         self.eps = eps
-        self.exp_avg = {k: torch.zeros_like(v) for k, v in params.items()}
-        self.exp_avg_sq = {k: torch.zeros_like(v) for k, v in params.items()}
+        # float32 moments also for bfloat16 parameters
+        self.exp_avg = {k: torch.zeros_like(v, dtype=torch.float32) for k, v in params.items()}
+        self.exp_avg_sq = {k: torch.zeros_like(v, dtype=torch.float32) for k, v in params.items()}
         self.t = 0
 
     def step(self, grads: Dict[str, torch.Tensor], stream=None) -> None:
@@ -75,13 +78,18 @@ class FusedAdam:
 
 def train_step(params: Dict[str, torch.Tensor], rasterizer: B.Rasterizer, target: torch.Tensor,
                optimizer: FusedAdam, dl_dimage: Optional[torch.Tensor] = None,
-               loss_out: Optional[torch.Tensor] = None) -> Dict[str, torch.Tensor]:
+               loss_out: Optional[torch.Tensor] = None, fused: bool = False) -> Dict[str, torch.Tensor]:
     """One training step without autograd bookkeeping: forward, L1 gradient,
-    backward, Adam.  Returns the rendered image and the gradients."""
+    backward, Adam.  Returns the rendered image and (unless fused, where the
+    Adam step runs inside the backward pass) the gradients."""
     image, t_final, last = rasterizer.forward(params)
     if dl_dimage is None:
         dl_dimage = torch.empty_like(image)
     B.l1_loss_backward(image, target, dl_dimage, loss_out)
-    grads = rasterizer.backward(params, image, last, dl_dimage)
-    optimizer.step(grads)
+    grads = None
+    if fused:
+        rasterizer.backward_adam(params, image, last, dl_dimage, optimizer)
+    else:
+        grads = rasterizer.backward(params, image, last, dl_dimage)
+        optimizer.step(grads)
     return {"image": image, "t_final": t_final, "last": last, "grads": grads, "dl_dimage": dl_dimage}

@@ -5,7 +5,10 @@ rasterizer and the optimizer runs in the HIP kernels of libfastergs.so.
 Parameter tensors use the library's structure-of-arrays layout:
 
     means [3, N], log_scales [3, N], quats [4, N], opacity_logits [N],
-    sh_dc [3, N], sh_rest [45, N]   (float32, contiguous, on the GPU)
+    sh_dc [3, N], sh_rest [45, N]   (contiguous, on the GPU)
+
+All planes are float32, except that sh_dc and sh_rest may both be bfloat16
+(the precision form); their gradients then are bfloat16 too.
 """
 from __future__ import annotations
 
@@ -67,15 +70,31 @@ def default_settings(**overrides) -> L.Settings:
     return s
 
 
+SH_NAMES = ("sh_dc", "sh_rest")
+
+
+def sh_dtype_of(params: Dict[str, torch.Tensor]) -> torch.dtype:
+    """torch.float32 or torch.bfloat16: the element type of both SH tensors."""
+    dt = params["sh_dc"].dtype
+    if dt not in (torch.float32, torch.bfloat16):
+        raise TypeError(f"SH coefficients must be float32 or bfloat16, got {dt}")
+    return dt
+
+
+def param_dtype(name: str, sh_dtype: torch.dtype) -> torch.dtype:
+    return sh_dtype if name in SH_NAMES else torch.float32
+
+
 def gaussians_struct(params: Dict[str, torch.Tensor], sh_degree: int = 3) -> L.Gaussians:
     n = int(params["opacity_logits"].shape[0])
+    shd = sh_dtype_of(params)
     for name, rows in PARAM_SHAPES.items():
-        _check_tensor(params[name], name, shape=(n,) if rows == 0 else (rows, n))
+        _check_tensor(params[name], name, dtype=param_dtype(name, shd), shape=(n,) if rows == 0 else (rows, n))
     g = L.Gaussians()
     g.n = n
     g.means, g.log_scales, g.quats = (_ptr(params[k]) for k in ("means", "log_scales", "quats"))
     g.opacity_logits, g.sh_dc, g.sh_rest = (_ptr(params[k]) for k in ("opacity_logits", "sh_dc", "sh_rest"))
-    g.sh_dtype = L.FGS_F32
+    g.sh_dtype = L.FGS_BF16 if shd == torch.bfloat16 else L.FGS_F32
     g.sh_degree = int(sh_degree)
     return g
 
@@ -139,8 +158,10 @@ def rasterize_backward(params: Dict[str, torch.Tensor], camera, settings: Option
     _check_tensor(dl_dimage, "dl_dimage", shape=(3, h, w))
     _check_tensor(last, "last", dtype=torch.int32, shape=(h, w))
     _check_tensor(workspace, "workspace", dtype=torch.uint8)
+    shd = sh_dtype_of(params)
     for name, rows in PARAM_SHAPES.items():
-        _check_tensor(grads[name], f"grads[{name}]", shape=(n,) if rows == 0 else (rows, n))
+        _check_tensor(grads[name], f"grads[{name}]", dtype=param_dtype(name, shd),
+                      shape=(n,) if rows == 0 else (rows, n))
     gr = L.GaussianGrads()
     for name in PARAM_NAMES:
         setattr(gr, name, _ptr(grads[name]))
@@ -150,17 +171,53 @@ def rasterize_backward(params: Dict[str, torch.Tensor], camera, settings: Option
         _stream_handle(stream)), "fgs_rasterize_backward")
 
 
+def rasterize_backward_adam(params: Dict[str, torch.Tensor], camera, settings: Optional[L.Settings],
+                            workspace: torch.Tensor, instance_capacity: int, image: torch.Tensor,
+                            last: torch.Tensor, dl_dimage: torch.Tensor, exp_avg: Dict[str, torch.Tensor],
+                            exp_avg_sq: Dict[str, torch.Tensor], lrs: Dict[str, float], step: int,
+                            beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15, *, sh_degree: int = 3,
+                            stream=None) -> None:
+    """fgs_rasterize_backward_adam: backward fused with the Adam step; params
+    and the float32 moments are updated in place, no gradient is returned."""
+    st = settings or default_settings()
+    cam = make_camera(camera)
+    g = gaussians_struct(params, sh_degree)
+    n = g.n
+    h, w = cam.height, cam.width
+    _check_tensor(image, "image", shape=(3, h, w))
+    _check_tensor(dl_dimage, "dl_dimage", shape=(3, h, w))
+    _check_tensor(last, "last", dtype=torch.int32, shape=(h, w))
+    _check_tensor(workspace, "workspace", dtype=torch.uint8)
+    mo = L.AdamMoments()
+    for k, name in enumerate(PARAM_NAMES):
+        rows = PARAM_SHAPES[name]
+        shape = (n,) if rows == 0 else (rows, n)
+        _check_tensor(exp_avg[name], f"exp_avg[{name}]", shape=shape)
+        _check_tensor(exp_avg_sq[name], f"exp_avg_sq[{name}]", shape=shape)
+        mo.exp_avg[k], mo.exp_avg_sq[k] = _ptr(exp_avg[name]), _ptr(exp_avg_sq[name])
+        mo.lr[k] = float(lrs[name])
+    L.check(L.load().fgs_rasterize_backward_adam(
+        ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), _ptr(workspace), workspace.numel(),
+        int(instance_capacity), _ptr(image), _ptr(last), _ptr(dl_dimage), ctypes.byref(mo), int(step),
+        float(beta1), float(beta2), float(eps), _stream_handle(stream)), "fgs_rasterize_backward_adam")
+
+
 def adam_step(groups: Sequence[Tuple[torch.Tensor, torch.Tensor, torch.Tensor, torch.Tensor, float]], step: int,
               beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15, *, stream=None) -> None:
-    """fgs_adam_step over groups of (param, grad, exp_avg, exp_avg_sq, lr), updated in place."""
+    """fgs_adam_step over groups of (param, grad, exp_avg, exp_avg_sq, lr), updated in place.
+    param and grad: float32 or bfloat16 (the same); moments: float32."""
     arr = (L.AdamGroup * len(groups))()
     for k, (p, g, m, v, lr) in enumerate(groups):
-        for t, nm in ((p, "param"), (g, "grad"), (m, "exp_avg"), (v, "exp_avg_sq")):
+        if p.dtype not in (torch.float32, torch.bfloat16):
+            raise TypeError(f"param must be float32 or bfloat16, got {p.dtype}")
+        _check_tensor(p, "param", dtype=p.dtype)
+        _check_tensor(g, "grad", dtype=p.dtype, shape=p.shape)
+        for t, nm in ((m, "exp_avg"), (v, "exp_avg_sq")):
             _check_tensor(t, nm, shape=p.shape)
         arr[k].param, arr[k].grad, arr[k].exp_avg, arr[k].exp_avg_sq = _ptr(p), _ptr(g), _ptr(m), _ptr(v)
         arr[k].numel = p.numel()
         arr[k].lr = float(lr)
-        arr[k].dtype = L.FGS_F32
+        arr[k].dtype = L.FGS_BF16 if p.dtype == torch.bfloat16 else L.FGS_F32
     L.check(L.load().fgs_adam_step(arr, len(groups), int(step), float(beta1), float(beta2), float(eps),
                                    _stream_handle(stream)), "fgs_adam_step")
 
@@ -175,6 +232,70 @@ def l1_loss_backward(image: torch.Tensor, target: torch.Tensor, dl_dimage: torch
         _check_tensor(loss, "loss", dtype=torch.float64, shape=(1,))
     L.check(L.load().fgs_l1_loss_backward(_ptr(image), _ptr(target), image.numel(), _ptr(dl_dimage), _ptr(loss),
                                           _stream_handle(stream)), "fgs_l1_loss_backward")
+
+
+def time_next_launch(step: Optional[str], start: Optional[torch.cuda.Event] = None,
+                     stop: Optional[torch.cuda.Event] = None) -> None:
+    """fgs_time_next_launch: record `start`/`stop` (timing-enabled torch events
+    that have been recorded at least once, so that they exist) around the next
+    run of `step` on this thread; None disarms."""
+    if step is None:
+        L.check(L.load().fgs_time_next_launch(None, None, None), "fgs_time_next_launch")
+        return
+    ha, hb = int(start.cuda_event), int(stop.cuda_event)
+    if not ha or not hb:
+        raise ValueError("record each event once before passing it (torch creates events lazily)")
+    L.check(L.load().fgs_time_next_launch(step.encode(), ha, hb), "fgs_time_next_launch")
+
+
+def zorder_workspace_size(n: int) -> int:
+    out = ctypes.c_size_t()
+    L.check(L.load().fgs_zorder_workspace_size(int(n), ctypes.byref(out)), "fgs_zorder_workspace_size")
+    return int(out.value)
+
+
+def zorder_permutation(means: torch.Tensor, *, stream=None) -> torch.Tensor:
+    """fgs_zorder_permutation: int32 [n] tensor (uint32 values) with perm[k] =
+    index of the Gaussian placed at position k of the Morton order."""
+    n = int(means.shape[1]) if means.dim() == 2 else 0
+    _check_tensor(means, "means", shape=(3, n))
+    perm = torch.empty(n, dtype=torch.int32, device=means.device)
+    ws = torch.empty(max(zorder_workspace_size(n), 256), dtype=torch.uint8, device=means.device)
+    L.check(L.load().fgs_zorder_permutation(_ptr(means), n, _ptr(ws), ws.numel(), _ptr(perm),
+                                            _stream_handle(stream)), "fgs_zorder_permutation")
+    return perm
+
+
+def permute_planes(src: torch.Tensor, perm: torch.Tensor, out: Optional[torch.Tensor] = None, *,
+                   stream=None) -> torch.Tensor:
+    """fgs_permute_planes: out[..., k] = src[..., perm[k]] for a [P, n] or [n]
+    tensor of float32 or bfloat16."""
+    if src.dtype not in (torch.float32, torch.bfloat16):
+        raise TypeError(f"src must be float32 or bfloat16, got {src.dtype}")
+    n = int(src.shape[-1])
+    planes = 1 if src.dim() == 1 else int(src.shape[0])
+    _check_tensor(src, "src", dtype=src.dtype)
+    _check_tensor(perm, "perm", dtype=torch.int32, shape=(n,))
+    if out is None:
+        out = torch.empty_like(src)
+    _check_tensor(out, "out", dtype=src.dtype, shape=src.shape)
+    L.check(L.load().fgs_permute_planes(_ptr(src), _ptr(out), n, planes, src.element_size(), _ptr(perm),
+                                        _stream_handle(stream)), "fgs_permute_planes")
+    return out
+
+
+def apply_zorder(params: Dict[str, torch.Tensor], optimizer=None, *, stream=None) -> torch.Tensor:
+    """Re-lay the Gaussians out in Morton order: every tensor of ``params``
+    (and, when given, the optimizer's moments) is replaced in its dict by its
+    permuted copy.  Returns the permutation."""
+    perm = zorder_permutation(params["means"], stream=stream)
+    dicts = [params]
+    if optimizer is not None:
+        dicts += [optimizer.exp_avg, optimizer.exp_avg_sq]
+    for d in dicts:
+        for k in list(d):
+            d[k] = permute_planes(d[k], perm, stream=stream)
+    return perm
 
 
 class Rasterizer:
@@ -231,6 +352,16 @@ class Rasterizer:
         rasterize_backward(params, self.camera, self.settings, self.workspace, self.capacity, image, last,
                            dl_dimage.contiguous(), grads, sh_degree=self.sh_degree, stream=stream)
         return grads
+
+    def backward_adam(self, params: Dict[str, torch.Tensor], image: torch.Tensor, last: torch.Tensor,
+                      dl_dimage: torch.Tensor, optimizer, stream=None) -> None:
+        """Backward fused with optimizer's Adam step (a FusedAdam over params):
+        updates params and the moments in place and advances optimizer.t."""
+        optimizer.t += 1
+        rasterize_backward_adam(params, self.camera, self.settings, self.workspace, self.capacity, image, last,
+                                dl_dimage.contiguous(), optimizer.exp_avg, optimizer.exp_avg_sq, optimizer.lrs,
+                                optimizer.t, optimizer.betas[0], optimizer.betas[1], optimizer.eps,
+                                sh_degree=self.sh_degree, stream=stream)
 
     # -- views of the workspace (for inspection and tests)
     def view(self, field: str, count: int, dtype=torch.int32, index: Optional[int] = None) -> torch.Tensor:

@@ -9,41 +9,66 @@
 //   p -= (lr / (1 - b1^t)) m / (sqrt(v) / sqrt(1 - b2^t) + eps).
 #include "fgs_internal.h"
 
+#include <cmath>
+
 namespace fgs {
 
 constexpr int kMaxGroups = 16;
 
 struct AdamGroupDev {
-  float* p;
-  const float* g;
+  void* p;        // float32 or bfloat16 (bf16), like the gradient
+  const void* g;
   float* m;
   float* v;
   uint64_t numel;
-  uint64_t vec_begin;  // first float4 slot of this group in the flattened launch
+  uint64_t vec_begin;  // first 4-element slot of this group in the flattened launch
   float step_size;     // lr / (1 - b1^t)
-  int32_t vec4;        // all four pointers 16-byte aligned
+  int32_t vec4;        // pointers aligned for 4-element vector accesses
+  int32_t bf16;
 };
 
 struct AdamArgs {
   AdamGroupDev grp[kMaxGroups];
   int32_t n_groups;
-  float one_minus_b1, beta2, one_minus_b2, inv_sqrt_bc2, eps;
+  AdamCoef c;
 };
 
-__device__ __forceinline__ void adam_elem(float& p, float g, float& m, float& v, const AdamArgs& a, float step) {
-  m = fmaf(a.one_minus_b1, g - m, m);
-  v = fmaf(a.one_minus_b2, g * g, v * a.beta2);
-  const float denom = sqrtf(v) * a.inv_sqrt_bc2 + a.eps;
-  p = p - step * (m / denom);
+AdamCoef adam_coef(int64_t step, double beta1, double beta2, double eps, double* bias1) {
+  const double bc1 = 1.0 - std::pow(beta1, (double)step);
+  const double bc2 = 1.0 - std::pow(beta2, (double)step);
+  AdamCoef c;
+  c.one_minus_b1 = (float)(1.0 - beta1);
+  c.beta2 = (float)beta2;
+  c.one_minus_b2 = (float)(1.0 - beta2);
+  c.inv_sqrt_bc2 = (float)(1.0 / std::sqrt(bc2));
+  c.eps = (float)eps;
+  if (bias1) *bias1 = bc1;
+  return c;
 }
 
-constexpr int kAdamSlots = 2;  // float4 slots per thread (more loads in flight)
+constexpr int kAdamSlots = 2;  // 4-element slots per thread (more loads in flight)
 
 typedef float vf4 __attribute__((ext_vector_type(4)));
-// Streaming load of a gradient that is read exactly once.
-__device__ __forceinline__ float4 load_once4(const float* p) {
+typedef unsigned int vu2 __attribute__((ext_vector_type(2)));
+// Streaming loads of a gradient that is read exactly once.
+__device__ __forceinline__ float4 load_once4(const void* p) {
   const vf4 v = __builtin_nontemporal_load(reinterpret_cast<const vf4*>(p));
   return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float4 load_once_bf16x4(const void* p) {
+  const vu2 v = __builtin_nontemporal_load(reinterpret_cast<const vu2*>(p));
+  return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u),
+                     __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xffff0000u));
+}
+__device__ __forceinline__ float4 load_bf16x4(const void* p) {
+  const uint2 v = *reinterpret_cast<const uint2*>(p);
+  return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u),
+                     __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xffff0000u));
+}
+__device__ __forceinline__ void store_bf16x4(void* p, float4 f) {
+  const uint2 v = make_uint2((uint32_t)f32_to_bf16(f.x) | ((uint32_t)f32_to_bf16(f.y) << 16),
+                             (uint32_t)f32_to_bf16(f.z) | ((uint32_t)f32_to_bf16(f.w) << 16));
+  *reinterpret_cast<uint2*>(p) = v;
 }
 
 __device__ __forceinline__ int adam_group(const AdamArgs& a, uint64_t slot) {
@@ -53,8 +78,18 @@ __device__ __forceinline__ int adam_group(const AdamArgs& a, uint64_t slot) {
   return gi;
 }
 
-// Each workgroup covers kAdamSlots * 256 consecutive float4 slots; thread t
+__device__ __forceinline__ void adam4(float4& p, const float4& g, float4& m, float4& v, const AdamCoef& c,
+                                      float step) {
+  adam_elem(p.x, g.x, m.x, v.x, c, step);
+  adam_elem(p.y, g.y, m.y, v.y, c, step);
+  adam_elem(p.z, g.z, m.z, v.z, c, step);
+  adam_elem(p.w, g.w, m.w, v.w, c, step);
+}
+
+// Each workgroup covers kAdamSlots * 256 consecutive 4-element slots; thread t
 // takes slots t and t + 256 so that every load instruction is coalesced.
+// bfloat16 parameters are widened, updated in float32 against float32
+// moments and rounded back to nearest-even.
 __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a, uint64_t total_vec) {
   const uint64_t base = (uint64_t)blockIdx.x * (kBlock * kAdamSlots) + threadIdx.x;
   float4 p[kAdamSlots], g[kAdamSlots], m[kAdamSlots], v[kAdamSlots];
@@ -71,8 +106,13 @@ __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a, uint64_t total_vec)
     const uint64_t e0 = (slot - G.vec_begin) * 4;
     vec[u] = G.vec4 && e0 + 4 <= G.numel;
     if (vec[u]) {
-      p[u] = *reinterpret_cast<const float4*>(G.p + e0);
-      g[u] = load_once4(G.g + e0);
+      if (G.bf16) {
+        p[u] = load_bf16x4(static_cast<const uint16_t*>(G.p) + e0);
+        g[u] = load_once_bf16x4(static_cast<const uint16_t*>(G.g) + e0);
+      } else {
+        p[u] = *reinterpret_cast<const float4*>(static_cast<const float*>(G.p) + e0);
+        g[u] = load_once4(static_cast<const float*>(G.g) + e0);
+      }
       m[u] = *reinterpret_cast<const float4*>(G.m + e0);
       v[u] = *reinterpret_cast<const float4*>(G.v + e0);
     }
@@ -84,18 +124,24 @@ __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a, uint64_t total_vec)
     const AdamGroupDev& G = a.grp[gi[u]];
     const uint64_t e0 = (slot - G.vec_begin) * 4;
     if (vec[u]) {
-      adam_elem(p[u].x, g[u].x, m[u].x, v[u].x, a, G.step_size);
-      adam_elem(p[u].y, g[u].y, m[u].y, v[u].y, a, G.step_size);
-      adam_elem(p[u].z, g[u].z, m[u].z, v[u].z, a, G.step_size);
-      adam_elem(p[u].w, g[u].w, m[u].w, v[u].w, a, G.step_size);
-      *reinterpret_cast<float4*>(G.p + e0) = p[u];
+      adam4(p[u], g[u], m[u], v[u], a.c, G.step_size);
+      if (G.bf16) store_bf16x4(static_cast<uint16_t*>(G.p) + e0, p[u]);
+      else *reinterpret_cast<float4*>(static_cast<float*>(G.p) + e0) = p[u];
       *reinterpret_cast<float4*>(G.m + e0) = m[u];
       *reinterpret_cast<float4*>(G.v + e0) = v[u];
+    } else if (G.bf16) {
+      for (uint64_t e = e0; e < e0 + 4 && e < G.numel; ++e) {
+        float pe = sh_load<true>(G.p, e), me = G.m[e], ve = G.v[e];
+        adam_elem(pe, sh_load<true>(G.g, e), me, ve, a.c, G.step_size);
+        sh_store<true>(G.p, e, pe);
+        G.m[e] = me;
+        G.v[e] = ve;
+      }
     } else {
       for (uint64_t e = e0; e < e0 + 4 && e < G.numel; ++e) {
-        float pe = G.p[e], me = G.m[e], ve = G.v[e];
-        adam_elem(pe, G.g[e], me, ve, a, G.step_size);
-        G.p[e] = pe;
+        float pe = sh_load<false>(G.p, e), me = G.m[e], ve = G.v[e];
+        adam_elem(pe, sh_load<false>(G.g, e), me, ve, a.c, G.step_size);
+        sh_store<false>(G.p, e, pe);
         G.m[e] = me;
         G.v[e] = ve;
       }
@@ -107,13 +153,8 @@ hipError_t launch_adam(const fgs_adam_group* groups, int n_groups, int64_t step,
                        double eps, hipStream_t s) {
   AdamArgs a = {};
   a.n_groups = n_groups;
-  const double bc1 = 1.0 - std::pow(beta1, (double)step);
-  const double bc2 = 1.0 - std::pow(beta2, (double)step);
-  a.one_minus_b1 = (float)(1.0 - beta1);
-  a.beta2 = (float)beta2;
-  a.one_minus_b2 = (float)(1.0 - beta2);
-  a.inv_sqrt_bc2 = (float)(1.0 / std::sqrt(bc2));
-  a.eps = (float)eps;
+  double bc1 = 1.0;
+  a.c = adam_coef(step, beta1, beta2, eps, &bc1);
   uint64_t vec = 0;
   for (int k = 0; k < n_groups; ++k) {
     AdamGroupDev& G = a.grp[k];
@@ -124,13 +165,105 @@ hipError_t launch_adam(const fgs_adam_group* groups, int n_groups, int64_t step,
     G.numel = (uint64_t)groups[k].numel;
     G.vec_begin = vec;
     G.step_size = (float)((double)groups[k].lr / bc1);
-    const uintptr_t bits = (uintptr_t)G.p | (uintptr_t)G.g | (uintptr_t)G.m | (uintptr_t)G.v;
-    G.vec4 = (bits & 15u) == 0 ? 1 : 0;
+    G.bf16 = groups[k].dtype == FGS_BF16 ? 1 : 0;
+    const uintptr_t pg = (uintptr_t)G.p | (uintptr_t)G.g, mv = (uintptr_t)G.m | (uintptr_t)G.v;
+    G.vec4 = ((pg & (G.bf16 ? 7u : 15u)) == 0 && (mv & 15u) == 0) ? 1 : 0;
     vec += (G.numel + 3) / 4;
   }
   if (vec == 0) return hipSuccess;
   const uint64_t per_block = (uint64_t)kBlock * kAdamSlots;
   k_adam<<<(uint32_t)((vec + per_block - 1) / per_block), kBlock, 0, s>>>(a, vec);
+  return hipGetLastError();
+}
+
+// Zero-gradient Adam step over the six parameter groups of the Gaussians
+// (planes of length `plane`), skipping the elements of Gaussians whose bit is
+// set in `touched` (updated already, with their gradient, by the fused
+// backward kernel).  Same slot layout as k_adam; no gradient stream, so
+// 12 bytes are read and 12 written per float32 element.  vec4 slots require
+// plane % 4 == 0 so that a slot never straddles two planes.
+__global__ __launch_bounds__(kBlock) void k_adam_untouched(AdamArgs a, uint64_t total_vec, uint64_t plane,
+                                                           const uint8_t* __restrict__ touched) {
+  const uint64_t base = (uint64_t)blockIdx.x * (kBlock * kAdamSlots) + threadIdx.x;
+  float4 p[kAdamSlots], m[kAdamSlots], v[kAdamSlots];
+  int gi[kAdamSlots];
+  uint32_t skip[kAdamSlots];
+#pragma unroll
+  for (int u = 0; u < kAdamSlots; ++u) {
+    const uint64_t slot = base + (uint64_t)u * kBlock;
+    gi[u] = 0;
+    skip[u] = 0xfu;
+    if (slot >= total_vec) continue;
+    gi[u] = adam_group(a, slot);
+    const AdamGroupDev& G = a.grp[gi[u]];
+    const uint64_t e0 = (slot - G.vec_begin) * 4;
+    if (!G.vec4) {
+      skip[u] = 0x10u;  // element-wise path below
+      continue;
+    }
+    skip[u] = touched[(e0 % plane) >> 2];
+    if (skip[u] == 0xfu) continue;
+    if (G.bf16) p[u] = load_bf16x4(static_cast<const uint16_t*>(G.p) + e0);
+    else p[u] = *reinterpret_cast<const float4*>(static_cast<const float*>(G.p) + e0);
+    m[u] = *reinterpret_cast<const float4*>(G.m + e0);
+    v[u] = *reinterpret_cast<const float4*>(G.v + e0);
+  }
+#pragma unroll
+  for (int u = 0; u < kAdamSlots; ++u) {
+    const uint64_t slot = base + (uint64_t)u * kBlock;
+    if (slot >= total_vec || skip[u] == 0xfu) continue;
+    const AdamGroupDev& G = a.grp[gi[u]];
+    const uint64_t e0 = (slot - G.vec_begin) * 4;
+    if (skip[u] != 0x10u) {
+      if (!(skip[u] & 1u)) adam_elem(p[u].x, 0.0f, m[u].x, v[u].x, a.c, G.step_size);
+      if (!(skip[u] & 2u)) adam_elem(p[u].y, 0.0f, m[u].y, v[u].y, a.c, G.step_size);
+      if (!(skip[u] & 4u)) adam_elem(p[u].z, 0.0f, m[u].z, v[u].z, a.c, G.step_size);
+      if (!(skip[u] & 8u)) adam_elem(p[u].w, 0.0f, m[u].w, v[u].w, a.c, G.step_size);
+      if (G.bf16) store_bf16x4(static_cast<uint16_t*>(G.p) + e0, p[u]);
+      else *reinterpret_cast<float4*>(static_cast<float*>(G.p) + e0) = p[u];
+      *reinterpret_cast<float4*>(G.m + e0) = m[u];
+      *reinterpret_cast<float4*>(G.v + e0) = v[u];
+    } else {
+      for (uint64_t e = e0; e < e0 + 4 && e < G.numel; ++e) {
+        const uint64_t i = e % plane;
+        if (touched[i >> 2] >> (i & 3) & 1u) continue;
+        float pe = G.bf16 ? sh_load<true>(G.p, e) : sh_load<false>(G.p, e), me = G.m[e], ve = G.v[e];
+        adam_elem(pe, 0.0f, me, ve, a.c, G.step_size);
+        if (G.bf16) sh_store<true>(G.p, e, pe);
+        else sh_store<false>(G.p, e, pe);
+        G.m[e] = me;
+        G.v[e] = ve;
+      }
+    }
+  }
+}
+
+hipError_t launch_adam_untouched(void* const params[6], float* const exp_avg[6], float* const exp_avg_sq[6],
+                                 const float lr[6], bool sh_bf16, uint64_t n, const uint8_t* touched, int64_t step,
+                                 double beta1, double beta2, double eps, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  static const int kPlanes[6] = {3, 3, 4, 1, 3, 45};
+  AdamArgs a = {};
+  a.n_groups = 6;
+  double bc1 = 1.0;
+  a.c = adam_coef(step, beta1, beta2, eps, &bc1);
+  uint64_t vec = 0;
+  for (int k = 0; k < 6; ++k) {
+    AdamGroupDev& G = a.grp[k];
+    G.p = params[k];
+    G.g = nullptr;
+    G.m = exp_avg[k];
+    G.v = exp_avg_sq[k];
+    G.numel = (uint64_t)kPlanes[k] * n;
+    G.vec_begin = vec;
+    G.step_size = (float)((double)lr[k] / bc1);
+    G.bf16 = (sh_bf16 && k >= 4) ? 1 : 0;
+    const uintptr_t pp = (uintptr_t)G.p, mv = (uintptr_t)G.m | (uintptr_t)G.v;
+    G.vec4 = (n % 4 == 0 && (pp & (G.bf16 ? 7u : 15u)) == 0 && (mv & 15u) == 0) ? 1 : 0;
+    vec += (G.numel + 3) / 4;
+  }
+  const uint64_t per_block = (uint64_t)kBlock * kAdamSlots;
+  k_adam_untouched<<<(uint32_t)((vec + per_block - 1) / per_block), kBlock, 0, s>>>(a, vec, n, touched);
   return hipGetLastError();
 }
 
@@ -162,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_l1(const float* __restrict__ img, co
 hipError_t launch_l1_backward(const float* image, const float* target, uint32_t n, float* dl, double* loss,
                               hipStream_t s) {
   if (loss) {
-    hipError_t e = hipMemsetAsync(loss, 0, sizeof(double), s);
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(loss), 0u, 2, s);  // +0.0
     if (e != hipSuccess) return e;
   }
   if (n == 0) return hipSuccess;

@@ -33,9 +33,9 @@ __device__ __forceinline__ void load_batch(const uint32_t* __restrict__ vals, co
   const uint32_t j = base + (uint32_t)lane;
   if (j < end) {
     b.gid = vals[j];
-    b.r0 = rec[3 * (size_t)b.gid + 0];
-    b.r1 = rec[3 * (size_t)b.gid + 1];
-    b.r2 = rec[3 * (size_t)b.gid + 2];
+    b.r0 = rec[kRecWords * (size_t)b.gid + 0];
+    b.r1 = rec[kRecWords * (size_t)b.gid + 1];
+    b.r2 = rec[kRecWords * (size_t)b.gid + 2];
   }
 }
 

@@ -35,6 +35,36 @@ fgs_status hip_fail(hipError_t e, const char* where) {
     if (e_ != hipSuccess) return hip_fail(e_, where); \
   } while (0)
 
+// One-shot timing hook (fgs_time_next_launch): when armed for `name`, events
+// are recorded on the launch stream around the next run of that step.
+struct TimerHook {
+  std::string name;
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool armed = false;
+};
+thread_local TimerHook g_timer;
+
+struct TimedStep {
+  bool on;
+  hipStream_t s;
+  TimedStep(const char* name, hipStream_t st) : on(g_timer.armed && g_timer.name == name), s(st) {
+    if (on) on = hipEventRecord(g_timer.start, s) == hipSuccess;
+  }
+  ~TimedStep() {
+    if (on) {
+      (void)hipEventRecord(g_timer.stop, s);
+      g_timer.armed = false;
+    }
+  }
+};
+
+// Runs a launch (or a short sequence) as one timed step.
+#define FGS_TIMED(name, stream, expr, where) \
+  do {                                       \
+    TimedStep timed_(name, stream);          \
+    FGS_HIP(expr, where);                    \
+  } while (0)
+
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
@@ -68,7 +98,8 @@ fgs_status check_settings(const fgs_settings* st) {
   if (st->tile != 8 && st->tile != 16 && st->tile != 32)
     return fail(FGS_ERR_INVALID_ARGUMENT, "tile must be 8, 16 or 32 (got %d)", st->tile);
   if (st->tile != 16) return fail(FGS_ERR_UNSUPPORTED, "tile %d is not implemented; use 16", st->tile);
-  if (st->flags != 0) return fail(FGS_ERR_INVALID_ARGUMENT, "settings.flags must be 0");
+  if (st->flags & ~(uint32_t)FGS_FLAG_FP64_CONIC)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "unknown bits in settings.flags 0x%x", st->flags);
   if (!(st->alpha_min > 0.0f && st->alpha_min < st->alpha_max && st->alpha_max <= 1.0f))
     return fail(FGS_ERR_INVALID_ARGUMENT, "need 0 < alpha_min < alpha_max <= 1");
   if (!(st->t_min > 0.0f && st->t_min < 1.0f)) return fail(FGS_ERR_INVALID_ARGUMENT, "need 0 < t_min < 1");
@@ -84,7 +115,6 @@ fgs_status check_gaussians(const fgs_gaussians* g) {
   if (g->n < 0 || g->n > INT32_MAX) return fail(FGS_ERR_INVALID_ARGUMENT, "n = %lld out of range", (long long)g->n);
   if (g->sh_dtype != FGS_F32 && g->sh_dtype != FGS_BF16)
     return fail(FGS_ERR_INVALID_ARGUMENT, "unknown sh_dtype %d", g->sh_dtype);
-  if (g->sh_dtype != FGS_F32) return fail(FGS_ERR_UNSUPPORTED, "only float32 SH coefficients are implemented");
   if (g->sh_degree < 0 || g->sh_degree > 3)
     return fail(FGS_ERR_INVALID_ARGUMENT, "sh_degree %d not in 0..3", g->sh_degree);
   if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh_dc ||
@@ -112,8 +142,7 @@ fgs_status make_layout(int64_t n, const fgs_camera* cam, const fgs_settings* st,
     return o;
   };
   const size_t un = (size_t)n, uc = (size_t)cap, tiles = (size_t)(tx * ty);
-  L->rec = take(un * 48);
-  L->rect = take(un * 8);
+  L->rec = take(un * 64);
   L->n_tiles = take(un * 4);
   L->depth_key = take(un * 4);
   L->counters = take(64);
@@ -128,9 +157,11 @@ fgs_status make_layout(int64_t n, const fgs_camera* cam, const fgs_settings* st,
   L->inst_vals[1] = take(uc * 4);
   L->ranges = take(tiles * 8);
   L->accum = take(un * 9 * 4);
+  L->touched = take((un + 3) / 4);
   size_t words = scan_scratch_words(un);
   words = std::max(words, radix_scratch_words(un));
   words = std::max(words, radix_scratch_words(uc));
+  words = std::max(words, 4 * ((un + kBlock - 1) / kBlock));  // preprocess partials
   L->scratch = take(words * 4 + 256);
   L->total = off;
   L->inst_final = ((tile_key_bits((uint64_t)tiles) + kRadixBits - 1) / kRadixBits) & 1;
@@ -158,7 +189,8 @@ CamDev make_cam(const fgs_camera* c, const fgs_layout& L) {
 }
 
 SetDev make_set(const fgs_settings* s) {
-  return SetDev{s->alpha_min, s->alpha_max, s->t_min, s->dilation, s->quat_min, s->det_min};
+  return SetDev{s->alpha_min, s->alpha_max, s->t_min, s->dilation, s->quat_min, s->det_min,
+                (s->flags & FGS_FLAG_FP64_CONIC) ? 1 : 0};
 }
 
 GaussDev make_gauss(const fgs_gaussians* g) {
@@ -167,10 +199,11 @@ GaussDev make_gauss(const fgs_gaussians* g) {
   d.log_scales = g->log_scales;
   d.quats = g->quats;
   d.logits = g->opacity_logits;
-  d.sh_dc = static_cast<const float*>(g->sh_dc);
-  d.sh_rest = static_cast<const float*>(g->sh_rest);
+  d.sh_dc = g->sh_dc;
+  d.sh_rest = g->sh_rest;
   d.n = (uint32_t)g->n;
   d.sh_coeffs = (g->sh_degree + 1) * (g->sh_degree + 1);
+  d.sh_bf16 = g->sh_dtype == FGS_BF16 ? 1 : 0;
   return d;
 }
 
@@ -246,7 +279,6 @@ fgs_status fgs_rasterize_forward(const fgs_gaussians* g, const fgs_camera* cam, 
   const SetDev sd = make_set(st);
   const uint32_t n = gd.n;
   float4* rec = at<float4>(workspace, L.rec);
-  uint2* rect = at<uint2>(workspace, L.rect);
   uint32_t* n_tiles = at<uint32_t>(workspace, L.n_tiles);
   uint32_t* depth_key = at<uint32_t>(workspace, L.depth_key);
   uint32_t* counters = at<uint32_t>(workspace, L.counters);
@@ -262,8 +294,10 @@ fgs_status fgs_rasterize_forward(const fgs_gaussians* g, const fgs_camera* cam, 
   // the instance count I and the depth-key range size every later launch.
   uint32_t stats_host[8] = {0, 0xffffffffu, 0, 0, 0, 0, 0, 0};
   if (n > 0) {
-    FGS_HIP(launch_preprocess(gd, cd, sd, st->tile, rec, rect, n_tiles, depth_key, hs), "preprocess");
-    FGS_HIP(launch_stats(n_tiles, depth_key, n, counters, hs), "stats");
+    uint4* partials = reinterpret_cast<uint4*>(scratch);  // free until the compaction scan
+    FGS_TIMED("preprocess", hs, launch_preprocess(gd, cd, sd, st->tile, rec, n_tiles, depth_key, partials, hs),
+              "preprocess");
+    FGS_HIP(launch_stats(partials, ceil_div(n, kBlock), counters, hs), "stats");
     FGS_HIP(hipMemcpyAsync(stats_host, counters, sizeof(stats_host), hipMemcpyDeviceToHost, hs), "stats copy");
     FGS_HIP(hipStreamSynchronize(hs), "stats sync");
   }
@@ -298,41 +332,43 @@ fgs_status fgs_rasterize_forward(const fgs_gaussians* g, const fgs_camera* cam, 
   }
 
   const size_t tiles = (size_t)L.tiles_x * L.tiles_y;
-  FGS_HIP(hipMemsetAsync(ranges, 0, tiles * sizeof(uint2), hs), "ranges clear");
+  FGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, tiles * 2, hs), "ranges clear");
   if (inst > 0) {
-    FGS_HIP(launch_duplicate(vis_ids[vis_final], counters + kStatVisible, nvis, offsets, rec, rect, n_tiles, cd,
+    FGS_TIMED("duplicate", hs, launch_duplicate(vis_ids[vis_final], counters + kStatVisible, nvis, offsets, rec, cd,
                              st->tile, (uint32_t)instance_capacity, ikeys[0], ivals[0], hs),
             "duplicate");
     int inst_final = 0;
-    FGS_HIP(radix_sort_pairs(ikeys, ivals, inst, nullptr, 0, tile_key_bits(tiles), scratch, &inst_final, hs),
+    FGS_TIMED("tile_sort", hs, radix_sort_pairs(ikeys, ivals, inst, nullptr, 0, tile_key_bits(tiles), scratch, &inst_final, hs),
             "tile sort");
     if (inst_final != L.inst_final) return fail(FGS_ERR_HIP, "internal: tile sort buffer mismatch");
     FGS_HIP(launch_tile_ranges(ikeys[inst_final], inst, (uint32_t)tiles, ranges, hs), "tile ranges");
   }
-  FGS_HIP(launch_blend_forward(ranges, ivals[L.inst_final], rec, cd, sd, image, t_final, last, hs), "blend");
+  FGS_TIMED("blend_forward", hs, launch_blend_forward(ranges, ivals[L.inst_final], rec, cd, sd, image, t_final, last, hs),
+            "blend");
   return FGS_OK;
 }
 
-fgs_status fgs_rasterize_backward(const fgs_gaussians* g, const fgs_camera* cam, const fgs_settings* st,
-                                  void* workspace, size_t workspace_bytes, int64_t instance_capacity,
-                                  const float* image, const uint32_t* last, const float* dl_dimage,
-                                  const fgs_gaussian_grads* grads, void* stream) {
+// Checks shared by the two backward entry points; on success fills the
+// layout and the workspace regions the blend backward reads.
+static fgs_status check_backward(const fgs_gaussians* g, const fgs_camera* cam, const fgs_settings* st,
+                                 void* workspace, size_t workspace_bytes, int64_t instance_capacity,
+                                 const float* image, const uint32_t* last, const float* dl_dimage, fgs_layout* L) {
   fgs_status s = check_gaussians(g);
   if (s != FGS_OK) return s;
-  fgs_layout L;
-  s = make_layout(g->n, cam, st, instance_capacity, &L);
+  s = make_layout(g->n, cam, st, instance_capacity, L);
   if (s != FGS_OK) return s;
   if (!workspace) return fail(FGS_ERR_INVALID_ARGUMENT, "workspace is NULL");
-  if (workspace_bytes < L.total)
-    return fail(FGS_ERR_INVALID_ARGUMENT, "workspace holds %zu bytes, %zu needed", workspace_bytes, L.total);
+  if (workspace_bytes < L->total)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "workspace holds %zu bytes, %zu needed", workspace_bytes, L->total);
   if (!image || !last || !dl_dimage) return fail(FGS_ERR_INVALID_ARGUMENT, "image, last and dl_dimage are required");
-  if (!grads) return fail(FGS_ERR_INVALID_ARGUMENT, "grads is NULL");
-  if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits ||
-                   !grads->sh_dc || !grads->sh_rest))
-    return fail(FGS_ERR_INVALID_ARGUMENT, "a gradient pointer is NULL");
-  if (g->n == 0) return FGS_OK;
+  return FGS_OK;
+}
 
-  hipStream_t hs = static_cast<hipStream_t>(stream);
+// Clears the accumulators and runs the blend backward (per-Gaussian 2D
+// gradients into accum[9][n]).
+static fgs_status blend_backward(const fgs_gaussians* g, const fgs_camera* cam, const fgs_settings* st,
+                                 void* workspace, const fgs_layout& L, const float* image, const uint32_t* last,
+                                 const float* dl_dimage, hipStream_t hs) {
   const GaussDev gd = make_gauss(g);
   const CamDev cd = make_cam(cam, L);
   const SetDev sd = make_set(st);
@@ -340,16 +376,82 @@ fgs_status fgs_rasterize_backward(const fgs_gaussians* g, const fgs_camera* cam,
   uint2* ranges = at<uint2>(workspace, L.ranges);
   uint32_t* ivals = at<uint32_t>(workspace, L.inst_vals[L.inst_final]);
   float* accum = at<float>(workspace, L.accum);
-  FGS_HIP(hipMemsetAsync(accum, 0, (size_t)gd.n * 9 * sizeof(float), hs), "accum clear");
-  FGS_HIP(launch_blend_backward(ranges, ivals, rec, cd, sd, image, last, dl_dimage, accum, gd.n, hs), "blend bwd");
+  FGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(accum), 0u, (uint64_t)gd.n * 9, hs), "accum clear");
+  FGS_TIMED("blend_backward", hs, launch_blend_backward(ranges, ivals, rec, cd, sd, image, last, dl_dimage, accum, gd.n, hs),
+            "blend bwd");
+  return FGS_OK;
+}
+
+fgs_status fgs_rasterize_backward(const fgs_gaussians* g, const fgs_camera* cam, const fgs_settings* st,
+                                  void* workspace, size_t workspace_bytes, int64_t instance_capacity,
+                                  const float* image, const uint32_t* last, const float* dl_dimage,
+                                  const fgs_gaussian_grads* grads, void* stream) {
+  fgs_layout L;
+  fgs_status s = check_backward(g, cam, st, workspace, workspace_bytes, instance_capacity, image, last, dl_dimage, &L);
+  if (s != FGS_OK) return s;
+  if (!grads) return fail(FGS_ERR_INVALID_ARGUMENT, "grads is NULL");
+  if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits ||
+                   !grads->sh_dc || !grads->sh_rest))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "a gradient pointer is NULL");
+  if (g->n == 0) return FGS_OK;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  s = blend_backward(g, cam, st, workspace, L, image, last, dl_dimage, hs);
+  if (s != FGS_OK) return s;
   GradDev gr;
   gr.means = grads->means;
   gr.log_scales = grads->log_scales;
   gr.quats = grads->quats;
   gr.logits = grads->opacity_logits;
-  gr.sh_dc = static_cast<float*>(grads->sh_dc);
-  gr.sh_rest = static_cast<float*>(grads->sh_rest);
-  FGS_HIP(launch_preprocess_backward(gd, cd, sd, rec, accum, gr, hs), "preprocess bwd");
+  gr.sh_dc = grads->sh_dc;
+  gr.sh_rest = grads->sh_rest;
+  FGS_TIMED("preprocess_backward", hs, launch_preprocess_backward(make_gauss(g), make_cam(cam, L), at<float4>(workspace, L.rec),
+                                     at<float>(workspace, L.accum), gr, hs),
+          "preprocess bwd");
+  return FGS_OK;
+}
+
+static fgs_status check_adam_hyper(int64_t step, double beta1, double beta2, double eps) {
+  if (step < 1) return fail(FGS_ERR_INVALID_ARGUMENT, "step must be >= 1");
+  if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "betas must lie in [0, 1)");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(FGS_ERR_INVALID_ARGUMENT, "eps must be finite, >= 0");
+  return FGS_OK;
+}
+
+fgs_status fgs_rasterize_backward_adam(const fgs_gaussians* g, const fgs_camera* cam, const fgs_settings* st,
+                                       void* workspace, size_t workspace_bytes, int64_t instance_capacity,
+                                       const float* image, const uint32_t* last, const float* dl_dimage,
+                                       const fgs_adam_moments* opt, int64_t step, double beta1, double beta2,
+                                       double eps, void* stream) {
+  fgs_layout L;
+  fgs_status s = check_backward(g, cam, st, workspace, workspace_bytes, instance_capacity, image, last, dl_dimage, &L);
+  if (s != FGS_OK) return s;
+  if (!opt) return fail(FGS_ERR_INVALID_ARGUMENT, "opt is NULL");
+  s = check_adam_hyper(step, beta1, beta2, eps);
+  if (s != FGS_OK) return s;
+  for (int k = 0; k < 6; ++k)
+    if (!std::isfinite(opt->lr[k])) return fail(FGS_ERR_INVALID_ARGUMENT, "lr[%d] not finite", k);
+  if (g->n == 0) return FGS_OK;
+  if (!g->sh_rest) return fail(FGS_ERR_INVALID_ARGUMENT, "sh_rest (all 45 planes) is required");
+  for (int k = 0; k < 6; ++k)
+    if (!opt->exp_avg[k] || !opt->exp_avg_sq[k]) return fail(FGS_ERR_INVALID_ARGUMENT, "moment %d is NULL", k);
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  s = blend_backward(g, cam, st, workspace, L, image, last, dl_dimage, hs);
+  if (s != FGS_OK) return s;
+  void* const params[6] = {const_cast<float*>(g->means), const_cast<float*>(g->log_scales),
+                           const_cast<float*>(g->quats), const_cast<float*>(g->opacity_logits),
+                           const_cast<void*>(g->sh_dc), const_cast<void*>(g->sh_rest)};
+  const GaussDev gd = make_gauss(g);
+  uint8_t* touched = at<uint8_t>(workspace, L.touched);
+  FGS_TIMED("preprocess_backward_adam", hs,
+            launch_preprocess_backward_adam(gd, make_cam(cam, L), at<float4>(workspace, L.rec),
+                                            at<float>(workspace, L.accum), params, opt->exp_avg, opt->exp_avg_sq,
+                                            opt->lr, step, beta1, beta2, eps, touched, hs),
+            "preprocess bwd + adam");
+  FGS_TIMED("adam_untouched", hs,
+            launch_adam_untouched(params, opt->exp_avg, opt->exp_avg_sq, opt->lr, gd.sh_bf16 != 0, gd.n, touched,
+                                  step, beta1, beta2, eps, hs),
+            "adam (zero gradient)");
   return FGS_OK;
 }
 
@@ -357,19 +459,73 @@ fgs_status fgs_adam_step(const fgs_adam_group* groups, int32_t n_groups, int64_t
                          double eps, void* stream) {
   if (!groups) return fail(FGS_ERR_INVALID_ARGUMENT, "groups is NULL");
   if (n_groups < 1 || n_groups > 16) return fail(FGS_ERR_INVALID_ARGUMENT, "n_groups %d not in 1..16", n_groups);
-  if (step < 1) return fail(FGS_ERR_INVALID_ARGUMENT, "step must be >= 1");
-  if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0))
-    return fail(FGS_ERR_INVALID_ARGUMENT, "betas must lie in [0, 1)");
-  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(FGS_ERR_INVALID_ARGUMENT, "eps must be finite, >= 0");
+  fgs_status hs = check_adam_hyper(step, beta1, beta2, eps);
+  if (hs != FGS_OK) return hs;
   for (int k = 0; k < n_groups; ++k) {
     const fgs_adam_group& G = groups[k];
     if (G.numel < 0) return fail(FGS_ERR_INVALID_ARGUMENT, "group %d: numel < 0", k);
-    if (G.dtype != FGS_F32) return fail(FGS_ERR_UNSUPPORTED, "group %d: only float32 parameters", k);
+    if (G.dtype != FGS_F32 && G.dtype != FGS_BF16) return fail(FGS_ERR_INVALID_ARGUMENT, "group %d: bad dtype", k);
     if (G.numel > 0 && (!G.param || !G.grad || !G.exp_avg || !G.exp_avg_sq))
       return fail(FGS_ERR_INVALID_ARGUMENT, "group %d: NULL pointer", k);
     if (!std::isfinite(G.lr)) return fail(FGS_ERR_INVALID_ARGUMENT, "group %d: lr not finite", k);
   }
-  FGS_HIP(launch_adam(groups, n_groups, step, beta1, beta2, eps, static_cast<hipStream_t>(stream)), "adam");
+  FGS_TIMED("adam", static_cast<hipStream_t>(stream),
+            launch_adam(groups, n_groups, step, beta1, beta2, eps, static_cast<hipStream_t>(stream)), "adam");
+  return FGS_OK;
+}
+
+fgs_status fgs_zorder_workspace_size(int64_t n, size_t* bytes) {
+  if (!bytes) return fail(FGS_ERR_INVALID_ARGUMENT, "bytes is NULL");
+  if (n < 0 || n > INT32_MAX) return fail(FGS_ERR_INVALID_ARGUMENT, "n = %lld out of range", (long long)n);
+  *bytes = zorder_scratch_bytes((uint64_t)n);
+  return FGS_OK;
+}
+
+fgs_status fgs_zorder_permutation(const float* means, int64_t n, void* workspace, size_t workspace_bytes,
+                                  uint32_t* perm, void* stream) {
+  if (n < 0 || n > INT32_MAX) return fail(FGS_ERR_INVALID_ARGUMENT, "n = %lld out of range", (long long)n);
+  if (n == 0) return FGS_OK;
+  if (!means || !workspace || !perm) return fail(FGS_ERR_INVALID_ARGUMENT, "NULL pointer");
+  const size_t need = zorder_scratch_bytes((uint64_t)n);
+  if (workspace_bytes < need)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "workspace holds %zu bytes, %zu needed", workspace_bytes, need);
+  if ((uintptr_t)workspace % 256) return fail(FGS_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+  FGS_HIP(launch_zorder(means, (uint32_t)n, workspace, perm, static_cast<hipStream_t>(stream)), "zorder");
+  return FGS_OK;
+}
+
+fgs_status fgs_permute_planes(const void* src, void* dst, int64_t n, int32_t planes, int32_t elem_bytes,
+                              const uint32_t* perm, void* stream) {
+  if (n < 0 || n > INT32_MAX) return fail(FGS_ERR_INVALID_ARGUMENT, "n = %lld out of range", (long long)n);
+  if (planes < 0 || planes > 65535) return fail(FGS_ERR_INVALID_ARGUMENT, "planes %d not in 0..65535", planes);
+  if (elem_bytes != 2 && elem_bytes != 4) return fail(FGS_ERR_INVALID_ARGUMENT, "elem_bytes must be 2 or 4");
+  if (n == 0 || planes == 0) return FGS_OK;
+  if (!src || !dst || !perm) return fail(FGS_ERR_INVALID_ARGUMENT, "NULL pointer");
+  const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst, len = (uintptr_t)n * planes * elem_bytes;
+  if (a < b + len && b < a + len) return fail(FGS_ERR_INVALID_ARGUMENT, "src and dst overlap");
+  FGS_HIP(launch_permute(src, dst, (uint32_t)n, planes, elem_bytes, perm, static_cast<hipStream_t>(stream)),
+          "permute");
+  return FGS_OK;
+}
+
+fgs_status fgs_time_next_launch(const char* step, void* start_event, void* stop_event) {
+  static const char* const kSteps[] = {"preprocess",          "duplicate",
+                                       "tile_sort",           "blend_forward",
+                                       "blend_backward",      "preprocess_backward",
+                                       "preprocess_backward_adam", "adam_untouched",
+                                       "adam"};
+  if (!step) {
+    g_timer.armed = false;
+    return FGS_OK;
+  }
+  bool known = false;
+  for (const char* k : kSteps) known |= std::strcmp(k, step) == 0;
+  if (!known) return fail(FGS_ERR_INVALID_ARGUMENT, "unknown step '%s'", step);
+  if (!start_event || !stop_event) return fail(FGS_ERR_INVALID_ARGUMENT, "events must not be NULL");
+  g_timer.name = step;
+  g_timer.start = static_cast<hipEvent_t>(start_event);
+  g_timer.stop = static_cast<hipEvent_t>(stop_event);
+  g_timer.armed = true;
   return FGS_OK;
 }
 

@@ -31,17 +31,21 @@ struct CamDev {
 
 struct SetDev {
   float alpha_min, alpha_max, t_min, dilation, quat_min, det_min;
+  int32_t fp64_conic;  // determinant and 2x2 inverse in float64 (precision form)
 };
 
+// SH planes hold float32 or bfloat16 elements (sh_bf16); kernels that touch
+// them are instantiated for both.
 struct GaussDev {
   const float* means;
   const float* log_scales;
   const float* quats;
   const float* logits;
-  const float* sh_dc;
-  const float* sh_rest;
+  const void* sh_dc;
+  const void* sh_rest;
   uint32_t n;
   int32_t sh_coeffs;  // (degree + 1)^2
+  int32_t sh_bf16;
 };
 
 struct GradDev {
@@ -49,9 +53,55 @@ struct GradDev {
   float* log_scales;
   float* quats;
   float* logits;
-  float* sh_dc;
-  float* sh_rest;
+  void* sh_dc;  // element type of the SH parameters
+  void* sh_rest;
 };
+
+// bfloat16 <-> float32.  Widening is exact; narrowing rounds to nearest, ties
+// to even (add 0x7fff plus the lowest kept bit, then truncate), NaN stays NaN.
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+  return __uint_as_float((uint32_t)h << 16);
+}
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+template <bool BF16>
+__device__ __forceinline__ float sh_load(const void* p, size_t idx) {
+  if constexpr (BF16) return bf16_to_f32(static_cast<const uint16_t*>(p)[idx]);
+  else return static_cast<const float*>(p)[idx];
+}
+template <bool BF16>
+__device__ __forceinline__ void sh_store(void* p, size_t idx, float v) {
+  if constexpr (BF16) static_cast<uint16_t*>(p)[idx] = f32_to_bf16(v);
+  else static_cast<float*>(p)[idx] = v;
+}
+// The value a float32 takes once stored in the SH element type.
+template <bool BF16>
+__device__ __forceinline__ float sh_round(float v) {
+  if constexpr (BF16) return bf16_to_f32(f32_to_bf16(v));
+  else return v;
+}
+
+// One Adam element in torch.optim.Adam's float32 order (Sec. 3.3 "Parameter
+// Updates"):  m += (1 - b1)(g - m);  v = b2 v + (1 - b2) g^2;
+//             p -= step_size * m / (sqrt(v) / sqrt(1 - b2^t) + eps),
+// with step_size = lr / (1 - b1^t).  Shared by the optimizer kernel and the
+// fused backward + optimizer kernel so both give identical results.
+struct AdamCoef {
+  float one_minus_b1, beta2, one_minus_b2, inv_sqrt_bc2, eps;
+};
+__device__ __forceinline__ void adam_elem(float& p, float g, float& m, float& v, const AdamCoef& a, float step) {
+#pragma clang fp contract(on)
+  m = fmaf(a.one_minus_b1, g - m, m);
+  v = fmaf(a.one_minus_b2, g * g, v * a.beta2);
+  const float denom = sqrtf(v) * a.inv_sqrt_bc2 + a.eps;
+  p = p - step * (m / denom);
+}
+// Host side: coefficients from double hyperparameters (1 - beta and the bias
+// corrections are formed in double before rounding, as PyTorch does).
+AdamCoef adam_coef(int64_t step, double beta1, double beta2, double eps, double* bias1);
 
 // ----------------------------------------------------------------------------
 // Workgroup -> tile mapping.  Workgroups are dealt to the 8 XCDs round-robin
@@ -228,16 +278,22 @@ __device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, volatile 
 }
 
 inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+// a word count rounded up to a multiple of 64 words (256 bytes)
+inline uint64_t round_up64(uint64_t w) { return (w + 63) & ~uint64_t(63); }
 
 // ----------------------------------------------------------------------------
 // Host-side launchers (each .hip file owns its kernels).
 // ----------------------------------------------------------------------------
+// p[0..n) = v (a kernel, so captured graphs contain no memset nodes)
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+
 enum ScanMode { SCAN_IDENTITY = 0, SCAN_NONZERO = 1, SCAN_GATHER = 2 };
 
 // Scratch words needed by scan_u32 for n items.
 size_t scan_scratch_words(uint64_t n);
 // Exclusive scan of x[i] for i < n where x[i] = in[i] (IDENTITY), in[i] != 0
-// (NONZERO) or, for i < *d_count, in[idx[i]] (GATHER; 0 beyond the count).
+// (NONZERO) or, for i < *d_count, in[idx[i]] (GATHER; 0 beyond the count; out
+// must not alias in or idx).
 // Writes out[0..n) and, when d_total != NULL, the grand total to *d_total.
 hipError_t scan_u32(ScanMode mode, const uint32_t* in, const uint32_t* idx, const uint32_t* d_count,
                     uint32_t* out, uint32_t n, uint32_t* d_total, uint32_t* scratch, hipStream_t s);
@@ -249,8 +305,17 @@ size_t radix_scratch_words(uint64_t n);
 hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
                             int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s);
 
+// Per-Gaussian splat record: four float4 (64 bytes, so a gather of any three
+// of them touches one cache line):
+//   [0] {mu2D.x, mu2D.y, opacity, 2 ln(opacity / alpha_min)}
+//   [1] {conic a, b, c, camera z}
+//   [2] {r, g, b, flags (colour clamp bits 0-2, bit 3 set)}
+//   [3] {tile rectangle (tx0 | ty0 << 16, tx1 | ty1 << 16), instance count, 0}
+constexpr int kRecWords = 4;
+// Also writes one uint4 {visible, instances, min key, max key} per 256-thread
+// block into partials[ceil(n / 256)].
 hipError_t launch_preprocess(const GaussDev& g, const CamDev& cam, const SetDev& st, int tile,
-                             float4* rec, uint2* rect, uint32_t* n_tiles, uint32_t* depth_key,
+                             float4* rec, uint32_t* n_tiles, uint32_t* depth_key, uint4* partials,
                              hipStream_t s);
 // Slots of the workspace counters (uint32 words).
 constexpr int kStatVisible = 0;    // visible Gaussians
@@ -259,14 +324,21 @@ constexpr int kStatKeyMax = 2;     // largest visible depth key
 constexpr int kStatDepthBuf = 3;   // ping-pong buffer holding the depth-sorted visible ids
 constexpr int kStatInstances = 4;  // instance count I, uint64 at words 4-5
 hipError_t launch_set_word(uint32_t* p, uint32_t v, hipStream_t s);
-hipError_t launch_stats(const uint32_t* n_tiles, const uint32_t* depth_key, uint32_t n, uint32_t* counters,
-                        hipStream_t s);
+// Z-order: scratch bytes for n Gaussians; perm[k] = index of the Gaussian at
+// position k of the Morton order of the means [3][n]; gather of `planes`
+// planes of n elements of 2 or 4 bytes: dst[p][k] = src[p][perm[k]].
+size_t zorder_scratch_bytes(uint64_t n);
+hipError_t launch_zorder(const float* means, uint32_t n, void* scratch, uint32_t* perm, hipStream_t s);
+hipError_t launch_permute(const void* src, void* dst, uint32_t n, int planes, int elem_bytes,
+                          const uint32_t* perm, hipStream_t s);
+// Reduces the preprocess partials of nb blocks into the counter words.
+hipError_t launch_stats(const uint4* partials, uint32_t nb, uint32_t* counters, hipStream_t s);
 hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth_key, uint32_t n,
                                   const uint32_t* pos, uint32_t* vis_keys, uint32_t* vis_ids,
                                   hipStream_t s);
 hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uint32_t n,
-                            const uint32_t* offsets, const float4* rec, const uint2* rect,
-                            const uint32_t* n_tiles, const CamDev& cam, int tile, uint32_t cap,
+                            const uint32_t* offsets, const float4* rec, const CamDev& cam, int tile,
+                            uint32_t cap,
                             uint32_t* keys, uint32_t* vals, hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t* keys, uint32_t count, uint32_t tiles, uint2* ranges,
                               hipStream_t s);
@@ -277,9 +349,21 @@ hipError_t launch_blend_backward(const uint2* ranges, const uint32_t* vals, cons
                                  const CamDev& cam, const SetDev& st, const float* image,
                                  const uint32_t* last, const float* dl_dimage, float* accum,
                                  uint32_t n, hipStream_t s);
-hipError_t launch_preprocess_backward(const GaussDev& g, const CamDev& cam, const SetDev& st,
-                                      const float4* rec, const float* accum, const GradDev& gr,
-                                      hipStream_t s);
+hipError_t launch_preprocess_backward(const GaussDev& g, const CamDev& cam, const float4* rec, const float* accum,
+                                      const GradDev& gr, hipStream_t s);
+// Fused preprocess backward + Adam for the Gaussians with a gradient, which it
+// marks in `touched`; params/exp_avg/exp_avg_sq/lr in the group order means,
+// log_scales, quats, logits, sh_dc, sh_rest.
+hipError_t launch_preprocess_backward_adam(const GaussDev& g, const CamDev& cam, const float4* rec,
+                                           const float* accum, void* const params[6], float* const exp_avg[6],
+                                           float* const exp_avg_sq[6], const float lr[6], int64_t step,
+                                           double beta1, double beta2, double eps, uint8_t* touched,
+                                           hipStream_t s);
+// The zero-gradient Adam step of every parameter of the Gaussians not marked
+// in `touched` (groups as above, planes of length n).
+hipError_t launch_adam_untouched(void* const params[6], float* const exp_avg[6], float* const exp_avg_sq[6],
+                                 const float lr[6], bool sh_bf16, uint64_t n, const uint8_t* touched, int64_t step,
+                                 double beta1, double beta2, double eps, hipStream_t s);
 hipError_t launch_adam(const fgs_adam_group* groups, int n_groups, int64_t step, double beta1,
                        double beta2, double eps, hipStream_t s);
 hipError_t launch_l1_backward(const float* image, const float* target, uint32_t n, float* dl,

@@ -36,6 +36,7 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y) {
 
 // View-dependent colour: sum_k coeff_k Y_k(dir) + 0.5, clipped at 0 per channel.
 // Returns the clip flags (bit c set when channel c was clipped).
+template <bool SHB>
 __device__ __forceinline__ uint32_t sh_colour(const GaussDev& g, uint32_t i, float px, float py, float pz,
                                               const CamDev& cam, float* rgb) {
   float dx = px - cam.campos[0], dy = py - cam.campos[1], dz = pz - cam.campos[2];
@@ -44,12 +45,13 @@ __device__ __forceinline__ uint32_t sh_colour(const GaussDev& g, uint32_t i, flo
   float Y[16];
   sh_basis(dx, dy, dz, Y);
   const size_t n = g.n;
-  float c0 = Y[0] * g.sh_dc[i], c1 = Y[0] * g.sh_dc[n + i], c2 = Y[0] * g.sh_dc[2 * n + i];
+  float c0 = Y[0] * sh_load<SHB>(g.sh_dc, i), c1 = Y[0] * sh_load<SHB>(g.sh_dc, n + i),
+        c2 = Y[0] * sh_load<SHB>(g.sh_dc, 2 * n + i);
   for (int k = 1; k < g.sh_coeffs; ++k) {
-    const float* p = g.sh_rest + (size_t)(3 * (k - 1)) * n + i;
-    c0 = fmaf(Y[k], p[0], c0);
-    c1 = fmaf(Y[k], p[n], c1);
-    c2 = fmaf(Y[k], p[2 * n], c2);
+    const size_t o = (size_t)(3 * (k - 1)) * n + i;
+    c0 = fmaf(Y[k], sh_load<SHB>(g.sh_rest, o), c0);
+    c1 = fmaf(Y[k], sh_load<SHB>(g.sh_rest, o + n), c1);
+    c2 = fmaf(Y[k], sh_load<SHB>(g.sh_rest, o + 2 * n), c2);
   }
   c0 += 0.5f; c1 += 0.5f; c2 += 0.5f;
   uint32_t flags = (c0 < 0.0f ? 1u : 0u) | (c1 < 0.0f ? 2u : 0u) | (c2 < 0.0f ? 4u : 0u);
@@ -59,9 +61,10 @@ __device__ __forceinline__ uint32_t sh_colour(const GaussDev& g, uint32_t i, flo
   return flags;
 }
 
+template <bool SHB>
 __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, CamDev cam, SetDev st, int tile,
-                                                       float4* __restrict__ rec, uint2* __restrict__ rect,
-                                                       uint32_t* __restrict__ n_tiles,
+                                                       float4* __restrict__ rec, uint32_t* __restrict__ n_tiles,
+                                                       uint4* __restrict__ partials,
                                                        uint32_t* __restrict__ depth_key) {
 #pragma clang fp contract(off)
   __shared__ uint32_t s_owner[kBlock / kWave][kWave];
@@ -118,14 +121,30 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, CamDev cam, S
   const float c00 = (U00 * T00 + U01 * T01) + U02 * T02;
   const float c01 = (U00 * T10 + U01 * T11) + U02 * T12;
   const float c11 = (U10 * T10 + U11 * T11) + U12 * T12;
-  const float det = c00 * c11 - c01 * c01;
-  // dilation (2D low-pass filter) and conic
+  // dilation (2D low-pass filter) and conic; the precision form takes the
+  // near-degenerate determinant and inverse in float64 (exact products, one
+  // rounding per subtraction and per division, conic rounded to float32)
   const float h00 = c00 + st.dilation, h11 = c11 + st.dilation, h01 = c01;
-  const float deth = h00 * h11 - h01 * h01;
-  const float ca = h11 / deth, cb = -h01 / deth, cc = h00 / deth;
+  float ca, cb, cc;
+  bool det_ok;
+  if (st.fp64_conic) {
+    const double det = (double)c00 * (double)c11 - (double)c01 * (double)c01;
+    const double deth = (double)h00 * (double)h11 - (double)h01 * (double)h01;
+    ca = (float)((double)h11 / deth);
+    cb = (float)(-(double)h01 / deth);
+    cc = (float)((double)h00 / deth);
+    det_ok = det >= (double)st.det_min;
+  } else {
+    const float det = c00 * c11 - c01 * c01;
+    const float deth = h00 * h11 - h01 * h01;
+    ca = h11 / deth;
+    cb = -h01 / deth;
+    cc = h00 / deth;
+    det_ok = det >= st.det_min;
+  }
   const float o = 1.0f / (1.0f + expf(-g.logits[i]));
 
-  bool ok = (qn >= st.quat_min) && (Z >= cam.near_z) && (det >= st.det_min) && (o > st.alpha_min);
+  bool ok = (qn >= st.quat_min) && (Z >= cam.near_z) && det_ok && (o > st.alpha_min);
   // opacity-aware extent: alpha reaches alpha_min out to d^T Sigma^-1 d = 2 ln(o / alpha_min)
   const float thr = 2.0f * logf(o / st.alpha_min);
   const float ext_x = sqrtf(thr * h00), ext_y = sqrtf(thr * h11);
@@ -138,6 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, CamDev cam, S
   const float wm1 = (float)(cam.width - 1), hm1 = (float)(cam.height - 1);
   bool nonempty = in_range && ok && (hx >= 0.0f) && (lx <= wm1) && (hy >= 0.0f) && (ly <= hm1);
   CandLane me = {mx, my, ca, cb, cc, thr, 0, 0, 1, 0u};
+  uint32_t rect_lo = 0, rect_hi = 0;
   if (nonempty) {
     const int i0x = (lx <= 0.0f) ? 0 : (int)ceilf(lx);
     const int i1x = (hx >= wm1) ? cam.width - 1 : (int)floorf(hx);
@@ -149,59 +169,78 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, CamDev cam, S
       me.ty0 = ty0;
       me.w = tx1 - tx0 + 1;
       me.cand = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-      rect[i] = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
+      rect_lo = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
+      rect_hi = (uint32_t)tx1 | ((uint32_t)ty1 << 16);
     }
   }
   // exact per-tile test of every candidate tile, load-balanced over the wave
   const uint32_t count = wave_tile_walk(me, s_owner[threadIdx.x / kWave], tile, cam.width, cam.height,
                                         [](int, uint32_t, int, int, bool) {});
-  if (!in_range) return;
-  n_tiles[i] = count;
-  if (count == 0) return;
-
-  float rgb[3];
-  const uint32_t clip = sh_colour(g, i, mu0, mu1, mu2, cam, rgb);
-  rec[3 * (size_t)i + 0] = make_float4(mx, my, o, thr);
-  rec[3 * (size_t)i + 1] = make_float4(ca, cb, cc, Z);
-  rec[3 * (size_t)i + 2] = make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(clip | 8u));
-}
-
-hipError_t launch_preprocess(const GaussDev& g, const CamDev& cam, const SetDev& st, int tile, float4* rec,
-                             uint2* rect, uint32_t* n_tiles, uint32_t* depth_key, hipStream_t s) {
-  if (g.n == 0) return hipSuccess;
-  k_preprocess<<<ceil_div(g.n, kBlock), kBlock, 0, s>>>(g, cam, st, tile, rec, rect, n_tiles, depth_key);
-  return hipGetLastError();
-}
-
-// Statistics the host needs to size the rest of the pass: visible count,
-// instance count I (= the sum of the per-Gaussian counts, independent of the
-// depth order) and the range of the visible depth keys.
-__global__ void k_init_stats(uint32_t* __restrict__ c) {
+  const bool vis = in_range && count > 0;
+  if (in_range) n_tiles[i] = count;
+  if (vis) {
+    float rgb[3];
+    const uint32_t clip = sh_colour<SHB>(g, i, mu0, mu1, mu2, cam, rgb);
+    rec[kRecWords * (size_t)i + 0] = make_float4(mx, my, o, thr);
+    rec[kRecWords * (size_t)i + 1] = make_float4(ca, cb, cc, Z);
+    rec[kRecWords * (size_t)i + 2] = make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(clip | 8u));
+    rec[kRecWords * (size_t)i + 3] = make_float4(__uint_as_float(rect_lo), __uint_as_float(rect_hi),
+                                                 __uint_as_float(count), 0.0f);
+  }
+  // this block's share of the statistics the host reads after the preprocess
+  // (visible count, instance count, smallest and largest visible depth key),
+  // reduced last so that no wave waits on another before its own work is done
+  uint32_t b_vis = vis ? 1u : 0u, b_sum = vis ? count : 0u;
+  uint32_t b_min = vis ? __float_as_uint(Z) : 0xffffffffu, b_max = vis ? __float_as_uint(Z) : 0u;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    b_vis += __shfl_xor(b_vis, d, kWave);
+    b_sum += __shfl_xor(b_sum, d, kWave);
+    b_min = min(b_min, (uint32_t)__shfl_xor((int)b_min, d, kWave));
+    b_max = max(b_max, (uint32_t)__shfl_xor((int)b_max, d, kWave));
+  }
+  __shared__ uint4 s_part[kBlock / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  if (lane == 0) s_part[wave] = make_uint4(b_vis, b_sum, b_min, b_max);
+  __syncthreads();
   if (threadIdx.x == 0) {
-    c[kStatVisible] = 0u;
-    c[kStatKeyMin] = 0xffffffffu;
-    c[kStatKeyMax] = 0u;
-    c[kStatDepthBuf] = 0u;
-    reinterpret_cast<unsigned long long*>(c + kStatInstances)[0] = 0ull;
+    uint4 t = s_part[0];
+#pragma unroll
+    for (int w = 1; w < kBlock / kWave; ++w) {
+      const uint4 u = s_part[w];
+      t = make_uint4(t.x + u.x, t.y + u.y, min(t.z, u.z), max(t.w, u.w));
+    }
+    partials[blockIdx.x] = t;
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_stats(const uint32_t* __restrict__ n_tiles,
-                                                  const uint32_t* __restrict__ depth_key, uint32_t n,
+hipError_t launch_preprocess(const GaussDev& g, const CamDev& cam, const SetDev& st, int tile, float4* rec,
+                             uint32_t* n_tiles, uint32_t* depth_key, uint4* partials, hipStream_t s) {
+  if (g.n == 0) return hipSuccess;
+  const uint32_t blocks = ceil_div(g.n, kBlock);
+  if (g.sh_bf16)
+    k_preprocess<true><<<blocks, kBlock, 0, s>>>(g, cam, st, tile, rec, n_tiles, partials, depth_key);
+  else
+    k_preprocess<false><<<blocks, kBlock, 0, s>>>(g, cam, st, tile, rec, n_tiles, partials, depth_key);
+  return hipGetLastError();
+}
+
+// Statistics the host needs to size the rest of the pass -- visible count,
+// instance count I (the sum of the per-Gaussian counts, independent of the
+// depth order) and the range of the visible depth keys -- from the
+// preprocess blocks' partials.  One workgroup; writes every counter word.
+__global__ __launch_bounds__(kBlock) void k_stats(const uint4* __restrict__ partials, uint32_t nb,
                                                   uint32_t* __restrict__ c) {
   __shared__ uint32_t s_vis[kBlock / kWave], s_min[kBlock / kWave], s_max[kBlock / kWave];
   __shared__ unsigned long long s_sum[kBlock / kWave];
   uint32_t vis = 0, kmin = 0xffffffffu, kmax = 0u;
   unsigned long long sum = 0;
-  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    const uint32_t t = n_tiles[i];
-    if (t != 0) {
-      const uint32_t k = depth_key[i];
-      ++vis;
-      sum += t;
-      kmin = min(kmin, k);
-      kmax = max(kmax, k);
-    }
+  for (uint32_t b = threadIdx.x; b < nb; b += kBlock) {
+    const uint4 t = partials[b];
+    vis += t.x;
+    sum += t.y;
+    kmin = min(kmin, t.z);
+    kmax = max(kmax, t.w);
   }
 #pragma unroll
   for (int d = 1; d < kWave; d <<= 1) {
@@ -219,12 +258,11 @@ __global__ __launch_bounds__(kBlock) void k_stats(const uint32_t* __restrict__ n
     for (int w = 1; w < kBlock / kWave; ++w) {
       vis += s_vis[w]; sum += s_sum[w]; kmin = min(kmin, s_min[w]); kmax = max(kmax, s_max[w]);
     }
-    if (vis) {
-      atomicAdd(c + kStatVisible, vis);
-      atomicMin(c + kStatKeyMin, kmin);
-      atomicMax(c + kStatKeyMax, kmax);
-      atomicAdd(reinterpret_cast<unsigned long long*>(c + kStatInstances), sum);
-    }
+    c[kStatVisible] = vis;
+    c[kStatKeyMin] = kmin;
+    c[kStatKeyMax] = kmax;
+    c[kStatDepthBuf] = 0u;
+    reinterpret_cast<unsigned long long*>(c + kStatInstances)[0] = sum;
   }
 }
 
@@ -237,13 +275,8 @@ hipError_t launch_set_word(uint32_t* p, uint32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_stats(const uint32_t* n_tiles, const uint32_t* depth_key, uint32_t n, uint32_t* counters,
-                        hipStream_t s) {
-  k_init_stats<<<1, kWave, 0, s>>>(counters);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || n == 0) return e;
-  const uint32_t blocks = min(ceil_div(n, kBlock * 8), 2048u);
-  k_stats<<<blocks, kBlock, 0, s>>>(n_tiles, depth_key, n, counters);
+hipError_t launch_stats(const uint4* partials, uint32_t nb, uint32_t* counters, hipStream_t s) {
+  k_stats<<<1, kBlock, 0, s>>>(partials, nb, counters);
   return hipGetLastError();
 }
 
@@ -277,10 +310,8 @@ hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth
 __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict__ vis_ids,
                                                       const uint32_t* __restrict__ d_nvis, uint32_t n,
                                                       const uint32_t* __restrict__ offsets,
-                                                      const float4* __restrict__ rec,
-                                                      const uint2* __restrict__ rect,
-                                                      const uint32_t* __restrict__ n_tiles, CamDev cam,
-                                                      int tile, uint32_t cap, uint32_t* __restrict__ keys,
+                                                      const float4* __restrict__ rec, CamDev cam, int tile,
+                                                      uint32_t cap, uint32_t* __restrict__ keys,
                                                       uint32_t* __restrict__ vals) {
   __shared__ uint32_t s_owner[kBlock / kWave][kWave];
   const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
@@ -291,13 +322,16 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
   if (p < nv) {
     gid = vis_ids[p];
     off = offsets[p];
-    end = min(off + n_tiles[gid], cap);
-    const float4 r0 = rec[3 * (size_t)gid + 0];
-    const float4 r1 = rec[3 * (size_t)gid + 1];
+    // three float4 of one 64-byte record: one cache line per Gaussian
+    const float4 r0 = rec[kRecWords * (size_t)gid + 0];
+    const float4 r1 = rec[kRecWords * (size_t)gid + 1];
+    const float4 r3 = rec[kRecWords * (size_t)gid + 3];
+    const uint32_t count = __float_as_uint(r3.z);
+    end = min(off + count, cap);
     int tx0, ty0, tx1, ty1;
-    unpack_rect(rect[gid], tx0, ty0, tx1, ty1);
+    unpack_rect(make_uint2(__float_as_uint(r3.x), __float_as_uint(r3.y)), tx0, ty0, tx1, ty1);
     me = CandLane{r0.x, r0.y, r1.x, r1.y, r1.z, r0.w, tx0, ty0, tx1 - tx0 + 1,
-                  n_tiles[gid] ? (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1)) : 0u};
+                  count ? (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1)) : 0u};
   }
   const uint32_t tiles = (uint32_t)(cam.tiles_x * cam.tiles_y);
   const uint32_t written = wave_tile_walk(
@@ -322,27 +356,45 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
 }
 
 hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uint32_t n, const uint32_t* offsets,
-                            const float4* rec, const uint2* rect, const uint32_t* n_tiles, const CamDev& cam,
-                            int tile, uint32_t cap, uint32_t* keys, uint32_t* vals, hipStream_t s) {
+                            const float4* rec, const CamDev& cam, int tile, uint32_t cap, uint32_t* keys,
+                            uint32_t* vals, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  k_duplicate<<<ceil_div(n, kBlock), kBlock, 0, s>>>(vis_ids, d_nvis, n, offsets, rec, rect, n_tiles, cam, tile,
-                                                     cap, keys, vals);
+  k_duplicate<<<ceil_div(n, kBlock), kBlock, 0, s>>>(vis_ids, d_nvis, n, offsets, rec, cam, tile, cap, keys, vals);
   return hipGetLastError();
 }
 
+// Start and end of each tile's run in the sorted keys.  A thread takes four
+// consecutive keys with one 16-byte load (the key buffer is 256-byte aligned);
+// the neighbours on either side come from cached loads.  Keys >= tiles (the
+// duplicate kernel's padding) are ignored.
 __global__ __launch_bounds__(kBlock) void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t count,
                                                         uint32_t tiles, uint2* __restrict__ ranges) {
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= count) return;
-  const uint32_t k = keys[i];
-  if (k >= tiles) return;
-  if (i == 0 || keys[i - 1] != k) ranges[k].x = i;
-  if (i == count - 1 || keys[i + 1] != k) ranges[k].y = i + 1;
+  const uint32_t i0 = (blockIdx.x * kBlock + threadIdx.x) * 4u;
+  if (i0 >= count) return;
+  uint32_t k[4];
+  if (i0 + 4 <= count) {
+    const uint4 v = *reinterpret_cast<const uint4*>(keys + i0);
+    k[0] = v.x; k[1] = v.y; k[2] = v.z; k[3] = v.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) k[j] = (i0 + j < count) ? keys[i0 + j] : 0xffffffffu;
+  }
+  const uint32_t prev = (i0 == 0) ? 0xffffffffu : keys[i0 - 1];
+  const uint32_t next = (i0 + 4 < count) ? keys[i0 + 4] : 0xffffffffu;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t kj = k[j];
+    if (kj >= tiles) continue;
+    const uint32_t before = j ? k[j - 1] : prev;
+    const uint32_t after = j < 3 ? k[j + 1] : next;
+    if (before != kj) ranges[kj].x = i0 + j;
+    if (after != kj) ranges[kj].y = i0 + j + 1;
+  }
 }
 
 hipError_t launch_tile_ranges(const uint32_t* keys, uint32_t count, uint32_t tiles, uint2* ranges, hipStream_t s) {
   if (count == 0) return hipSuccess;
-  k_tile_ranges<<<ceil_div(count, kBlock), kBlock, 0, s>>>(keys, count, tiles, ranges);
+  k_tile_ranges<<<ceil_div(ceil_div(count, 4), kBlock), kBlock, 0, s>>>(keys, count, tiles, ranges);
   return hipGetLastError();
 }
 

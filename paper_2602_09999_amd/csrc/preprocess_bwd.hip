@@ -2,11 +2,20 @@
 // the 2D splat (mu2D, conic, opacity, colour) to the raw parameters, with the
 // activation gradients fused in (Sec. 3.2 "Rasterization Kernel Fusion").
 //
-// One thread per Gaussian.  Gaussians whose nine accumulators are all zero
-// (not rendered, or hidden behind terminated pixels) get zero gradients
-// without touching their parameters.  The forward quantities needed by the
-// chain rule are recomputed from the parameters; the conic, opacity and the
+// A thread takes four consecutive Gaussians, so the planes of Gaussians
+// whose nine accumulators are all zero (not rendered, or hidden behind
+// terminated pixels; the large majority) are streamed with 16-byte accesses.
+// A lane then loops over its own Gaussians that did receive a gradient, so the
+// lanes of a wave evaluate the chain rule together.  The forward quantities it
+// needs are recomputed from the parameters; the conic, opacity and the
 // colour-clip flags are read from the forward record.
+//
+// The fused variant (Sec. 3.3 "Fusing Backward and Optimizer") applies Adam
+// to each parameter of a Gaussian with a gradient as soon as the gradient is
+// known, so no gradient is stored, and marks those Gaussians; the
+// zero-gradient step of all other parameters is a separate streaming kernel
+// (k_adam_untouched), which runs at the occupancy of a plain stream instead of
+// that of this register-heavy chain rule.
 //
 // Chain (per Gaussian, K = conic = H^-1 with H the dilated Sigma2D):
 //   dL/dH = -K dL/dK K                         (b counted on both off-diagonals)
@@ -49,36 +58,69 @@ __device__ __forceinline__ void sh_basis_and_grad(float x, float y, float z, flo
   Y[15] = C36 * x * (xx - 3.f * yy); dYx[15] = C36 * 3.f * (xx - yy); dYy[15] = C36 * (-6.f * x * y); dYz[15] = 0.f;
 }
 
-__global__ __launch_bounds__(kBlock) void k_preprocess_bwd(GaussDev g, CamDev cam, SetDev st,
-                                                           const float4* __restrict__ rec,
-                                                           const float* __restrict__ accum, GradDev gr) {
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= g.n) return;
+// The 59 raw parameters of a Gaussian, as planes of six groups: means (3),
+// log_scales (3), quats (4), opacity logit (1), sh_dc (3), sh_rest (45).
+constexpr int kParams = 59;
+__host__ __device__ constexpr int group_of(int p) {
+  return p < 3 ? 0 : p < 6 ? 1 : p < 10 ? 2 : p < 11 ? 3 : p < 14 ? 4 : 5;
+}
+__host__ __device__ constexpr int first_plane(int grp) {
+  return grp == 0 ? 0 : grp == 1 ? 3 : grp == 2 ? 6 : grp == 3 ? 10 : grp == 4 ? 11 : 14;
+}
+
+// Plane p of a group set (groups 4 and 5 hold the SH element type).
+template <bool SHB>
+__device__ __forceinline__ float plane_load(const void* const* base, int p, size_t n, size_t i) {
+  const int gi = group_of(p);
+  const size_t off = (size_t)(p - first_plane(gi)) * n + i;
+  if (gi >= 4) return sh_load<SHB>(base[gi], off);
+  return static_cast<const float*>(base[gi])[off];
+}
+template <bool SHB>
+__device__ __forceinline__ void plane_store(void* const* base, int p, size_t n, size_t i, float v) {
+  const int gi = group_of(p);
+  const size_t off = (size_t)(p - first_plane(gi)) * n + i;
+  if (gi >= 4) sh_store<SHB>(base[gi], off, v);
+  else static_cast<float*>(base[gi])[off] = v;
+}
+// Four consecutive elements (i0 % 4 == 0, planes aligned).
+template <bool SHB>
+__device__ __forceinline__ float4 plane_load4(const void* const* base, int p, size_t n, size_t i0) {
+  const int gi = group_of(p);
+  const size_t off = (size_t)(p - first_plane(gi)) * n + i0;
+  if (SHB && gi >= 4) {
+    const uint2 v = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(base[gi]) + off);
+    return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u),
+                       __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xffff0000u));
+  }
+  return *reinterpret_cast<const float4*>(static_cast<const float*>(base[gi]) + off);
+}
+template <bool SHB>
+__device__ __forceinline__ void plane_store4(void* const* base, int p, size_t n, size_t i0, float4 v) {
+  const int gi = group_of(p);
+  const size_t off = (size_t)(p - first_plane(gi)) * n + i0;
+  if (SHB && gi >= 4) {
+    *reinterpret_cast<uint2*>(static_cast<uint16_t*>(base[gi]) + off) =
+        make_uint2((uint32_t)f32_to_bf16(v.x) | ((uint32_t)f32_to_bf16(v.y) << 16),
+                   (uint32_t)f32_to_bf16(v.z) | ((uint32_t)f32_to_bf16(v.w) << 16));
+  } else {
+    *reinterpret_cast<float4*>(static_cast<float*>(base[gi]) + off) = v;
+  }
+}
+
+// Gradient of the loss w.r.t. the 59 raw parameters of Gaussian i, from its
+// nine accumulated 2D gradients acc = dL/d(mu2D.x, mu2D.y, a, b, c, o, r, g, b).
+// Each gradient is handed to emit(p, value) as soon as it is known, with the
+// parameter index p a compile-time constant after unrolling.
+template <bool SHB, typename Emit>
+__device__ __forceinline__ void gaussian_grads(const GaussDev& g, const CamDev& cam, const float4* __restrict__ rec,
+                                               const float* acc, uint32_t i, Emit&& emit) {
+#pragma clang fp contract(on)
   const size_t n = g.n;
-  float acc[9];
-  bool any = false;
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    acc[q] = accum[q * n + i];
-    any |= acc[q] != 0.0f;
-  }
-  if (!any) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      gr.means[k * n + i] = 0.f;
-      gr.log_scales[k * n + i] = 0.f;
-      gr.sh_dc[k * n + i] = 0.f;
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) gr.quats[k * n + i] = 0.f;
-    gr.logits[i] = 0.f;
-    for (int k = 0; k < 45; ++k) gr.sh_rest[k * n + i] = 0.f;
-    return;
-  }
   const float gmx = acc[0], gmy = acc[1], ga = acc[2], gb = acc[3], gc = acc[4], go = acc[5];
-  const float4 r0 = rec[3 * (size_t)i + 0];
-  const float4 r1 = rec[3 * (size_t)i + 1];
-  const float4 r2 = rec[3 * (size_t)i + 2];
+  const float4 r0 = rec[kRecWords * (size_t)i + 0];
+  const float4 r1 = rec[kRecWords * (size_t)i + 1];
+  const float4 r2 = rec[kRecWords * (size_t)i + 2];
   const float o = r0.z, ka = r1.x, kb = r1.y, kc = r1.z;
   const uint32_t clip = __float_as_uint(r2.w);
   const float* W = cam.w;
@@ -151,10 +193,10 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(GaussDev g, CamDev ca
   const float dj11 = dT[1][0] * W[4] + dT[1][1] * W[5] + dT[1][2] * W[6];
   const float dj12 = dT[1][0] * W[8] + dT[1][1] * W[9] + dT[1][2] * W[10];
   const float iz2 = iz * iz, iz3 = iz2 * iz;
-  float dX = -cam.fx * iz2 * dj02 + gmx * cam.fx * iz;
-  float dY = -cam.fy * iz2 * dj12 + gmy * cam.fy * iz;
-  float dZ = -cam.fx * iz2 * dj00 - cam.fy * iz2 * dj11 + 2.f * cam.fx * X * iz3 * dj02 +
-             2.f * cam.fy * Yc * iz3 * dj12 - gmx * cam.fx * X * iz2 - gmy * cam.fy * Yc * iz2;
+  const float dX = -cam.fx * iz2 * dj02 + gmx * cam.fx * iz;
+  const float dY = -cam.fy * iz2 * dj12 + gmy * cam.fy * iz;
+  const float dZ = -cam.fx * iz2 * dj00 - cam.fy * iz2 * dj11 + 2.f * cam.fx * X * iz3 * dj02 +
+                   2.f * cam.fy * Yc * iz3 * dj12 - gmx * cam.fx * X * iz2 - gmy * cam.fy * Yc * iz2;
   float dmu[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) dmu[k] = W[k] * dX + W[4 + k] * dY + W[8 + k] * dZ;
@@ -171,33 +213,32 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(GaussDev g, CamDev ca
   sh_basis_and_grad(ddx, ddy, ddz, Y, dYx, dYy, dYz);
   float gdx = 0.f, gdy = 0.f, gdz = 0.f;
   // the DC band: Y[0] is constant, so it adds no view-direction term
-  gr.sh_dc[i] = dc0 * Y[0];
-  gr.sh_dc[n + i] = dc1 * Y[0];
-  gr.sh_dc[2 * n + i] = dc2 * Y[0];
+  emit(11, dc0 * Y[0]);
+  emit(12, dc1 * Y[0]);
+  emit(13, dc2 * Y[0]);
+#pragma unroll
   for (int k = 1; k < 16; ++k) {
-    float* gp = gr.sh_rest + (size_t)(3 * (k - 1)) * n + i;
+    const int q = 14 + 3 * (k - 1);
     if (k < g.sh_coeffs) {
-      const float* p = g.sh_rest + (size_t)(3 * (k - 1)) * n + i;
-      const float e = dc0 * p[0] + dc1 * p[n] + dc2 * p[2 * n];
+      const size_t o3 = (size_t)(3 * (k - 1)) * n + i;
+      const float e = dc0 * sh_load<SHB>(g.sh_rest, o3) + dc1 * sh_load<SHB>(g.sh_rest, o3 + n) +
+                      dc2 * sh_load<SHB>(g.sh_rest, o3 + 2 * n);
       gdx = fmaf(e, dYx[k], gdx);
       gdy = fmaf(e, dYy[k], gdy);
       gdz = fmaf(e, dYz[k], gdz);
-      gp[0] = dc0 * Y[k];
-      gp[n] = dc1 * Y[k];
-      gp[2 * n] = dc2 * Y[k];
+      emit(q, dc0 * Y[k]);
+      emit(q + 1, dc1 * Y[k]);
+      emit(q + 2, dc2 * Y[k]);
     } else {
-      gp[0] = 0.f;
-      gp[n] = 0.f;
-      gp[2 * n] = 0.f;
+      emit(q, 0.f);
+      emit(q + 1, 0.f);
+      emit(q + 2, 0.f);
     }
   }
   const float dot = ddx * gdx + ddy * gdy + ddz * gdz;
-  dmu[0] += (gdx - ddx * dot) * il;
-  dmu[1] += (gdy - ddy * dot) * il;
-  dmu[2] += (gdz - ddz * dot) * il;
-  gr.means[i] = dmu[0];
-  gr.means[n + i] = dmu[1];
-  gr.means[2 * n + i] = dmu[2];
+  emit(0, dmu[0] + (gdx - ddx * dot) * il);
+  emit(1, dmu[1] + (gdy - ddy * dot) * il);
+  emit(2, dmu[2] + (gdz - ddz * dot) * il);
 
   // ---- Sigma = M M^T, M = R diag(s)
   float dM[3][3];
@@ -208,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(GaussDev g, CamDev ca
 #pragma unroll
   for (int b = 0; b < 3; ++b) {
     const float ds = dM[0][b] * R[0][b] + dM[1][b] * R[1][b] + dM[2][b] * R[2][b];
-    gr.log_scales[b * n + i] = ds * s[b];
+    emit(3 + b, ds * s[b]);
   }
   float dR[3][3];
 #pragma unroll
@@ -223,20 +264,218 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(GaussDev g, CamDev ca
   const float dz = 2.f * (-2.f * z * dR[0][0] - w * dR[0][1] + x * dR[0][2] + w * dR[1][0] - 2.f * z * dR[1][1] +
                           y * dR[1][2] + x * dR[2][0] + y * dR[2][1]);
   const float qdot = w * dw + x * dx + y * dy + z * dz;
-  gr.quats[i] = (dw - w * qdot) * iqn;
-  gr.quats[n + i] = (dx - x * qdot) * iqn;
-  gr.quats[2 * n + i] = (dy - y * qdot) * iqn;
-  gr.quats[3 * n + i] = (dz - z * qdot) * iqn;
+  emit(6, (dw - w * qdot) * iqn);
+  emit(7, (dx - x * qdot) * iqn);
+  emit(8, (dy - y * qdot) * iqn);
+  emit(9, (dz - z * qdot) * iqn);
 
   // ---- opacity = sigmoid(logit)
-  gr.logits[i] = go * o * (1.f - o);
-  (void)st;
+  emit(10, go * o * (1.f - o));
 }
 
-hipError_t launch_preprocess_backward(const GaussDev& g, const CamDev& cam, const SetDev& st, const float4* rec,
-                                      const float* accum, const GradDev& gr, hipStream_t s) {
+// The nine accumulators of Gaussians i0..i0+3 (zero past n) and the mask of
+// those with any nonzero one.
+__device__ __forceinline__ uint32_t load_accum4(const float* __restrict__ accum, size_t n, uint32_t i0, bool full,
+                                                float (&acc)[4][9]) {
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    if (full) {
+      const float4 a = *reinterpret_cast<const float4*>(accum + q * n + i0);
+      acc[0][q] = a.x; acc[1][q] = a.y; acc[2][q] = a.z; acc[3][q] = a.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j][q] = (i0 + j < n) ? accum[q * n + i0 + j] : 0.0f;
+    }
+  }
+  uint32_t mask = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) any |= acc[j][q] != 0.0f;
+    mask |= any ? (1u << j) : 0u;
+  }
+  return mask;
+}
+
+// acc[j] for a lane-varying j, by selects (no indexed register arrays).
+__device__ __forceinline__ void pick_accum(const float (&acc)[4][9], int j, float* a) {
+#pragma unroll
+  for (int q = 0; q < 9; ++q)
+    a[q] = j == 0 ? acc[0][q] : j == 1 ? acc[1][q] : j == 2 ? acc[2][q] : acc[3][q];
+}
+
+// vec: n % 4 == 0 and every plane base aligned for 4-element accesses.
+template <bool SHB>
+__global__ __launch_bounds__(kBlock) void k_preprocess_bwd(GaussDev g, CamDev cam, const float4* __restrict__ rec,
+                                                           const float* __restrict__ accum, GradDev gr, int vec) {
+  const uint32_t i0 = (blockIdx.x * kBlock + threadIdx.x) * 4u;
+  const size_t n = g.n;
+  if (i0 >= n) return;
+  void* const out[6] = {gr.means, gr.log_scales, gr.quats, gr.logits, gr.sh_dc, gr.sh_rest};
+  const bool full = vec && i0 + 4 <= n;
+  float acc[4][9];
+  const uint32_t mask = load_accum4(accum, n, i0, full, acc);
+  // zeros first (16-byte stores when the four are complete); the Gaussians
+  // with a gradient overwrite theirs below
+  if (full) {
+    if (mask != 0xfu) {
+#pragma unroll
+      for (int p = 0; p < kParams; ++p) plane_store4<SHB>(out, p, n, i0, make_float4(0.f, 0.f, 0.f, 0.f));
+    }
+  } else {
+    for (int j = 0; j < 4; ++j) {
+      if (i0 + j >= n || (mask >> j & 1u)) continue;
+#pragma unroll
+      for (int p = 0; p < kParams; ++p) plane_store<SHB>(out, p, n, i0 + j, 0.0f);
+    }
+  }
+  uint32_t todo = mask;
+  while (todo) {
+    const int j = __builtin_ctz(todo);
+    todo &= todo - 1u;
+    float a[9];
+    pick_accum(acc, j, a);
+    const uint32_t i = i0 + j;
+    gaussian_grads<SHB>(g, cam, rec, a, i, [&](int p, float v) { plane_store<SHB>(out, p, n, i, v); });
+  }
+}
+
+// Parameters (updated in place), moments and per-group step sizes.
+struct FusedAdamDev {
+  void* param[6];
+  float* m[6];
+  float* v[6];
+  float step_size[6];
+  AdamCoef c;
+};
+
+// Adam on one parameter (plane p, Gaussian i) with its gradient; p is a
+// run-time value here, so the group and its element type are picked at run time.
+template <bool SHB>
+__device__ __forceinline__ void adam_param(const FusedAdamDev& o, int p, size_t n, uint32_t i, float grad) {
+  const int gi = group_of(p);
+  const size_t off = (size_t)(p - first_plane(gi)) * n + i;
+  float* M = o.m[gi] + off;
+  float* V = o.v[gi] + off;
+  float mm = *M, vv = *V;
+  if (SHB && gi >= 4) {
+    uint16_t* P = static_cast<uint16_t*>(o.param[gi]) + off;
+    float pp = bf16_to_f32(*P);
+    adam_elem(pp, grad, mm, vv, o.c, o.step_size[gi]);
+    *P = f32_to_bf16(pp);
+  } else {
+    float* P = static_cast<float*>(o.param[gi]) + off;
+    float pp = *P;
+    adam_elem(pp, grad, mm, vv, o.c, o.step_size[gi]);
+    *P = pp;
+  }
+  *M = mm;
+  *V = vv;
+}
+
+// For the Gaussians with a gradient: the chain rule (one Gaussian per lane),
+// then Adam on their parameters.  The lanes' gradients go through LDS so the
+// wave spreads the (Gaussian, parameter) updates over all 64 lanes: a wave
+// waits for one or two memory round trips per round instead of one per
+// parameter.  Writes the marks the zero-gradient kernel skips.
+template <bool SHB>
+__global__ __launch_bounds__(kBlock) void k_preprocess_bwd_adam(GaussDev g, CamDev cam,
+                                                                const float4* __restrict__ rec,
+                                                                const float* __restrict__ accum, FusedAdamDev o,
+                                                                uint8_t* __restrict__ touched, int vec) {
+  constexpr int kWaves = kBlock / kWave;
+  __shared__ float s_grad[kWaves][kParams][kWave];
+  __shared__ uint32_t s_gid[kWaves][kWave];
+  __shared__ uint32_t s_src[kWaves][kWave];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const uint32_t i0 = (blockIdx.x * kBlock + threadIdx.x) * 4u;
+  const size_t n = g.n;
+  if (blockIdx.x * kBlock * 4u + (uint32_t)(wave * kWave) * 4u >= n) return;  // whole wave past the end
+  const bool in_range = i0 < n;  // other lanes stay to help with the updates
+  const bool full = in_range && vec && i0 + 4 <= n;
+  float acc[4][9];
+  uint32_t todo = 0;
+  if (in_range) {
+    todo = load_accum4(accum, n, i0, full, acc);
+    touched[i0 / 4] = (uint8_t)todo;  // the zero-gradient kernel leaves these to this one
+  }
+  volatile float* vg = &s_grad[wave][0][0];
+  volatile uint32_t* vid = s_gid[wave];
+  volatile uint32_t* vsrc = s_src[wave];
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  while (true) {
+    const bool mine = todo != 0;
+    const uint64_t act = __ballot(mine);
+    if (act == 0) break;
+    if (mine) {
+      const int j = __builtin_ctz(todo);
+      todo &= todo - 1u;
+      float a[9];
+      pick_accum(acc, j, a);
+      const uint32_t i = i0 + j;
+      gaussian_grads<SHB>(g, cam, rec, a, i, [&](int p, float v) {
+        vg[p * kWave + lane] = group_of(p) >= 4 ? sh_round<SHB>(v) : v;  // as if stored
+      });
+      vid[lane] = i;
+      vsrc[__popcll(act & below)] = (uint32_t)lane;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int c = __popcll(act);
+    for (int idx = lane; idx < c * kParams; idx += kWave) {
+      const int k = idx % c, p = idx / c;
+      const uint32_t src = vsrc[k];
+      adam_param<SHB>(o, p, n, vid[src], vg[p * kWave + src]);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+static bool planes_vec(const void* const* base, int count, bool sh_bf16, size_t n) {
+  if (n % 4 != 0) return false;
+  for (int k = 0; k < count; ++k) {
+    const uintptr_t a = (uintptr_t)base[k];
+    const uintptr_t need = (sh_bf16 && (k % 6) >= 4) ? 8u : 16u;
+    if (a % need) return false;
+  }
+  return true;
+}
+
+hipError_t launch_preprocess_backward(const GaussDev& g, const CamDev& cam, const float4* rec, const float* accum,
+                                      const GradDev& gr, hipStream_t s) {
   if (g.n == 0) return hipSuccess;
-  k_preprocess_bwd<<<ceil_div(g.n, kBlock), kBlock, 0, s>>>(g, cam, st, rec, accum, gr);
+  const void* const planes[6] = {gr.means, gr.log_scales, gr.quats, gr.logits, gr.sh_dc, gr.sh_rest};
+  const int vec = planes_vec(planes, 6, g.sh_bf16, g.n) ? 1 : 0;
+  const uint32_t grid = ceil_div(ceil_div(g.n, 4), kBlock);
+  if (g.sh_bf16)
+    k_preprocess_bwd<true><<<grid, kBlock, 0, s>>>(g, cam, rec, accum, gr, vec);
+  else
+    k_preprocess_bwd<false><<<grid, kBlock, 0, s>>>(g, cam, rec, accum, gr, vec);
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess_backward_adam(const GaussDev& g, const CamDev& cam, const float4* rec,
+                                           const float* accum, void* const params[6], float* const exp_avg[6],
+                                           float* const exp_avg_sq[6], const float lr[6], int64_t step,
+                                           double beta1, double beta2, double eps, uint8_t* touched,
+                                           hipStream_t s) {
+  if (g.n == 0) return hipSuccess;
+  FusedAdamDev o;
+  double bc1 = 1.0;
+  o.c = adam_coef(step, beta1, beta2, eps, &bc1);
+  for (int k = 0; k < 6; ++k) {
+    o.param[k] = params[k];
+    o.m[k] = exp_avg[k];
+    o.v[k] = exp_avg_sq[k];
+    o.step_size[k] = (float)((double)lr[k] / bc1);
+  }
+  const int vec = (g.n % 4 == 0 && ((uintptr_t)accum & 15u) == 0) ? 1 : 0;
+  const uint32_t grid = ceil_div(ceil_div(g.n, 4), kBlock);
+  if (g.sh_bf16)
+    k_preprocess_bwd_adam<true><<<grid, kBlock, 0, s>>>(g, cam, rec, accum, o, touched, vec);
+  else
+    k_preprocess_bwd_adam<false><<<grid, kBlock, 0, s>>>(g, cam, rec, accum, o, touched, vec);
   return hipGetLastError();
 }
 

@@ -13,6 +13,24 @@
 
 namespace fgs {
 
+// Fill of n 32-bit words with a value: used instead of hipMemsetAsync so that
+// a captured graph holds only kernel nodes.  16-byte stores where aligned.
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, uint64_t n) {
+  const uint64_t i4 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * 4;
+  if (i4 + 4 <= n && ((uintptr_t)p & 15u) == 0) {
+    *reinterpret_cast<uint4*>(p + i4) = make_uint4(v, v, v, v);
+  } else {
+    for (uint64_t i = i4; i < i4 + 4 && i < n; ++i) p[i] = v;
+  }
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint64_t threads = (n + 3) / 4;
+  k_fill_u32<<<(uint32_t)((threads + kBlock - 1) / kBlock), kBlock, 0, s>>>(p, v, n);
+  return hipGetLastError();
+}
+
 template <int MODE>
 __device__ __forceinline__ uint32_t scan_load(const uint32_t* __restrict__ in,
                                               const uint32_t* __restrict__ idx, uint32_t count,
@@ -26,7 +44,8 @@ template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ in,
                                                         const uint32_t* __restrict__ idx,
                                                         const uint32_t* __restrict__ d_count,
-                                                        uint32_t n, uint32_t* __restrict__ partials) {
+                                                        uint32_t n, uint32_t* __restrict__ partials,
+                                                        uint32_t* __restrict__ staged) {
   __shared__ uint32_t lds[kBlock / kWave];
   const uint32_t count = (MODE == SCAN_GATHER) ? min(*d_count, n) : n;
   const uint32_t base = blockIdx.x * kScanTile;
@@ -34,7 +53,12 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restri
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const uint32_t i = base + k * kBlock + threadIdx.x;
-    if (i < n) sum += scan_load<MODE>(in, idx, count, i);
+    if (i < n) {
+      const uint32_t v = scan_load<MODE>(in, idx, count, i);
+      // a gathered input is read once: it is kept in `staged` for the down-sweep
+      if (MODE == SCAN_GATHER) staged[i] = v;
+      sum += v;
+    }
   }
   const uint32_t tot = block_reduce_sum(sum, lds);
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
@@ -77,7 +101,7 @@ static hipError_t scan_impl(const uint32_t* in, const uint32_t* idx, const uint3
                             uint32_t* out, uint32_t n, uint32_t* d_total, uint32_t* scratch,
                             hipStream_t s) {
   if (n == 0) {
-    if (d_total) return hipMemsetAsync(d_total, 0, sizeof(uint32_t), s);
+    if (d_total) return launch_fill_u32(d_total, 0u, 1, s);
     return hipSuccess;
   }
   const uint32_t nb = ceil_div(n, kScanTile);
@@ -86,13 +110,17 @@ static hipError_t scan_impl(const uint32_t* in, const uint32_t* idx, const uint3
     return hipGetLastError();
   }
   uint32_t* partials = scratch;
-  k_scan_reduce<MODE><<<nb, kBlock, 0, s>>>(in, idx, d_count, n, partials);
+  k_scan_reduce<MODE><<<nb, kBlock, 0, s>>>(in, idx, d_count, n, partials, out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = scan_impl<SCAN_IDENTITY>(partials, nullptr, nullptr, partials, nb, d_total,
                                scratch + round_words(nb), s);
   if (e != hipSuccess) return e;
-  k_scan_down<MODE><<<nb, kBlock, 0, s>>>(in, idx, d_count, n, partials, out, nullptr);
+  if (MODE == SCAN_GATHER) {  // the gathered values already sit in `out`
+    k_scan_down<SCAN_IDENTITY><<<nb, kBlock, 0, s>>>(out, nullptr, nullptr, n, partials, out, nullptr);
+  } else {
+    k_scan_down<MODE><<<nb, kBlock, 0, s>>>(in, idx, d_count, n, partials, out, nullptr);
+  }
   return hipGetLastError();
 }
 
@@ -107,40 +135,69 @@ hipError_t scan_u32(ScanMode mode, const uint32_t* in, const uint32_t* idx, cons
 
 // ----------------------------------------------------------------------------
 // Radix sort
+//
+// A pass over RB <= 8 key bits is three launches:
+//   hist     per-block digit counts, digit-major: hist[d * nb + b]
+//   colscan  one workgroup per digit: exclusive prefix of hist[d][*] over the
+//            blocks, in place, and the digit total
+//   scatter  digit starts from the 2^RB totals (scanned in LDS), then the
+//            stable block-local ranking and the coalesced write-out
+// The bits of a sort are split evenly over ceil(bits / 8) passes, so a 13-bit
+// tile key takes 7 + 6 bits: fewer, longer runs per digit in each block.
 // ----------------------------------------------------------------------------
+template <int RB>
 __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restrict__ keys, uint32_t n,
                                                        const uint32_t* __restrict__ d_count, int shift,
                                                        uint32_t* __restrict__ hist, uint32_t nb) {
-  __shared__ uint32_t h[kRadix];
-  static_assert(kRadix == kBlock, "one digit per thread");
-  h[threadIdx.x] = 0;
+  constexpr int R = 1 << RB;
+  __shared__ uint32_t h[R];
+  if (threadIdx.x < R) h[threadIdx.x] = 0;
   __syncthreads();
   const uint32_t count = d_count ? min(*d_count, n) : n;
   const uint32_t base = blockIdx.x * kScanTile;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const uint32_t i = base + k * kBlock + threadIdx.x;
-    if (i < count) atomicAdd(&h[(keys[i] >> shift) & (kRadix - 1)], 1u);
+    if (i < count) atomicAdd(&h[(keys[i] >> shift) & (R - 1)], 1u);
   }
   __syncthreads();
-  hist[(size_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+  if (threadIdx.x < R) hist[(size_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-// Scatter of one radix pass.  Each workgroup ranks its 4096 keys stably
-// (wave ballots + per-wave digit counters), places them in LDS in
-// (digit, input order) order, and then writes them out so that consecutive
+// Workgroup d: exclusive scan of hist[d][0..nb) in place; totals[d] = its sum.
+__global__ __launch_bounds__(kBlock) void k_radix_colscan(uint32_t* __restrict__ hist, uint32_t nb,
+                                                          uint32_t* __restrict__ totals) {
+  __shared__ uint32_t lds[kBlock / kWave];
+  uint32_t* col = hist + (size_t)blockIdx.x * nb;
+  uint32_t carry = 0;
+  for (uint32_t b0 = 0; b0 < nb; b0 += kBlock) {
+    const uint32_t b = b0 + threadIdx.x;
+    const uint32_t v = b < nb ? col[b] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(v, lds, &tot);
+    if (b < nb) col[b] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+}
+
+// Scatter of one pass.  Each workgroup ranks its 4096 keys stably (wave
+// ballots over the RB digit bits + per-wave digit counters), places them in
+// LDS in (digit, input order) order, and writes them out so that consecutive
 // threads store consecutive addresses of each digit's run.
+template <int RB>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __restrict__ keys_in,
                                                           const uint32_t* __restrict__ vals_in,
                                                           uint32_t* __restrict__ keys_out,
                                                           uint32_t* __restrict__ vals_out, uint32_t n,
                                                           const uint32_t* __restrict__ d_count, int shift,
                                                           const uint32_t* __restrict__ hist_scan,
-                                                          uint32_t nb) {
+                                                          const uint32_t* __restrict__ totals, uint32_t nb) {
+  constexpr int R = 1 << RB;
   constexpr int kWaves = kBlock / kWave;
-  __shared__ uint32_t wcnt[kWaves][kRadix];
-  __shared__ uint32_t gdelta[kRadix];  // global start of the digit minus its block-local start (mod 2^32)
-  __shared__ uint32_t lstart[kRadix];  // block-local start of each digit
+  __shared__ uint32_t wcnt[kWaves][R];
+  __shared__ uint32_t gdelta[R];  // global start of the digit minus its block-local start (mod 2^32)
+  __shared__ uint32_t lstart[R];  // block-local start of each digit
   __shared__ uint32_t s_key[kScanTile];
   __shared__ uint32_t s_val[kScanTile];
   __shared__ uint32_t scan_lds[kBlock / kWave];
@@ -150,9 +207,19 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
   const uint32_t in_block = min((uint32_t)kScanTile, count - base);
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
+  const bool digit_thread = threadIdx.x < R;
+  if (digit_thread) {
 #pragma unroll
-  for (int w = 0; w < kWaves; ++w) wcnt[w][threadIdx.x] = 0;
-  const uint32_t gbase = hist_scan[(size_t)threadIdx.x * nb + blockIdx.x];
+    for (int w = 0; w < kWaves; ++w) wcnt[w][threadIdx.x] = 0;
+  }
+  // global start of this block's run of digit t: digit start (scan of the
+  // totals) + the blocks before this one
+  uint32_t gbase;
+  {
+    uint32_t tot;
+    const uint32_t dstart = block_exclusive_scan(digit_thread ? totals[threadIdx.x] : 0u, scan_lds, &tot);
+    gbase = digit_thread ? dstart + hist_scan[(size_t)threadIdx.x * nb + blockIdx.x] : 0u;
+  }
   __syncthreads();
 
   // Wave w owns items [base + w*1024, base + (w+1)*1024), visited 64 at a time
@@ -167,10 +234,10 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
     const bool valid = i < count;
     key[k] = valid ? keys_in[i] : 0u;
     val[k] = valid ? vals_in[i] : 0u;
-    const uint32_t d = (key[k] >> shift) & (kRadix - 1);
+    const uint32_t d = (key[k] >> shift) & (R - 1);
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
+    for (int b = 0; b < RB; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t m = __ballot(bit);
       peers &= bit ? m : ~m;
@@ -185,23 +252,27 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
   {
     // thread t = digit t: prefix over waves, block-local digit start, global offset
     uint32_t run = 0;
+    if (digit_thread) {
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-      const uint32_t t = wcnt[w][threadIdx.x];
-      wcnt[w][threadIdx.x] = run;
-      run += t;
+      for (int w = 0; w < kWaves; ++w) {
+        const uint32_t t = wcnt[w][threadIdx.x];
+        wcnt[w][threadIdx.x] = run;
+        run += t;
+      }
     }
     uint32_t tot;
     const uint32_t ls = block_exclusive_scan(run, scan_lds, &tot);
-    lstart[threadIdx.x] = ls;
-    gdelta[threadIdx.x] = gbase - ls;
+    if (digit_thread) {
+      lstart[threadIdx.x] = ls;
+      gdelta[threadIdx.x] = gbase - ls;
+    }
   }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const uint32_t i = wbase + k * kWave + lane;
     if (i < count) {
-      const uint32_t d = (key[k] >> shift) & (kRadix - 1);
+      const uint32_t d = (key[k] >> shift) & (R - 1);
       const uint32_t lp = lstart[d] + wcnt[wave][d] + rank[k];
       s_key[lp] = key[k];
       s_val[lp] = val[k];
@@ -213,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
     const uint32_t j = k * kBlock + threadIdx.x;
     if (j < in_block) {
       const uint32_t kk = s_key[j];
-      const uint32_t d = (kk >> shift) & (kRadix - 1);
+      const uint32_t d = (kk >> shift) & (R - 1);
       const uint32_t pos = gdelta[d] + j;  // = gbase[d] + (j - lstart[d])
       keys_out[pos] = kk;
       vals_out[pos] = s_val[j];
@@ -223,8 +294,18 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
 
 size_t radix_scratch_words(uint64_t n) {
   const uint64_t nb = (n + kScanTile - 1) / kScanTile;
-  const uint64_t hist = (uint64_t)kRadix * nb;
-  return round_words(hist) + scan_scratch_words(hist);
+  return round_words((uint64_t)kRadix * nb) + round_words(kRadix);
+}
+
+template <int RB>
+static hipError_t radix_pass(uint32_t* keys_in, uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
+                             uint32_t n, const uint32_t* d_count, int shift, uint32_t* hist, uint32_t* totals,
+                             uint32_t nb, hipStream_t s) {
+  k_radix_hist<RB><<<nb, kBlock, 0, s>>>(keys_in, n, d_count, shift, hist, nb);
+  k_radix_colscan<<<1u << RB, kBlock, 0, s>>>(hist, nb, totals);
+  k_radix_scatter<RB><<<nb, kBlock, 0, s>>>(keys_in, vals_in, keys_out, vals_out, n, d_count, shift, hist,
+                                            totals, nb);
+  return hipGetLastError();
 }
 
 hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
@@ -237,17 +318,26 @@ hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], uint32_t n, co
   }
   const uint32_t nb = ceil_div(n, kScanTile);
   uint32_t* hist = scratch;
-  uint32_t* scan_tmp = scratch + round_words((size_t)kRadix * nb);
-  for (int shift = begin_bit; shift < end_bit; shift += kRadixBits) {
-    k_radix_hist<<<nb, kBlock, 0, s>>>(keys[cur], n, d_count, shift, hist, nb);
-    hipError_t e = hipGetLastError();
+  uint32_t* totals = scratch + round_words((size_t)kRadix * nb);
+  const int bits = end_bit - begin_bit;
+  const int passes = (bits + kRadixBits - 1) / kRadixBits;
+  int shift = begin_bit;
+  for (int p = 0; p < passes; ++p) {
+    // the remaining bits, split evenly over the remaining passes
+    const int rb = (end_bit - shift + (passes - p) - 1) / (passes - p);
+    hipError_t e = hipSuccess;
+    switch (rb) {
+      case 1: e = radix_pass<1>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
+      case 2: e = radix_pass<2>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
+      case 3: e = radix_pass<3>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
+      case 4: e = radix_pass<4>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
+      case 5: e = radix_pass<5>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
+      case 6: e = radix_pass<6>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
+      case 7: e = radix_pass<7>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
+      default: e = radix_pass<8>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
+    }
     if (e != hipSuccess) return e;
-    e = scan_u32(SCAN_IDENTITY, hist, nullptr, nullptr, hist, (uint32_t)(kRadix * nb), nullptr, scan_tmp, s);
-    if (e != hipSuccess) return e;
-    k_radix_scatter<<<nb, kBlock, 0, s>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, d_count,
-                                          shift, hist, nb);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    shift += rb;
     cur ^= 1;
   }
   *final_buf = cur;

@@ -42,7 +42,8 @@ def sorted_instances(rz: B.Rasterizer):
 
 
 def record(rz: B.Rasterizer, n: int) -> np.ndarray:
-    return rz.view("rec", 12 * n, dtype=torch.float32).cpu().numpy().reshape(n, 12)
+    """The first three float4 of each 64-byte record: mu2D, o, thr | a, b, c, z | rgb, flags."""
+    return rz.view("rec", 16 * n, dtype=torch.float32).cpu().numpy().reshape(n, 16)[:, :12]
 
 
 def last_ids(rz: B.Rasterizer, last: torch.Tensor) -> np.ndarray:

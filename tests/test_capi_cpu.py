@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported_and_bound(lib):
     for name in names:
         assert hasattr(lib, name), name
         assert name in L.SIGNATURES, name
-    assert lib.fgs_abi_version() == 1
+    assert lib.fgs_abi_version() == 4
 
 
 def test_default_settings_match_the_paper(lib):
@@ -50,8 +50,9 @@ def test_workspace_size_and_layout(lib):
     b = B.workspace_size(10_000, cam, instance_capacity=200_000)
     assert b - a >= 4 * 4 * 100_000
     lay = B.workspace_layout(10_000, cam, instance_capacity=100_000)
-    offs = [lay.rec, lay.rect, lay.n_tiles, lay.depth_key, lay.counters, lay.vis_keys[0], lay.vis_ids[0],
-            lay.inst_offsets, lay.inst_keys[0], lay.inst_vals[0], lay.ranges, lay.accum, lay.scratch]
+    offs = [lay.rec, lay.n_tiles, lay.depth_key, lay.counters, lay.vis_keys[0], lay.vis_ids[0],
+            lay.inst_offsets, lay.inst_keys[0], lay.inst_vals[0], lay.ranges, lay.accum, lay.touched, lay.scratch]
+    assert lay.scratch - lay.touched >= (10_000 + 3) // 4
     assert all(o % 256 == 0 for o in offs)
     assert lay.total == a and lay.tiles_x == 16 and lay.tiles_y == 16
     assert lay.inst_final == 1  # 256 tiles -> 8 key bits -> one radix pass
@@ -79,6 +80,10 @@ def test_invalid_arguments_are_rejected_without_launching(lib):
     assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(st8), 0, ctypes.byref(size)) == L.FGS_ERR_UNSUPPORTED
     st7 = B.default_settings(tile=7)
     assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(st7), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
+    stf = B.default_settings(flags=2)  # only FGS_FLAG_FP64_CONIC (bit 0) is defined
+    assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(stf), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
+    st1 = B.default_settings(flags=1)
+    assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(st1), 0, ctypes.byref(size)) == L.FGS_OK
     stb = B.default_settings(alpha_min=0.995)
     assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(stb), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
 
@@ -91,14 +96,14 @@ def test_invalid_arguments_are_rejected_without_launching(lib):
     r = lib.fgs_rasterize_forward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), None, 0, 0, None, None, None,
                                   ctypes.byref(stats), None)
     assert r == L.FGS_ERR_INVALID_ARGUMENT
-    # bf16 SH is a valid option that is not implemented yet
+    # an unknown SH element type is rejected before any launch
     fake = 1 << 20
     for f in ("means", "log_scales", "quats", "opacity_logits", "sh_dc", "sh_rest"):
         setattr(g, f, fake)
-    g.sh_dtype = L.FGS_BF16
+    g.sh_dtype = 7
     r = lib.fgs_rasterize_forward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), fake, 1 << 30, 0, fake, None,
                                   fake, ctypes.byref(stats), None)
-    assert r == L.FGS_ERR_UNSUPPORTED
+    assert r == L.FGS_ERR_INVALID_ARGUMENT
     g.sh_dtype = L.FGS_F32
     g.sh_degree = 4
     r = lib.fgs_rasterize_forward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), fake, 1 << 30, 0, fake, None,
@@ -118,6 +123,22 @@ def test_invalid_arguments_are_rejected_without_launching(lib):
     r = lib.fgs_rasterize_backward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), fake, 1 << 30, 0, fake, fake,
                                    None, ctypes.byref(gr), None)
     assert r == L.FGS_ERR_INVALID_ARGUMENT
+    # fused backward + Adam: missing state, bad hyperparameters, non-finite lr
+    mo = L.AdamMoments()
+    r = lib.fgs_rasterize_backward_adam(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), fake, 1 << 30, 0, fake,
+                                        fake, fake, None, 1, 0.9, 0.999, 1e-15, None)
+    assert r == L.FGS_ERR_INVALID_ARGUMENT
+    r = lib.fgs_rasterize_backward_adam(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), fake, 1 << 30, 0, fake,
+                                        fake, fake, ctypes.byref(mo), 0, 0.9, 0.999, 1e-15, None)
+    assert r == L.FGS_ERR_INVALID_ARGUMENT
+    mo.lr[2] = float("nan")
+    r = lib.fgs_rasterize_backward_adam(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), fake, 1 << 30, 0, fake,
+                                        fake, fake, ctypes.byref(mo), 1, 0.9, 0.999, 1e-15, None)
+    assert r == L.FGS_ERR_INVALID_ARGUMENT and b"lr[2]" in lib.fgs_last_error()
+    mo.lr[2] = 1e-3
+    r = lib.fgs_rasterize_backward_adam(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), fake, 1 << 30, 0, fake,
+                                        fake, fake, ctypes.byref(mo), 1, 0.9, 0.999, 1e-15, None)
+    assert r == L.FGS_ERR_INVALID_ARGUMENT and b"moment" in lib.fgs_last_error()
     # Adam argument checks
     arr = (L.AdamGroup * 1)()
     assert lib.fgs_adam_step(arr, 0, 1, 0.9, 0.999, 1e-15, None) == L.FGS_ERR_INVALID_ARGUMENT
@@ -125,7 +146,14 @@ def test_invalid_arguments_are_rejected_without_launching(lib):
     arr[0].numel = 4
     assert lib.fgs_adam_step(arr, 1, 1, 0.9, 0.999, 1e-15, None) == L.FGS_ERR_INVALID_ARGUMENT
     assert lib.fgs_adam_step(arr, 1, 1, 1.5, 0.999, 1e-15, None) == L.FGS_ERR_INVALID_ARGUMENT
+    arr[0].param = arr[0].grad = arr[0].exp_avg = arr[0].exp_avg_sq = fake
+    arr[0].dtype = 5
+    assert lib.fgs_adam_step(arr, 1, 1, 0.9, 0.999, 1e-15, None) == L.FGS_ERR_INVALID_ARGUMENT
     assert lib.fgs_l1_loss_backward(None, None, 10, None, None, None) == L.FGS_ERR_INVALID_ARGUMENT
+    # timing hook: known step names only, non-NULL events; NULL disarms
+    assert lib.fgs_time_next_launch(b"no_such_step", fake, fake) == L.FGS_ERR_INVALID_ARGUMENT
+    assert lib.fgs_time_next_launch(b"adam", None, fake) == L.FGS_ERR_INVALID_ARGUMENT
+    assert lib.fgs_time_next_launch(None, None, None) == L.FGS_OK
     assert lib.fgs_status_string(2) == b"instance capacity exceeded"
 
 

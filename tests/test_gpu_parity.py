@@ -44,6 +44,8 @@ CASES = {
     "lookat": lambda: (S.make_scene(5_000, 3, z_range=(-1.0, 1.0)),
                        S.look_at_camera((0.5, -1.0, -4.0), (0.0, 0.0, 0.0), 120, 96, 130.0, bg=(0.1, 0.1, 0.1))),
     "dense": lambda: (S.make_scene(6_000, 4, log_scale_mean=-3.0), S.identity_camera(64, 48, 64.0)),
+    # n % 4 != 0 exercises the per-element tails of the four-Gaussian kernels
+    "ragged_n": lambda: (S.make_scene(2_999, 5), S.identity_camera(90, 70, 100.0, bg=(0.3, 0.1, 0.6))),
 }
 
 
@@ -76,6 +78,13 @@ def test_preprocess_record_matches_oracle(case):
         assert (np.abs(rec[vis, 4 + j] - con[:, j]) / cs).max() < 1e-4
     assert np.abs(rec[vis, 8:11] - pre["rgb"][vis]).max() < 2e-6
     assert np.array_equal(rec[vis, 7], ref["depth"][vis])
+    # fourth float4: packed tile rectangle and the instance count, as uint32 bits
+    r3 = rz.view("rec", 16 * n, dtype=torch.float32).cpu().numpy().reshape(n, 16)[:, 12:15].view(np.uint32)
+    assert np.array_equal(r3[vis, 2], n_tiles[vis])
+    tx0, ty0, tx1, ty1, _ = O.tile_rect(O.record32(sc, cam), cam.width, cam.height, 16)
+    sure = vis & ~np.isin(np.arange(n), list(bg))
+    assert np.array_equal(r3[sure, 0], (tx0 | (ty0 << 16))[sure].astype(np.uint32))
+    assert np.array_equal(r3[sure, 1], (tx1 | (ty1 << 16))[sure].astype(np.uint32))
 
 
 @pytest.mark.parametrize("case", list(CASES))
@@ -112,7 +121,7 @@ def test_forward_image_matches_oracle(case):
     assert np.array_equal(lid[ok], ref["last_id"].numpy()[ok])
 
 
-@pytest.mark.parametrize("case", ["c1", "ragged_bg", "lookat", "dense"])
+@pytest.mark.parametrize("case", ["c1", "ragged_bg", "lookat", "dense", "ragged_n"])
 def test_backward_gradients_match_oracle(case):
     sc, cam = CASES[case]()
     say("backward", case)
