@@ -204,3 +204,37 @@ def test_adam_bf16_parameters_match_fp64_update():
     for i in range(3):
         assert rel_l2(ms[i], rm[i]) <= 1e-6
         assert rel_l2(vs[i], rv[i]) <= 1e-6
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_precision_form_fp64_conic_keys_and_image(case):
+    """Precision form: bfloat16 SH plus the float64 determinant/inverse of the
+    2x2 covariance.  Keys stay bit-exact against the key reference taking the
+    same float64 steps; the image against the FP64 oracle."""
+    from tests.gpu_util import compare_lists, sorted_instances
+    sc, cam = CASES[case]()
+    say("precision form", case)
+    st = B.default_settings(flags=1)
+    rz = B.Rasterizer(cam, settings=st)
+    params = gpu_params(sc, torch.bfloat16)
+    image, t_final, last = rz.forward(params)
+    torch.cuda.synchronize()
+    keys, vals, ranges = sorted_instances(rz)
+    nom, border = O.keys_ref_banded(sc, cam, fp64_conic=True)
+    flips = compare_lists(keys, vals, ranges, nom, border, depth=nom["depth"])
+    say("  instances", len(keys), "borderline pairs", len(border), "flipped", flips)
+    assert flips <= len(border)
+    # the conic of the float64 path against the reference's float64 steps (the
+    # float32 exp of the scales may differ by an ulp between the two sides)
+    n = S.count(sc)
+    rec = rz.view("rec", 16 * n, dtype=torch.float32).cpu().numpy().reshape(n, 16)
+    vis = rz.view("n_tiles", n).cpu().numpy() > 0
+    ref_con = np.stack([nom["record"][k][vis] for k in ("a", "b", "c")], 1).astype(np.float64)
+    e = (np.abs(rec[vis, 4:7] - ref_con) / np.abs(ref_con).max(1, keepdims=True)).max()
+    say("  conic max relative difference to the reference's float64 path", float(e))
+    assert e < 1e-4
+    ref = O.render64(bf16_scene(sc), cam)
+    ok = ~ref["borderline"].numpy()
+    err = np.abs(image.cpu().double().numpy() - ref["image"].numpy()).max(0)
+    say("  image max err vs FP64 oracle", float(err[ok].max()))
+    assert err[ok].max() <= IMG_TOL
