@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--workload", default="c3", choices=sorted(S.WORKLOADS))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 16-view batched step")
+    ap.add_argument("--no-dynamic", action="store_true", help="skip the dynamic (4D) step")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured with rocprofv3 counters (optional)")
@@ -249,6 +251,115 @@ def run_variant(name, args, scene, cam, target, dev, w):
             "fused": fused, "sh_bf16": shd == torch.bfloat16, "zorder": zorder, "zorder_ms": zorder_ms}
 
 
+BATCH_VIEWS, BATCH_N = 16, 1_500_000
+DYN_STEPS, DYN_N = 8, 1_000_000
+
+
+def batched_step_fn(br, params, opt, target, dl, grads, mode):
+    from paper_2602_09999_amd import binding as B
+
+    def step():
+        images, _, _ = br.forward(params, mode=mode)
+        B.l1_loss_backward(images, target, dl)
+        br.backward(params, dl, grads)
+        opt.step(grads)
+    return step
+
+
+def time_steps(step, steps, warmup):
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def run_batched(args, dev):
+    """Several views per step: 1.5M Gaussians around the origin, 16 cameras on
+    the radius-5 sphere with seeded uneven resolutions (640-1920 x 480-1080,
+    f = width); tile size from the autotuner; the step timed eagerly and as a
+    captured graph replayed (synchronisation-free forward, device step count)."""
+    import paper_2602_09999_amd as P
+    from paper_2602_09999_amd import _lib as L
+    from paper_2602_09999_amd import binding as B
+    from paper_2602_09999_amd.autotune import TileAutotuner
+    scene = S.batch_scene(BATCH_N, seed=args.seed)
+    cams = S.uniform_sphere_cameras(BATCH_VIEWS, seed=args.seed)
+    params = {k: v.to(dev) for k, v in scene.items()}
+    del scene
+    tuner = TileAutotuner(reps=2)
+    tile = tuner.choose(params, cams)
+    tile_ms = next(iter(tuner.cache.values()))["ms"]
+    st = B.default_settings(tile=tile)
+    npix = sum(B.view_pixels(cams))
+    target = torch.rand(3 * npix, generator=torch.Generator().manual_seed(args.seed)).to(dev)
+    dl = torch.empty(3 * npix, device=dev)
+    out = {"workload": f"{BATCH_N} Gaussians, {BATCH_VIEWS} views on a radius-5 sphere, "
+                       f"{npix} pixels in all", "tile": tile, "autotune_ms_per_fwd_bwd": tile_ms}
+    for mode_name, graph in (("eager", False), ("graph", True)):
+        br = B.BatchRasterizer(cams, settings=st)
+        opt = P.FusedAdam(params, S.ADAM_LR, device_step=graph)
+        grads = {k: torch.empty_like(v) for k, v in params.items()}
+        br.forward(params)
+        br.ensure(BATCH_N, int(br.last_stats["n_instances"] * 1.3))
+        out["instances"] = br.last_stats["n_instances"]
+        step = batched_step_fn(br, params, opt, target, dl, grads, L.FGS_FORWARD_NO_SYNC if graph else 0)
+        if graph:
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                step()
+            torch.cuda.current_stream().wait_stream(side)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                step()
+            sec = time_steps(g.replay, max(3, args.steps // 5), 1)
+            if int(br.counters()[7].item()) != 0:
+                raise RuntimeError("instance capacity exceeded during graph replay")
+        else:
+            sec = time_steps(step, max(3, args.steps // 5), 1)
+        out[f"{mode_name}_ms_per_step"] = sec * 1e3
+        out[f"{mode_name}_steps_per_s"] = 1.0 / sec
+        out[f"{mode_name}_views_per_s"] = BATCH_VIEWS / sec
+        log(f"batched {mode_name}: {sec * 1e3:.2f} ms per step of {BATCH_VIEWS} views (tile {tile})")
+        del br, opt, grads
+        torch.cuda.empty_cache()
+    return out
+
+
+def run_dynamic(args, dev):
+    """Dynamic Gaussians: mean(t) = mu + v t + a t^2 (v ~ N(0, 0.1), a ~
+    N(0, 0.02)), 1M Gaussians, 8 timesteps t = k/7 at 1280x720 (identity
+    camera, f = 1000) in one batched step, bfloat16 SH; the backward yields the
+    velocity and acceleration gradients, and Adam updates them too."""
+    import paper_2602_09999_amd as P
+    from paper_2602_09999_amd import binding as B
+    scene = S.make_scene(DYN_N, seed=args.seed)
+    scene.update(S.make_motion(DYN_N, seed=args.seed))
+    params = {k: v.to(dev) for k, v in scene.items()}
+    del scene
+    for k in ("sh_dc", "sh_rest"):
+        params[k] = params[k].bfloat16().contiguous()
+    cam = S.identity_camera(1280, 720, 1000.0)
+    times = S.timesteps(DYN_STEPS)
+    br = B.BatchRasterizer([cam] * DYN_STEPS, times=times)
+    lrs = dict(S.ADAM_LR, velocity=S.ADAM_LR["means"], accel=S.ADAM_LR["means"])
+    opt = P.FusedAdam(params, lrs)
+    npix = sum(B.view_pixels([cam] * DYN_STEPS))
+    target = torch.rand(3 * npix, generator=torch.Generator().manual_seed(args.seed + 1)).to(dev)
+    dl = torch.empty(3 * npix, device=dev)
+    grads = {k: torch.empty_like(v) for k, v in params.items()}
+    step = batched_step_fn(br, params, opt, target, dl, grads, 0)
+    sec = time_steps(step, max(3, args.steps // 5), 2)
+    log(f"dynamic: {sec * 1e3:.2f} ms per step of {DYN_STEPS} timesteps")
+    return {"workload": f"{DYN_N} dynamic Gaussians, {DYN_STEPS} timesteps, 1280x720, bf16 SH",
+            "ms_per_step": sec * 1e3, "steps_per_s": 1.0 / sec, "timesteps_per_s": DYN_STEPS / sec,
+            "instances": br.last_stats["n_instances"]}
+
+
 def workload_counts(r, w, dev):
     """Instance and gradient counts of a finished run (outside any timed region)."""
     rz, last = r["rz"], r["last"]
@@ -361,6 +472,12 @@ def main():
             "covers": "Morton permutation of the means + gather of all parameters and both Adam moments"},
         "variants": variants,
     }
+    if not args.no_batched:
+        out["batched"] = run_batched(args, dev)
+        torch.cuda.empty_cache()
+    if not args.no_dynamic:
+        out["dynamic"] = run_dynamic(args, dev)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.seed, args.cpu_budget_s)
     print(json.dumps(out))

@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define FGS_ABI_VERSION 4
+#define FGS_ABI_VERSION 5
 
 typedef enum fgs_status {
   FGS_OK = 0,
@@ -63,7 +63,10 @@ typedef enum fgs_dtype { FGS_F32 = 0, FGS_BF16 = 1 } fgs_dtype;
  * sh_dtype: FGS_F32, or FGS_BF16 for the precision form (SH coefficients
  * and their gradients stored as bfloat16; everything else, including all
  * blending, transmittance and gradient accumulation, stays float32).
- * sh_degree in 0..3 (planes beyond the degree are not read). n may be 0.   */
+ * sh_degree in 0..3 (planes beyond the degree are not read). n may be 0.
+ * Dynamic scenes (the batched entry points, one time per view): velocity and
+ * accel [3][n] (both or neither; NULL = static) give the mean at time t as
+ * (means + velocity t) + accel t^2 in float32.                            */
 typedef struct fgs_gaussians {
   int64_t n;
   const float* means;
@@ -74,10 +77,13 @@ typedef struct fgs_gaussians {
   const void* sh_rest;
   int32_t sh_dtype;
   int32_t sh_degree;
+  const float* velocity;
+  const float* accel;
 } fgs_gaussians;
 
 /* Gradient planes with the layout of fgs_gaussians (all written in full);
- * sh_dc and sh_rest have the element type of the SH coefficients. */
+ * sh_dc and sh_rest have the element type of the SH coefficients; velocity
+ * and accel are written for dynamic Gaussians (else unused). */
 typedef struct fgs_gaussian_grads {
   float* means;
   float* log_scales;
@@ -85,6 +91,8 @@ typedef struct fgs_gaussian_grads {
   float* opacity_logits;
   void* sh_dc;
   void* sh_rest;
+  float* velocity;
+  float* accel;
 } fgs_gaussian_grads;
 
 /* Pinhole camera of Eq. (1)-(2).  (host struct)
@@ -107,7 +115,7 @@ typedef struct fgs_camera {
  *   t_min 1e-4       (stop once the transmittance falls below it, App. B.1)
  *   dilation 0.3     (Sigma2D + 0.3 I, App. C.2)
  *   quat_min 1e-4, det_min 1e-6 (degenerate-Gaussian guard, App. B.1)
- * Only tile = 16 is implemented (others: FGS_ERR_UNSUPPORTED).              */
+ * tile: 8, 16 or 32 pixels (one wavefront per tile in every case).         */
 typedef struct fgs_settings {
   int32_t tile;
   float alpha_min;
@@ -139,7 +147,10 @@ typedef struct fgs_forward_stats {
  *   counters   uint32[16]   [0] visible count, [1] smallest and [2] largest
  *                           visible depth key, [3] index of the ping-pong buffer
  *                           holding the depth-sorted visible ids, [4..5] the
- *                           instance count I (uint64)
+ *                           instance count I (uint64), [6] min(I, capacity),
+ *                           [7] 1 when I exceeded the capacity
+ * With several views, the per-Gaussian regions (rec, n_tiles, depth_key,
+ * vis_*, accum) hold n_views * n entries, entry v * n + i for view v.
  *   vis_ids    uint32[n] x2 ping-pong (see counters[3])
  *   inst_keys  uint32[cap] x2, inst_vals uint32[cap] x2: tile ids and
  *                           Gaussian ids; sorted in [inst_final]
@@ -155,8 +166,10 @@ typedef struct fgs_layout {
   size_t ranges, accum, touched, scratch, total;
   int32_t inst_final;
   int32_t reserved;
-  int32_t tiles_x, tiles_y;
+  int32_t tiles_x, tiles_y;      /* tile grid of view 0 */
   int64_t instance_capacity;
+  int64_t n_views;
+  int64_t total_tiles;           /* all views; tile ranges and sort keys span them */
 } fgs_layout;
 
 /* One Adam parameter group (host struct).  param and grad: [numel] of
@@ -276,6 +289,15 @@ fgs_status fgs_rasterize_backward_adam(const fgs_gaussians* g, const fgs_camera*
 fgs_status fgs_adam_step(const fgs_adam_group* groups, int32_t n_groups, int64_t step,
                          double beta1, double beta2, double eps, void* stream);
 
+/* fgs_adam_step with the step count on the device, for a step captured into
+ * a graph and replayed: d_state is a device buffer of at least 256 bytes,
+ * 8-byte aligned, whose first int64 is the step counter t (zero it before
+ * the first step); each call increments it, forms the bias corrections of
+ * the new t on the device (in double, as fgs_adam_step does on the host) and
+ * applies Adam.  The rest of the buffer is the call's scratch. */
+fgs_status fgs_adam_step_device(const fgs_adam_group* groups, int32_t n_groups, void* d_state, double beta1,
+                                double beta2, double eps, void* stream);
+
 /* L1 loss term of Sec. 2.1 / App. A: dl_dimage[i] = sign(image[i] - target[i]) / n
  * (sign(0) = 0) for i < n; when loss (device double, nullable) is given, it
  * receives mean |image - target| reduced in float64. */
@@ -301,6 +323,43 @@ fgs_status fgs_zorder_permutation(const float* means, int64_t n, void* workspace
  * optimizer moments alike).  src and dst must not overlap. */
 fgs_status fgs_permute_planes(const void* src, void* dst, int64_t n, int32_t planes, int32_t elem_bytes,
                               const uint32_t* perm, void* stream);
+
+/* Batched views (several cameras, or timesteps of a dynamic scene, rendered
+ * and differentiated in one pass; the paper renders image batches per
+ * iteration for its 4D extension, Sec. 3.4).  Up to FGS_MAX_VIEWS cameras
+ * cams[0..n_views) (host array); times[v] (host, nullable = all 0) is the time
+ * of view v for dynamic Gaussians.  Every (view, Gaussian) pair is
+ * preprocessed; all pairs share one depth sort, instances are keyed by a
+ * global tile id (the tiles of view 0, then view 1, ...) and one stable tile
+ * sort, and one launch blends every tile of every view.  images: the views'
+ * [3][H_v][W_v] blocks one after another; t_finals (nullable) and lasts the
+ * views' [H_v][W_v] planes one after another.  The per-view results equal
+ * those of single-view calls; the backward sums each Gaussian's gradient
+ * over the views (and, for dynamic Gaussians, writes dL/dvelocity =
+ * sum_v t_v dL/dmean_v and dL/daccel = sum_v t_v^2 dL/dmean_v).
+ * mode FGS_FORWARD_NO_SYNC: the forward call never synchronises the stream,
+ * so the whole step can be captured into a graph; every launch is sized by
+ * the capacities and reads the counts from the workspace counters, *stats is
+ * not filled (n_visible = n_instances = -1), and an instance count above the
+ * capacity sets counters[7] (the image is then incomplete: grow the
+ * capacity, re-capture and run again).  Without it the call behaves like
+ * fgs_rasterize_forward (one synchronisation, FGS_ERR_CAPACITY). */
+#define FGS_MAX_VIEWS 16
+#define FGS_FORWARD_NO_SYNC 1u
+fgs_status fgs_batch_workspace_size(int64_t n, const fgs_camera* cams, int32_t n_views, const fgs_settings* st,
+                                    int64_t instance_capacity, size_t* bytes);
+fgs_status fgs_batch_workspace_layout(int64_t n, const fgs_camera* cams, int32_t n_views, const fgs_settings* st,
+                                      int64_t instance_capacity, fgs_layout* out);
+fgs_status fgs_rasterize_forward_batch(const fgs_gaussians* g, const fgs_camera* cams, const float* times,
+                                       int32_t n_views, const fgs_settings* st, void* workspace,
+                                       size_t workspace_bytes, int64_t instance_capacity, float* images,
+                                       float* t_finals, uint32_t* lasts, uint32_t mode, fgs_forward_stats* stats,
+                                       void* stream);
+fgs_status fgs_rasterize_backward_batch(const fgs_gaussians* g, const fgs_camera* cams, const float* times,
+                                        int32_t n_views, const fgs_settings* st, void* workspace,
+                                        size_t workspace_bytes, int64_t instance_capacity, const float* images,
+                                        const uint32_t* lasts, const float* dl_dimages,
+                                        const fgs_gaussian_grads* grads, void* stream);
 
 /* Timing hook for measurement: arms a one-shot timer on the calling thread.
  * The next time this thread's library calls run `step`, start_event is

@@ -14,17 +14,20 @@ c_int32, c_int64, c_uint32, c_float, c_size_t, c_void_p, c_double = (
 
 FGS_OK, FGS_ERR_INVALID_ARGUMENT, FGS_ERR_CAPACITY, FGS_ERR_HIP, FGS_ERR_UNSUPPORTED = range(5)
 FGS_F32, FGS_BF16 = 0, 1
+FGS_MAX_VIEWS = 16
+FGS_FORWARD_NO_SYNC = 1
 
 
 class Gaussians(ctypes.Structure):
     _fields_ = [("n", c_int64), ("means", c_void_p), ("log_scales", c_void_p), ("quats", c_void_p),
                 ("opacity_logits", c_void_p), ("sh_dc", c_void_p), ("sh_rest", c_void_p),
-                ("sh_dtype", c_int32), ("sh_degree", c_int32)]
+                ("sh_dtype", c_int32), ("sh_degree", c_int32), ("velocity", c_void_p), ("accel", c_void_p)]
 
 
 class GaussianGrads(ctypes.Structure):
     _fields_ = [("means", c_void_p), ("log_scales", c_void_p), ("quats", c_void_p),
-                ("opacity_logits", c_void_p), ("sh_dc", c_void_p), ("sh_rest", c_void_p)]
+                ("opacity_logits", c_void_p), ("sh_dc", c_void_p), ("sh_rest", c_void_p),
+                ("velocity", c_void_p), ("accel", c_void_p)]
 
 
 class Camera(ctypes.Structure):
@@ -49,7 +52,7 @@ class Layout(ctypes.Structure):
                 ("ranges", c_size_t), ("accum", c_size_t), ("touched", c_size_t), ("scratch", c_size_t),
                 ("total", c_size_t),
                 ("inst_final", c_int32), ("reserved", c_int32), ("tiles_x", c_int32), ("tiles_y", c_int32),
-                ("instance_capacity", c_int64)]
+                ("instance_capacity", c_int64), ("n_views", c_int64), ("total_tiles", c_int64)]
 
 
 class AdamGroup(ctypes.Structure):
@@ -81,8 +84,22 @@ SIGNATURES = {
                                               ctypes.POINTER(Settings), c_void_p, c_size_t, c_int64, c_void_p,
                                               c_void_p, c_void_p, ctypes.POINTER(AdamMoments), c_int64, c_double,
                                               c_double, c_double, c_void_p]),
+    "fgs_batch_workspace_size": (c_int32, [c_int64, ctypes.POINTER(Camera), c_int32, ctypes.POINTER(Settings),
+                                           c_int64, ctypes.POINTER(c_size_t)]),
+    "fgs_batch_workspace_layout": (c_int32, [c_int64, ctypes.POINTER(Camera), c_int32, ctypes.POINTER(Settings),
+                                             c_int64, ctypes.POINTER(Layout)]),
+    "fgs_rasterize_forward_batch": (c_int32, [ctypes.POINTER(Gaussians), ctypes.POINTER(Camera),
+                                              ctypes.POINTER(c_float), c_int32, ctypes.POINTER(Settings), c_void_p,
+                                              c_size_t, c_int64, c_void_p, c_void_p, c_void_p, c_uint32,
+                                              ctypes.POINTER(ForwardStats), c_void_p]),
+    "fgs_rasterize_backward_batch": (c_int32, [ctypes.POINTER(Gaussians), ctypes.POINTER(Camera),
+                                               ctypes.POINTER(c_float), c_int32, ctypes.POINTER(Settings), c_void_p,
+                                               c_size_t, c_int64, c_void_p, c_void_p, c_void_p,
+                                               ctypes.POINTER(GaussianGrads), c_void_p]),
     "fgs_adam_step": (c_int32, [ctypes.POINTER(AdamGroup), c_int32, c_int64, c_double, c_double, c_double,
                                 c_void_p]),
+    "fgs_adam_step_device": (c_int32, [ctypes.POINTER(AdamGroup), c_int32, c_void_p, c_double, c_double, c_double,
+                                       c_void_p]),
     "fgs_l1_loss_backward": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
     "fgs_time_next_launch": (c_int32, [ctypes.c_char_p, c_void_p, c_void_p]),
     "fgs_zorder_workspace_size": (c_int32, [c_int64, ctypes.POINTER(c_size_t)]),

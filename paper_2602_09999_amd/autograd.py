@@ -49,11 +49,16 @@ class FusedAdam:
     into the backward pass (no gradient tensors)."""
 
     def __init__(self, params: Dict[str, torch.Tensor], lrs: Dict[str, float], betas=(0.9, 0.999),
-                 eps: float = 1e-15):
+                 eps: float = 1e-15, device_step: bool = False):
         self.params = params
         self.lrs = dict(lrs)
         self.betas = betas
         self.eps = eps
+        # device_step: the step counter lives on the device (fgs_adam_step_device),
+        # so a step captured into a graph advances it on every replay
+        self.device_step = device_step
+        dev = next(iter(params.values())).device
+        self.state = torch.zeros(32, dtype=torch.int64, device=dev) if device_step else None
         # float32 moments also for bfloat16 parameters
         self.exp_avg = {k: torch.zeros_like(v, dtype=torch.float32) for k, v in params.items()}
         self.exp_avg_sq = {k: torch.zeros_like(v, dtype=torch.float32) for k, v in params.items()}
@@ -63,7 +68,10 @@ class FusedAdam:
         self.t += 1
         groups = [(self.params[k], grads[k], self.exp_avg[k], self.exp_avg_sq[k], self.lrs[k])
                   for k in self.params if k in self.lrs]
-        B.adam_step(groups, self.t, self.betas[0], self.betas[1], self.eps, stream=stream)
+        if self.device_step:
+            B.adam_step_device(groups, self.state, self.betas[0], self.betas[1], self.eps, stream=stream)
+        else:
+            B.adam_step(groups, self.t, self.betas[0], self.betas[1], self.eps, stream=stream)
 
     def state_dict(self) -> Dict[str, object]:
         return {"t": self.t, "exp_avg": self.exp_avg, "exp_avg_sq": self.exp_avg_sq, "lrs": self.lrs}

@@ -96,7 +96,107 @@ def gaussians_struct(params: Dict[str, torch.Tensor], sh_degree: int = 3) -> L.G
     g.opacity_logits, g.sh_dc, g.sh_rest = (_ptr(params[k]) for k in ("opacity_logits", "sh_dc", "sh_rest"))
     g.sh_dtype = L.FGS_BF16 if shd == torch.bfloat16 else L.FGS_F32
     g.sh_degree = int(sh_degree)
+    if "velocity" in params or "accel" in params:
+        for name in ("velocity", "accel"):
+            _check_tensor(params[name], name, shape=(3, n))
+        g.velocity, g.accel = _ptr(params["velocity"]), _ptr(params["accel"])
     return g
+
+
+DYNAMIC_NAMES = ("velocity", "accel")
+
+
+def _camera_array(cameras: Sequence) -> "ctypes.Array":
+    arr = (L.Camera * len(cameras))()
+    for k, c in enumerate(cameras):
+        arr[k] = make_camera(c)
+    return arr
+
+
+def _times_array(times: Optional[Sequence[float]], n_views: int):
+    if times is None:
+        return None
+    if len(times) != n_views:
+        raise ValueError(f"{len(times)} times for {n_views} views")
+    return (ctypes.c_float * n_views)(*[float(t) for t in times])
+
+
+def batch_workspace_size(n: int, cameras: Sequence, settings: Optional[L.Settings] = None,
+                         instance_capacity: int = 0) -> int:
+    st = settings or default_settings()
+    out = ctypes.c_size_t()
+    L.check(L.load().fgs_batch_workspace_size(int(n), _camera_array(cameras), len(cameras), ctypes.byref(st),
+                                              int(instance_capacity), ctypes.byref(out)), "fgs_batch_workspace_size")
+    return int(out.value)
+
+
+def batch_workspace_layout(n: int, cameras: Sequence, settings: Optional[L.Settings] = None,
+                           instance_capacity: int = 0) -> L.Layout:
+    st = settings or default_settings()
+    out = L.Layout()
+    L.check(L.load().fgs_batch_workspace_layout(int(n), _camera_array(cameras), len(cameras), ctypes.byref(st),
+                                                int(instance_capacity), ctypes.byref(out)),
+            "fgs_batch_workspace_layout")
+    return out
+
+
+def view_pixels(cameras: Sequence) -> Tuple[int, ...]:
+    return tuple(int(c.width) * int(c.height) for c in cameras)
+
+
+def rasterize_forward_batch(params: Dict[str, torch.Tensor], cameras: Sequence, times: Optional[Sequence[float]],
+                            settings: Optional[L.Settings], workspace: torch.Tensor, instance_capacity: int,
+                            images: torch.Tensor, t_finals: Optional[torch.Tensor], lasts: torch.Tensor, *,
+                            mode: int = 0, sh_degree: int = 3, stream=None,
+                            raise_on_capacity: bool = True) -> Dict[str, int]:
+    """fgs_rasterize_forward_batch.  images: float32 [3 * sum(H_v W_v)] (the
+    views' [3][H][W] blocks one after another); t_finals float32 and lasts int32
+    [sum(H_v W_v)].  mode=FGS_FORWARD_NO_SYNC never synchronises (graph capture)."""
+    st = settings or default_settings()
+    g = gaussians_struct(params, sh_degree)
+    npix = sum(view_pixels(cameras))
+    _check_tensor(images, "images", shape=(3 * npix,))
+    _check_tensor(lasts, "lasts", dtype=torch.int32, shape=(npix,))
+    if t_finals is not None:
+        _check_tensor(t_finals, "t_finals", shape=(npix,))
+    _check_tensor(workspace, "workspace", dtype=torch.uint8)
+    stats = L.ForwardStats()
+    status = L.load().fgs_rasterize_forward_batch(
+        ctypes.byref(g), _camera_array(cameras), _times_array(times, len(cameras)), len(cameras), ctypes.byref(st),
+        _ptr(workspace), workspace.numel(), int(instance_capacity), _ptr(images), _ptr(t_finals), _ptr(lasts),
+        int(mode), ctypes.byref(stats), _stream_handle(stream))
+    out = {"status": int(status), "n_visible": int(stats.n_visible), "n_instances": int(stats.n_instances)}
+    if status == L.FGS_ERR_CAPACITY and not raise_on_capacity:
+        return out
+    L.check(status, "fgs_rasterize_forward_batch")
+    return out
+
+
+def rasterize_backward_batch(params: Dict[str, torch.Tensor], cameras: Sequence, times: Optional[Sequence[float]],
+                             settings: Optional[L.Settings], workspace: torch.Tensor, instance_capacity: int,
+                             images: torch.Tensor, lasts: torch.Tensor, dl_dimages: torch.Tensor,
+                             grads: Dict[str, torch.Tensor], *, sh_degree: int = 3, stream=None) -> None:
+    """fgs_rasterize_backward_batch: gradients summed over the views (plus
+    velocity / accel gradients for dynamic Gaussians)."""
+    st = settings or default_settings()
+    g = gaussians_struct(params, sh_degree)
+    n = g.n
+    npix = sum(view_pixels(cameras))
+    _check_tensor(images, "images", shape=(3 * npix,))
+    _check_tensor(dl_dimages, "dl_dimages", shape=(3 * npix,))
+    _check_tensor(lasts, "lasts", dtype=torch.int32, shape=(npix,))
+    shd = sh_dtype_of(params)
+    gr = L.GaussianGrads()
+    names = PARAM_NAMES + (DYNAMIC_NAMES if "velocity" in params else ())
+    for name in names:
+        rows = PARAM_SHAPES.get(name, 3)
+        _check_tensor(grads[name], f"grads[{name}]", dtype=param_dtype(name, shd),
+                      shape=(n,) if rows == 0 else (rows, n))
+        setattr(gr, name, _ptr(grads[name]))
+    L.check(L.load().fgs_rasterize_backward_batch(
+        ctypes.byref(g), _camera_array(cameras), _times_array(times, len(cameras)), len(cameras), ctypes.byref(st),
+        _ptr(workspace), workspace.numel(), int(instance_capacity), _ptr(images), _ptr(lasts), _ptr(dl_dimages),
+        ctypes.byref(gr), _stream_handle(stream)), "fgs_rasterize_backward_batch")
 
 
 def workspace_size(n: int, camera, settings: Optional[L.Settings] = None, instance_capacity: int = 0) -> int:
@@ -220,6 +320,29 @@ def adam_step(groups: Sequence[Tuple[torch.Tensor, torch.Tensor, torch.Tensor, t
         arr[k].dtype = L.FGS_BF16 if p.dtype == torch.bfloat16 else L.FGS_F32
     L.check(L.load().fgs_adam_step(arr, len(groups), int(step), float(beta1), float(beta2), float(eps),
                                    _stream_handle(stream)), "fgs_adam_step")
+
+
+def adam_step_device(groups: Sequence[Tuple[torch.Tensor, torch.Tensor, torch.Tensor, torch.Tensor, float]],
+                     state: torch.Tensor, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15, *,
+                     stream=None) -> None:
+    """fgs_adam_step_device: like adam_step with the step counter kept on the
+    device in ``state`` (>= 256 bytes, its first int64 the counter t, zeroed
+    before the first step), so a captured graph advances t on every replay."""
+    _check_tensor(state, "state", dtype=state.dtype)
+    if state.numel() * state.element_size() < 256:
+        raise ValueError("state must hold at least 256 bytes")
+    arr = (L.AdamGroup * len(groups))()
+    for k, (p, g, m, v, lr) in enumerate(groups):
+        _check_tensor(p, "param", dtype=p.dtype)
+        _check_tensor(g, "grad", dtype=p.dtype, shape=p.shape)
+        for t, nm in ((m, "exp_avg"), (v, "exp_avg_sq")):
+            _check_tensor(t, nm, shape=p.shape)
+        arr[k].param, arr[k].grad, arr[k].exp_avg, arr[k].exp_avg_sq = _ptr(p), _ptr(g), _ptr(m), _ptr(v)
+        arr[k].numel = p.numel()
+        arr[k].lr = float(lr)
+        arr[k].dtype = L.FGS_BF16 if p.dtype == torch.bfloat16 else L.FGS_F32
+    L.check(L.load().fgs_adam_step_device(arr, len(groups), _ptr(state), float(beta1), float(beta2), float(eps),
+                                          _stream_handle(stream)), "fgs_adam_step_device")
 
 
 def l1_loss_backward(image: torch.Tensor, target: torch.Tensor, dl_dimage: torch.Tensor,
@@ -371,6 +494,86 @@ class Rasterizer:
             off = off[index]
         itemsize = torch.empty(0, dtype=dtype).element_size()
         return self.workspace[off:off + count * itemsize].view(dtype)
+
+
+class BatchRasterizer:
+    """Several views (or timesteps) per call: owns the workspace and the
+    concatenated outputs.  forward() returns per-view (image [3,H,W], t_final,
+    last) views of those buffers; backward() the gradients summed over views."""
+
+    def __init__(self, cameras: Sequence, settings: Optional[L.Settings] = None,
+                 times: Optional[Sequence[float]] = None, sh_degree: int = 3,
+                 device: Optional[torch.device] = None, headroom: float = 1.25):
+        if not 1 <= len(cameras) <= L.FGS_MAX_VIEWS:
+            raise ValueError(f"1..{L.FGS_MAX_VIEWS} views")
+        self.cameras = list(cameras)
+        self.times = None if times is None else [float(t) for t in times]
+        self.settings = settings or default_settings()
+        self.sh_degree = sh_degree
+        self.device = device or torch.device("cuda", torch.cuda.current_device())
+        self.headroom = headroom
+        self.capacity = 0
+        self.n = -1
+        self.workspace: Optional[torch.Tensor] = None
+        self.last_stats: Dict[str, int] = {}
+        npix = sum(view_pixels(self.cameras))
+        self.images = torch.empty(3 * npix, dtype=torch.float32, device=self.device)
+        self.t_finals = torch.empty(npix, dtype=torch.float32, device=self.device)
+        self.lasts = torch.empty(npix, dtype=torch.int32, device=self.device)
+
+    def ensure(self, n: int, capacity: int) -> None:
+        if self.workspace is not None and n == self.n and capacity <= self.capacity:
+            return
+        capacity = max(capacity, self.capacity if n == self.n else 0)
+        size = batch_workspace_size(n, self.cameras, self.settings, capacity)
+        self.workspace = torch.empty(size, dtype=torch.uint8, device=self.device)
+        self.capacity, self.n = capacity, n
+
+    def layout(self) -> L.Layout:
+        return batch_workspace_layout(self.n, self.cameras, self.settings, self.capacity)
+
+    def split(self, flat: torch.Tensor, channels: int):
+        out, off = [], 0
+        for c in self.cameras:
+            hw = int(c.width) * int(c.height)
+            out.append(flat[off * channels:(off + hw) * channels].view(channels, int(c.height), int(c.width))
+                       if channels > 1 else flat[off:off + hw].view(int(c.height), int(c.width)))
+            off += hw
+        return out
+
+    def forward(self, params: Dict[str, torch.Tensor], *, mode: int = 0, stream=None):
+        n = int(params["opacity_logits"].shape[0])
+        self.ensure(n, max(self.capacity, 1024) if n == self.n else max(1024, 16 * n * len(self.cameras)))
+        for _ in range(3):
+            st = rasterize_forward_batch(params, self.cameras, self.times, self.settings, self.workspace,
+                                         self.capacity, self.images, self.t_finals, self.lasts, mode=mode,
+                                         sh_degree=self.sh_degree, stream=stream, raise_on_capacity=False)
+            if st["status"] == L.FGS_OK:
+                self.last_stats = st
+                return self.images, self.t_finals, self.lasts
+            self.ensure(n, int(st["n_instances"] * self.headroom) + 1024)
+        raise RuntimeError("instance capacity could not be satisfied")
+
+    def view(self, field: str, count: int, dtype=torch.int32, index: Optional[int] = None) -> torch.Tensor:
+        lay = self.layout()
+        off = getattr(lay, field)
+        if index is not None:
+            off = off[index]
+        itemsize = torch.empty(0, dtype=dtype).element_size()
+        return self.workspace[off:off + count * itemsize].view(dtype)
+
+    def counters(self) -> torch.Tensor:
+        """The workspace counter words (device): [0] visible, [4..5] I, [7] overflow."""
+        return self.workspace[self.layout().counters:self.layout().counters + 64].view(torch.int32)
+
+    def backward(self, params: Dict[str, torch.Tensor], dl_dimages: torch.Tensor,
+                 grads: Optional[Dict[str, torch.Tensor]] = None, stream=None):
+        if grads is None:
+            grads = {k: torch.empty_like(v) for k, v in params.items()}
+        rasterize_backward_batch(params, self.cameras, self.times, self.settings, self.workspace, self.capacity,
+                                 self.images, self.lasts, dl_dimages.contiguous(), grads, sh_degree=self.sh_degree,
+                                 stream=stream)
+        return grads
 
 
 def exported_symbols() -> Iterable[str]:

@@ -27,11 +27,41 @@ struct AdamGroupDev {
   int32_t bf16;
 };
 
+// Optimizer state on the device, for steps whose count must advance inside a
+// replayed graph: the step counter t and the scalars of step t.
+struct AdamDevState {
+  int64_t step;
+  AdamCoef c;
+  float step_size[kMaxGroups];  // lr_g / (1 - b1^t)
+};
+static_assert(sizeof(AdamDevState) <= 256, "state fits the caller's 256 bytes");
+
 struct AdamArgs {
   AdamGroupDev grp[kMaxGroups];
   int32_t n_groups;
   AdamCoef c;
+  const AdamDevState* dev;  // non-NULL: take c and the step sizes from here
 };
+
+struct LrList {
+  float lr[kMaxGroups];
+};
+
+// One thread: t <- t + 1, then the scalars of step t in double, rounded once.
+__global__ void k_adam_scalars(AdamDevState* __restrict__ st, double beta1, double beta2, double eps, LrList lrs,
+                               int32_t n_groups) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t t = st->step + 1;
+  st->step = t;
+  const double bc1 = 1.0 - pow(beta1, (double)t);
+  const double bc2 = 1.0 - pow(beta2, (double)t);
+  st->c.one_minus_b1 = (float)(1.0 - beta1);
+  st->c.beta2 = (float)beta2;
+  st->c.one_minus_b2 = (float)(1.0 - beta2);
+  st->c.inv_sqrt_bc2 = (float)(1.0 / sqrt(bc2));
+  st->c.eps = (float)eps;
+  for (int k = 0; k < n_groups; ++k) st->step_size[k] = (float)((double)lrs.lr[k] / bc1);
+}
 
 AdamCoef adam_coef(int64_t step, double beta1, double beta2, double eps, double* bias1) {
   const double bc1 = 1.0 - std::pow(beta1, (double)step);
@@ -91,6 +121,8 @@ __device__ __forceinline__ void adam4(float4& p, const float4& g, float4& m, flo
 // bfloat16 parameters are widened, updated in float32 against float32
 // moments and rounded back to nearest-even.
 __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a, uint64_t total_vec) {
+  // the scalars of this step: from the arguments, or from the device state
+  const AdamCoef c = a.dev ? a.dev->c : a.c;
   const uint64_t base = (uint64_t)blockIdx.x * (kBlock * kAdamSlots) + threadIdx.x;
   float4 p[kAdamSlots], g[kAdamSlots], m[kAdamSlots], v[kAdamSlots];
   int gi[kAdamSlots];
@@ -124,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a, uint64_t total_vec)
     const AdamGroupDev& G = a.grp[gi[u]];
     const uint64_t e0 = (slot - G.vec_begin) * 4;
     if (vec[u]) {
-      adam4(p[u], g[u], m[u], v[u], a.c, G.step_size);
+      adam4(p[u], g[u], m[u], v[u], c, a.dev ? a.dev->step_size[gi[u]] : G.step_size);
       if (G.bf16) store_bf16x4(static_cast<uint16_t*>(G.p) + e0, p[u]);
       else *reinterpret_cast<float4*>(static_cast<float*>(G.p) + e0) = p[u];
       *reinterpret_cast<float4*>(G.m + e0) = m[u];
@@ -132,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a, uint64_t total_vec)
     } else if (G.bf16) {
       for (uint64_t e = e0; e < e0 + 4 && e < G.numel; ++e) {
         float pe = sh_load<true>(G.p, e), me = G.m[e], ve = G.v[e];
-        adam_elem(pe, sh_load<true>(G.g, e), me, ve, a.c, G.step_size);
+        adam_elem(pe, sh_load<true>(G.g, e), me, ve, c, a.dev ? a.dev->step_size[gi[u]] : G.step_size);
         sh_store<true>(G.p, e, pe);
         G.m[e] = me;
         G.v[e] = ve;
@@ -140,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a, uint64_t total_vec)
     } else {
       for (uint64_t e = e0; e < e0 + 4 && e < G.numel; ++e) {
         float pe = sh_load<false>(G.p, e), me = G.m[e], ve = G.v[e];
-        adam_elem(pe, sh_load<false>(G.g, e), me, ve, a.c, G.step_size);
+        adam_elem(pe, sh_load<false>(G.g, e), me, ve, c, a.dev ? a.dev->step_size[gi[u]] : G.step_size);
         sh_store<false>(G.p, e, pe);
         G.m[e] = me;
         G.v[e] = ve;
@@ -149,12 +181,16 @@ __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a, uint64_t total_vec)
   }
 }
 
+// step >= 1: host step count; step == 0: advance and use the device counter
+// of dev_state (an AdamDevState).
 hipError_t launch_adam(const fgs_adam_group* groups, int n_groups, int64_t step, double beta1, double beta2,
-                       double eps, hipStream_t s) {
+                       double eps, void* dev_state, hipStream_t s) {
   AdamArgs a = {};
   a.n_groups = n_groups;
   double bc1 = 1.0;
-  a.c = adam_coef(step, beta1, beta2, eps, &bc1);
+  a.c = adam_coef(step > 0 ? step : 1, beta1, beta2, eps, &bc1);
+  a.dev = step > 0 ? nullptr : static_cast<const AdamDevState*>(dev_state);
+  LrList lrs = {};
   uint64_t vec = 0;
   for (int k = 0; k < n_groups; ++k) {
     AdamGroupDev& G = a.grp[k];
@@ -165,10 +201,16 @@ hipError_t launch_adam(const fgs_adam_group* groups, int n_groups, int64_t step,
     G.numel = (uint64_t)groups[k].numel;
     G.vec_begin = vec;
     G.step_size = (float)((double)groups[k].lr / bc1);
+    lrs.lr[k] = groups[k].lr;
     G.bf16 = groups[k].dtype == FGS_BF16 ? 1 : 0;
     const uintptr_t pg = (uintptr_t)G.p | (uintptr_t)G.g, mv = (uintptr_t)G.m | (uintptr_t)G.v;
     G.vec4 = ((pg & (G.bf16 ? 7u : 15u)) == 0 && (mv & 15u) == 0) ? 1 : 0;
     vec += (G.numel + 3) / 4;
+  }
+  if (a.dev) {
+    k_adam_scalars<<<1, kWave, 0, s>>>(static_cast<AdamDevState*>(dev_state), beta1, beta2, eps, lrs, n_groups);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
   if (vec == 0) return hipSuccess;
   const uint64_t per_block = (uint64_t)kBlock * kAdamSlots;

@@ -19,8 +19,25 @@
 
 namespace fgs {
 
-constexpr int kTile = 16;
-constexpr int kRows = 4;  // pixels per lane
+// A tile of TILE x TILE pixels is one wave64: lane l owns column l % TILE
+// and rows l / TILE + (64 / TILE) r, for TILE * TILE / 64 values of r
+// (1 pixel per lane at 8x8, 4 at 16x16, 16 at 32x32).
+template <int TILE>
+struct TileShape {
+  static_assert(TILE == 8 || TILE == 16 || TILE == 32, "tile size");
+  static constexpr int kRows = TILE * TILE / kWave;  // pixels per lane
+  static constexpr int kStep = kWave / TILE;         // rows between a lane's pixels
+};
+
+// The view of a block's global tile and that view's tile, camera and outputs.
+struct TileView {
+  uint32_t view, tile;
+  uint64_t pix0;  // first pixel of the view in the concatenated images
+};
+__device__ __forceinline__ TileView tile_view(const ViewSet& vs, uint32_t gt) {
+  const uint32_t v = view_of_tile(vs, gt);
+  return TileView{v, gt - vs.tile_base[v], vs.pix_base[v]};
+}
 
 // A batch of up to 64 consecutive list entries: lane i holds entry base + i.
 struct Batch {
@@ -73,28 +90,38 @@ __device__ __forceinline__ float pixel_alpha(const Splat& s, float ax, float bx,
   return fminf(alpha_max, s.o * G);
 }
 
+// Grid: one wave per global tile of all views.  images: the views' [3][H][W]
+// blocks one after another; t_finals and lasts likewise with one plane.
+template <int TILE>
 __global__ __launch_bounds__(kWave) void k_blend_fwd(const uint2* __restrict__ ranges,
                                                      const uint32_t* __restrict__ vals,
-                                                     const float4* __restrict__ rec, CamDev cam, SetDev st,
-                                                     float* __restrict__ image, float* __restrict__ t_final,
-                                                     uint32_t* __restrict__ last) {
-  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+                                                     const float4* __restrict__ rec, ViewSet vs, SetDev st,
+                                                     float* __restrict__ images, float* __restrict__ t_finals,
+                                                     uint32_t* __restrict__ lasts) {
+  constexpr int kRows = TileShape<TILE>::kRows, kStep = TileShape<TILE>::kStep;
+  const uint32_t gt = xcd_tile(blockIdx.x, gridDim.x);
+  const TileView tv = tile_view(vs, gt);
+  const CamDev& cam = vs.cam[tv.view];
+  float* __restrict__ image = images + 3 * tv.pix0;
+  float* __restrict__ t_final = t_finals ? t_finals + tv.pix0 : nullptr;
+  uint32_t* __restrict__ last = lasts + tv.pix0;
+  const uint32_t tile = tv.tile;
   const int tx = (int)(tile % (uint32_t)cam.tiles_x), ty = (int)(tile / (uint32_t)cam.tiles_x);
   const int lane = threadIdx.x;
-  const int px = tx * kTile + (lane % kTile);
+  const int px = tx * TILE + (lane % TILE);
   const float fx = (float)px + 0.5f;
   float fy[kRows], T[kRows], C0[kRows], C1[kRows], C2[kRows];
   uint32_t lpos[kRows];
   bool live[kRows];
 #pragma unroll
   for (int r = 0; r < kRows; ++r) {
-    const int py = ty * kTile + lane / kTile + 4 * r;
+    const int py = ty * TILE + lane / TILE + kStep * r;
     fy[r] = (float)py + 0.5f;
     T[r] = 1.0f; C0[r] = C1[r] = C2[r] = 0.0f;
     lpos[r] = 0;
     live[r] = px < cam.width && py < cam.height;
   }
-  const uint2 range = ranges[tile];
+  const uint2 range = ranges[gt];
   const uint32_t beg = __builtin_amdgcn_readfirstlane(range.x);
   const uint32_t end = __builtin_amdgcn_readfirstlane(range.y);
   Batch cur = {}, nxt = {};
@@ -134,7 +161,7 @@ __global__ __launch_bounds__(kWave) void k_blend_fwd(const uint2* __restrict__ r
   const size_t hw = (size_t)cam.width * cam.height;
 #pragma unroll
   for (int r = 0; r < kRows; ++r) {
-    const int py = ty * kTile + lane / kTile + 4 * r;
+    const int py = ty * TILE + lane / TILE + kStep * r;
     if (px < cam.width && py < cam.height) {
       const size_t pix = (size_t)py * cam.width + px;
       image[pix] = fmaf(T[r], cam.bg[0], C0[r]);
@@ -146,11 +173,17 @@ __global__ __launch_bounds__(kWave) void k_blend_fwd(const uint2* __restrict__ r
   }
 }
 
-hipError_t launch_blend_forward(const uint2* ranges, const uint32_t* vals, const float4* rec, const CamDev& cam,
-                                const SetDev& st, float* image, float* t_final, uint32_t* last, hipStream_t s) {
-  const uint32_t tiles = (uint32_t)cam.tiles_x * (uint32_t)cam.tiles_y;
+hipError_t launch_blend_forward(const uint2* ranges, const uint32_t* vals, const float4* rec, const ViewSet& vs,
+                                const SetDev& st, int tile, float* images, float* t_finals, uint32_t* lasts,
+                                hipStream_t s) {
+  const uint32_t tiles = vs.tile_base[vs.n_views];
   if (tiles == 0) return hipSuccess;
-  k_blend_fwd<<<tiles, kWave, 0, s>>>(ranges, vals, rec, cam, st, image, t_final, last);
+  if (tile == 8)
+    k_blend_fwd<8><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, t_finals, lasts);
+  else if (tile == 32)
+    k_blend_fwd<32><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, t_finals, lasts);
+  else
+    k_blend_fwd<16><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, t_finals, lasts);
   return hipGetLastError();
 }
 
@@ -214,17 +247,26 @@ __device__ __forceinline__ float wave_reduce1(float x) {
 
 constexpr int kGrad = 9;  // dL/d(mu2D.x, mu2D.y, a, b, c, opacity, r, g, b)
 
+// accum: [9][n] with n the (view, Gaussian) index range of the record.
+template <int TILE>
 __global__ __launch_bounds__(kWave) void k_blend_bwd(const uint2* __restrict__ ranges,
                                                      const uint32_t* __restrict__ vals,
-                                                     const float4* __restrict__ rec, CamDev cam, SetDev st,
-                                                     const float* __restrict__ image,
-                                                     const uint32_t* __restrict__ last,
-                                                     const float* __restrict__ dl_dimage,
+                                                     const float4* __restrict__ rec, ViewSet vs, SetDev st,
+                                                     const float* __restrict__ images,
+                                                     const uint32_t* __restrict__ lasts,
+                                                     const float* __restrict__ dl_dimages,
                                                      float* __restrict__ accum, uint32_t n) {
-  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  constexpr int kRows = TileShape<TILE>::kRows, kStep = TileShape<TILE>::kStep;
+  const uint32_t gt = xcd_tile(blockIdx.x, gridDim.x);
+  const TileView tv = tile_view(vs, gt);
+  const CamDev& cam = vs.cam[tv.view];
+  const float* __restrict__ image = images + 3 * tv.pix0;
+  const float* __restrict__ dl_dimage = dl_dimages + 3 * tv.pix0;
+  const uint32_t* __restrict__ last = lasts + tv.pix0;
+  const uint32_t tile = tv.tile;
   const int tx = (int)(tile % (uint32_t)cam.tiles_x), ty = (int)(tile / (uint32_t)cam.tiles_x);
   const int lane = threadIdx.x;
-  const int px = tx * kTile + (lane % kTile);
+  const int px = tx * TILE + (lane % TILE);
   const float fx = (float)px + 0.5f;
   const size_t hw = (size_t)cam.width * cam.height;
   float fy[kRows], gc0[kRows], gc1[kRows], gc2[kRows], gF[kRows];
@@ -233,7 +275,7 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const uint2* __restrict__ r
   uint32_t walk = 0;
 #pragma unroll
   for (int r = 0; r < kRows; ++r) {
-    const int py = ty * kTile + lane / kTile + 4 * r;
+    const int py = ty * TILE + lane / TILE + kStep * r;
     fy[r] = (float)py + 0.5f;
     T[r] = 1.0f;
     gS[r] = 0.0f;  // g . S_i, the upstream gradient dotted with the colour blended so far
@@ -251,8 +293,8 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const uint2* __restrict__ r
   // longest walk of the tile (wave max)
 #pragma unroll
   for (int d = 1; d < kWave; d <<= 1) walk = max(walk, (uint32_t)__shfl_xor((int)walk, d, kWave));
-  const uint32_t beg = __builtin_amdgcn_readfirstlane(ranges[tile].x);
-  const uint32_t lim = __builtin_amdgcn_readfirstlane(ranges[tile].y);
+  const uint32_t beg = __builtin_amdgcn_readfirstlane(ranges[gt].x);
+  const uint32_t lim = __builtin_amdgcn_readfirstlane(ranges[gt].y);
   const uint32_t end = min(beg + __builtin_amdgcn_readfirstlane(walk), lim);
   // lanes that publish the wave sums: l % 8 >= 4 of the first row hold value 4*b0 + 2*b1 + b3
   const bool writer = lane < 16 && (lane & 4);
@@ -320,12 +362,17 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const uint2* __restrict__ r
   }
 }
 
-hipError_t launch_blend_backward(const uint2* ranges, const uint32_t* vals, const float4* rec, const CamDev& cam,
-                                 const SetDev& st, const float* image, const uint32_t* last, const float* dl_dimage,
-                                 float* accum, uint32_t n, hipStream_t s) {
-  const uint32_t tiles = (uint32_t)cam.tiles_x * (uint32_t)cam.tiles_y;
+hipError_t launch_blend_backward(const uint2* ranges, const uint32_t* vals, const float4* rec, const ViewSet& vs,
+                                 const SetDev& st, int tile, const float* images, const uint32_t* lasts,
+                                 const float* dl_dimages, float* accum, uint32_t n, hipStream_t s) {
+  const uint32_t tiles = vs.tile_base[vs.n_views];
   if (tiles == 0 || n == 0) return hipSuccess;
-  k_blend_bwd<<<tiles, kWave, 0, s>>>(ranges, vals, rec, cam, st, image, last, dl_dimage, accum, n);
+  if (tile == 8)
+    k_blend_bwd<8><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, n);
+  else if (tile == 32)
+    k_blend_bwd<32><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, n);
+  else
+    k_blend_bwd<16><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, n);
   return hipGetLastError();
 }
 

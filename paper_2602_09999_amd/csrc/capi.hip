@@ -83,8 +83,10 @@ fgs_status check_camera(const fgs_camera* cam) {
     return fail(FGS_ERR_INVALID_ARGUMENT, "image of %dx%d pixels exceeds 2^30 pixels", cam->width, cam->height);
   if (!finite_pos(cam->fx) || !finite_pos(cam->fy))
     return fail(FGS_ERR_INVALID_ARGUMENT, "focal lengths must be finite and positive");
-  if (!std::isfinite(cam->cx) || !std::isfinite(cam->cy) || !std::isfinite(cam->near_z))
-    return fail(FGS_ERR_INVALID_ARGUMENT, "principal point and near plane must be finite");
+  if (!std::isfinite(cam->cx) || !std::isfinite(cam->cy))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "principal point must be finite");
+  // z > 0 for every rendered Gaussian makes the float bits of z an ordered key
+  if (!finite_pos(cam->near_z)) return fail(FGS_ERR_INVALID_ARGUMENT, "near plane must be finite and > 0");
   for (int k = 0; k < 12; ++k)
     if (!std::isfinite(cam->world_to_cam[k]))
       return fail(FGS_ERR_INVALID_ARGUMENT, "world_to_cam[%d] is not finite", k);
@@ -97,7 +99,6 @@ fgs_status check_settings(const fgs_settings* st) {
   if (!st) return fail(FGS_ERR_INVALID_ARGUMENT, "settings is NULL");
   if (st->tile != 8 && st->tile != 16 && st->tile != 32)
     return fail(FGS_ERR_INVALID_ARGUMENT, "tile must be 8, 16 or 32 (got %d)", st->tile);
-  if (st->tile != 16) return fail(FGS_ERR_UNSUPPORTED, "tile %d is not implemented; use 16", st->tile);
   if (st->flags & ~(uint32_t)FGS_FLAG_FP64_CONIC)
     return fail(FGS_ERR_INVALID_ARGUMENT, "unknown bits in settings.flags 0x%x", st->flags);
   if (!(st->alpha_min > 0.0f && st->alpha_min < st->alpha_max && st->alpha_max <= 1.0f))
@@ -120,20 +121,35 @@ fgs_status check_gaussians(const fgs_gaussians* g) {
   if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh_dc ||
                    (g->sh_degree > 0 && !g->sh_rest)))
     return fail(FGS_ERR_INVALID_ARGUMENT, "a parameter pointer is NULL");
+  if ((g->velocity == nullptr) != (g->accel == nullptr))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "velocity and accel are given together or not at all");
   return FGS_OK;
 }
 
-fgs_status make_layout(int64_t n, const fgs_camera* cam, const fgs_settings* st, int64_t cap, fgs_layout* L) {
+// Workspace of n Gaussians seen from n_views cameras (index j = v n + i for
+// the per-(view, Gaussian) regions) with room for `cap` instances.
+fgs_status make_layout(int64_t n, const fgs_camera* cams, int32_t n_views, const fgs_settings* st, int64_t cap,
+                       fgs_layout* L) {
   if (n < 0 || n > INT32_MAX) return fail(FGS_ERR_INVALID_ARGUMENT, "n = %lld out of range", (long long)n);
   if (cap < 0 || cap > (int64_t)UINT32_MAX - 1)
     return fail(FGS_ERR_INVALID_ARGUMENT, "instance_capacity = %lld out of range", (long long)cap);
-  fgs_status s = check_camera(cam);
-  if (s != FGS_OK) return s;
-  s = check_settings(st);
+  if (n_views < 1 || n_views > kMaxViews)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "n_views = %d not in 1..%d", n_views, kMaxViews);
+  if (!cams) return fail(FGS_ERR_INVALID_ARGUMENT, "cameras are NULL");
+  if ((int64_t)n * n_views > INT32_MAX)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "n * n_views = %lld exceeds 2^31 - 1", (long long)n * n_views);
+  fgs_status s = check_settings(st);
   if (s != FGS_OK) return s;
   const int t = st->tile;
-  const int64_t tx = (cam->width + t - 1) / t, ty = (cam->height + t - 1) / t;
-  if (tx > 65535 || ty > 65535) return fail(FGS_ERR_INVALID_ARGUMENT, "tile grid too large");
+  uint64_t tiles = 0;
+  for (int v = 0; v < n_views; ++v) {
+    s = check_camera(cams + v);
+    if (s != FGS_OK) return s;
+    const int64_t tx = (cams[v].width + t - 1) / t, ty = (cams[v].height + t - 1) / t;
+    if (tx > 65535 || ty > 65535) return fail(FGS_ERR_INVALID_ARGUMENT, "tile grid too large");
+    tiles += (uint64_t)(tx * ty);
+  }
+  if (tiles > (uint64_t(1) << 30)) return fail(FGS_ERR_INVALID_ARGUMENT, "more than 2^30 tiles");
   std::memset(L, 0, sizeof(*L));
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -141,37 +157,39 @@ fgs_status make_layout(int64_t n, const fgs_camera* cam, const fgs_settings* st,
     off += align256(bytes);
     return o;
   };
-  const size_t un = (size_t)n, uc = (size_t)cap, tiles = (size_t)(tx * ty);
-  L->rec = take(un * 64);
-  L->n_tiles = take(un * 4);
-  L->depth_key = take(un * 4);
+  const size_t un = (size_t)n, vn = un * (size_t)n_views, uc = (size_t)cap;
+  L->rec = take(vn * 64);
+  L->n_tiles = take(vn * 4);
+  L->depth_key = take(vn * 4);
   L->counters = take(64);
-  L->vis_keys[0] = take(un * 4);
-  L->vis_keys[1] = take(un * 4);
-  L->vis_ids[0] = take(un * 4);
-  L->vis_ids[1] = take(un * 4);
-  L->inst_offsets = take((un + 1) * 4);
+  L->vis_keys[0] = take(vn * 4);
+  L->vis_keys[1] = take(vn * 4);
+  L->vis_ids[0] = take(vn * 4);
+  L->vis_ids[1] = take(vn * 4);
+  L->inst_offsets = take((vn + 1) * 4);
   L->inst_keys[0] = take(uc * 4);
   L->inst_keys[1] = take(uc * 4);
   L->inst_vals[0] = take(uc * 4);
   L->inst_vals[1] = take(uc * 4);
   L->ranges = take(tiles * 8);
-  L->accum = take(un * 9 * 4);
+  L->accum = take(vn * 9 * 4);
   L->touched = take((un + 3) / 4);
-  size_t words = scan_scratch_words(un);
-  words = std::max(words, radix_scratch_words(un));
+  size_t words = scan_scratch_words(vn);
+  words = std::max(words, radix_scratch_words(vn));
   words = std::max(words, radix_scratch_words(uc));
-  words = std::max(words, 4 * ((un + kBlock - 1) / kBlock));  // preprocess partials
+  words = std::max(words, 4 * (size_t)n_views * ((un + kBlock - 1) / kBlock));  // preprocess partials
   L->scratch = take(words * 4 + 256);
   L->total = off;
-  L->inst_final = ((tile_key_bits((uint64_t)tiles) + kRadixBits - 1) / kRadixBits) & 1;
-  L->tiles_x = (int32_t)tx;
-  L->tiles_y = (int32_t)ty;
+  L->inst_final = ((tile_key_bits(tiles) + kRadixBits - 1) / kRadixBits) & 1;
+  L->tiles_x = (int32_t)((cams[0].width + t - 1) / t);
+  L->tiles_y = (int32_t)((cams[0].height + t - 1) / t);
   L->instance_capacity = cap;
+  L->n_views = n_views;
+  L->total_tiles = (int64_t)tiles;
   return FGS_OK;
 }
 
-CamDev make_cam(const fgs_camera* c, const fgs_layout& L) {
+CamDev make_cam(const fgs_camera* c, int tile) {
   CamDev d;
   for (int k = 0; k < 12; ++k) d.w[k] = c->world_to_cam[k];
   // camera centre -W3^T t, computed in double and rounded once
@@ -182,10 +200,30 @@ CamDev make_cam(const fgs_camera* c, const fgs_layout& L) {
   }
   d.fx = c->fx; d.fy = c->fy; d.cx = c->cx; d.cy = c->cy;
   d.width = c->width; d.height = c->height;
-  d.tiles_x = L.tiles_x; d.tiles_y = L.tiles_y;
+  d.tiles_x = (c->width + tile - 1) / tile;
+  d.tiles_y = (c->height + tile - 1) / tile;
   d.near_z = c->near_z;
   for (int k = 0; k < 3; ++k) d.bg[k] = c->bg[k];
   return d;
+}
+
+ViewSet make_views(const fgs_camera* cams, int32_t n_views, int tile, const float* times) {
+  ViewSet vs;
+  std::memset(&vs, 0, sizeof(vs));
+  vs.n_views = (uint32_t)n_views;
+  uint32_t tb = 0;
+  uint64_t pb = 0;
+  for (int v = 0; v < n_views; ++v) {
+    vs.cam[v] = make_cam(cams + v, tile);
+    vs.time[v] = times ? times[v] : 0.0f;
+    vs.tile_base[v] = tb;
+    vs.pix_base[v] = pb;
+    tb += (uint32_t)(vs.cam[v].tiles_x * vs.cam[v].tiles_y);
+    pb += (uint64_t)cams[v].width * (uint64_t)cams[v].height;
+  }
+  vs.tile_base[n_views] = tb;
+  vs.pix_base[n_views] = pb;
+  return vs;
 }
 
 SetDev make_set(const fgs_settings* s) {
@@ -204,6 +242,8 @@ GaussDev make_gauss(const fgs_gaussians* g) {
   d.n = (uint32_t)g->n;
   d.sh_coeffs = (g->sh_degree + 1) * (g->sh_degree + 1);
   d.sh_bf16 = g->sh_dtype == FGS_BF16 ? 1 : 0;
+  d.velocity = g->velocity;
+  d.accel = g->accel;
   return d;
 }
 
@@ -246,38 +286,66 @@ fgs_status fgs_default_settings(fgs_settings* out) {
 
 fgs_status fgs_workspace_size(int64_t n, const fgs_camera* cam, const fgs_settings* st, int64_t instance_capacity,
                               size_t* bytes) {
+  return fgs_batch_workspace_size(n, cam, 1, st, instance_capacity, bytes);
+}
+
+fgs_status fgs_workspace_layout(int64_t n, const fgs_camera* cam, const fgs_settings* st, int64_t instance_capacity,
+                                fgs_layout* out) {
+  return fgs_batch_workspace_layout(n, cam, 1, st, instance_capacity, out);
+}
+
+fgs_status fgs_batch_workspace_size(int64_t n, const fgs_camera* cams, int32_t n_views, const fgs_settings* st,
+                                    int64_t instance_capacity, size_t* bytes) {
   if (!bytes) return fail(FGS_ERR_INVALID_ARGUMENT, "bytes is NULL");
   fgs_layout L;
-  fgs_status s = make_layout(n, cam, st, instance_capacity, &L);
+  fgs_status s = make_layout(n, cams, n_views, st, instance_capacity, &L);
   if (s != FGS_OK) return s;
   *bytes = L.total;
   return FGS_OK;
 }
 
-fgs_status fgs_workspace_layout(int64_t n, const fgs_camera* cam, const fgs_settings* st, int64_t instance_capacity,
-                                fgs_layout* out) {
+fgs_status fgs_batch_workspace_layout(int64_t n, const fgs_camera* cams, int32_t n_views, const fgs_settings* st,
+                                      int64_t instance_capacity, fgs_layout* out) {
   if (!out) return fail(FGS_ERR_INVALID_ARGUMENT, "out is NULL");
-  return make_layout(n, cam, st, instance_capacity, out);
+  return make_layout(n, cams, n_views, st, instance_capacity, out);
 }
 
 fgs_status fgs_rasterize_forward(const fgs_gaussians* g, const fgs_camera* cam, const fgs_settings* st,
                                  void* workspace, size_t workspace_bytes, int64_t instance_capacity, float* image,
                                  float* t_final, uint32_t* last, fgs_forward_stats* stats, void* stream) {
+  if (g && (g->velocity || g->accel))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "dynamic Gaussians take fgs_rasterize_forward_batch with times");
+  return fgs_rasterize_forward_batch(g, cam, nullptr, 1, st, workspace, workspace_bytes, instance_capacity, image,
+                                     t_final, last, 0u, stats, stream);
+}
+
+fgs_status fgs_rasterize_forward_batch(const fgs_gaussians* g, const fgs_camera* cams, const float* times,
+                                       int32_t n_views, const fgs_settings* st, void* workspace,
+                                       size_t workspace_bytes, int64_t instance_capacity, float* images,
+                                       float* t_finals, uint32_t* lasts, uint32_t mode, fgs_forward_stats* stats,
+                                       void* stream) {
   fgs_status s = check_gaussians(g);
   if (s != FGS_OK) return s;
   fgs_layout L;
-  s = make_layout(g->n, cam, st, instance_capacity, &L);
+  s = make_layout(g->n, cams, n_views, st, instance_capacity, &L);
   if (s != FGS_OK) return s;
+  if (mode & ~(uint32_t)FGS_FORWARD_NO_SYNC) return fail(FGS_ERR_INVALID_ARGUMENT, "unknown mode bits 0x%x", mode);
+  const bool no_sync = (mode & FGS_FORWARD_NO_SYNC) != 0;
   if (!workspace) return fail(FGS_ERR_INVALID_ARGUMENT, "workspace is NULL");
   if (workspace_bytes < L.total)
     return fail(FGS_ERR_INVALID_ARGUMENT, "workspace holds %zu bytes, %zu needed", workspace_bytes, L.total);
-  if (!image || !last) return fail(FGS_ERR_INVALID_ARGUMENT, "image and last are required");
+  if ((uintptr_t)workspace % 256) return fail(FGS_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+  if (!images || !lasts) return fail(FGS_ERR_INVALID_ARGUMENT, "images and lasts are required");
+  if (times)
+    for (int v = 0; v < n_views; ++v)
+      if (!std::isfinite(times[v])) return fail(FGS_ERR_INVALID_ARGUMENT, "times[%d] is not finite", v);
 
   hipStream_t hs = static_cast<hipStream_t>(stream);
   const GaussDev gd = make_gauss(g);
-  const CamDev cd = make_cam(cam, L);
+  const ViewSet vs = make_views(cams, n_views, st->tile, times);
   const SetDev sd = make_set(st);
   const uint32_t n = gd.n;
+  const uint32_t vn = n * (uint32_t)n_views;
   float4* rec = at<float4>(workspace, L.rec);
   uint32_t* n_tiles = at<uint32_t>(workspace, L.n_tiles);
   uint32_t* depth_key = at<uint32_t>(workspace, L.depth_key);
@@ -289,114 +357,123 @@ fgs_status fgs_rasterize_forward(const fgs_gaussians* g, const fgs_camera* cam, 
   uint32_t* ivals[2] = {at<uint32_t>(workspace, L.inst_vals[0]), at<uint32_t>(workspace, L.inst_vals[1])};
   uint2* ranges = at<uint2>(workspace, L.ranges);
   uint32_t* scratch = at<uint32_t>(workspace, L.scratch);
+  const uint32_t tiles = (uint32_t)L.total_tiles;
+  const uint32_t cap = (uint32_t)instance_capacity;
 
-  // One host synchronisation, right after the preprocess: the visible count,
-  // the instance count I and the depth-key range size every later launch.
+  // Statistics after the preprocess: the visible count, the instance count I
+  // and the depth-key range.  By default the host reads them once (one
+  // synchronisation) to size every later launch; with FGS_FORWARD_NO_SYNC
+  // every launch is sized by the capacities and reads the counts on the device.
   uint32_t stats_host[8] = {0, 0xffffffffu, 0, 0, 0, 0, 0, 0};
   if (n > 0) {
     uint4* partials = reinterpret_cast<uint4*>(scratch);  // free until the compaction scan
-    FGS_TIMED("preprocess", hs, launch_preprocess(gd, cd, sd, st->tile, rec, n_tiles, depth_key, partials, hs),
+    FGS_TIMED("preprocess", hs, launch_preprocess(gd, vs, sd, st->tile, rec, n_tiles, depth_key, partials, hs),
               "preprocess");
-    FGS_HIP(launch_stats(partials, ceil_div(n, kBlock), counters, hs), "stats");
-    FGS_HIP(hipMemcpyAsync(stats_host, counters, sizeof(stats_host), hipMemcpyDeviceToHost, hs), "stats copy");
-    FGS_HIP(hipStreamSynchronize(hs), "stats sync");
+    FGS_HIP(launch_stats(partials, (uint32_t)n_views * ceil_div(n, kBlock), (uint64_t)cap, counters, hs), "stats");
+    if (!no_sync) {
+      FGS_HIP(hipMemcpyAsync(stats_host, counters, sizeof(stats_host), hipMemcpyDeviceToHost, hs), "stats copy");
+      FGS_HIP(hipStreamSynchronize(hs), "stats sync");
+    }
+  } else {
+    FGS_HIP(launch_fill_u32(counters, 0u, 8, hs), "counters clear");
   }
-  const uint32_t nvis = stats_host[kStatVisible];
-  uint64_t inst64 = 0;
-  std::memcpy(&inst64, stats_host + kStatInstances, sizeof(inst64));
-  if (stats) {
-    stats->n_visible = nvis;
-    stats->n_instances = (int64_t)inst64;
+  uint32_t nvis = vn;  // capacity of the visible list
+  uint64_t inst64 = cap;
+  int depth_bits = 31;  // z > 0: the sign bit of every key is 0
+  if (!no_sync) {
+    nvis = stats_host[kStatVisible];
+    std::memcpy(&inst64, stats_host + kStatInstances, sizeof(inst64));
+    const uint32_t diff = stats_host[kStatKeyMin] ^ stats_host[kStatKeyMax];
+    depth_bits = diff ? 32 - __builtin_clz(diff) : 0;
+    if (stats) {
+      stats->n_visible = nvis;
+      stats->n_instances = (int64_t)inst64;
+      stats->tiles_x = L.tiles_x;
+      stats->tiles_y = L.tiles_y;
+    }
+    if (inst64 > (uint64_t)instance_capacity)
+      return fail(FGS_ERR_CAPACITY, "%llu instances exceed the capacity of %lld", (unsigned long long)inst64,
+                  (long long)instance_capacity);
+  } else if (stats) {
+    stats->n_visible = -1;
+    stats->n_instances = -1;
     stats->tiles_x = L.tiles_x;
     stats->tiles_y = L.tiles_y;
   }
-  if (inst64 > (uint64_t)instance_capacity)
-    return fail(FGS_ERR_CAPACITY, "%llu instances exceed the capacity of %lld", (unsigned long long)inst64,
-                (long long)instance_capacity);
+  const uint32_t* d_vis = counters + kStatVisible;
+  const uint32_t* d_sorted = no_sync ? counters + kStatSortCount : nullptr;
   const uint32_t inst = (uint32_t)inst64;
 
   int vis_final = 0;
   if (nvis > 0) {
     // visible compaction (prefix sum, so index order is kept) and the depth
-    // sort over the key bits that vary among the visible Gaussians
-    FGS_HIP(scan_u32(SCAN_NONZERO, n_tiles, nullptr, nullptr, offsets, n, nullptr, scratch, hs), "scan");
-    FGS_HIP(launch_compact_visible(n_tiles, depth_key, n, offsets, vis_keys[0], vis_ids[0], hs), "compact");
-    const uint32_t diff = stats_host[kStatKeyMin] ^ stats_host[kStatKeyMax];
-    const int depth_bits = diff ? 32 - __builtin_clz(diff) : 0;
-    FGS_HIP(radix_sort_pairs(vis_keys, vis_ids, nvis, nullptr, 0, depth_bits, scratch, &vis_final, hs),
+    // sort over the key bits that vary among the visible entries
+    FGS_HIP(scan_u32(SCAN_NONZERO, n_tiles, nullptr, nullptr, offsets, vn, nullptr, scratch, hs), "scan");
+    FGS_HIP(launch_compact_visible(n_tiles, depth_key, vn, offsets, vis_keys[0], vis_ids[0], hs), "compact");
+    FGS_HIP(radix_sort_pairs(vis_keys, vis_ids, nvis, no_sync ? d_vis : nullptr, 0, depth_bits, scratch, &vis_final,
+                             hs),
             "depth sort");
     FGS_HIP(launch_set_word(counters + kStatDepthBuf, (uint32_t)vis_final, hs), "depth buffer note");
     // instance offsets in depth order
-    FGS_HIP(scan_u32(SCAN_GATHER, n_tiles, vis_ids[vis_final], counters + kStatVisible, offsets, nvis, nullptr,
-                     scratch, hs), "offset scan");
+    FGS_HIP(scan_u32(SCAN_GATHER, n_tiles, vis_ids[vis_final], d_vis, offsets, nvis, nullptr, scratch, hs),
+            "offset scan");
   }
 
-  const size_t tiles = (size_t)L.tiles_x * L.tiles_y;
-  FGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, tiles * 2, hs), "ranges clear");
-  if (inst > 0) {
-    FGS_TIMED("duplicate", hs, launch_duplicate(vis_ids[vis_final], counters + kStatVisible, nvis, offsets, rec, cd,
-                             st->tile, (uint32_t)instance_capacity, ikeys[0], ivals[0], hs),
-            "duplicate");
+  FGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, (uint64_t)tiles * 2, hs), "ranges clear");
+  if (inst > 0 && nvis > 0) {
+    FGS_TIMED("duplicate", hs,
+              launch_duplicate(vis_ids[vis_final], d_vis, nvis, offsets, rec, vs, n, st->tile, cap, ikeys[0],
+                               ivals[0], hs),
+              "duplicate");
     int inst_final = 0;
-    FGS_TIMED("tile_sort", hs, radix_sort_pairs(ikeys, ivals, inst, nullptr, 0, tile_key_bits(tiles), scratch, &inst_final, hs),
-            "tile sort");
+    FGS_TIMED("tile_sort", hs,
+              radix_sort_pairs(ikeys, ivals, inst, d_sorted, 0, tile_key_bits(tiles), scratch, &inst_final, hs),
+              "tile sort");
     if (inst_final != L.inst_final) return fail(FGS_ERR_HIP, "internal: tile sort buffer mismatch");
-    FGS_HIP(launch_tile_ranges(ikeys[inst_final], inst, (uint32_t)tiles, ranges, hs), "tile ranges");
+    FGS_HIP(launch_tile_ranges(ikeys[inst_final], inst, d_sorted, tiles, ranges, hs), "tile ranges");
   }
-  FGS_TIMED("blend_forward", hs, launch_blend_forward(ranges, ivals[L.inst_final], rec, cd, sd, image, t_final, last, hs),
+  FGS_TIMED("blend_forward", hs,
+            launch_blend_forward(ranges, ivals[L.inst_final], rec, vs, sd, st->tile, images, t_finals, lasts, hs),
             "blend");
   return FGS_OK;
 }
 
-// Checks shared by the two backward entry points; on success fills the
-// layout and the workspace regions the blend backward reads.
-static fgs_status check_backward(const fgs_gaussians* g, const fgs_camera* cam, const fgs_settings* st,
-                                 void* workspace, size_t workspace_bytes, int64_t instance_capacity,
-                                 const float* image, const uint32_t* last, const float* dl_dimage, fgs_layout* L) {
+// Checks shared by the backward entry points; on success fills the layout.
+static fgs_status check_backward(const fgs_gaussians* g, const fgs_camera* cams, int32_t n_views,
+                                 const fgs_settings* st, void* workspace, size_t workspace_bytes,
+                                 int64_t instance_capacity, const float* image, const uint32_t* last,
+                                 const float* dl_dimage, fgs_layout* L) {
   fgs_status s = check_gaussians(g);
   if (s != FGS_OK) return s;
-  s = make_layout(g->n, cam, st, instance_capacity, L);
+  s = make_layout(g->n, cams, n_views, st, instance_capacity, L);
   if (s != FGS_OK) return s;
   if (!workspace) return fail(FGS_ERR_INVALID_ARGUMENT, "workspace is NULL");
   if (workspace_bytes < L->total)
     return fail(FGS_ERR_INVALID_ARGUMENT, "workspace holds %zu bytes, %zu needed", workspace_bytes, L->total);
+  if ((uintptr_t)workspace % 256) return fail(FGS_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
   if (!image || !last || !dl_dimage) return fail(FGS_ERR_INVALID_ARGUMENT, "image, last and dl_dimage are required");
   return FGS_OK;
 }
 
-// Clears the accumulators and runs the blend backward (per-Gaussian 2D
-// gradients into accum[9][n]).
-static fgs_status blend_backward(const fgs_gaussians* g, const fgs_camera* cam, const fgs_settings* st,
-                                 void* workspace, const fgs_layout& L, const float* image, const uint32_t* last,
-                                 const float* dl_dimage, hipStream_t hs) {
-  const GaussDev gd = make_gauss(g);
-  const CamDev cd = make_cam(cam, L);
+// Clears the accumulators and runs the blend backward over all views'
+// tiles (per-(view, Gaussian) 2D gradients into accum[9][n_views n]).
+static fgs_status blend_backward(const fgs_gaussians* g, const ViewSet& vs, const fgs_settings* st, void* workspace,
+                                 const fgs_layout& L, const float* images, const uint32_t* lasts,
+                                 const float* dl_dimages, hipStream_t hs) {
+  const uint32_t vn = (uint32_t)g->n * vs.n_views;
   const SetDev sd = make_set(st);
   float4* rec = at<float4>(workspace, L.rec);
   uint2* ranges = at<uint2>(workspace, L.ranges);
   uint32_t* ivals = at<uint32_t>(workspace, L.inst_vals[L.inst_final]);
   float* accum = at<float>(workspace, L.accum);
-  FGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(accum), 0u, (uint64_t)gd.n * 9, hs), "accum clear");
-  FGS_TIMED("blend_backward", hs, launch_blend_backward(ranges, ivals, rec, cd, sd, image, last, dl_dimage, accum, gd.n, hs),
+  FGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(accum), 0u, (uint64_t)vn * 9, hs), "accum clear");
+  FGS_TIMED("blend_backward", hs,
+            launch_blend_backward(ranges, ivals, rec, vs, sd, st->tile, images, lasts, dl_dimages, accum, vn, hs),
             "blend bwd");
   return FGS_OK;
 }
 
-fgs_status fgs_rasterize_backward(const fgs_gaussians* g, const fgs_camera* cam, const fgs_settings* st,
-                                  void* workspace, size_t workspace_bytes, int64_t instance_capacity,
-                                  const float* image, const uint32_t* last, const float* dl_dimage,
-                                  const fgs_gaussian_grads* grads, void* stream) {
-  fgs_layout L;
-  fgs_status s = check_backward(g, cam, st, workspace, workspace_bytes, instance_capacity, image, last, dl_dimage, &L);
-  if (s != FGS_OK) return s;
-  if (!grads) return fail(FGS_ERR_INVALID_ARGUMENT, "grads is NULL");
-  if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits ||
-                   !grads->sh_dc || !grads->sh_rest))
-    return fail(FGS_ERR_INVALID_ARGUMENT, "a gradient pointer is NULL");
-  if (g->n == 0) return FGS_OK;
-  hipStream_t hs = static_cast<hipStream_t>(stream);
-  s = blend_backward(g, cam, st, workspace, L, image, last, dl_dimage, hs);
-  if (s != FGS_OK) return s;
+static GradDev grad_dev(const fgs_gaussian_grads* grads) {
   GradDev gr;
   gr.means = grads->means;
   gr.log_scales = grads->log_scales;
@@ -404,9 +481,55 @@ fgs_status fgs_rasterize_backward(const fgs_gaussians* g, const fgs_camera* cam,
   gr.logits = grads->opacity_logits;
   gr.sh_dc = grads->sh_dc;
   gr.sh_rest = grads->sh_rest;
-  FGS_TIMED("preprocess_backward", hs, launch_preprocess_backward(make_gauss(g), make_cam(cam, L), at<float4>(workspace, L.rec),
-                                     at<float>(workspace, L.accum), gr, hs),
-          "preprocess bwd");
+  gr.velocity = grads->velocity;
+  gr.accel = grads->accel;
+  return gr;
+}
+
+fgs_status fgs_rasterize_backward(const fgs_gaussians* g, const fgs_camera* cam, const fgs_settings* st,
+                                  void* workspace, size_t workspace_bytes, int64_t instance_capacity,
+                                  const float* image, const uint32_t* last, const float* dl_dimage,
+                                  const fgs_gaussian_grads* grads, void* stream) {
+  if (g && (g->velocity || g->accel))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "dynamic Gaussians take fgs_rasterize_backward_batch with times");
+  return fgs_rasterize_backward_batch(g, cam, nullptr, 1, st, workspace, workspace_bytes, instance_capacity, image,
+                                      last, dl_dimage, grads, stream);
+}
+
+fgs_status fgs_rasterize_backward_batch(const fgs_gaussians* g, const fgs_camera* cams, const float* times,
+                                        int32_t n_views, const fgs_settings* st, void* workspace,
+                                        size_t workspace_bytes, int64_t instance_capacity, const float* images,
+                                        const uint32_t* lasts, const float* dl_dimages,
+                                        const fgs_gaussian_grads* grads, void* stream) {
+  fgs_layout L;
+  fgs_status s = check_backward(g, cams, n_views, st, workspace, workspace_bytes, instance_capacity, images, lasts,
+                                dl_dimages, &L);
+  if (s != FGS_OK) return s;
+  if (!grads) return fail(FGS_ERR_INVALID_ARGUMENT, "grads is NULL");
+  if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits ||
+                   !grads->sh_dc || !grads->sh_rest))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "a gradient pointer is NULL");
+  const bool dyn = g->velocity != nullptr;
+  if (dyn && g->n > 0 && (!grads->velocity || !grads->accel))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "dynamic Gaussians need velocity and accel gradients");
+  if (g->n == 0) return FGS_OK;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const ViewSet vs = make_views(cams, n_views, st->tile, times);
+  s = blend_backward(g, vs, st, workspace, L, images, lasts, dl_dimages, hs);
+  if (s != FGS_OK) return s;
+  const GradDev gr = grad_dev(grads);
+  const GaussDev gd = make_gauss(g);
+  if (n_views == 1 && !dyn) {
+    FGS_TIMED("preprocess_backward", hs,
+              launch_preprocess_backward(gd, vs.cam[0], at<float4>(workspace, L.rec), at<float>(workspace, L.accum),
+                                         gr, hs),
+              "preprocess bwd");
+  } else {
+    FGS_TIMED("preprocess_backward", hs,
+              launch_preprocess_backward_views(gd, vs, at<float4>(workspace, L.rec), at<float>(workspace, L.accum),
+                                               gr, hs),
+              "preprocess bwd (views)");
+  }
   return FGS_OK;
 }
 
@@ -424,8 +547,10 @@ fgs_status fgs_rasterize_backward_adam(const fgs_gaussians* g, const fgs_camera*
                                        const fgs_adam_moments* opt, int64_t step, double beta1, double beta2,
                                        double eps, void* stream) {
   fgs_layout L;
-  fgs_status s = check_backward(g, cam, st, workspace, workspace_bytes, instance_capacity, image, last, dl_dimage, &L);
+  fgs_status s = check_backward(g, cam, 1, st, workspace, workspace_bytes, instance_capacity, image, last, dl_dimage,
+                                &L);
   if (s != FGS_OK) return s;
+  if (g->velocity || g->accel) return fail(FGS_ERR_UNSUPPORTED, "the fused backward + Adam takes static Gaussians");
   if (!opt) return fail(FGS_ERR_INVALID_ARGUMENT, "opt is NULL");
   s = check_adam_hyper(step, beta1, beta2, eps);
   if (s != FGS_OK) return s;
@@ -436,7 +561,8 @@ fgs_status fgs_rasterize_backward_adam(const fgs_gaussians* g, const fgs_camera*
   for (int k = 0; k < 6; ++k)
     if (!opt->exp_avg[k] || !opt->exp_avg_sq[k]) return fail(FGS_ERR_INVALID_ARGUMENT, "moment %d is NULL", k);
   hipStream_t hs = static_cast<hipStream_t>(stream);
-  s = blend_backward(g, cam, st, workspace, L, image, last, dl_dimage, hs);
+  const ViewSet vs = make_views(cam, 1, st->tile, nullptr);
+  s = blend_backward(g, vs, st, workspace, L, image, last, dl_dimage, hs);
   if (s != FGS_OK) return s;
   void* const params[6] = {const_cast<float*>(g->means), const_cast<float*>(g->log_scales),
                            const_cast<float*>(g->quats), const_cast<float*>(g->opacity_logits),
@@ -444,7 +570,7 @@ fgs_status fgs_rasterize_backward_adam(const fgs_gaussians* g, const fgs_camera*
   const GaussDev gd = make_gauss(g);
   uint8_t* touched = at<uint8_t>(workspace, L.touched);
   FGS_TIMED("preprocess_backward_adam", hs,
-            launch_preprocess_backward_adam(gd, make_cam(cam, L), at<float4>(workspace, L.rec),
+            launch_preprocess_backward_adam(gd, vs.cam[0], at<float4>(workspace, L.rec),
                                             at<float>(workspace, L.accum), params, opt->exp_avg, opt->exp_avg_sq,
                                             opt->lr, step, beta1, beta2, eps, touched, hs),
             "preprocess bwd + adam");
@@ -455,11 +581,26 @@ fgs_status fgs_rasterize_backward_adam(const fgs_gaussians* g, const fgs_camera*
   return FGS_OK;
 }
 
+static fgs_status adam_impl(const fgs_adam_group* groups, int32_t n_groups, int64_t step, void* d_state,
+                            double beta1, double beta2, double eps, void* stream);
+
 fgs_status fgs_adam_step(const fgs_adam_group* groups, int32_t n_groups, int64_t step, double beta1, double beta2,
                          double eps, void* stream) {
+  if (step < 1) return fail(FGS_ERR_INVALID_ARGUMENT, "step must be >= 1");
+  return adam_impl(groups, n_groups, step, nullptr, beta1, beta2, eps, stream);
+}
+
+fgs_status fgs_adam_step_device(const fgs_adam_group* groups, int32_t n_groups, void* d_state, double beta1,
+                                double beta2, double eps, void* stream) {
+  if (!d_state || (uintptr_t)d_state % 8) return fail(FGS_ERR_INVALID_ARGUMENT, "d_state must be 8-byte aligned");
+  return adam_impl(groups, n_groups, 0, d_state, beta1, beta2, eps, stream);
+}
+
+static fgs_status adam_impl(const fgs_adam_group* groups, int32_t n_groups, int64_t step, void* d_state,
+                            double beta1, double beta2, double eps, void* stream) {
   if (!groups) return fail(FGS_ERR_INVALID_ARGUMENT, "groups is NULL");
   if (n_groups < 1 || n_groups > 16) return fail(FGS_ERR_INVALID_ARGUMENT, "n_groups %d not in 1..16", n_groups);
-  fgs_status hs = check_adam_hyper(step, beta1, beta2, eps);
+  fgs_status hs = check_adam_hyper(step > 0 ? step : 1, beta1, beta2, eps);
   if (hs != FGS_OK) return hs;
   for (int k = 0; k < n_groups; ++k) {
     const fgs_adam_group& G = groups[k];
@@ -470,7 +611,8 @@ fgs_status fgs_adam_step(const fgs_adam_group* groups, int32_t n_groups, int64_t
     if (!std::isfinite(G.lr)) return fail(FGS_ERR_INVALID_ARGUMENT, "group %d: lr not finite", k);
   }
   FGS_TIMED("adam", static_cast<hipStream_t>(stream),
-            launch_adam(groups, n_groups, step, beta1, beta2, eps, static_cast<hipStream_t>(stream)), "adam");
+            launch_adam(groups, n_groups, step, beta1, beta2, eps, d_state, static_cast<hipStream_t>(stream)),
+            "adam");
   return FGS_OK;
 }
 

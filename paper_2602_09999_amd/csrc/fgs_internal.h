@@ -29,6 +29,26 @@ struct CamDev {
   float bg[3];
 };
 
+// Up to kMaxViews cameras rendered in one pass (batched views, or timesteps of
+// a dynamic scene).  Passed by value as a kernel argument, so a captured graph
+// carries it.  A single view is n_views = 1.
+constexpr int kMaxViews = 16;
+struct ViewSet {
+  CamDev cam[kMaxViews];
+  float time[kMaxViews];                // t of each view (dynamic means; 0 otherwise)
+  uint32_t tile_base[kMaxViews + 1];    // first global tile of each view; [n_views] = total tiles
+  uint64_t pix_base[kMaxViews + 1];     // first pixel of each view in the concatenated images
+  uint32_t n_views;
+};
+
+// View of global tile t (tile_base is increasing).
+__device__ __forceinline__ uint32_t view_of_tile(const ViewSet& vs, uint32_t t) {
+  uint32_t v = 0;
+#pragma unroll 1
+  while (v + 1 < vs.n_views && t >= vs.tile_base[v + 1]) ++v;
+  return v;
+}
+
 struct SetDev {
   float alpha_min, alpha_max, t_min, dilation, quat_min, det_min;
   int32_t fp64_conic;  // determinant and 2x2 inverse in float64 (precision form)
@@ -38,6 +58,8 @@ struct SetDev {
 // them are instantiated for both.
 struct GaussDev {
   const float* means;
+  const float* velocity;  // dynamic scenes: mean(t) = means + velocity t + accel t^2 (NULL: static)
+  const float* accel;
   const float* log_scales;
   const float* quats;
   const float* logits;
@@ -50,6 +72,8 @@ struct GaussDev {
 
 struct GradDev {
   float* means;
+  float* velocity;  // written when the Gaussians are dynamic
+  float* accel;
   float* log_scales;
   float* quats;
   float* logits;
@@ -216,6 +240,7 @@ struct CandLane {
   float mx, my, a, b, c, thr;
   int tx0, ty0, w;  // rectangle origin and width in tiles
   uint32_t cand;    // candidate tiles (0: none)
+  int width, height;  // image of this Gaussian's view
 };
 
 __device__ __forceinline__ uint32_t udiv_small(uint32_t r, uint32_t w) {
@@ -227,7 +252,7 @@ __device__ __forceinline__ uint32_t udiv_small(uint32_t r, uint32_t w) {
 
 template <typename Emit>
 __device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, volatile uint32_t* owner_at, int tile,
-                                                   int width, int height, Emit emit) {
+                                                   Emit emit) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t incl = wave_inclusive_scan(me.cand, lane);
   const uint32_t cstart = incl - me.cand;
@@ -261,7 +286,8 @@ __device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, volatile 
     const float o_mx = __shfl(me.mx, owner, kWave), o_my = __shfl(me.my, owner, kWave);
     const float o_a = __shfl(me.a, owner, kWave), o_b = __shfl(me.b, owner, kWave);
     const float o_c = __shfl(me.c, owner, kWave), o_thr = __shfl(me.thr, owner, kWave);
-    const bool keep = tile_keep(o_mx, o_my, o_a, o_b, o_c, o_thr, tx, ty, tile, width, height) & valid;
+    const int o_width = __shfl(me.width, owner, kWave), o_height = __shfl(me.height, owner, kWave);
+    const bool keep = tile_keep(o_mx, o_my, o_a, o_b, o_c, o_thr, tx, ty, tile, o_width, o_height) & valid;
     const uint64_t kb = __ballot(keep);
     const uint32_t first = o_cstart > c0 ? o_cstart - c0 : 0u;
     const uint64_t from_first = first >= 64 ? 0ull : ~((first == 0) ? 0ull : (~0ull >> (64 - first)));
@@ -312,9 +338,10 @@ hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], uint32_t n, co
 //   [2] {r, g, b, flags (colour clamp bits 0-2, bit 3 set)}
 //   [3] {tile rectangle (tx0 | ty0 << 16, tx1 | ty1 << 16), instance count, 0}
 constexpr int kRecWords = 4;
-// Also writes one uint4 {visible, instances, min key, max key} per 256-thread
-// block into partials[ceil(n / 256)].
-hipError_t launch_preprocess(const GaussDev& g, const CamDev& cam, const SetDev& st, int tile,
+// Grid (Gaussian blocks, views); outputs at j = v n + i.  Also writes one
+// uint4 {visible, instances, min key, max key} per (view, 256-thread block)
+// into partials[n_views * ceil(n / 256)].
+hipError_t launch_preprocess(const GaussDev& g, const ViewSet& vs, const SetDev& st, int tile,
                              float4* rec, uint32_t* n_tiles, uint32_t* depth_key, uint4* partials,
                              hipStream_t s);
 // Slots of the workspace counters (uint32 words).
@@ -323,6 +350,8 @@ constexpr int kStatKeyMin = 1;     // smallest visible depth key
 constexpr int kStatKeyMax = 2;     // largest visible depth key
 constexpr int kStatDepthBuf = 3;   // ping-pong buffer holding the depth-sorted visible ids
 constexpr int kStatInstances = 4;  // instance count I, uint64 at words 4-5
+constexpr int kStatSortCount = 6;  // min(I, instance capacity): instances written and sorted
+constexpr int kStatOverflow = 7;   // 1 when I exceeds the instance capacity
 hipError_t launch_set_word(uint32_t* p, uint32_t v, hipStream_t s);
 // Z-order: scratch bytes for n Gaussians; perm[k] = index of the Gaussian at
 // position k of the Morton order of the means [3][n]; gather of `planes`
@@ -331,26 +360,32 @@ size_t zorder_scratch_bytes(uint64_t n);
 hipError_t launch_zorder(const float* means, uint32_t n, void* scratch, uint32_t* perm, hipStream_t s);
 hipError_t launch_permute(const void* src, void* dst, uint32_t n, int planes, int elem_bytes,
                           const uint32_t* perm, hipStream_t s);
-// Reduces the preprocess partials of nb blocks into the counter words.
-hipError_t launch_stats(const uint4* partials, uint32_t nb, uint32_t* counters, hipStream_t s);
+// Reduces the preprocess partials of nb blocks into the counter words,
+// including min(I, cap) and the overflow flag.
+hipError_t launch_stats(const uint4* partials, uint32_t nb, uint64_t cap, uint32_t* counters, hipStream_t s);
 hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth_key, uint32_t n,
                                   const uint32_t* pos, uint32_t* vis_keys, uint32_t* vis_ids,
                                   hipStream_t s);
-hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uint32_t n,
-                            const uint32_t* offsets, const float4* rec, const CamDev& cam, int tile,
-                            uint32_t cap,
+hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uint32_t n, const uint32_t* offsets,
+                            const float4* rec, const ViewSet& vs, uint32_t n_gauss, int tile, uint32_t cap,
                             uint32_t* keys, uint32_t* vals, hipStream_t s);
-hipError_t launch_tile_ranges(const uint32_t* keys, uint32_t count, uint32_t tiles, uint2* ranges,
-                              hipStream_t s);
-hipError_t launch_blend_forward(const uint2* ranges, const uint32_t* vals, const float4* rec,
-                                const CamDev& cam, const SetDev& st, float* image, float* t_final,
-                                uint32_t* last, hipStream_t s);
-hipError_t launch_blend_backward(const uint2* ranges, const uint32_t* vals, const float4* rec,
-                                 const CamDev& cam, const SetDev& st, const float* image,
-                                 const uint32_t* last, const float* dl_dimage, float* accum,
-                                 uint32_t n, hipStream_t s);
+// Ranges of the first min(*d_count, n) (or n) sorted keys.
+hipError_t launch_tile_ranges(const uint32_t* keys, uint32_t n, const uint32_t* d_count, uint32_t tiles,
+                              uint2* ranges, hipStream_t s);
+// One wave per global tile of all views (tile size 8, 16 or 32); images,
+// t_finals, lasts and dl_dimages hold the views one after another.
+hipError_t launch_blend_forward(const uint2* ranges, const uint32_t* vals, const float4* rec, const ViewSet& vs,
+                                const SetDev& st, int tile, float* images, float* t_finals, uint32_t* lasts,
+                                hipStream_t s);
+hipError_t launch_blend_backward(const uint2* ranges, const uint32_t* vals, const float4* rec, const ViewSet& vs,
+                                 const SetDev& st, int tile, const float* images, const uint32_t* lasts,
+                                 const float* dl_dimages, float* accum, uint32_t n, hipStream_t s);
 hipError_t launch_preprocess_backward(const GaussDev& g, const CamDev& cam, const float4* rec, const float* accum,
                                       const GradDev& gr, hipStream_t s);
+// Several views / timesteps: gradients summed over the views (accum is
+// [9][n_views n]); dynamic Gaussians also get dL/dvelocity and dL/daccel.
+hipError_t launch_preprocess_backward_views(const GaussDev& g, const ViewSet& vs, const float4* rec,
+                                            const float* accum, const GradDev& gr, hipStream_t s);
 // Fused preprocess backward + Adam for the Gaussians with a gradient, which it
 // marks in `touched`; params/exp_avg/exp_avg_sq/lr in the group order means,
 // log_scales, quats, logits, sh_dc, sh_rest.
@@ -364,8 +399,10 @@ hipError_t launch_preprocess_backward_adam(const GaussDev& g, const CamDev& cam,
 hipError_t launch_adam_untouched(void* const params[6], float* const exp_avg[6], float* const exp_avg_sq[6],
                                  const float lr[6], bool sh_bf16, uint64_t n, const uint8_t* touched, int64_t step,
                                  double beta1, double beta2, double eps, hipStream_t s);
-hipError_t launch_adam(const fgs_adam_group* groups, int n_groups, int64_t step, double beta1,
-                       double beta2, double eps, hipStream_t s);
+// step >= 1: host step count; step == 0: advance the device step counter in
+// dev_state (256 bytes, first an int64 t) and use it.
+hipError_t launch_adam(const fgs_adam_group* groups, int n_groups, int64_t step, double beta1, double beta2,
+                       double eps, void* dev_state, hipStream_t s);
 hipError_t launch_l1_backward(const float* image, const float* target, uint32_t n, float* dl,
                               double* loss, hipStream_t s);
 

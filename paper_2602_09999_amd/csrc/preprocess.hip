@@ -61,24 +61,35 @@ __device__ __forceinline__ uint32_t sh_colour(const GaussDev& g, uint32_t i, flo
   return flags;
 }
 
+// Grid: (Gaussian blocks, views).  Outputs of (view v, Gaussian i) sit at
+// index j = v n + i.
 template <bool SHB>
-__global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, CamDev cam, SetDev st, int tile,
+__global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, ViewSet vs, SetDev st, int tile,
                                                        float4* __restrict__ rec, uint32_t* __restrict__ n_tiles,
                                                        uint4* __restrict__ partials,
                                                        uint32_t* __restrict__ depth_key) {
 #pragma clang fp contract(off)
   __shared__ uint32_t s_owner[kBlock / kWave][kWave];
+  const uint32_t view = blockIdx.y;
+  const CamDev& cam = vs.cam[view];
   const uint32_t i0 = blockIdx.x * kBlock + threadIdx.x;
   const bool in_range = i0 < g.n;
   const uint32_t i = in_range ? i0 : g.n - 1;  // lanes past the end mirror the last Gaussian, then drop it
   const size_t n = g.n;
+  const size_t j = (size_t)view * n + i;
   const float* W = cam.w;
 
-  const float mu0 = g.means[i], mu1 = g.means[n + i], mu2 = g.means[2 * n + i];
+  float mu0 = g.means[i], mu1 = g.means[n + i], mu2 = g.means[2 * n + i];
+  if (g.velocity) {  // dynamic scene: mean at the view's time, (mu + v t) + a t^2
+    const float t = vs.time[view], tt = t * t;
+    mu0 = (mu0 + g.velocity[i] * t) + g.accel[i] * tt;
+    mu1 = (mu1 + g.velocity[n + i] * t) + g.accel[n + i] * tt;
+    mu2 = (mu2 + g.velocity[2 * n + i] * t) + g.accel[2 * n + i] * tt;
+  }
   const float X = ((W[0] * mu0 + W[1] * mu1) + W[2] * mu2) + W[3];
   const float Yc = ((W[4] * mu0 + W[5] * mu1) + W[6] * mu2) + W[7];
   const float Z = ((W[8] * mu0 + W[9] * mu1) + W[10] * mu2) + W[11];
-  if (in_range) depth_key[i] = __float_as_uint(Z);
+  if (in_range) depth_key[j] = __float_as_uint(Z);
 
   // activations: normalised quaternion, exp scales, sigmoid opacity
   const float qw0 = g.quats[i], qx0 = g.quats[n + i], qy0 = g.quats[2 * n + i], qz0 = g.quats[3 * n + i];
@@ -156,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, CamDev cam, S
   const float ly = (my - ext_y) - 0.5f, hy = (my + ext_y) - 0.5f;
   const float wm1 = (float)(cam.width - 1), hm1 = (float)(cam.height - 1);
   bool nonempty = in_range && ok && (hx >= 0.0f) && (lx <= wm1) && (hy >= 0.0f) && (ly <= hm1);
-  CandLane me = {mx, my, ca, cb, cc, thr, 0, 0, 1, 0u};
+  CandLane me = {mx, my, ca, cb, cc, thr, 0, 0, 1, 0u, cam.width, cam.height};
   uint32_t rect_lo = 0, rect_hi = 0;
   if (nonempty) {
     const int i0x = (lx <= 0.0f) ? 0 : (int)ceilf(lx);
@@ -174,18 +185,18 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, CamDev cam, S
     }
   }
   // exact per-tile test of every candidate tile, load-balanced over the wave
-  const uint32_t count = wave_tile_walk(me, s_owner[threadIdx.x / kWave], tile, cam.width, cam.height,
+  const uint32_t count = wave_tile_walk(me, s_owner[threadIdx.x / kWave], tile,
                                         [](int, uint32_t, int, int, bool) {});
   const bool vis = in_range && count > 0;
-  if (in_range) n_tiles[i] = count;
+  if (in_range) n_tiles[j] = count;
   if (vis) {
     float rgb[3];
     const uint32_t clip = sh_colour<SHB>(g, i, mu0, mu1, mu2, cam, rgb);
-    rec[kRecWords * (size_t)i + 0] = make_float4(mx, my, o, thr);
-    rec[kRecWords * (size_t)i + 1] = make_float4(ca, cb, cc, Z);
-    rec[kRecWords * (size_t)i + 2] = make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(clip | 8u));
-    rec[kRecWords * (size_t)i + 3] = make_float4(__uint_as_float(rect_lo), __uint_as_float(rect_hi),
-                                                 __uint_as_float(count), 0.0f);
+    rec[kRecWords * j + 0] = make_float4(mx, my, o, thr);
+    rec[kRecWords * j + 1] = make_float4(ca, cb, cc, Z);
+    rec[kRecWords * j + 2] = make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(clip | 8u));
+    rec[kRecWords * j + 3] = make_float4(__uint_as_float(rect_lo), __uint_as_float(rect_hi),
+                                         __uint_as_float(count), 0.0f);
   }
   // this block's share of the statistics the host reads after the preprocess
   // (visible count, instance count, smallest and largest visible depth key),
@@ -210,18 +221,18 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, CamDev cam, S
       const uint4 u = s_part[w];
       t = make_uint4(t.x + u.x, t.y + u.y, min(t.z, u.z), max(t.w, u.w));
     }
-    partials[blockIdx.x] = t;
+    partials[(size_t)view * gridDim.x + blockIdx.x] = t;
   }
 }
 
-hipError_t launch_preprocess(const GaussDev& g, const CamDev& cam, const SetDev& st, int tile, float4* rec,
+hipError_t launch_preprocess(const GaussDev& g, const ViewSet& vs, const SetDev& st, int tile, float4* rec,
                              uint32_t* n_tiles, uint32_t* depth_key, uint4* partials, hipStream_t s) {
-  if (g.n == 0) return hipSuccess;
-  const uint32_t blocks = ceil_div(g.n, kBlock);
+  if (g.n == 0 || vs.n_views == 0) return hipSuccess;
+  const dim3 grid(ceil_div(g.n, kBlock), vs.n_views);
   if (g.sh_bf16)
-    k_preprocess<true><<<blocks, kBlock, 0, s>>>(g, cam, st, tile, rec, n_tiles, partials, depth_key);
+    k_preprocess<true><<<grid, kBlock, 0, s>>>(g, vs, st, tile, rec, n_tiles, partials, depth_key);
   else
-    k_preprocess<false><<<blocks, kBlock, 0, s>>>(g, cam, st, tile, rec, n_tiles, partials, depth_key);
+    k_preprocess<false><<<grid, kBlock, 0, s>>>(g, vs, st, tile, rec, n_tiles, partials, depth_key);
   return hipGetLastError();
 }
 
@@ -229,7 +240,7 @@ hipError_t launch_preprocess(const GaussDev& g, const CamDev& cam, const SetDev&
 // instance count I (the sum of the per-Gaussian counts, independent of the
 // depth order) and the range of the visible depth keys -- from the
 // preprocess blocks' partials.  One workgroup; writes every counter word.
-__global__ __launch_bounds__(kBlock) void k_stats(const uint4* __restrict__ partials, uint32_t nb,
+__global__ __launch_bounds__(kBlock) void k_stats(const uint4* __restrict__ partials, uint32_t nb, uint64_t cap,
                                                   uint32_t* __restrict__ c) {
   __shared__ uint32_t s_vis[kBlock / kWave], s_min[kBlock / kWave], s_max[kBlock / kWave];
   __shared__ unsigned long long s_sum[kBlock / kWave];
@@ -263,6 +274,8 @@ __global__ __launch_bounds__(kBlock) void k_stats(const uint4* __restrict__ part
     c[kStatKeyMax] = kmax;
     c[kStatDepthBuf] = 0u;
     reinterpret_cast<unsigned long long*>(c + kStatInstances)[0] = sum;
+    c[kStatSortCount] = (uint32_t)(sum < cap ? sum : cap);
+    c[kStatOverflow] = sum > cap ? 1u : 0u;
   }
 }
 
@@ -275,8 +288,8 @@ hipError_t launch_set_word(uint32_t* p, uint32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_stats(const uint4* partials, uint32_t nb, uint32_t* counters, hipStream_t s) {
-  k_stats<<<1, kBlock, 0, s>>>(partials, nb, counters);
+hipError_t launch_stats(const uint4* partials, uint32_t nb, uint64_t cap, uint32_t* counters, hipStream_t s) {
+  k_stats<<<1, kBlock, 0, s>>>(partials, nb, cap, counters);
   return hipGetLastError();
 }
 
@@ -307,21 +320,28 @@ hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth
 // over its lanes (load-balanced walk), so the wave's kept tiles are written as
 // one contiguous, coalesced run.  Writes never pass a Gaussian's own count nor
 // `cap`.
+// Entries are (view, Gaussian) indices j = v n_gauss + i; the key of an
+// instance is its global tile id tile_base[v] + ty tiles_x(v) + tx.
 __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict__ vis_ids,
                                                       const uint32_t* __restrict__ d_nvis, uint32_t n,
                                                       const uint32_t* __restrict__ offsets,
-                                                      const float4* __restrict__ rec, CamDev cam, int tile,
-                                                      uint32_t cap, uint32_t* __restrict__ keys,
-                                                      uint32_t* __restrict__ vals) {
+                                                      const float4* __restrict__ rec, ViewSet vs,
+                                                      uint32_t n_gauss, int tile, uint32_t cap,
+                                                      uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
   __shared__ uint32_t s_owner[kBlock / kWave][kWave];
   const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
   const uint32_t nv = min(*d_nvis, n);
   if (blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1)) >= nv) return;  // whole wave idle
   CandLane me = {};
-  uint32_t gid = 0, off = 0, end = 0;
+  uint32_t gid = 0, off = 0, end = 0, kbase = 0, krow = 0;
   if (p < nv) {
     gid = vis_ids[p];
     off = offsets[p];
+    const uint32_t v = vs.n_views > 1 ? gid / n_gauss : 0u;
+    kbase = vs.tile_base[v];
+    krow = (uint32_t)vs.cam[v].tiles_x;
+    me.width = vs.cam[v].width;
+    me.height = vs.cam[v].height;
     // three float4 of one 64-byte record: one cache line per Gaussian
     const float4 r0 = rec[kRecWords * (size_t)gid + 0];
     const float4 r1 = rec[kRecWords * (size_t)gid + 1];
@@ -331,18 +351,20 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
     int tx0, ty0, tx1, ty1;
     unpack_rect(make_uint2(__float_as_uint(r3.x), __float_as_uint(r3.y)), tx0, ty0, tx1, ty1);
     me = CandLane{r0.x, r0.y, r1.x, r1.y, r1.z, r0.w, tx0, ty0, tx1 - tx0 + 1,
-                  count ? (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1)) : 0u};
+                  count ? (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1)) : 0u, me.width, me.height};
   }
-  const uint32_t tiles = (uint32_t)(cam.tiles_x * cam.tiles_y);
+  const uint32_t tiles = vs.tile_base[vs.n_views];
   const uint32_t written = wave_tile_walk(
-      me, s_owner[threadIdx.x / kWave], tile, cam.width, cam.height,
+      me, s_owner[threadIdx.x / kWave], tile,
       [&](int owner, uint32_t rank, int tx, int ty, bool keep) {
         const uint32_t o_off = __shfl(off, owner, kWave);
         const uint32_t o_end = __shfl(end, owner, kWave);
         const uint32_t o_gid = __shfl(gid, owner, kWave);
+        const uint32_t o_kbase = __shfl(kbase, owner, kWave);
+        const uint32_t o_krow = __shfl(krow, owner, kWave);
         const uint32_t slot = o_off + rank;
         if (keep && slot < o_end) {
-          keys[slot] = (uint32_t)(ty * cam.tiles_x + tx);
+          keys[slot] = o_kbase + (uint32_t)ty * o_krow + (uint32_t)tx;
           vals[slot] = o_gid;
         }
       });
@@ -356,10 +378,11 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
 }
 
 hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uint32_t n, const uint32_t* offsets,
-                            const float4* rec, const CamDev& cam, int tile, uint32_t cap, uint32_t* keys,
-                            uint32_t* vals, hipStream_t s) {
+                            const float4* rec, const ViewSet& vs, uint32_t n_gauss, int tile, uint32_t cap,
+                            uint32_t* keys, uint32_t* vals, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  k_duplicate<<<ceil_div(n, kBlock), kBlock, 0, s>>>(vis_ids, d_nvis, n, offsets, rec, cam, tile, cap, keys, vals);
+  k_duplicate<<<ceil_div(n, kBlock), kBlock, 0, s>>>(vis_ids, d_nvis, n, offsets, rec, vs, n_gauss, tile, cap, keys,
+                                                     vals);
   return hipGetLastError();
 }
 
@@ -367,8 +390,10 @@ hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uin
 // consecutive keys with one 16-byte load (the key buffer is 256-byte aligned);
 // the neighbours on either side come from cached loads.  Keys >= tiles (the
 // duplicate kernel's padding) are ignored.
-__global__ __launch_bounds__(kBlock) void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t count,
-                                                        uint32_t tiles, uint2* __restrict__ ranges) {
+__global__ __launch_bounds__(kBlock) void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t n,
+                                                        const uint32_t* __restrict__ d_count, uint32_t tiles,
+                                                        uint2* __restrict__ ranges) {
+  const uint32_t count = d_count ? min(*d_count, n) : n;
   const uint32_t i0 = (blockIdx.x * kBlock + threadIdx.x) * 4u;
   if (i0 >= count) return;
   uint32_t k[4];
@@ -392,9 +417,10 @@ __global__ __launch_bounds__(kBlock) void k_tile_ranges(const uint32_t* __restri
   }
 }
 
-hipError_t launch_tile_ranges(const uint32_t* keys, uint32_t count, uint32_t tiles, uint2* ranges, hipStream_t s) {
-  if (count == 0) return hipSuccess;
-  k_tile_ranges<<<ceil_div(ceil_div(count, 4), kBlock), kBlock, 0, s>>>(keys, count, tiles, ranges);
+hipError_t launch_tile_ranges(const uint32_t* keys, uint32_t n, const uint32_t* d_count, uint32_t tiles,
+                              uint2* ranges, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_tile_ranges<<<ceil_div(ceil_div(n, 4), kBlock), kBlock, 0, s>>>(keys, n, d_count, tiles, ranges);
   return hipGetLastError();
 }
 

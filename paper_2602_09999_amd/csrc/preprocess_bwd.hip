@@ -112,21 +112,25 @@ __device__ __forceinline__ void plane_store4(void* const* base, int p, size_t n,
 // nine accumulated 2D gradients acc = dL/d(mu2D.x, mu2D.y, a, b, c, o, r, g, b).
 // Each gradient is handed to emit(p, value) as soon as it is known, with the
 // parameter index p a compile-time constant after unrolling.
+// The record of this (view, Gaussian) is rec[rj]; mu is the mean the view saw
+// (the means themselves, or mean(t) of a dynamic scene), and emit(0..2, .)
+// receives dL/dmu.
 template <bool SHB, typename Emit>
 __device__ __forceinline__ void gaussian_grads(const GaussDev& g, const CamDev& cam, const float4* __restrict__ rec,
-                                               const float* acc, uint32_t i, Emit&& emit) {
+                                               const float* acc, uint32_t i, size_t rj, const float* mu,
+                                               Emit&& emit) {
 #pragma clang fp contract(on)
   const size_t n = g.n;
   const float gmx = acc[0], gmy = acc[1], ga = acc[2], gb = acc[3], gc = acc[4], go = acc[5];
-  const float4 r0 = rec[kRecWords * (size_t)i + 0];
-  const float4 r1 = rec[kRecWords * (size_t)i + 1];
-  const float4 r2 = rec[kRecWords * (size_t)i + 2];
+  const float4 r0 = rec[kRecWords * rj + 0];
+  const float4 r1 = rec[kRecWords * rj + 1];
+  const float4 r2 = rec[kRecWords * rj + 2];
   const float o = r0.z, ka = r1.x, kb = r1.y, kc = r1.z;
   const uint32_t clip = __float_as_uint(r2.w);
   const float* W = cam.w;
 
   // ---- recompute the forward quantities
-  const float mu0 = g.means[i], mu1 = g.means[n + i], mu2 = g.means[2 * n + i];
+  const float mu0 = mu[0], mu1 = mu[1], mu2 = mu[2];
   const float X = W[0] * mu0 + W[1] * mu1 + W[2] * mu2 + W[3];
   const float Yc = W[4] * mu0 + W[5] * mu1 + W[6] * mu2 + W[7];
   const float Z = W[8] * mu0 + W[9] * mu1 + W[10] * mu2 + W[11];
@@ -337,7 +341,8 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(GaussDev g, CamDev ca
     float a[9];
     pick_accum(acc, j, a);
     const uint32_t i = i0 + j;
-    gaussian_grads<SHB>(g, cam, rec, a, i, [&](int p, float v) { plane_store<SHB>(out, p, n, i, v); });
+    const float mu[3] = {g.means[i], g.means[n + i], g.means[2 * n + i]};
+    gaussian_grads<SHB>(g, cam, rec, a, i, i, mu, [&](int p, float v) { plane_store<SHB>(out, p, n, i, v); });
   }
 }
 
@@ -415,7 +420,8 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd_adam(GaussDev g, CamD
       float a[9];
       pick_accum(acc, j, a);
       const uint32_t i = i0 + j;
-      gaussian_grads<SHB>(g, cam, rec, a, i, [&](int p, float v) {
+      const float mu[3] = {g.means[i], g.means[n + i], g.means[2 * n + i]};
+      gaussian_grads<SHB>(g, cam, rec, a, i, i, mu, [&](int p, float v) {
         vg[p * kWave + lane] = group_of(p) >= 4 ? sh_round<SHB>(v) : v;  // as if stored
       });
       vid[lane] = i;
@@ -430,6 +436,71 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd_adam(GaussDev g, CamD
     }
     __builtin_amdgcn_wave_barrier();
   }
+}
+
+// Several views (or timesteps): Gaussian i sums, over the views that gave it
+// a gradient, the chain rule through view v's camera and record j = v n + i.
+// Dynamic scenes (mean(t) = mu + v t + a t^2) also get dL/dvelocity =
+// sum_t t dL/dmean(t) and dL/daccel = sum_t t^2 dL/dmean(t).  One thread per
+// Gaussian; every gradient plane is written in full.
+template <bool SHB>
+__global__ __launch_bounds__(kBlock) void k_preprocess_bwd_views(GaussDev g, ViewSet vs,
+                                                                 const float4* __restrict__ rec,
+                                                                 const float* __restrict__ accum, GradDev gr) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  const size_t n = g.n;
+  if (i >= n) return;
+  const size_t vn = n * vs.n_views;
+  void* const out[6] = {gr.means, gr.log_scales, gr.quats, gr.logits, gr.sh_dc, gr.sh_rest};
+  const bool dyn = g.velocity != nullptr;
+  float sum[kParams], dvel[3] = {0.f, 0.f, 0.f}, dacc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int p = 0; p < kParams; ++p) sum[p] = 0.0f;
+  for (uint32_t v = 0; v < vs.n_views; ++v) {
+    const size_t rj = (size_t)v * n + i;
+    float a[9];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      a[q] = accum[q * vn + rj];
+      any |= a[q] != 0.0f;
+    }
+    if (!any) continue;
+    const float t = vs.time[v], tt = t * t;
+    float mu[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      mu[k] = g.means[k * n + i];
+      if (dyn) mu[k] = (mu[k] + g.velocity[k * n + i] * t) + g.accel[k * n + i] * tt;
+    }
+    gaussian_grads<SHB>(g, vs.cam[v], rec, a, i, rj, mu, [&](int p, float val) {
+      sum[p] += val;
+      if (p < 3) {
+        dvel[p] = fmaf(t, val, dvel[p]);
+        dacc[p] = fmaf(tt, val, dacc[p]);
+      }
+    });
+  }
+#pragma unroll
+  for (int p = 0; p < kParams; ++p) plane_store<SHB>(out, p, n, i, sum[p]);
+  if (dyn) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      gr.velocity[k * n + i] = dvel[k];
+      gr.accel[k * n + i] = dacc[k];
+    }
+  }
+}
+
+hipError_t launch_preprocess_backward_views(const GaussDev& g, const ViewSet& vs, const float4* rec,
+                                            const float* accum, const GradDev& gr, hipStream_t s) {
+  if (g.n == 0) return hipSuccess;
+  const uint32_t grid = ceil_div(g.n, kBlock);
+  if (g.sh_bf16)
+    k_preprocess_bwd_views<true><<<grid, kBlock, 0, s>>>(g, vs, rec, accum, gr);
+  else
+    k_preprocess_bwd_views<false><<<grid, kBlock, 0, s>>>(g, vs, rec, accum, gr);
+  return hipGetLastError();
 }
 
 static bool planes_vec(const void* const* base, int count, bool sh_bf16, size_t n) {

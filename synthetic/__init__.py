@@ -173,6 +173,27 @@ def uniform_sphere_cameras(n_views: int, seed: int, radius: float = 5.0,
     return cams
 
 
+def make_motion(n: int, seed: int = 0, v_std: float = 0.1, a_std: float = 0.02) -> Dict[str, torch.Tensor]:
+    """Per-Gaussian velocity ~ N(0, v_std) and acceleration ~ N(0, a_std),
+    float32 [3, n] each (the dynamic workload's motion model)."""
+    g = torch.Generator(device="cpu")
+    g.manual_seed(int(seed) + 4_000_003)
+    vel = torch.randn(3, n, generator=g, dtype=torch.float64) * v_std
+    acc = torch.randn(3, n, generator=g, dtype=torch.float64) * a_std
+    return {"velocity": vel.to(torch.float32).contiguous(), "accel": acc.to(torch.float32).contiguous()}
+
+
+def timesteps(count: int):
+    """t_k = k / (count - 1), k = 0 .. count-1 (times in [0, 1])."""
+    return [k / (count - 1) if count > 1 else 0.0 for k in range(count)]
+
+
+def batch_scene(n: int, seed: int = 0) -> Dict[str, torch.Tensor]:
+    """The multi-view workload's scene: the usual draws with means recentred to
+    x, y in [-1, 1], z in [-2, 2] around the origin the cameras look at."""
+    return make_scene(n, seed, z_range=(-2.0, 2.0))
+
+
 def subset(scene: Dict[str, torch.Tensor], idx) -> Dict[str, torch.Tensor]:
     """Gaussians ``idx`` of a scene (same SoA layout)."""
     return {k: (v[..., idx] if v.dim() > 1 else v[idx]).contiguous() for k, v in scene.items()}
@@ -193,5 +214,6 @@ def scene_checksum(scene: Dict[str, torch.Tensor]) -> float:
 __all__ = [
     "Camera", "Workload", "WORKLOADS", "ADAM_LR", "PARAM_NAMES", "identity_camera",
     "look_at_camera", "make_scene", "workload_camera", "make_dl_dimage", "make_target",
-    "uniform_sphere_cameras", "subset", "count", "bytes_per_gaussian", "scene_checksum",
+    "uniform_sphere_cameras", "subset", "count", "bytes_per_gaussian", "scene_checksum", "make_motion",
+    "timesteps", "batch_scene",
 ]

@@ -21,8 +21,8 @@ def to_gpu(scene: Dict[str, torch.Tensor]) -> Dict[str, torch.Tensor]:
     return {k: v.to("cuda").contiguous() for k, v in scene.items()}
 
 
-def forward(scene, cam, capacity: Optional[int] = None):
-    rz = B.Rasterizer(cam)
+def forward(scene, cam, capacity: Optional[int] = None, settings=None):
+    rz = B.Rasterizer(cam, settings=settings)
     params = to_gpu(scene)
     if capacity is not None:
         rz._ensure(int(params["opacity_logits"].shape[0]), capacity)
@@ -36,7 +36,7 @@ def sorted_instances(rz: B.Rasterizer):
     I = rz.last_stats["n_instances"]
     keys = rz.view("inst_keys", I, index=lay.inst_final).cpu().numpy().view(np.uint32)
     vals = rz.view("inst_vals", I, index=lay.inst_final).cpu().numpy().view(np.uint32)
-    tiles = lay.tiles_x * lay.tiles_y
+    tiles = int(lay.total_tiles)
     ranges = rz.view("ranges", 2 * tiles).cpu().numpy().view(np.uint32).reshape(tiles, 2)
     return keys, vals, ranges
 
@@ -51,8 +51,9 @@ def last_ids(rz: B.Rasterizer, last: torch.Tensor) -> np.ndarray:
     keys, vals, ranges = sorted_instances(rz)
     lay = rz.layout()
     h, w = last.shape
+    t = int(rz.settings.tile)
     ys, xs = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
-    tile = (ys // 16) * lay.tiles_x + xs // 16
+    tile = (ys // t) * lay.tiles_x + xs // t
     lp = last.cpu().numpy().astype(np.int64)
     pos = ranges[tile, 0].astype(np.int64) + lp - 1
     out = np.full((h, w), -1, np.int64)

@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported_and_bound(lib):
     for name in names:
         assert hasattr(lib, name), name
         assert name in L.SIGNATURES, name
-    assert lib.fgs_abi_version() == 4
+    assert lib.fgs_abi_version() == 5
 
 
 def test_default_settings_match_the_paper(lib):
@@ -76,8 +76,23 @@ def test_invalid_arguments_are_rejected_without_launching(lib):
     bad = B.make_camera(S.workload_camera("c1"))
     bad.fx = float("nan")
     assert lib.fgs_workspace_size(10, ctypes.byref(bad), ctypes.byref(st), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
-    st8 = B.default_settings(tile=8)
-    assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(st8), 0, ctypes.byref(size)) == L.FGS_ERR_UNSUPPORTED
+    for t in (8, 16, 32):  # the three tile sizes are implemented
+        stt = B.default_settings(tile=t)
+        assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(stt), 0, ctypes.byref(size)) == L.FGS_OK
+    near0 = B.make_camera(S.workload_camera("c1"))
+    near0.near_z = 0.0
+    assert lib.fgs_workspace_size(10, ctypes.byref(near0), ctypes.byref(st), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
+    # batched views: 1..16 cameras, every camera checked
+    cams = (L.Camera * 17)(*([B.make_camera(S.workload_camera("c1"))] * 17))
+    for v, want in ((0, L.FGS_ERR_INVALID_ARGUMENT), (1, L.FGS_OK), (16, L.FGS_OK), (17, L.FGS_ERR_INVALID_ARGUMENT)):
+        assert lib.fgs_batch_workspace_size(10, cams, v, ctypes.byref(st), 0, ctypes.byref(size)) == want, v
+    cams[3] = bad
+    assert lib.fgs_batch_workspace_size(10, cams, 5, ctypes.byref(st), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
+    one = ctypes.c_size_t()
+    cams[3] = B.make_camera(S.workload_camera("c1"))
+    assert lib.fgs_batch_workspace_size(1000, cams, 1, ctypes.byref(st), 500, ctypes.byref(one)) == L.FGS_OK
+    assert lib.fgs_batch_workspace_size(1000, cams, 4, ctypes.byref(st), 500, ctypes.byref(size)) == L.FGS_OK
+    assert size.value > 3 * one.value // 2
     st7 = B.default_settings(tile=7)
     assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(st7), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
     stf = B.default_settings(flags=2)  # only FGS_FLAG_FP64_CONIC (bit 0) is defined
@@ -123,6 +138,25 @@ def test_invalid_arguments_are_rejected_without_launching(lib):
     r = lib.fgs_rasterize_backward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), fake, 1 << 30, 0, fake, fake,
                                    None, ctypes.byref(gr), None)
     assert r == L.FGS_ERR_INVALID_ARGUMENT
+    # dynamic Gaussians: velocity and accel together, and only through the batched calls
+    g.velocity = fake
+    cam1 = (L.Camera * 1)(B.make_camera(S.workload_camera("c1")))
+    r = lib.fgs_rasterize_forward_batch(ctypes.byref(g), cam1, None, 1, ctypes.byref(st), fake, 1 << 40, 0, fake,
+                                        None, fake, 0, ctypes.byref(stats), None)
+    assert r == L.FGS_ERR_INVALID_ARGUMENT and b"together" in lib.fgs_last_error()
+    g.accel = fake
+    r = lib.fgs_rasterize_forward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), fake, 1 << 30, 0, fake, None,
+                                  fake, ctypes.byref(stats), None)
+    assert r == L.FGS_ERR_INVALID_ARGUMENT and b"batch" in lib.fgs_last_error()
+    times = (ctypes.c_float * 2)(0.0, float("inf"))
+    cams2 = (L.Camera * 2)(B.make_camera(S.workload_camera("c1")), B.make_camera(S.workload_camera("c1")))
+    r = lib.fgs_rasterize_forward_batch(ctypes.byref(g), cams2, times, 2, ctypes.byref(st), fake, 1 << 40, 0, fake,
+                                        None, fake, 0, ctypes.byref(stats), None)
+    assert r == L.FGS_ERR_INVALID_ARGUMENT and b"times[1]" in lib.fgs_last_error()
+    r = lib.fgs_rasterize_forward_batch(ctypes.byref(g), cams2, None, 2, ctypes.byref(st), fake, 1 << 40, 0, fake,
+                                        None, fake, 4, ctypes.byref(stats), None)
+    assert r == L.FGS_ERR_INVALID_ARGUMENT and b"mode" in lib.fgs_last_error()
+    g.velocity = g.accel = None
     # fused backward + Adam: missing state, bad hyperparameters, non-finite lr
     mo = L.AdamMoments()
     r = lib.fgs_rasterize_backward_adam(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), fake, 1 << 30, 0, fake,

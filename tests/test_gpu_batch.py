@@ -1,0 +1,244 @@
+"""GPU tests of the batched forms: tile sizes 8 and 32, several views in one
+pass (uneven resolutions, one depth sort, one tile sort, one blend launch),
+the synchronisation-free mode and its graph capture, and dynamic (4D)
+Gaussians whose means move with time.
+
+A batched result must equal the per-view results: images and last
+contributors bit-identical, keys per view bit-exact against the key
+reference, gradients equal to the sum of the per-view gradients.  Dynamic
+Gaussians: per timestep the oracle renders the means at that time, computed
+in float32 in the kernel's order; the velocity and acceleration gradients
+must equal sum_t t dL/dmean(t) and sum_t t^2 dL/dmean(t) of the oracle's
+per-timestep mean gradients."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synthetic as S
+from paper_2602_09999_amd import _lib as L
+from paper_2602_09999_amd import binding as B
+from paper_2602_09999_amd.autograd import FusedAdam
+from tests.gpu_util import compare_lists, forward, last_ids, say, sorted_instances, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 1e-5
+GRAD_TOL = 1e-3
+
+
+def rel_l2(a, b):
+    a, b = a.double().cpu(), b.double().cpu()
+    return float((a - b).norm()) / max(float(b.norm()), 1e-30)
+
+
+def small_views():
+    """Three cameras on the radius-5 sphere around a recentred scene, uneven sizes."""
+    cams = S.uniform_sphere_cameras(3, seed=11, w_range=(60, 140), h_range=(50, 120))
+    return [c.copy(fx=0.9 * c.width, fy=0.9 * c.width) for c in cams]
+
+
+@pytest.mark.parametrize("tile", [8, 32])
+@pytest.mark.parametrize("case", ["c1", "ragged"])
+def test_tile_sizes_keys_image_gradients(tile, case):
+    if case == "c1":
+        sc, cam = S.make_scene(10_000, 0), S.workload_camera("c1")
+    else:
+        sc, cam = S.make_scene(3_000, 1), S.identity_camera(100, 75, 110.0, bg=(0.2, 0.5, 0.9))
+    say("tile", tile, case)
+    st = B.default_settings(tile=tile)
+    rz, params, image, t_final, last = forward(sc, cam, settings=st)
+    keys, vals, ranges = sorted_instances(rz)
+    nom, border = O.keys_ref_banded(sc, cam, tile=tile)
+    flips = compare_lists(keys, vals, ranges, nom, border, depth=nom["depth"])
+    say("  instances", len(keys), "borderline pairs", len(border), "flipped", flips)
+    assert flips <= len(border)
+    ref0 = O.render64(sc, cam)
+    ok = ~ref0["borderline"].numpy()
+    err = np.abs(image.cpu().double().numpy() - ref0["image"].numpy()).max(0)
+    say("  image max err", float(err[ok].max()))
+    assert err[ok].max() <= IMG_TOL
+    assert np.array_equal(last_ids(rz, last)[ok], ref0["last_id"].numpy()[ok])
+    dl = S.make_dl_dimage(cam.height, cam.width, seed=5)
+    dl[:, ref0["borderline"]] = 0.0
+    ref = O.render64(sc, cam, dl_dimage=dl)
+    grads = rz.backward(params, image, last, dl.cuda())
+    torch.cuda.synchronize()
+    for k in B.PARAM_NAMES:
+        e = rel_l2(grads[k], ref["grads"][k])
+        say(f"  {k:15s} rel L2 {e:.2e}")
+        assert e <= GRAD_TOL, (k, e)
+
+
+@pytest.mark.parametrize("tile", [16, 8])
+def test_batch_equals_single_views(tile):
+    sc = S.batch_scene(20_000, 3)
+    cams = small_views()
+    say("batch", [(c.width, c.height) for c in cams], "tile", tile)
+    st = B.default_settings(tile=tile)
+    params = to_gpu(sc)
+    br = B.BatchRasterizer(cams, settings=st)
+    images, t_finals, lasts = br.forward(params)
+    imgs, tfs, lss = br.split(images, 3), br.split(t_finals, 1), br.split(lasts, 1)
+    dls = [S.make_dl_dimage(c.height, c.width, seed=20 + k) for k, c in enumerate(cams)]
+    gb = br.backward(params, torch.cat([d.reshape(-1) for d in dls]).cuda())
+    gsum = {k: torch.zeros_like(v, dtype=torch.float64) for k, v in params.items()}
+    total = 0
+    for k, cam in enumerate(cams):
+        rz, p1, image, t_final, last = forward(sc, cam, settings=st)
+        assert torch.equal(imgs[k], image), k
+        assert torch.equal(tfs[k], t_final), k
+        assert torch.equal(lss[k], last), k
+        total += rz.last_stats["n_instances"]
+        g1 = rz.backward(p1, image, last, dls[k].cuda())
+        for name in gsum:
+            gsum[name] += g1[name].double()
+    torch.cuda.synchronize()
+    assert br.last_stats["n_instances"] == total
+    for name in B.PARAM_NAMES:
+        e = rel_l2(gb[name], gsum[name])
+        say(f"  {name:15s} batch vs sum of views rel L2 {e:.1e}")
+        assert e <= 1e-5, (name, e)
+
+
+def test_batch_without_synchronisation_and_overflow_flag():
+    sc = S.batch_scene(20_000, 4)
+    cams = small_views()
+    say("no-sync batch")
+    params = to_gpu(sc)
+    br = B.BatchRasterizer(cams)
+    images, t_finals, lasts = br.forward(params)
+    ref_img, ref_last = images.clone(), lasts.clone()
+    need = br.last_stats["n_instances"]
+    images, t_finals, lasts = br.forward(params, mode=L.FGS_FORWARD_NO_SYNC)
+    torch.cuda.synchronize()
+    c = br.counters().cpu()
+    assert int(c[7]) == 0 and int(c[4]) == need
+    assert torch.equal(images, ref_img) and torch.equal(lasts, ref_last)
+    # too small a capacity: the step completes, flags the overflow and writes
+    # no instance beyond the capacity
+    small = B.BatchRasterizer(cams)
+    small.ensure(S.count(sc), need // 2)
+    small.forward(params, mode=L.FGS_FORWARD_NO_SYNC)
+    torch.cuda.synchronize()
+    c = small.counters().cpu()
+    say("  instances", need, "capacity", need // 2, "overflow flag", int(c[7]))
+    assert int(c[7]) == 1 and int(c[4]) == need and int(c[6]) == need // 2
+
+
+def test_graph_captured_batched_step_matches_eager():
+    """forward (no synchronisation) + L1 + backward + Adam captured once and
+    replayed; each replay is checked against the same step run eagerly."""
+    sc = S.batch_scene(20_000, 5)
+    cams = small_views()
+    say("graph capture")
+    npix = sum(B.view_pixels(cams))
+    target = torch.rand(3 * npix, generator=torch.Generator().manual_seed(3)).cuda()
+    pe, pg = to_gpu(sc), to_gpu(sc)
+    be, bg = B.BatchRasterizer(cams), B.BatchRasterizer(cams)
+    oe, og = FusedAdam(pe, S.ADAM_LR), FusedAdam(pg, S.ADAM_LR, device_step=True)
+    dle, dlg = torch.empty(3 * npix, device="cuda"), torch.empty(3 * npix, device="cuda")
+    ge = {k: torch.empty_like(v) for k, v in pe.items()}
+    gg = {k: torch.empty_like(v) for k, v in pg.items()}
+    for r in (be, bg):  # size the workspaces outside the capture
+        r.forward(pe if r is be else pg)
+        r.ensure(S.count(sc), int(r.last_stats["n_instances"] * 1.5))
+
+    def step(r, p, o, dl, g):
+        images, _, _ = r.forward(p, mode=L.FGS_FORWARD_NO_SYNC)
+        B.l1_loss_backward(images, target, dl)
+        r.backward(p, dl, g)
+        o.step(g)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step(bg, pg, og, dlg, gg)  # warm-up on the side stream, as torch's capture expects
+    torch.cuda.current_stream().wait_stream(s)
+    step(be, pe, oe, dle, ge)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step(bg, pg, og, dlg, gg)
+    for rep in range(3):
+        # both start the step from the same state (gradient atomics make the
+        # two runs differ in the last bits, which would compound over steps)
+        for k in pe:
+            pg[k].copy_(pe[k])
+            og.exp_avg[k].copy_(oe.exp_avg[k])
+            og.exp_avg_sq[k].copy_(oe.exp_avg_sq[k])
+        p0 = {k: v.clone() for k, v in pe.items()}
+        step(be, pe, oe, dle, ge)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert int(bg.counters().cpu()[7]) == 0
+        assert int(og.state[0].cpu()) == oe.t, "the device step counter advances with every replay"
+        assert torch.equal(bg.images, be.images), rep
+        for k in pe:
+            em = rel_l2(og.exp_avg[k], oe.exp_avg[k])
+            ed = rel_l2(pg[k] - p0[k], pe[k] - p0[k])
+            assert em <= 1e-5 and ed <= 1e-3, (rep, k, em, ed)
+        say(f"  replay {rep} (t = {oe.t}): images equal, moments within 1e-5, steps within 1e-3")
+
+
+def test_dynamic_gaussians_match_oracle_and_chain_rule():
+    n = 3_000
+    sc = S.make_scene(n, 6)
+    motion = S.make_motion(n, 6)
+    cam = S.identity_camera(96, 72, 100.0, bg=(0.1, 0.2, 0.3))
+    times = S.timesteps(3)
+    say("dynamic", times)
+    params = to_gpu(sc)
+    params.update({k: v.cuda() for k, v in motion.items()})
+    br = B.BatchRasterizer([cam] * len(times), times=times)
+    images, t_finals, lasts = br.forward(params)
+    imgs = br.split(images, 3)
+    dls = [S.make_dl_dimage(cam.height, cam.width, seed=30 + k) for k in range(len(times))]
+    # per timestep: the means the kernel sees, in float32 in its operation order
+    mu0, vel, acc = sc["means"].numpy(), motion["velocity"].numpy(), motion["accel"].numpy()
+    g_mean = []
+    gsum = {k: torch.zeros(v.shape, dtype=torch.float64) for k, v in sc.items()}
+    keys, vals, ranges = sorted_instances(br)
+    tiles_per_view = ranges.shape[0] // len(times)
+    for k, t in enumerate(times):
+        t32 = np.float32(t)
+        mu_t = (mu0 + vel * t32) + acc * (t32 * t32)
+        sk = dict(sc)
+        sk["means"] = torch.from_numpy(mu_t.astype(np.float32))
+        ref0 = O.render64(sk, cam)
+        ok = ~ref0["borderline"].numpy()
+        err = np.abs(imgs[k].cpu().double().numpy() - ref0["image"].numpy()).max(0)
+        say(f"  t={t:.3f} image max err {float(err[ok].max()):.2e}")
+        assert err[ok].max() <= IMG_TOL
+        # keys of this view's tiles, shifted to local tile ids, entries j = k n + i
+        lo = int(np.searchsorted(keys, k * tiles_per_view))
+        hi = int(np.searchsorted(keys, (k + 1) * tiles_per_view))
+        nom, border = O.keys_ref_banded(sk, cam)
+        kv = vals[lo:hi].astype(np.int64)
+        assert np.all(kv // n == k)
+        view_ranges = ranges[k * tiles_per_view:(k + 1) * tiles_per_view]
+        loc_ranges = view_ranges.astype(np.int64) - lo
+        loc_ranges[view_ranges[:, 1] == 0] = 0
+        flips = compare_lists(keys[lo:hi] - k * tiles_per_view, (kv % n).astype(np.uint32),
+                              loc_ranges.astype(np.uint32), nom, border, depth=nom["depth"])
+        assert flips <= len(border)
+        dl = dls[k].clone()
+        dl[:, ref0["borderline"]] = 0.0
+        dls[k] = dl
+        ref = O.render64(sk, cam, dl_dimage=dl)
+        g_mean.append(ref["grads"]["means"].double())
+        for name in gsum:
+            if name != "means":
+                gsum[name] += ref["grads"][name].double()
+    grads = {k: torch.empty_like(v) for k, v in params.items()}
+    br.backward(params, torch.cat([d.reshape(-1) for d in dls]).cuda(), grads)
+    torch.cuda.synchronize()
+    want = {
+        "means": sum(g_mean),
+        "velocity": sum(t * g for t, g in zip(times, g_mean)),
+        "accel": sum(t * t * g for t, g in zip(times, g_mean)),
+    }
+    want.update({k: v for k, v in gsum.items() if k != "means"})
+    for name, w in want.items():
+        e = rel_l2(grads[name], w)
+        say(f"  {name:15s} rel L2 {e:.2e}")
+        assert e <= GRAD_TOL, (name, e)
