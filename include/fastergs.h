@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define FGS_ABI_VERSION 5
+#define FGS_ABI_VERSION 6
 
 typedef enum fgs_status {
   FGS_OK = 0,
@@ -152,8 +152,10 @@ typedef struct fgs_forward_stats {
  * With several views, the per-Gaussian regions (rec, n_tiles, depth_key,
  * vis_*, accum) hold n_views * n entries, entry v * n + i for view v.
  *   vis_ids    uint32[n] x2 ping-pong (see counters[3])
- *   inst_keys  uint32[cap] x2, inst_vals uint32[cap] x2: tile ids and
- *                           Gaussian ids; sorted in [inst_final]
+ *   inst_keys  uint16 or uint32 (inst_key_bytes) [cap] x2, inst_vals
+ *                           uint32[cap] x2: global tile ids and Gaussian ids;
+ *                           sorted in [inst_final].  Keys are 16-bit when
+ *                           total_tiles < 65536, else 32-bit.
  *   ranges     uint32[2*tiles] [start, end) of each tile's list
  *   accum      float[9][n]  backward: dL/d(mu2D.x, mu2D.y, a, b, c, opacity, r, g, b)
  *   touched    uint8[ceil(n/4)]  fused backward + Adam: bit j of byte k set when
@@ -165,7 +167,7 @@ typedef struct fgs_layout {
   size_t inst_keys[2], inst_vals[2];
   size_t ranges, accum, touched, scratch, total;
   int32_t inst_final;
-  int32_t reserved;
+  int32_t inst_key_bytes;        /* 2 or 4: width of the inst_keys entries */
   int32_t tiles_x, tiles_y;      /* tile grid of view 0 */
   int64_t instance_capacity;
   int64_t n_views;

@@ -90,15 +90,14 @@ __device__ __forceinline__ float4 load_once_bf16x4(const void* p) {
   return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u),
                      __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xffff0000u));
 }
-__device__ __forceinline__ float4 load_bf16x4(const void* p) {
-  const uint2 v = *reinterpret_cast<const uint2*>(p);
-  return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u),
-                     __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xffff0000u));
+__device__ __forceinline__ void store_once4(float* p, float4 f) {
+  const vf4 v = {f.x, f.y, f.z, f.w};
+  __builtin_nontemporal_store(v, reinterpret_cast<vf4*>(p));
 }
 __device__ __forceinline__ void store_bf16x4(void* p, float4 f) {
-  const uint2 v = make_uint2((uint32_t)f32_to_bf16(f.x) | ((uint32_t)f32_to_bf16(f.y) << 16),
-                             (uint32_t)f32_to_bf16(f.z) | ((uint32_t)f32_to_bf16(f.w) << 16));
-  *reinterpret_cast<uint2*>(p) = v;
+  const vu2 v = {(uint32_t)f32_to_bf16(f.x) | ((uint32_t)f32_to_bf16(f.y) << 16),
+                 (uint32_t)f32_to_bf16(f.z) | ((uint32_t)f32_to_bf16(f.w) << 16)};
+  __builtin_nontemporal_store(v, reinterpret_cast<vu2*>(p));
 }
 
 __device__ __forceinline__ int adam_group(const AdamArgs& a, uint64_t slot) {
@@ -138,15 +137,16 @@ __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a, uint64_t total_vec)
     const uint64_t e0 = (slot - G.vec_begin) * 4;
     vec[u] = G.vec4 && e0 + 4 <= G.numel;
     if (vec[u]) {
+      // every stream is read once and written once: non-temporal accesses
       if (G.bf16) {
-        p[u] = load_bf16x4(static_cast<const uint16_t*>(G.p) + e0);
+        p[u] = load_once_bf16x4(static_cast<const uint16_t*>(G.p) + e0);
         g[u] = load_once_bf16x4(static_cast<const uint16_t*>(G.g) + e0);
       } else {
-        p[u] = *reinterpret_cast<const float4*>(static_cast<const float*>(G.p) + e0);
+        p[u] = load_once4(static_cast<const float*>(G.p) + e0);
         g[u] = load_once4(static_cast<const float*>(G.g) + e0);
       }
-      m[u] = *reinterpret_cast<const float4*>(G.m + e0);
-      v[u] = *reinterpret_cast<const float4*>(G.v + e0);
+      m[u] = load_once4(G.m + e0);
+      v[u] = load_once4(G.v + e0);
     }
   }
 #pragma unroll
@@ -158,9 +158,9 @@ __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a, uint64_t total_vec)
     if (vec[u]) {
       adam4(p[u], g[u], m[u], v[u], c, a.dev ? a.dev->step_size[gi[u]] : G.step_size);
       if (G.bf16) store_bf16x4(static_cast<uint16_t*>(G.p) + e0, p[u]);
-      else *reinterpret_cast<float4*>(static_cast<float*>(G.p) + e0) = p[u];
-      *reinterpret_cast<float4*>(G.m + e0) = m[u];
-      *reinterpret_cast<float4*>(G.v + e0) = v[u];
+      else store_once4(static_cast<float*>(G.p) + e0, p[u]);
+      store_once4(G.m + e0, m[u]);
+      store_once4(G.v + e0, v[u]);
     } else if (G.bf16) {
       for (uint64_t e = e0; e < e0 + 4 && e < G.numel; ++e) {
         float pe = sh_load<true>(G.p, e), me = G.m[e], ve = G.v[e];
@@ -218,64 +218,85 @@ hipError_t launch_adam(const fgs_adam_group* groups, int n_groups, int64_t step,
   return hipGetLastError();
 }
 
-// Zero-gradient Adam step over the six parameter groups of the Gaussians
-// (planes of length `plane`), skipping the elements of Gaussians whose bit is
-// set in `touched` (updated already, with their gradient, by the fused
-// backward kernel).  Same slot layout as k_adam; no gradient stream, so
-// 12 bytes are read and 12 written per float32 element.  vec4 slots require
-// plane % 4 == 0 so that a slot never straddles two planes.
-__global__ __launch_bounds__(kBlock) void k_adam_untouched(AdamArgs a, uint64_t total_vec, uint64_t plane,
-                                                           const uint8_t* __restrict__ touched) {
-  const uint64_t base = (uint64_t)blockIdx.x * (kBlock * kAdamSlots) + threadIdx.x;
-  float4 p[kAdamSlots], m[kAdamSlots], v[kAdamSlots];
-  int gi[kAdamSlots];
-  uint32_t skip[kAdamSlots];
-#pragma unroll
-  for (int u = 0; u < kAdamSlots; ++u) {
-    const uint64_t slot = base + (uint64_t)u * kBlock;
-    gi[u] = 0;
-    skip[u] = 0xfu;
-    if (slot >= total_vec) continue;
-    gi[u] = adam_group(a, slot);
-    const AdamGroupDev& G = a.grp[gi[u]];
-    const uint64_t e0 = (slot - G.vec_begin) * 4;
-    if (!G.vec4) {
-      skip[u] = 0x10u;  // element-wise path below
-      continue;
-    }
-    skip[u] = touched[(e0 % plane) >> 2];
-    if (skip[u] == 0xfu) continue;
-    if (G.bf16) p[u] = load_bf16x4(static_cast<const uint16_t*>(G.p) + e0);
-    else p[u] = *reinterpret_cast<const float4*>(static_cast<const float*>(G.p) + e0);
-    m[u] = *reinterpret_cast<const float4*>(G.m + e0);
-    v[u] = *reinterpret_cast<const float4*>(G.v + e0);
-  }
-#pragma unroll
-  for (int u = 0; u < kAdamSlots; ++u) {
-    const uint64_t slot = base + (uint64_t)u * kBlock;
-    if (slot >= total_vec || skip[u] == 0xfu) continue;
-    const AdamGroupDev& G = a.grp[gi[u]];
-    const uint64_t e0 = (slot - G.vec_begin) * 4;
-    if (skip[u] != 0x10u) {
-      if (!(skip[u] & 1u)) adam_elem(p[u].x, 0.0f, m[u].x, v[u].x, a.c, G.step_size);
-      if (!(skip[u] & 2u)) adam_elem(p[u].y, 0.0f, m[u].y, v[u].y, a.c, G.step_size);
-      if (!(skip[u] & 4u)) adam_elem(p[u].z, 0.0f, m[u].z, v[u].z, a.c, G.step_size);
-      if (!(skip[u] & 8u)) adam_elem(p[u].w, 0.0f, m[u].w, v[u].w, a.c, G.step_size);
-      if (G.bf16) store_bf16x4(static_cast<uint16_t*>(G.p) + e0, p[u]);
-      else *reinterpret_cast<float4*>(static_cast<float*>(G.p) + e0) = p[u];
-      *reinterpret_cast<float4*>(G.m + e0) = m[u];
-      *reinterpret_cast<float4*>(G.v + e0) = v[u];
+// Zero-gradient Adam step over the six parameter groups of the Gaussians,
+// skipping the elements of Gaussians whose bit is set in `touched` (updated
+// already, with their gradient, by the fused backward kernel).  Grid:
+// (chunks of 4 * 256 Gaussians, the 59 planes): a thread takes four
+// consecutive Gaussians of one plane, so the Gaussian index and the mark byte
+// need no division, and every access is a 16-byte (8-byte for bfloat16) one
+// that streams (read once, written once).  No gradient stream: 12 bytes are
+// read and 12 written per float32 element.
+struct UntouchedArgs {
+  void* p[6];
+  float* m[6];
+  float* v[6];
+  float step_size[6];
+  AdamCoef c;
+  uint32_t n;
+  int32_t sh_bf16;
+  int32_t vec;  // n % 4 == 0 and every plane 16-byte (8-byte for bfloat16) aligned
+};
+
+__device__ __forceinline__ int plane_group(int p) {
+  return p < 3 ? 0 : p < 6 ? 1 : p < 10 ? 2 : p < 11 ? 3 : p < 14 ? 4 : 5;
+}
+__device__ __forceinline__ int group_first_plane(int g) {
+  return g == 0 ? 0 : g == 1 ? 3 : g == 2 ? 6 : g == 3 ? 10 : g == 4 ? 11 : 14;
+}
+
+__global__ __launch_bounds__(kBlock) void k_adam_untouched(UntouchedArgs a, const uint8_t* __restrict__ touched) {
+  const int plane = blockIdx.y;
+  const int gi = plane_group(plane);
+  const size_t n = a.n;
+  const size_t off = (size_t)(plane - group_first_plane(gi)) * n;
+  const uint32_t q = blockIdx.x * kBlock + threadIdx.x;  // four Gaussians 4q .. 4q+3
+  const uint32_t i0 = q * 4u;
+  if (i0 >= a.n) return;
+  const uint32_t skip = touched[q];
+  if (skip == 0xfu) return;
+  const bool bf = a.sh_bf16 && gi >= 4;
+  const float st = a.step_size[gi];
+  float* M = a.m[gi] + off;
+  float* V = a.v[gi] + off;
+  if (a.vec && i0 + 4 <= a.n) {
+    float4 pp;
+    if (bf) {
+      const vu2 u = __builtin_nontemporal_load(reinterpret_cast<const vu2*>(static_cast<uint16_t*>(a.p[gi]) + off + i0));
+      pp = make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                       __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
     } else {
-      for (uint64_t e = e0; e < e0 + 4 && e < G.numel; ++e) {
-        const uint64_t i = e % plane;
-        if (touched[i >> 2] >> (i & 3) & 1u) continue;
-        float pe = G.bf16 ? sh_load<true>(G.p, e) : sh_load<false>(G.p, e), me = G.m[e], ve = G.v[e];
-        adam_elem(pe, 0.0f, me, ve, a.c, G.step_size);
-        if (G.bf16) sh_store<true>(G.p, e, pe);
-        else sh_store<false>(G.p, e, pe);
-        G.m[e] = me;
-        G.v[e] = ve;
-      }
+      const vf4 u = __builtin_nontemporal_load(reinterpret_cast<const vf4*>(static_cast<float*>(a.p[gi]) + off + i0));
+      pp = make_float4(u.x, u.y, u.z, u.w);
+    }
+    vf4 mm = __builtin_nontemporal_load(reinterpret_cast<const vf4*>(M + i0));
+    vf4 vv = __builtin_nontemporal_load(reinterpret_cast<const vf4*>(V + i0));
+    float m4[4] = {mm.x, mm.y, mm.z, mm.w}, v4[4] = {vv.x, vv.y, vv.z, vv.w};
+    float p4[4] = {pp.x, pp.y, pp.z, pp.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (!(skip >> e & 1u)) adam_elem(p4[e], 0.0f, m4[e], v4[e], a.c, st);
+    if (bf) {
+      const vu2 u = {(uint32_t)f32_to_bf16(p4[0]) | ((uint32_t)f32_to_bf16(p4[1]) << 16),
+                     (uint32_t)f32_to_bf16(p4[2]) | ((uint32_t)f32_to_bf16(p4[3]) << 16)};
+      __builtin_nontemporal_store(u, reinterpret_cast<vu2*>(static_cast<uint16_t*>(a.p[gi]) + off + i0));
+    } else {
+      const vf4 u = {p4[0], p4[1], p4[2], p4[3]};
+      __builtin_nontemporal_store(u, reinterpret_cast<vf4*>(static_cast<float*>(a.p[gi]) + off + i0));
+    }
+    const vf4 mo = {m4[0], m4[1], m4[2], m4[3]}, vo = {v4[0], v4[1], v4[2], v4[3]};
+    __builtin_nontemporal_store(mo, reinterpret_cast<vf4*>(M + i0));
+    __builtin_nontemporal_store(vo, reinterpret_cast<vf4*>(V + i0));
+  } else {
+    for (uint32_t e = 0; e < 4 && i0 + e < a.n; ++e) {
+      if (skip >> e & 1u) continue;
+      const size_t k = off + i0 + e;
+      float pe = bf ? sh_load<true>(a.p[gi], k) : sh_load<false>(a.p[gi], k);
+      float me = a.m[gi][k], ve = a.v[gi][k];
+      adam_elem(pe, 0.0f, me, ve, a.c, st);
+      if (bf) sh_store<true>(a.p[gi], k, pe);
+      else sh_store<false>(a.p[gi], k, pe);
+      a.m[gi][k] = me;
+      a.v[gi][k] = ve;
     }
   }
 }
@@ -284,28 +305,24 @@ hipError_t launch_adam_untouched(void* const params[6], float* const exp_avg[6],
                                  const float lr[6], bool sh_bf16, uint64_t n, const uint8_t* touched, int64_t step,
                                  double beta1, double beta2, double eps, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  static const int kPlanes[6] = {3, 3, 4, 1, 3, 45};
-  AdamArgs a = {};
-  a.n_groups = 6;
+  UntouchedArgs a = {};
   double bc1 = 1.0;
   a.c = adam_coef(step, beta1, beta2, eps, &bc1);
-  uint64_t vec = 0;
+  a.n = (uint32_t)n;
+  a.sh_bf16 = sh_bf16 ? 1 : 0;
+  bool vec = n % 4 == 0;
   for (int k = 0; k < 6; ++k) {
-    AdamGroupDev& G = a.grp[k];
-    G.p = params[k];
-    G.g = nullptr;
-    G.m = exp_avg[k];
-    G.v = exp_avg_sq[k];
-    G.numel = (uint64_t)kPlanes[k] * n;
-    G.vec_begin = vec;
-    G.step_size = (float)((double)lr[k] / bc1);
-    G.bf16 = (sh_bf16 && k >= 4) ? 1 : 0;
-    const uintptr_t pp = (uintptr_t)G.p, mv = (uintptr_t)G.m | (uintptr_t)G.v;
-    G.vec4 = (n % 4 == 0 && (pp & (G.bf16 ? 7u : 15u)) == 0 && (mv & 15u) == 0) ? 1 : 0;
-    vec += (G.numel + 3) / 4;
+    a.p[k] = params[k];
+    a.m[k] = exp_avg[k];
+    a.v[k] = exp_avg_sq[k];
+    a.step_size[k] = (float)((double)lr[k] / bc1);
+    const uintptr_t need = (sh_bf16 && k >= 4) ? 7u : 15u;
+    vec = vec && ((uintptr_t)params[k] & need) == 0 && ((uintptr_t)exp_avg[k] & 15u) == 0 &&
+          ((uintptr_t)exp_avg_sq[k] & 15u) == 0;
   }
-  const uint64_t per_block = (uint64_t)kBlock * kAdamSlots;
-  k_adam_untouched<<<(uint32_t)((vec + per_block - 1) / per_block), kBlock, 0, s>>>(a, vec, n, touched);
+  a.vec = vec ? 1 : 0;
+  const dim3 grid(ceil_div(ceil_div(n, 4), kBlock), 59);
+  k_adam_untouched<<<grid, kBlock, 0, s>>>(a, touched);
   return hipGetLastError();
 }
 

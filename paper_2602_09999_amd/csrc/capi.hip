@@ -69,6 +69,10 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
 
+// 16-bit sort keys when every global tile id and the out-of-range id `tiles`
+// fit in them, else 32-bit.
+static int tile_key_bytes(uint64_t tiles) { return tiles < 65536 ? 2 : 4; }
+
 int tile_key_bits(uint64_t tiles) {
   int b = 1;
   while (b < 32 && (uint64_t(1) << b) < tiles) ++b;
@@ -167,8 +171,9 @@ fgs_status make_layout(int64_t n, const fgs_camera* cams, int32_t n_views, const
   L->vis_ids[0] = take(vn * 4);
   L->vis_ids[1] = take(vn * 4);
   L->inst_offsets = take((vn + 1) * 4);
-  L->inst_keys[0] = take(uc * 4);
-  L->inst_keys[1] = take(uc * 4);
+  const int key_bytes = tile_key_bytes(tiles);
+  L->inst_keys[0] = take(uc * key_bytes);
+  L->inst_keys[1] = take(uc * key_bytes);
   L->inst_vals[0] = take(uc * 4);
   L->inst_vals[1] = take(uc * 4);
   L->ranges = take(tiles * 8);
@@ -181,6 +186,7 @@ fgs_status make_layout(int64_t n, const fgs_camera* cams, int32_t n_views, const
   L->scratch = take(words * 4 + 256);
   L->total = off;
   L->inst_final = ((tile_key_bits(tiles) + kRadixBits - 1) / kRadixBits) & 1;
+  L->inst_key_bytes = key_bytes;
   L->tiles_x = (int32_t)((cams[0].width + t - 1) / t);
   L->tiles_y = (int32_t)((cams[0].height + t - 1) / t);
   L->instance_capacity = cap;
@@ -353,7 +359,8 @@ fgs_status fgs_rasterize_forward_batch(const fgs_gaussians* g, const fgs_camera*
   uint32_t* vis_keys[2] = {at<uint32_t>(workspace, L.vis_keys[0]), at<uint32_t>(workspace, L.vis_keys[1])};
   uint32_t* vis_ids[2] = {at<uint32_t>(workspace, L.vis_ids[0]), at<uint32_t>(workspace, L.vis_ids[1])};
   uint32_t* offsets = at<uint32_t>(workspace, L.inst_offsets);
-  uint32_t* ikeys[2] = {at<uint32_t>(workspace, L.inst_keys[0]), at<uint32_t>(workspace, L.inst_keys[1])};
+  void* ikeys[2] = {at<uint8_t>(workspace, L.inst_keys[0]), at<uint8_t>(workspace, L.inst_keys[1])};
+  const int key_bytes = L.inst_key_bytes;
   uint32_t* ivals[2] = {at<uint32_t>(workspace, L.inst_vals[0]), at<uint32_t>(workspace, L.inst_vals[1])};
   uint2* ranges = at<uint2>(workspace, L.ranges);
   uint32_t* scratch = at<uint32_t>(workspace, L.scratch);
@@ -423,14 +430,21 @@ fgs_status fgs_rasterize_forward_batch(const fgs_gaussians* g, const fgs_camera*
   if (inst > 0 && nvis > 0) {
     FGS_TIMED("duplicate", hs,
               launch_duplicate(vis_ids[vis_final], d_vis, nvis, offsets, rec, vs, n, st->tile, cap, ikeys[0],
-                               ivals[0], hs),
+                               key_bytes, ivals[0], hs),
               "duplicate");
     int inst_final = 0;
-    FGS_TIMED("tile_sort", hs,
-              radix_sort_pairs(ikeys, ivals, inst, d_sorted, 0, tile_key_bits(tiles), scratch, &inst_final, hs),
-              "tile sort");
+    const int bits = tile_key_bits(tiles);
+    if (key_bytes == 2) {
+      uint16_t* k16[2] = {static_cast<uint16_t*>(ikeys[0]), static_cast<uint16_t*>(ikeys[1])};
+      FGS_TIMED("tile_sort", hs, radix_sort_pairs16(k16, ivals, inst, d_sorted, 0, bits, scratch, &inst_final, hs),
+                "tile sort");
+    } else {
+      uint32_t* k32[2] = {static_cast<uint32_t*>(ikeys[0]), static_cast<uint32_t*>(ikeys[1])};
+      FGS_TIMED("tile_sort", hs, radix_sort_pairs(k32, ivals, inst, d_sorted, 0, bits, scratch, &inst_final, hs),
+                "tile sort");
+    }
     if (inst_final != L.inst_final) return fail(FGS_ERR_HIP, "internal: tile sort buffer mismatch");
-    FGS_HIP(launch_tile_ranges(ikeys[inst_final], inst, d_sorted, tiles, ranges, hs), "tile ranges");
+    FGS_HIP(launch_tile_ranges(ikeys[inst_final], key_bytes, inst, d_sorted, tiles, ranges, hs), "tile ranges");
   }
   FGS_TIMED("blend_forward", hs,
             launch_blend_forward(ranges, ivals[L.inst_final], rec, vs, sd, st->tile, images, t_finals, lasts, hs),

@@ -14,6 +14,10 @@ constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 constexpr int kWave = 64;
 constexpr int kScanItems = 16;       // items per thread in scan / radix kernels
 constexpr int kScanTile = kBlock * kScanItems;
+// pairs per thread of the 16-bit-key sort (a build-time tuning constant)
+#ifndef FGS_SORT16_ITEMS
+#define FGS_SORT16_ITEMS 16
+#endif
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kNumXcd = 8;           // MI355X: 8 XCDs, workgroups dealt round-robin
@@ -330,6 +334,9 @@ size_t radix_scratch_words(uint64_t n);
 // starts in keys[0]/vals[0]; returns (in *final_buf) the buffer holding the result.
 hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
                             int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s);
+// The same for 16-bit keys (begin_bit < end_bit <= 16).
+hipError_t radix_sort_pairs16(uint16_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
+                              int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s);
 
 // Per-Gaussian splat record: four float4 (64 bytes, so a gather of any three
 // of them touches one cache line):
@@ -366,11 +373,13 @@ hipError_t launch_stats(const uint4* partials, uint32_t nb, uint64_t cap, uint32
 hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth_key, uint32_t n,
                                   const uint32_t* pos, uint32_t* vis_keys, uint32_t* vis_ids,
                                   hipStream_t s);
+// Tile keys are written as uint16 (key_bytes 2: every global tile id and the
+// out-of-range id `tiles` fit) or uint32 (key_bytes 4).
 hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uint32_t n, const uint32_t* offsets,
                             const float4* rec, const ViewSet& vs, uint32_t n_gauss, int tile, uint32_t cap,
-                            uint32_t* keys, uint32_t* vals, hipStream_t s);
+                            void* keys, int key_bytes, uint32_t* vals, hipStream_t s);
 // Ranges of the first min(*d_count, n) (or n) sorted keys.
-hipError_t launch_tile_ranges(const uint32_t* keys, uint32_t n, const uint32_t* d_count, uint32_t tiles,
+hipError_t launch_tile_ranges(const void* keys, int key_bytes, uint32_t n, const uint32_t* d_count, uint32_t tiles,
                               uint2* ranges, hipStream_t s);
 // One wave per global tile of all views (tile size 8, 16 or 32); images,
 // t_finals, lasts and dl_dimages hold the views one after another.

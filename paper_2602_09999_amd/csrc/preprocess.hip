@@ -322,12 +322,13 @@ hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth
 // `cap`.
 // Entries are (view, Gaussian) indices j = v n_gauss + i; the key of an
 // instance is its global tile id tile_base[v] + ty tiles_x(v) + tx.
+template <typename KT>
 __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict__ vis_ids,
                                                       const uint32_t* __restrict__ d_nvis, uint32_t n,
                                                       const uint32_t* __restrict__ offsets,
                                                       const float4* __restrict__ rec, ViewSet vs,
                                                       uint32_t n_gauss, int tile, uint32_t cap,
-                                                      uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                                                      KT* __restrict__ keys, uint32_t* __restrict__ vals) {
   __shared__ uint32_t s_owner[kBlock / kWave][kWave];
   const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
   const uint32_t nv = min(*d_nvis, n);
@@ -364,7 +365,7 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
         const uint32_t o_krow = __shfl(krow, owner, kWave);
         const uint32_t slot = o_off + rank;
         if (keep && slot < o_end) {
-          keys[slot] = o_kbase + (uint32_t)ty * o_krow + (uint32_t)tx;
+          keys[slot] = (KT)(o_kbase + (uint32_t)ty * o_krow + (uint32_t)tx);
           vals[slot] = o_gid;
         }
       });
@@ -372,55 +373,68 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
   // loop never runs; it keeps every slot defined (an out-of-range tile id
   // that the range kernel ignores) should the two ever disagree.
   for (uint32_t slot = off + written; p < nv && slot < end; ++slot) {
-    keys[slot] = tiles;
+    keys[slot] = (KT)tiles;
     vals[slot] = gid;
   }
 }
 
 hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uint32_t n, const uint32_t* offsets,
                             const float4* rec, const ViewSet& vs, uint32_t n_gauss, int tile, uint32_t cap,
-                            uint32_t* keys, uint32_t* vals, hipStream_t s) {
+                            void* keys, int key_bytes, uint32_t* vals, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  k_duplicate<<<ceil_div(n, kBlock), kBlock, 0, s>>>(vis_ids, d_nvis, n, offsets, rec, vs, n_gauss, tile, cap, keys,
-                                                     vals);
+  if (key_bytes == 2)
+    k_duplicate<uint16_t><<<ceil_div(n, kBlock), kBlock, 0, s>>>(vis_ids, d_nvis, n, offsets, rec, vs, n_gauss, tile,
+                                                                 cap, static_cast<uint16_t*>(keys), vals);
+  else
+    k_duplicate<uint32_t><<<ceil_div(n, kBlock), kBlock, 0, s>>>(vis_ids, d_nvis, n, offsets, rec, vs, n_gauss, tile,
+                                                                 cap, static_cast<uint32_t*>(keys), vals);
   return hipGetLastError();
 }
 
-// Start and end of each tile's run in the sorted keys.  A thread takes four
-// consecutive keys with one 16-byte load (the key buffer is 256-byte aligned);
-// the neighbours on either side come from cached loads.  Keys >= tiles (the
-// duplicate kernel's padding) are ignored.
-__global__ __launch_bounds__(kBlock) void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t n,
+// Start and end of each tile's run in the sorted keys.  A thread takes 16
+// bytes of consecutive keys with one load (the key buffer is 256-byte
+// aligned); a run boundary is where a key differs from its neighbour.
+template <typename KT>
+__global__ __launch_bounds__(kBlock) void k_tile_ranges(const KT* __restrict__ keys, uint32_t n,
                                                         const uint32_t* __restrict__ d_count, uint32_t tiles,
                                                         uint2* __restrict__ ranges) {
+  constexpr int V = 16 / (int)sizeof(KT);
+  constexpr uint32_t kNone = 0xffffffffu;  // differs from every key
   const uint32_t count = d_count ? min(*d_count, n) : n;
-  const uint32_t i0 = (blockIdx.x * kBlock + threadIdx.x) * 4u;
+  const uint32_t i0 = (blockIdx.x * kBlock + threadIdx.x) * (uint32_t)V;
   if (i0 >= count) return;
-  uint32_t k[4];
-  if (i0 + 4 <= count) {
-    const uint4 v = *reinterpret_cast<const uint4*>(keys + i0);
-    k[0] = v.x; k[1] = v.y; k[2] = v.z; k[3] = v.w;
+  uint32_t k[V];
+  if (i0 + V <= count) {
+    struct alignas(16) Vec { KT k[V]; };
+    const Vec v = *reinterpret_cast<const Vec*>(keys + i0);
+#pragma unroll
+    for (int j = 0; j < V; ++j) k[j] = v.k[j];
   } else {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) k[j] = (i0 + j < count) ? keys[i0 + j] : 0xffffffffu;
+    for (int j = 0; j < V; ++j) k[j] = (i0 + j < count) ? (uint32_t)keys[i0 + j] : kNone;
   }
-  const uint32_t prev = (i0 == 0) ? 0xffffffffu : keys[i0 - 1];
-  const uint32_t next = (i0 + 4 < count) ? keys[i0 + 4] : 0xffffffffu;
+  const uint32_t prev = (i0 == 0) ? kNone : (uint32_t)keys[i0 - 1];
+  const uint32_t next = (i0 + V < count) ? (uint32_t)keys[i0 + V] : kNone;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < V; ++j) {
     const uint32_t kj = k[j];
     if (kj >= tiles) continue;
     const uint32_t before = j ? k[j - 1] : prev;
-    const uint32_t after = j < 3 ? k[j + 1] : next;
+    const uint32_t after = j < V - 1 ? k[j + 1] : next;
     if (before != kj) ranges[kj].x = i0 + j;
     if (after != kj) ranges[kj].y = i0 + j + 1;
   }
 }
 
-hipError_t launch_tile_ranges(const uint32_t* keys, uint32_t n, const uint32_t* d_count, uint32_t tiles,
+hipError_t launch_tile_ranges(const void* keys, int key_bytes, uint32_t n, const uint32_t* d_count, uint32_t tiles,
                               uint2* ranges, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  k_tile_ranges<<<ceil_div(ceil_div(n, 4), kBlock), kBlock, 0, s>>>(keys, n, d_count, tiles, ranges);
+  if (key_bytes == 2)
+    k_tile_ranges<uint16_t><<<ceil_div(ceil_div(n, 8), kBlock), kBlock, 0, s>>>(static_cast<const uint16_t*>(keys), n,
+                                                                                d_count, tiles, ranges);
+  else
+    k_tile_ranges<uint32_t><<<ceil_div(ceil_div(n, 4), kBlock), kBlock, 0, s>>>(static_cast<const uint32_t*>(keys), n,
+                                                                                d_count, tiles, ranges);
   return hipGetLastError();
 }
 

@@ -1,5 +1,5 @@
-// Device-wide exclusive scan and stable LSD radix sort of (u32 key, u32 value)
-// pairs for gfx950.  Both serve the compaction and the two sorts of the
+// Device-wide exclusive scan and stable LSD radix sort of (u32 or u16 key,
+// u32 value) pairs for gfx950.  Both serve the compaction and the two sorts of the
 // separate-sorting scheme (Sec. 3.2 "Sorting", App. B.2): a 32-bit depth sort
 // of the visible Gaussians, then a stable sort of the instances by tile.
 //
@@ -144,24 +144,49 @@ hipError_t scan_u32(ScanMode mode, const uint32_t* in, const uint32_t* idx, cons
 //            stable block-local ranking and the coalesced write-out
 // The bits of a sort are split evenly over ceil(bits / 8) passes, so a 13-bit
 // tile key takes 7 + 6 bits: fewer, longer runs per digit in each block.
+// Keys are 32-bit, or 16-bit for tile ids that fit (half the key traffic);
+// values are 32-bit.  A block sorts kBlock * ITEMS pairs.
 // ----------------------------------------------------------------------------
-template <int RB>
-__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restrict__ keys, uint32_t n,
+template <typename KT>
+struct alignas(16) KeyVec {  // one 16-byte load of consecutive keys
+  static constexpr int V = 16 / (int)sizeof(KT);
+  KT k[V];
+};
+
+template <int RB, typename KT, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const KT* __restrict__ keys, uint32_t n,
                                                        const uint32_t* __restrict__ d_count, int shift,
                                                        uint32_t* __restrict__ hist, uint32_t nb) {
   constexpr int R = 1 << RB;
-  __shared__ uint32_t h[R];
-  if (threadIdx.x < R) h[threadIdx.x] = 0;
+  constexpr int kWaves = kBlock / kWave;
+  constexpr int V = KeyVec<KT>::V;
+  static_assert(ITEMS % V == 0, "whole 16-byte loads per thread");
+  // one histogram per wave: four times fewer lanes contend for a counter
+  __shared__ uint32_t h[kWaves][R];
+  for (int i = threadIdx.x; i < kWaves * R; i += kBlock) (&h[0][0])[i] = 0;
   __syncthreads();
   const uint32_t count = d_count ? min(*d_count, n) : n;
-  const uint32_t base = blockIdx.x * kScanTile;
+  const uint32_t base = blockIdx.x * (uint32_t)(kBlock * ITEMS);
+  uint32_t* hw = h[threadIdx.x / kWave];
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const uint32_t i = base + k * kBlock + threadIdx.x;
-    if (i < count) atomicAdd(&h[(keys[i] >> shift) & (R - 1)], 1u);
+  for (int k = 0; k < ITEMS / V; ++k) {
+    const uint32_t i0 = base + (uint32_t)(k * kBlock + threadIdx.x) * V;
+    if (i0 + V <= count) {
+      const KeyVec<KT> kv = *reinterpret_cast<const KeyVec<KT>*>(keys + i0);  // 16-byte aligned: base is
+#pragma unroll
+      for (int j = 0; j < V; ++j) atomicAdd(&hw[(kv.k[j] >> shift) & (R - 1)], 1u);
+    } else {
+      for (int j = 0; j < V; ++j)
+        if (i0 + j < count) atomicAdd(&hw[(keys[i0 + j] >> shift) & (R - 1)], 1u);
+    }
   }
   __syncthreads();
-  if (threadIdx.x < R) hist[(size_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+  for (int d = threadIdx.x; d < R; d += kBlock) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) t += h[w][d];
+    hist[(size_t)d * nb + blockIdx.x] = t;
+  }
 }
 
 // Workgroup d: exclusive scan of hist[d][0..nb) in place; totals[d] = its sum.
@@ -181,30 +206,33 @@ __global__ __launch_bounds__(kBlock) void k_radix_colscan(uint32_t* __restrict__
   if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
-// Scatter of one pass.  Each workgroup ranks its 4096 keys stably (wave
-// ballots over the RB digit bits + per-wave digit counters), places them in
-// LDS in (digit, input order) order, and writes them out so that consecutive
-// threads store consecutive addresses of each digit's run.
-template <int RB>
-__global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __restrict__ keys_in,
+// Scatter of one pass.  Each workgroup ranks its kBlock * ITEMS keys stably
+// (wave ballots over the RB digit bits + per-wave digit counters), places them
+// in LDS in (digit, input order) order, and writes them out so that
+// consecutive threads store consecutive addresses of each digit's run.  With
+// keys_out == NULL (the last pass of a sort whose keys are not needed) only
+// the values are written.
+template <int RB, typename KT, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT* __restrict__ keys_in,
                                                           const uint32_t* __restrict__ vals_in,
-                                                          uint32_t* __restrict__ keys_out,
+                                                          KT* __restrict__ keys_out,
                                                           uint32_t* __restrict__ vals_out, uint32_t n,
                                                           const uint32_t* __restrict__ d_count, int shift,
                                                           const uint32_t* __restrict__ hist_scan,
                                                           const uint32_t* __restrict__ totals, uint32_t nb) {
   constexpr int R = 1 << RB;
   constexpr int kWaves = kBlock / kWave;
+  constexpr uint32_t kTile = kBlock * ITEMS;
   __shared__ uint32_t wcnt[kWaves][R];
   __shared__ uint32_t gdelta[R];  // global start of the digit minus its block-local start (mod 2^32)
   __shared__ uint32_t lstart[R];  // block-local start of each digit
-  __shared__ uint32_t s_key[kScanTile];
-  __shared__ uint32_t s_val[kScanTile];
+  __shared__ KT s_key[kTile];
+  __shared__ uint32_t s_val[kTile];
   __shared__ uint32_t scan_lds[kBlock / kWave];
   const uint32_t count = d_count ? min(*d_count, n) : n;
-  const uint32_t base = blockIdx.x * kScanTile;
+  const uint32_t base = blockIdx.x * kTile;
   if (base >= count) return;  // uniform for the whole workgroup
-  const uint32_t in_block = min((uint32_t)kScanTile, count - base);
+  const uint32_t in_block = min(kTile, count - base);
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const bool digit_thread = threadIdx.x < R;
@@ -222,18 +250,22 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
   }
   __syncthreads();
 
-  // Wave w owns items [base + w*1024, base + (w+1)*1024), visited 64 at a time
-  // in index order, so (wave, step, lane) order is the input order.
-  const uint32_t wbase = base + wave * (kWave * kScanItems);
+  // Wave w owns items [base + w*64*ITEMS, base + (w+1)*64*ITEMS), visited 64
+  // at a time in index order, so (wave, step, lane) order is the input order.
+  const uint32_t wbase = base + wave * (kWave * ITEMS);
   const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   volatile uint32_t* my_cnt = wcnt[wave];
-  uint32_t key[kScanItems], val[kScanItems], rank[kScanItems];
+  uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
+  for (int k = 0; k < ITEMS; ++k) {
     const uint32_t i = wbase + k * kWave + lane;
     const bool valid = i < count;
-    key[k] = valid ? keys_in[i] : 0u;
+    key[k] = valid ? (uint32_t)keys_in[i] : 0u;
     val[k] = valid ? vals_in[i] : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const bool valid = wbase + k * kWave + lane < count;
     const uint32_t d = (key[k] >> shift) & (R - 1);
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -269,54 +301,73 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
+  for (int k = 0; k < ITEMS; ++k) {
     const uint32_t i = wbase + k * kWave + lane;
     if (i < count) {
       const uint32_t d = (key[k] >> shift) & (R - 1);
       const uint32_t lp = lstart[d] + wcnt[wave][d] + rank[k];
-      s_key[lp] = key[k];
+      s_key[lp] = (KT)key[k];
       s_val[lp] = val[k];
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
+  for (int k = 0; k < ITEMS; ++k) {
     const uint32_t j = k * kBlock + threadIdx.x;
     if (j < in_block) {
       const uint32_t kk = s_key[j];
       const uint32_t d = (kk >> shift) & (R - 1);
       const uint32_t pos = gdelta[d] + j;  // = gbase[d] + (j - lstart[d])
-      keys_out[pos] = kk;
+      if (keys_out) keys_out[pos] = (KT)kk;
       vals_out[pos] = s_val[j];
     }
   }
 }
 
+// Pairs per block of the sorts: the 16-bit tile sort takes larger blocks
+// (longer digit runs per block, so fuller write-out lines) in the same LDS.
+template <typename KT>
+struct SortShape;
+template <>
+struct SortShape<uint32_t> {
+  static constexpr int kItems = kScanItems;
+};
+template <>
+struct SortShape<uint16_t> {
+  static constexpr int kItems = FGS_SORT16_ITEMS;
+};
+
 size_t radix_scratch_words(uint64_t n) {
-  const uint64_t nb = (n + kScanTile - 1) / kScanTile;
+  // the smallest block size of any sort bounds the number of blocks
+  constexpr uint64_t tile = (uint64_t)kBlock * (SortShape<uint32_t>::kItems < SortShape<uint16_t>::kItems
+                                                    ? SortShape<uint32_t>::kItems
+                                                    : SortShape<uint16_t>::kItems);
+  const uint64_t nb = (n + tile - 1) / tile;
   return round_words((uint64_t)kRadix * nb) + round_words(kRadix);
 }
 
-template <int RB>
-static hipError_t radix_pass(uint32_t* keys_in, uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
+template <int RB, typename KT>
+static hipError_t radix_pass(const KT* keys_in, const uint32_t* vals_in, KT* keys_out, uint32_t* vals_out,
                              uint32_t n, const uint32_t* d_count, int shift, uint32_t* hist, uint32_t* totals,
                              uint32_t nb, hipStream_t s) {
-  k_radix_hist<RB><<<nb, kBlock, 0, s>>>(keys_in, n, d_count, shift, hist, nb);
+  constexpr int kItems = SortShape<KT>::kItems;
+  k_radix_hist<RB, KT, kItems><<<nb, kBlock, 0, s>>>(keys_in, n, d_count, shift, hist, nb);
   k_radix_colscan<<<1u << RB, kBlock, 0, s>>>(hist, nb, totals);
-  k_radix_scatter<RB><<<nb, kBlock, 0, s>>>(keys_in, vals_in, keys_out, vals_out, n, d_count, shift, hist,
-                                            totals, nb);
+  k_radix_scatter<RB, KT, kItems><<<nb, kBlock, 0, s>>>(keys_in, vals_in, keys_out, vals_out, n, d_count, shift,
+                                                        hist, totals, nb);
   return hipGetLastError();
 }
 
-hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
-                            int begin_bit, int end_bit, uint32_t* scratch, int* final_buf,
-                            hipStream_t s) {
+template <typename KT>
+static hipError_t radix_sort_impl(KT* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
+                                  int begin_bit, int end_bit, bool keep_keys, uint32_t* scratch, int* final_buf,
+                                  hipStream_t s) {
   int cur = 0;
   if (n == 0 || end_bit <= begin_bit) {
     *final_buf = 0;
     return hipSuccess;
   }
-  const uint32_t nb = ceil_div(n, kScanTile);
+  const uint32_t nb = ceil_div(n, (uint64_t)kBlock * SortShape<KT>::kItems);
   uint32_t* hist = scratch;
   uint32_t* totals = scratch + round_words((size_t)kRadix * nb);
   const int bits = end_bit - begin_bit;
@@ -325,16 +376,17 @@ hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], uint32_t n, co
   for (int p = 0; p < passes; ++p) {
     // the remaining bits, split evenly over the remaining passes
     const int rb = (end_bit - shift + (passes - p) - 1) / (passes - p);
+    KT* kout = (p + 1 == passes && !keep_keys) ? nullptr : keys[cur ^ 1];
     hipError_t e = hipSuccess;
     switch (rb) {
-      case 1: e = radix_pass<1>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
-      case 2: e = radix_pass<2>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
-      case 3: e = radix_pass<3>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
-      case 4: e = radix_pass<4>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
-      case 5: e = radix_pass<5>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
-      case 6: e = radix_pass<6>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
-      case 7: e = radix_pass<7>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
-      default: e = radix_pass<8>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
+      case 1: e = radix_pass<1, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
+      case 2: e = radix_pass<2, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
+      case 3: e = radix_pass<3, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
+      case 4: e = radix_pass<4, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
+      case 5: e = radix_pass<5, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
+      case 6: e = radix_pass<6, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
+      case 7: e = radix_pass<7, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
+      default: e = radix_pass<8, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
     }
     if (e != hipSuccess) return e;
     shift += rb;
@@ -342,6 +394,16 @@ hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], uint32_t n, co
   }
   *final_buf = cur;
   return hipSuccess;
+}
+
+hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
+                            int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s) {
+  return radix_sort_impl<uint32_t>(keys, vals, n, d_count, begin_bit, end_bit, true, scratch, final_buf, s);
+}
+
+hipError_t radix_sort_pairs16(uint16_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
+                              int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s) {
+  return radix_sort_impl<uint16_t>(keys, vals, n, d_count, begin_bit, end_bit, true, scratch, final_buf, s);
 }
 
 }  // namespace fgs

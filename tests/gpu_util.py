@@ -34,7 +34,9 @@ def forward(scene, cam, capacity: Optional[int] = None, settings=None):
 def sorted_instances(rz: B.Rasterizer):
     lay = rz.layout()
     I = rz.last_stats["n_instances"]
-    keys = rz.view("inst_keys", I, index=lay.inst_final).cpu().numpy().view(np.uint32)
+    kdt = torch.int16 if lay.inst_key_bytes == 2 else torch.int32
+    keys = rz.view("inst_keys", I, dtype=kdt, index=lay.inst_final).cpu().numpy()
+    keys = keys.view(np.uint16 if lay.inst_key_bytes == 2 else np.uint32).astype(np.uint32)
     vals = rz.view("inst_vals", I, index=lay.inst_final).cpu().numpy().view(np.uint32)
     tiles = int(lay.total_tiles)
     ranges = rz.view("ranges", 2 * tiles).cpu().numpy().view(np.uint32).reshape(tiles, 2)

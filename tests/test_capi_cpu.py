@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported_and_bound(lib):
     for name in names:
         assert hasattr(lib, name), name
         assert name in L.SIGNATURES, name
-    assert lib.fgs_abi_version() == 5
+    assert lib.fgs_abi_version() == 6
 
 
 def test_default_settings_match_the_paper(lib):
@@ -48,7 +48,7 @@ def test_workspace_size_and_layout(lib):
     cam = S.workload_camera("c1")
     a = B.workspace_size(10_000, cam, instance_capacity=100_000)
     b = B.workspace_size(10_000, cam, instance_capacity=200_000)
-    assert b - a >= 4 * 4 * 100_000
+    assert b - a >= (2 * 2 + 2 * 4) * 100_000  # two 16-bit key and two value buffers
     lay = B.workspace_layout(10_000, cam, instance_capacity=100_000)
     offs = [lay.rec, lay.n_tiles, lay.depth_key, lay.counters, lay.vis_keys[0], lay.vis_ids[0],
             lay.inst_offsets, lay.inst_keys[0], lay.inst_vals[0], lay.ranges, lay.accum, lay.touched, lay.scratch]
@@ -56,6 +56,7 @@ def test_workspace_size_and_layout(lib):
     assert all(o % 256 == 0 for o in offs)
     assert lay.total == a and lay.tiles_x == 16 and lay.tiles_y == 16
     assert lay.inst_final == 1  # 256 tiles -> 8 key bits -> one radix pass
+    assert lay.inst_key_bytes == 2
     lay2 = B.workspace_layout(10, S.workload_camera("c3"), instance_capacity=10)
     assert (lay2.tiles_x, lay2.tiles_y) == (100, 67) and lay2.inst_final == 0
 

@@ -70,15 +70,27 @@ def test_tile_sizes_keys_image_gradients(tile, case):
         assert e <= GRAD_TOL, (k, e)
 
 
-@pytest.mark.parametrize("tile", [16, 8])
-def test_batch_equals_single_views(tile):
+def wide_views():
+    """Three near-1080p cameras: at tile 8 the views hold >= 65536 tiles in
+    all, so the batch sorts 32-bit tile keys while each view alone sorts
+    16-bit ones."""
+    cams = S.uniform_sphere_cameras(3, seed=12, w_range=(1900, 1920), h_range=(1060, 1080))
+    return [c.copy(fx=0.9 * c.width, fy=0.9 * c.width) for c in cams]
+
+
+@pytest.mark.parametrize("tile,views", [(16, "small"), (8, "small"), (8, "wide")])
+def test_batch_equals_single_views(tile, views):
     sc = S.batch_scene(20_000, 3)
-    cams = small_views()
+    cams = small_views() if views == "small" else wide_views()
     say("batch", [(c.width, c.height) for c in cams], "tile", tile)
     st = B.default_settings(tile=tile)
     params = to_gpu(sc)
     br = B.BatchRasterizer(cams, settings=st)
     images, t_finals, lasts = br.forward(params)
+    lay = br.layout()
+    say("  global tiles", lay.total_tiles, "key bytes", lay.inst_key_bytes)
+    assert lay.inst_key_bytes == (4 if lay.total_tiles >= 65536 else 2)
+    assert (views == "wide") == (lay.inst_key_bytes == 4)
     imgs, tfs, lss = br.split(images, 3), br.split(t_finals, 1), br.split(lasts, 1)
     dls = [S.make_dl_dimage(c.height, c.width, seed=20 + k) for k, c in enumerate(cams)]
     gb = br.backward(params, torch.cat([d.reshape(-1) for d in dls]).cuda())
@@ -86,6 +98,7 @@ def test_batch_equals_single_views(tile):
     total = 0
     for k, cam in enumerate(cams):
         rz, p1, image, t_final, last = forward(sc, cam, settings=st)
+        assert rz.layout().inst_key_bytes == 2
         assert torch.equal(imgs[k], image), k
         assert torch.equal(tfs[k], t_final), k
         assert torch.equal(lss[k], last), k
