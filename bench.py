@@ -375,8 +375,8 @@ def workload_counts(r, w, dev):
     log("tile walk p50/p90/p99/max", [int(x) for x in torch.quantile(walks.double(), q)],
         "list length p50/p90/p99/max", [int(x) for x in torch.quantile(lens.double(), q)],
         "tiles walking their whole list", int(((walks == lens) & (lens > 0)).sum()))
-    accum = rz.view("accum", 9 * n, dtype=torch.float32).view(9, n)
-    return {"i_proc": int(walks.sum()), "n_touched": int((accum != 0).any(0).sum()),
+    accum = rz.view("accum", 9 * n, dtype=torch.float32).view(n, 9)
+    return {"i_proc": int(walks.sum()), "n_touched": int((accum != 0).any(1).sum()),
             "visible": rz.last_stats.get("n_visible"), "instances": rz.last_stats.get("n_instances")}
 
 

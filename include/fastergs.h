@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define FGS_ABI_VERSION 6
+#define FGS_ABI_VERSION 7
 
 typedef enum fgs_status {
   FGS_OK = 0,
@@ -157,7 +157,8 @@ typedef struct fgs_forward_stats {
  *                           sorted in [inst_final].  Keys are 16-bit when
  *                           total_tiles < 65536, else 32-bit.
  *   ranges     uint32[2*tiles] [start, end) of each tile's list
- *   accum      float[9][n]  backward: dL/d(mu2D.x, mu2D.y, a, b, c, opacity, r, g, b)
+ *   accum      float[n][9]  backward: dL/d(mu2D.x, mu2D.y, a, b, c, opacity, r, g, b),
+ *                           one row of nine per (view, Gaussian) entry
  *   touched    uint8[ceil(n/4)]  fused backward + Adam: bit j of byte k set when
  *                           Gaussian 4k+j received a gradient */
 typedef struct fgs_layout {

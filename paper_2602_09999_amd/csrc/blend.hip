@@ -137,16 +137,16 @@ __global__ __launch_bounds__(kWave) void k_blend_fwd(const uint2* __restrict__ r
       const float cr = bcast(cur.r2.x, k), cg = bcast(cur.r2.y, k), cb = bcast(cur.r2.z, k);
       bool any = false;
 #pragma unroll
-      for (int r = 0; r < kRows; ++r) {  // branch-free: a skipped fragment has alpha 0
+      for (int r = 0; r < kRows; ++r) {
         float G;
         const float alpha = pixel_alpha(sp, ax, bx, fy[r] - sp.my, st.alpha_max, G);
         const bool blend = live[r] && alpha >= st.alpha_min;
-        const float a = blend ? alpha : 0.0f;
+        const float a = blend ? alpha : 0.0f;  // branch-free: a skipped fragment has alpha 0
         const float wgt = a * T[r];
         C0[r] = fmaf(wgt, cr, C0[r]);
         C1[r] = fmaf(wgt, cg, C1[r]);
         C2[r] = fmaf(wgt, cb, C2[r]);
-        T[r] = T[r] * (1.0f - a);
+        T[r] -= wgt;  // T (1 - alpha)
         lpos[r] = blend ? base - beg + (uint32_t)k + 1u : lpos[r];
         live[r] = live[r] && !(T[r] < st.t_min);
         any |= live[r];
@@ -247,7 +247,7 @@ __device__ __forceinline__ float wave_reduce1(float x) {
 
 constexpr int kGrad = 9;  // dL/d(mu2D.x, mu2D.y, a, b, c, opacity, r, g, b)
 
-// accum: [9][n] with n the (view, Gaussian) index range of the record.
+// accum: [n][9] with n the (view, Gaussian) index range of the record.
 template <int TILE>
 __global__ __launch_bounds__(kWave) void k_blend_bwd(const uint2* __restrict__ ranges,
                                                      const uint32_t* __restrict__ vals,
@@ -269,8 +269,10 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const uint2* __restrict__ r
   const int px = tx * TILE + (lane % TILE);
   const float fx = (float)px + 0.5f;
   const size_t hw = (size_t)cam.width * cam.height;
-  float fy[kRows], gc0[kRows], gc1[kRows], gc2[kRows], gF[kRows];
-  float T[kRows], gS[kRows];
+  float fy[kRows], gc0[kRows], gc1[kRows], gc2[kRows];
+  // R = g . (C - S_i): the upstream gradient dotted with the part of the final
+  // colour C (background included) not yet blended after fragment i
+  float T[kRows], R[kRows];
   uint32_t my_last[kRows];
   uint32_t walk = 0;
 #pragma unroll
@@ -278,15 +280,14 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const uint2* __restrict__ r
     const int py = ty * TILE + lane / TILE + kStep * r;
     fy[r] = (float)py + 0.5f;
     T[r] = 1.0f;
-    gS[r] = 0.0f;  // g . S_i, the upstream gradient dotted with the colour blended so far
-    gc0[r] = gc1[r] = gc2[r] = gF[r] = 0.0f;
+    R[r] = 0.0f;
+    gc0[r] = gc1[r] = gc2[r] = 0.0f;
     my_last[r] = 0;
     if (px < cam.width && py < cam.height) {
       const size_t pix = (size_t)py * cam.width + px;
       my_last[r] = last[pix];
       gc0[r] = dl_dimage[pix]; gc1[r] = dl_dimage[hw + pix]; gc2[r] = dl_dimage[2 * hw + pix];
-      // g . C with C the final pixel colour (including T_final * bg)
-      gF[r] = gc0[r] * image[pix] + gc1[r] * image[hw + pix] + gc2[r] * image[2 * hw + pix];
+      R[r] = gc0[r] * image[pix] + gc1[r] * image[hw + pix] + gc2[r] * image[2 * hw + pix];
     }
     walk = max(walk, my_last[r]);
   }
@@ -311,52 +312,59 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const uint2* __restrict__ r
       const float cr = bcast(cur.r2.x, k), cg = bcast(cur.r2.y, k), cb = bcast(cur.r2.z, k);
       const float dx = fx - sp.mx;
       const float ax = sp.a2 * dx * dx, bx = sp.b2 * dx;
-      // per lane, summed over its four pixels: dL/dG * o (= dL/dpower) times
-      // dx, dy, dx^2, dx dy, dy^2; dL/dG * G (= dL/do); and the colour weights
-      float sP = 0.f, sQ = 0.f, sXX = 0.f, sXY = 0.f, sYY = 0.f, sO = 0.f, w0 = 0.f, w1 = 0.f, w2 = 0.f;
+      // Per lane, over its pixels: dG = dL/dalpha * G for the blended,
+      // uncapped ones (dL/do = sum dG; dL/dpower = o dG with power =
+      // -(a dx^2 + 2 b dx dy + c dy^2) / 2), its dy and dy^2 moments (dx is the
+      // lane's own constant, so the dx moments follow from sO), and the colour
+      // weights.
+      float sO = 0.f, sQ = 0.f, sYY = 0.f, w0 = 0.f, w1 = 0.f, w2 = 0.f;
       bool any = false;
-      const float dxx = dx * dx;
 #pragma unroll
-      for (int r = 0; r < kRows; ++r) {  // branch-free: a fragment that is not blended has alpha 0
+      for (int r = 0; r < kRows; ++r) {
         const float dy = fy[r] - sp.my;
         float G;
         const float alpha = pixel_alpha(sp, ax, bx, dy, st.alpha_max, G);
         const bool blend = pos < my_last[r] && alpha >= st.alpha_min;
-        any |= blend;
+        // a strip of the tile that no pixel of blends the fragment keeps its
+        // state unchanged: skip it (a wave-uniform branch)
+        if (__ballot(blend) == 0ull) continue;
+        any = true;
         const float a = blend ? alpha : 0.0f;
         const float wgt = a * T[r];
         w0 = fmaf(wgt, gc0[r], w0);
         w1 = fmaf(wgt, gc1[r], w1);
         w2 = fmaf(wgt, gc2[r], w2);
         const float gcol = gc0[r] * cr + gc1[r] * cg + gc2[r] * cb;
-        gS[r] = fmaf(wgt, gcol, gS[r]);
-        // dC/dalpha_i . g = T_i (g . c_i) - (g . C - g . S_i) / (1 - alpha_i)
-        const float dalpha = fmaf(-(gF[r] - gS[r]), __builtin_amdgcn_rcpf(1.0f - alpha), T[r] * gcol);
-        T[r] = T[r] * (1.0f - a);
+        R[r] = fmaf(-wgt, gcol, R[r]);
+        // dC/dalpha_i . g = T_i (g . c_i) - g . (C - S_i) / (1 - alpha_i)
+        const float dalpha = fmaf(-R[r], __builtin_amdgcn_rcpf(1.0f - alpha), T[r] * gcol);
+        T[r] -= wgt;
         // a capped alpha carries no gradient to o or G
-        const float dGG = (blend && !(sp.o * G > st.alpha_max)) ? dalpha * G : 0.0f;
-        sO += dGG;
-        const float dpow = dGG * sp.o;  // dL/dpower, power = -(a dx^2 + 2 b dx dy + c dy^2) / 2
-        sP = fmaf(dpow, dx, sP);
-        sQ = fmaf(dpow, dy, sQ);
-        sXX = fmaf(dpow, dxx, sXX);
-        sXY = fmaf(dpow, dx * dy, sXY);
-        sYY = fmaf(dpow, dy * dy, sYY);
+        const float dG = (blend && !(sp.o * G > st.alpha_max)) ? dalpha * G : 0.0f;
+        sO += dG;
+        const float dyG = dG * dy;
+        sQ += dyG;
+        sYY = fmaf(dyG, dy, sYY);
       }
+      if (!any) continue;  // no pixel of the tile blends this fragment
+      // the lane's nine terms, the opacity factor of the first five applied
+      // after the wave sum
+      const float dxO = dx * sO;
       float v[kGrad];
-      v[0] = sp.a * sP + sp.b * sQ;   // dL/dmu2D.x
-      v[1] = sp.b * sP + sp.c * sQ;   // dL/dmu2D.y
-      v[2] = -0.5f * sXX;             // dL/da
-      v[3] = -sXY;                    // dL/db
-      v[4] = -0.5f * sYY;             // dL/dc
-      v[5] = sO;                      // dL/do
+      v[0] = fmaf(sp.a, dxO, sp.b * sQ);  // dL/dmu2D.x / o
+      v[1] = fmaf(sp.b, dxO, sp.c * sQ);  // dL/dmu2D.y / o
+      v[2] = -0.5f * dx * dxO;            // dL/da / o
+      v[3] = -dx * sQ;                    // dL/db / o
+      v[4] = -0.5f * sYY;                 // dL/dc / o
+      v[5] = sO;                          // dL/do
       v[6] = w0; v[7] = w1; v[8] = w2;
-      if (__ballot(any) == 0ull) continue;  // no pixel of the tile blends this fragment
-      const float r8 = wave_reduce8(v, lane);
+      const float r8 = wave_reduce8(v, lane) * (wq < 5 ? sp.o : 1.0f);
       const float r1 = wave_reduce1(v[8]);
       const uint32_t gid = (uint32_t)__builtin_amdgcn_readlane((int)cur.gid, k);
-      if (writer && r8 != 0.0f) unsafeAtomicAdd(accum + (size_t)wq * n + gid, r8);
-      if (lane == 0 && r1 != 0.0f) unsafeAtomicAdd(accum + (size_t)8 * n + gid, r1);
+      // one atomic instruction for the nine sums: they are adjacent in the
+      // Gaussian's [9] accumulator row
+      const float val = writer ? r8 : r1;
+      if ((writer || lane == 0) && val != 0.0f) unsafeAtomicAdd(accum + (size_t)gid * kGrad + (writer ? wq : 8), val);
     }
     cur = nxt;
   }

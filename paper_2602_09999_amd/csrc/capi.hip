@@ -470,7 +470,7 @@ static fgs_status check_backward(const fgs_gaussians* g, const fgs_camera* cams,
 }
 
 // Clears the accumulators and runs the blend backward over all views'
-// tiles (per-(view, Gaussian) 2D gradients into accum[9][n_views n]).
+// tiles (per-(view, Gaussian) 2D gradients into accum[n_views n][9]).
 static fgs_status blend_backward(const fgs_gaussians* g, const ViewSet& vs, const fgs_settings* st, void* workspace,
                                  const fgs_layout& L, const float* images, const uint32_t* lasts,
                                  const float* dl_dimages, hipStream_t hs) {

@@ -392,7 +392,7 @@ hipError_t launch_blend_backward(const uint2* ranges, const uint32_t* vals, cons
 hipError_t launch_preprocess_backward(const GaussDev& g, const CamDev& cam, const float4* rec, const float* accum,
                                       const GradDev& gr, hipStream_t s);
 // Several views / timesteps: gradients summed over the views (accum is
-// [9][n_views n]); dynamic Gaussians also get dL/dvelocity and dL/daccel.
+// [n_views n][9]); dynamic Gaussians also get dL/dvelocity and dL/daccel.
 hipError_t launch_preprocess_backward_views(const GaussDev& g, const ViewSet& vs, const float4* rec,
                                             const float* accum, const GradDev& gr, hipStream_t s);
 // Fused preprocess backward + Adam for the Gaussians with a gradient, which it

@@ -277,19 +277,28 @@ __device__ __forceinline__ void gaussian_grads(const GaussDev& g, const CamDev& 
   emit(10, go * o * (1.f - o));
 }
 
-// The nine accumulators of Gaussians i0..i0+3 (zero past n) and the mask of
-// those with any nonzero one.
+// The nine accumulators of Gaussians i0..i0+3 (zero past n; accum is
+// [n][9], so the four are 36 consecutive floats: nine 16-byte loads when
+// `full`) and the mask of those with any nonzero one.
 __device__ __forceinline__ uint32_t load_accum4(const float* __restrict__ accum, size_t n, uint32_t i0, bool full,
                                                 float (&acc)[4][9]) {
+  const float* src = accum + (size_t)i0 * 9;
+  if (full) {
+    float f[36];
 #pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    if (full) {
-      const float4 a = *reinterpret_cast<const float4*>(accum + q * n + i0);
-      acc[0][q] = a.x; acc[1][q] = a.y; acc[2][q] = a.z; acc[3][q] = a.w;
-    } else {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[j][q] = (i0 + j < n) ? accum[q * n + i0 + j] : 0.0f;
+    for (int w = 0; w < 9; ++w) {
+      const float4 a = reinterpret_cast<const float4*>(src)[w];
+      f[4 * w] = a.x; f[4 * w + 1] = a.y; f[4 * w + 2] = a.z; f[4 * w + 3] = a.w;
     }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int q = 0; q < 9; ++q) acc[j][q] = f[9 * j + q];
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int q = 0; q < 9; ++q) acc[j][q] = (i0 + j < n) ? src[9 * j + q] : 0.0f;
   }
   uint32_t mask = 0;
 #pragma unroll
@@ -462,7 +471,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd_views(GaussDev g, Vie
     bool any = false;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-      a[q] = accum[q * vn + rj];
+      a[q] = accum[rj * 9 + q];
       any |= a[q] != 0.0f;
     }
     if (!any) continue;

@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported_and_bound(lib):
     for name in names:
         assert hasattr(lib, name), name
         assert name in L.SIGNATURES, name
-    assert lib.fgs_abi_version() == 6
+    assert lib.fgs_abi_version() == 7
 
 
 def test_default_settings_match_the_paper(lib):
