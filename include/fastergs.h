@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define FGS_ABI_VERSION 7
+#define FGS_ABI_VERSION 8
 
 typedef enum fgs_status {
   FGS_OK = 0,
@@ -148,7 +148,8 @@ typedef struct fgs_forward_stats {
  *                           visible depth key, [3] index of the ping-pong buffer
  *                           holding the depth-sorted visible ids, [4..5] the
  *                           instance count I (uint64), [6] min(I, capacity),
- *                           [7] 1 when I exceeded the capacity
+ *                           [7] 1 when I exceeded the capacity, [8] the
+ *                           Gaussians with a gradient (fused backward)
  * With several views, the per-Gaussian regions (rec, n_tiles, depth_key,
  * vis_*, accum) hold n_views * n entries, entry v * n + i for view v.
  *   vis_ids    uint32[n] x2 ping-pong (see counters[3])
@@ -160,13 +161,16 @@ typedef struct fgs_forward_stats {
  *   accum      float[n][9]  backward: dL/d(mu2D.x, mu2D.y, a, b, c, opacity, r, g, b),
  *                           one row of nine per (view, Gaussian) entry
  *   touched    uint8[ceil(n/4)]  fused backward + Adam: bit j of byte k set when
- *                           Gaussian 4k+j received a gradient */
+ *                           Gaussian 4k+j received a gradient
+ *   touched_list uint32[n]  fused: the marked Gaussians (count in counters[8])
+ *   slot_of    uint32[n]    fused: slot s of a marked Gaussian i (list[s] = i)
+ *   sparse_grads float[59][n]  fused: plane p's gradient of list[s] at [p][s] */
 typedef struct fgs_layout {
   size_t rec, n_tiles, depth_key, counters;
   size_t vis_keys[2], vis_ids[2];
   size_t inst_offsets;
   size_t inst_keys[2], inst_vals[2];
-  size_t ranges, accum, touched, scratch, total;
+  size_t ranges, accum, touched, touched_list, slot_of, sparse_grads, scratch, total;
   int32_t inst_final;
   int32_t inst_key_bytes;        /* 2 or 4: width of the inst_keys entries */
   int32_t tiles_x, tiles_y;      /* tile grid of view 0 */
@@ -262,13 +266,13 @@ fgs_status fgs_rasterize_backward(const fgs_gaussians* g, const fgs_camera* cam,
                                   const fgs_gaussian_grads* grads, void* stream);
 
 /* Backward pass fused with the Adam step (Sec. 3.3 "Fusing Backward and
- * Optimizer"): the blend backward of fgs_rasterize_backward; then, for each
- * Gaussian that received a gradient, one kernel chains its accumulated 2D
- * gradients to the raw parameters and immediately applies Adam with the
- * moments of *opt (no gradient buffer is written), and marks it; a streaming
- * kernel then applies the zero-gradient Adam step to every parameter of all
- * other Gaussians.  Every parameter is updated, also those whose gradient is
- * zero, so the result equals fgs_rasterize_backward followed by
+ * Optimizer"): the blend backward of fgs_rasterize_backward; then one pass
+ * marks and lists the Gaussians that received a gradient, the chain rule runs
+ * for those only (their gradients go to compact slots of the workspace, no
+ * full gradient buffer is written), and one streaming kernel applies Adam
+ * with the moments of *opt to every parameter, with zero gradient for the
+ * unmarked Gaussians.  Every parameter is updated, also those whose gradient
+ * is zero, so the result equals fgs_rasterize_backward followed by
  * fgs_adam_step over the six groups (with bfloat16 SH, the SH gradient is
  * rounded to bfloat16 first, as a stored gradient would be).  The parameter
  * planes *g points to are updated in place and must be writable; sh_rest must
@@ -371,9 +375,9 @@ fgs_status fgs_rasterize_backward_batch(const fgs_gaussians* g, const fgs_camera
  * Steps (one kernel each unless noted): "preprocess", "duplicate",
  * "tile_sort" (all passes of the tile radix sort), "blend_forward",
  * "blend_backward", "preprocess_backward", and for
- * fgs_rasterize_backward_adam "preprocess_backward_adam" (gradients and Adam
- * of the Gaussians with a gradient) and "adam_untouched" (the zero-gradient
- * step of all others), "adam".  step = NULL
+ * fgs_rasterize_backward_adam "touched_gradients" (marks, list and chain rule
+ * of the Gaussians with a gradient: three launches) and "adam_sparse" (the
+ * Adam step of every parameter), "adam".  step = NULL
  * disarms.  An unknown name returns FGS_ERR_INVALID_ARGUMENT. */
 fgs_status fgs_time_next_launch(const char* step, void* start_event, void* stop_event);
 

@@ -49,7 +49,8 @@ class Layout(ctypes.Structure):
     _fields_ = [("rec", c_size_t), ("n_tiles", c_size_t), ("depth_key", c_size_t),
                 ("counters", c_size_t), ("vis_keys", c_size_t * 2), ("vis_ids", c_size_t * 2),
                 ("inst_offsets", c_size_t), ("inst_keys", c_size_t * 2), ("inst_vals", c_size_t * 2),
-                ("ranges", c_size_t), ("accum", c_size_t), ("touched", c_size_t), ("scratch", c_size_t),
+                ("ranges", c_size_t), ("accum", c_size_t), ("touched", c_size_t), ("touched_list", c_size_t),
+                ("slot_of", c_size_t), ("sparse_grads", c_size_t), ("scratch", c_size_t),
                 ("total", c_size_t),
                 ("inst_final", c_int32), ("inst_key_bytes", c_int32), ("tiles_x", c_int32), ("tiles_y", c_int32),
                 ("instance_capacity", c_int64), ("n_views", c_int64), ("total_tiles", c_int64)]

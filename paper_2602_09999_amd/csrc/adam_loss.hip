@@ -218,15 +218,16 @@ hipError_t launch_adam(const fgs_adam_group* groups, int n_groups, int64_t step,
   return hipGetLastError();
 }
 
-// Zero-gradient Adam step over the six parameter groups of the Gaussians,
-// skipping the elements of Gaussians whose bit is set in `touched` (updated
-// already, with their gradient, by the fused backward kernel).  Grid:
-// (chunks of 4 * 256 Gaussians, the 59 planes): a thread takes four
-// consecutive Gaussians of one plane, so the Gaussian index and the mark byte
-// need no division, and every access is a 16-byte (8-byte for bfloat16) one
-// that streams (read once, written once).  No gradient stream: 12 bytes are
-// read and 12 written per float32 element.
-struct UntouchedArgs {
+// Adam step over the six parameter groups of the Gaussians with sparse
+// gradients: a Gaussian whose bit is set in `touched` takes its gradient of
+// plane p from grads[p][slot_of[i]] (written by the fused backward), every
+// other one a zero gradient; every parameter is updated.  Grid: (chunks of
+// 4 * 256 Gaussians, the 59 planes): a thread takes four consecutive Gaussians
+// of one plane, so the Gaussian index and the mark byte need no division, and
+// every stream access is a 16-byte (8-byte for bfloat16) non-temporal one.
+// Per float32 element 12 bytes are read and 12 written, plus the marks and,
+// for marked Gaussians only, the slot and the gradient.
+struct SparseAdamArgs {
   void* p[6];
   float* m[6];
   float* v[6];
@@ -244,7 +245,9 @@ __device__ __forceinline__ int group_first_plane(int g) {
   return g == 0 ? 0 : g == 1 ? 3 : g == 2 ? 6 : g == 3 ? 10 : g == 4 ? 11 : 14;
 }
 
-__global__ __launch_bounds__(kBlock) void k_adam_untouched(UntouchedArgs a, const uint8_t* __restrict__ touched) {
+__global__ __launch_bounds__(kBlock) void k_adam_sparse(SparseAdamArgs a, const uint8_t* __restrict__ touched,
+                                                        const uint32_t* __restrict__ slot_of,
+                                                        const float* __restrict__ grads) {
   const int plane = blockIdx.y;
   const int gi = plane_group(plane);
   const size_t n = a.n;
@@ -252,8 +255,14 @@ __global__ __launch_bounds__(kBlock) void k_adam_untouched(UntouchedArgs a, cons
   const uint32_t q = blockIdx.x * kBlock + threadIdx.x;  // four Gaussians 4q .. 4q+3
   const uint32_t i0 = q * 4u;
   if (i0 >= a.n) return;
-  const uint32_t skip = touched[q];
-  if (skip == 0xfu) return;
+  const uint32_t mark = touched[q];
+  float g4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (mark) {
+    const float* gp = grads + (size_t)plane * n;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (mark >> e & 1u) g4[e] = gp[slot_of[i0 + e]];
+  }
   const bool bf = a.sh_bf16 && gi >= 4;
   const float st = a.step_size[gi];
   float* M = a.m[gi] + off;
@@ -273,8 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_adam_untouched(UntouchedArgs a, cons
     float m4[4] = {mm.x, mm.y, mm.z, mm.w}, v4[4] = {vv.x, vv.y, vv.z, vv.w};
     float p4[4] = {pp.x, pp.y, pp.z, pp.w};
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (!(skip >> e & 1u)) adam_elem(p4[e], 0.0f, m4[e], v4[e], a.c, st);
+    for (int e = 0; e < 4; ++e) adam_elem(p4[e], g4[e], m4[e], v4[e], a.c, st);
     if (bf) {
       const vu2 u = {(uint32_t)f32_to_bf16(p4[0]) | ((uint32_t)f32_to_bf16(p4[1]) << 16),
                      (uint32_t)f32_to_bf16(p4[2]) | ((uint32_t)f32_to_bf16(p4[3]) << 16)};
@@ -288,11 +296,10 @@ __global__ __launch_bounds__(kBlock) void k_adam_untouched(UntouchedArgs a, cons
     __builtin_nontemporal_store(vo, reinterpret_cast<vf4*>(V + i0));
   } else {
     for (uint32_t e = 0; e < 4 && i0 + e < a.n; ++e) {
-      if (skip >> e & 1u) continue;
       const size_t k = off + i0 + e;
       float pe = bf ? sh_load<true>(a.p[gi], k) : sh_load<false>(a.p[gi], k);
       float me = a.m[gi][k], ve = a.v[gi][k];
-      adam_elem(pe, 0.0f, me, ve, a.c, st);
+      adam_elem(pe, g4[e], me, ve, a.c, st);
       if (bf) sh_store<true>(a.p[gi], k, pe);
       else sh_store<false>(a.p[gi], k, pe);
       a.m[gi][k] = me;
@@ -301,11 +308,12 @@ __global__ __launch_bounds__(kBlock) void k_adam_untouched(UntouchedArgs a, cons
   }
 }
 
-hipError_t launch_adam_untouched(void* const params[6], float* const exp_avg[6], float* const exp_avg_sq[6],
-                                 const float lr[6], bool sh_bf16, uint64_t n, const uint8_t* touched, int64_t step,
-                                 double beta1, double beta2, double eps, hipStream_t s) {
+hipError_t launch_adam_sparse(void* const params[6], float* const exp_avg[6], float* const exp_avg_sq[6],
+                              const float lr[6], bool sh_bf16, uint64_t n, const uint8_t* touched,
+                              const uint32_t* slot_of, const float* grads, int64_t step, double beta1, double beta2,
+                              double eps, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  UntouchedArgs a = {};
+  SparseAdamArgs a = {};
   double bc1 = 1.0;
   a.c = adam_coef(step, beta1, beta2, eps, &bc1);
   a.n = (uint32_t)n;
@@ -322,7 +330,7 @@ hipError_t launch_adam_untouched(void* const params[6], float* const exp_avg[6],
   }
   a.vec = vec ? 1 : 0;
   const dim3 grid(ceil_div(ceil_div(n, 4), kBlock), 59);
-  k_adam_untouched<<<grid, kBlock, 0, s>>>(a, touched);
+  k_adam_sparse<<<grid, kBlock, 0, s>>>(a, touched, slot_of, grads);
   return hipGetLastError();
 }
 

@@ -179,6 +179,9 @@ fgs_status make_layout(int64_t n, const fgs_camera* cams, int32_t n_views, const
   L->ranges = take(tiles * 8);
   L->accum = take(vn * 9 * 4);
   L->touched = take((un + 3) / 4);
+  L->touched_list = take(un * 4);
+  L->slot_of = take(un * 4);
+  L->sparse_grads = take(un * 59 * 4);
   size_t words = scan_scratch_words(vn);
   words = std::max(words, radix_scratch_words(vn));
   words = std::max(words, radix_scratch_words(uc));
@@ -583,15 +586,17 @@ fgs_status fgs_rasterize_backward_adam(const fgs_gaussians* g, const fgs_camera*
                            const_cast<void*>(g->sh_dc), const_cast<void*>(g->sh_rest)};
   const GaussDev gd = make_gauss(g);
   uint8_t* touched = at<uint8_t>(workspace, L.touched);
-  FGS_TIMED("preprocess_backward_adam", hs,
-            launch_preprocess_backward_adam(gd, vs.cam[0], at<float4>(workspace, L.rec),
-                                            at<float>(workspace, L.accum), params, opt->exp_avg, opt->exp_avg_sq,
-                                            opt->lr, step, beta1, beta2, eps, touched, hs),
-            "preprocess bwd + adam");
-  FGS_TIMED("adam_untouched", hs,
-            launch_adam_untouched(params, opt->exp_avg, opt->exp_avg_sq, opt->lr, gd.sh_bf16 != 0, gd.n, touched,
-                                  step, beta1, beta2, eps, hs),
-            "adam (zero gradient)");
+  uint32_t* slot_of = at<uint32_t>(workspace, L.slot_of);
+  float* sparse = at<float>(workspace, L.sparse_grads);
+  FGS_TIMED("touched_gradients", hs,
+            launch_touched_gradients(gd, vs.cam[0], at<float4>(workspace, L.rec), at<float>(workspace, L.accum),
+                                     touched, at<uint32_t>(workspace, L.counters) + kStatTouched,
+                                     at<uint32_t>(workspace, L.touched_list), slot_of, sparse, hs),
+            "touched gradients");
+  FGS_TIMED("adam_sparse", hs,
+            launch_adam_sparse(params, opt->exp_avg, opt->exp_avg_sq, opt->lr, gd.sh_bf16 != 0, gd.n, touched,
+                               slot_of, sparse, step, beta1, beta2, eps, hs),
+            "adam (sparse gradients)");
   return FGS_OK;
 }
 
@@ -668,7 +673,7 @@ fgs_status fgs_time_next_launch(const char* step, void* start_event, void* stop_
   static const char* const kSteps[] = {"preprocess",          "duplicate",
                                        "tile_sort",           "blend_forward",
                                        "blend_backward",      "preprocess_backward",
-                                       "preprocess_backward_adam", "adam_untouched",
+                                       "touched_gradients", "adam_sparse",
                                        "adam"};
   if (!step) {
     g_timer.armed = false;

@@ -359,6 +359,7 @@ constexpr int kStatDepthBuf = 3;   // ping-pong buffer holding the depth-sorted 
 constexpr int kStatInstances = 4;  // instance count I, uint64 at words 4-5
 constexpr int kStatSortCount = 6;  // min(I, instance capacity): instances written and sorted
 constexpr int kStatOverflow = 7;   // 1 when I exceeds the instance capacity
+constexpr int kStatTouched = 8;    // fused backward: Gaussians that received a gradient
 hipError_t launch_set_word(uint32_t* p, uint32_t v, hipStream_t s);
 // Z-order: scratch bytes for n Gaussians; perm[k] = index of the Gaussian at
 // position k of the Morton order of the means [3][n]; gather of `planes`
@@ -395,19 +396,20 @@ hipError_t launch_preprocess_backward(const GaussDev& g, const CamDev& cam, cons
 // [n_views n][9]); dynamic Gaussians also get dL/dvelocity and dL/daccel.
 hipError_t launch_preprocess_backward_views(const GaussDev& g, const ViewSet& vs, const float4* rec,
                                             const float* accum, const GradDev& gr, hipStream_t s);
-// Fused preprocess backward + Adam for the Gaussians with a gradient, which it
-// marks in `touched`; params/exp_avg/exp_avg_sq/lr in the group order means,
-// log_scales, quats, logits, sh_dc, sh_rest.
-hipError_t launch_preprocess_backward_adam(const GaussDev& g, const CamDev& cam, const float4* rec,
-                                           const float* accum, void* const params[6], float* const exp_avg[6],
-                                           float* const exp_avg_sq[6], const float lr[6], int64_t step,
-                                           double beta1, double beta2, double eps, uint8_t* touched,
-                                           hipStream_t s);
-// The zero-gradient Adam step of every parameter of the Gaussians not marked
-// in `touched` (groups as above, planes of length n).
-hipError_t launch_adam_untouched(void* const params[6], float* const exp_avg[6], float* const exp_avg_sq[6],
-                                 const float lr[6], bool sh_bf16, uint64_t n, const uint8_t* touched, int64_t step,
-                                 double beta1, double beta2, double eps, hipStream_t s);
+// Fused backward + Adam, first part: marks the Gaussians with a gradient in
+// `touched` (4 bits per byte), lists them (count in *counter, cleared here),
+// gives Gaussian list[s] slot s (slot_of) and writes its 59 raw-parameter
+// gradients to grads[p][s] (grads: float [59][n]).
+hipError_t launch_touched_gradients(const GaussDev& g, const CamDev& cam, const float4* rec, const float* accum,
+                                    uint8_t* touched, uint32_t* counter, uint32_t* list, uint32_t* slot_of,
+                                    float* grads, hipStream_t s);
+// Second part: Adam on every parameter of the six groups (means, log_scales,
+// quats, logits, sh_dc, sh_rest; planes of length n), with the gradient of
+// the marked Gaussians from their slots and zero for all others.
+hipError_t launch_adam_sparse(void* const params[6], float* const exp_avg[6], float* const exp_avg_sq[6],
+                              const float lr[6], bool sh_bf16, uint64_t n, const uint8_t* touched,
+                              const uint32_t* slot_of, const float* grads, int64_t step, double beta1, double beta2,
+                              double eps, hipStream_t s);
 // step >= 1: host step count; step == 0: advance the device step counter in
 // dev_state (256 bytes, first an int64 t) and use it.
 hipError_t launch_adam(const fgs_adam_group* groups, int n_groups, int64_t step, double beta1, double beta2,

@@ -10,12 +10,10 @@
 // needs are recomputed from the parameters; the conic, opacity and the
 // colour-clip flags are read from the forward record.
 //
-// The fused variant (Sec. 3.3 "Fusing Backward and Optimizer") applies Adam
-// to each parameter of a Gaussian with a gradient as soon as the gradient is
-// known, so no gradient is stored, and marks those Gaussians; the
-// zero-gradient step of all other parameters is a separate streaming kernel
-// (k_adam_untouched), which runs at the occupancy of a plain stream instead of
-// that of this register-heavy chain rule.
+// The fused variant (Sec. 3.3 "Fusing Backward and Optimizer") evaluates the
+// chain rule only for the Gaussians that received a gradient, keeps their
+// gradients in slots of a compact buffer, and leaves every parameter update
+// to one streaming Adam pass (see k_touched_list below).
 //
 // Chain (per Gaussian, K = conic = H^-1 with H the dilated Sigma2D):
 //   dL/dH = -K dL/dK K                         (b counted on both off-diagonals)
@@ -24,6 +22,8 @@
 //   Sigma = M M^T, M = R diag(s): dL/dM = 2 dL/dSigma M
 //   R(q/|q|) and the normalisation; s = exp(log s); o = sigmoid(logit)
 //   colour: SH coefficients and the view direction (through mu).
+#include <algorithm>
+
 #include "fgs_internal.h"
 
 namespace fgs {
@@ -355,95 +355,79 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(GaussDev g, CamDev ca
   }
 }
 
-// Parameters (updated in place), moments and per-group step sizes.
-struct FusedAdamDev {
-  void* param[6];
-  float* m[6];
-  float* v[6];
-  float step_size[6];
-  AdamCoef c;
-};
-
-// Adam on one parameter (plane p, Gaussian i) with its gradient; p is a
-// run-time value here, so the group and its element type are picked at run time.
-template <bool SHB>
-__device__ __forceinline__ void adam_param(const FusedAdamDev& o, int p, size_t n, uint32_t i, float grad) {
-  const int gi = group_of(p);
-  const size_t off = (size_t)(p - first_plane(gi)) * n + i;
-  float* M = o.m[gi] + off;
-  float* V = o.v[gi] + off;
-  float mm = *M, vv = *V;
-  if (SHB && gi >= 4) {
-    uint16_t* P = static_cast<uint16_t*>(o.param[gi]) + off;
-    float pp = bf16_to_f32(*P);
-    adam_elem(pp, grad, mm, vv, o.c, o.step_size[gi]);
-    *P = f32_to_bf16(pp);
-  } else {
-    float* P = static_cast<float*>(o.param[gi]) + off;
-    float pp = *P;
-    adam_elem(pp, grad, mm, vv, o.c, o.step_size[gi]);
-    *P = pp;
+// ---------------------------------------------------------------------------
+// Fused backward + Adam (Sec. 3.3 "Fusing Backward and Optimizer").  In a
+// step only a small share of the Gaussians receives a gradient, scattered
+// over the index range; updating their parameters where they lie costs a
+// memory sector per 4-byte access, and the streaming step then reads the same
+// lines again.  So no full gradient buffer and no separate update:
+//   k_touched_list   one pass over the accumulators: the 4-bit mark of each
+//                    group of four Gaussians, and for the marked ones a
+//                    compact list and each one's slot in it (one atomic per
+//                    wave on a counter)
+//   k_touched_grads  the chain rule for the listed Gaussians only; their 59
+//                    gradients go to slot s of plane-major [59][n] storage,
+//                    so a plane's gradients of neighbouring Gaussians are
+//                    adjacent
+//   k_adam_sparse    one streaming Adam pass over every parameter, which
+//                    takes a marked Gaussian's gradient from its slot and
+//                    zero for all others (adam_loss.hip).
+__global__ __launch_bounds__(kBlock) void k_touched_list(const float* __restrict__ accum, uint32_t n, int vec,
+                                                         uint8_t* __restrict__ touched,
+                                                         uint32_t* __restrict__ counter,
+                                                         uint32_t* __restrict__ list,
+                                                         uint32_t* __restrict__ slot_of) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t i0 = (blockIdx.x * kBlock + threadIdx.x) * 4u;
+  if ((blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1u))) * 4u >= n) return;  // whole wave past the end
+  uint32_t mask = 0;
+  if (i0 < n) {
+    float acc[4][9];
+    mask = load_accum4(accum, n, i0, vec && i0 + 4 <= n, acc);
+    touched[i0 / 4] = (uint8_t)mask;
   }
-  *M = mm;
-  *V = vv;
+  // exclusive prefix of the lanes' counts (0..4, three bit planes) and the wave total
+  const uint32_t cnt = (uint32_t)__popc(mask);
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const uint64_t m = __ballot((cnt >> b) & 1u);
+    pre += (uint32_t)__popcll(m & below) << b;
+    tot += (uint32_t)__popcll(m) << b;
+  }
+  if (tot == 0) return;  // wave-uniform
+  uint32_t base = 0;
+  if (lane == 0) base = atomicAdd(counter, tot);
+  base = (uint32_t)__shfl((int)base, 0, kWave);
+  uint32_t slot = base + pre;
+  for (int j = 0; j < 4; ++j) {
+    if (!(mask >> j & 1u)) continue;
+    list[slot] = i0 + j;
+    slot_of[i0 + j] = slot;
+    ++slot;
+  }
 }
 
-// For the Gaussians with a gradient: the chain rule (one Gaussian per lane),
-// then Adam on their parameters.  The lanes' gradients go through LDS so the
-// wave spreads the (Gaussian, parameter) updates over all 64 lanes: a wave
-// waits for one or two memory round trips per round instead of one per
-// parameter.  Writes the marks the zero-gradient kernel skips.
+// One thread per listed Gaussian (grid-stride; every thread exits once the
+// list is done).  A bfloat16 SH gradient is rounded as a stored one would be.
 template <bool SHB>
-__global__ __launch_bounds__(kBlock) void k_preprocess_bwd_adam(GaussDev g, CamDev cam,
-                                                                const float4* __restrict__ rec,
-                                                                const float* __restrict__ accum, FusedAdamDev o,
-                                                                uint8_t* __restrict__ touched, int vec) {
-  constexpr int kWaves = kBlock / kWave;
-  __shared__ float s_grad[kWaves][kParams][kWave];
-  __shared__ uint32_t s_gid[kWaves][kWave];
-  __shared__ uint32_t s_src[kWaves][kWave];
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
-  const uint32_t i0 = (blockIdx.x * kBlock + threadIdx.x) * 4u;
+__global__ __launch_bounds__(kBlock) void k_touched_grads(GaussDev g, CamDev cam, const float4* __restrict__ rec,
+                                                          const float* __restrict__ accum,
+                                                          const uint32_t* __restrict__ counter,
+                                                          const uint32_t* __restrict__ list,
+                                                          float* __restrict__ grads) {
   const size_t n = g.n;
-  if (blockIdx.x * kBlock * 4u + (uint32_t)(wave * kWave) * 4u >= n) return;  // whole wave past the end
-  const bool in_range = i0 < n;  // other lanes stay to help with the updates
-  const bool full = in_range && vec && i0 + 4 <= n;
-  float acc[4][9];
-  uint32_t todo = 0;
-  if (in_range) {
-    todo = load_accum4(accum, n, i0, full, acc);
-    touched[i0 / 4] = (uint8_t)todo;  // the zero-gradient kernel leaves these to this one
-  }
-  volatile float* vg = &s_grad[wave][0][0];
-  volatile uint32_t* vid = s_gid[wave];
-  volatile uint32_t* vsrc = s_src[wave];
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  while (true) {
-    const bool mine = todo != 0;
-    const uint64_t act = __ballot(mine);
-    if (act == 0) break;
-    if (mine) {
-      const int j = __builtin_ctz(todo);
-      todo &= todo - 1u;
-      float a[9];
-      pick_accum(acc, j, a);
-      const uint32_t i = i0 + j;
-      const float mu[3] = {g.means[i], g.means[n + i], g.means[2 * n + i]};
-      gaussian_grads<SHB>(g, cam, rec, a, i, i, mu, [&](int p, float v) {
-        vg[p * kWave + lane] = group_of(p) >= 4 ? sh_round<SHB>(v) : v;  // as if stored
-      });
-      vid[lane] = i;
-      vsrc[__popcll(act & below)] = (uint32_t)lane;
-    }
-    __builtin_amdgcn_wave_barrier();
-    const int c = __popcll(act);
-    for (int idx = lane; idx < c * kParams; idx += kWave) {
-      const int k = idx % c, p = idx / c;
-      const uint32_t src = vsrc[k];
-      adam_param<SHB>(o, p, n, vid[src], vg[p * kWave + src]);
-    }
-    __builtin_amdgcn_wave_barrier();
+  const uint32_t count = min(*counter, (uint32_t)n);
+  for (uint32_t slot = blockIdx.x * kBlock + threadIdx.x; slot < count; slot += gridDim.x * kBlock) {
+    const uint32_t i = list[slot];
+    float a[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) a[q] = accum[(size_t)i * 9 + q];
+    const float mu[3] = {g.means[i], g.means[n + i], g.means[2 * n + i]};
+    gaussian_grads<SHB>(g, cam, rec, a, i, i, mu, [&](int p, float v) {
+      grads[(size_t)p * n + slot] = group_of(p) >= 4 ? sh_round<SHB>(v) : v;
+    });
   }
 }
 
@@ -535,27 +519,20 @@ hipError_t launch_preprocess_backward(const GaussDev& g, const CamDev& cam, cons
   return hipGetLastError();
 }
 
-hipError_t launch_preprocess_backward_adam(const GaussDev& g, const CamDev& cam, const float4* rec,
-                                           const float* accum, void* const params[6], float* const exp_avg[6],
-                                           float* const exp_avg_sq[6], const float lr[6], int64_t step,
-                                           double beta1, double beta2, double eps, uint8_t* touched,
-                                           hipStream_t s) {
+hipError_t launch_touched_gradients(const GaussDev& g, const CamDev& cam, const float4* rec, const float* accum,
+                                    uint8_t* touched, uint32_t* counter, uint32_t* list, uint32_t* slot_of,
+                                    float* grads, hipStream_t s) {
   if (g.n == 0) return hipSuccess;
-  FusedAdamDev o;
-  double bc1 = 1.0;
-  o.c = adam_coef(step, beta1, beta2, eps, &bc1);
-  for (int k = 0; k < 6; ++k) {
-    o.param[k] = params[k];
-    o.m[k] = exp_avg[k];
-    o.v[k] = exp_avg_sq[k];
-    o.step_size[k] = (float)((double)lr[k] / bc1);
-  }
-  const int vec = (g.n % 4 == 0 && ((uintptr_t)accum & 15u) == 0) ? 1 : 0;
-  const uint32_t grid = ceil_div(ceil_div(g.n, 4), kBlock);
+  hipError_t e = launch_fill_u32(counter, 0u, 1, s);
+  if (e != hipSuccess) return e;
+  const int vec = ((uintptr_t)accum & 15u) == 0 ? 1 : 0;
+  k_touched_list<<<ceil_div(ceil_div(g.n, 4), kBlock), kBlock, 0, s>>>(accum, g.n, vec, touched, counter, list,
+                                                                      slot_of);
+  const uint32_t grid = std::min<uint32_t>(ceil_div(g.n, kBlock), 2048u);
   if (g.sh_bf16)
-    k_preprocess_bwd_adam<true><<<grid, kBlock, 0, s>>>(g, cam, rec, accum, o, touched, vec);
+    k_touched_grads<true><<<grid, kBlock, 0, s>>>(g, cam, rec, accum, counter, list, grads);
   else
-    k_preprocess_bwd_adam<false><<<grid, kBlock, 0, s>>>(g, cam, rec, accum, o, touched, vec);
+    k_touched_grads<false><<<grid, kBlock, 0, s>>>(g, cam, rec, accum, counter, list, grads);
   return hipGetLastError();
 }
 
