@@ -140,14 +140,18 @@ def cpu_baseline(workload: str, seed: int, budget_s: float):
             "seconds_per_step_extrapolated": sec}
 
 
-# name: (backward fused with Adam, SH element type, z-ordered layout); the
-# first is the headline
+# name: (backward fused with Adam, SH element type, z-ordered layout, forward
+# waits for the instance count on the host); the first is the headline.  The
+# synchronisation-free forward sizes its launches by the instance capacity
+# (set by the synchronised warm-up steps, with headroom) and reads the counts
+# on the device; after the timed steps the overflow flag is checked.
 VARIANTS = {
-    "fused_f32": (True, torch.float32, True),
-    "unfused_f32": (False, torch.float32, True),
-    "fused_bf16sh": (True, torch.bfloat16, True),
-    "unfused_bf16sh": (False, torch.bfloat16, True),
-    "fused_f32_unordered": (True, torch.float32, False),
+    "fused_f32": (True, torch.float32, True, False),
+    "unfused_f32": (False, torch.float32, True, False),
+    "fused_bf16sh": (True, torch.bfloat16, True, False),
+    "unfused_bf16sh": (False, torch.bfloat16, True, False),
+    "fused_f32_unordered": (True, torch.float32, False, False),
+    "fused_f32_hostsync": (True, torch.float32, True, True),
 }
 ZORDER_EVERY = 5000  # iterations between z-order re-layouts (Sec. 3.3)
 # the step each variant times live with the library's timing hook, and the kernel it is
@@ -178,7 +182,7 @@ def adam_bytes(n, sh_bf16):
 def run_variant(name, args, scene, cam, target, dev, w):
     import paper_2602_09999_amd as P
     from paper_2602_09999_amd import binding as B
-    fused, shd, zorder = VARIANTS[name]
+    fused, shd, zorder, host_sync = VARIANTS[name]
     params = {k: v.to(dev) for k, v in scene.items()}
     for k in ("sh_dc", "sh_rest"):
         params[k] = params[k].to(shd).contiguous()
@@ -203,12 +207,12 @@ def run_variant(name, args, scene, cam, target, dev, w):
     grads = None if fused else {k: torch.empty_like(v) for k, v in params.items()}
     step_name, kernel = TIMED[fused]
 
-    def step(ev=None, kev=None):
+    def step(ev=None, kev=None, sync=True):
         if kev is not None:
             B.time_next_launch(step_name, kev[0], kev[1])
         if ev is not None:
             ev[0].record(stream)
-        rz.forward(params, image, t_final, last)
+        rz.forward(params, image, t_final, last, sync=sync)
         if ev is not None:
             ev[1].record(stream)
         B.l1_loss_backward(image, target, dl)
@@ -237,9 +241,11 @@ def run_variant(name, args, scene, cam, target, dev, w):
     log(f"{name}: warmup done; N_vis={rz.last_stats.get('n_visible')} I={rz.last_stats.get('n_instances')}")
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(evs[k], kevs[k])
+        step(evs[k], kevs[k], sync=host_sync)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    if rz.overflowed():
+        raise SystemExit(f"{name}: a timed step exceeded the instance capacity {rz.capacity}")
     ph = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(4)] for k in range(args.steps)]).mean(0)
     kms = float(np.mean([kevs[k][0].elapsed_time(kevs[k][1]) for k in range(args.steps)]))
     ms_step = 1000.0 * elapsed / args.steps
@@ -249,7 +255,8 @@ def run_variant(name, args, scene, cam, target, dev, w):
         f"; {kernel} {kms:.3f} ms")
     return {"steps": args.steps, "elapsed": elapsed, "ms_per_step": ms_step, "steps_per_s": args.steps / elapsed,
             "phase_ms": phases, "kernel": kernel, "kernel_ms": kms, "rz": rz, "params": params, "last": last,
-            "fused": fused, "sh_bf16": shd == torch.bfloat16, "zorder": zorder, "zorder_ms": zorder_ms}
+            "fused": fused, "sh_bf16": shd == torch.bfloat16, "zorder": zorder, "zorder_ms": zorder_ms,
+            "host_sync": host_sync}
 
 
 BATCH_VIEWS, BATCH_N = 16, 1_500_000
@@ -438,7 +445,7 @@ def main():
         kb = fused_bytes(n, counts["n_touched"], r["sh_bf16"])["adam"] if r["fused"] else adam_bytes(n, r["sh_bf16"])
         variants[v] = {"steps_per_s": r["steps_per_s"], "ms_per_step": r["ms_per_step"], "phase_ms": r["phase_ms"],
                        "sh": "bf16" if r["sh_bf16"] else "f32", "backward_fused_with_adam": r["fused"],
-                       "zorder_layout": r["zorder"],
+                       "zorder_layout": r["zorder"], "forward_host_sync": r["host_sync"],
                        "timed_kernel": {"name": r["kernel"], "avg_launch_ms": r["kernel_ms"],
                                         "algorithmic_bytes": kb,
                                         "GB_per_s": kb / (r["kernel_ms"] * 1e-3) / 1e9}}
@@ -457,6 +464,7 @@ def main():
         "data": "synthetic (seeded scene, random uniform target)",
         "config": {"workload": f"{w.name}: {w.description}", "gaussians": n, "width": w.width,
                    "height": w.height, "tile": 16, "sh_degree": 3, "seed": args.seed, "variant": head,
+                   "forward_host_sync": hr["host_sync"],
                    "visible": counts["visible"], "instances": counts["instances"],
                    "instances_walked": counts["i_proc"], "gaussians_with_gradient": counts["n_touched"]},
         "roofline": {"bound": "hbm", "kernel": hr["kernel"], "achieved": k_gbs, "peak": HBM_PEAK_GBS,

@@ -449,7 +449,12 @@ class Rasterizer:
         return workspace_layout(self.n, self.camera, self.settings, self.capacity)
 
     def forward(self, params: Dict[str, torch.Tensor], image: Optional[torch.Tensor] = None,
-                t_final: Optional[torch.Tensor] = None, last: Optional[torch.Tensor] = None, stream=None):
+                t_final: Optional[torch.Tensor] = None, last: Optional[torch.Tensor] = None, stream=None,
+                sync: bool = True):
+        """sync=False (once a synchronised forward has sized the workspace for
+        this Gaussian count): the host never waits for the GPU; launches are
+        sized by the capacity and read the counts on the device.  An instance
+        count beyond the capacity then only sets a flag, see overflowed()."""
         n = int(params["opacity_logits"].shape[0])
         h, w = int(self.camera.height), int(self.camera.width)
         if image is None:
@@ -458,6 +463,11 @@ class Rasterizer:
             last = torch.empty(h, w, dtype=torch.int32, device=self.device)
         if t_final is None:
             t_final = torch.empty(h, w, dtype=torch.float32, device=self.device)
+        if not sync and self.workspace is not None and n == self.n:
+            rasterize_forward_batch(params, [self.camera], None, self.settings, self.workspace, self.capacity,
+                                    image.view(-1), t_final.view(-1), last.view(-1), mode=L.FGS_FORWARD_NO_SYNC,
+                                    sh_degree=self.sh_degree, stream=stream)
+            return image, t_final, last
         self._ensure(n, max(self.capacity, 1024) if n == self.n else max(1024, 16 * n))
         for _ in range(3):
             st = rasterize_forward(params, self.camera, self.settings, self.workspace, self.capacity, image,
@@ -485,6 +495,12 @@ class Rasterizer:
                                 dl_dimage.contiguous(), optimizer.exp_avg, optimizer.exp_avg_sq, optimizer.lrs,
                                 optimizer.t, optimizer.betas[0], optimizer.betas[1], optimizer.eps,
                                 sh_degree=self.sh_degree, stream=stream)
+
+    def overflowed(self) -> bool:
+        """Whether the last forward found more instances than the capacity (its
+        result is then incomplete); reads the device counters, so it waits for
+        the GPU."""
+        return bool(int(self.view("counters", 8)[7].item()))
 
     # -- views of the workspace (for inspection and tests)
     def view(self, field: str, count: int, dtype=torch.int32, index: Optional[int] = None) -> torch.Tensor:

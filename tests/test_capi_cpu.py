@@ -44,6 +44,20 @@ def test_default_settings_match_the_paper(lib):
     assert s.quat_min == pytest.approx(1e-4, rel=1e-7) and s.det_min == pytest.approx(1e-6, rel=1e-7)
 
 
+def test_single_view_layout_equals_one_view_batch(lib):
+    # the synchronisation-free single-view forward goes through the batch
+    # entry point with one view on the same workspace
+    for name in ("c1", "c3"):
+        cam = S.workload_camera(name)
+        a = B.workspace_layout(20_000, cam, instance_capacity=300_000)
+        b = B.batch_workspace_layout(20_000, [cam], instance_capacity=300_000)
+        for f, _ in a._fields_:
+            va, vb = getattr(a, f), getattr(b, f)
+            if hasattr(va, "__len__"):
+                va, vb = list(va), list(vb)
+            assert va == vb, f
+
+
 def test_workspace_size_and_layout(lib):
     cam = S.workload_camera("c1")
     a = B.workspace_size(10_000, cam, instance_capacity=100_000)

@@ -114,6 +114,31 @@ def test_batch_equals_single_views(tile, views):
         assert e <= 1e-5, (name, e)
 
 
+def test_single_view_forward_without_synchronisation():
+    sc, cam = S.make_scene(10_000, 0), S.workload_camera("c1")
+    say("single-view no-sync forward")
+    params = to_gpu(sc)
+    rz = B.Rasterizer(cam)
+    img, tf, last = rz.forward(params)
+    img, tf, last = img.clone(), tf.clone(), last.clone()
+    need = rz.last_stats["n_instances"]
+    img2, tf2, last2 = rz.forward(params, sync=False)
+    assert not rz.overflowed()
+    assert torch.equal(img2, img) and torch.equal(tf2, tf) and torch.equal(last2, last)
+    dl = S.make_dl_dimage(cam.height, cam.width, seed=3).cuda()
+    g1 = rz.backward(params, img, last, dl)
+    g1 = {k: v.clone() for k, v in g1.items()}
+    rz.forward(params, sync=False)
+    g2 = rz.backward(params, img, last, dl)
+    for k in B.PARAM_NAMES:
+        assert rel_l2(g2[k], g1[k]) <= 1e-6, k
+    small = B.Rasterizer(cam)
+    small._ensure(S.count(sc), need // 2)  # a workspace too small for this view
+    small.forward(params, sync=False)
+    say("  instances", need, "capacity", small.capacity, "overflow", small.overflowed())
+    assert small.overflowed()
+
+
 def test_batch_without_synchronisation_and_overflow_flag():
     sc = S.batch_scene(20_000, 4)
     cams = small_views()
