@@ -169,17 +169,16 @@ __device__ __forceinline__ bool tile_keep(float mx, float my, float a, float b, 
   const float y0 = (float)(ty * tile) + 0.5f;
   const float y1 = (float)min(ty * tile + tile - 1, height - 1) + 0.5f;
   const bool left = mx < x0, right = mx > x1, top = my < y0, bottom = my > y1;
-  // All four edges are evaluated and the facing ones selected (no divergent
-  // branches); the minimum is 0 inside the hull.
-  const float qL = edge_min_q(a, b, c, x0 - mx, my, y0, y1, true);
-  const float qR = edge_min_q(a, b, c, x1 - mx, my, y0, y1, true);
-  const float qT = edge_min_q(a, b, c, y0 - my, mx, x0, x1, false);
-  const float qB = edge_min_q(a, b, c, y1 - my, mx, x0, x1, false);
+  // At most one vertical and one horizontal edge face the centre (left and
+  // right exclude each other, as do top and bottom): the minimum over the hull
+  // is the smaller of those two edge minima, and 0 inside the hull.  Both are
+  // evaluated and selected without divergent branches.
+  const bool out_x = left || right, out_y = top || bottom;
+  const float qX = edge_min_q(a, b, c, (left ? x0 : x1) - mx, my, y0, y1, true);
+  const float qY = edge_min_q(a, b, c, (top ? y0 : y1) - my, mx, x0, x1, false);
   const float inf = __builtin_huge_valf();
-  float q = fminf(left ? qL : inf, right ? qR : inf);
-  q = fminf(q, fminf(top ? qT : inf, bottom ? qB : inf));
-  const bool inside = !(left || right || top || bottom);
-  return inside || q <= thr;
+  const float q = fminf(out_x ? qX : inf, out_y ? qY : inf);
+  return !(out_x || out_y) || q <= thr;
 }
 
 // Decode the packed tile rectangle.
@@ -254,9 +253,35 @@ __device__ __forceinline__ uint32_t udiv_small(uint32_t r, uint32_t w) {
   return q;
 }
 
+// What a lane needs of the Gaussian that owns its candidate: staged in LDS
+// once per walk and read with three 16-byte loads per step (instead of a
+// cross-lane shuffle per field).
+struct alignas(16) OwnerRec {
+  float mx, my, a, b;
+  float c, thr;
+  int tx0, ty0;
+  int w, width, height;
+  uint32_t cstart;  // first candidate's position in the wave's candidate list
+};
+
+// LDS of one wave's walk.
+struct WalkLds {
+  OwnerRec own[kWave];
+  uint32_t owner_at[kWave];
+};
+
+// Orders a wave's LDS writes before its later LDS reads by other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// emit(owner, const OwnerRec&, rank among the owner's kept tiles, tx, ty, keep)
+// is called by every lane at every step (uniform control flow); LDS the
+// caller wrote before the call is visible to all lanes inside emit.
 template <typename Emit>
-__device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, volatile uint32_t* owner_at, int tile,
-                                                   Emit emit) {
+__device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, WalkLds& L, int tile, Emit emit) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t incl = wave_inclusive_scan(me.cand, lane);
   const uint32_t cstart = incl - me.cand;
@@ -265,7 +290,10 @@ __device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, volatile 
   const uint64_t upto = below | (1ull << lane);
   uint32_t kept = 0;
   uint32_t tag = 0;
+  L.own[lane] = OwnerRec{me.mx, me.my, me.a, me.b, me.c, me.thr, me.tx0, me.ty0, me.w, me.width, me.height, cstart};
+  volatile uint32_t* owner_at = L.owner_at;
   owner_at[lane] = 0xffffffffu;  // no step tag matches
+  wave_lds_sync();
   for (uint32_t c0 = 0; c0 < total; c0 += kWave, tag += 0x100u) {
     // the Gaussian whose candidates start in (or run into) this step claims its first slot
     const bool claims = me.cand > 0 && cstart < c0 + kWave && cstart + me.cand > c0;
@@ -278,24 +306,18 @@ __device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, volatile 
     const int owner = (int)(owner_at[src_slot] & 0xffu);
     const uint32_t pos = c0 + (uint32_t)lane;
     const bool valid = pos < total;
-    const uint32_t o_cstart = __shfl(cstart, owner, kWave);
+    const OwnerRec o = L.own[owner];
+    // the running count is the one per-step value: a shuffle, with all lanes active
     const uint32_t o_kept = __shfl(kept, owner, kWave);
-    const int o_w = __shfl(me.w, owner, kWave);
-    const uint32_t r = pos - o_cstart;
-    const uint32_t ry = udiv_small(r, (uint32_t)o_w);
-    const int tx = __shfl(me.tx0, owner, kWave) + (int)(r - ry * (uint32_t)o_w);
-    const int ty = __shfl(me.ty0, owner, kWave) + (int)ry;
-    // Every cross-lane read happens with all lanes active: a lane past the
-    // end of the candidates may still own the Gaussian another lane reads.
-    const float o_mx = __shfl(me.mx, owner, kWave), o_my = __shfl(me.my, owner, kWave);
-    const float o_a = __shfl(me.a, owner, kWave), o_b = __shfl(me.b, owner, kWave);
-    const float o_c = __shfl(me.c, owner, kWave), o_thr = __shfl(me.thr, owner, kWave);
-    const int o_width = __shfl(me.width, owner, kWave), o_height = __shfl(me.height, owner, kWave);
-    const bool keep = tile_keep(o_mx, o_my, o_a, o_b, o_c, o_thr, tx, ty, tile, o_width, o_height) & valid;
+    const uint32_t r = pos - o.cstart;
+    const uint32_t ry = udiv_small(r, (uint32_t)o.w);
+    const int tx = o.tx0 + (int)(r - ry * (uint32_t)o.w);
+    const int ty = o.ty0 + (int)ry;
+    const bool keep = tile_keep(o.mx, o.my, o.a, o.b, o.c, o.thr, tx, ty, tile, o.width, o.height) & valid;
     const uint64_t kb = __ballot(keep);
-    const uint32_t first = o_cstart > c0 ? o_cstart - c0 : 0u;
+    const uint32_t first = o.cstart > c0 ? o.cstart - c0 : 0u;
     const uint64_t from_first = first >= 64 ? 0ull : ~((first == 0) ? 0ull : (~0ull >> (64 - first)));
-    emit(owner, o_kept + (uint32_t)__popcll(kb & below & from_first), tx, ty, keep);  // uniform call
+    emit(owner, o, o_kept + (uint32_t)__popcll(kb & below & from_first), tx, ty, keep);  // uniform call
     // this lane's Gaussian: add the kept tiles of its segment in this step
     if (claims) {
       const uint32_t lo = slot;

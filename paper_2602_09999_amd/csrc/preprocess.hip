@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, ViewSet vs, S
                                                        uint4* __restrict__ partials,
                                                        uint32_t* __restrict__ depth_key) {
 #pragma clang fp contract(off)
-  __shared__ uint32_t s_owner[kBlock / kWave][kWave];
+  __shared__ WalkLds s_walk[kBlock / kWave];
   const uint32_t view = blockIdx.y;
   const CamDev& cam = vs.cam[view];
   const uint32_t i0 = blockIdx.x * kBlock + threadIdx.x;
@@ -185,8 +185,8 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, ViewSet vs, S
     }
   }
   // exact per-tile test of every candidate tile, load-balanced over the wave
-  const uint32_t count = wave_tile_walk(me, s_owner[threadIdx.x / kWave], tile,
-                                        [](int, uint32_t, int, int, bool) {});
+  const uint32_t count = wave_tile_walk(me, s_walk[threadIdx.x / kWave], tile,
+                                        [](int, const OwnerRec&, uint32_t, int, int, bool) {});
   const bool vis = in_range && count > 0;
   if (in_range) n_tiles[j] = count;
   if (vis) {
@@ -329,18 +329,18 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
                                                       const float4* __restrict__ rec, ViewSet vs,
                                                       uint32_t n_gauss, int tile, uint32_t cap,
                                                       KT* __restrict__ keys, uint32_t* __restrict__ vals) {
-  __shared__ uint32_t s_owner[kBlock / kWave][kWave];
+  __shared__ WalkLds s_walk[kBlock / kWave];
+  __shared__ uint4 s_dup[kBlock / kWave][kWave];
   const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
   const uint32_t nv = min(*d_nvis, n);
   if (blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1)) >= nv) return;  // whole wave idle
   CandLane me = {};
-  uint32_t gid = 0, off = 0, end = 0, kbase = 0, krow = 0;
+  uint32_t gid = 0, off = 0, end = 0, kbase = 0;
   if (p < nv) {
     gid = vis_ids[p];
     off = offsets[p];
     const uint32_t v = vs.n_views > 1 ? gid / n_gauss : 0u;
     kbase = vs.tile_base[v];
-    krow = (uint32_t)vs.cam[v].tiles_x;
     me.width = vs.cam[v].width;
     me.height = vs.cam[v].height;
     // three float4 of one 64-byte record: one cache line per Gaussian
@@ -355,18 +355,18 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
                   count ? (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1)) : 0u, me.width, me.height};
   }
   const uint32_t tiles = vs.tile_base[vs.n_views];
+  // the owner's output slots, Gaussian and key base, read by owner in emit
+  s_dup[threadIdx.x / kWave][threadIdx.x & (kWave - 1)] = make_uint4(off, end, gid, kbase);
+  const int tile_shift = __builtin_ctz((unsigned)tile);
   const uint32_t written = wave_tile_walk(
-      me, s_owner[threadIdx.x / kWave], tile,
-      [&](int owner, uint32_t rank, int tx, int ty, bool keep) {
-        const uint32_t o_off = __shfl(off, owner, kWave);
-        const uint32_t o_end = __shfl(end, owner, kWave);
-        const uint32_t o_gid = __shfl(gid, owner, kWave);
-        const uint32_t o_kbase = __shfl(kbase, owner, kWave);
-        const uint32_t o_krow = __shfl(krow, owner, kWave);
-        const uint32_t slot = o_off + rank;
-        if (keep && slot < o_end) {
-          keys[slot] = (KT)(o_kbase + (uint32_t)ty * o_krow + (uint32_t)tx);
-          vals[slot] = o_gid;
+      me, s_walk[threadIdx.x / kWave], tile,
+      [&](int owner, const OwnerRec& o, uint32_t rank, int tx, int ty, bool keep) {
+        const uint4 d = s_dup[threadIdx.x / kWave][owner];
+        const uint32_t slot = d.x + rank;
+        if (keep && slot < d.y) {
+          const uint32_t row = (uint32_t)(o.width + tile - 1) >> tile_shift;  // tiles_x of the owner's view
+          keys[slot] = (KT)(d.w + (uint32_t)ty * row + (uint32_t)tx);
+          vals[slot] = d.z;
         }
       });
   // The walk repeats the preprocess count on the same stored values, so this
