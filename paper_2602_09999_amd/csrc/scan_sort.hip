@@ -240,13 +240,14 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT* __restrict__
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) wcnt[w][threadIdx.x] = 0;
   }
-  // global start of this block's run of digit t: digit start (scan of the
-  // totals) + the blocks before this one
-  uint32_t gbase;
-  {
+  // global start of this block's run of digit t: with per-digit scans, the
+  // digit start (scan of the totals) + the blocks before this one; with a flat
+  // scan of the digit-major histogram (totals == NULL), the entry itself
+  uint32_t gbase = digit_thread ? hist_scan[(size_t)threadIdx.x * nb + blockIdx.x] : 0u;
+  if (totals) {  // uniform
     uint32_t tot;
     const uint32_t dstart = block_exclusive_scan(digit_thread ? totals[threadIdx.x] : 0u, scan_lds, &tot);
-    gbase = digit_thread ? dstart + hist_scan[(size_t)threadIdx.x * nb + blockIdx.x] : 0u;
+    gbase += digit_thread ? dstart : 0u;
   }
   __syncthreads();
 
@@ -337,24 +338,37 @@ struct SortShape<uint16_t> {
   static constexpr int kItems = FGS_SORT16_ITEMS;
 };
 
+// Up to this many blocks a pass scans its histogram with one workgroup per
+// digit (a few chunks each); beyond, one device-wide scan of the flat
+// digit-major histogram, whose entry (d, b) is then the block's global start.
+constexpr uint32_t kColscanMaxBlocks = 2048;
+
 size_t radix_scratch_words(uint64_t n) {
   // the smallest block size of any sort bounds the number of blocks
   constexpr uint64_t tile = (uint64_t)kBlock * (SortShape<uint32_t>::kItems < SortShape<uint16_t>::kItems
                                                     ? SortShape<uint32_t>::kItems
                                                     : SortShape<uint16_t>::kItems);
   const uint64_t nb = (n + tile - 1) / tile;
-  return round_words((uint64_t)kRadix * nb) + round_words(kRadix);
+  return round_words((uint64_t)kRadix * nb) + round_words(kRadix) + scan_scratch_words((uint64_t)kRadix * nb);
 }
 
 template <int RB, typename KT>
 static hipError_t radix_pass(const KT* keys_in, const uint32_t* vals_in, KT* keys_out, uint32_t* vals_out,
                              uint32_t n, const uint32_t* d_count, int shift, uint32_t* hist, uint32_t* totals,
-                             uint32_t nb, hipStream_t s) {
+                             uint32_t* scan_scratch, uint32_t nb, hipStream_t s) {
   constexpr int kItems = SortShape<KT>::kItems;
   k_radix_hist<RB, KT, kItems><<<nb, kBlock, 0, s>>>(keys_in, n, d_count, shift, hist, nb);
-  k_radix_colscan<<<1u << RB, kBlock, 0, s>>>(hist, nb, totals);
+  const uint32_t* digit_totals = totals;
+  if (nb > kColscanMaxBlocks) {
+    const hipError_t e = scan_u32(SCAN_IDENTITY, hist, nullptr, nullptr, hist, (uint32_t)(nb << RB), nullptr,
+                                  scan_scratch, s);
+    if (e != hipSuccess) return e;
+    digit_totals = nullptr;
+  } else {
+    k_radix_colscan<<<1u << RB, kBlock, 0, s>>>(hist, nb, totals);
+  }
   k_radix_scatter<RB, KT, kItems><<<nb, kBlock, 0, s>>>(keys_in, vals_in, keys_out, vals_out, n, d_count, shift,
-                                                        hist, totals, nb);
+                                                        hist, digit_totals, nb);
   return hipGetLastError();
 }
 
@@ -370,6 +384,7 @@ static hipError_t radix_sort_impl(KT* keys[2], uint32_t* vals[2], uint32_t n, co
   const uint32_t nb = ceil_div(n, (uint64_t)kBlock * SortShape<KT>::kItems);
   uint32_t* hist = scratch;
   uint32_t* totals = scratch + round_words((size_t)kRadix * nb);
+  uint32_t* scan_scratch = totals + round_words(kRadix);
   const int bits = end_bit - begin_bit;
   const int passes = (bits + kRadixBits - 1) / kRadixBits;
   int shift = begin_bit;
@@ -379,14 +394,14 @@ static hipError_t radix_sort_impl(KT* keys[2], uint32_t* vals[2], uint32_t n, co
     KT* kout = (p + 1 == passes && !keep_keys) ? nullptr : keys[cur ^ 1];
     hipError_t e = hipSuccess;
     switch (rb) {
-      case 1: e = radix_pass<1, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
-      case 2: e = radix_pass<2, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
-      case 3: e = radix_pass<3, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
-      case 4: e = radix_pass<4, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
-      case 5: e = radix_pass<5, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
-      case 6: e = radix_pass<6, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
-      case 7: e = radix_pass<7, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
-      default: e = radix_pass<8, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, nb, s); break;
+      case 1: e = radix_pass<1, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, scan_scratch, nb, s); break;
+      case 2: e = radix_pass<2, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, scan_scratch, nb, s); break;
+      case 3: e = radix_pass<3, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, scan_scratch, nb, s); break;
+      case 4: e = radix_pass<4, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, scan_scratch, nb, s); break;
+      case 5: e = radix_pass<5, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, scan_scratch, nb, s); break;
+      case 6: e = radix_pass<6, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, scan_scratch, nb, s); break;
+      case 7: e = radix_pass<7, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, scan_scratch, nb, s); break;
+      default: e = radix_pass<8, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, scan_scratch, nb, s); break;
     }
     if (e != hipSuccess) return e;
     shift += rb;
