@@ -45,13 +45,22 @@ __device__ __forceinline__ uint32_t sh_colour(const GaussDev& g, uint32_t i, flo
   float Y[16];
   sh_basis(dx, dy, dz, Y);
   const size_t n = g.n;
-  float c0 = Y[0] * sh_load<SHB>(g.sh_dc, i), c1 = Y[0] * sh_load<SHB>(g.sh_dc, n + i),
-        c2 = Y[0] * sh_load<SHB>(g.sh_dc, 2 * n + i);
-  for (int k = 1; k < g.sh_coeffs; ++k) {
-    const size_t o = (size_t)(3 * (k - 1)) * n + i;
-    c0 = fmaf(Y[k], sh_load<SHB>(g.sh_rest, o), c0);
-    c1 = fmaf(Y[k], sh_load<SHB>(g.sh_rest, o + n), c1);
-    c2 = fmaf(Y[k], sh_load<SHB>(g.sh_rest, o + 2 * n), c2);
+  const int K = g.sh_coeffs;  // 1, 4, 9 or 16
+  // every coefficient is loaded before the first is used (a loop over the
+  // run-time count waits for each one's loads in turn)
+  float dc[3], rest[45];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) dc[q] = sh_load<SHB>(g.sh_dc, (size_t)q * n + i);
+#pragma unroll
+  for (int q = 0; q < 45; ++q) rest[q] = (q < 3 * (K - 1)) ? sh_load<SHB>(g.sh_rest, (size_t)q * n + i) : 0.0f;
+  float c0 = Y[0] * dc[0], c1 = Y[0] * dc[1], c2 = Y[0] * dc[2];
+#pragma unroll
+  for (int k = 1; k < 16; ++k) {
+    if (k < K) {  // uniform
+      c0 = fmaf(Y[k], rest[3 * (k - 1)], c0);
+      c1 = fmaf(Y[k], rest[3 * (k - 1) + 1], c1);
+      c2 = fmaf(Y[k], rest[3 * (k - 1) + 2], c2);
+    }
   }
   c0 += 0.5f; c1 += 0.5f; c2 += 0.5f;
   uint32_t flags = (c0 < 0.0f ? 1u : 0u) | (c1 < 0.0f ? 2u : 0u) | (c2 < 0.0f ? 4u : 0u);
