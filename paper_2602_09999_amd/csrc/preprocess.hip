@@ -51,8 +51,13 @@ __device__ __forceinline__ uint32_t sh_colour(const GaussDev& g, uint32_t i, flo
   float dc[3], rest[45];
 #pragma unroll
   for (int q = 0; q < 3; ++q) dc[q] = sh_load<SHB>(g.sh_dc, (size_t)q * n + i);
+  if (K == 16) {  // uniform; degree 3: no per-load guard (a guarded load is waited for inside its guard)
 #pragma unroll
-  for (int q = 0; q < 45; ++q) rest[q] = (q < 3 * (K - 1)) ? sh_load<SHB>(g.sh_rest, (size_t)q * n + i) : 0.0f;
+    for (int q = 0; q < 45; ++q) rest[q] = sh_load<SHB>(g.sh_rest, (size_t)q * n + i);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 45; ++q) rest[q] = (q < 3 * (K - 1)) ? sh_load<SHB>(g.sh_rest, (size_t)q * n + i) : 0.0f;
+  }
   float c0 = Y[0] * dc[0], c1 = Y[0] * dc[1], c2 = Y[0] * dc[2];
 #pragma unroll
   for (int k = 1; k < 16; ++k) {
