@@ -270,6 +270,15 @@ struct WalkLds {
   uint32_t owner_at[kWave];
 };
 
+// A volatile pointer into LDS that keeps its address space: through a plain
+// volatile pointer the compiler emits flat (system-coherent) loads and stores
+// and waits on them like on memory.
+typedef __attribute__((address_space(3))) volatile uint32_t lds_volatile_u32;
+template <typename T>
+__device__ __forceinline__ lds_volatile_u32* lds_volatile(T* p) {
+  return (lds_volatile_u32*)(p);
+}
+
 // Orders a wave's LDS writes before its later LDS reads by other lanes.
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -291,7 +300,7 @@ __device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, WalkLds& 
   uint32_t kept = 0;
   uint32_t tag = 0;
   L.own[lane] = OwnerRec{me.mx, me.my, me.a, me.b, me.c, me.thr, me.tx0, me.ty0, me.w, me.width, me.height, cstart};
-  volatile uint32_t* owner_at = L.owner_at;
+  lds_volatile_u32* owner_at = lds_volatile(L.owner_at);
   owner_at[lane] = 0xffffffffu;  // no step tag matches
   wave_lds_sync();
   for (uint32_t c0 = 0; c0 < total; c0 += kWave, tag += 0x100u) {

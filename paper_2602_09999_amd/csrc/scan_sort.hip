@@ -236,6 +236,19 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT* __restrict__
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const bool digit_thread = threadIdx.x < R;
+  // Wave w owns items [base + w*64*ITEMS, base + (w+1)*64*ITEMS), visited 64
+  // at a time in index order, so (wave, step, lane) order is the input order.
+  // The block's loads go out first, so that their latency overlaps the digit
+  // starts' loads and the barrier below.
+  const uint32_t wbase = base + wave * (kWave * ITEMS);
+  uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const uint32_t i = wbase + k * kWave + lane;
+    const bool valid = i < count;
+    key[k] = valid ? (uint32_t)keys_in[i] : 0u;
+    val[k] = valid ? vals_in[i] : 0u;
+  }
   if (digit_thread) {
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) wcnt[w][threadIdx.x] = 0;
@@ -251,34 +264,28 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT* __restrict__
   }
   __syncthreads();
 
-  // Wave w owns items [base + w*64*ITEMS, base + (w+1)*64*ITEMS), visited 64
-  // at a time in index order, so (wave, step, lane) order is the input order.
-  const uint32_t wbase = base + wave * (kWave * ITEMS);
-  const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  volatile uint32_t* my_cnt = wcnt[wave];
-  uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
-#pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
-    const uint32_t i = wbase + k * kWave + lane;
-    const bool valid = i < count;
-    key[k] = valid ? (uint32_t)keys_in[i] : 0u;
-    val[k] = valid ? vals_in[i] : 0u;
-  }
+  lds_volatile_u32* my_cnt = lds_volatile(wcnt[wave]);
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     const bool valid = wbase + k * kWave + lane < count;
     const uint32_t d = (key[k] >> shift) & (R - 1);
-    uint64_t peers = __ballot(valid);
+    // lanes holding the same digit: the AND over the digit's bits of the
+    // ballot of that bit or of its complement, as two 32-bit halves
+    const uint64_t v = __ballot(valid);
+    uint32_t plo = (uint32_t)v, phi = (uint32_t)(v >> 32);
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t m = __ballot(bit);
-      peers &= bit ? m : ~m;
+      // the bit as 0 or all ones (sign-extended one-bit field)
+      const uint32_t x = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+      const uint64_t m = __ballot(x != 0u);
+      plo &= ~((uint32_t)m ^ x);
+      phi &= ~((uint32_t)(m >> 32) ^ x);
     }
-    const uint32_t below = (uint32_t)__popcll(peers & lanes_below);
+    // peers in lanes below this one, and in all
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));
     uint32_t before = 0;
     if (valid) before = my_cnt[d];           // every lane reads before the leader writes
-    if (valid && below == 0) my_cnt[d] = before + (uint32_t)__popcll(peers);
+    if (valid && below == 0) my_cnt[d] = before + (uint32_t)(__popc(plo) + __popc(phi));
     rank[k] = before + below;
   }
   __syncthreads();
