@@ -12,7 +12,9 @@ Culling", "Sorting"; App. B.2 "Separate Sorting"):
   tau_alpha somewhere in it: the minimum of d^T Sigma^-1 d over the tile's
   pixel-centre hull (restricted to pixels inside the image) is compared with
   2 ln(o / tau_alpha).  The minimum is 0 when mu2D lies in the hull, else it
-  is found on the hull edges that face mu2D (a clamped 1-D quadratic each).
+  is found on the hull edges that face mu2D (a clamped 1-D quadratic each,
+  whose minimiser -(b d) / c is formed with the reciprocal of c, or of a,
+  rounded once).
 * Every kept (tile, Gaussian) pair is an instance.  The per-tile lists are
   ordered by depth: the paper sorts visible Gaussians by a 32-bit depth key
   and then stably by tile, which yields the lexicographic order
@@ -169,11 +171,16 @@ def tile_rect(rec: Dict[str, np.ndarray], width: int, height: int, tile: int):
 
 
 def _edge_q(a, b, c, dfix, m_other, lo, hi, first_is_x: bool):
-    """Minimum of the quadratic form along one hull edge (FP32, fixed order)."""
+    """Minimum of the quadratic form along one hull edge (FP32, fixed order).
+
+    The unconstrained minimiser along the edge is -(b d) / c (vertical edge)
+    or -(b d) / a (horizontal edge); it is taken as -(b d) times the
+    reciprocal 1/c (1/a), the reciprocal rounded once per Gaussian."""
+    one = np.float32(1.0)
     if first_is_x:
-        t = -(b * dfix) / c
+        t = -(b * dfix) * (one / c)
     else:
-        t = -(b * dfix) / a
+        t = -(b * dfix) * (one / a)
     p = np.minimum(np.maximum(m_other + t, lo), hi)
     dvar = p - m_other
     if first_is_x:

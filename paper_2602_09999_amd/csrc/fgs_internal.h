@@ -150,10 +150,13 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nb) {
 // Keeps a tile when the minimum of d^T [[a,b],[b,c]] d over the tile's
 // pixel-centre hull (clipped to the image) is <= thr = 2 ln(o / alpha_min).
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ float edge_min_q(float a, float b, float c, float dfix, float m_other,
-                                            float lo, float hi, bool fix_is_x) {
+// The minimiser along an edge is -(b d) / c (vertical edge) or -(b d) / a
+// (horizontal), taken as -(b d) * (1/c) with the reciprocal rounded once per
+// Gaussian (ra = 1/a, rc = 1/c).
+__device__ __forceinline__ float edge_min_q(float a, float b, float c, float ra, float rc, float dfix,
+                                            float m_other, float lo, float hi, bool fix_is_x) {
 #pragma clang fp contract(off)
-  float t = fix_is_x ? (-(b * dfix)) / c : (-(b * dfix)) / a;
+  float t = fix_is_x ? (-(b * dfix)) * rc : (-(b * dfix)) * ra;
   float p = fminf(fmaxf(m_other + t, lo), hi);
   float dvar = p - m_other;
   float dx = fix_is_x ? dfix : dvar;
@@ -161,8 +164,8 @@ __device__ __forceinline__ float edge_min_q(float a, float b, float c, float dfi
   return ((a * dx) * dx + ((b + b) * dx) * dy) + (c * dy) * dy;
 }
 
-__device__ __forceinline__ bool tile_keep(float mx, float my, float a, float b, float c, float thr,
-                                          int tx, int ty, int tile, int width, int height) {
+__device__ __forceinline__ bool tile_keep(float mx, float my, float a, float b, float c, float ra, float rc,
+                                          float thr, int tx, int ty, int tile, int width, int height) {
 #pragma clang fp contract(off)
   const float x0 = (float)(tx * tile) + 0.5f;
   const float x1 = (float)min(tx * tile + tile - 1, width - 1) + 0.5f;
@@ -174,8 +177,8 @@ __device__ __forceinline__ bool tile_keep(float mx, float my, float a, float b, 
   // is the smaller of those two edge minima, and 0 inside the hull.  Both are
   // evaluated and selected without divergent branches.
   const bool out_x = left || right, out_y = top || bottom;
-  const float qX = edge_min_q(a, b, c, (left ? x0 : x1) - mx, my, y0, y1, true);
-  const float qY = edge_min_q(a, b, c, (top ? y0 : y1) - my, mx, x0, x1, false);
+  const float qX = edge_min_q(a, b, c, ra, rc, (left ? x0 : x1) - mx, my, y0, y1, true);
+  const float qY = edge_min_q(a, b, c, ra, rc, (top ? y0 : y1) - my, mx, x0, x1, false);
   const float inf = __builtin_huge_valf();
   const float q = fminf(out_x ? qX : inf, out_y ? qY : inf);
   return !(out_x || out_y) || q <= thr;
@@ -246,11 +249,12 @@ struct CandLane {
   int width, height;  // image of this Gaussian's view
 };
 
-__device__ __forceinline__ uint32_t udiv_small(uint32_t r, uint32_t w) {
-  uint32_t q = (uint32_t)((float)r * __builtin_amdgcn_rcpf((float)w));
-  if (q * w > r) --q;
-  if ((q + 1) * w <= r) ++q;
-  return q;
+// floor(r / w) for r < 2^31 from m = floor((2^32 - 1) / w): the high word of
+// r m is floor(r / w) or one less, and one step corrects it.
+__device__ __forceinline__ uint32_t div_magic(uint32_t w) { return 0xffffffffu / w; }
+__device__ __forceinline__ uint32_t udiv_magic(uint32_t r, uint32_t w, uint32_t m) {
+  const uint32_t q = __umulhi(r, m);
+  return (q + 1u) * w <= r ? q + 1u : q;
 }
 
 // What a lane needs of the Gaussian that owns its candidate: staged in LDS
@@ -258,10 +262,12 @@ __device__ __forceinline__ uint32_t udiv_small(uint32_t r, uint32_t w) {
 // cross-lane shuffle per field).
 struct alignas(16) OwnerRec {
   float mx, my, a, b;
-  float c, thr;
-  int tx0, ty0;
-  int w, width, height;
+  float c, thr, ra, rc;  // ra = 1/a, rc = 1/c (the tile test's reciprocals)
+  int tx0, ty0, w;
   uint32_t cstart;  // first candidate's position in the wave's candidate list
+  int width, height;
+  uint32_t wmagic;  // div_magic(w)
+  uint32_t pad;
 };
 
 // LDS of one wave's walk.
@@ -299,7 +305,12 @@ __device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, WalkLds& 
   const uint64_t upto = below | (1ull << lane);
   uint32_t kept = 0;
   uint32_t tag = 0;
-  L.own[lane] = OwnerRec{me.mx, me.my, me.a, me.b, me.c, me.thr, me.tx0, me.ty0, me.w, me.width, me.height, cstart};
+  {
+#pragma clang fp contract(off)
+    const float ra = me.cand ? 1.0f / me.a : 0.0f, rc = me.cand ? 1.0f / me.c : 0.0f;
+    L.own[lane] = OwnerRec{me.mx, me.my, me.a, me.b, me.c, me.thr, ra, rc, me.tx0, me.ty0, me.w, cstart,
+                           me.width, me.height, div_magic((uint32_t)max(me.w, 1)), 0u};
+  }
   lds_volatile_u32* owner_at = lds_volatile(L.owner_at);
   owner_at[lane] = 0xffffffffu;  // no step tag matches
   wave_lds_sync();
@@ -319,10 +330,10 @@ __device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, WalkLds& 
     // the running count is the one per-step value: a shuffle, with all lanes active
     const uint32_t o_kept = __shfl(kept, owner, kWave);
     const uint32_t r = pos - o.cstart;
-    const uint32_t ry = udiv_small(r, (uint32_t)o.w);
+    const uint32_t ry = udiv_magic(r, (uint32_t)o.w, o.wmagic);
     const int tx = o.tx0 + (int)(r - ry * (uint32_t)o.w);
     const int ty = o.ty0 + (int)ry;
-    const bool keep = tile_keep(o.mx, o.my, o.a, o.b, o.c, o.thr, tx, ty, tile, o.width, o.height) & valid;
+    const bool keep = tile_keep(o.mx, o.my, o.a, o.b, o.c, o.ra, o.rc, o.thr, tx, ty, tile, o.width, o.height) & valid;
     const uint64_t kb = __ballot(keep);
     const uint32_t first = o.cstart > c0 ? o.cstart - c0 : 0u;
     const uint64_t from_first = first >= 64 ? 0ull : ~((first == 0) ? 0ull : (~0ull >> (64 - first)));
