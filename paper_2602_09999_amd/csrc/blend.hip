@@ -5,8 +5,8 @@
 // One wave64 per 16x16 tile; lane l owns the four pixels (l % 16, l / 16 + 4r),
 // r = 0..3.  The tile's list is read in batches of 64 entries: lane i gathers
 // entry i's 48-byte splat record with vector loads (the next batch is in flight
-// while the current one is used) and each fragment is broadcast to the wave with
-// v_readlane -- no LDS traffic and no barriers.  The x-terms of the quadratic
+// in registers while the current one is used); the current batch sits in LDS,
+// from where every lane reads fragment k at the same address (a broadcast).  The x-terms of the quadratic
 // are shared by a lane's four pixels and the conic is pre-scaled so that alpha
 // takes one v_exp_f32.  A wave stops as soon as its 256 pixels are done.
 //
@@ -56,8 +56,20 @@ __device__ __forceinline__ void load_batch(const uint32_t* __restrict__ vals, co
   }
 }
 
-__device__ __forceinline__ float bcast(float v, int k) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+// The batch being blended, staged in LDS so that every lane reads entry k
+// with the same address (a broadcast read, no bank conflict) instead of a
+// v_readlane per field, and so that only the prefetched batch occupies
+// registers.
+struct BatchLds {
+  float4 r0[kWave], r1[kWave], r2[kWave];
+  uint32_t gid[kWave];
+};
+
+__device__ __forceinline__ void stage_batch(const Batch& b, BatchLds& L, int lane) {
+  L.r0[lane] = b.r0;
+  L.r1[lane] = b.r1;
+  L.r2[lane] = b.r2;
+  L.gid[lane] = b.gid;
 }
 
 // Splat k of a batch, broadcast to the wave, with the conic pre-scaled so that
@@ -67,14 +79,15 @@ struct Splat {
 };
 constexpr float kHalfLog2e = 0.72134752044448170368f;  // log2(e) / 2
 
-__device__ __forceinline__ Splat splat_of(const Batch& B, int k) {
+__device__ __forceinline__ Splat splat_of(const BatchLds& L, int k) {
+  const float4 r0 = L.r0[k], r1 = L.r1[k];
   Splat s;
-  s.mx = bcast(B.r0.x, k);
-  s.my = bcast(B.r0.y, k);
-  s.o = bcast(B.r0.z, k);
-  s.a = bcast(B.r1.x, k);
-  s.b = bcast(B.r1.y, k);
-  s.c = bcast(B.r1.z, k);
+  s.mx = r0.x;
+  s.my = r0.y;
+  s.o = r0.z;
+  s.a = r1.x;
+  s.b = r1.y;
+  s.c = r1.z;
   s.a2 = -kHalfLog2e * s.a;
   s.b2 = -2.0f * kHalfLog2e * s.b;
   s.c2 = -kHalfLog2e * s.c;
@@ -124,17 +137,22 @@ __global__ __launch_bounds__(kWave) void k_blend_fwd(const uint2* __restrict__ r
   const uint2 range = ranges[gt];
   const uint32_t beg = __builtin_amdgcn_readfirstlane(range.x);
   const uint32_t end = __builtin_amdgcn_readfirstlane(range.y);
-  Batch cur = {}, nxt = {};
-  load_batch(vals, rec, beg, end, lane, cur);
+  __shared__ BatchLds s_batch;
+  Batch nxt = {};
+  load_batch(vals, rec, beg, end, lane, nxt);
   bool running = beg < end;
   for (uint32_t base = beg; running && base < end; base += kWave) {
+    __syncthreads();  // (one wave) the previous batch's reads are done
+    stage_batch(nxt, s_batch, lane);
+    __syncthreads();
     if (base + kWave < end) load_batch(vals, rec, base + kWave, end, lane, nxt);
     const int cnt = (int)min((uint32_t)kWave, end - base);
     for (int k = 0; k < cnt; ++k) {
-      const Splat sp = splat_of(cur, k);
+      const Splat sp = splat_of(s_batch, k);
       const float dx = fx - sp.mx;
       const float ax = sp.a2 * dx * dx, bx = sp.b2 * dx;
-      const float cr = bcast(cur.r2.x, k), cg = bcast(cur.r2.y, k), cb = bcast(cur.r2.z, k);
+      const float4 r2 = s_batch.r2[k];
+      const float cr = r2.x, cg = r2.y, cb = r2.z;
       bool any = false;
 #pragma unroll
       for (int r = 0; r < kRows; ++r) {
@@ -156,7 +174,6 @@ __global__ __launch_bounds__(kWave) void k_blend_fwd(const uint2* __restrict__ r
         break;
       }
     }
-    cur = nxt;
   }
   const size_t hw = (size_t)cam.width * cam.height;
 #pragma unroll
@@ -301,15 +318,20 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const uint2* __restrict__ r
   const bool writer = lane < 16 && (lane & 4);
   const int wq = ((lane & 1) << 2) | (lane & 2) | ((lane >> 3) & 1);
 
-  Batch cur = {}, nxt = {};
-  load_batch(vals, rec, beg, end, lane, cur);
+  __shared__ BatchLds s_batch;
+  Batch nxt = {};
+  load_batch(vals, rec, beg, end, lane, nxt);
   for (uint32_t base = beg; base < end; base += kWave) {
+    __syncthreads();  // (one wave) the previous batch's reads are done
+    stage_batch(nxt, s_batch, lane);
+    __syncthreads();
     if (base + kWave < end) load_batch(vals, rec, base + kWave, end, lane, nxt);
     const int cnt = (int)min((uint32_t)kWave, end - base);
     for (int k = 0; k < cnt; ++k) {
       const uint32_t pos = base - beg + (uint32_t)k;
-      const Splat sp = splat_of(cur, k);
-      const float cr = bcast(cur.r2.x, k), cg = bcast(cur.r2.y, k), cb = bcast(cur.r2.z, k);
+      const Splat sp = splat_of(s_batch, k);
+      const float4 r2 = s_batch.r2[k];
+      const float cr = r2.x, cg = r2.y, cb = r2.z;
       const float dx = fx - sp.mx;
       const float ax = sp.a2 * dx * dx, bx = sp.b2 * dx;
       // Per lane, over its pixels: dG = dL/dalpha * G for the blended,
@@ -360,13 +382,12 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const uint2* __restrict__ r
       v[6] = w0; v[7] = w1; v[8] = w2;
       const float r8 = wave_reduce8(v, lane) * (wq < 5 ? sp.o : 1.0f);
       const float r1 = wave_reduce1(v[8]);
-      const uint32_t gid = (uint32_t)__builtin_amdgcn_readlane((int)cur.gid, k);
+      const uint32_t gid = s_batch.gid[k];
       // one atomic instruction for the nine sums: they are adjacent in the
       // Gaussian's [9] accumulator row
       const float val = writer ? r8 : r1;
       if ((writer || lane == 0) && val != 0.0f) unsafeAtomicAdd(accum + (size_t)gid * kGrad + (writer ? wq : 8), val);
     }
-    cur = nxt;
   }
 }
 
