@@ -185,7 +185,7 @@ fgs_status make_layout(int64_t n, const fgs_camera* cams, int32_t n_views, const
   size_t words = scan_scratch_words(vn);
   words = std::max(words, radix_scratch_words(vn));
   words = std::max(words, radix_scratch_words(uc));
-  words = std::max(words, 4 * (size_t)n_views * ((un + kBlock - 1) / kBlock));  // preprocess partials
+  words = std::max(words, stats_scratch_words((uint32_t)((size_t)n_views * ((un + kBlock - 1) / kBlock))));
   L->scratch = take(words * 4 + 256);
   L->total = off;
   L->inst_final = ((tile_key_bits(tiles) + kRadixBits - 1) / kRadixBits) & 1;
@@ -416,10 +416,11 @@ fgs_status fgs_rasterize_forward_batch(const fgs_gaussians* g, const fgs_camera*
 
   int vis_final = 0;
   if (nvis > 0) {
-    // visible compaction (prefix sum, so index order is kept) and the depth
+    // visible compaction (block offsets from the statistics, index order kept) and the depth
     // sort over the key bits that vary among the visible entries
-    FGS_HIP(scan_u32(SCAN_NONZERO, n_tiles, nullptr, nullptr, offsets, vn, nullptr, scratch, hs), "scan");
-    FGS_HIP(launch_compact_visible(n_tiles, depth_key, vn, offsets, vis_keys[0], vis_ids[0], hs), "compact");
+    FGS_HIP(launch_compact_visible(n_tiles, depth_key, n, (uint32_t)n_views, reinterpret_cast<uint4*>(scratch),
+                                   vis_keys[0], vis_ids[0], hs),
+            "compact");
     FGS_HIP(radix_sort_pairs(vis_keys, vis_ids, nvis, no_sync ? d_vis : nullptr, 0, depth_bits, scratch, &vis_final,
                              hs),
             "depth sort");

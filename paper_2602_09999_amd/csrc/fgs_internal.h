@@ -412,10 +412,16 @@ hipError_t launch_permute(const void* src, void* dst, uint32_t n, int planes, in
                           const uint32_t* perm, hipStream_t s);
 // Reduces the preprocess partials of nb blocks into the counter words,
 // including min(I, cap) and the overflow flag.
-hipError_t launch_stats(const uint4* partials, uint32_t nb, uint64_t cap, uint32_t* counters, hipStream_t s);
-hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth_key, uint32_t n,
-                                  const uint32_t* pos, uint32_t* vis_keys, uint32_t* vis_ids,
-                                  hipStream_t s);
+// Reduces the preprocess's per-block partials {visible, instances, key min,
+// key max} into the counters and replaces each block's visible count by its
+// exclusive prefix (the block's first compacted position).
+// partials sits at the start of a scratch of stats_scratch_words(nb) words.
+hipError_t launch_stats(uint4* partials, uint32_t nb, uint64_t cap, uint32_t* counters, hipStream_t s);
+size_t stats_scratch_words(uint32_t nb);
+// n: Gaussians per view; entries j = v n + i of n_views views; partials as
+// left by launch_stats (nb = n_views * ceil(n / 256)).
+hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth_key, uint32_t n, uint32_t n_views,
+                                  uint4* partials, uint32_t* vis_keys, uint32_t* vis_ids, hipStream_t s);
 // Tile keys are written as uint16 (key_bytes 2: every global tile id and the
 // out-of-range id `tiles` fit) or uint32 (key_bytes 4).
 hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uint32_t n, const uint32_t* offsets,

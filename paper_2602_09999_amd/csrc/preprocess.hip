@@ -254,36 +254,84 @@ hipError_t launch_preprocess(const GaussDev& g, const ViewSet& vs, const SetDev&
 // instance count I (the sum of the per-Gaussian counts, independent of the
 // depth order) and the range of the visible depth keys -- from the
 // preprocess blocks' partials.  One workgroup; writes every counter word.
-__global__ __launch_bounds__(kBlock) void k_stats(const uint4* __restrict__ partials, uint32_t nb, uint64_t cap,
-                                                  uint32_t* __restrict__ c) {
-  __shared__ uint32_t s_vis[kBlock / kWave], s_min[kBlock / kWave], s_max[kBlock / kWave];
+// Statistics read after the preprocess (visible count, instance count,
+// smallest and largest visible depth key, sort count and overflow flag) and
+// each preprocess block's first position in the compacted list, in two
+// launches.  k_stats_group: workgroup g takes partials [256 g, 256 g + 256)
+// (coalesced), replaces each block's visible count by its exclusive prefix
+// within the group and writes the group's totals.  k_stats_final: one
+// workgroup over the groups: the counters, and each group's first position.
+struct StatsGroup {
+  uint32_t vis, kmin, kmax, pad;
+  unsigned long long sum;
+};
+
+__global__ __launch_bounds__(kBlock) void k_stats_group(uint4* __restrict__ partials, uint32_t nb,
+                                                        StatsGroup* __restrict__ groups) {
+  __shared__ uint32_t s_lds[kBlock / kWave];
+  __shared__ uint32_t s_min[kBlock / kWave], s_max[kBlock / kWave];
   __shared__ unsigned long long s_sum[kBlock / kWave];
-  uint32_t vis = 0, kmin = 0xffffffffu, kmax = 0u;
-  unsigned long long sum = 0;
-  for (uint32_t b = threadIdx.x; b < nb; b += kBlock) {
-    const uint4 t = partials[b];
-    vis += t.x;
-    sum += t.y;
-    kmin = min(kmin, t.z);
-    kmax = max(kmax, t.w);
-  }
+  const uint32_t b = blockIdx.x * kBlock + threadIdx.x;
+  const uint4 t = b < nb ? partials[b] : make_uint4(0u, 0u, 0xffffffffu, 0u);
+  uint32_t total;
+  const uint32_t ex = block_exclusive_scan(t.x, s_lds, &total);
+  if (b < nb) partials[b].x = ex;
+  unsigned long long sum = t.y;
+  uint32_t kmin = t.z, kmax = t.w;
 #pragma unroll
   for (int d = 1; d < kWave; d <<= 1) {
-    vis += __shfl_xor(vis, d, kWave);
     sum += __shfl_xor(sum, d, kWave);
     kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, d, kWave));
     kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, d, kWave));
   }
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   if (lane == 0) {
-    s_vis[wave] = vis; s_min[wave] = kmin; s_max[wave] = kmax; s_sum[wave] = sum;
+    s_min[wave] = kmin; s_max[wave] = kmax; s_sum[wave] = sum;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < kBlock / kWave; ++w) {
-      vis += s_vis[w]; sum += s_sum[w]; kmin = min(kmin, s_min[w]); kmax = max(kmax, s_max[w]);
+      sum += s_sum[w]; kmin = min(kmin, s_min[w]); kmax = max(kmax, s_max[w]);
     }
-    c[kStatVisible] = vis;
+    groups[blockIdx.x] = StatsGroup{total, kmin, kmax, 0u, sum};
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_stats_final(const StatsGroup* __restrict__ groups, uint32_t ng,
+                                                        uint64_t cap, uint32_t* __restrict__ c,
+                                                        uint32_t* __restrict__ group_start) {
+  __shared__ uint32_t s_lds[kBlock / kWave];
+  __shared__ uint32_t s_min[kBlock / kWave], s_max[kBlock / kWave];
+  __shared__ unsigned long long s_sum[kBlock / kWave];
+  uint32_t carry = 0, kmin = 0xffffffffu, kmax = 0u;
+  unsigned long long sum = 0;
+  for (uint32_t g0 = 0; g0 < ng; g0 += kBlock) {
+    const uint32_t g = g0 + threadIdx.x;
+    const StatsGroup t = g < ng ? groups[g] : StatsGroup{0u, 0xffffffffu, 0u, 0u, 0ull};
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(t.vis, s_lds, &tot);
+    if (g < ng) group_start[g] = carry + ex;
+    carry += tot;
+    sum += t.sum;
+    kmin = min(kmin, t.kmin);
+    kmax = max(kmax, t.kmax);
+  }
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    sum += __shfl_xor(sum, d, kWave);
+    kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, d, kWave));
+    kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, d, kWave));
+  }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  if (lane == 0) {
+    s_min[wave] = kmin; s_max[wave] = kmax; s_sum[wave] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / kWave; ++w) {
+      sum += s_sum[w]; kmin = min(kmin, s_min[w]); kmax = max(kmax, s_max[w]);
+    }
+    c[kStatVisible] = carry;
     c[kStatKeyMin] = kmin;
     c[kStatKeyMax] = kmax;
     c[kStatDepthBuf] = 0u;
@@ -291,6 +339,11 @@ __global__ __launch_bounds__(kBlock) void k_stats(const uint4* __restrict__ part
     c[kStatSortCount] = (uint32_t)(sum < cap ? sum : cap);
     c[kStatOverflow] = sum > cap ? 1u : 0u;
   }
+}
+
+size_t stats_scratch_words(uint32_t nb) {
+  const size_t ng = (nb + kBlock - 1) / kBlock;
+  return 4 * (size_t)nb + round_up64(sizeof(StatsGroup) / 4 * ng) + round_up64(ng);
 }
 
 __global__ void k_set_word(uint32_t* __restrict__ p, uint32_t v) {
@@ -302,30 +355,62 @@ hipError_t launch_set_word(uint32_t* p, uint32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_stats(const uint4* partials, uint32_t nb, uint64_t cap, uint32_t* counters, hipStream_t s) {
-  k_stats<<<1, kBlock, 0, s>>>(partials, nb, cap, counters);
+// The group records and group starts follow the nb partials in the same scratch.
+static StatsGroup* stats_groups(uint4* partials, uint32_t nb) {
+  return reinterpret_cast<StatsGroup*>(reinterpret_cast<uint32_t*>(partials) + 4 * (size_t)nb);
+}
+static uint32_t* stats_group_start(uint4* partials, uint32_t nb) {
+  const size_t ng = (nb + kBlock - 1) / kBlock;
+  return reinterpret_cast<uint32_t*>(partials) + 4 * (size_t)nb + round_up64(sizeof(StatsGroup) / 4 * ng);
+}
+
+hipError_t launch_stats(uint4* partials, uint32_t nb, uint64_t cap, uint32_t* counters, hipStream_t s) {
+  const uint32_t ng = ceil_div(nb, kBlock);
+  k_stats_group<<<ng, kBlock, 0, s>>>(partials, nb, stats_groups(partials, nb));
+  k_stats_final<<<1, kBlock, 0, s>>>(stats_groups(partials, nb), ng, cap, counters,
+                                     stats_group_start(partials, nb));
   return hipGetLastError();
 }
 
-// Writes (depth key, index) of every Gaussian with at least one instance at its
-// prefix-sum position: index order is kept, which the stable depth sort turns
-// into the (depth, index) tie-break.
+// Writes (depth key, entry index) of every entry with at least one instance,
+// in index order (which the stable depth sort turns into the (depth, index)
+// tie-break).  Same grid as the preprocess: block (b, v), preprocess block
+// q = v * gridDim.x + b, takes entries v n + [256 b, 256 b + 256), starts at
+// its group's start plus its prefix within the group, and ranks its visible
+// entries with ballots.
 __global__ __launch_bounds__(kBlock) void k_compact(const uint32_t* __restrict__ n_tiles,
                                                     const uint32_t* __restrict__ depth_key, uint32_t n,
-                                                    const uint32_t* __restrict__ pos,
+                                                    const uint4* __restrict__ partials,
+                                                    const uint32_t* __restrict__ group_start,
                                                     uint32_t* __restrict__ vis_keys,
                                                     uint32_t* __restrict__ vis_ids) {
+  __shared__ uint32_t s_w[kBlock / kWave];
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n || n_tiles[i] == 0) return;
-  const uint32_t p = pos[i];
-  vis_keys[p] = depth_key[i];
-  vis_ids[p] = i;
+  const size_t j = (size_t)blockIdx.y * n + i;
+  const bool vis = i < n && n_tiles[j] != 0u;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const uint64_t m = __ballot(vis);
+  const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  if (lane == 0) s_w[wave] = (uint32_t)__popcll(m);
+  __syncthreads();
+  uint32_t pre = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / kWave; ++w) pre += (w < wave) ? s_w[w] : 0u;
+  if (vis) {
+    const size_t q = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const uint32_t p = group_start[q / kBlock] + partials[q].x + pre + below;
+    vis_keys[p] = depth_key[j];
+    vis_ids[p] = (uint32_t)j;
+  }
 }
 
-hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth_key, uint32_t n,
-                                  const uint32_t* pos, uint32_t* vis_keys, uint32_t* vis_ids, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  k_compact<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n_tiles, depth_key, n, pos, vis_keys, vis_ids);
+hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth_key, uint32_t n, uint32_t n_views,
+                                  uint4* partials, uint32_t* vis_keys, uint32_t* vis_ids, hipStream_t s) {
+  if (n == 0 || n_views == 0) return hipSuccess;
+  const dim3 grid(ceil_div(n, kBlock), n_views);
+  const uint32_t nb = grid.x * n_views;
+  k_compact<<<grid, kBlock, 0, s>>>(n_tiles, depth_key, n, partials, stats_group_start(partials, nb), vis_keys,
+                                    vis_ids);
   return hipGetLastError();
 }
 
