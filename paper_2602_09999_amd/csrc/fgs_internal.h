@@ -167,10 +167,12 @@ __device__ __forceinline__ float edge_min_q(float a, float b, float c, float ra,
 __device__ __forceinline__ bool tile_keep(float mx, float my, float a, float b, float c, float ra, float rc,
                                           float thr, int tx, int ty, int tile, int width, int height) {
 #pragma clang fp contract(off)
-  const float x0 = (float)(tx * tile) + 0.5f;
-  const float x1 = (float)min(tx * tile + tile - 1, width - 1) + 0.5f;
-  const float y0 = (float)(ty * tile) + 0.5f;
-  const float y1 = (float)min(ty * tile + tile - 1, height - 1) + 0.5f;
+  // tile is a power of two (8, 16 or 32): shifts, not integer multiplies
+  const int sh = __builtin_ctz((unsigned)tile);
+  const float x0 = (float)(tx << sh) + 0.5f;
+  const float x1 = (float)min(((tx + 1) << sh) - 1, width - 1) + 0.5f;
+  const float y0 = (float)(ty << sh) + 0.5f;
+  const float y1 = (float)min(((ty + 1) << sh) - 1, height - 1) + 0.5f;
   const bool left = mx < x0, right = mx > x1, top = my < y0, bottom = my > y1;
   // At most one vertical and one horizontal edge face the centre (left and
   // right exclude each other, as do top and bottom): the minimum over the hull
@@ -250,11 +252,12 @@ struct CandLane {
 };
 
 // floor(r / w) for r < 2^31 from m = floor((2^32 - 1) / w): the high word of
-// r m is floor(r / w) or one less, and one step corrects it.
+// r m is floor(r / w) or one less, and one step corrects it.  Tile
+// coordinates are 16-bit, so the quotient and w fit the 24-bit multiplier.
 __device__ __forceinline__ uint32_t div_magic(uint32_t w) { return 0xffffffffu / w; }
 __device__ __forceinline__ uint32_t udiv_magic(uint32_t r, uint32_t w, uint32_t m) {
   const uint32_t q = __umulhi(r, m);
-  return (q + 1u) * w <= r ? q + 1u : q;
+  return __umul24(q + 1u, w) <= r ? q + 1u : q;
 }
 
 // What a lane needs of the Gaussian that owns its candidate: staged in LDS
@@ -331,7 +334,7 @@ __device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, WalkLds& 
     const uint32_t o_kept = __shfl(kept, owner, kWave);
     const uint32_t r = pos - o.cstart;
     const uint32_t ry = udiv_magic(r, (uint32_t)o.w, o.wmagic);
-    const int tx = o.tx0 + (int)(r - ry * (uint32_t)o.w);
+    const int tx = o.tx0 + (int)(r - __umul24(ry, (uint32_t)o.w));
     const int ty = o.ty0 + (int)ry;
     const bool keep = tile_keep(o.mx, o.my, o.a, o.b, o.c, o.ra, o.rc, o.thr, tx, ty, tile, o.width, o.height) & valid;
     const uint64_t kb = __ballot(keep);

@@ -464,7 +464,7 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
         const uint32_t slot = d.x + rank;
         if (keep && slot < d.y) {
           const uint32_t row = (uint32_t)(o.width + tile - 1) >> tile_shift;  // tiles_x of the owner's view
-          keys[slot] = (KT)(d.w + (uint32_t)ty * row + (uint32_t)tx);
+          keys[slot] = (KT)(d.w + __umul24((uint32_t)ty, row) + (uint32_t)tx);  // 16-bit tile coordinates
           vals[slot] = d.z;
         }
       });
