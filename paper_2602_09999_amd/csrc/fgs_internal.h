@@ -362,13 +362,13 @@ inline uint64_t round_up64(uint64_t w) { return (w + 63) & ~uint64_t(63); }
 // p[0..n) = v (a kernel, so captured graphs contain no memset nodes)
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 
-enum ScanMode { SCAN_IDENTITY = 0, SCAN_NONZERO = 1, SCAN_GATHER = 2 };
+enum ScanMode { SCAN_IDENTITY = 0, SCAN_GATHER = 2 };
 
 // Scratch words needed by scan_u32 for n items.
 size_t scan_scratch_words(uint64_t n);
-// Exclusive scan of x[i] for i < n where x[i] = in[i] (IDENTITY), in[i] != 0
-// (NONZERO) or, for i < *d_count, in[idx[i]] (GATHER; 0 beyond the count; out
-// must not alias in or idx).
+// Exclusive scan of x[i] for i < n where x[i] = in[i] (IDENTITY) or, for
+// i < *d_count, in[idx[i]] (GATHER; 0 beyond the count; out must not alias in
+// or idx).
 // Writes out[0..n) and, when d_total != NULL, the grand total to *d_total.
 hipError_t scan_u32(ScanMode mode, const uint32_t* in, const uint32_t* idx, const uint32_t* d_count,
                     uint32_t* out, uint32_t n, uint32_t* d_total, uint32_t* scratch, hipStream_t s);

@@ -36,7 +36,6 @@ __device__ __forceinline__ uint32_t scan_load(const uint32_t* __restrict__ in,
                                               const uint32_t* __restrict__ idx, uint32_t count,
                                               uint32_t i) {
   if (MODE == SCAN_IDENTITY) return in[i];
-  if (MODE == SCAN_NONZERO) return in[i] != 0u ? 1u : 0u;
   return i < count ? in[idx[i]] : 0u;
 }
 
@@ -128,7 +127,6 @@ hipError_t scan_u32(ScanMode mode, const uint32_t* in, const uint32_t* idx, cons
                     uint32_t* out, uint32_t n, uint32_t* d_total, uint32_t* scratch, hipStream_t s) {
   switch (mode) {
     case SCAN_IDENTITY: return scan_impl<SCAN_IDENTITY>(in, idx, d_count, out, n, d_total, scratch, s);
-    case SCAN_NONZERO: return scan_impl<SCAN_NONZERO>(in, idx, d_count, out, n, d_total, scratch, s);
     default: return scan_impl<SCAN_GATHER>(in, idx, d_count, out, n, d_total, scratch, s);
   }
 }
