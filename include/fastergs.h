@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define FGS_ABI_VERSION 8
+#define FGS_ABI_VERSION 9
 
 typedef enum fgs_status {
   FGS_OK = 0,
@@ -153,6 +153,13 @@ typedef struct fgs_forward_stats {
  * With several views, the per-Gaussian regions (rec, n_tiles, depth_key,
  * vis_*, accum) hold n_views * n entries, entry v * n + i for view v.
  *   vis_ids    uint32[n] x2 ping-pong (see counters[3])
+ *   dup_scan   the duplication's look-back words (offsets of each visible
+ *                           Gaussian's instances are found in the kernel):
+ *                           word 0 the number of workgroups whose look-back
+ *                           wait ran out and that summed the earlier counts
+ *                           directly (exact, only slower; 0 in normal
+ *                           operation), from word 64 one 64-bit status per
+ *                           256 entries
  *   inst_keys  uint16 or uint32 (inst_key_bytes) [cap] x2, inst_vals
  *                           uint32[cap] x2: global tile ids and Gaussian ids;
  *                           sorted in [inst_final].  Keys are 16-bit when
@@ -168,7 +175,7 @@ typedef struct fgs_forward_stats {
 typedef struct fgs_layout {
   size_t rec, n_tiles, depth_key, counters;
   size_t vis_keys[2], vis_ids[2];
-  size_t inst_offsets;
+  size_t dup_scan;
   size_t inst_keys[2], inst_vals[2];
   size_t ranges, accum, touched, touched_list, slot_of, sparse_grads, scratch, total;
   int32_t inst_final;

@@ -48,7 +48,7 @@ class ForwardStats(ctypes.Structure):
 class Layout(ctypes.Structure):
     _fields_ = [("rec", c_size_t), ("n_tiles", c_size_t), ("depth_key", c_size_t),
                 ("counters", c_size_t), ("vis_keys", c_size_t * 2), ("vis_ids", c_size_t * 2),
-                ("inst_offsets", c_size_t), ("inst_keys", c_size_t * 2), ("inst_vals", c_size_t * 2),
+                ("dup_scan", c_size_t), ("inst_keys", c_size_t * 2), ("inst_vals", c_size_t * 2),
                 ("ranges", c_size_t), ("accum", c_size_t), ("touched", c_size_t), ("touched_list", c_size_t),
                 ("slot_of", c_size_t), ("sparse_grads", c_size_t), ("scratch", c_size_t),
                 ("total", c_size_t),

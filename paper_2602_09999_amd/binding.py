@@ -502,6 +502,12 @@ class Rasterizer:
         the GPU."""
         return bool(int(self.view("counters", 8)[7].item()))
 
+    def lookback_slow_count(self) -> int:
+        """Workgroups of the last forward's duplication whose look-back wait ran
+        out and that summed the earlier counts directly (exact, slower; 0 in
+        normal operation); waits for the GPU."""
+        return int(self.view("dup_scan", 1)[0].item())
+
     # -- views of the workspace (for inspection and tests)
     def view(self, field: str, count: int, dtype=torch.int32, index: Optional[int] = None) -> torch.Tensor:
         lay = self.layout()

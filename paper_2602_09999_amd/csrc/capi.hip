@@ -170,7 +170,7 @@ fgs_status make_layout(int64_t n, const fgs_camera* cams, int32_t n_views, const
   L->vis_keys[1] = take(vn * 4);
   L->vis_ids[0] = take(vn * 4);
   L->vis_ids[1] = take(vn * 4);
-  L->inst_offsets = take((vn + 1) * 4);
+  L->dup_scan = take(dup_scan_words(vn) * 4);
   const int key_bytes = tile_key_bytes(tiles);
   L->inst_keys[0] = take(uc * key_bytes);
   L->inst_keys[1] = take(uc * key_bytes);
@@ -182,8 +182,7 @@ fgs_status make_layout(int64_t n, const fgs_camera* cams, int32_t n_views, const
   L->touched_list = take(un * 4);
   L->slot_of = take(un * 4);
   L->sparse_grads = take(un * 59 * 4);
-  size_t words = scan_scratch_words(vn);
-  words = std::max(words, radix_scratch_words(vn));
+  size_t words = radix_scratch_words(vn);
   words = std::max(words, radix_scratch_words(uc));
   words = std::max(words, stats_scratch_words((uint32_t)((size_t)n_views * ((un + kBlock - 1) / kBlock))));
   L->scratch = take(words * 4 + 256);
@@ -361,7 +360,7 @@ fgs_status fgs_rasterize_forward_batch(const fgs_gaussians* g, const fgs_camera*
   uint32_t* counters = at<uint32_t>(workspace, L.counters);
   uint32_t* vis_keys[2] = {at<uint32_t>(workspace, L.vis_keys[0]), at<uint32_t>(workspace, L.vis_keys[1])};
   uint32_t* vis_ids[2] = {at<uint32_t>(workspace, L.vis_ids[0]), at<uint32_t>(workspace, L.vis_ids[1])};
-  uint32_t* offsets = at<uint32_t>(workspace, L.inst_offsets);
+  uint32_t* dup_scan = at<uint32_t>(workspace, L.dup_scan);
   void* ikeys[2] = {at<uint8_t>(workspace, L.inst_keys[0]), at<uint8_t>(workspace, L.inst_keys[1])};
   const int key_bytes = L.inst_key_bytes;
   uint32_t* ivals[2] = {at<uint32_t>(workspace, L.inst_vals[0]), at<uint32_t>(workspace, L.inst_vals[1])};
@@ -419,22 +418,19 @@ fgs_status fgs_rasterize_forward_batch(const fgs_gaussians* g, const fgs_camera*
     // visible compaction (block offsets from the statistics, index order kept) and the depth
     // sort over the key bits that vary among the visible entries
     FGS_HIP(launch_compact_visible(n_tiles, depth_key, n, (uint32_t)n_views, reinterpret_cast<uint4*>(scratch),
-                                   vis_keys[0], vis_ids[0], hs),
+                                   vis_keys[0], vis_ids[0], dup_scan, dup_scan_words(vn), hs),
             "compact");
     FGS_HIP(radix_sort_pairs(vis_keys, vis_ids, nvis, no_sync ? d_vis : nullptr, 0, depth_bits, scratch, &vis_final,
                              hs),
             "depth sort");
     FGS_HIP(launch_set_word(counters + kStatDepthBuf, (uint32_t)vis_final, hs), "depth buffer note");
-    // instance offsets in depth order
-    FGS_HIP(scan_u32(SCAN_GATHER, n_tiles, vis_ids[vis_final], d_vis, offsets, nvis, nullptr, scratch, hs),
-            "offset scan");
   }
 
   FGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, (uint64_t)tiles * 2, hs), "ranges clear");
   if (inst > 0 && nvis > 0) {
     FGS_TIMED("duplicate", hs,
-              launch_duplicate(vis_ids[vis_final], d_vis, nvis, offsets, rec, vs, n, st->tile, cap, ikeys[0],
-                               key_bytes, ivals[0], hs),
+              launch_duplicate(vis_ids[vis_final], d_vis, nvis, dup_scan, dup_scan, rec, vs, n, st->tile, cap,
+                               ikeys[0], key_bytes, ivals[0], hs),
               "duplicate");
     int inst_final = 0;
     const int bits = tile_key_bits(tiles);

@@ -362,16 +362,12 @@ inline uint64_t round_up64(uint64_t w) { return (w + 63) & ~uint64_t(63); }
 // p[0..n) = v (a kernel, so captured graphs contain no memset nodes)
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 
-enum ScanMode { SCAN_IDENTITY = 0, SCAN_GATHER = 2 };
-
 // Scratch words needed by scan_u32 for n items.
 size_t scan_scratch_words(uint64_t n);
-// Exclusive scan of x[i] for i < n where x[i] = in[i] (IDENTITY) or, for
-// i < *d_count, in[idx[i]] (GATHER; 0 beyond the count; out must not alias in
-// or idx).
-// Writes out[0..n) and, when d_total != NULL, the grand total to *d_total.
-hipError_t scan_u32(ScanMode mode, const uint32_t* in, const uint32_t* idx, const uint32_t* d_count,
-                    uint32_t* out, uint32_t n, uint32_t* d_total, uint32_t* scratch, hipStream_t s);
+// Exclusive scan of in[0..n) into out (which may alias in); writes the grand
+// total to *d_total when d_total != NULL.
+hipError_t scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* d_total, uint32_t* scratch,
+                    hipStream_t s);
 
 size_t radix_scratch_words(uint64_t n);
 // Stable LSD radix sort of (key, value) pairs on bits [begin_bit, end_bit).
@@ -422,14 +418,20 @@ hipError_t launch_permute(const void* src, void* dst, uint32_t n, int planes, in
 hipError_t launch_stats(uint4* partials, uint32_t nb, uint64_t cap, uint32_t* counters, hipStream_t s);
 size_t stats_scratch_words(uint32_t nb);
 // n: Gaussians per view; entries j = v n + i of n_views views; partials as
-// left by launch_stats (nb = n_views * ceil(n / 256)).
+// left by launch_stats (nb = n_views * ceil(n / 256)).  Also zeroes
+// clear[0 .. clear_words) (the duplication's look-back words).
 hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth_key, uint32_t n, uint32_t n_views,
-                                  uint4* partials, uint32_t* vis_keys, uint32_t* vis_ids, hipStream_t s);
+                                  uint4* partials, uint32_t* vis_keys, uint32_t* vis_ids, uint32_t* clear,
+                                  size_t clear_words, hipStream_t s);
 // Tile keys are written as uint16 (key_bytes 2: every global tile id and the
-// out-of-range id `tiles` fit) or uint32 (key_bytes 4).
-hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uint32_t n, const uint32_t* offsets,
-                            const float4* rec, const ViewSet& vs, uint32_t n_gauss, int tile, uint32_t cap,
-                            void* keys, int key_bytes, uint32_t* vals, hipStream_t s);
+// out-of-range id `tiles` fit) or uint32 (key_bytes 4).  Each visible entry's
+// first slot is found by the kernel (decoupled look-back over its workgroups
+// in dup_scan, dup_scan_words(n) words zeroed beforehand; a workgroup whose
+// wait runs out sums the earlier counts itself and adds 1 to *slow).
+size_t dup_scan_words(uint64_t n);
+hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uint32_t n, uint32_t* dup_scan,
+                            uint32_t* slow, const float4* rec, const ViewSet& vs, uint32_t n_gauss, int tile,
+                            uint32_t cap, void* keys, int key_bytes, uint32_t* vals, hipStream_t s);
 // Ranges of the first min(*d_count, n) (or n) sorted keys.
 hipError_t launch_tile_ranges(const void* keys, int key_bytes, uint32_t n, const uint32_t* d_count, uint32_t tiles,
                               uint2* ranges, hipStream_t s);

@@ -383,8 +383,15 @@ __global__ __launch_bounds__(kBlock) void k_compact(const uint32_t* __restrict__
                                                     const uint4* __restrict__ partials,
                                                     const uint32_t* __restrict__ group_start,
                                                     uint32_t* __restrict__ vis_keys,
-                                                    uint32_t* __restrict__ vis_ids) {
+                                                    uint32_t* __restrict__ vis_ids,
+                                                    uint32_t* __restrict__ clear, size_t clear_words) {
   __shared__ uint32_t s_w[kBlock / kWave];
+  {  // also clears the duplication's look-back words (and flag) for this forward
+    const size_t nthreads = (size_t)gridDim.x * gridDim.y * kBlock;
+    for (size_t w = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * kBlock + threadIdx.x; w < clear_words;
+         w += nthreads)
+      clear[w] = 0u;
+  }
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
   const size_t j = (size_t)blockIdx.y * n + i;
   const bool vis = i < n && n_tiles[j] != 0u;
@@ -405,39 +412,117 @@ __global__ __launch_bounds__(kBlock) void k_compact(const uint32_t* __restrict__
 }
 
 hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth_key, uint32_t n, uint32_t n_views,
-                                  uint4* partials, uint32_t* vis_keys, uint32_t* vis_ids, hipStream_t s) {
+                                  uint4* partials, uint32_t* vis_keys, uint32_t* vis_ids, uint32_t* clear,
+                                  size_t clear_words, hipStream_t s) {
   if (n == 0 || n_views == 0) return hipSuccess;
   const dim3 grid(ceil_div(n, kBlock), n_views);
   const uint32_t nb = grid.x * n_views;
   k_compact<<<grid, kBlock, 0, s>>>(n_tiles, depth_key, n, partials, stats_group_start(partials, nb), vis_keys,
-                                    vis_ids);
+                                    vis_ids, clear, clear_words);
   return hipGetLastError();
 }
 
-// Each visible Gaussian, in depth order, writes its kept tiles at its offset.
+// Duplication with its own offsets.  Each visible Gaussian, in depth order,
+// writes its kept tiles starting at the sum of the counts of the Gaussians
+// before it; the counts come from the records the kernel reads anyway (no
+// separate scan gathering them in depth order).  Workgroup b sums its 256
+// counts, publishes the sum, then adds the sums of workgroups 0..b-1 by
+// decoupled look-back and publishes its inclusive prefix.  A workgroup only
+// waits for workgroups with smaller indices, which the dispatcher starts
+// first and which never wait for it.  The results do not rest on that order:
+// every wait is bounded, and a wait that runs out sums the counts of all
+// earlier entries directly (slow, exact) and counts itself in `slow`.
+//
 // A wave handles 64 consecutive Gaussians and spreads their candidate tiles
 // over its lanes (load-balanced walk), so the wave's kept tiles are written as
 // one contiguous, coalesced run.  Writes never pass a Gaussian's own count nor
-// `cap`.
-// Entries are (view, Gaussian) indices j = v n_gauss + i; the key of an
-// instance is its global tile id tile_base[v] + ty tiles_x(v) + tx.
+// `cap`.  Entries are (view, Gaussian) indices j = v n_gauss + i; the key of
+// an instance is its global tile id tile_base[v] + ty tiles_x(v) + tx.
+//
+// dup_scan: word 0 the slow-path count, then at word 64 one 64-bit status per
+// workgroup: 0 (not published), kDupAggregate | sum, kDupInclusive | prefix;
+// cleared by the compaction.
+constexpr uint64_t kDupAggregate = 1ull << 32, kDupInclusive = 2ull << 32;
+constexpr uint32_t kDupSpinLimit = 1u << 14;
+constexpr uint32_t kDupStatusWord = 64;
+
+size_t dup_scan_words(uint64_t n) { return kDupStatusWord + 2 * ((n + kBlock - 1) / kBlock); }
+
+__device__ __forceinline__ uint64_t dup_status_load(uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void dup_status_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The count of entry q: the last word of its record's fourth float4.
+__device__ __forceinline__ uint32_t dup_count(const uint32_t* __restrict__ vis_ids, const float4* __restrict__ rec,
+                                              uint32_t q) {
+  return __float_as_uint(rec[kRecWords * (size_t)vis_ids[q] + 3].z);
+}
+
+// Wave 0 of workgroup blk > 0: the sum of the counts of workgroups 0..blk-1.
+// Lane l looks at workgroup top - l of a 64-wide window (indices below 0 read
+// as an inclusive prefix of 0); once every workgroup nearer than the window's
+// nearest inclusive prefix has published its sum, the sums down to that
+// prefix are added and the look-back ends, or moves on to the next window if
+// the window holds no inclusive prefix.  (Windows of several statuses per
+// lane cost registers, and so occupancy in the walk that follows, for no
+// gain.)  After kDupSpinLimit polls of a window the wave adds up the counts
+// of entries 0..blk*256-1 itself.
+__device__ __forceinline__ uint64_t dup_lookback(uint64_t* status, uint32_t blk, const uint32_t* __restrict__ vis_ids,
+                                                 const float4* __restrict__ rec, uint32_t* slow) {
+  const int lane = threadIdx.x & (kWave - 1);
+  uint64_t acc = 0;
+  for (int64_t top = (int64_t)blk - 1;; top -= kWave) {
+    const int64_t j = top - lane;
+    uint64_t st = 0, incl = 0, needed = 0;
+    bool ready = false;
+    for (uint32_t spin = 0; spin < kDupSpinLimit && !ready; ++spin) {
+      st = j >= 0 ? dup_status_load(status + j) : kDupInclusive;
+      const uint32_t flag = (uint32_t)(st >> 32);
+      incl = __ballot(flag == 2u);
+      const int last = incl ? __ffsll((long long)incl) - 1 : kWave - 1;  // lanes 0..last are needed
+      needed = last >= kWave - 1 ? ~0ull : ((2ull << last) - 1ull);
+      ready = (__ballot(flag == 0u) & needed) == 0ull;
+      if (!ready) __builtin_amdgcn_s_sleep(1);
+    }
+    if (!ready) {
+      uint64_t v = 0;
+      for (uint32_t q = (uint32_t)lane; q < blk * kBlock; q += kWave) v += dup_count(vis_ids, rec, q);
+#pragma unroll
+      for (int d = 1; d < kWave; d <<= 1) v += __shfl_xor(v, d, kWave);
+      if (lane == 0) atomicAdd(slow, 1u);
+      return v;
+    }
+    uint64_t v = (needed >> lane) & 1ull ? (uint64_t)(uint32_t)st : 0ull;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) v += __shfl_xor(v, d, kWave);
+    acc += v;
+    if (incl) return acc;
+  }
+}
+
 template <typename KT>
 __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict__ vis_ids,
                                                       const uint32_t* __restrict__ d_nvis, uint32_t n,
-                                                      const uint32_t* __restrict__ offsets,
+                                                      uint32_t* __restrict__ dup_scan, uint32_t* __restrict__ slow,
                                                       const float4* __restrict__ rec, ViewSet vs,
                                                       uint32_t n_gauss, int tile, uint32_t cap,
                                                       KT* __restrict__ keys, uint32_t* __restrict__ vals) {
   __shared__ WalkLds s_walk[kBlock / kWave];
   __shared__ uint4 s_dup[kBlock / kWave][kWave];
-  const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+  __shared__ uint32_t s_scan[kBlock / kWave];
+  __shared__ uint32_t s_base;
+  const uint32_t blk = blockIdx.x;
   const uint32_t nv = min(*d_nvis, n);
-  if (blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1)) >= nv) return;  // whole wave idle
+  if (blk * kBlock >= nv) return;  // uniform; no later workgroup has entries either
+  uint64_t* status = reinterpret_cast<uint64_t*>(dup_scan + kDupStatusWord);
+  const uint32_t p = blk * kBlock + threadIdx.x;
   CandLane me = {};
-  uint32_t gid = 0, off = 0, end = 0, kbase = 0;
+  uint32_t gid = 0, count = 0, kbase = 0;
   if (p < nv) {
     gid = vis_ids[p];
-    off = offsets[p];
     const uint32_t v = vs.n_views > 1 ? gid / n_gauss : 0u;
     kbase = vs.tile_base[v];
     me.width = vs.cam[v].width;
@@ -446,13 +531,27 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
     const float4 r0 = rec[kRecWords * (size_t)gid + 0];
     const float4 r1 = rec[kRecWords * (size_t)gid + 1];
     const float4 r3 = rec[kRecWords * (size_t)gid + 3];
-    const uint32_t count = __float_as_uint(r3.z);
-    end = min(off + count, cap);
+    count = __float_as_uint(r3.z);  // the same word dup_count reads
     int tx0, ty0, tx1, ty1;
     unpack_rect(make_uint2(__float_as_uint(r3.x), __float_as_uint(r3.y)), tx0, ty0, tx1, ty1);
     me = CandLane{r0.x, r0.y, r1.x, r1.y, r1.z, r0.w, tx0, ty0, tx1 - tx0 + 1,
                   count ? (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1)) : 0u, me.width, me.height};
   }
+  // this workgroup's offsets: its own exclusive prefix plus the look-back sum
+  uint32_t btotal;
+  const uint32_t excl = block_exclusive_scan(count, s_scan, &btotal);
+  if (threadIdx.x == 0) dup_status_store(status + blk, (blk == 0 ? kDupInclusive : kDupAggregate) | btotal);
+  if (threadIdx.x < kWave) {
+    const uint64_t prefix = blk > 0 ? dup_lookback(status, blk, vis_ids, rec, slow) : 0ull;
+    if (threadIdx.x == 0) {
+      if (blk > 0) dup_status_store(status + blk, kDupInclusive | (uint32_t)(prefix + btotal));
+      s_base = (uint32_t)prefix;
+    }
+  }
+  __syncthreads();
+  if ((blk * kBlock + (threadIdx.x & ~(kWave - 1u))) >= nv) return;  // whole wave past the end
+  const uint32_t off = s_base + excl;
+  const uint32_t end = p < nv ? min(off + count, cap) : 0u;
   const uint32_t tiles = vs.tile_base[vs.n_views];
   // the owner's output slots, Gaussian and key base, read by owner in emit
   s_dup[threadIdx.x / kWave][threadIdx.x & (kWave - 1)] = make_uint4(off, end, gid, kbase);
@@ -477,16 +576,18 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
   }
 }
 
-hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uint32_t n, const uint32_t* offsets,
-                            const float4* rec, const ViewSet& vs, uint32_t n_gauss, int tile, uint32_t cap,
-                            void* keys, int key_bytes, uint32_t* vals, hipStream_t s) {
+hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uint32_t n, uint32_t* dup_scan,
+                            uint32_t* slow, const float4* rec, const ViewSet& vs, uint32_t n_gauss, int tile,
+                            uint32_t cap, void* keys, int key_bytes, uint32_t* vals, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (key_bytes == 2)
-    k_duplicate<uint16_t><<<ceil_div(n, kBlock), kBlock, 0, s>>>(vis_ids, d_nvis, n, offsets, rec, vs, n_gauss, tile,
-                                                                 cap, static_cast<uint16_t*>(keys), vals);
+    k_duplicate<uint16_t><<<ceil_div(n, kBlock), kBlock, 0, s>>>(vis_ids, d_nvis, n, dup_scan, slow, rec, vs,
+                                                                 n_gauss, tile, cap, static_cast<uint16_t*>(keys),
+                                                                 vals);
   else
-    k_duplicate<uint32_t><<<ceil_div(n, kBlock), kBlock, 0, s>>>(vis_ids, d_nvis, n, offsets, rec, vs, n_gauss, tile,
-                                                                 cap, static_cast<uint32_t*>(keys), vals);
+    k_duplicate<uint32_t><<<ceil_div(n, kBlock), kBlock, 0, s>>>(vis_ids, d_nvis, n, dup_scan, slow, rec, vs,
+                                                                 n_gauss, tile, cap, static_cast<uint32_t*>(keys),
+                                                                 vals);
   return hipGetLastError();
 }
 

@@ -31,33 +31,15 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int MODE>
-__device__ __forceinline__ uint32_t scan_load(const uint32_t* __restrict__ in,
-                                              const uint32_t* __restrict__ idx, uint32_t count,
-                                              uint32_t i) {
-  if (MODE == SCAN_IDENTITY) return in[i];
-  return i < count ? in[idx[i]] : 0u;
-}
-
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ in,
-                                                        const uint32_t* __restrict__ idx,
-                                                        const uint32_t* __restrict__ d_count,
-                                                        uint32_t n, uint32_t* __restrict__ partials,
-                                                        uint32_t* __restrict__ staged) {
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ in, uint32_t n,
+                                                        uint32_t* __restrict__ partials) {
   __shared__ uint32_t lds[kBlock / kWave];
-  const uint32_t count = (MODE == SCAN_GATHER) ? min(*d_count, n) : n;
   const uint32_t base = blockIdx.x * kScanTile;
   uint32_t sum = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const uint32_t i = base + k * kBlock + threadIdx.x;
-    if (i < n) {
-      const uint32_t v = scan_load<MODE>(in, idx, count, i);
-      // a gathered input is read once: it is kept in `staged` for the down-sweep
-      if (MODE == SCAN_GATHER) staged[i] = v;
-      sum += v;
-    }
+    if (i < n) sum += in[i];
   }
   const uint32_t tot = block_reduce_sum(sum, lds);
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
@@ -67,18 +49,15 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restri
 // scanned block offsets (NULL for a single-block scan, which then also writes
 // the grand total).  out may alias in (each item is read before it is written
 // by the same thread).
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t* in, const uint32_t* __restrict__ idx,
-                                                      const uint32_t* __restrict__ d_count, uint32_t n,
+__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t* in, uint32_t n,
                                                       const uint32_t* __restrict__ partials, uint32_t* out,
                                                       uint32_t* __restrict__ d_total) {
   __shared__ uint32_t lds[kBlock / kWave];
-  const uint32_t count = (MODE == SCAN_GATHER) ? min(*d_count, n) : n;
   const uint32_t base = blockIdx.x * kScanTile;
   uint32_t carry = partials ? partials[blockIdx.x] : 0u;
   for (int k = 0; k < kScanItems; ++k) {
     const uint32_t i = base + k * kBlock + threadIdx.x;
-    const uint32_t v = (i < n) ? scan_load<MODE>(in, idx, count, i) : 0u;
+    const uint32_t v = (i < n) ? in[i] : 0u;
     uint32_t tot;
     const uint32_t ex = block_exclusive_scan(v, lds, &tot);
     if (i < n) out[i] = carry + ex;
@@ -95,40 +74,25 @@ size_t scan_scratch_words(uint64_t n) {
   return round_words(nb) + scan_scratch_words(nb);
 }
 
-template <int MODE>
-static hipError_t scan_impl(const uint32_t* in, const uint32_t* idx, const uint32_t* d_count,
-                            uint32_t* out, uint32_t n, uint32_t* d_total, uint32_t* scratch,
-                            hipStream_t s) {
+hipError_t scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* d_total, uint32_t* scratch,
+                    hipStream_t s) {
   if (n == 0) {
     if (d_total) return launch_fill_u32(d_total, 0u, 1, s);
     return hipSuccess;
   }
   const uint32_t nb = ceil_div(n, kScanTile);
   if (nb == 1) {
-    k_scan_down<MODE><<<1, kBlock, 0, s>>>(in, idx, d_count, n, nullptr, out, d_total);
+    k_scan_down<<<1, kBlock, 0, s>>>(in, n, nullptr, out, d_total);
     return hipGetLastError();
   }
   uint32_t* partials = scratch;
-  k_scan_reduce<MODE><<<nb, kBlock, 0, s>>>(in, idx, d_count, n, partials, out);
+  k_scan_reduce<<<nb, kBlock, 0, s>>>(in, n, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = scan_impl<SCAN_IDENTITY>(partials, nullptr, nullptr, partials, nb, d_total,
-                               scratch + round_words(nb), s);
+  e = scan_u32(partials, partials, nb, d_total, scratch + round_words(nb), s);
   if (e != hipSuccess) return e;
-  if (MODE == SCAN_GATHER) {  // the gathered values already sit in `out`
-    k_scan_down<SCAN_IDENTITY><<<nb, kBlock, 0, s>>>(out, nullptr, nullptr, n, partials, out, nullptr);
-  } else {
-    k_scan_down<MODE><<<nb, kBlock, 0, s>>>(in, idx, d_count, n, partials, out, nullptr);
-  }
+  k_scan_down<<<nb, kBlock, 0, s>>>(in, n, partials, out, nullptr);
   return hipGetLastError();
-}
-
-hipError_t scan_u32(ScanMode mode, const uint32_t* in, const uint32_t* idx, const uint32_t* d_count,
-                    uint32_t* out, uint32_t n, uint32_t* d_total, uint32_t* scratch, hipStream_t s) {
-  switch (mode) {
-    case SCAN_IDENTITY: return scan_impl<SCAN_IDENTITY>(in, idx, d_count, out, n, d_total, scratch, s);
-    default: return scan_impl<SCAN_GATHER>(in, idx, d_count, out, n, d_total, scratch, s);
-  }
 }
 
 // ----------------------------------------------------------------------------
@@ -365,8 +329,7 @@ static hipError_t radix_pass(const KT* keys_in, const uint32_t* vals_in, KT* key
   k_radix_hist<RB, KT, kItems><<<nb, kBlock, 0, s>>>(keys_in, n, d_count, shift, hist, nb);
   const uint32_t* digit_totals = totals;
   if (nb > kColscanMaxBlocks) {
-    const hipError_t e = scan_u32(SCAN_IDENTITY, hist, nullptr, nullptr, hist, (uint32_t)(nb << RB), nullptr,
-                                  scan_scratch, s);
+    const hipError_t e = scan_u32(hist, hist, (uint32_t)(nb << RB), nullptr, scan_scratch, s);
     if (e != hipSuccess) return e;
     digit_totals = nullptr;
   } else {

@@ -264,6 +264,8 @@ def test_full_size_sampled_parity(name):
     rz, params, image, t_final, last = forward(sc, cam)
     keys, vals, ranges = sorted_instances(rz)
     say("  N_vis", rz.last_stats["n_visible"], "I", rz.last_stats["n_instances"])
+    # the duplication's offsets came from its look-back, not its slow path
+    assert rz.lookback_slow_count() == 0
     tiles_x = rz.layout().tiles_x
     rng = np.random.default_rng(0)
     sample = sorted(set(rng.integers(0, ranges.shape[0], 12).tolist()) | {0, ranges.shape[0] - 1,
@@ -307,7 +309,7 @@ def test_full_size_sampled_parity(name):
     # on each run's gradients is 1e-3)
     img2, tf2, last2 = rz.forward(params, sync=False)
     torch.cuda.synchronize()
-    assert not rz.overflowed()
+    assert not rz.overflowed() and rz.lookback_slow_count() == 0
     assert torch.equal(img2, image) and torch.equal(tf2, t_final) and torch.equal(last2, last)
     dl = S.make_dl_dimage(w.height, w.width, seed=4).cuda()
     pa = {k: v.clone() for k, v in params.items()}
