@@ -338,6 +338,20 @@ fgs_status fgs_zorder_permutation(const float* means, int64_t n, void* workspace
 fgs_status fgs_permute_planes(const void* src, void* dst, int64_t n, int32_t planes, int32_t elem_bytes,
                               const uint32_t* perm, void* stream);
 
+/* Stable radix sort of (key, value) pairs, the device sort the forward runs
+ * by depth (32-bit keys) and by tile (16- or 32-bit keys) (Sec. 3.2
+ * "Sorting"): afterwards the pairs are ordered by the value of key bits
+ * [0, key_bits), and pairs with equal such bits keep their input order; bits
+ * at and above key_bits are carried along unsorted.  keys: device array of
+ * n keys of key_bytes (2 or 4) bytes; vals: device uint32[n]; both sorted in
+ * place.  key_bits: 0..8*key_bytes (0 leaves the arrays as they are).
+ * workspace: device, 256-byte aligned, at least fgs_sort_workspace_size bytes
+ * (host *bytes); its contents are scratch.  Errors: FGS_ERR_INVALID_ARGUMENT
+ * for a bad size, width, pointer or workspace; nothing is launched then. */
+fgs_status fgs_sort_workspace_size(int64_t n, int32_t key_bytes, size_t* bytes);
+fgs_status fgs_sort_pairs(void* keys, uint32_t* vals, int64_t n, int32_t key_bytes, int32_t key_bits,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
 /* Batched views (several cameras, or timesteps of a dynamic scene, rendered
  * and differentiated in one pass; the paper renders image batches per
  * iteration for its 4D extension, Sec. 3.4).  Up to FGS_MAX_VIEWS cameras

@@ -105,6 +105,8 @@ SIGNATURES = {
     "fgs_time_next_launch": (c_int32, [ctypes.c_char_p, c_void_p, c_void_p]),
     "fgs_zorder_workspace_size": (c_int32, [c_int64, ctypes.POINTER(c_size_t)]),
     "fgs_zorder_permutation": (c_int32, [c_void_p, c_int64, c_void_p, c_size_t, c_void_p, c_void_p]),
+    "fgs_sort_workspace_size": (c_int32, [c_int64, c_int32, ctypes.POINTER(c_size_t)]),
+    "fgs_sort_pairs": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p, c_size_t, c_void_p]),
     "fgs_permute_planes": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p, c_void_p]),
 }
 

@@ -389,6 +389,26 @@ def zorder_permutation(means: torch.Tensor, *, stream=None) -> torch.Tensor:
     return perm
 
 
+def sort_workspace_size(n: int, key_bytes: int) -> int:
+    out = ctypes.c_size_t(0)
+    L.check(L.load().fgs_sort_workspace_size(int(n), int(key_bytes), ctypes.byref(out)), "fgs_sort_workspace_size")
+    return int(out.value)
+
+
+def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, key_bits: int, *, stream=None) -> None:
+    """fgs_sort_pairs: stable in-place sort of (keys, vals) by key bits
+    [0, key_bits); keys int16 or int32 (read as unsigned), vals int32 [n]."""
+    if keys.dtype not in (torch.int16, torch.int32):
+        raise TypeError(f"keys must be int16 or int32, got {keys.dtype}")
+    n = int(keys.numel())
+    _check_tensor(keys, "keys", dtype=keys.dtype, shape=(n,))
+    _check_tensor(vals, "vals", dtype=torch.int32, shape=(n,))
+    kb = keys.element_size()
+    ws = torch.empty(max(sort_workspace_size(n, kb), 256), dtype=torch.uint8, device=keys.device)
+    L.check(L.load().fgs_sort_pairs(_ptr(keys), _ptr(vals), n, kb, int(key_bits), _ptr(ws), ws.numel(),
+                                    _stream_handle(stream)), "fgs_sort_pairs")
+
+
 def permute_planes(src: torch.Tensor, perm: torch.Tensor, out: Optional[torch.Tensor] = None, *,
                    stream=None) -> torch.Tensor:
     """fgs_permute_planes: out[..., k] = src[..., perm[k]] for a [P, n] or [n]

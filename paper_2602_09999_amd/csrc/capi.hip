@@ -666,6 +666,55 @@ fgs_status fgs_permute_planes(const void* src, void* dst, int64_t n, int32_t pla
   return FGS_OK;
 }
 
+static size_t sort_workspace_bytes(uint64_t n, int key_bytes) {
+  auto a256 = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return a256(n * key_bytes) + a256(n * 4) + a256(radix_scratch_words(n) * 4);
+}
+
+fgs_status fgs_sort_workspace_size(int64_t n, int32_t key_bytes, size_t* bytes) {
+  if (!bytes) return fail(FGS_ERR_INVALID_ARGUMENT, "bytes is NULL");
+  if (n < 0 || n > INT32_MAX) return fail(FGS_ERR_INVALID_ARGUMENT, "n = %lld out of range", (long long)n);
+  if (key_bytes != 2 && key_bytes != 4) return fail(FGS_ERR_INVALID_ARGUMENT, "key_bytes must be 2 or 4");
+  *bytes = sort_workspace_bytes((uint64_t)n, key_bytes);
+  return FGS_OK;
+}
+
+fgs_status fgs_sort_pairs(void* keys, uint32_t* vals, int64_t n, int32_t key_bytes, int32_t key_bits,
+                          void* workspace, size_t workspace_bytes, void* stream) {
+  if (n < 0 || n > INT32_MAX) return fail(FGS_ERR_INVALID_ARGUMENT, "n = %lld out of range", (long long)n);
+  if (key_bytes != 2 && key_bytes != 4) return fail(FGS_ERR_INVALID_ARGUMENT, "key_bytes must be 2 or 4");
+  if (key_bits < 0 || key_bits > 8 * key_bytes)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "key_bits %d not in 0..%d", key_bits, 8 * key_bytes);
+  if (n == 0 || key_bits == 0) return FGS_OK;
+  if (!keys || !vals || !workspace) return fail(FGS_ERR_INVALID_ARGUMENT, "NULL pointer");
+  const size_t need = sort_workspace_bytes((uint64_t)n, key_bytes);
+  if (workspace_bytes < need)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "workspace holds %zu bytes, %zu needed", workspace_bytes, need);
+  if ((uintptr_t)workspace % 256) return fail(FGS_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+  if ((uintptr_t)keys % 16 || (uintptr_t)vals % 16)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "keys and vals must be 16-byte aligned");
+  const hipStream_t hs = static_cast<hipStream_t>(stream);
+  const size_t key_region = ((size_t)n * key_bytes + 255) & ~size_t(255);
+  const size_t val_region = ((size_t)n * 4 + 255) & ~size_t(255);
+  char* w = static_cast<char*>(workspace);
+  uint32_t* alt_vals = reinterpret_cast<uint32_t*>(w + key_region);
+  uint32_t* scratch = reinterpret_cast<uint32_t*>(w + key_region + val_region);
+  uint32_t* vbuf[2] = {vals, alt_vals};
+  int final_buf = 0;
+  if (key_bytes == 2) {
+    uint16_t* kbuf[2] = {static_cast<uint16_t*>(keys), reinterpret_cast<uint16_t*>(w)};
+    FGS_HIP(radix_sort_pairs16(kbuf, vbuf, (uint32_t)n, nullptr, 0, key_bits, scratch, &final_buf, hs), "sort");
+  } else {
+    uint32_t* kbuf[2] = {static_cast<uint32_t*>(keys), reinterpret_cast<uint32_t*>(w)};
+    FGS_HIP(radix_sort_pairs(kbuf, vbuf, (uint32_t)n, nullptr, 0, key_bits, scratch, &final_buf, hs), "sort");
+  }
+  if (final_buf == 1) {
+    FGS_HIP(hipMemcpyAsync(keys, w, (size_t)n * key_bytes, hipMemcpyDeviceToDevice, hs), "sort copy");
+    FGS_HIP(hipMemcpyAsync(vals, alt_vals, (size_t)n * 4, hipMemcpyDeviceToDevice, hs), "sort copy");
+  }
+  return FGS_OK;
+}
+
 fgs_status fgs_time_next_launch(const char* step, void* start_event, void* stop_event) {
   static const char* const kSteps[] = {"preprocess",          "duplicate",
                                        "tile_sort",           "blend_forward",

@@ -31,47 +31,69 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Flat exclusive scan: a thread owns 4 consecutive items (one 16-byte access),
+// so a workgroup covers kFlatTile items with a single workgroup scan.  Up to
+// kFlatDirect blocks, each block of the down-sweep adds up the partial sums
+// of the blocks before it itself (no scan of the partials in between).
+constexpr uint32_t kFlatItems = 4;
+constexpr uint32_t kFlatTile = kBlock * kFlatItems;
+constexpr uint32_t kFlatDirect = 2048;
+
+__device__ __forceinline__ uint4 flat_load(const uint32_t* in, uint32_t i, uint32_t n) {
+  if (i + kFlatItems <= n) return *reinterpret_cast<const uint4*>(in + i);
+  uint4 v = make_uint4(0u, 0u, 0u, 0u);
+  if (i < n) v.x = in[i];
+  if (i + 1 < n) v.y = in[i + 1];
+  if (i + 2 < n) v.z = in[i + 2];
+  return v;
+}
+
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ in, uint32_t n,
                                                         uint32_t* __restrict__ partials) {
   __shared__ uint32_t lds[kBlock / kWave];
-  const uint32_t base = blockIdx.x * kScanTile;
-  uint32_t sum = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const uint32_t i = base + k * kBlock + threadIdx.x;
-    if (i < n) sum += in[i];
-  }
-  const uint32_t tot = block_reduce_sum(sum, lds);
+  const uint4 v = flat_load(in, (blockIdx.x * kBlock + threadIdx.x) * kFlatItems, n);
+  const uint32_t tot = block_reduce_sum(v.x + v.y + v.z + v.w, lds);
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-// Items are processed in 16 coalesced rounds of 256; `partials` holds the
-// scanned block offsets (NULL for a single-block scan, which then also writes
-// the grand total).  out may alias in (each item is read before it is written
-// by the same thread).
+// partials: NULL for a single block; else the blocks' sums (direct) or their
+// scanned offsets.  The block holding the last item writes the grand total to
+// d_total when it is given.  out may alias in (a thread reads its items before
+// writing them, and no other thread reads them).
 __global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t* in, uint32_t n,
-                                                      const uint32_t* __restrict__ partials, uint32_t* out,
-                                                      uint32_t* __restrict__ d_total) {
+                                                      const uint32_t* __restrict__ partials, int direct,
+                                                      uint32_t* out, uint32_t* __restrict__ d_total) {
   __shared__ uint32_t lds[kBlock / kWave];
-  const uint32_t base = blockIdx.x * kScanTile;
-  uint32_t carry = partials ? partials[blockIdx.x] : 0u;
-  for (int k = 0; k < kScanItems; ++k) {
-    const uint32_t i = base + k * kBlock + threadIdx.x;
-    const uint32_t v = (i < n) ? in[i] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_exclusive_scan(v, lds, &tot);
-    if (i < n) out[i] = carry + ex;
-    carry += tot;
+  uint32_t carry = 0;
+  if (partials != nullptr && direct) {
+    uint32_t part = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kBlock) part += partials[b];
+    carry = block_reduce_sum(part, lds);
+  } else if (partials != nullptr) {
+    carry = partials[blockIdx.x];
   }
-  if (partials == nullptr && d_total != nullptr && threadIdx.x == 0) *d_total = carry;
+  const uint32_t i = (blockIdx.x * kBlock + threadIdx.x) * kFlatItems;
+  const uint4 v = flat_load(in, i, n);
+  const uint32_t s0 = v.x, s1 = s0 + v.y, s2 = s1 + v.z, s3 = s2 + v.w;
+  uint32_t tot;
+  const uint32_t base = carry + block_exclusive_scan(s3, lds, &tot);
+  const uint4 r = make_uint4(base, base + s0, base + s1, base + s2);
+  if (i + kFlatItems <= n) {
+    *reinterpret_cast<uint4*>(out + i) = r;
+  } else {
+    if (i < n) out[i] = r.x;
+    if (i + 1 < n) out[i + 1] = r.y;
+    if (i + 2 < n) out[i + 2] = r.z;
+  }
+  if (d_total != nullptr && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *d_total = carry + tot;
 }
 
 static inline size_t round_words(size_t w) { return (w + 63) & ~size_t(63); }
 
 size_t scan_scratch_words(uint64_t n) {
-  const uint64_t nb = (n + kScanTile - 1) / kScanTile;
+  const uint64_t nb = (n + kFlatTile - 1) / kFlatTile;
   if (nb <= 1) return 0;
-  return round_words(nb) + scan_scratch_words(nb);
+  return round_words(nb) + (nb > kFlatDirect ? scan_scratch_words(nb) : 0);
 }
 
 hipError_t scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* d_total, uint32_t* scratch,
@@ -80,18 +102,23 @@ hipError_t scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* d_t
     if (d_total) return launch_fill_u32(d_total, 0u, 1, s);
     return hipSuccess;
   }
-  const uint32_t nb = ceil_div(n, kScanTile);
+  if (((uintptr_t)in | (uintptr_t)out | (uintptr_t)scratch) % 16) return hipErrorInvalidValue;
+  const uint32_t nb = ceil_div(n, kFlatTile);
   if (nb == 1) {
-    k_scan_down<<<1, kBlock, 0, s>>>(in, n, nullptr, out, d_total);
+    k_scan_down<<<1, kBlock, 0, s>>>(in, n, nullptr, 0, out, d_total);
     return hipGetLastError();
   }
   uint32_t* partials = scratch;
   k_scan_reduce<<<nb, kBlock, 0, s>>>(in, n, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (nb <= kFlatDirect) {
+    k_scan_down<<<nb, kBlock, 0, s>>>(in, n, partials, 1, out, d_total);
+    return hipGetLastError();
+  }
   e = scan_u32(partials, partials, nb, d_total, scratch + round_words(nb), s);
   if (e != hipSuccess) return e;
-  k_scan_down<<<nb, kBlock, 0, s>>>(in, n, partials, out, nullptr);
+  k_scan_down<<<nb, kBlock, 0, s>>>(in, n, partials, 0, out, nullptr);
   return hipGetLastError();
 }
 
