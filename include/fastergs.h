@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define FGS_ABI_VERSION 9
+#define FGS_ABI_VERSION 10
 
 typedef enum fgs_status {
   FGS_OK = 0,
@@ -167,6 +167,8 @@ typedef struct fgs_forward_stats {
  *   ranges     uint32[2*tiles] [start, end) of each tile's list
  *   accum      float[n][9]  backward: dL/d(mu2D.x, mu2D.y, a, b, c, opacity, r, g, b),
  *                           one row of nine per (view, Gaussian) entry
+ *   marks      uint8[n]     backward: nonzero when the entry's accumulator row
+ *                           received a nonzero value (directly after accum)
  *   touched    uint8[ceil(n/4)]  fused backward + Adam: bit j of byte k set when
  *                           Gaussian 4k+j received a gradient
  *   touched_list uint32[n]  fused: the marked Gaussians (count in counters[8])
@@ -177,7 +179,7 @@ typedef struct fgs_layout {
   size_t vis_keys[2], vis_ids[2];
   size_t dup_scan;
   size_t inst_keys[2], inst_vals[2];
-  size_t ranges, accum, touched, touched_list, slot_of, sparse_grads, scratch, total;
+  size_t ranges, accum, marks, touched, touched_list, slot_of, sparse_grads, scratch, total;
   int32_t inst_final;
   int32_t inst_key_bytes;        /* 2 or 4: width of the inst_keys entries */
   int32_t tiles_x, tiles_y;      /* tile grid of view 0 */

@@ -49,8 +49,8 @@ class Layout(ctypes.Structure):
     _fields_ = [("rec", c_size_t), ("n_tiles", c_size_t), ("depth_key", c_size_t),
                 ("counters", c_size_t), ("vis_keys", c_size_t * 2), ("vis_ids", c_size_t * 2),
                 ("dup_scan", c_size_t), ("inst_keys", c_size_t * 2), ("inst_vals", c_size_t * 2),
-                ("ranges", c_size_t), ("accum", c_size_t), ("touched", c_size_t), ("touched_list", c_size_t),
-                ("slot_of", c_size_t), ("sparse_grads", c_size_t), ("scratch", c_size_t),
+                ("ranges", c_size_t), ("accum", c_size_t), ("marks", c_size_t), ("touched", c_size_t),
+                ("touched_list", c_size_t), ("slot_of", c_size_t), ("sparse_grads", c_size_t), ("scratch", c_size_t),
                 ("total", c_size_t),
                 ("inst_final", c_int32), ("inst_key_bytes", c_int32), ("tiles_x", c_int32), ("tiles_y", c_int32),
                 ("instance_capacity", c_int64), ("n_views", c_int64), ("total_tiles", c_int64)]
@@ -120,6 +120,10 @@ class FasterGSError(RuntimeError):
         self.status = status
 
 
+# the structures above mirror include/fastergs.h at this ABI version
+ABI_VERSION = 10
+
+
 def load(path: str = LIB_PATH) -> ctypes.CDLL:
     """Load the HIP library; raises if it has not been built (there is no fallback)."""
     global _lib
@@ -134,6 +138,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                 fn = getattr(lib, name)
                 fn.restype = res
                 fn.argtypes = args
+            if lib.fgs_abi_version() != ABI_VERSION:
+                raise RuntimeError(f"{path} has ABI version {lib.fgs_abi_version()}, this binding expects "
+                                   f"{ABI_VERSION}: rebuild it with `python -m paper_2602_09999_amd.build`")
             _lib = lib
         return _lib
 

@@ -272,8 +272,10 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const uint2* __restrict__ r
                                                      const float* __restrict__ images,
                                                      const uint32_t* __restrict__ lasts,
                                                      const float* __restrict__ dl_dimages,
-                                                     float* __restrict__ accum, uint32_t n) {
+                                                     float* __restrict__ accum, uint8_t* __restrict__ marks,
+                                                     uint32_t* __restrict__ reset_word, uint32_t n) {
   constexpr int kRows = TileShape<TILE>::kRows, kStep = TileShape<TILE>::kStep;
+  if (reset_word != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *reset_word = 0u;
   const uint32_t gt = xcd_tile(blockIdx.x, gridDim.x);
   const TileView tv = tile_view(vs, gt);
   const CamDev& cam = vs.cam[tv.view];
@@ -386,22 +388,29 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const uint2* __restrict__ r
       // one atomic instruction for the nine sums: they are adjacent in the
       // Gaussian's [9] accumulator row
       const float val = writer ? r8 : r1;
-      if ((writer || lane == 0) && val != 0.0f) unsafeAtomicAdd(accum + (size_t)gid * kGrad + (writer ? wq : 8), val);
+      if ((writer || lane == 0) && val != 0.0f) {
+        unsafeAtomicAdd(accum + (size_t)gid * kGrad + (writer ? wq : 8), val);
+        marks[gid] = 1u;  // the same byte from every lane that adds: no atomic needed
+      }
     }
   }
 }
 
 hipError_t launch_blend_backward(const uint2* ranges, const uint32_t* vals, const float4* rec, const ViewSet& vs,
                                  const SetDev& st, int tile, const float* images, const uint32_t* lasts,
-                                 const float* dl_dimages, float* accum, uint32_t n, hipStream_t s) {
+                                 const float* dl_dimages, float* accum, uint8_t* marks, uint32_t* reset_word,
+                                 uint32_t n, hipStream_t s) {
   const uint32_t tiles = vs.tile_base[vs.n_views];
   if (tiles == 0 || n == 0) return hipSuccess;
   if (tile == 8)
-    k_blend_bwd<8><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, n);
+    k_blend_bwd<8><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, marks,
+                                                     reset_word, n);
   else if (tile == 32)
-    k_blend_bwd<32><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, n);
+    k_blend_bwd<32><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, marks,
+                                                     reset_word, n);
   else
-    k_blend_bwd<16><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, n);
+    k_blend_bwd<16><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, marks,
+                                                     reset_word, n);
   return hipGetLastError();
 }
 

@@ -178,6 +178,7 @@ fgs_status make_layout(int64_t n, const fgs_camera* cams, int32_t n_views, const
   L->inst_vals[1] = take(uc * 4);
   L->ranges = take(tiles * 8);
   L->accum = take(vn * 9 * 4);
+  L->marks = take(vn);  // directly after accum: one fill clears both
   L->touched = take((un + 3) / 4);
   L->touched_list = take(un * 4);
   L->slot_of = take(un * 4);
@@ -420,8 +421,9 @@ fgs_status fgs_rasterize_forward_batch(const fgs_gaussians* g, const fgs_camera*
     FGS_HIP(launch_compact_visible(n_tiles, depth_key, n, (uint32_t)n_views, reinterpret_cast<uint4*>(scratch),
                                    vis_keys[0], vis_ids[0], dup_scan, dup_scan_words(vn), hs),
             "compact");
+    // without the host's key range, passes whose digit no visible key varies in only copy
     FGS_HIP(radix_sort_pairs(vis_keys, vis_ids, nvis, no_sync ? d_vis : nullptr, 0, depth_bits, scratch, &vis_final,
-                             hs),
+                             hs, no_sync ? counters + kStatKeyMin : nullptr, false),
             "depth sort");
     FGS_HIP(launch_set_word(counters + kStatDepthBuf, (uint32_t)vis_final, hs), "depth buffer note");
   }
@@ -473,16 +475,20 @@ static fgs_status check_backward(const fgs_gaussians* g, const fgs_camera* cams,
 // tiles (per-(view, Gaussian) 2D gradients into accum[n_views n][9]).
 static fgs_status blend_backward(const fgs_gaussians* g, const ViewSet& vs, const fgs_settings* st, void* workspace,
                                  const fgs_layout& L, const float* images, const uint32_t* lasts,
-                                 const float* dl_dimages, hipStream_t hs) {
+                                 const float* dl_dimages, hipStream_t hs, uint32_t* reset_word = nullptr) {
   const uint32_t vn = (uint32_t)g->n * vs.n_views;
   const SetDev sd = make_set(st);
   float4* rec = at<float4>(workspace, L.rec);
   uint2* ranges = at<uint2>(workspace, L.ranges);
   uint32_t* ivals = at<uint32_t>(workspace, L.inst_vals[L.inst_final]);
   float* accum = at<float>(workspace, L.accum);
-  FGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(accum), 0u, (uint64_t)vn * 9, hs), "accum clear");
+  uint8_t* marks = at<uint8_t>(workspace, L.marks);
+  // accum and the marks after it, one fill
+  const uint64_t clear_words = (L.marks - L.accum) / 4 + ((uint64_t)vn + 3) / 4;
+  FGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(accum), 0u, clear_words, hs), "accum clear");
   FGS_TIMED("blend_backward", hs,
-            launch_blend_backward(ranges, ivals, rec, vs, sd, st->tile, images, lasts, dl_dimages, accum, vn, hs),
+            launch_blend_backward(ranges, ivals, rec, vs, sd, st->tile, images, lasts, dl_dimages, accum, marks,
+                                  reset_word, vn, hs),
             "blend bwd");
   return FGS_OK;
 }
@@ -576,7 +582,8 @@ fgs_status fgs_rasterize_backward_adam(const fgs_gaussians* g, const fgs_camera*
     if (!opt->exp_avg[k] || !opt->exp_avg_sq[k]) return fail(FGS_ERR_INVALID_ARGUMENT, "moment %d is NULL", k);
   hipStream_t hs = static_cast<hipStream_t>(stream);
   const ViewSet vs = make_views(cam, 1, st->tile, nullptr);
-  s = blend_backward(g, vs, st, workspace, L, image, last, dl_dimage, hs);
+  uint32_t* touch_count = at<uint32_t>(workspace, L.counters) + kStatTouched;
+  s = blend_backward(g, vs, st, workspace, L, image, last, dl_dimage, hs, touch_count);
   if (s != FGS_OK) return s;
   void* const params[6] = {const_cast<float*>(g->means), const_cast<float*>(g->log_scales),
                            const_cast<float*>(g->quats), const_cast<float*>(g->opacity_logits),
@@ -587,7 +594,7 @@ fgs_status fgs_rasterize_backward_adam(const fgs_gaussians* g, const fgs_camera*
   float* sparse = at<float>(workspace, L.sparse_grads);
   FGS_TIMED("touched_gradients", hs,
             launch_touched_gradients(gd, vs.cam[0], at<float4>(workspace, L.rec), at<float>(workspace, L.accum),
-                                     touched, at<uint32_t>(workspace, L.counters) + kStatTouched,
+                                     at<uint8_t>(workspace, L.marks), touched, touch_count,
                                      at<uint32_t>(workspace, L.touched_list), slot_of, sparse, hs),
             "touched gradients");
   FGS_TIMED("adam_sparse", hs,

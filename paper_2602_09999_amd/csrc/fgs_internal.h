@@ -372,9 +372,13 @@ hipError_t scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* d_t
 size_t radix_scratch_words(uint64_t n);
 // Stable LSD radix sort of (key, value) pairs on bits [begin_bit, end_bit).
 // Items: n (host) or *d_count (device, <= n) when d_count != NULL.  Data
-// starts in keys[0]/vals[0]; returns (in *final_buf) the buffer holding the result.
+// starts in keys[0]/vals[0]; returns (in *final_buf) the buffer holding the
+// result.  d_range (device, optional): {min, max} of the keys, so that passes
+// whose digit is the same in every key only copy.  keep_keys = false: the
+// last pass writes the values only (the sorted keys are not needed).
 hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
-                            int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s);
+                            int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s,
+                            const uint32_t* d_range = nullptr, bool keep_keys = true);
 // The same for 16-bit keys (begin_bit < end_bit <= 16).
 hipError_t radix_sort_pairs16(uint16_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
                               int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s);
@@ -440,9 +444,13 @@ hipError_t launch_tile_ranges(const void* keys, int key_bytes, uint32_t n, const
 hipError_t launch_blend_forward(const uint2* ranges, const uint32_t* vals, const float4* rec, const ViewSet& vs,
                                 const SetDev& st, int tile, float* images, float* t_finals, uint32_t* lasts,
                                 hipStream_t s);
+// Adds each fragment's nine gradient sums to its entry's accumulator row and
+// sets the entry's byte in `marks` when it adds a nonzero value; accum and
+// marks start at zero.  reset_word (optional) is set to 0 by the launch.
 hipError_t launch_blend_backward(const uint2* ranges, const uint32_t* vals, const float4* rec, const ViewSet& vs,
                                  const SetDev& st, int tile, const float* images, const uint32_t* lasts,
-                                 const float* dl_dimages, float* accum, uint32_t n, hipStream_t s);
+                                 const float* dl_dimages, float* accum, uint8_t* marks, uint32_t* reset_word,
+                                 uint32_t n, hipStream_t s);
 hipError_t launch_preprocess_backward(const GaussDev& g, const CamDev& cam, const float4* rec, const float* accum,
                                       const GradDev& gr, hipStream_t s);
 // Several views / timesteps: gradients summed over the views (accum is
@@ -453,9 +461,10 @@ hipError_t launch_preprocess_backward_views(const GaussDev& g, const ViewSet& vs
 // `touched` (4 bits per byte), lists them (count in *counter, cleared here),
 // gives Gaussian list[s] slot s (slot_of) and writes its 59 raw-parameter
 // gradients to grads[p][s] (grads: float [59][n]).
+// *counter must be 0 on entry (the blend backward's reset_word).
 hipError_t launch_touched_gradients(const GaussDev& g, const CamDev& cam, const float4* rec, const float* accum,
-                                    uint8_t* touched, uint32_t* counter, uint32_t* list, uint32_t* slot_of,
-                                    float* grads, hipStream_t s);
+                                    const uint8_t* marks, uint8_t* touched, uint32_t* counter, uint32_t* list,
+                                    uint32_t* slot_of, float* grads, hipStream_t s);
 // Second part: Adam on every parameter of the six groups (means, log_scales,
 // quats, logits, sh_dc, sh_rest; planes of length n), with the gradient of
 // the marked Gaussians from their slots and zero for all others.

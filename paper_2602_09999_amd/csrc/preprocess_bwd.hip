@@ -361,10 +361,11 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(GaussDev g, CamDev ca
 // over the index range; updating their parameters where they lie costs a
 // memory sector per 4-byte access, and the streaming step then reads the same
 // lines again.  So no full gradient buffer and no separate update:
-//   k_touched_list   one pass over the accumulators: the 4-bit mark of each
-//                    group of four Gaussians, and for the marked ones a
-//                    compact list and each one's slot in it (one atomic per
-//                    wave on a counter)
+//   k_touched_list   one pass over the blend backward's byte marks (1 byte
+//                    per Gaussian instead of its 36-byte accumulator row):
+//                    the 4-bit mark of each group of four Gaussians, and for
+//                    the marked ones a compact list and each one's slot in it
+//                    (one atomic per wave on a counter)
 //   k_touched_grads  the chain rule for the listed Gaussians only; their 59
 //                    gradients go to slot s of plane-major [59][n] storage,
 //                    so a plane's gradients of neighbouring Gaussians are
@@ -372,7 +373,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(GaussDev g, CamDev ca
 //   k_adam_sparse    one streaming Adam pass over every parameter, which
 //                    takes a marked Gaussian's gradient from its slot and
 //                    zero for all others (adam_loss.hip).
-__global__ __launch_bounds__(kBlock) void k_touched_list(const float* __restrict__ accum, uint32_t n, int vec,
+__global__ __launch_bounds__(kBlock) void k_touched_list(const uint8_t* __restrict__ marks, uint32_t n,
                                                          uint8_t* __restrict__ touched,
                                                          uint32_t* __restrict__ counter,
                                                          uint32_t* __restrict__ list,
@@ -382,8 +383,14 @@ __global__ __launch_bounds__(kBlock) void k_touched_list(const float* __restrict
   if ((blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1u))) * 4u >= n) return;  // whole wave past the end
   uint32_t mask = 0;
   if (i0 < n) {
-    float acc[4][9];
-    mask = load_accum4(accum, n, i0, vec && i0 + 4 <= n, acc);
+    uint32_t m4 = 0;  // the four mark bytes (the region is 256-byte aligned, i0 a multiple of 4)
+    if (i0 + 4 <= n) {
+      m4 = *reinterpret_cast<const uint32_t*>(marks + i0);
+    } else {
+      for (uint32_t j = 0; i0 + j < n; ++j) m4 |= (uint32_t)marks[i0 + j] << (8 * j);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) mask |= ((m4 >> (8 * j)) & 0xffu) ? (1u << j) : 0u;
     touched[i0 / 4] = (uint8_t)mask;
   }
   // exclusive prefix of the lanes' counts (0..4, three bit planes) and the wave total
@@ -520,14 +527,11 @@ hipError_t launch_preprocess_backward(const GaussDev& g, const CamDev& cam, cons
 }
 
 hipError_t launch_touched_gradients(const GaussDev& g, const CamDev& cam, const float4* rec, const float* accum,
-                                    uint8_t* touched, uint32_t* counter, uint32_t* list, uint32_t* slot_of,
-                                    float* grads, hipStream_t s) {
+                                    const uint8_t* marks, uint8_t* touched, uint32_t* counter, uint32_t* list,
+                                    uint32_t* slot_of, float* grads, hipStream_t s) {
   if (g.n == 0) return hipSuccess;
-  hipError_t e = launch_fill_u32(counter, 0u, 1, s);
-  if (e != hipSuccess) return e;
-  const int vec = ((uintptr_t)accum & 15u) == 0 ? 1 : 0;
-  k_touched_list<<<ceil_div(ceil_div(g.n, 4), kBlock), kBlock, 0, s>>>(accum, g.n, vec, touched, counter, list,
-                                                                      slot_of);
+  if ((uintptr_t)marks % 4) return hipErrorInvalidValue;
+  k_touched_list<<<ceil_div(ceil_div(g.n, 4), kBlock), kBlock, 0, s>>>(marks, g.n, touched, counter, list, slot_of);
   const uint32_t grid = std::min<uint32_t>(ceil_div(g.n, kBlock), 2048u);
   if (g.sh_bf16)
     k_touched_grads<true><<<grid, kBlock, 0, s>>>(g, cam, rec, accum, counter, list, grads);

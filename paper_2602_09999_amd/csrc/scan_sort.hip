@@ -136,6 +136,13 @@ hipError_t scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* d_t
 // Keys are 32-bit, or 16-bit for tile ids that fit (half the key traffic);
 // values are 32-bit.  A block sorts kBlock * ITEMS pairs.
 // ----------------------------------------------------------------------------
+// With d_range = {min, max} of all keys given, a pass whose digit and every
+// bit above it are the same in both (so in every key) keeps the order: its
+// histogram and scan do nothing and its scatter is a copy.
+__device__ __forceinline__ bool pass_is_constant(const uint32_t* __restrict__ d_range, int shift) {
+  return d_range != nullptr && ((d_range[0] ^ d_range[1]) >> shift) == 0u;
+}
+
 template <typename KT>
 struct alignas(16) KeyVec {  // one 16-byte load of consecutive keys
   static constexpr int V = 16 / (int)sizeof(KT);
@@ -145,11 +152,13 @@ struct alignas(16) KeyVec {  // one 16-byte load of consecutive keys
 template <int RB, typename KT, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_radix_hist(const KT* __restrict__ keys, uint32_t n,
                                                        const uint32_t* __restrict__ d_count, int shift,
+                                                       const uint32_t* __restrict__ d_range,
                                                        uint32_t* __restrict__ hist, uint32_t nb) {
   constexpr int R = 1 << RB;
   constexpr int kWaves = kBlock / kWave;
   constexpr int V = KeyVec<KT>::V;
   static_assert(ITEMS % V == 0, "whole 16-byte loads per thread");
+  if (pass_is_constant(d_range, shift)) return;
   // one histogram per wave: four times fewer lanes contend for a counter
   __shared__ uint32_t h[kWaves][R];
   for (int i = threadIdx.x; i < kWaves * R; i += kBlock) (&h[0][0])[i] = 0;
@@ -180,8 +189,10 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const KT* __restrict__ ke
 
 // Workgroup d: exclusive scan of hist[d][0..nb) in place; totals[d] = its sum.
 __global__ __launch_bounds__(kBlock) void k_radix_colscan(uint32_t* __restrict__ hist, uint32_t nb,
-                                                          uint32_t* __restrict__ totals) {
+                                                          uint32_t* __restrict__ totals,
+                                                          const uint32_t* __restrict__ d_range, int shift) {
   __shared__ uint32_t lds[kBlock / kWave];
+  if (pass_is_constant(d_range, shift)) return;
   uint32_t* col = hist + (size_t)blockIdx.x * nb;
   uint32_t carry = 0;
   for (uint32_t b0 = 0; b0 < nb; b0 += kBlock) {
@@ -207,6 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT* __restrict__
                                                           KT* __restrict__ keys_out,
                                                           uint32_t* __restrict__ vals_out, uint32_t n,
                                                           const uint32_t* __restrict__ d_count, int shift,
+                                                          const uint32_t* __restrict__ d_range,
                                                           const uint32_t* __restrict__ hist_scan,
                                                           const uint32_t* __restrict__ totals, uint32_t nb) {
   constexpr int R = 1 << RB;
@@ -222,6 +234,13 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT* __restrict__
   const uint32_t base = blockIdx.x * kTile;
   if (base >= count) return;  // uniform for the whole workgroup
   const uint32_t in_block = min(kTile, count - base);
+  if (pass_is_constant(d_range, shift)) {  // uniform: the pass keeps the order
+    for (uint32_t i = base + threadIdx.x; i < base + in_block; i += kBlock) {
+      if (keys_out) keys_out[i] = keys_in[i];
+      vals_out[i] = vals_in[i];
+    }
+    return;
+  }
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const bool digit_thread = threadIdx.x < R;
@@ -350,27 +369,27 @@ size_t radix_scratch_words(uint64_t n) {
 
 template <int RB, typename KT>
 static hipError_t radix_pass(const KT* keys_in, const uint32_t* vals_in, KT* keys_out, uint32_t* vals_out,
-                             uint32_t n, const uint32_t* d_count, int shift, uint32_t* hist, uint32_t* totals,
-                             uint32_t* scan_scratch, uint32_t nb, hipStream_t s) {
+                             uint32_t n, const uint32_t* d_count, const uint32_t* d_range, int shift,
+                             uint32_t* hist, uint32_t* totals, uint32_t* scan_scratch, uint32_t nb, hipStream_t s) {
   constexpr int kItems = SortShape<KT>::kItems;
-  k_radix_hist<RB, KT, kItems><<<nb, kBlock, 0, s>>>(keys_in, n, d_count, shift, hist, nb);
+  k_radix_hist<RB, KT, kItems><<<nb, kBlock, 0, s>>>(keys_in, n, d_count, shift, d_range, hist, nb);
   const uint32_t* digit_totals = totals;
   if (nb > kColscanMaxBlocks) {
     const hipError_t e = scan_u32(hist, hist, (uint32_t)(nb << RB), nullptr, scan_scratch, s);
     if (e != hipSuccess) return e;
     digit_totals = nullptr;
   } else {
-    k_radix_colscan<<<1u << RB, kBlock, 0, s>>>(hist, nb, totals);
+    k_radix_colscan<<<1u << RB, kBlock, 0, s>>>(hist, nb, totals, d_range, shift);
   }
   k_radix_scatter<RB, KT, kItems><<<nb, kBlock, 0, s>>>(keys_in, vals_in, keys_out, vals_out, n, d_count, shift,
-                                                        hist, digit_totals, nb);
+                                                        d_range, hist, digit_totals, nb);
   return hipGetLastError();
 }
 
 template <typename KT>
 static hipError_t radix_sort_impl(KT* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
-                                  int begin_bit, int end_bit, bool keep_keys, uint32_t* scratch, int* final_buf,
-                                  hipStream_t s) {
+                                  const uint32_t* d_range, int begin_bit, int end_bit, bool keep_keys,
+                                  uint32_t* scratch, int* final_buf, hipStream_t s) {
   int cur = 0;
   if (n == 0 || end_bit <= begin_bit) {
     *final_buf = 0;
@@ -389,14 +408,14 @@ static hipError_t radix_sort_impl(KT* keys[2], uint32_t* vals[2], uint32_t n, co
     KT* kout = (p + 1 == passes && !keep_keys) ? nullptr : keys[cur ^ 1];
     hipError_t e = hipSuccess;
     switch (rb) {
-      case 1: e = radix_pass<1, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, scan_scratch, nb, s); break;
-      case 2: e = radix_pass<2, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, scan_scratch, nb, s); break;
-      case 3: e = radix_pass<3, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, scan_scratch, nb, s); break;
-      case 4: e = radix_pass<4, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, scan_scratch, nb, s); break;
-      case 5: e = radix_pass<5, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, scan_scratch, nb, s); break;
-      case 6: e = radix_pass<6, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, scan_scratch, nb, s); break;
-      case 7: e = radix_pass<7, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, scan_scratch, nb, s); break;
-      default: e = radix_pass<8, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, shift, hist, totals, scan_scratch, nb, s); break;
+      case 1: e = radix_pass<1, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, d_range, shift, hist, totals, scan_scratch, nb, s); break;
+      case 2: e = radix_pass<2, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, d_range, shift, hist, totals, scan_scratch, nb, s); break;
+      case 3: e = radix_pass<3, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, d_range, shift, hist, totals, scan_scratch, nb, s); break;
+      case 4: e = radix_pass<4, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, d_range, shift, hist, totals, scan_scratch, nb, s); break;
+      case 5: e = radix_pass<5, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, d_range, shift, hist, totals, scan_scratch, nb, s); break;
+      case 6: e = radix_pass<6, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, d_range, shift, hist, totals, scan_scratch, nb, s); break;
+      case 7: e = radix_pass<7, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, d_range, shift, hist, totals, scan_scratch, nb, s); break;
+      default: e = radix_pass<8, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, d_range, shift, hist, totals, scan_scratch, nb, s); break;
     }
     if (e != hipSuccess) return e;
     shift += rb;
@@ -407,13 +426,16 @@ static hipError_t radix_sort_impl(KT* keys[2], uint32_t* vals[2], uint32_t n, co
 }
 
 hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
-                            int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s) {
-  return radix_sort_impl<uint32_t>(keys, vals, n, d_count, begin_bit, end_bit, true, scratch, final_buf, s);
+                            int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s,
+                            const uint32_t* d_range, bool keep_keys) {
+  return radix_sort_impl<uint32_t>(keys, vals, n, d_count, d_range, begin_bit, end_bit, keep_keys, scratch,
+                                   final_buf, s);
 }
 
 hipError_t radix_sort_pairs16(uint16_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
                               int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s) {
-  return radix_sort_impl<uint16_t>(keys, vals, n, d_count, begin_bit, end_bit, true, scratch, final_buf, s);
+  return radix_sort_impl<uint16_t>(keys, vals, n, d_count, nullptr, begin_bit, end_bit, true, scratch, final_buf,
+                                   s);
 }
 
 }  // namespace fgs

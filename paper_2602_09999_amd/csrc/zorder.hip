@@ -147,7 +147,7 @@ hipError_t launch_zorder(const float* means, uint32_t n, void* scratch, uint32_t
   uint32_t* keys[2] = {codes0, codes1};
   uint32_t* vals[2] = {perm, idx1};
   int fin = 0;
-  e = radix_sort_pairs(keys, vals, n, nullptr, 0, 30, rscratch, &fin, s);
+  e = radix_sort_pairs(keys, vals, n, nullptr, 0, 30, rscratch, &fin, s, nullptr, false);
   if (e != hipSuccess) return e;
   if (fin != 0) return hipMemcpyAsync(perm, vals[fin], (size_t)n * 4, hipMemcpyDeviceToDevice, s);
   return hipSuccess;

@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported_and_bound(lib):
     for name in names:
         assert hasattr(lib, name), name
         assert name in L.SIGNATURES, name
-    assert lib.fgs_abi_version() == 9
+    assert lib.fgs_abi_version() == 10 == L.ABI_VERSION
 
 
 def test_default_settings_match_the_paper(lib):
@@ -65,7 +65,9 @@ def test_workspace_size_and_layout(lib):
     assert b - a >= (2 * 2 + 2 * 4) * 100_000  # two 16-bit key and two value buffers
     lay = B.workspace_layout(10_000, cam, instance_capacity=100_000)
     offs = [lay.rec, lay.n_tiles, lay.depth_key, lay.counters, lay.vis_keys[0], lay.vis_ids[0],
-            lay.dup_scan, lay.inst_keys[0], lay.inst_vals[0], lay.ranges, lay.accum, lay.touched, lay.touched_list, lay.slot_of, lay.sparse_grads, lay.scratch]
+            lay.dup_scan, lay.inst_keys[0], lay.inst_vals[0], lay.ranges, lay.accum, lay.marks, lay.touched,
+            lay.touched_list, lay.slot_of, lay.sparse_grads, lay.scratch]
+    assert lay.marks - lay.accum >= 9 * 4 * 10_000 and lay.touched - lay.marks >= 10_000
     assert lay.touched_list - lay.touched >= (10_000 + 3) // 4
     assert lay.slot_of - lay.touched_list >= 4 * 10_000 and lay.sparse_grads - lay.slot_of >= 4 * 10_000
     assert lay.scratch - lay.sparse_grads >= 59 * 4 * 10_000

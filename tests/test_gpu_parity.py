@@ -318,6 +318,13 @@ def test_full_size_sampled_parity(name):
     oa.step(rz.backward(pa, img2, last2, dl))
     rz.backward_adam(pb, img2, last2, dl, ob)
     torch.cuda.synchronize()
+    # the fused path lists the Gaussians the blend backward marked: exactly
+    # those whose accumulator row is nonzero
+    rows = rz.view("accum", 9 * w.n, dtype=torch.float32).view(w.n, 9)
+    n_rows = int(rows.ne(0).any(1).sum().item())
+    n_listed = int(rz.view("counters", 16)[8].item())
+    say("  Gaussians with a gradient", n_listed)
+    assert n_listed == n_rows > 0
     for k in B.PARAM_NAMES:
         em = rel_l2(ob.exp_avg[k], oa.exp_avg[k])
         ev = rel_l2(ob.exp_avg_sq[k], oa.exp_avg_sq[k])
