@@ -164,15 +164,12 @@ __device__ __forceinline__ float edge_min_q(float a, float b, float c, float ra,
   return ((a * dx) * dx + ((b + b) * dx) * dy) + (c * dy) * dy;
 }
 
+// The hull is [x0, x1] x [y0, y1] in pixel centres: x0 = tx*tile + 0.5 and
+// x1 = min(x0 + tile - 1, width - 0.5), likewise in y (integers + 0.5, exact
+// in FP32).
 __device__ __forceinline__ bool tile_keep(float mx, float my, float a, float b, float c, float ra, float rc,
-                                          float thr, int tx, int ty, int tile, int width, int height) {
+                                          float thr, float x0, float x1, float y0, float y1) {
 #pragma clang fp contract(off)
-  // tile is a power of two (8, 16 or 32): shifts, not integer multiplies
-  const int sh = __builtin_ctz((unsigned)tile);
-  const float x0 = (float)(tx << sh) + 0.5f;
-  const float x1 = (float)min(((tx + 1) << sh) - 1, width - 1) + 0.5f;
-  const float y0 = (float)(ty << sh) + 0.5f;
-  const float y1 = (float)min(((ty + 1) << sh) - 1, height - 1) + 0.5f;
   const bool left = mx < x0, right = mx > x1, top = my < y0, bottom = my > y1;
   // At most one vertical and one horizontal edge face the centre (left and
   // right exclude each other, as do top and bottom): the minimum over the hull
@@ -239,10 +236,8 @@ __device__ __forceinline__ uint32_t block_reduce_sum(uint32_t v, uint32_t* lds) 
 // order, so every lane tests one candidate per step whatever the rectangle
 // sizes.  Every step calls emit(owner_lane, rank, tx, ty, keep) in all lanes
 // (uniform control flow, so emit may use cross-lane shuffles); for a kept tile
-// rank is its index among the owner's kept tiles, so consecutive kept tiles of
-// the wave map to consecutive output slots.  Returns,
-// in each lane, the number of kept tiles of its own Gaussian.
-// `owner_at` is 64 words of LDS private to the wave.
+// rank is its index among all kept tiles of the wave in that order, so the
+// wave's kept tiles map to one contiguous run of output slots.
 // ----------------------------------------------------------------------------
 struct CandLane {
   float mx, my, a, b, c, thr;
@@ -265,18 +260,20 @@ __device__ __forceinline__ uint32_t udiv_magic(uint32_t r, uint32_t w, uint32_t 
 // cross-lane shuffle per field).
 struct alignas(16) OwnerRec {
   float mx, my, a, b;
-  float c, thr, ra, rc;  // ra = 1/a, rc = 1/c (the tile test's reciprocals)
-  int tx0, ty0, w;
-  uint32_t cstart;  // first candidate's position in the wave's candidate list
-  int width, height;
-  uint32_t wmagic;  // div_magic(w)
-  uint32_t pad;
+  float c, thr, ra, rc;    // ra = 1/a, rc = 1/c (the tile test's reciprocals)
+  float x0b, y0b;          // pixel-centre origin of the rectangle: tx0*tile + 0.5, ty0*tile + 0.5
+  float xmax, ymax;        // last pixel centres of the view: width - 0.5, height - 0.5
+  int w;                   // rectangle width in tiles
+  uint32_t cstart;         // first candidate's position in the wave's candidate list
+  uint32_t wmagic;         // div_magic(w)
+  uint32_t txy0;           // tx0 | ty0 << 16
 };
 
 // LDS of one wave's walk.
 struct WalkLds {
   OwnerRec own[kWave];
   uint32_t owner_at[kWave];
+  uint32_t count[kWave];  // kept tiles per Gaussian (counting walk)
 };
 
 // A volatile pointer into LDS that keeps its address space: through a plain
@@ -295,27 +292,37 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// emit(owner, const OwnerRec&, rank among the owner's kept tiles, tx, ty, keep)
+// emit(owner, const OwnerRec&, rank among the wave's kept tiles, tx, ty, keep)
 // is called by every lane at every step (uniform control flow); LDS the
 // caller wrote before the call is visible to all lanes inside emit.
-template <typename Emit>
+// RANKS = true: returns the number of kept tiles of the whole wave (the same
+// in every lane).  RANKS = false (a walk that only counts): the ranks passed
+// to emit are 0, each kept candidate adds 1 to its owner's LDS counter, and
+// each lane gets the kept tiles of its own Gaussian.
+template <bool RANKS, typename Emit>
 __device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, WalkLds& L, int tile, Emit emit) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t incl = wave_inclusive_scan(me.cand, lane);
   const uint32_t cstart = incl - me.cand;
   const uint32_t total = __shfl(incl, kWave - 1, kWave);
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint64_t upto = below | (1ull << lane);
-  uint32_t kept = 0;
+  const uint64_t upto = ((lane == 0) ? 0ull : (~0ull >> (64 - lane))) | (1ull << lane);
+  const float ftile = (float)tile, ftile1 = (float)(tile - 1);
+  uint32_t running = 0;  // wave-uniform: kept candidates of the earlier steps
   uint32_t tag = 0;
   {
 #pragma clang fp contract(off)
     const float ra = me.cand ? 1.0f / me.a : 0.0f, rc = me.cand ? 1.0f / me.c : 0.0f;
-    L.own[lane] = OwnerRec{me.mx, me.my, me.a, me.b, me.c, me.thr, ra, rc, me.tx0, me.ty0, me.w, cstart,
-                           me.width, me.height, div_magic((uint32_t)max(me.w, 1)), 0u};
+    const int sh = __builtin_ctz((unsigned)tile);
+    L.own[lane] = OwnerRec{me.mx, me.my, me.a, me.b, me.c, me.thr, ra, rc,
+                           (float)(me.tx0 << sh) + 0.5f, (float)(me.ty0 << sh) + 0.5f,
+                           (float)(me.width - 1) + 0.5f, (float)(me.height - 1) + 0.5f,
+                           me.w, cstart, div_magic((uint32_t)max(me.w, 1)),
+                           (uint32_t)me.tx0 | ((uint32_t)me.ty0 << 16)};
   }
   lds_volatile_u32* owner_at = lds_volatile(L.owner_at);
+  lds_volatile_u32* count = lds_volatile(L.count);
   owner_at[lane] = 0xffffffffu;  // no step tag matches
+  if (!RANKS) count[lane] = 0u;
   wave_lds_sync();
   for (uint32_t c0 = 0; c0 < total; c0 += kWave, tag += 0x100u) {
     // the Gaussian whose candidates start in (or run into) this step claims its first slot
@@ -330,26 +337,27 @@ __device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, WalkLds& 
     const uint32_t pos = c0 + (uint32_t)lane;
     const bool valid = pos < total;
     const OwnerRec o = L.own[owner];
-    // the running count is the one per-step value: a shuffle, with all lanes active
-    const uint32_t o_kept = __shfl(kept, owner, kWave);
     const uint32_t r = pos - o.cstart;
     const uint32_t ry = udiv_magic(r, (uint32_t)o.w, o.wmagic);
-    const int tx = o.tx0 + (int)(r - __umul24(ry, (uint32_t)o.w));
-    const int ty = o.ty0 + (int)ry;
-    const bool keep = tile_keep(o.mx, o.my, o.a, o.b, o.c, o.ra, o.rc, o.thr, tx, ty, tile, o.width, o.height) & valid;
-    const uint64_t kb = __ballot(keep);
-    const uint32_t first = o.cstart > c0 ? o.cstart - c0 : 0u;
-    const uint64_t from_first = first >= 64 ? 0ull : ~((first == 0) ? 0ull : (~0ull >> (64 - first)));
-    emit(owner, o, o_kept + (uint32_t)__popcll(kb & below & from_first), tx, ty, keep);  // uniform call
-    // this lane's Gaussian: add the kept tiles of its segment in this step
-    if (claims) {
-      const uint32_t lo = slot;
-      const uint32_t hi = min(cstart + me.cand - c0, (uint32_t)kWave);  // exclusive
-      const uint64_t seg = (hi >= 64 ? ~0ull : ((1ull << hi) - 1ull)) & ~((lo == 0) ? 0ull : ((1ull << lo) - 1ull));
-      kept += (uint32_t)__popcll(kb & seg);
+    const uint32_t rx = r - __umul24(ry, (uint32_t)o.w);
+    const float x0 = fmaf((float)rx, ftile, o.x0b), y0 = fmaf((float)ry, ftile, o.y0b);
+    const float x1 = fminf(x0 + ftile1, o.xmax), y1 = fminf(y0 + ftile1, o.ymax);
+    const int tx = (int)(o.txy0 & 0xffffu) + (int)rx;
+    const int ty = (int)(o.txy0 >> 16) + (int)ry;
+    const bool keep = tile_keep(o.mx, o.my, o.a, o.b, o.c, o.ra, o.rc, o.thr, x0, x1, y0, y1) & valid;
+    if (!RANKS) {
+      if (keep) atomicAdd((uint32_t*)&L.count[owner], 1u);
+      emit(owner, o, 0u, tx, ty, keep);
+      continue;
     }
+    const uint64_t kb = __ballot(keep);
+    const uint32_t before = __builtin_amdgcn_mbcnt_hi((uint32_t)(kb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)kb, 0u));
+    emit(owner, o, running + before, tx, ty, keep);  // uniform call
+    running += (uint32_t)__popcll(kb);
   }
-  return kept;
+  if (RANKS) return running;
+  wave_lds_sync();
+  return count[lane];
 }
 
 inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }

@@ -199,8 +199,8 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, ViewSet vs, S
     }
   }
   // exact per-tile test of every candidate tile, load-balanced over the wave
-  const uint32_t count = wave_tile_walk(me, s_walk[threadIdx.x / kWave], tile,
-                                        [](int, const OwnerRec&, uint32_t, int, int, bool) {});
+  const uint32_t count = wave_tile_walk<false>(me, s_walk[threadIdx.x / kWave], tile,
+                                               [](int, const OwnerRec&, uint32_t, int, int, bool) {});
   const bool vis = in_range && count > 0;
   if (in_range) n_tiles[j] = count;
   if (vis) {
@@ -511,7 +511,7 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
                                                       uint32_t n_gauss, int tile, uint32_t cap,
                                                       KT* __restrict__ keys, uint32_t* __restrict__ vals) {
   __shared__ WalkLds s_walk[kBlock / kWave];
-  __shared__ uint4 s_dup[kBlock / kWave][kWave];
+  __shared__ uint2 s_dup[kBlock / kWave][kWave];
   __shared__ uint32_t s_scan[kBlock / kWave];
   __shared__ uint32_t s_base;
   const uint32_t blk = blockIdx.x;
@@ -551,28 +551,39 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
   __syncthreads();
   if ((blk * kBlock + (threadIdx.x & ~(kWave - 1u))) >= nv) return;  // whole wave past the end
   const uint32_t off = s_base + excl;
-  const uint32_t end = p < nv ? min(off + count, cap) : 0u;
   const uint32_t tiles = vs.tile_base[vs.n_views];
-  // the owner's output slots, Gaussian and key base, read by owner in emit
-  s_dup[threadIdx.x / kWave][threadIdx.x & (kWave - 1)] = make_uint4(off, end, gid, kbase);
+  // The wave's Gaussians own one contiguous run of slots (their offsets are
+  // consecutive) and the walk visits their candidates in the same order, so a
+  // kept tile's slot is the run's start plus its rank among the wave's kept
+  // tiles.  Lanes past nv have count 0, so lane 63's off + count ends the run.
+  const uint32_t run_start = __shfl(off, 0, kWave);
+  const uint32_t run_end = __shfl(off + count, kWave - 1, kWave);
+  const uint32_t lim = min(run_end, cap);
+  // the owner's Gaussian and key base, read by owner in emit
+  s_dup[threadIdx.x / kWave][threadIdx.x & (kWave - 1)] = make_uint2(gid, kbase);
   const int tile_shift = __builtin_ctz((unsigned)tile);
-  const uint32_t written = wave_tile_walk(
+  const uint32_t written = wave_tile_walk<true>(
       me, s_walk[threadIdx.x / kWave], tile,
       [&](int owner, const OwnerRec& o, uint32_t rank, int tx, int ty, bool keep) {
-        const uint4 d = s_dup[threadIdx.x / kWave][owner];
-        const uint32_t slot = d.x + rank;
-        if (keep && slot < d.y) {
-          const uint32_t row = (uint32_t)(o.width + tile - 1) >> tile_shift;  // tiles_x of the owner's view
-          keys[slot] = (KT)(d.w + __umul24((uint32_t)ty, row) + (uint32_t)tx);  // 16-bit tile coordinates
-          vals[slot] = d.z;
+        const uint32_t slot = run_start + rank;
+        if (keep && slot < lim) {
+          const uint2 d = s_dup[threadIdx.x / kWave][owner];
+          // tiles_x of the owner's view (xmax = width - 0.5)
+          const uint32_t row = ((uint32_t)(o.xmax + 0.5f) + (uint32_t)tile - 1u) >> tile_shift;
+          keys[slot] = (KT)(d.y + __umul24((uint32_t)ty, row) + (uint32_t)tx);  // 16-bit tile coordinates
+          vals[slot] = d.x;
         }
       });
-  // The walk repeats the preprocess count on the same stored values, so this
-  // loop never runs; it keeps every slot defined (an out-of-range tile id
-  // that the range kernel ignores) should the two ever disagree.
-  for (uint32_t slot = off + written; p < nv && slot < end; ++slot) {
-    keys[slot] = (KT)tiles;
-    vals[slot] = gid;
+  // The walk repeats the preprocess count on the same stored values, so the
+  // totals agree and this never runs; should they ever disagree, the wave's
+  // whole run is filled with an out-of-range tile id (ignored by the range
+  // kernel) so that no slot is left undefined.
+  if (written != run_end - run_start) {  // wave-uniform
+    const uint32_t g0 = __shfl(gid, 0, kWave);
+    for (uint32_t slot = run_start + (threadIdx.x & (kWave - 1)); slot < lim; slot += kWave) {
+      keys[slot] = (KT)tiles;
+      vals[slot] = g0;
+    }
   }
 }
 
