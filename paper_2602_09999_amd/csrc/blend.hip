@@ -60,27 +60,30 @@ __device__ __forceinline__ void load_batch(const uint32_t* __restrict__ vals, co
 // with the same address (a broadcast read, no bank conflict) instead of a
 // v_readlane per field, and so that only the prefetched batch occupies
 // registers.
+// q: the conic pre-scaled once per entry when the batch is staged (not once
+// per fragment in every lane), so that
+// alpha = min(alpha_max, o * 2^(a2 dx^2 + b2 dx dy + c2 dy^2)).
 struct BatchLds {
-  float4 r0[kWave], r1[kWave], r2[kWave];
+  float4 r0[kWave], r1[kWave], r2[kWave], q[kWave];
   uint32_t gid[kWave];
 };
+constexpr float kHalfLog2e = 0.72134752044448170368f;  // log2(e) / 2
 
 __device__ __forceinline__ void stage_batch(const Batch& b, BatchLds& L, int lane) {
   L.r0[lane] = b.r0;
   L.r1[lane] = b.r1;
   L.r2[lane] = b.r2;
+  L.q[lane] = make_float4(-kHalfLog2e * b.r1.x, -2.0f * kHalfLog2e * b.r1.y, -kHalfLog2e * b.r1.z, 0.0f);
   L.gid[lane] = b.gid;
 }
 
-// Splat k of a batch, broadcast to the wave, with the conic pre-scaled so that
-// alpha = min(alpha_max, o * 2^(a2 dx^2 + b2 dx dy + c2 dy^2)).
+// Splat k of a batch, broadcast to the wave.
 struct Splat {
   float mx, my, o, a, b, c, a2, b2, c2;
 };
-constexpr float kHalfLog2e = 0.72134752044448170368f;  // log2(e) / 2
 
 __device__ __forceinline__ Splat splat_of(const BatchLds& L, int k) {
-  const float4 r0 = L.r0[k], r1 = L.r1[k];
+  const float4 r0 = L.r0[k], r1 = L.r1[k], q = L.q[k];
   Splat s;
   s.mx = r0.x;
   s.my = r0.y;
@@ -88,9 +91,9 @@ __device__ __forceinline__ Splat splat_of(const BatchLds& L, int k) {
   s.a = r1.x;
   s.b = r1.y;
   s.c = r1.z;
-  s.a2 = -kHalfLog2e * s.a;
-  s.b2 = -2.0f * kHalfLog2e * s.b;
-  s.c2 = -kHalfLog2e * s.c;
+  s.a2 = q.x;
+  s.b2 = q.y;
+  s.c2 = q.z;
   return s;
 }
 
