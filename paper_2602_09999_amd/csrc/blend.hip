@@ -103,7 +103,9 @@ __device__ __forceinline__ Splat splat_of(const BatchLds& L, int k) {
 __device__ __forceinline__ float pixel_alpha(const Splat& s, float ax, float bx, float dy, float alpha_max,
                                              float& G) {
   G = __builtin_amdgcn_exp2f(fmaf(fmaf(s.c2, dy, bx), dy, ax));
-  return fminf(alpha_max, s.o * G);
+  // min(alpha_max, o G) for o G >= 0, as a median (one instruction; fminf
+  // would re-canonicalise alpha_max at every fragment)
+  return __builtin_amdgcn_fmed3f(s.o * G, 0.0f, alpha_max);
 }
 
 // Grid: one wave per global tile of all views.  images: the views' [3][H][W]

@@ -273,7 +273,6 @@ struct alignas(16) OwnerRec {
 struct WalkLds {
   OwnerRec own[kWave];
   uint32_t owner_at[kWave];
-  uint32_t count[kWave];  // kept tiles per Gaussian (counting walk)
 };
 
 // A volatile pointer into LDS that keeps its address space: through a plain
@@ -297,8 +296,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // caller wrote before the call is visible to all lanes inside emit.
 // RANKS = true: returns the number of kept tiles of the whole wave (the same
 // in every lane).  RANKS = false (a walk that only counts): the ranks passed
-// to emit are 0, each kept candidate adds 1 to its owner's LDS counter, and
-// each lane gets the kept tiles of its own Gaussian.
+// to emit are 0 and each lane gets the kept tiles of its own Gaussian.
 template <bool RANKS, typename Emit>
 __device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, WalkLds& L, int tile, Emit emit) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -307,7 +305,9 @@ __device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, WalkLds& 
   const uint32_t total = __shfl(incl, kWave - 1, kWave);
   const uint64_t upto = ((lane == 0) ? 0ull : (~0ull >> (64 - lane))) | (1ull << lane);
   const float ftile = (float)tile, ftile1 = (float)(tile - 1);
-  uint32_t running = 0;  // wave-uniform: kept candidates of the earlier steps
+  // RANKS: wave-uniform count of the kept candidates of the earlier steps;
+  // else this lane's Gaussian's kept tiles so far
+  uint32_t running = 0;
   uint32_t tag = 0;
   {
 #pragma clang fp contract(off)
@@ -320,9 +320,7 @@ __device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, WalkLds& 
                            (uint32_t)me.tx0 | ((uint32_t)me.ty0 << 16)};
   }
   lds_volatile_u32* owner_at = lds_volatile(L.owner_at);
-  lds_volatile_u32* count = lds_volatile(L.count);
   owner_at[lane] = 0xffffffffu;  // no step tag matches
-  if (!RANKS) count[lane] = 0u;
   wave_lds_sync();
   for (uint32_t c0 = 0; c0 < total; c0 += kWave, tag += 0x100u) {
     // the Gaussian whose candidates start in (or run into) this step claims its first slot
@@ -346,7 +344,15 @@ __device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, WalkLds& 
     const int ty = (int)(o.txy0 >> 16) + (int)ry;
     const bool keep = tile_keep(o.mx, o.my, o.a, o.b, o.c, o.ra, o.rc, o.thr, x0, x1, y0, y1) & valid;
     if (!RANKS) {
-      if (keep) atomicAdd((uint32_t*)&L.count[owner], 1u);
+      // the claiming lane adds the kept tiles of its Gaussian's segment of
+      // this step (an LDS atomic per kept tile serialises on the owner's
+      // counter and was slower)
+      const uint64_t kb = __ballot(keep);
+      if (claims) {
+        const uint32_t hi = min(cstart + me.cand - c0, (uint32_t)kWave);  // exclusive
+        const uint64_t seg = (hi >= 64 ? ~0ull : ((1ull << hi) - 1ull)) & ~((slot == 0) ? 0ull : ((1ull << slot) - 1ull));
+        running += (uint32_t)__popcll(kb & seg);
+      }
       emit(owner, o, 0u, tx, ty, keep);
       continue;
     }
@@ -355,9 +361,7 @@ __device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, WalkLds& 
     emit(owner, o, running + before, tx, ty, keep);  // uniform call
     running += (uint32_t)__popcll(kb);
   }
-  if (RANKS) return running;
-  wave_lds_sync();
-  return count[lane];
+  return running;
 }
 
 inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }

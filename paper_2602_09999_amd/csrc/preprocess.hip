@@ -605,6 +605,9 @@ hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uin
 // Start and end of each tile's run in the sorted keys.  A thread takes 16
 // bytes of consecutive keys with one load (the key buffer is 256-byte
 // aligned); a run boundary is where a key differs from its neighbour.
+// Each thread takes V consecutive keys (one 16-byte load); the key before and
+// after its run come from the neighbouring lanes (a shuffle), only the wave's
+// first and last lane read them from memory.
 template <typename KT>
 __global__ __launch_bounds__(kBlock) void k_tile_ranges(const KT* __restrict__ keys, uint32_t n,
                                                         const uint32_t* __restrict__ d_count, uint32_t tiles,
@@ -612,8 +615,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_ranges(const KT* __restrict__ k
   constexpr int V = 16 / (int)sizeof(KT);
   constexpr uint32_t kNone = 0xffffffffu;  // differs from every key
   const uint32_t count = d_count ? min(*d_count, n) : n;
+  const int lane = threadIdx.x & (kWave - 1);
   const uint32_t i0 = (blockIdx.x * kBlock + threadIdx.x) * (uint32_t)V;
-  if (i0 >= count) return;
+  if ((blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1u))) * (uint32_t)V >= count) return;  // whole wave
   uint32_t k[V];
   if (i0 + V <= count) {
     struct alignas(16) Vec { KT k[V]; };
@@ -624,8 +628,11 @@ __global__ __launch_bounds__(kBlock) void k_tile_ranges(const KT* __restrict__ k
 #pragma unroll
     for (int j = 0; j < V; ++j) k[j] = (i0 + j < count) ? (uint32_t)keys[i0 + j] : kNone;
   }
-  const uint32_t prev = (i0 == 0) ? kNone : (uint32_t)keys[i0 - 1];
-  const uint32_t next = (i0 + V < count) ? (uint32_t)keys[i0 + V] : kNone;
+  uint32_t prev = (uint32_t)__shfl((int)k[V - 1], (lane + kWave - 1) & (kWave - 1), kWave);
+  uint32_t next = (uint32_t)__shfl((int)k[0], (lane + 1) & (kWave - 1), kWave);
+  if (lane == 0) prev = (i0 == 0) ? kNone : (uint32_t)keys[i0 - 1];
+  if (lane == kWave - 1) next = (i0 + V < count) ? (uint32_t)keys[i0 + V] : kNone;
+  if (i0 >= count) return;
 #pragma unroll
   for (int j = 0; j < V; ++j) {
     const uint32_t kj = k[j];
