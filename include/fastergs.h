@@ -48,6 +48,13 @@ typedef enum fgs_dtype { FGS_F32 = 0, FGS_BF16 = 1 } fgs_dtype;
  *   the dilated matrix are formed in float64 from the float32 entries and the
  *   conic is rounded to float32 (everything else stays float32). */
 #define FGS_FLAG_FP64_CONIC 1u
+/* FGS_FLAG_LOOKBACK_FALLBACK: a test aid.  The duplication's look-back
+ *   (which finds each visible Gaussian's first instance slot) polls no
+ *   status at all, so every workgroup after the first sums the counts of all
+ *   earlier entries directly, the exact path otherwise taken only when a
+ *   bounded wait runs out.  Same results, much slower; for tests of that
+ *   path. */
+#define FGS_FLAG_LOOKBACK_FALLBACK 2u
 
 /* The Gaussian parameters of Sec. 2.1 ("3D Gaussian Splatting"): mean mu,
  * log-scales (scale = exp, "Activation Functions"), rotation quaternion

@@ -16,6 +16,7 @@ FGS_OK, FGS_ERR_INVALID_ARGUMENT, FGS_ERR_CAPACITY, FGS_ERR_HIP, FGS_ERR_UNSUPPO
 FGS_F32, FGS_BF16 = 0, 1
 FGS_MAX_VIEWS = 16
 FGS_FORWARD_NO_SYNC = 1
+FGS_FLAG_FP64_CONIC, FGS_FLAG_LOOKBACK_FALLBACK = 1, 2
 
 
 class Gaussians(ctypes.Structure):

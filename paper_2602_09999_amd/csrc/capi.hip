@@ -103,7 +103,7 @@ fgs_status check_settings(const fgs_settings* st) {
   if (!st) return fail(FGS_ERR_INVALID_ARGUMENT, "settings is NULL");
   if (st->tile != 8 && st->tile != 16 && st->tile != 32)
     return fail(FGS_ERR_INVALID_ARGUMENT, "tile must be 8, 16 or 32 (got %d)", st->tile);
-  if (st->flags & ~(uint32_t)FGS_FLAG_FP64_CONIC)
+  if (st->flags & ~(uint32_t)(FGS_FLAG_FP64_CONIC | FGS_FLAG_LOOKBACK_FALLBACK))
     return fail(FGS_ERR_INVALID_ARGUMENT, "unknown bits in settings.flags 0x%x", st->flags);
   if (!(st->alpha_min > 0.0f && st->alpha_min < st->alpha_max && st->alpha_max <= 1.0f))
     return fail(FGS_ERR_INVALID_ARGUMENT, "need 0 < alpha_min < alpha_max <= 1");
@@ -431,7 +431,8 @@ fgs_status fgs_rasterize_forward_batch(const fgs_gaussians* g, const fgs_camera*
   FGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, (uint64_t)tiles * 2, hs), "ranges clear");
   if (inst > 0 && nvis > 0) {
     FGS_TIMED("duplicate", hs,
-              launch_duplicate(vis_ids[vis_final], d_vis, nvis, dup_scan, dup_scan, rec, vs, n, st->tile, cap,
+              launch_duplicate(vis_ids[vis_final], d_vis, nvis, dup_scan, dup_scan,
+                               (st->flags & FGS_FLAG_LOOKBACK_FALLBACK) != 0, rec, vs, n, st->tile, cap,
                                ikeys[0], key_bytes, ivals[0], hs),
               "duplicate");
     int inst_final = 0;

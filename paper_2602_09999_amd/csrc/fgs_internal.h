@@ -443,10 +443,12 @@ hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth
 // out-of-range id `tiles` fit) or uint32 (key_bytes 4).  Each visible entry's
 // first slot is found by the kernel (decoupled look-back over its workgroups
 // in dup_scan, dup_scan_words(n) words zeroed beforehand; a workgroup whose
-// wait runs out sums the earlier counts itself and adds 1 to *slow).
+// wait runs out sums the earlier counts itself and adds 1 to *slow;
+// no_wait: every workgroup after the first takes that path, for tests).
 size_t dup_scan_words(uint64_t n);
 hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uint32_t n, uint32_t* dup_scan,
-                            uint32_t* slow, const float4* rec, const ViewSet& vs, uint32_t n_gauss, int tile,
+                            uint32_t* slow, bool no_wait, const float4* rec, const ViewSet& vs,
+                            uint32_t n_gauss, int tile,
                             uint32_t cap, void* keys, int key_bytes, uint32_t* vals, hipStream_t s);
 // Ranges of the first min(*d_count, n) (or n) sorted keys.
 hipError_t launch_tile_ranges(const void* keys, int key_bytes, uint32_t n, const uint32_t* d_count, uint32_t tiles,

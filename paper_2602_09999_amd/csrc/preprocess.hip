@@ -468,17 +468,17 @@ __device__ __forceinline__ uint32_t dup_count(const uint32_t* __restrict__ vis_i
 // prefix are added and the look-back ends, or moves on to the next window if
 // the window holds no inclusive prefix.  (Windows of several statuses per
 // lane cost registers, and so occupancy in the walk that follows, for no
-// gain.)  After kDupSpinLimit polls of a window the wave adds up the counts
-// of entries 0..blk*256-1 itself.
+// gain.)  After spin_limit polls of a window (kDupSpinLimit; 0 to test the
+// fallback) the wave adds up the counts of entries 0..blk*256-1 itself.
 __device__ __forceinline__ uint64_t dup_lookback(uint64_t* status, uint32_t blk, const uint32_t* __restrict__ vis_ids,
-                                                 const float4* __restrict__ rec, uint32_t* slow) {
+                                                 const float4* __restrict__ rec, uint32_t* slow, uint32_t spin_limit) {
   const int lane = threadIdx.x & (kWave - 1);
   uint64_t acc = 0;
   for (int64_t top = (int64_t)blk - 1;; top -= kWave) {
     const int64_t j = top - lane;
     uint64_t st = 0, incl = 0, needed = 0;
     bool ready = false;
-    for (uint32_t spin = 0; spin < kDupSpinLimit && !ready; ++spin) {
+    for (uint32_t spin = 0; spin < spin_limit && !ready; ++spin) {
       st = j >= 0 ? dup_status_load(status + j) : kDupInclusive;
       const uint32_t flag = (uint32_t)(st >> 32);
       incl = __ballot(flag == 2u);
@@ -507,6 +507,7 @@ template <typename KT>
 __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict__ vis_ids,
                                                       const uint32_t* __restrict__ d_nvis, uint32_t n,
                                                       uint32_t* __restrict__ dup_scan, uint32_t* __restrict__ slow,
+                                                      uint32_t spin_limit,
                                                       const float4* __restrict__ rec, ViewSet vs,
                                                       uint32_t n_gauss, int tile, uint32_t cap,
                                                       KT* __restrict__ keys, uint32_t* __restrict__ vals) {
@@ -542,7 +543,7 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
   const uint32_t excl = block_exclusive_scan(count, s_scan, &btotal);
   if (threadIdx.x == 0) dup_status_store(status + blk, (blk == 0 ? kDupInclusive : kDupAggregate) | btotal);
   if (threadIdx.x < kWave) {
-    const uint64_t prefix = blk > 0 ? dup_lookback(status, blk, vis_ids, rec, slow) : 0ull;
+    const uint64_t prefix = blk > 0 ? dup_lookback(status, blk, vis_ids, rec, slow, spin_limit) : 0ull;
     if (threadIdx.x == 0) {
       if (blk > 0) dup_status_store(status + blk, kDupInclusive | (uint32_t)(prefix + btotal));
       s_base = (uint32_t)prefix;
@@ -588,17 +589,17 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
 }
 
 hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uint32_t n, uint32_t* dup_scan,
-                            uint32_t* slow, const float4* rec, const ViewSet& vs, uint32_t n_gauss, int tile,
-                            uint32_t cap, void* keys, int key_bytes, uint32_t* vals, hipStream_t s) {
+                            uint32_t* slow, bool no_wait, const float4* rec, const ViewSet& vs, uint32_t n_gauss,
+                            int tile, uint32_t cap, void* keys, int key_bytes, uint32_t* vals, hipStream_t s) {
   if (n == 0) return hipSuccess;
+  const uint32_t spin_limit = no_wait ? 0u : kDupSpinLimit;
+  const uint32_t grid = ceil_div(n, kBlock);
   if (key_bytes == 2)
-    k_duplicate<uint16_t><<<ceil_div(n, kBlock), kBlock, 0, s>>>(vis_ids, d_nvis, n, dup_scan, slow, rec, vs,
-                                                                 n_gauss, tile, cap, static_cast<uint16_t*>(keys),
-                                                                 vals);
+    k_duplicate<uint16_t><<<grid, kBlock, 0, s>>>(vis_ids, d_nvis, n, dup_scan, slow, spin_limit, rec, vs, n_gauss,
+                                                  tile, cap, static_cast<uint16_t*>(keys), vals);
   else
-    k_duplicate<uint32_t><<<ceil_div(n, kBlock), kBlock, 0, s>>>(vis_ids, d_nvis, n, dup_scan, slow, rec, vs,
-                                                                 n_gauss, tile, cap, static_cast<uint32_t*>(keys),
-                                                                 vals);
+    k_duplicate<uint32_t><<<grid, kBlock, 0, s>>>(vis_ids, d_nvis, n, dup_scan, slow, spin_limit, rec, vs, n_gauss,
+                                                  tile, cap, static_cast<uint32_t*>(keys), vals);
   return hipGetLastError();
 }
 

@@ -114,10 +114,11 @@ def test_invalid_arguments_are_rejected_without_launching(lib):
     assert size.value > 3 * one.value // 2
     st7 = B.default_settings(tile=7)
     assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(st7), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
-    stf = B.default_settings(flags=2)  # only FGS_FLAG_FP64_CONIC (bit 0) is defined
+    stf = B.default_settings(flags=4)  # only bits 0 and 1 are defined
     assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(stf), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
-    st1 = B.default_settings(flags=1)
-    assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(st1), 0, ctypes.byref(size)) == L.FGS_OK
+    for flags in (L.FGS_FLAG_FP64_CONIC, L.FGS_FLAG_LOOKBACK_FALLBACK, 3):
+        st1 = B.default_settings(flags=flags)
+        assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(st1), 0, ctypes.byref(size)) == L.FGS_OK
     stb = B.default_settings(alpha_min=0.995)
     assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(stb), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
 

@@ -232,6 +232,26 @@ def test_forward_is_deterministic():
     assert np.array_equal(va, vb) and np.array_equal(ra, rb)
 
 
+@pytest.mark.parametrize("case", ["c1", "ragged_n"])
+def test_lookback_fallback_gives_the_same_lists(case):
+    """The duplication's exact fallback (a workgroup sums the counts of all
+    earlier entries itself), forced from the host for every workgroup after
+    the first: the instance lists and the image equal those of the look-back,
+    which the keys test checks against the oracle."""
+    sc, cam = CASES[case]()
+    say("look-back fallback", case)
+    a = forward(sc, cam)
+    b = forward(sc, cam, settings=B.default_settings(flags=L.FGS_FLAG_LOOKBACK_FALLBACK))
+    nvis = a[0].last_stats["n_visible"]
+    say("  visible", nvis, "slow-path workgroups", b[0].lookback_slow_count())
+    assert a[0].lookback_slow_count() == 0
+    assert b[0].lookback_slow_count() == (nvis + 255) // 256 - 1 > 0
+    ka, va, ra = sorted_instances(a[0])
+    kb, vb, rb = sorted_instances(b[0])
+    assert np.array_equal(ka, kb) and np.array_equal(va, vb) and np.array_equal(ra, rb)
+    assert torch.equal(a[2], b[2]) and torch.equal(a[4], b[4])
+
+
 def test_capacity_overflow_reports_count_and_retry_succeeds():
     sc, cam = CASES["c1"]()
     say("capacity")
