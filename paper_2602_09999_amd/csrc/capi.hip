@@ -425,10 +425,12 @@ fgs_status fgs_rasterize_forward_batch(const fgs_gaussians* g, const fgs_camera*
     FGS_HIP(radix_sort_pairs(vis_keys, vis_ids, nvis, no_sync ? d_vis : nullptr, 0, depth_bits, scratch, &vis_final,
                              hs, no_sync ? counters + kStatKeyMin : nullptr, false),
             "depth sort");
-    FGS_HIP(launch_set_word(counters + kStatDepthBuf, (uint32_t)vis_final, hs), "depth buffer note");
   }
 
-  FGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, (uint64_t)tiles * 2, hs), "ranges clear");
+  // (the same launch notes which depth buffer holds the sorted visible ids)
+  FGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, (uint64_t)tiles * 2, hs,
+                          nvis > 0 ? counters + kStatDepthBuf : nullptr, (uint32_t)vis_final),
+          "ranges clear");
   if (inst > 0 && nvis > 0) {
     FGS_TIMED("duplicate", hs,
               launch_duplicate(vis_ids[vis_final], d_vis, nvis, dup_scan, dup_scan,

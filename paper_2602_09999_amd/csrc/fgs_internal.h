@@ -371,8 +371,10 @@ inline uint64_t round_up64(uint64_t w) { return (w + 63) & ~uint64_t(63); }
 // ----------------------------------------------------------------------------
 // Host-side launchers (each .hip file owns its kernels).
 // ----------------------------------------------------------------------------
-// p[0..n) = v (a kernel, so captured graphs contain no memset nodes)
-hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+// p[0..n) = v (a kernel, so captured graphs contain no memset nodes); the
+// same launch also sets *word = word_v when word is given.
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s, uint32_t* word = nullptr,
+                           uint32_t word_v = 0u);
 
 // Scratch words needed by scan_u32 for n items.
 size_t scan_scratch_words(uint64_t n);
@@ -417,7 +419,6 @@ constexpr int kStatInstances = 4;  // instance count I, uint64 at words 4-5
 constexpr int kStatSortCount = 6;  // min(I, instance capacity): instances written and sorted
 constexpr int kStatOverflow = 7;   // 1 when I exceeds the instance capacity
 constexpr int kStatTouched = 8;    // fused backward: Gaussians that received a gradient
-hipError_t launch_set_word(uint32_t* p, uint32_t v, hipStream_t s);
 // Z-order: scratch bytes for n Gaussians; perm[k] = index of the Gaussian at
 // position k of the Morton order of the means [3][n]; gather of `planes`
 // planes of n elements of 2 or 4 bytes: dst[p][k] = src[p][perm[k]].

@@ -346,15 +346,6 @@ size_t stats_scratch_words(uint32_t nb) {
   return 4 * (size_t)nb + round_up64(sizeof(StatsGroup) / 4 * ng) + round_up64(ng);
 }
 
-__global__ void k_set_word(uint32_t* __restrict__ p, uint32_t v) {
-  if (threadIdx.x == 0) *p = v;
-}
-
-hipError_t launch_set_word(uint32_t* p, uint32_t v, hipStream_t s) {
-  k_set_word<<<1, kWave, 0, s>>>(p, v);
-  return hipGetLastError();
-}
-
 // The group records and group starts follow the nb partials in the same scratch.
 static StatsGroup* stats_groups(uint4* partials, uint32_t nb) {
   return reinterpret_cast<StatsGroup*>(reinterpret_cast<uint32_t*>(partials) + 4 * (size_t)nb);

@@ -9,13 +9,17 @@
 // ballots, count the ones below them, and keep a running per-digit counter
 // per wave in LDS; wave offsets are then prefixed in wave order.  The ranked
 // block is staged in LDS in digit order and written out in coalesced runs.
+#include <algorithm>
+
 #include "fgs_internal.h"
 
 namespace fgs {
 
 // Fill of n 32-bit words with a value: used instead of hipMemsetAsync so that
 // a captured graph holds only kernel nodes.  16-byte stores where aligned.
-__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, uint64_t n) {
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, uint64_t n,
+                                                    uint32_t* __restrict__ word, uint32_t word_v) {
+  if (word != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *word = word_v;
   const uint64_t i4 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * 4;
   if (i4 + 4 <= n && ((uintptr_t)p & 15u) == 0) {
     *reinterpret_cast<uint4*>(p + i4) = make_uint4(v, v, v, v);
@@ -24,10 +28,10 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* __restrict__ p, u
   }
 }
 
-hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  const uint64_t threads = (n + 3) / 4;
-  k_fill_u32<<<(uint32_t)((threads + kBlock - 1) / kBlock), kBlock, 0, s>>>(p, v, n);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s, uint32_t* word, uint32_t word_v) {
+  if (n == 0 && word == nullptr) return hipSuccess;
+  const uint64_t threads = std::max<uint64_t>((n + 3) / 4, 1);
+  k_fill_u32<<<(uint32_t)((threads + kBlock - 1) / kBlock), kBlock, 0, s>>>(p, v, n, word, word_v);
   return hipGetLastError();
 }
 
