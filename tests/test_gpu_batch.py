@@ -139,6 +139,29 @@ def test_single_view_forward_without_synchronisation():
     assert small.overflowed()
 
 
+def test_forward_without_synchronisation_skips_constant_depth_digits():
+    """A scene spread over a very thin depth range: the visible depth keys
+    agree in all bits from 16 up, so the synchronisation-free depth sort
+    (four passes over 31 bits) only copies in its last two passes, taking
+    the key range from the device.  Its results equal the synchronised
+    forward's, which sorts only the bits that vary."""
+    sc, cam = S.make_scene(8_000, 6, z_range=(3.0, 3.0005)), S.workload_camera("c1")
+    say("no-sync forward, thin depth range")
+    params = to_gpu(sc)
+    rz = B.Rasterizer(cam)
+    img, tf, last = (t.clone() for t in rz.forward(params))
+    keys, vals, ranges = sorted_instances(rz)
+    c = rz.view("counters", 16).cpu().numpy().view(np.uint32)
+    kmin, kmax = int(c[1]), int(c[2])
+    say("  visible", rz.last_stats["n_visible"], "depth keys differ in bits", hex(kmin ^ kmax))
+    assert rz.last_stats["n_visible"] > 256 and (kmin ^ kmax) >> 16 == 0 and (kmin ^ kmax) >> 8 != 0
+    img2, tf2, last2 = rz.forward(params, sync=False)
+    assert not rz.overflowed()
+    assert torch.equal(img2, img) and torch.equal(tf2, tf) and torch.equal(last2, last)
+    keys2, vals2, ranges2 = sorted_instances(rz)
+    assert np.array_equal(keys2, keys) and np.array_equal(vals2, vals) and np.array_equal(ranges2, ranges)
+
+
 def test_batch_without_synchronisation_and_overflow_flag():
     sc = S.batch_scene(20_000, 4)
     cams = small_views()
