@@ -426,8 +426,8 @@ hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth
 //
 // A wave handles 64 consecutive Gaussians and spreads their candidate tiles
 // over its lanes (load-balanced walk), so the wave's kept tiles are written as
-// one contiguous, coalesced run.  Writes never pass a Gaussian's own count nor
-// `cap`.  Entries are (view, Gaussian) indices j = v n_gauss + i; the key of
+// one contiguous, coalesced run.  Writes stay inside the wave's run of slots
+// and below `cap`.  Entries are (view, Gaussian) indices j = v n_gauss + i; the key of
 // an instance is its global tile id tile_base[v] + ty tiles_x(v) + tx.
 //
 // dup_scan: word 0 the slow-path count, then at word 64 one 64-bit status per
