@@ -220,13 +220,23 @@ __device__ __forceinline__ void gaussian_grads(const GaussDev& g, const CamDev& 
   emit(11, dc0 * Y[0]);
   emit(12, dc1 * Y[0]);
   emit(13, dc2 * Y[0]);
+  // every coefficient is loaded before the first is used (loads guarded by the
+  // run-time band count would each be waited for in turn)
+  const int K = g.sh_coeffs;  // 1, 4, 9 or 16
+  float rest[45];
+  if (K == 16) {  // uniform
+#pragma unroll
+    for (int q = 0; q < 45; ++q) rest[q] = sh_load<SHB>(g.sh_rest, (size_t)q * n + i);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 45; ++q) rest[q] = (q < 3 * (K - 1)) ? sh_load<SHB>(g.sh_rest, (size_t)q * n + i) : 0.0f;
+  }
 #pragma unroll
   for (int k = 1; k < 16; ++k) {
     const int q = 14 + 3 * (k - 1);
-    if (k < g.sh_coeffs) {
-      const size_t o3 = (size_t)(3 * (k - 1)) * n + i;
-      const float e = dc0 * sh_load<SHB>(g.sh_rest, o3) + dc1 * sh_load<SHB>(g.sh_rest, o3 + n) +
-                      dc2 * sh_load<SHB>(g.sh_rest, o3 + 2 * n);
+    if (k < K) {
+      const int q3 = 3 * (k - 1);
+      const float e = dc0 * rest[q3] + dc1 * rest[q3 + 1] + dc2 * rest[q3 + 2];
       gdx = fmaf(e, dYx[k], gdx);
       gdy = fmaf(e, dYy[k], gdy);
       gdz = fmaf(e, dYz[k], gdz);
@@ -432,9 +442,17 @@ __global__ __launch_bounds__(kBlock) void k_touched_grads(GaussDev g, CamDev cam
 #pragma unroll
     for (int q = 0; q < 9; ++q) a[q] = accum[(size_t)i * 9 + q];
     const float mu[3] = {g.means[i], g.means[n + i], g.means[2 * n + i]};
+    // the 59 gradients are kept in registers and stored after the chain rule,
+    // so that none of its loads has to wait behind a store (the kernel runs
+    // few waves and is bound by this thread's chain of memory round trips)
+    float out[kParams];
+#pragma unroll
+    for (int p = 0; p < kParams; ++p) out[p] = 0.0f;
     gaussian_grads<SHB>(g, cam, rec, a, i, i, mu, [&](int p, float v) {
-      grads[(size_t)p * n + slot] = group_of(p) >= 4 ? sh_round<SHB>(v) : v;
+      out[p] = group_of(p) >= 4 ? sh_round<SHB>(v) : v;
     });
+#pragma unroll
+    for (int p = 0; p < kParams; ++p) grads[(size_t)p * n + slot] = out[p];
   }
 }
 
@@ -450,7 +468,6 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd_views(GaussDev g, Vie
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
   const size_t n = g.n;
   if (i >= n) return;
-  const size_t vn = n * vs.n_views;
   void* const out[6] = {gr.means, gr.log_scales, gr.quats, gr.logits, gr.sh_dc, gr.sh_rest};
   const bool dyn = g.velocity != nullptr;
   float sum[kParams], dvel[3] = {0.f, 0.f, 0.f}, dacc[3] = {0.f, 0.f, 0.f};
