@@ -93,7 +93,12 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, ViewSet vs, S
   const size_t j = (size_t)view * n + i;
   const float* W = cam.w;
 
+  // every parameter load goes out before the first store (the depth key),
+  // which they could otherwise not pass
   float mu0 = g.means[i], mu1 = g.means[n + i], mu2 = g.means[2 * n + i];
+  const float qw0 = g.quats[i], qx0 = g.quats[n + i], qy0 = g.quats[2 * n + i], qz0 = g.quats[3 * n + i];
+  const float ls0 = g.log_scales[i], ls1 = g.log_scales[n + i], ls2 = g.log_scales[2 * n + i];
+  const float logit = g.logits[i];
   if (g.velocity) {  // dynamic scene: mean at the view's time, (mu + v t) + a t^2
     const float t = vs.time[view], tt = t * t;
     mu0 = (mu0 + g.velocity[i] * t) + g.accel[i] * tt;
@@ -106,7 +111,6 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, ViewSet vs, S
   if (in_range) depth_key[j] = __float_as_uint(Z);
 
   // activations: normalised quaternion, exp scales, sigmoid opacity
-  const float qw0 = g.quats[i], qx0 = g.quats[n + i], qy0 = g.quats[2 * n + i], qz0 = g.quats[3 * n + i];
   const float n2 = ((qw0 * qw0 + qx0 * qx0) + qy0 * qy0) + qz0 * qz0;
   const float qn = sqrtf(n2);
   const float w = qw0 / qn, x = qx0 / qn, y = qy0 / qn, z = qz0 / qn;
@@ -115,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, ViewSet vs, S
   const float r00 = 1.0f - 2.0f * (yy + zz), r01 = 2.0f * (xy - wz), r02 = 2.0f * (xz + wy);
   const float r10 = 2.0f * (xy + wz), r11 = 1.0f - 2.0f * (xx + zz), r12 = 2.0f * (yz - wx);
   const float r20 = 2.0f * (xz - wy), r21 = 2.0f * (yz + wx), r22 = 1.0f - 2.0f * (xx + yy);
-  const float s0 = expf(g.log_scales[i]), s1 = expf(g.log_scales[n + i]), s2 = expf(g.log_scales[2 * n + i]);
+  const float s0 = expf(ls0), s1 = expf(ls1), s2 = expf(ls2);
   const float m00 = r00 * s0, m01 = r01 * s1, m02 = r02 * s2;
   const float m10 = r10 * s0, m11 = r11 * s1, m12 = r12 * s2;
   const float m20 = r20 * s0, m21 = r21 * s1, m22 = r22 * s2;
@@ -167,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, ViewSet vs, S
     cc = h00 / deth;
     det_ok = det >= st.det_min;
   }
-  const float o = 1.0f / (1.0f + expf(-g.logits[i]));
+  const float o = 1.0f / (1.0f + expf(-logit));
 
   bool ok = (qn >= st.quat_min) && (Z >= cam.near_z) && det_ok && (o > st.alpha_min);
   // opacity-aware extent: alpha reaches alpha_min out to d^T Sigma^-1 d = 2 ln(o / alpha_min)
