@@ -299,19 +299,29 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const uint2* __restrict__ r
   float T[kRows], R[kRows];
   uint32_t my_last[kRows];
   uint32_t walk = 0;
+  // the pixels' inputs are loaded all at once: a pixel outside the image
+  // reads the nearest one inside (always a valid address) and is zeroed
+  // (loads under a per-lane guard would go out one row at a time)
+  float img[kRows][3];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int py = ty * TILE + lane / TILE + kStep * r;
+    const size_t pix = (size_t)min(py, cam.height - 1) * cam.width + min(px, cam.width - 1);
+    my_last[r] = last[pix];
+    gc0[r] = dl_dimage[pix]; gc1[r] = dl_dimage[hw + pix]; gc2[r] = dl_dimage[2 * hw + pix];
+    img[r][0] = image[pix]; img[r][1] = image[hw + pix]; img[r][2] = image[2 * hw + pix];
+  }
 #pragma unroll
   for (int r = 0; r < kRows; ++r) {
     const int py = ty * TILE + lane / TILE + kStep * r;
     fy[r] = (float)py + 0.5f;
     T[r] = 1.0f;
-    R[r] = 0.0f;
-    gc0[r] = gc1[r] = gc2[r] = 0.0f;
-    my_last[r] = 0;
     if (px < cam.width && py < cam.height) {
-      const size_t pix = (size_t)py * cam.width + px;
-      my_last[r] = last[pix];
-      gc0[r] = dl_dimage[pix]; gc1[r] = dl_dimage[hw + pix]; gc2[r] = dl_dimage[2 * hw + pix];
-      R[r] = gc0[r] * image[pix] + gc1[r] * image[hw + pix] + gc2[r] * image[2 * hw + pix];
+      R[r] = gc0[r] * img[r][0] + gc1[r] * img[r][1] + gc2[r] * img[r][2];
+    } else {
+      my_last[r] = 0;
+      gc0[r] = gc1[r] = gc2[r] = 0.0f;
+      R[r] = 0.0f;
     }
     walk = max(walk, my_last[r]);
   }
