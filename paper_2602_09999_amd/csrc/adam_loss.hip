@@ -335,16 +335,33 @@ hipError_t launch_adam_sparse(void* const params[6], float* const exp_avg[6], fl
 }
 
 // dL/dC = sign(C - target) / n; optional float64 sum of |C - target| / n.
+// A thread takes four consecutive pixels values (16-byte accesses) when the
+// buffers are 16-byte aligned, else one.
+template <int V>
 __global__ __launch_bounds__(kBlock) void k_l1(const float* __restrict__ img, const float* __restrict__ tgt,
                                                uint32_t n, float inv_n, double inv_n64, float* __restrict__ dl,
                                                double* __restrict__ loss) {
   __shared__ double part[kBlock / kWave];
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t i0 = (blockIdx.x * kBlock + threadIdx.x) * (uint32_t)V;
   double a = 0.0;
-  if (i < n) {
-    const float d = img[i] - tgt[i];
-    dl[i] = d > 0.0f ? inv_n : (d < 0.0f ? -inv_n : 0.0f);
-    a = fabs((double)img[i] - (double)tgt[i]);
+  if (V == 4 && i0 + 4 <= n) {
+    const float4 c = *reinterpret_cast<const float4*>(img + i0);
+    const float4 t = *reinterpret_cast<const float4*>(tgt + i0);
+    const float cv[4] = {c.x, c.y, c.z, c.w}, tv[4] = {t.x, t.y, t.z, t.w};
+    float o[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float d = cv[e] - tv[e];
+      o[e] = d > 0.0f ? inv_n : (d < 0.0f ? -inv_n : 0.0f);
+      if (loss) a += fabs((double)cv[e] - (double)tv[e]);
+    }
+    *reinterpret_cast<float4*>(dl + i0) = make_float4(o[0], o[1], o[2], o[3]);
+  } else {
+    for (uint32_t i = i0; i < i0 + V && i < n; ++i) {
+      const float d = img[i] - tgt[i];
+      dl[i] = d > 0.0f ? inv_n : (d < 0.0f ? -inv_n : 0.0f);
+      a += fabs((double)img[i] - (double)tgt[i]);
+    }
   }
   if (loss == nullptr) return;
 #pragma unroll
@@ -366,8 +383,12 @@ hipError_t launch_l1_backward(const float* image, const float* target, uint32_t 
     if (e != hipSuccess) return e;
   }
   if (n == 0) return hipSuccess;
-  k_l1<<<ceil_div(n, kBlock), kBlock, 0, s>>>(image, target, n, (float)(1.0 / (double)n), 1.0 / (double)n, dl,
-                                              loss);
+  const float inv_n = (float)(1.0 / (double)n);
+  const double inv_n64 = 1.0 / (double)n;
+  if ((((uintptr_t)image | (uintptr_t)target | (uintptr_t)dl) & 15u) == 0)
+    k_l1<4><<<ceil_div(ceil_div(n, 4), kBlock), kBlock, 0, s>>>(image, target, n, inv_n, inv_n64, dl, loss);
+  else
+    k_l1<1><<<ceil_div(n, kBlock), kBlock, 0, s>>>(image, target, n, inv_n, inv_n64, dl, loss);
   return hipGetLastError();
 }
 
