@@ -12,8 +12,11 @@ namespace fgs {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 constexpr int kWave = 64;
-constexpr int kScanItems = 16;       // items per thread in the 32-bit-key radix kernels
-constexpr int kScanTile = kBlock * kScanItems;
+// items per thread in the 32-bit-key radix kernels (a build-time tuning constant)
+#ifndef FGS_SORT32_ITEMS
+#define FGS_SORT32_ITEMS 16
+#endif
+constexpr int kScanItems = FGS_SORT32_ITEMS;
 // pairs per thread of the 16-bit-key sort (a build-time tuning constant)
 #ifndef FGS_SORT16_ITEMS
 #define FGS_SORT16_ITEMS 16

@@ -516,11 +516,12 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
   uint64_t* status = reinterpret_cast<uint64_t*>(dup_scan + kDupStatusWord);
   const uint32_t p = blk * kBlock + threadIdx.x;
   CandLane me = {};
-  uint32_t gid = 0, count = 0, kbase = 0;
+  uint32_t gid = 0, count = 0, kbase = 0, tiles_x = 0;
   if (p < nv) {
     gid = vis_ids[p];
     const uint32_t v = vs.n_views > 1 ? gid / n_gauss : 0u;
     kbase = vs.tile_base[v];
+    tiles_x = (uint32_t)vs.cam[v].tiles_x;
     me.width = vs.cam[v].width;
     me.height = vs.cam[v].height;
     // three float4 of one 64-byte record: one cache line per Gaussian
@@ -555,18 +556,26 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
   const uint32_t run_start = __shfl(off, 0, kWave);
   const uint32_t run_end = __shfl(off + count, kWave - 1, kWave);
   const uint32_t lim = min(run_end, cap);
-  // the owner's Gaussian and key base, read by owner in emit
-  s_dup[threadIdx.x / kWave][threadIdx.x & (kWave - 1)] = make_uint2(gid, kbase);
+  // the owner's Gaussian and key base, read by owner in emit; with 16-bit
+  // keys the base and the view's tiles_x both fit in 16 bits and share a word
   const int tile_shift = __builtin_ctz((unsigned)tile);
+  s_dup[threadIdx.x / kWave][threadIdx.x & (kWave - 1)] =
+      make_uint2(gid, sizeof(KT) == 2 ? (kbase | (tiles_x << 16)) : kbase);
   const uint32_t written = wave_tile_walk<true>(
       me, s_walk[threadIdx.x / kWave], tile,
       [&](int owner, const OwnerRec& o, uint32_t rank, int tx, int ty, bool keep) {
         const uint32_t slot = run_start + rank;
         if (keep && slot < lim) {
           const uint2 d = s_dup[threadIdx.x / kWave][owner];
-          // tiles_x of the owner's view (xmax = width - 0.5)
-          const uint32_t row = ((uint32_t)(o.xmax + 0.5f) + (uint32_t)tile - 1u) >> tile_shift;
-          keys[slot] = (KT)(d.y + __umul24((uint32_t)ty, row) + (uint32_t)tx);  // 16-bit tile coordinates
+          // tile coordinates and tiles_x stay below 2^16, so __umul24 is exact
+          uint32_t key;
+          if (sizeof(KT) == 2) {
+            key = (d.y & 0xffffu) + __umul24((uint32_t)ty, d.y >> 16) + (uint32_t)tx;
+          } else {  // tiles_x of the owner's view (xmax = width - 0.5)
+            const uint32_t row = ((uint32_t)(o.xmax + 0.5f) + (uint32_t)tile - 1u) >> tile_shift;
+            key = d.y + __umul24((uint32_t)ty, row) + (uint32_t)tx;
+          }
+          keys[slot] = (KT)key;
           vals[slot] = d.x;
         }
       });
@@ -598,12 +607,11 @@ hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uin
   return hipGetLastError();
 }
 
-// Start and end of each tile's run in the sorted keys.  A thread takes 16
-// bytes of consecutive keys with one load (the key buffer is 256-byte
-// aligned); a run boundary is where a key differs from its neighbour.
-// Each thread takes V consecutive keys (one 16-byte load); the key before and
-// after its run come from the neighbouring lanes (a shuffle), only the wave's
-// first and last lane read them from memory.
+// Start and end of each tile's run in the sorted keys; a run boundary is where
+// a key differs from its neighbour.  Each thread takes V consecutive keys with
+// one 16-byte load (the key buffer is 256-byte aligned); the keys just before
+// and after its V come from the neighbouring lanes by shuffle, and only the
+// wave's first and last lane read them from memory.
 template <typename KT>
 __global__ __launch_bounds__(kBlock) void k_tile_ranges(const KT* __restrict__ keys, uint32_t n,
                                                         const uint32_t* __restrict__ d_count, uint32_t tiles,

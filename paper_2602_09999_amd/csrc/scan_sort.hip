@@ -344,8 +344,9 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT* __restrict__
   }
 }
 
-// Pairs per block of the sorts: the 16-bit tile sort takes larger blocks
-// (longer digit runs per block, so fuller write-out lines) in the same LDS.
+// Pairs per block of the sorts (kBlock times the items per thread): smaller
+// blocks mean more histogram entries and shorter digit runs per block to
+// write out, larger ones fewer waves per SIMD (more registers and LDS).
 template <typename KT>
 struct SortShape;
 template <>
