@@ -413,8 +413,13 @@ static hipError_t radix_sort_impl(KT* keys[2], uint32_t* vals[2], uint32_t n, co
   const int passes = (bits + kRadixBits - 1) / kRadixBits;
   int shift = begin_bit;
   for (int p = 0; p < passes; ++p) {
-    // the remaining bits, split evenly over the remaining passes
-    const int rb = (end_bit - shift + (passes - p) - 1) / (passes - p);
+    // the remaining bits, split evenly over the remaining passes; with 16-bit
+    // keys the narrower digit goes first (13 tile bits as 6 + 7: histograms
+    // and scatters 276 instead of 289 us per step at 3M Gaussians), with
+    // 32-bit keys last (the depth keys' top digit is nearly constant, and its
+    // histogram gains from having fewer digits)
+    const int left = end_bit - shift, rest = passes - p;
+    const int rb = sizeof(KT) == 2 ? left / rest : (left + rest - 1) / rest;
     KT* kout = (p + 1 == passes && !keep_keys) ? nullptr : keys[cur ^ 1];
     hipError_t e = hipSuccess;
     switch (rb) {
