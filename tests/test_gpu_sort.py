@@ -20,6 +20,9 @@ CASES = [
     (2, 13, 4095, None),
     (2, 13, 4097, 7),
     (2, 16, 1_000_003, None),
+    (2, 9, 300_007, None),        # digits 4 + 5 (16-bit keys: the narrower digit first)
+    (2, 15, 500_009, 20_000),     # digits 7 + 8
+    (4, 9, 300_007, None),        # digits 5 + 4 (32-bit keys: the narrower digit last)
     (2, 13, 9_000_001, None),     # flat scan, direct partial sums
     (2, 13, 70_000_017, 6_700),   # flat scan over scanned partial sums (7-bit pass)
     (4, 31, 5, None),
