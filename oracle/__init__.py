@@ -18,6 +18,9 @@ keys32     FP32 emulation of the (tile, depth) instance keys: opacity-aware
 adam64     Adam in FP64 with the paper's hyperparameters.
 zorder32   Morton (z-order) permutation of the means: FP32 quantisation,
            bit interleave, stable order.
+fp32err    float32 error model of the threshold decisions (Monte Carlo
+           arithmetic over the per-Gaussian formulas): the width of the
+           borderline bands the comparison protocol exempts.
 
 Pins (tests/test_oracle_*.py) tie each function to closed forms, invariants,
 finite differences, library special cases and brute force; see those tests.
@@ -29,3 +32,4 @@ from .render64 import (  # noqa: F401
 from .adam64 import adam64  # noqa: F401
 from .keys32 import keys_ref, keys_ref_banded, depth_key32, tile_lists_for, record32, tile_rect  # noqa: F401
 from . import zorder32  # noqa: F401
+from . import fp32err  # noqa: F401

@@ -45,6 +45,8 @@ from typing import Dict, Optional, Sequence, Tuple
 import numpy as np
 import torch
 
+from . import fp32err as E
+
 F64 = torch.float64
 
 
@@ -67,10 +69,9 @@ class Settings:
 
 DEFAULT_SETTINGS = Settings()
 
-# Relative half-widths of the borderline bands used by the comparison protocol.
-ALPHA_BAND = 1e-4
-T_BAND = 5e-4
-CULL_BAND = 1e-4
+# Borderline decisions (a threshold test whose float64 value lies within the
+# float32 error of the compared quantity) are found with the float32 error
+# model of ``fp32err``.
 
 
 # ----------------------------------------------------------------------------
@@ -135,7 +136,7 @@ def _rows(scene: Dict[str, torch.Tensor]) -> Dict[str, torch.Tensor]:
 
 
 def preprocess64(p: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTINGS,
-                 sh_degree: int = 3) -> Dict[str, torch.Tensor]:
+                 sh_degree: int = 3, mca: bool = False) -> Dict[str, torch.Tensor]:
     """Per-Gaussian projection in float64 (differentiable w.r.t. the row tensors in p).
 
     p holds row tensors: means [N,3], log_scales [N,3], quats [N,4],
@@ -143,7 +144,9 @@ def preprocess64(p: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
     Returns mean2d [N,2], cov2d [N,2,2] (un-dilated), cov2d_dil, conic [N,3]
     (a, b, c of the inverse dilated matrix [[a, b], [b, c]]), opacity [N],
     rgb [N,3], colour before the clip, camera-space position, the cull mask
-    ``valid`` and the opacity-aware rectangle half-extents.  Rows failing a
+    ``valid``, the opacity-aware rectangle half-extents, the borderline flags
+    of the culls and the colour clip, and with ``mca`` the float32 deviation
+    samples of ``fp32err.mca_deviations`` (key ``dev``).  Rows failing a
     cull test may hold non-finite values; callers select ``valid`` rows.
     """
     mu = p["means"]
@@ -193,40 +196,89 @@ def preprocess64(p: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
     with torch.no_grad():
         valid = ((qn >= st.quat_min) & (z >= float(cam.near)) & (det2d >= st.det_min)
                  & (opacity > st.tau_alpha) & torch.isfinite(det2d))
-        cull_border = ((torch.abs(qn - st.quat_min) <= CULL_BAND * st.quat_min)
-                       | (torch.abs(z - float(cam.near)) <= CULL_BAND * float(cam.near))
-                       | (torch.abs(det2d - st.det_min) <= CULL_BAND * st.det_min)
-                       | (torch.abs(opacity - st.tau_alpha) <= CULL_BAND * st.tau_alpha))
         thr = 2.0 * torch.log(torch.clamp(opacity, min=1e-300) / st.tau_alpha)
         thr = torch.where(valid, thr, torch.zeros_like(thr))
         ext = torch.sqrt(torch.clamp(thr[:, None] * torch.stack(
             [cov2d_dil[:, 0, 0], cov2d_dil[:, 1, 1]], -1), min=0.0))
+        # float32 error model: the decisions of a culled Gaussian's guards,
+        # and (mca=True) the per-Gaussian deviations the fragments' bands need
+        lam = E.LAMBDA
+        kappa = (torch.abs(cov2d[:, 0, 0] * cov2d[:, 1, 1]) + cov2d[:, 0, 1] ** 2) / torch.abs(det2d)
+        near_cull = ((torch.abs(qn - st.quat_min) <= 1e-3 * st.quat_min)
+                     | (torch.abs(z - float(cam.near)) <= 1e-3 * float(cam.near))
+                     | (torch.abs(det2d - st.det_min) <= 1e3 * E.U32 * kappa * torch.abs(det2d))
+                     | (torch.abs(opacity - st.tau_alpha) <= 1e-3 * st.tau_alpha))
+        cull_border = torch.zeros_like(valid)
+        idx = torch.nonzero(near_cull | ~torch.isfinite(kappa)).flatten()
+        idx = idx[torch.isfinite(det2d[idx])]
+        if len(idx):
+            d = _mca(p, idx, cam, st)
+            cull_border[idx] = ((torch.abs(qn[idx] - st.quat_min) <= lam * E.band_sigma(d["qn"]))
+                                | (torch.abs(z[idx] - float(cam.near)) <= lam * E.band_sigma(d["z"]))
+                                | (torch.abs(det2d[idx] - st.det_min) <= lam * E.band_sigma(d["det2d"]))
+                                | (torch.abs(opacity[idx] - st.tau_alpha)
+                                   <= lam * E.band_sigma(d["opacity_rel"]) * opacity[idx]))
+        # colour clip at 0: a dot product of up to 16 basis terms, each a few roundings
+        terms = Y[:, :, None] * coeffs
+        col_sigma = E.U32 * torch.sqrt((4.0 * terms * terms).sum(dim=1) + colour * colour)
+        clip_border = (torch.abs(colour) <= lam * col_sigma).any(dim=-1)
+        dev = _mca(p, torch.arange(n), cam, st) if mca else None
     return {
         "mean2d": mean2d, "cov2d": cov2d, "cov2d_dil": cov2d_dil, "conic": conic,
         "opacity": opacity, "rgb": rgb, "colour": colour, "cam_pos": mh, "det2d": det2d,
-        "valid": valid, "cull_border": cull_border, "thr": thr, "extent": ext,
+        "valid": valid, "cull_border": cull_border, "clip_border": clip_border, "thr": thr, "extent": ext,
+        "dev": dev,
     }
+
+
+def _mca(p: Dict[str, torch.Tensor], idx: torch.Tensor, cam, st: Settings, chunk: int = 32768):
+    """fp32err.mca_deviations of rows idx (in chunks), detached from autograd."""
+    W3, t = _camera64(cam)
+    outs = []
+    for c0 in range(0, len(idx), chunk):
+        sel = idx[c0:c0 + chunk]
+        rows = {k: p[k].detach().index_select(0, sel) for k in ("means", "log_scales", "quats", "opacity_logits")}
+        outs.append(E.mca_deviations(rows, W3, t, float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy),
+                                     st.dilation))
+    if not outs:
+        return None
+    return {k: torch.cat([o[k] for o in outs], dim=1) for k in outs[0]}
 
 
 def composite64(px: torch.Tensor, py: torch.Tensor, mean2d: torch.Tensor,
                 conic: torch.Tensor, opacity: torch.Tensor, rgb: torch.Tensor,
-                bg: Sequence[float], st: Settings = DEFAULT_SETTINGS, block: int = 256):
+                bg: Sequence[float], st: Settings = DEFAULT_SETTINGS, block: int = 256,
+                dev: Optional[Dict[str, torch.Tensor]] = None, stats: Optional[Dict[str, torch.Tensor]] = None):
     """Front-to-back compositing of candidates (already in canonical order).
 
     px, py [P]: pixel sample points.  Candidates: mean2d [G,2], conic [G,3],
-    opacity [G], rgb [G,3].  Walks the candidates in blocks of ``block``,
-    carrying the transmittance, and stops once no pixel can blend further (the
-    rest would not be blended, so this changes nothing).
+    opacity [G], rgb [G,3]; dev: their float32 deviation samples
+    (``fp32err.mca_deviations``, [K, G] each), which set the borderline bands
+    (None: no bands).  Walks the candidates in blocks of ``block``, carrying
+    the transmittance, and stops once no pixel can blend further (the rest
+    would not be blended, so this changes nothing).
     Returns (C [P,3] differentiable, T_final [P], last [P] candidate index of
     the last blended fragment or -1, borderline [P] bool, blended count [P]).
+    A pixel is borderline when one of its decisions lies within LAMBDA standard
+    deviations of the float32 error of the compared quantity: the skip test of
+    a walked fragment, the 0.99 cap of a blended one (which switches its
+    gradient), or the stop test after a blended fragment.  stats (a dict, with
+    dev): receives ``sigma_T`` [P], the relative standard deviation of the
+    final transmittance under the float32 error model.
     """
     P = px.shape[0]
     G = mean2d.shape[0]
+    lam = E.LAMBDA
     T_run = torch.ones(P, dtype=F64)
     C = torch.zeros(P, 3, dtype=F64)
     last = torch.full((P,), -1, dtype=torch.long)
     border = torch.zeros(P, dtype=torch.bool)
     nblend = torch.zeros(P, dtype=torch.long)
+    # the transmittance's relative deviation per sample, and the variance of
+    # its independent rounding part, carried along the walk
+    K = dev["mean_x"].shape[0] if dev is not None else 0
+    dT_run = torch.zeros(K, P, dtype=F64)
+    vT_run = torch.zeros(P, dtype=F64)
     for s in range(0, G, block):
         if not bool((T_run.detach() >= st.t_min).any()):
             break
@@ -236,7 +288,8 @@ def composite64(px: torch.Tensor, py: torch.Tensor, mean2d: torch.Tensor,
         a, b, c = conic[s:e, 0], conic[s:e, 1], conic[s:e, 2]
         quad = a * dx * dx + 2.0 * b * dx * dy + c * dy * dy
         gauss = torch.exp(-0.5 * quad)
-        alpha = torch.clamp(opacity[None, s:e] * gauss, max=st.alpha_max)
+        og = opacity[None, s:e] * gauss
+        alpha = torch.clamp(og, max=st.alpha_max)
         use = (alpha >= st.tau_alpha).detach()
         a_eff = torch.where(use, alpha, torch.zeros_like(alpha))
         one_minus = 1.0 - a_eff
@@ -254,11 +307,34 @@ def composite64(px: torch.Tensor, py: torch.Tensor, mean2d: torch.Tensor,
             rev_first = torch.argmax(torch.flip(contrib, dims=[1]).to(torch.int8), dim=1)
             last = torch.where(has, s + (k - 1 - rev_first), last)
             nblend += contrib.sum(dim=1)
-            near_tau = torch.abs(alpha.detach() - st.tau_alpha) <= ALPHA_BAND * st.tau_alpha
+            if dev is None:
+                continue
+            ddx, ddy = dx.detach(), dy.detach()
+            ga, gb, gc = a.detach(), b.detach(), c.detach()
+            dsub = {key: v[:, s:e] for key, v in dev.items()}
+            d_ln = E.alpha_deviation(ddx, ddy, ga, gb, gc, dsub)            # [K, P, B]
+            v_bl = E.blend_rounding_var(ddx, ddy, ga, gb, gc)               # [P, B]
+            sig_a = torch.sqrt(torch.mean(d_ln * d_ln, dim=0) + v_bl)      # relative sigma of alpha (o G)
+            al = alpha.detach()
+            near_tau = torch.abs(al - st.tau_alpha) <= lam * sig_a * st.tau_alpha
             border |= (keep & near_tau).any(dim=1)
+            near_cap = torch.abs(og.detach() - st.alpha_max) <= lam * sig_a * st.alpha_max
+            border |= (contrib & near_cap).any(dim=1)
+            # T (1 - alpha) as T - alpha T: the factor deviates by
+            # -alpha / (1 - alpha) times alpha's relative deviation, plus two roundings
+            ae = torch.where(contrib, a_eff.detach(), torch.zeros_like(al))
+            ratio = ae / (1.0 - ae)
+            dT = dT_run[:, :, None] - torch.cumsum(ratio[None] * d_ln, dim=2)
+            vT = vT_run[:, None] + torch.cumsum(torch.where(
+                contrib, ratio * ratio * v_bl + 2.0 * E.U32 * E.U32 / 3.0, torch.zeros_like(al)), dim=1)
+            dT_run = dT[:, :, -1].clone()
+            vT_run = vT[:, -1].clone()
+            sig_T = torch.sqrt(torch.mean(dT * dT, dim=0) + vT)
             T_after = Tb.detach() * one_minus.detach()
-            near_t = torch.abs(T_after - st.t_min) <= T_BAND * st.t_min
+            near_t = torch.abs(T_after - st.t_min) <= lam * sig_T * st.t_min
             border |= (contrib & near_t).any(dim=1)
+    if stats is not None and dev is not None:
+        stats["sigma_T"] = torch.sqrt(torch.mean(dT_run * dT_run, dim=0) + vT_run)
     bg_t = torch.as_tensor(list(bg), dtype=F64)
     C = C + T_run[:, None] * bg_t[None, :]
     return C, T_run, last, border, nblend
@@ -274,7 +350,7 @@ def _canonical_order(scene: Dict[str, torch.Tensor], cam, idx: np.ndarray) -> np
 def render64(scene: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTINGS, *,
              dl_dimage: Optional[torch.Tensor] = None, crop: Optional[Tuple[int, int, int, int]] = None,
              cull: bool = True, block_px: int = 16, sh_degree: int = 3,
-             depth_block: int = 256) -> Dict[str, object]:
+             depth_block: int = 256, mask_borderline: bool = False) -> Dict[str, object]:
     """Render (and optionally differentiate) a scene in float64 on the CPU.
 
     scene: SoA float32 tensors (see ``synthetic``); cam: camera with
@@ -282,7 +358,14 @@ def render64(scene: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
     crop: (x0, y0, x1, y1) pixel box, default the whole image.
     dl_dimage: optional upstream gradient [3, h, w] over the crop; when given,
     gradients of sum(dl_dimage * C) w.r.t. the six raw tensors are returned in
-    the SoA layout of ``scene`` (float64).
+    the SoA layout of ``scene`` (float64).  mask_borderline: the upstream
+    gradient is taken as zero on borderline pixels (whose decisions a float32
+    evaluation may take either way); the gradient actually used is returned
+    as ``dl_used``.
+    cull: restrict each block's candidates to the Gaussians whose widened
+    opacity-aware rectangle reaches it (exact: outside it alpha < tau_alpha,
+    see the module docstring); False makes every Gaussian a candidate of every
+    pixel.
     """
     x0, y0, x1, y1 = crop if crop is not None else (0, 0, int(cam.width), int(cam.height))
     h, w = y1 - y0, x1 - x0
@@ -307,9 +390,10 @@ def render64(scene: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
     for k, v in rows.items():
         leaves[k] = v.clone().requires_grad_(want_grad)
     sub = {k: v.index_select(0, order_t) for k, v in leaves.items()}
-    pre = preprocess64(sub, cam, st, sh_degree)
+    pre = preprocess64(sub, cam, st, sh_degree, mca=True)
     m2d, con, opa, rgb = pre["mean2d"], pre["conic"], pre["opacity"], pre["rgb"]
     lv = [t.detach().clone().requires_grad_(want_grad) for t in (m2d, con, opa, rgb)]
+    devs = pre["dev"]
 
     image = torch.zeros(3, h, w, dtype=F64)
     tfin = torch.ones(h, w, dtype=F64)
@@ -338,6 +422,7 @@ def render64(scene: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
         myk = np.abs(ys - my) <= float(e2[1]) + 1.0
         border |= torch.as_tensor(myk[:, None] & mxk[None, :])
 
+    dl_used = dl_dimage.to(F64).clone() if want_grad else None
     import time as _time
     t_blend0 = _time.perf_counter()
     for by in range(y0, y1, block_px):
@@ -356,7 +441,8 @@ def render64(scene: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
             else:
                 cand = torch.arange(len(order))
             cm, cc, co, cr = (t.index_select(0, cand) for t in lv)
-            Cc, Tc, lc, bc, nc = composite64(px, py, cm, cc, co, cr, bgt, st, block=depth_block)
+            cd = {key: v.index_select(1, cand) for key, v in devs.items()} if devs is not None else None
+            Cc, Tc, lc, bc, nc = composite64(px, py, cm, cc, co, cr, bgt, st, block=depth_block, dev=cd)
             hh, ww = ey - by, ex - bx
             sl = (slice(by - y0, ey - y0), slice(bx - x0, ex - x0))
             image[:, sl[0], sl[1]] = Cc.detach().T.reshape(3, hh, ww)
@@ -366,9 +452,13 @@ def render64(scene: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
             last_id[sl] = gid.reshape(hh, ww)
             border[sl] |= bc.reshape(hh, ww)
             nblend[sl] = nc.reshape(hh, ww)
-            if want_grad and len(cand):
+            if want_grad:
                 g = dl_dimage[:, by - y0:ey - y0, bx - x0:ex - x0].to(F64).reshape(3, -1).T
-                (Cc * g).sum().backward()
+                if mask_borderline:
+                    g = g * (~border[sl]).reshape(-1, 1).to(F64)
+                    dl_used[:, sl[0], sl[1]] = g.T.reshape(3, hh, ww)
+                if len(cand):
+                    (Cc * g).sum().backward()
 
     t_blend = _time.perf_counter() - t_blend0
     out: Dict[str, object] = {
@@ -376,6 +466,9 @@ def render64(scene: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
         "image": image, "t_final": tfin, "last_id": last_id, "borderline": border,
         "n_blended": nblend, "order": order, "n_valid": int(len(order)),
         "n_cull_border": int(cb.numel()),
+        # Gaussians whose colour clip is borderline: the clip switches their
+        # SH (and view-direction) gradients, which elementwise comparisons skip
+        "clip_border": torch.as_tensor(order, dtype=torch.long)[pre["clip_border"]],
     }
     if want_grad:
         outs, grads = [], []
@@ -390,6 +483,7 @@ def render64(scene: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
             g = v.grad if v.grad is not None else torch.zeros_like(v)
             gsoa[k] = g.T.contiguous() if g.dim() == 2 else g
         out["grads"] = gsoa
+        out["dl_used"] = dl_used
         out["grads_2d"] = {"mean2d": lv[0].grad, "conic": lv[1].grad, "opacity": lv[2].grad,
                            "rgb": lv[3].grad, "order": order}
     return out

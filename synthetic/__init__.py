@@ -188,6 +188,21 @@ def timesteps(count: int):
     return [k / (count - 1) if count > 1 else 0.0 for k in range(count)]
 
 
+def make_adam_state(shapes: Dict[str, Tuple[int, ...]], scales: Dict[str, float],
+                    seed: int = 0) -> Tuple[Dict[str, torch.Tensor], Dict[str, torch.Tensor]]:
+    """Seeded Adam moments for a step that does not start from zero: per group
+    g, exp_avg ~ N(0, (scales[g] / 2)^2) and exp_avg_sq = scales[g]^2 (1/2 + U[0, 1]),
+    float32 tensors of shapes[g]."""
+    g = torch.Generator(device="cpu")
+    g.manual_seed(int(seed) + 5_000_003)
+    m, v = {}, {}
+    for k in sorted(shapes):
+        sh, sc = tuple(shapes[k]), float(scales[k])
+        m[k] = (torch.randn(sh, generator=g, dtype=torch.float64) * (0.5 * sc)).to(torch.float32)
+        v[k] = ((torch.rand(sh, generator=g, dtype=torch.float64) + 0.5) * sc * sc).to(torch.float32)
+    return m, v
+
+
 def batch_scene(n: int, seed: int = 0) -> Dict[str, torch.Tensor]:
     """The multi-view workload's scene: the usual draws with means recentred to
     x, y in [-1, 1], z in [-2, 2] around the origin the cameras look at."""
@@ -215,5 +230,5 @@ __all__ = [
     "Camera", "Workload", "WORKLOADS", "ADAM_LR", "PARAM_NAMES", "identity_camera",
     "look_at_camera", "make_scene", "workload_camera", "make_dl_dimage", "make_target",
     "uniform_sphere_cameras", "subset", "count", "bytes_per_gaussian", "scene_checksum", "make_motion",
-    "timesteps", "batch_scene",
+    "timesteps", "batch_scene", "make_adam_state",
 ]
