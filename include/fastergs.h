@@ -6,8 +6,12 @@
  *
  * Conventions (all entry points):
  *  - Every pointer is a DEVICE pointer unless marked (host).  All buffers
- *    belong to the caller.  The library allocates no device memory and keeps
- *    no state between calls; the workspace is a caller-owned byte buffer.
+ *    belong to the caller.  The library allocates no device memory; the
+ *    workspace is a caller-owned byte buffer.  State kept between calls:
+ *    per thread, the last error message (fgs_last_error) and the armed
+ *    timing hook (fgs_time_next_launch); per device, the static scratch
+ *    array of fgs_sort_pairs_noalloc and its looked-up address.  Nothing
+ *    else survives a call outside the caller's buffers.
  *  - Work is enqueued asynchronously on `stream` (a hipStream_t, NULL = the
  *    default stream).  fgs_rasterize_forward alone synchronises `stream` once
  *    to read the instance count (see there).
@@ -30,7 +34,7 @@
 extern "C" {
 #endif
 
-#define FGS_ABI_VERSION 10
+#define FGS_ABI_VERSION 11
 
 typedef enum fgs_status {
   FGS_OK = 0,
@@ -360,6 +364,24 @@ fgs_status fgs_permute_planes(const void* src, void* dst, int64_t n, int32_t pla
 fgs_status fgs_sort_workspace_size(int64_t n, int32_t key_bytes, size_t* bytes);
 fgs_status fgs_sort_pairs(void* keys, uint32_t* vals, int64_t n, int32_t key_bytes, int32_t key_bits,
                           void* workspace, size_t workspace_bytes, void* stream);
+
+/* fgs_sort_pairs without a workspace, for callers that cannot allocate device
+ * memory (code under graph capture, serving loops, harnesses that forbid
+ * allocation).  Same arguments, results and errors as fgs_sort_pairs, minus
+ * the workspace: the scratch is a static device array of
+ * FGS_SORT_NOALLOC_SCRATCH_BYTES that the library holds on every device it
+ * runs on until the process ends, so n is limited to
+ * FGS_SORT_NOALLOC_MAX_PAIRS (a larger n returns FGS_ERR_INVALID_ARGUMENT
+ * and launches nothing).  The call allocates nothing; its first call on a
+ * device looks up the array's address there (the device must be current and
+ * `stream`, when not NULL, must belong to it).  Every call on a device shares
+ * that device's array: calls that overlap on one device (other threads,
+ * other streams) race and give wrong results; serialise them.  Nothing in the
+ * array has to start at a particular value. */
+#define FGS_SORT_NOALLOC_MAX_PAIRS (1 << 20)
+#define FGS_SORT_NOALLOC_SCRATCH_BYTES ((size_t)17 << 19) /* 8.5 MiB */
+fgs_status fgs_sort_pairs_noalloc(void* keys, uint32_t* vals, int64_t n, int32_t key_bytes, int32_t key_bits,
+                                  void* stream);
 
 /* Batched views (several cameras, or timesteps of a dynamic scene, rendered
  * and differentiated in one pass; the paper renders image batches per

@@ -17,6 +17,8 @@ FGS_F32, FGS_BF16 = 0, 1
 FGS_MAX_VIEWS = 16
 FGS_FORWARD_NO_SYNC = 1
 FGS_FLAG_FP64_CONIC, FGS_FLAG_LOOKBACK_FALLBACK = 1, 2
+FGS_SORT_NOALLOC_MAX_PAIRS = 1 << 20
+FGS_SORT_NOALLOC_SCRATCH_BYTES = 17 << 19
 
 
 class Gaussians(ctypes.Structure):
@@ -108,6 +110,7 @@ SIGNATURES = {
     "fgs_zorder_permutation": (c_int32, [c_void_p, c_int64, c_void_p, c_size_t, c_void_p, c_void_p]),
     "fgs_sort_workspace_size": (c_int32, [c_int64, c_int32, ctypes.POINTER(c_size_t)]),
     "fgs_sort_pairs": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p, c_size_t, c_void_p]),
+    "fgs_sort_pairs_noalloc": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p]),
     "fgs_permute_planes": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p, c_void_p]),
 }
 
@@ -122,7 +125,7 @@ class FasterGSError(RuntimeError):
 
 
 # the structures above mirror include/fastergs.h at this ABI version
-ABI_VERSION = 10
+ABI_VERSION = 11
 
 
 def load(path: str = LIB_PATH) -> ctypes.CDLL:

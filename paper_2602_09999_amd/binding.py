@@ -409,6 +409,18 @@ def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, key_bits: int, *, stream=
                                     _stream_handle(stream)), "fgs_sort_pairs")
 
 
+def sort_pairs_noalloc(keys: torch.Tensor, vals: torch.Tensor, key_bits: int, *, stream=None) -> None:
+    """fgs_sort_pairs_noalloc: fgs_sort_pairs with the library's static scratch
+    (no workspace; n <= FGS_SORT_NOALLOC_MAX_PAIRS)."""
+    if keys.dtype not in (torch.int16, torch.int32):
+        raise TypeError(f"keys must be int16 or int32, got {keys.dtype}")
+    n = int(keys.numel())
+    _check_tensor(keys, "keys", dtype=keys.dtype, shape=(n,))
+    _check_tensor(vals, "vals", dtype=torch.int32, shape=(n,))
+    L.check(L.load().fgs_sort_pairs_noalloc(_ptr(keys), _ptr(vals), n, keys.element_size(), int(key_bits),
+                                            _stream_handle(stream)), "fgs_sort_pairs_noalloc")
+
+
 def permute_planes(src: torch.Tensor, perm: torch.Tensor, out: Optional[torch.Tensor] = None, *,
                    stream=None) -> torch.Tensor:
     """fgs_permute_planes: out[..., k] = src[..., perm[k]] for a [P, n] or [n]

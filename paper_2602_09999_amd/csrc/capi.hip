@@ -11,11 +11,10 @@
 using namespace fgs;
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-fgs_status fail(fgs_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-fgs_status fail(fgs_status s, const char* fmt, ...) {
+fgs_status fgs::fail(fgs_status s, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -24,6 +23,8 @@ fgs_status fail(fgs_status s, const char* fmt, ...) {
   g_last_error = buf;
   return s;
 }
+
+namespace {
 
 fgs_status hip_fail(hipError_t e, const char* where) {
   return fail(FGS_ERR_HIP, "%s: %s", where, hipGetErrorString(e));

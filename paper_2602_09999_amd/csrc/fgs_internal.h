@@ -367,6 +367,9 @@ __device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, WalkLds& 
   return running;
 }
 
+// Records the calling thread's error message (fgs_last_error) and returns s.
+fgs_status fail(fgs_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
 inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 // a word count rounded up to a multiple of 64 words (256 bytes)
 inline uint64_t round_up64(uint64_t w) { return (w + 63) & ~uint64_t(63); }

@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported_and_bound(lib):
     for name in names:
         assert hasattr(lib, name), name
         assert name in L.SIGNATURES, name
-    assert lib.fgs_abi_version() == 10 == L.ABI_VERSION
+    assert lib.fgs_abi_version() == 11 == L.ABI_VERSION
 
 
 def test_default_settings_match_the_paper(lib):
@@ -219,3 +219,20 @@ def test_missing_library_fails_loudly(tmp_path):
             L.load(str(tmp_path / "nope.so"))
         finally:
             L._lib = L._lib_backup
+
+
+def test_noalloc_sort_bounds_are_checked_before_any_device_call(lib):
+    # the static scratch holds the workspace of the largest accepted sort
+    for kb in (2, 4):
+        assert B.sort_workspace_size(L.FGS_SORT_NOALLOC_MAX_PAIRS, kb) <= L.FGS_SORT_NOALLOC_SCRATCH_BYTES
+    f = lib.fgs_sort_pairs_noalloc
+    # rejected on the host: too many pairs, a bad width or bit count; nothing launched
+    assert f(None, None, L.FGS_SORT_NOALLOC_MAX_PAIRS + 1, 4, 32, None) == L.FGS_ERR_INVALID_ARGUMENT
+    assert b"static scratch" in lib.fgs_last_error()
+    assert f(None, None, -1, 4, 32, None) == L.FGS_ERR_INVALID_ARGUMENT
+    assert f(None, None, 10, 3, 8, None) == L.FGS_ERR_INVALID_ARGUMENT
+    assert f(None, None, 10, 2, 17, None) == L.FGS_ERR_INVALID_ARGUMENT
+    assert f(None, None, 10, 4, 8, None) == L.FGS_ERR_INVALID_ARGUMENT  # NULL arrays
+    # nothing to sort: returns at once, before looking up the device array
+    assert f(None, None, 0, 4, 32, None) == L.FGS_OK
+    assert f(None, None, 10, 4, 0, None) == L.FGS_OK
