@@ -122,7 +122,8 @@ typedef struct fgs_camera {
 /* Thresholds (host struct).  Defaults from fgs_default_settings:
  *   tile 16 (16x16 pixel tiles, Sec. 3.1)
  *   alpha_min 1/255  (skip fragments below it, Sec. 3.2 "Splat Bounding")
- *   alpha_max 0.99   (alpha cap, App. B.1)
+ *   alpha_max 0.99   (alpha cap, App. B.1; must be below 1, since the backward
+ *                     divides by 1 - alpha)
  *   t_min 1e-4       (stop once the transmittance falls below it, App. B.1)
  *   dilation 0.3     (Sigma2D + 0.3 I, App. C.2)
  *   quat_min 1e-4, det_min 1e-6 (degenerate-Gaussian guard, App. B.1)

@@ -106,8 +106,10 @@ fgs_status check_settings(const fgs_settings* st) {
     return fail(FGS_ERR_INVALID_ARGUMENT, "tile must be 8, 16 or 32 (got %d)", st->tile);
   if (st->flags & ~(uint32_t)(FGS_FLAG_FP64_CONIC | FGS_FLAG_LOOKBACK_FALLBACK))
     return fail(FGS_ERR_INVALID_ARGUMENT, "unknown bits in settings.flags 0x%x", st->flags);
-  if (!(st->alpha_min > 0.0f && st->alpha_min < st->alpha_max && st->alpha_max <= 1.0f))
-    return fail(FGS_ERR_INVALID_ARGUMENT, "need 0 < alpha_min < alpha_max <= 1");
+  // alpha_max < 1: the backward divides by 1 - alpha (App. B.1's front-to-back
+  // gradient), which the cap keeps at least 1 - alpha_max away from zero
+  if (!(st->alpha_min > 0.0f && st->alpha_min < st->alpha_max && st->alpha_max < 1.0f))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "need 0 < alpha_min < alpha_max < 1");
   if (!(st->t_min > 0.0f && st->t_min < 1.0f)) return fail(FGS_ERR_INVALID_ARGUMENT, "need 0 < t_min < 1");
   if (!(st->dilation >= 0.0f && std::isfinite(st->dilation)))
     return fail(FGS_ERR_INVALID_ARGUMENT, "dilation must be finite and >= 0");

@@ -121,6 +121,10 @@ def test_invalid_arguments_are_rejected_without_launching(lib):
         assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(st1), 0, ctypes.byref(size)) == L.FGS_OK
     stb = B.default_settings(alpha_min=0.995)
     assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(stb), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
+    # no cap at 1: the backward divides by 1 - alpha
+    st_cap = B.default_settings(alpha_max=1.0)
+    assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(st_cap), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
+    assert b"alpha_max < 1" in lib.fgs_last_error()
 
     g = L.Gaussians()
     g.n = 5
