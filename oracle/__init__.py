@@ -27,7 +27,7 @@ finite differences, library special cases and brute force; see those tests.
 """
 from .render64 import (  # noqa: F401
     Settings, DEFAULT_SETTINGS, sh_basis64, quat_to_rotation64, preprocess64,
-    composite64, render64, l1_loss_grad64, camera_center64,
+    composite64, rect_candidates64, render64, l1_loss_grad64, camera_center64,
 )
 from .adam64 import adam64  # noqa: F401
 from .keys32 import keys_ref, keys_ref_banded, depth_key32, tile_lists_for, record32, tile_rect  # noqa: F401

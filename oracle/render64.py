@@ -34,7 +34,10 @@ Per pixel, every candidate Gaussian is composited in the canonical order
 scenes candidates may be restricted, per block of pixels, to Gaussians whose
 FP64 opacity-aware rectangle (Sec. 3.2), widened by one pixel, reaches the
 block: outside that rectangle alpha < tau_alpha holds exactly, so the result
-is unchanged (pinned by a test that compares culled and unculled output).
+is unchanged (pinned by a test that compares culled and unculled output, and
+by a certificate, over the whole 10k-Gaussian frame and the 3M-Gaussian
+crops, that every dropped Gaussian stays below tau_alpha in the dropped
+block: an eigenvalue bound, else brute force over the block's pixels).
 """
 from __future__ import annotations
 
@@ -347,6 +350,16 @@ def _canonical_order(scene: Dict[str, torch.Tensor], cam, idx: np.ndarray) -> np
     return idx[np.lexsort((idx, keys))]
 
 
+def rect_candidates64(mean2d: torch.Tensor, extent: torch.Tensor, box: Tuple[int, int, int, int]) -> torch.Tensor:
+    """Mask of the Gaussians whose opacity-aware rectangle (Sec. 3.2, "Splat
+    Bounding"; half-extents ``extent``), widened by one pixel, reaches the
+    pixel centres of box = (x0, y0, x1, y1), a half-open pixel range.  The
+    others have alpha < tau_alpha at every pixel of the box."""
+    x0, y0, x1, y1 = box
+    return ((mean2d[:, 0] + extent[:, 0] + 1.0 >= x0 + 0.5) & (mean2d[:, 0] - extent[:, 0] - 1.0 <= x1 - 0.5)
+            & (mean2d[:, 1] + extent[:, 1] + 1.0 >= y0 + 0.5) & (mean2d[:, 1] - extent[:, 1] - 1.0 <= y1 - 0.5))
+
+
 def render64(scene: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTINGS, *,
              dl_dimage: Optional[torch.Tensor] = None, crop: Optional[Tuple[int, int, int, int]] = None,
              cull: bool = True, block_px: int = 16, sh_degree: int = 3,
@@ -379,10 +392,7 @@ def render64(scene: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
     order = _canonical_order(scene, cam, valid_idx) if len(valid_idx) else valid_idx
     if cull and len(order):
         # Gaussians whose widened FP64 rectangle misses the crop have alpha < tau there.
-        m_all = pre_all["mean2d"][order]
-        e_all = pre_all["extent"][order]
-        near = ((m_all[:, 0] + e_all[:, 0] + 1.0 >= x0 + 0.5) & (m_all[:, 0] - e_all[:, 0] - 1.0 <= x1 - 0.5)
-                & (m_all[:, 1] + e_all[:, 1] + 1.0 >= y0 + 0.5) & (m_all[:, 1] - e_all[:, 1] - 1.0 <= y1 - 0.5))
+        near = rect_candidates64(pre_all["mean2d"][order], pre_all["extent"][order], (x0, y0, x1, y1))
         order = order[near.numpy()]
     order_t = torch.as_tensor(order, dtype=torch.long)
 
@@ -433,11 +443,7 @@ def render64(scene: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
             px = xs.flatten() + 0.5
             py = ys.flatten() + 0.5
             if cull and len(order):
-                lo_x, hi_x = bx + 0.5, ex - 0.5
-                lo_y, hi_y = by + 0.5, ey - 0.5
-                sel = ((m2d_d[:, 0] + ext[:, 0] + 1.0 >= lo_x) & (m2d_d[:, 0] - ext[:, 0] - 1.0 <= hi_x)
-                       & (m2d_d[:, 1] + ext[:, 1] + 1.0 >= lo_y) & (m2d_d[:, 1] - ext[:, 1] - 1.0 <= hi_y))
-                cand = torch.nonzero(sel).flatten()
+                cand = torch.nonzero(rect_candidates64(m2d_d, ext, (bx, by, ex, ey))).flatten()
             else:
                 cand = torch.arange(len(order))
             cm, cc, co, cr = (t.index_select(0, cand) for t in lv)
@@ -498,4 +504,4 @@ def l1_loss_grad64(image: torch.Tensor, target: torch.Tensor) -> Tuple[float, to
 
 
 __all__ = ["Settings", "DEFAULT_SETTINGS", "sh_basis64", "quat_to_rotation64", "preprocess64",
-           "composite64", "render64", "l1_loss_grad64", "camera_center64"]
+           "composite64", "rect_candidates64", "render64", "l1_loss_grad64", "camera_center64"]

@@ -458,6 +458,65 @@ def test_candidate_culling_does_not_change_the_result():
         assert (a["grads"][k] - b["grads"][k]).abs().max() <= 1e-11 * max(1.0, float(b["grads"][k].abs().max()))
 
 
+def _certify_dropped(pre, keep, box, tau):
+    """Every valid Gaussian outside ``keep`` stays below tau_alpha at every
+    pixel centre of box = (x0, y0, x1, y1): proved for most of them by the
+    smallest eigenvalue of the conic and the distance from the mean to the
+    box (alpha <= o exp(-lambda_min dist^2 / 2)), and by brute force over the
+    box's pixel centres for the rest.  Returns (dropped, brute-forced)."""
+    x0, y0, x1, y1 = box
+    idx = torch.nonzero(pre["valid"] & ~keep).flatten()
+    m = pre["mean2d"][idx].detach()
+    a, b, c = (pre["conic"][idx, k].detach() for k in range(3))
+    o = pre["opacity"][idx].detach()
+    lam_min = 0.5 * (a + c) - torch.sqrt((0.5 * (a - c)) ** 2 + b * b)
+    assert bool((lam_min > 0).all())
+    dx = torch.clamp(torch.maximum(x0 + 0.5 - m[:, 0], m[:, 0] - (x1 - 0.5)), min=0.0)
+    dy = torch.clamp(torch.maximum(y0 + 0.5 - m[:, 1], m[:, 1] - (y1 - 0.5)), min=0.0)
+    bound = o * torch.exp(-0.5 * lam_min * (dx * dx + dy * dy))
+    rest = torch.nonzero(bound >= tau).flatten()
+    if len(rest):
+        ys, xs = torch.meshgrid(torch.arange(y0, y1, dtype=F64) + 0.5, torch.arange(x0, x1, dtype=F64) + 0.5,
+                                indexing="ij")
+        ddx = xs.flatten()[None, :] - m[rest, 0:1]
+        ddy = ys.flatten()[None, :] - m[rest, 1:2]
+        q = a[rest, None] * ddx * ddx + 2.0 * b[rest, None] * ddx * ddy + c[rest, None] * ddy * ddy
+        alpha = o[rest, None] * torch.exp(-0.5 * q)
+        assert float(alpha.max()) < tau, "a dropped candidate reaches tau_alpha"
+    return len(idx), len(rest)
+
+
+def _check_block_culling(scene, cam, box, block=16):
+    """The two-level candidate culling of render64 (the box, then each block
+    of it) drops only Gaussians that never reach tau_alpha there."""
+    rows = {k: (v.to(F64).T.contiguous() if v.dim() == 2 else v.to(F64)) for k, v in scene.items()}
+    with torch.no_grad():
+        pre = O.preprocess64(rows, cam, sh_degree=0)  # colour plays no part in the selection
+    tau = O.DEFAULT_SETTINGS.tau_alpha
+    x0, y0, x1, y1 = box
+    keep_box = O.rect_candidates64(pre["mean2d"], pre["extent"], box)
+    _certify_dropped(pre, keep_box, box, tau)
+    dropped = 0
+    for by in range(y0, y1, block):
+        for bx in range(x0, x1, block):
+            blk = (bx, by, min(bx + block, x1), min(by + block, y1))
+            keep = keep_box & O.rect_candidates64(pre["mean2d"], pre["extent"], blk)
+            dropped += _certify_dropped(pre, keep, blk, tau)[0]
+    assert dropped > 0
+
+
+def test_candidate_culling_is_exact_on_the_small_workload_frame():
+    """Candidate culling over the whole 10k-Gaussian 256x256 frame, block by block."""
+    _check_block_culling(S.make_scene(10_000, seed=0), S.workload_camera("c1"), (0, 0, 256, 256))
+
+
+@pytest.mark.parametrize("box", [(768, 498, 832, 562), (1336, 996, 1400, 1060), (0, 0, 64, 64)],
+                         ids=["centre", "edge", "corner"])
+def test_candidate_culling_is_exact_on_the_3m_crops(box):
+    """Candidate culling at the 64x64 crops of the 3M-Gaussian 1600x1060 frame."""
+    _check_block_culling(S.make_scene(3_000_000, seed=0), S.workload_camera("c3"), box)
+
+
 def test_degenerate_gaussians_are_not_rendered():
     """App. B.1: |q| < 1e-4 or det(Sigma2D) < 1e-6 -> not rendered; also behind the near plane."""
     cam = S.identity_camera(32, 32, 40.0)
