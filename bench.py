@@ -52,7 +52,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-view batched step")
     ap.add_argument("--no-dynamic", action="store_true", help="skip the dynamic (4D) step")
-    ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    ap.add_argument("--dist-steps", type=int, default=200,
+                    help="steps timed one by one (events around each) for the median and p10/p90")
+    ap.add_argument("--split-reps", type=int, default=3,
+                    help="steps per stage timed with the library's launch hook (per-kernel split)")
+    ap.add_argument("--extra-workloads", default="c2",
+                    help="comma-separated further workloads timed with the headline variant")
+    ap.add_argument("--no-oracle-error", action="store_true",
+                    help="skip the FP64-oracle error statement of the crops (part of the CPU baseline leg)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured with rocprofv3 counters (optional)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -97,19 +104,72 @@ def measured_traffic(path: str, kernel: str, workload: str):
         return None
 
 
-def cpu_baseline(workload: str, seed: int, budget_s: float):
-    """FP64 oracle on a bounded sample of the workload, extrapolated to one step."""
+# 64x64 windows of the full-size workloads where the FP64 oracle is run: the
+# image centre and the bottom edge (at 1600x1060 a partial tile row: 1060 =
+# 66 * 16 + 4).  The corner [0, 64)^2 of these scenes holds no Gaussian (the
+# projected means start about 200 pixels in), so it would time nothing.
+CROPS = {"c2": {"centre": (608, 328, 672, 392), "edge": (1076, 656, 1140, 720)},
+         "c3": {"centre": (768, 498, 832, 562), "edge": (1336, 996, 1400, 1060)}}
+SH_NAMES = ("sh_dc", "sh_rest")
+
+
+def bf16_rounded(scene):
+    """The scene with its SH coefficients rounded to bfloat16 (kept float32):
+    the precision form's inputs as the oracle consumes them."""
+    out = dict(scene)
+    for k in SH_NAMES:
+        out[k] = scene[k].bfloat16().float()
+    return out
+
+
+def crop_upstream(crop, seed):
+    x0, y0, x1, y1 = crop
+    return S.make_dl_dimage(y1 - y0, x1 - x0, seed=seed)
+
+
+# wave64 VALU instructions the chip can issue per second: 256 CUs x 4 SIMDs,
+# one FP32 wave instruction per 4 cycles (16 lanes per cycle), 2.4 GHz
+VALU_WAVE_INSTS_PER_S = 256 * 4 / 4 * 2.4e9
+
+
+def measured_counters(path: str, kernel: str, workload: str):
+    """Instruction and atomic counts per launch from the committed counter
+    summary, or None when missing or taken on other kernel sources."""
+    if not os.path.exists(path):
+        return None
+    try:
+        ent = json.load(open(path))["kernels"][kernel][workload]
+        if source_digest(ent["source"]) != ent["source_sha256_16"]:
+            return None
+        return {k: float(ent[k]) for k in ("valu_insts_per_launch", "atomics_per_launch") if k in ent}
+    except (KeyError, ValueError, OSError, TypeError):
+        return None
+
+
+def cpu_baseline(workload: str, seed: int, scene, with_bf16: bool):
+    """The FP64 oracle on the host cores, timed on a bounded sample of the
+    workload and extrapolated to one step: forward + backward of the 64x64
+    centre and edge crops (compositing seconds per pixel, scaled to the
+    frame), the preprocess forward + backward on a subset of the Gaussians,
+    Adam on a slice of the parameters.  The crop renders (also of the
+    bfloat16-rounded scene when with_bf16) are returned for the error
+    statement of the GPU results."""
     import oracle as O
     w = S.WORKLOADS[workload]
     threads = torch.get_num_threads()
     t_all = time.perf_counter()
-    scene = S.make_scene(w.n, seed=seed)
     cam = S.workload_camera(workload)
-    cx, cy = w.width // 2, w.height // 2
-    crop = (cx - 16, cy - 16, cx + 16, cy + 16)
-    dl = S.make_dl_dimage(32, 32, seed=1)
-    r = O.render64(scene, cam, crop=crop, dl_dimage=dl)
-    t_crop = r["seconds_compositing"]            # per-pixel compositing fwd+bwd of the crop only
+    refs, t_comp, px, t_crops = {}, 0.0, 0, 0.0
+    for where, crop in CROPS[workload].items():
+        for sh in (("f32", "bf16") if with_bf16 else ("f32",)):
+            sc = scene if sh == "f32" else bf16_rounded(scene)
+            t0 = time.perf_counter()
+            r = O.render64(sc, cam, crop=crop, dl_dimage=crop_upstream(crop, 7), mask_borderline=True)
+            if sh == "f32":
+                t_crops += time.perf_counter() - t0
+                t_comp += r["seconds_compositing"]
+                px += (crop[2] - crop[0]) * (crop[3] - crop[1])
+            refs[(where, sh)] = {k: r[k] for k in ("image", "t_final", "borderline", "dl_used", "grads")}
     # per-Gaussian preprocess + its backward on a subset
     m = min(w.n, 200_000)
     sub = S.subset(scene, slice(0, m))
@@ -127,17 +187,111 @@ def cpu_baseline(workload: str, seed: int, budget_s: float):
     t0 = time.perf_counter()
     O.adam64(p, p, torch.zeros_like(p), torch.zeros_like(p), 1, 1e-3)
     t_adam = (time.perf_counter() - t0) * (w.n * PARAMS_PER_GAUSSIAN / k)
-    px = (crop[2] - crop[0]) * (crop[3] - crop[1])
-    # the crop time is dominated by compositing; scale its pixel work to the frame
-    t_blend = t_crop * (w.width * w.height / px)
+    frame = w.width * w.height
+    t_blend = t_comp / px * frame   # per-pixel compositing (forward + backward) scaled to the frame
     sec = t_blend + t_pre + t_adam
-    log(f"cpu baseline: crop {t_crop:.1f}s (x{w.width * w.height / px:.0f} pixels), preprocess "
+    log(f"cpu baseline ({threads} threads, os.cpu_count() {os.cpu_count()}): crops {t_crops:.1f}s "
+        f"(compositing {t_comp:.2f}s for {px} pixels), per-frame compositing {t_blend:.1f}s, preprocess "
         f"{t_pre:.1f}s, adam {t_adam:.1f}s (extrapolated), sample wall {time.perf_counter() - t_all:.1f}s")
-    return {"value": 1.0 / sec, "unit": "steps/s", "cores": threads, "kind": "oracle",
-            "sample": (f"FP64 oracle: 32x32 central crop fwd+bwd (pixels scaled to {w.width}x{w.height}), "
-                       f"preprocess fwd+bwd on {m} of {w.n} Gaussians, Adam on {k} of "
-                       f"{w.n * PARAMS_PER_GAUSSIAN} parameters; extrapolated to one step"),
-            "seconds_per_step_extrapolated": sec}
+    base = {"value": 1.0 / sec, "unit": "steps/s", "cores": threads, "os_cpu_count": os.cpu_count(),
+            "kind": "oracle",
+            "sample": (f"FP64 oracle: forward + backward of the 64x64 centre and edge crops "
+                       f"({', '.join(str(c) for c in CROPS[workload].values())}), compositing time per pixel "
+                       f"scaled to {w.width}x{w.height}; preprocess forward + backward on {m} of {w.n} "
+                       f"Gaussians; Adam on {k} of {w.n * PARAMS_PER_GAUSSIAN} parameters; extrapolated to one "
+                       f"step (label: extrapolated)"),
+            "seconds_per_step_extrapolated": sec, "seconds_per_pixel_compositing": t_comp / px,
+            "crop_seconds_total": t_crops}
+    return base, refs
+
+
+def err_stats(got: torch.Tensor, ref: torch.Tensor, mask=None):
+    """max abs, max relative (|d| / max(|ref|, rms(ref))) and RMS of got - ref."""
+    d = (got.double() - ref.double()).abs()
+    r = ref.double().abs()
+    if mask is not None:
+        d, r = d[..., mask], r[..., mask]
+    if d.numel() == 0:
+        return {"max_abs": 0.0, "max_rel": 0.0, "rms": 0.0}
+    rms_ref = float(torch.sqrt((r ** 2).mean()))
+    rel = d / torch.clamp(r, min=max(rms_ref, 1e-300))
+    return {"max_abs": float(d.max()), "max_rel": float(rel.max()), "rms": float(torch.sqrt((d ** 2).mean()))}
+
+
+def unpermute(t: torch.Tensor, perm: torch.Tensor) -> torch.Tensor:
+    """Gaussian axis (last) back from z-order: out[..., perm[i]] = t[..., i]."""
+    out = torch.empty_like(t)
+    out[..., perm.long()] = t
+    return out
+
+
+def oracle_errors(refs, scene, workload: str, dev, with_bf16: bool):
+    """The error of each result of the benchmark's step against the FP64
+    oracle on the crops, for float32 and bfloat16 SH: the parameters in
+    z-order, the forward without host synchronisation, then (a) the
+    gradients of the separate backward and (b) the parameters after the
+    backward fused with Adam (seeded moments, step 3, against adam64 of the
+    oracle gradients).  Pixels with a borderline decision are left out of
+    the image statistics (their count is given); the relative error divides
+    by max(|reference|, its RMS)."""
+    import oracle as O
+    import paper_2602_09999_amd as P
+    from paper_2602_09999_amd import binding as B
+    cam = S.workload_camera(workload)
+    out = {}
+    for sh in (("f32", "bf16") if with_bf16 else ("f32",)):
+        shd = torch.float32 if sh == "f32" else torch.bfloat16
+        params = {k: v.to(dev) for k, v in scene.items()}
+        for k in SH_NAMES:
+            params[k] = params[k].to(shd).contiguous()
+        perm = B.apply_zorder(params)
+        rz = B.Rasterizer(cam, device=dev)
+        rz.forward(params)
+        image, t_final, last = rz.forward(params, sync=False)
+        torch.cuda.synchronize()
+        res = {}
+        for where, crop in CROPS[workload].items():
+            ref = refs[(where, sh)]
+            x0, y0, x1, y1 = crop
+            ok = ~ref["borderline"]
+            e = {"borderline_pixels_excluded": int((~ok).sum()), "pixels": int(ok.numel())}
+            e["image"] = err_stats(image[:, y0:y1, x0:x1].cpu(), ref["image"], ok)
+            e["t_final"] = err_stats(t_final[y0:y1, x0:x1].cpu(), ref["t_final"], ok)
+            dl = torch.zeros(3, cam.height, cam.width, device=dev)
+            dl[:, y0:y1, x0:x1] = ref["dl_used"].float().to(dev)
+            grads = rz.backward(params, image, last, dl)
+            e["gradients"] = {k: err_stats(unpermute(grads[k].float(), perm).cpu(), ref["grads"][k])
+                              for k in B.PARAM_NAMES}
+            scales = {}
+            for k, g in ref["grads"].items():
+                live = g[g != 0]
+                scales[k] = float(torch.sqrt((live ** 2).mean())) if live.numel() else 1e-6
+            m0, v0 = S.make_adam_state({k: tuple(v.shape) for k, v in scene.items()}, scales, seed=3)
+            pc = {k: v.clone() for k, v in params.items()}
+            opt = P.FusedAdam(pc, S.ADAM_LR)
+            inv = torch.argsort(perm.long().cpu())
+            for k in pc:  # the moments in z-order, like the parameters
+                opt.exp_avg[k].copy_(m0[k][..., perm.long().cpu()].to(dev))
+                opt.exp_avg_sq[k].copy_(v0[k][..., perm.long().cpu()].to(dev))
+            opt.t = 2
+            rz.backward_adam(pc, image, last, dl, opt)
+            torch.cuda.synchronize()
+            upd = {}
+            for k in B.PARAM_NAMES:
+                p0 = params[k].float().cpu()[..., inv]
+                p_ref, _, _ = O.adam64(p0, ref["grads"][k], m0[k], v0[k], 3, S.ADAM_LR[k])
+                p_gpu = pc[k].float().cpu()[..., inv]
+                upd[k] = err_stats(p_gpu - p0, p_ref - p0.double())  # the update of every parameter
+            e["fused_adam_update"] = upd
+            res[where] = e
+            log(f"oracle error {sh} {where}: image max abs {e['image']['max_abs']:.2e} "
+                f"({e['borderline_pixels_excluded']} borderline px), worst gradient max rel "
+                f"{max(v['max_rel'] for v in e['gradients'].values()):.2e}, worst update max rel "
+                f"{max(v['max_rel'] for v in upd.values()):.2e}")
+        out[sh] = res
+        del params, rz
+        torch.cuda.empty_cache()
+    return out
 
 
 # name: (backward fused with Adam, SH element type, z-ordered layout, forward
@@ -207,9 +361,9 @@ def run_variant(name, args, scene, cam, target, dev, w):
     grads = None if fused else {k: torch.empty_like(v) for k, v in params.items()}
     step_name, kernel = TIMED[fused]
 
-    def step(ev=None, kev=None, sync=True):
+    def step(ev=None, kev=None, sync=True, hook=None):
         if kev is not None:
-            B.time_next_launch(step_name, kev[0], kev[1])
+            B.time_next_launch(hook or step_name, kev[0], kev[1])
         if ev is not None:
             ev[0].record(stream)
         rz.forward(params, image, t_final, last, sync=sync)
@@ -249,12 +403,42 @@ def run_variant(name, args, scene, cam, target, dev, w):
     ph = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(4)] for k in range(args.steps)]).mean(0)
     kms = float(np.mean([kevs[k][0].elapsed_time(kevs[k][1]) for k in range(args.steps)]))
     ms_step = 1000.0 * elapsed / args.steps
+    # distribution: steps timed one by one with events on the launch stream
+    dist = None
+    if args.dist_steps > 0:
+        dev_ = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.dist_steps)]
+        for k in range(args.dist_steps):
+            step(dev_[k], sync=host_sync)
+        torch.cuda.synchronize()
+        per = np.array([dev_[k][0].elapsed_time(dev_[k][4]) for k in range(args.dist_steps)])
+        dist = {"steps": args.dist_steps, "median": float(np.median(per)), "p10": float(np.percentile(per, 10)),
+                "p90": float(np.percentile(per, 90)), "mean": float(per.mean()),
+                "steps_per_s_at_median": 1000.0 / float(np.median(per))}
+    # per-stage split: the library records events around one stage's launches
+    split = {}
+    stages = ["preprocess", "duplicate", "tile_sort", "blend_forward", "blend_backward"]
+    stages += ["touched_gradients", "adam_sparse"] if fused else ["preprocess_backward", "adam"]
+    sev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.split_reps)]
+    for pair in sev:
+        for e in pair:
+            e.record(stream)
+    for st_name in stages if args.split_reps > 0 else ():
+        for k in range(args.split_reps):
+            step(kev=sev[k], sync=host_sync, hook=st_name)
+        torch.cuda.synchronize()
+        split[st_name] = float(np.mean([sev[k][0].elapsed_time(sev[k][1]) for k in range(args.split_reps)]))
+    if rz.overflowed():
+        raise SystemExit(f"{name}: a step exceeded the instance capacity {rz.capacity}")
     names = ("forward", "l1", "backward+adam", "-") if fused else ("forward", "l1", "backward", "adam")
     phases = {names[j]: float(ph[j]) for j in range(4) if names[j] != "-"}
     log(f"{name}: ms/step {ms_step:.3f}; " + " ".join(f"{k} {v:.3f}" for k, v in phases.items()) +
-        f"; {kernel} {kms:.3f} ms")
+        f"; {kernel} {kms:.3f} ms" + (f"; {dist['steps']} steps median {dist['median']:.3f} p10 {dist['p10']:.3f} "
+                                      f"p90 {dist['p90']:.3f} ms" if dist else ""))
+    if split:
+        log(f"{name}: stage split (ms) " + " ".join(f"{k} {v:.3f}" for k, v in split.items()))
     return {"steps": args.steps, "elapsed": elapsed, "ms_per_step": ms_step, "steps_per_s": args.steps / elapsed,
             "phase_ms": phases, "kernel": kernel, "kernel_ms": kms, "rz": rz, "params": params, "last": last,
+            "step_ms": dist, "stage_ms": split,
             "fused": fused, "sh_bf16": shd == torch.bfloat16, "zorder": zorder, "zorder_ms": zorder_ms,
             "host_sync": host_sync}
 
@@ -272,6 +456,27 @@ def batched_step_fn(br, params, opt, target, dl, grads, mode):
         br.backward(params, dl, grads)
         opt.step(grads)
     return step
+
+
+def adam_roofline(step, params, sh_bf16_names=()):
+    """Duration of the separate Adam kernel inside one more eager step
+    (library launch hook) against its algorithmic bytes: read p, g, m, v and
+    write p, m, v of every parameter (bfloat16 p and g where stored so)."""
+    from paper_2602_09999_amd import binding as B
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for x in e:
+        x.record()
+    B.time_next_launch("adam", e[0], e[1])
+    step()
+    torch.cuda.synchronize()
+    ms = e[0].elapsed_time(e[1])
+    nbytes = 0
+    for k, v in params.items():
+        w = v.element_size()
+        nbytes += v.numel() * (3 * w + 16)  # p, g, p' at the parameter's width; m, v, m', v' float32
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": "k_adam", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes": nbytes, "avg_launch_ms": ms}
 
 
 def time_steps(step, steps, warmup):
@@ -329,6 +534,8 @@ def run_batched(args, dev):
                 raise RuntimeError("instance capacity exceeded during graph replay")
         else:
             sec = time_steps(step, max(3, args.steps // 5), 1)
+        if not graph:
+            out["roofline"] = adam_roofline(step, params)
         out[f"{mode_name}_ms_per_step"] = sec * 1e3
         out[f"{mode_name}_steps_per_s"] = 1.0 / sec
         out[f"{mode_name}_views_per_s"] = BATCH_VIEWS / sec
@@ -362,10 +569,12 @@ def run_dynamic(args, dev):
     grads = {k: torch.empty_like(v) for k, v in params.items()}
     step = batched_step_fn(br, params, opt, target, dl, grads, 0)
     sec = time_steps(step, max(3, args.steps // 5), 2)
-    log(f"dynamic: {sec * 1e3:.2f} ms per step of {DYN_STEPS} timesteps")
+    roof = adam_roofline(step, params)
+    log(f"dynamic: {sec * 1e3:.2f} ms per step of {DYN_STEPS} timesteps; k_adam {roof['avg_launch_ms']:.3f} ms "
+        f"({roof['frac']:.2f} of HBM peak)")
     return {"workload": f"{DYN_N} dynamic Gaussians, {DYN_STEPS} timesteps, 1280x720, bf16 SH",
             "ms_per_step": sec * 1e3, "steps_per_s": 1.0 / sec, "timesteps_per_s": DYN_STEPS / sec,
-            "instances": br.last_stats["n_instances"]}
+            "instances": br.last_stats["n_instances"], "roofline": roof}
 
 
 def workload_counts(r, w, dev):
@@ -440,6 +649,41 @@ def main():
     k_gbs = kbytes / (hr["kernel_ms"] * 1e-3) / 1e9
     bwd_gbs = bwd_bytes / (bwd_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.traffic_json, hr["kernel"], args.workload)
+    # the backward rasterizer alone (blend backward + preprocess backward, no
+    # Adam): the separate backward phase of an unfused variant
+    bwd_r = None
+    unf = next((v for v in results if not results[v]["fused"]), None)
+    if unf is not None:
+        ru = results[unf]
+        b_blend = bwd_blend
+        b_pre = algorithmic_bytes(n, counts["n_touched"], counts["i_proc"], pixels)["pre_bwd"]
+        if ru["sh_bf16"]:
+            b_pre -= n * 48 * 2  # bfloat16 SH gradients: 2 instead of 4 bytes
+        ms_b = ru["phase_ms"]["backward"]
+        bwd_r = {"variant": unf, "algorithmic_bytes": b_blend + b_pre, "ms": ms_b,
+                 "achieved": (b_blend + b_pre) / (ms_b * 1e-3) / 1e9, "unit": "GB/s",
+                 "frac": (b_blend + b_pre) / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                 "covers": "accumulator clear + k_blend_bwd + k_preprocess_bwd (the separate backward call)",
+                 "kernels": {}}
+        for st_name, kb in (("blend_backward", b_blend), ("preprocess_backward", b_pre)):
+            t = ru["stage_ms"].get(st_name)
+            if t:
+                bwd_r["kernels"][st_name] = {"ms": t, "algorithmic_bytes": kb, "GB_per_s": kb / (t * 1e-3) / 1e9,
+                                             "hbm_frac": kb / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        # the blend backward is bound by instruction issue and atomics, not HBM
+        cnt = measured_counters(args.traffic_json, "k_blend_bwd<16>", args.workload)
+        t = ru["stage_ms"].get("blend_backward")
+        if cnt and t and "blend_backward" in bwd_r["kernels"]:
+            kk = bwd_r["kernels"]["blend_backward"]
+            if cnt.get("valu_insts_per_launch"):
+                peak = VALU_WAVE_INSTS_PER_S
+                kk["valu"] = {"insts_per_launch": cnt["valu_insts_per_launch"],
+                              "achieved_insts_per_s": cnt["valu_insts_per_launch"] / (t * 1e-3),
+                              "peak_insts_per_s": peak,
+                              "frac": cnt["valu_insts_per_launch"] / (t * 1e-3) / peak}
+            if cnt.get("atomics_per_launch"):
+                kk["atomics"] = {"per_launch": cnt["atomics_per_launch"],
+                                 "per_s": cnt["atomics_per_launch"] / (t * 1e-3)}
     variants = {}
     for v, r in results.items():
         kb = fused_bytes(n, counts["n_touched"], r["sh_bf16"])["adam"] if r["fused"] else adam_bytes(n, r["sh_bf16"])
@@ -448,7 +692,8 @@ def main():
                        "zorder_layout": r["zorder"], "forward_host_sync": r["host_sync"],
                        "timed_kernel": {"name": r["kernel"], "avg_launch_ms": r["kernel_ms"],
                                         "algorithmic_bytes": kb,
-                                        "GB_per_s": kb / (r["kernel_ms"] * 1e-3) / 1e9}}
+                                        "GB_per_s": kb / (r["kernel_ms"] * 1e-3) / 1e9},
+                       "step_ms": r["step_ms"], "stage_ms": r["stage_ms"]}
     out = {
         "metric": "train steps/s (fwd+bwd+Adam) at 3M Gaussians 1600x1060; bwd HBM GB/s",
         "value": hr["steps_per_s"],
@@ -474,13 +719,39 @@ def main():
                     "algorithmic_bytes": bwd_bytes, "ms": bwd_ms,
                     "covers": "blend backward + " + ("preprocess backward fused with Adam (both kernels)"
                                                      if hr["fused"] else "preprocess backward")},
+        "step_ms": hr["step_ms"],
+        "bwd_rasterizer": bwd_r,
         "phase_ms": hr["phase_ms"],
+        "stage_ms": hr["stage_ms"],
         "zorder": None if hr["zorder_ms"] is None else {
             "layout_ms": hr["zorder_ms"], "every_iterations": ZORDER_EVERY,
             "amortized_ms_per_step": hr["zorder_ms"] / ZORDER_EVERY,
             "covers": "Morton permutation of the means + gather of all parameters and both Adam moments"},
         "variants": variants,
     }
+    extra = {}
+    for wl in [x for x in args.extra_workloads.split(",") if x and x != args.workload]:
+        if wl not in S.WORKLOADS:
+            raise SystemExit(f"unknown workload {wl}")
+        we = S.WORKLOADS[wl]
+        sc_e = S.make_scene(we.n, seed=args.seed)
+        tg_e = S.make_target(we.height, we.width, seed=args.seed).to(dev)
+        re = run_variant(head, argparse.Namespace(**dict(vars(args), split_reps=0)), sc_e,
+                         S.workload_camera(wl), tg_e, dev, we)
+        ce = workload_counts(re, we, dev)
+        kb = (fused_bytes(we.n, ce["n_touched"], re["sh_bf16"])["adam"] if re["fused"]
+              else adam_bytes(we.n, re["sh_bf16"]))
+        extra[wl] = {"workload": we.description, "variant": head, "steps_per_s": re["steps_per_s"],
+                     "ms_per_step": re["ms_per_step"], "step_ms": re["step_ms"], "phase_ms": re["phase_ms"],
+                     "visible": ce["visible"], "instances": ce["instances"], "instances_walked": ce["i_proc"],
+                     "roofline": {"bound": "hbm", "kernel": re["kernel"],
+                                  "achieved": kb / (re["kernel_ms"] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                                  "unit": "GB/s", "frac": kb / (re["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                  "algorithmic_bytes": kb, "avg_launch_ms": re["kernel_ms"]}}
+        del sc_e, tg_e, re
+        torch.cuda.empty_cache()
+    if extra:
+        out["other_workloads"] = extra
     if not args.no_batched:
         out["batched"] = run_batched(args, dev)
         torch.cuda.empty_cache()
@@ -488,7 +759,16 @@ def main():
         out["dynamic"] = run_dynamic(args, dev)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.seed, args.cpu_budget_s)
+        with_bf16 = any(results[v]["sh_bf16"] for v in results)
+        out["cpu_baseline"], refs = cpu_baseline(args.workload, args.seed, scene, with_bf16)
+        if not args.no_oracle_error:
+            # the GPU results on the crops the oracle just rendered
+            out["oracle_error"] = {
+                "covers": (f"64x64 crops {CROPS[args.workload]} of the {args.workload} frame; per SH form: "
+                           "image and T (borderline pixels excluded), the gradients of the separate backward, "
+                           "and the parameter update of the backward fused with Adam; z-ordered layout, "
+                           "forward without host synchronisation (the timed configuration)"),
+                "results": oracle_errors(refs, scene, args.workload, dev, with_bf16)}
     print(json.dumps(out))
 
 

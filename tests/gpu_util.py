@@ -20,10 +20,14 @@ def say(*a):
 # Comparison protocol against the FP64 oracle.
 IMG_TOL = 1e-5        # image and final transmittance, absolute, off borderline pixels
 GRAD_TOL = 1e-3       # gradients: per-group relative L2 and the elementwise bound below
-# Borderline pixels (a decision within the float32 error band of oracle/fp32err.py)
-# may make up at most this fraction of a comparison's pixels: the bands measured
-# 0.03 % at the small workload and 0.2-0.25 % at the 64x64 crops of the 3M one.
-EXEMPT_FRAC = 0.003
+# Borderline pixels (a decision within the float32 error band of oracle/fp32err.py,
+# 6 standard deviations of the modelled float32 error) may make up at most this
+# fraction of a comparison's pixels.  The fraction grows with the fragments whose
+# alpha ring or stop crosses a pixel centre inside a band: measured 0.03 % at the
+# small workload, 0.2-0.25 % at the 64x64 crops of the 3M one and up to 0.41 % at
+# the bottom-edge window of the dynamic workload (few, large, far off-axis
+# Gaussians).  The cap bounds a band model gone wide; it is not the tolerance.
+EXEMPT_FRAC = 0.005
 
 
 def exempt_cap(npix: int) -> int:
@@ -41,8 +45,10 @@ def check_image(label: str, image, ref, t_final=None, last_ids_gpu=None) -> np.n
     dm = d.max(0)
     n_ex = int((~ok).sum())
     rel = (d / np.maximum(np.abs(r), 1e-3)).max(0)
-    say(f"  {label}: exempt {n_ex} of {ok.size} (cap {exempt_cap(ok.size)}); image max abs "
-        f"{dm[ok].max():.2e} max rel {rel[ok].max():.2e} rms {np.sqrt((d[:, ok] ** 2).mean()):.2e}")
+    flips = int((dm[~ok] > IMG_TOL).sum())  # exempt pixels where a decision did go the other way
+    say(f"  {label}: exempt {n_ex} of {ok.size} (cap {exempt_cap(ok.size)}; {flips} of them off by more than "
+        f"{IMG_TOL:g}); image max abs {dm[ok].max():.2e} max rel {rel[ok].max():.2e} "
+        f"rms {np.sqrt((d[:, ok] ** 2).mean()):.2e}")
     assert n_ex <= exempt_cap(ok.size), (label, n_ex)
     assert dm[ok].max() <= IMG_TOL, (label, float(dm[ok].max()))
     if t_final is not None:
