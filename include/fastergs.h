@@ -233,7 +233,9 @@ const char* fgs_last_error(void);
 fgs_status fgs_default_settings(fgs_settings* out);
 
 /* Workspace size in bytes (host *bytes) for n Gaussians, one camera, and
- * room for `instance_capacity` (tile, Gaussian) instances. */
+ * room for `instance_capacity` (tile, Gaussian) instances.  n (times the
+ * views of a batch) and instance_capacity must stay below 2^30 (the limit of
+ * the device sorts); larger values give FGS_ERR_INVALID_ARGUMENT. */
 fgs_status fgs_workspace_size(int64_t n, const fgs_camera* cam, const fgs_settings* st,
                               int64_t instance_capacity, size_t* bytes);
 
@@ -340,7 +342,8 @@ fgs_status fgs_l1_loss_backward(const float* image, const float* target, int64_t
  * the means with side the largest per-axis extent; 10 bits per axis,
  * q = min(1023, floor((x - min) * (1024 / side))) in float32; codes interleave
  * the bits with x in bit 0; ties keep the index order (stable).
- * fgs_zorder_workspace_size: device scratch bytes for n Gaussians (host *bytes).
+ * fgs_zorder_workspace_size: device scratch bytes for n Gaussians (host *bytes);
+ *   n < 2^30.
  * fgs_zorder_permutation: perm[k] (device uint32[n]) = index of the Gaussian at
  *   position k; means float32 [3][n] (finite); workspace 256-byte aligned. */
 fgs_status fgs_zorder_workspace_size(int64_t n, size_t* bytes);
@@ -358,7 +361,8 @@ fgs_status fgs_permute_planes(const void* src, void* dst, int64_t n, int32_t pla
  * [0, key_bits), and pairs with equal such bits keep their input order; bits
  * at and above key_bits are carried along unsorted.  keys: device array of
  * n keys of key_bytes (2 or 4) bytes; vals: device uint32[n]; both sorted in
- * place.  key_bits: 0..8*key_bytes (0 leaves the arrays as they are).
+ * place; n < 2^30.  key_bits: 0..8*key_bytes (0 leaves the arrays as they
+ * are).
  * workspace: device, 256-byte aligned, at least fgs_sort_workspace_size bytes
  * (host *bytes); its contents are scratch.  Errors: FGS_ERR_INVALID_ARGUMENT
  * for a bad size, width, pointer or workspace; nothing is launched then. */

@@ -138,13 +138,14 @@ fgs_status check_gaussians(const fgs_gaussians* g) {
 fgs_status make_layout(int64_t n, const fgs_camera* cams, int32_t n_views, const fgs_settings* st, int64_t cap,
                        fgs_layout* L) {
   if (n < 0 || n > INT32_MAX) return fail(FGS_ERR_INVALID_ARGUMENT, "n = %lld out of range", (long long)n);
-  if (cap < 0 || cap > (int64_t)UINT32_MAX - 1)
-    return fail(FGS_ERR_INVALID_ARGUMENT, "instance_capacity = %lld out of range", (long long)cap);
+  // the device sorts take fewer than 2^30 pairs (32-bit byte offsets)
+  if (cap < 0 || cap >= kMaxSortPairs)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "instance_capacity = %lld not below 2^30", (long long)cap);
   if (n_views < 1 || n_views > kMaxViews)
     return fail(FGS_ERR_INVALID_ARGUMENT, "n_views = %d not in 1..%d", n_views, kMaxViews);
   if (!cams) return fail(FGS_ERR_INVALID_ARGUMENT, "cameras are NULL");
-  if ((int64_t)n * n_views > INT32_MAX)
-    return fail(FGS_ERR_INVALID_ARGUMENT, "n * n_views = %lld exceeds 2^31 - 1", (long long)n * n_views);
+  if ((int64_t)n * n_views >= kMaxSortPairs)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "n * n_views = %lld not below 2^30", (long long)n * n_views);
   fgs_status s = check_settings(st);
   if (s != FGS_OK) return s;
   const int t = st->tile;
@@ -424,19 +425,19 @@ fgs_status fgs_rasterize_forward_batch(const fgs_gaussians* g, const fgs_camera*
     FGS_HIP(launch_compact_visible(n_tiles, depth_key, n, (uint32_t)n_views, reinterpret_cast<uint4*>(scratch),
                                    vis_keys[0], vis_ids[0], dup_scan, dup_scan_words(vn), hs),
             "compact");
-    // without the host's key range, passes whose digit no visible key varies in only copy
+    // with the device's key range, trailing passes whose digit every visible key shares are
+    // skipped, and the buffer holding the sorted ids is noted in counters[kStatDepthBuf]
+    // (0, set by the statistics, when no pass runs)
     FGS_HIP(radix_sort_pairs(vis_keys, vis_ids, nvis, no_sync ? d_vis : nullptr, 0, depth_bits, scratch, &vis_final,
-                             hs, no_sync ? counters + kStatKeyMin : nullptr, false),
+                             hs, counters + kStatKeyMin, false, counters + kStatDepthBuf),
             "depth sort");
   }
 
-  // (the same launch notes which depth buffer holds the sorted visible ids)
-  FGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, (uint64_t)tiles * 2, hs,
-                          nvis > 0 ? counters + kStatDepthBuf : nullptr, (uint32_t)vis_final),
-          "ranges clear");
+  FGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, (uint64_t)tiles * 2, hs), "ranges clear");
   if (inst > 0 && nvis > 0) {
+    const uint32_t* depth_ids[2] = {vis_ids[0], vis_ids[1]};
     FGS_TIMED("duplicate", hs,
-              launch_duplicate(vis_ids[vis_final], d_vis, nvis, dup_scan, dup_scan,
+              launch_duplicate(depth_ids, counters + kStatDepthBuf, d_vis, nvis, dup_scan, dup_scan,
                                (st->flags & FGS_FLAG_LOOKBACK_FALLBACK) != 0, rec, vs, n, st->tile, cap,
                                ikeys[0], key_bytes, ivals[0], hs),
               "duplicate");
@@ -647,14 +648,14 @@ static fgs_status adam_impl(const fgs_adam_group* groups, int32_t n_groups, int6
 
 fgs_status fgs_zorder_workspace_size(int64_t n, size_t* bytes) {
   if (!bytes) return fail(FGS_ERR_INVALID_ARGUMENT, "bytes is NULL");
-  if (n < 0 || n > INT32_MAX) return fail(FGS_ERR_INVALID_ARGUMENT, "n = %lld out of range", (long long)n);
+  if (n < 0 || n >= kMaxSortPairs) return fail(FGS_ERR_INVALID_ARGUMENT, "n = %lld not in 0..2^30-1", (long long)n);
   *bytes = zorder_scratch_bytes((uint64_t)n);
   return FGS_OK;
 }
 
 fgs_status fgs_zorder_permutation(const float* means, int64_t n, void* workspace, size_t workspace_bytes,
                                   uint32_t* perm, void* stream) {
-  if (n < 0 || n > INT32_MAX) return fail(FGS_ERR_INVALID_ARGUMENT, "n = %lld out of range", (long long)n);
+  if (n < 0 || n >= kMaxSortPairs) return fail(FGS_ERR_INVALID_ARGUMENT, "n = %lld not in 0..2^30-1", (long long)n);
   if (n == 0) return FGS_OK;
   if (!means || !workspace || !perm) return fail(FGS_ERR_INVALID_ARGUMENT, "NULL pointer");
   const size_t need = zorder_scratch_bytes((uint64_t)n);
@@ -686,7 +687,7 @@ static size_t sort_workspace_bytes(uint64_t n, int key_bytes) {
 
 fgs_status fgs_sort_workspace_size(int64_t n, int32_t key_bytes, size_t* bytes) {
   if (!bytes) return fail(FGS_ERR_INVALID_ARGUMENT, "bytes is NULL");
-  if (n < 0 || n > INT32_MAX) return fail(FGS_ERR_INVALID_ARGUMENT, "n = %lld out of range", (long long)n);
+  if (n < 0 || n >= kMaxSortPairs) return fail(FGS_ERR_INVALID_ARGUMENT, "n = %lld not in 0..2^30-1", (long long)n);
   if (key_bytes != 2 && key_bytes != 4) return fail(FGS_ERR_INVALID_ARGUMENT, "key_bytes must be 2 or 4");
   *bytes = sort_workspace_bytes((uint64_t)n, key_bytes);
   return FGS_OK;
@@ -694,7 +695,7 @@ fgs_status fgs_sort_workspace_size(int64_t n, int32_t key_bytes, size_t* bytes) 
 
 fgs_status fgs_sort_pairs(void* keys, uint32_t* vals, int64_t n, int32_t key_bytes, int32_t key_bits,
                           void* workspace, size_t workspace_bytes, void* stream) {
-  if (n < 0 || n > INT32_MAX) return fail(FGS_ERR_INVALID_ARGUMENT, "n = %lld out of range", (long long)n);
+  if (n < 0 || n >= kMaxSortPairs) return fail(FGS_ERR_INVALID_ARGUMENT, "n = %lld not in 0..2^30-1", (long long)n);
   if (key_bytes != 2 && key_bytes != 4) return fail(FGS_ERR_INVALID_ARGUMENT, "key_bytes must be 2 or 4");
   if (key_bits < 0 || key_bits > 8 * key_bytes)
     return fail(FGS_ERR_INVALID_ARGUMENT, "key_bits %d not in 0..%d", key_bits, 8 * key_bytes);

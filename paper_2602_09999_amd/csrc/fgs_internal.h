@@ -21,6 +21,7 @@ constexpr int kScanItems = FGS_SORT32_ITEMS;
 #ifndef FGS_SORT16_ITEMS
 #define FGS_SORT16_ITEMS 16
 #endif
+constexpr int64_t kMaxSortPairs = int64_t(1) << 30;  // a device sort takes fewer pairs
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kNumXcd = 8;           // MI355X: 8 XCDs, workgroups dealt round-robin
@@ -391,14 +392,17 @@ hipError_t scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* d_t
 
 size_t radix_scratch_words(uint64_t n);
 // Stable LSD radix sort of (key, value) pairs on bits [begin_bit, end_bit).
-// Items: n (host) or *d_count (device, <= n) when d_count != NULL.  Data
-// starts in keys[0]/vals[0]; returns (in *final_buf) the buffer holding the
-// result.  d_range (device, optional): {min, max} of the keys, so that passes
-// whose digit is the same in every key only copy.  keep_keys = false: the
-// last pass writes the values only (the sorted keys are not needed).
+// Items: n (host, < 2^30) or *d_count (device, <= n) when d_count != NULL.
+// Data starts in keys[0]/vals[0]; returns (in *final_buf) the buffer holding
+// the result.  d_range (device, optional): {min, max} of the keys; the
+// trailing passes whose digit is the same in every key are then skipped, and
+// the buffer holding the result is written to the device word final_word
+// (required then; *final_buf is -1).  keep_keys = false: the last pass writes
+// the values only (the sorted keys are not needed).
 hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
                             int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s,
-                            const uint32_t* d_range = nullptr, bool keep_keys = true);
+                            const uint32_t* d_range = nullptr, bool keep_keys = true,
+                            uint32_t* final_word = nullptr);
 // The same for 16-bit keys (begin_bit < end_bit <= 16).
 hipError_t radix_sort_pairs16(uint16_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
                               int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s);
@@ -453,10 +457,12 @@ hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth
 // wait runs out sums the earlier counts itself and adds 1 to *slow;
 // no_wait: every workgroup after the first takes that path, for tests).
 size_t dup_scan_words(uint64_t n);
-hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uint32_t n, uint32_t* dup_scan,
-                            uint32_t* slow, bool no_wait, const float4* rec, const ViewSet& vs,
-                            uint32_t n_gauss, int tile,
-                            uint32_t cap, void* keys, int key_bytes, uint32_t* vals, hipStream_t s);
+// The depth-sorted entries are vis_ids[*which_ids] (vis_ids[0] when
+// which_ids is NULL).
+hipError_t launch_duplicate(const uint32_t* const vis_ids[2], const uint32_t* which_ids, const uint32_t* d_nvis,
+                            uint32_t n, uint32_t* dup_scan, uint32_t* slow, bool no_wait, const float4* rec,
+                            const ViewSet& vs, uint32_t n_gauss, int tile, uint32_t cap, void* keys, int key_bytes,
+                            uint32_t* vals, hipStream_t s);
 // Ranges of the first min(*d_count, n) (or n) sorted keys.
 hipError_t launch_tile_ranges(const void* keys, int key_bytes, uint32_t n, const uint32_t* d_count, uint32_t tiles,
                               uint2* ranges, hipStream_t s);

@@ -499,7 +499,9 @@ __device__ __forceinline__ uint64_t dup_lookback(uint64_t* status, uint32_t blk,
 }
 
 template <typename KT>
-__global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict__ vis_ids,
+__global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict__ vis_ids0,
+                                                      const uint32_t* __restrict__ vis_ids1,
+                                                      const uint32_t* __restrict__ which_ids,
                                                       const uint32_t* __restrict__ d_nvis, uint32_t n,
                                                       uint32_t* __restrict__ dup_scan, uint32_t* __restrict__ slow,
                                                       uint32_t spin_limit,
@@ -513,6 +515,8 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
   const uint32_t blk = blockIdx.x;
   const uint32_t nv = min(*d_nvis, n);
   if (blk * kBlock >= nv) return;  // uniform; no later workgroup has entries either
+  // the depth sort leaves its result in either buffer (noted on the device)
+  const uint32_t* __restrict__ vis_ids = (which_ids != nullptr && *which_ids != 0u) ? vis_ids1 : vis_ids0;
   uint64_t* status = reinterpret_cast<uint64_t*>(dup_scan + kDupStatusWord);
   const uint32_t p = blk * kBlock + threadIdx.x;
   CandLane me = {};
@@ -592,18 +596,21 @@ __global__ __launch_bounds__(kBlock) void k_duplicate(const uint32_t* __restrict
   }
 }
 
-hipError_t launch_duplicate(const uint32_t* vis_ids, const uint32_t* d_nvis, uint32_t n, uint32_t* dup_scan,
-                            uint32_t* slow, bool no_wait, const float4* rec, const ViewSet& vs, uint32_t n_gauss,
-                            int tile, uint32_t cap, void* keys, int key_bytes, uint32_t* vals, hipStream_t s) {
+hipError_t launch_duplicate(const uint32_t* const vis_ids[2], const uint32_t* which_ids, const uint32_t* d_nvis,
+                            uint32_t n, uint32_t* dup_scan, uint32_t* slow, bool no_wait, const float4* rec,
+                            const ViewSet& vs, uint32_t n_gauss, int tile, uint32_t cap, void* keys, int key_bytes,
+                            uint32_t* vals, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const uint32_t spin_limit = no_wait ? 0u : kDupSpinLimit;
   const uint32_t grid = ceil_div(n, kBlock);
   if (key_bytes == 2)
-    k_duplicate<uint16_t><<<grid, kBlock, 0, s>>>(vis_ids, d_nvis, n, dup_scan, slow, spin_limit, rec, vs, n_gauss,
-                                                  tile, cap, static_cast<uint16_t*>(keys), vals);
+    k_duplicate<uint16_t><<<grid, kBlock, 0, s>>>(vis_ids[0], vis_ids[1], which_ids, d_nvis, n, dup_scan, slow,
+                                                  spin_limit, rec, vs, n_gauss, tile, cap,
+                                                  static_cast<uint16_t*>(keys), vals);
   else
-    k_duplicate<uint32_t><<<grid, kBlock, 0, s>>>(vis_ids, d_nvis, n, dup_scan, slow, spin_limit, rec, vs, n_gauss,
-                                                  tile, cap, static_cast<uint32_t*>(keys), vals);
+    k_duplicate<uint32_t><<<grid, kBlock, 0, s>>>(vis_ids[0], vis_ids[1], which_ids, d_nvis, n, dup_scan, slow,
+                                                  spin_limit, rec, vs, n_gauss, tile, cap,
+                                                  static_cast<uint32_t*>(keys), vals);
   return hipGetLastError();
 }
 

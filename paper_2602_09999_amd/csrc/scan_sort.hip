@@ -147,6 +147,9 @@ __device__ __forceinline__ bool pass_is_constant(const uint32_t* __restrict__ d_
   return d_range != nullptr && ((d_range[0] ^ d_range[1]) >> shift) == 0u;
 }
 
+// fourth word of a raw buffer descriptor on gfx9-family GPUs (32-bit data format)
+constexpr int kBufferWord3 = 0x00020000;
+
 template <typename KT>
 struct alignas(16) KeyVec {  // one 16-byte load of consecutive keys
   static constexpr int V = 16 / (int)sizeof(KT);
@@ -157,12 +160,16 @@ template <int RB, typename KT, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_radix_hist(const KT* __restrict__ keys, uint32_t n,
                                                        const uint32_t* __restrict__ d_count, int shift,
                                                        const uint32_t* __restrict__ d_range,
-                                                       uint32_t* __restrict__ hist, uint32_t nb) {
+                                                       uint32_t* __restrict__ hist, uint32_t nb,
+                                                       uint32_t* __restrict__ final_word, uint32_t final_if_run) {
   constexpr int R = 1 << RB;
   constexpr int kWaves = kBlock / kWave;
   constexpr int V = KeyVec<KT>::V;
   static_assert(ITEMS % V == 0, "whole 16-byte loads per thread");
   if (pass_is_constant(d_range, shift)) return;
+  // a pass that runs notes the buffer its scatter writes: the last one to run
+  // leaves the buffer holding the result
+  if (final_word != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *final_word = final_if_run;
   // kSplit histograms per wave (lane l adds to histogram l mod kSplit), so
   // that fewer lanes of one instruction add to the same counter.  With few
   // digits the collisions cost most and the extra counters least (measured at
@@ -235,7 +242,6 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT* __restrict__
   constexpr uint32_t kTile = kBlock * ITEMS;
   __shared__ uint32_t wcnt[kWaves][R];
   __shared__ uint32_t gdelta[R];  // global start of the digit minus its block-local start (mod 2^32)
-  __shared__ uint32_t lstart[R];  // block-local start of each digit
   __shared__ KT s_key[kTile];
   __shared__ uint32_t s_val[kTile];
   __shared__ uint32_t scan_lds[kBlock / kWave];
@@ -243,13 +249,11 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT* __restrict__
   const uint32_t base = blockIdx.x * kTile;
   if (base >= count) return;  // uniform for the whole workgroup
   const uint32_t in_block = min(kTile, count - base);
-  if (pass_is_constant(d_range, shift)) {  // uniform: the pass keeps the order
-    for (uint32_t i = base + threadIdx.x; i < base + in_block; i += kBlock) {
-      if (keys_out) keys_out[i] = keys_in[i];
-      vals_out[i] = vals_in[i];
-    }
-    return;
-  }
+  // uniform: the pass keeps the order.  Constant passes come last (a digit
+  // is constant when it and every higher bit agree in the smallest and the
+  // largest key), so they are skipped and the result stays where the last
+  // pass that ran put it (noted on the device by that pass's histogram).
+  if (pass_is_constant(d_range, shift)) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const bool digit_thread = threadIdx.x < R;
@@ -258,13 +262,22 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT* __restrict__
   // The block's loads go out first, so that their latency overlaps the digit
   // starts' loads and the barrier below.
   const uint32_t wbase = base + wave * (kWave * ITEMS);
+  const bool full = in_block == kTile;  // uniform: no bounds tests in the block
   uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
+  if (full) {
 #pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
-    const uint32_t i = wbase + k * kWave + lane;
-    const bool valid = i < count;
-    key[k] = valid ? (uint32_t)keys_in[i] : 0u;
-    val[k] = valid ? vals_in[i] : 0u;
+    for (int k = 0; k < ITEMS; ++k) {
+      key[k] = (uint32_t)keys_in[wbase + k * kWave + lane];
+      val[k] = vals_in[wbase + k * kWave + lane];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t i = wbase + k * kWave + lane;
+      const bool valid = i < count;
+      key[k] = valid ? (uint32_t)keys_in[i] : 0u;
+      val[k] = valid ? vals_in[i] : 0u;
+    }
   }
   if (digit_thread) {
 #pragma unroll
@@ -284,20 +297,24 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT* __restrict__
   lds_volatile_u32* my_cnt = lds_volatile(wcnt[wave]);
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
-    const bool valid = wbase + k * kWave + lane < count;
+    const bool valid = full || wbase + k * kWave + lane < count;
     const uint32_t d = (key[k] >> shift) & (R - 1);
-    // lanes holding the same digit: the AND over the digit's bits of the
-    // ballot of that bit or of its complement, as two 32-bit halves
-    const uint64_t v = __ballot(valid);
-    uint32_t plo = (uint32_t)v, phi = (uint32_t)(v >> 32);
+    // lanes holding the same digit: the valid lanes minus those whose digit
+    // differs in some bit, as two 32-bit halves
+    const uint64_t v = full ? ~0ull : __ballot(valid);
+    // lanes whose digit differs from this lane's in some bit
+    uint32_t dlo = 0u, dhi = 0u;
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
-      // the bit as 0 or all ones (sign-extended one-bit field)
-      const uint32_t x = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
-      const uint64_t m = __ballot(x != 0u);
-      plo &= ~((uint32_t)m ^ x);
-      phi &= ~((uint32_t)(m >> 32) ^ x);
+      // the bit as 0 or all ones (sign-extended one-bit field); the lanes
+      // whose bit b differs are the ballot XOR that mask, OR-ed into the
+      // accumulator with one three-input bit operation per half
+      const int x = __builtin_amdgcn_sbfe((int)d, b, 1);
+      const uint64_t m = __ballot(x);
+      dlo = __builtin_amdgcn_bitop3_b32(dlo, (uint32_t)m, (uint32_t)x, 0xF6);          // dlo | (m ^ x)
+      dhi = __builtin_amdgcn_bitop3_b32(dhi, (uint32_t)(m >> 32), (uint32_t)x, 0xF6);  // dhi | (m ^ x)
     }
+    const uint32_t plo = (uint32_t)v & ~dlo, phi = (uint32_t)(v >> 32) & ~dhi;
     // peers in lanes below this one, and in all
     const uint32_t below = __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));
     uint32_t before = 0;
@@ -320,31 +337,42 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT* __restrict__
     uint32_t tot;
     const uint32_t ls = block_exclusive_scan(run, scan_lds, &tot);
     if (digit_thread) {
-      lstart[threadIdx.x] = ls;
       gdelta[threadIdx.x] = gbase - ls;
+      // wcnt[w][t] becomes the block-local slot of wave w's first key of digit t
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) wcnt[w][threadIdx.x] += ls;
     }
   }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
-    const uint32_t i = wbase + k * kWave + lane;
-    if (i < count) {
+    if (full || wbase + k * kWave + lane < count) {
       const uint32_t d = (key[k] >> shift) & (R - 1);
-      const uint32_t lp = lstart[d] + wcnt[wave][d] + rank[k];
+      const uint32_t lp = wcnt[wave][d] + rank[k];
       s_key[lp] = (KT)key[k];
       s_val[lp] = val[k];
     }
   }
   __syncthreads();
+  // scattered stores through buffer descriptors: a 32-bit byte offset per
+  // store instead of a 64-bit address (a sort takes fewer than 2^30 pairs, so
+  // every byte offset of 4-byte values fits)
+  const __amdgpu_buffer_rsrc_t kout = __builtin_amdgcn_make_buffer_rsrc(keys_out, 0, -1, kBufferWord3);
+  const __amdgpu_buffer_rsrc_t vout = __builtin_amdgcn_make_buffer_rsrc(vals_out, 0, -1, kBufferWord3);
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     const uint32_t j = k * kBlock + threadIdx.x;
-    if (j < in_block) {
+    if (full || j < in_block) {
       const uint32_t kk = s_key[j];
       const uint32_t d = (kk >> shift) & (R - 1);
-      const uint32_t pos = gdelta[d] + j;  // = gbase[d] + (j - lstart[d])
-      if (keys_out) keys_out[pos] = (KT)kk;
-      vals_out[pos] = s_val[j];
+      const uint32_t pos = gdelta[d] + j;  // = gbase[d] + (j - block-local start of d)
+      if (keys_out) {
+        if (sizeof(KT) == 2)
+          __builtin_amdgcn_raw_buffer_store_b16((uint16_t)kk, kout, (int)(pos * 2u), 0, 0);
+        else
+          __builtin_amdgcn_raw_buffer_store_b32(kk, kout, (int)(pos * 4u), 0, 0);
+      }
+      __builtin_amdgcn_raw_buffer_store_b32(s_val[j], vout, (int)(pos * 4u), 0, 0);
     }
   }
 }
@@ -380,9 +408,11 @@ size_t radix_scratch_words(uint64_t n) {
 template <int RB, typename KT>
 static hipError_t radix_pass(const KT* keys_in, const uint32_t* vals_in, KT* keys_out, uint32_t* vals_out,
                              uint32_t n, const uint32_t* d_count, const uint32_t* d_range, int shift,
-                             uint32_t* hist, uint32_t* totals, uint32_t* scan_scratch, uint32_t nb, hipStream_t s) {
+                             uint32_t* hist, uint32_t* totals, uint32_t* scan_scratch, uint32_t nb,
+                             uint32_t* final_word, uint32_t final_if_run, hipStream_t s) {
   constexpr int kItems = SortShape<KT>::kItems;
-  k_radix_hist<RB, KT, kItems><<<nb, kBlock, 0, s>>>(keys_in, n, d_count, shift, d_range, hist, nb);
+  k_radix_hist<RB, KT, kItems><<<nb, kBlock, 0, s>>>(keys_in, n, d_count, shift, d_range, hist, nb, final_word,
+                                                     final_if_run);
   const uint32_t* digit_totals = totals;
   if (nb > kColscanMaxBlocks) {
     const hipError_t e = scan_u32(hist, hist, (uint32_t)(nb << RB), nullptr, scan_scratch, s);
@@ -399,7 +429,7 @@ static hipError_t radix_pass(const KT* keys_in, const uint32_t* vals_in, KT* key
 template <typename KT>
 static hipError_t radix_sort_impl(KT* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
                                   const uint32_t* d_range, int begin_bit, int end_bit, bool keep_keys,
-                                  uint32_t* scratch, int* final_buf, hipStream_t s) {
+                                  uint32_t* scratch, int* final_buf, uint32_t* final_word, hipStream_t s) {
   int cur = 0;
   if (n == 0 || end_bit <= begin_bit) {
     *final_buf = 0;
@@ -421,36 +451,46 @@ static hipError_t radix_sort_impl(KT* keys[2], uint32_t* vals[2], uint32_t n, co
     const int left = end_bit - shift, rest = passes - p;
     const int rb = sizeof(KT) == 2 ? left / rest : (left + rest - 1) / rest;
     KT* kout = (p + 1 == passes && !keep_keys) ? nullptr : keys[cur ^ 1];
+    const uint32_t fin = (uint32_t)(cur ^ 1);
     hipError_t e = hipSuccess;
+#define FGS_RADIX_PASS(RB_)                                                                                     \
+  e = radix_pass<RB_, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, d_range, shift, hist, totals, \
+                          scan_scratch, nb, final_word, fin, s)
     switch (rb) {
-      case 1: e = radix_pass<1, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, d_range, shift, hist, totals, scan_scratch, nb, s); break;
-      case 2: e = radix_pass<2, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, d_range, shift, hist, totals, scan_scratch, nb, s); break;
-      case 3: e = radix_pass<3, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, d_range, shift, hist, totals, scan_scratch, nb, s); break;
-      case 4: e = radix_pass<4, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, d_range, shift, hist, totals, scan_scratch, nb, s); break;
-      case 5: e = radix_pass<5, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, d_range, shift, hist, totals, scan_scratch, nb, s); break;
-      case 6: e = radix_pass<6, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, d_range, shift, hist, totals, scan_scratch, nb, s); break;
-      case 7: e = radix_pass<7, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, d_range, shift, hist, totals, scan_scratch, nb, s); break;
-      default: e = radix_pass<8, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, d_range, shift, hist, totals, scan_scratch, nb, s); break;
+      case 1: FGS_RADIX_PASS(1); break;
+      case 2: FGS_RADIX_PASS(2); break;
+      case 3: FGS_RADIX_PASS(3); break;
+      case 4: FGS_RADIX_PASS(4); break;
+      case 5: FGS_RADIX_PASS(5); break;
+      case 6: FGS_RADIX_PASS(6); break;
+      case 7: FGS_RADIX_PASS(7); break;
+      default: FGS_RADIX_PASS(8); break;
     }
+#undef FGS_RADIX_PASS
     if (e != hipSuccess) return e;
     shift += rb;
     cur ^= 1;
   }
-  *final_buf = cur;
+  // with d_range, trailing passes whose digit every key shares are skipped on
+  // the device: the buffer holding the result is then known there only
+  *final_buf = d_range != nullptr ? -1 : cur;
   return hipSuccess;
 }
 
 hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
                             int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s,
-                            const uint32_t* d_range, bool keep_keys) {
+                            const uint32_t* d_range, bool keep_keys, uint32_t* final_word) {
+  if ((uint64_t)n >= (uint64_t)kMaxSortPairs || (d_range != nullptr && final_word == nullptr))
+    return hipErrorInvalidValue;
   return radix_sort_impl<uint32_t>(keys, vals, n, d_count, d_range, begin_bit, end_bit, keep_keys, scratch,
-                                   final_buf, s);
+                                   final_buf, final_word, s);
 }
 
 hipError_t radix_sort_pairs16(uint16_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
                               int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s) {
+  if ((uint64_t)n >= (uint64_t)kMaxSortPairs) return hipErrorInvalidValue;
   return radix_sort_impl<uint16_t>(keys, vals, n, d_count, nullptr, begin_bit, end_bit, true, scratch, final_buf,
-                                   s);
+                                   nullptr, s);
 }
 
 }  // namespace fgs
