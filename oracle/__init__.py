@@ -16,6 +16,9 @@ keys32     FP32 emulation of the (tile, depth) instance keys: opacity-aware
            rectangle, exact per-tile test, canonical (tile, depth, id) order
            and tile ranges, with borderline bands.
 adam64     Adam in FP64 with the paper's hyperparameters.
+cond4d64   conditional 4D Gaussians (Sec. 3.4): 4D rotation from a left and a
+           right quaternion, conditional mean and covariance at a time, the
+           marginal factor of the opacity.
 zorder32   Morton (z-order) permutation of the means: FP32 quantisation,
            bit interleave, stable order.
 fp32err    float32 error model of the threshold decisions (Monte Carlo
@@ -33,3 +36,4 @@ from .adam64 import adam64  # noqa: F401
 from .keys32 import keys_ref, keys_ref_banded, depth_key32, tile_lists_for, record32, tile_rect  # noqa: F401
 from . import zorder32  # noqa: F401
 from . import fp32err  # noqa: F401
+from . import cond4d64  # noqa: F401

@@ -28,7 +28,7 @@ exceeds its band with probability 2e-9.
 """
 from __future__ import annotations
 
-from typing import Dict
+from typing import Dict, Optional
 
 import torch
 
@@ -53,17 +53,21 @@ class _Perturb:
 
 
 def mca_deviations(rows: Dict[str, torch.Tensor], W3: torch.Tensor, t: torch.Tensor, fx: float, fy: float,
-                   cx: float, cy: float, dilation: float, K: int = K_SAMPLES, seed: int = 0
-                   ) -> Dict[str, torch.Tensor]:
+                   cx: float, cy: float, dilation: float, K: int = K_SAMPLES, seed: int = 0,
+                   time: Optional[float] = None) -> Dict[str, torch.Tensor]:
     """Deviations of K float32-rounding samples of the per-Gaussian quantities
     from their exact values (all float64).
 
     rows: the row tensors of ``render64.preprocess64`` (means [N,3],
     log_scales [N,3], quats [N,4], opacity_logits [N]); W3, t: the camera's
     rotation and translation; fx, fy, cx, cy: intrinsics; dilation: the 2D
-    filter variance.  Returns [K, N] tensors: mean2d x and y, conic a, b, c,
-    opacity (relative), quaternion norm, camera z, det of the un-dilated
-    Sigma2D.
+    filter variance.  Conditional 4D Gaussians (rows with mean_t,
+    log_scale_t, quats_r; Sec. 3.4) are conditioned on ``time`` first: the
+    4D rotation from the two normalised quaternions, the 4D covariance, the
+    conditional mean and covariance and the marginal factor, one rounding per
+    operation.  Returns [K, N] tensors: mean2d x and y, conic a, b, c, opacity
+    (relative), quaternion norm (the smaller of two), camera z, det of the
+    un-dilated Sigma2D.
     """
     N = rows["means"].shape[0]
     gen = torch.Generator().manual_seed(seed)
@@ -75,6 +79,41 @@ def mca_deviations(rows: Dict[str, torch.Tensor], W3: torch.Tensor, t: torch.Ten
         return v.unsqueeze(0).expand(K + 1, N).clone()
 
     mu = [ex(rows["means"][:, i]) for i in range(3)]
+    four_d = time is not None and "quats_r" in rows
+
+    def unit_quat(key):
+        q = [ex(rows[key][:, i]) for i in range(4)]
+        n2 = r(r(r(r(q[0] * q[0]) + r(q[1] * q[1])) + r(q[2] * q[2])) + r(q[3] * q[3]))
+        qn = r(torch.sqrt(n2), 2.0)
+        return [r(c / qn) for c in q], qn
+
+    def dot(a, b):
+        acc = r(a[0] * b[0])
+        for k in range(1, len(a)):
+            acc = r(acc + r(a[k] * b[k]))
+        return acc
+
+    if four_d:
+        # 4D rotation v -> ql v qr as L(ql) R(qr) in (w, x, y, z), then (x, y, z, t) order
+        a, qn_l = unit_quat("quats")
+        b, qn_r = unit_quat("quats_r")
+        Lm = [[a[0], -a[1], -a[2], -a[3]], [a[1], a[0], -a[3], a[2]], [a[2], a[3], a[0], -a[1]],
+              [a[3], -a[2], a[1], a[0]]]
+        Rq = [[b[0], -b[1], -b[2], -b[3]], [b[1], b[0], b[3], -b[2]], [b[2], -b[3], b[0], b[1]],
+              [b[3], b[2], -b[1], b[0]]]
+        P = [[dot(Lm[i], [Rq[k][j] for k in range(4)]) for j in range(4)] for i in range(4)]
+        perm = [1, 2, 3, 0]
+        R4 = [[P[perm[i]][perm[j]] for j in range(4)] for i in range(4)]
+        s4 = [r(torch.exp(ex(rows["log_scales"][:, j])), 2.0) for j in range(3)]
+        s4.append(r(torch.exp(ex(rows["log_scale_t"])), 2.0))
+        M4 = [[r(R4[i][k] * s4[k]) for k in range(4)] for i in range(4)]
+        S4 = [[dot(M4[i], M4[j]) for j in range(4)] for i in range(4)]
+        dt = r(float(time) - ex(rows["mean_t"]))
+        ic = r(1.0 / S4[3][3])
+        wv = [r(S4[i][3] * ic) for i in range(3)]
+        mu = [r(mu[i] + r(wv[i] * dt)) for i in range(3)]
+        Sig4c = [[r(S4[i][j] - r(wv[i] * S4[j][3])) for j in range(3)] for i in range(3)]
+        p_t = r(torch.exp(-r(0.5 * r(r(dt * dt) * ic))), 2.0)
     Wf = [[float(W3[i, j]) for j in range(3)] for i in range(3)]
     tf = [float(t[i]) for i in range(3)]
 
@@ -85,24 +124,24 @@ def mca_deviations(rows: Dict[str, torch.Tensor], W3: torch.Tensor, t: torch.Ten
     mx = r(r(fx * xz) + cx)
     my = r(r(fy * yz) + cy)
 
-    # activations: normalised quaternion -> rotation, exp scales
-    q = [ex(rows["quats"][:, i]) for i in range(4)]
-    n2 = r(r(r(r(q[0] * q[0]) + r(q[1] * q[1])) + r(q[2] * q[2])) + r(q[3] * q[3]))
-    qn = r(torch.sqrt(n2), 2.0)
-    w, x, y, z = (r(c / qn) for c in q)
-    xx, yy, zz = r(x * x), r(y * y), r(z * z)
-    xy, xz_, yz_ = r(x * y), r(x * z), r(y * z)
-    wx, wy, wz = r(w * x), r(w * y), r(w * z)
-    Rm = [[r(1.0 - 2.0 * r(yy + zz)), 2.0 * r(xy - wz), 2.0 * r(xz_ + wy)],
-          [2.0 * r(xy + wz), r(1.0 - 2.0 * r(xx + zz)), 2.0 * r(yz_ - wx)],
-          [2.0 * r(xz_ - wy), 2.0 * r(yz_ + wx), r(1.0 - 2.0 * r(xx + yy))]]
-    s = [r(torch.exp(ex(rows["log_scales"][:, j])), 2.0) for j in range(3)]
-    M = [[r(Rm[i][j] * s[j]) for j in range(3)] for i in range(3)]
-
     def dot3(a, b):
         return r(r(r(a[0] * b[0]) + r(a[1] * b[1])) + r(a[2] * b[2]))
 
-    Sig = [[dot3(M[i], M[j]) for j in range(3)] for i in range(3)]
+    if four_d:
+        Sig = Sig4c
+        qn = torch.minimum(qn_l, qn_r)
+    else:
+        # activations: normalised quaternion -> rotation, exp scales
+        (w, x, y, z), qn = unit_quat("quats")
+        xx, yy, zz = r(x * x), r(y * y), r(z * z)
+        xy, xz_, yz_ = r(x * y), r(x * z), r(y * z)
+        wx, wy, wz = r(w * x), r(w * y), r(w * z)
+        Rm = [[r(1.0 - 2.0 * r(yy + zz)), 2.0 * r(xy - wz), 2.0 * r(xz_ + wy)],
+              [2.0 * r(xy + wz), r(1.0 - 2.0 * r(xx + zz)), 2.0 * r(yz_ - wx)],
+              [2.0 * r(xz_ - wy), 2.0 * r(yz_ + wx), r(1.0 - 2.0 * r(xx + yy))]]
+        s = [r(torch.exp(ex(rows["log_scales"][:, j])), 2.0) for j in range(3)]
+        M = [[r(Rm[i][j] * s[j]) for j in range(3)] for i in range(3)]
+        Sig = [[dot3(M[i], M[j]) for j in range(3)] for i in range(3)]
     # Eq. (2): T = J W3 with J = [[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]]
     j00, j11 = r(fx / Z), r(fy / Z)
     j02, j12 = -r(j00 * xz), -r(j11 * yz)
@@ -116,6 +155,8 @@ def mca_deviations(rows: Dict[str, torch.Tensor], W3: torch.Tensor, t: torch.Ten
     ca, cb, cc = r(h11 / deth), -r(h01 / deth), r(h00 / deth)
     # opacity = sigmoid(logit)
     o = r(1.0 / r(1.0 + r(torch.exp(-ex(rows["opacity_logits"])), 2.0)))
+    if four_d:
+        o = r(o * p_t)
 
     def dev(v):
         return v[1:] - v[:1]

@@ -62,9 +62,27 @@ def depth_key32(means, cam) -> np.ndarray:
         return ((W[2, 0] * m[0] + W[2, 1] * m[1]) + W[2, 2] * m[2]) + W[2, 3]
 
 
+def cond_inputs32(scene: Dict[str, torch.Tensor], time: float) -> Dict[str, np.ndarray]:
+    """Conditional 4D Gaussians (Sec. 3.4) at ``time``: the conditional mean
+    [3, N], covariance entries and marginal factor [N] computed in float64 by
+    the oracle (``cond4d64``) and rounded to float32, as inputs of
+    ``record32``.  The kernel conditions in float32; the differences (a few
+    ulps) move decisions only inside the borderline band."""
+    from .cond4d64 import condition, rows4
+    rows = {k: (v.detach().to(torch.float64).T.contiguous() if v.dim() == 2 else v.detach().to(torch.float64))
+            for k, v in scene.items()}
+    with torch.no_grad():
+        mean3, cov3, p = condition(*rows4(rows), float(time))
+    return {"means": mean3.T.numpy().astype(np.float32),
+            "cov": {(i, j): cov3[:, i, j].numpy().astype(np.float32) for i in range(3) for j in range(3)},
+            "p": p.numpy().astype(np.float32),
+            "qn_r": np.sqrt((rows["quats_r"] ** 2).sum(1)).numpy().astype(np.float32)}
+
+
 def record32(scene: Dict[str, torch.Tensor], cam, *, thr_scale: float = 1.0,
              cull_slack: float = 0.0, dilation=DILATION, tau=TAU_ALPHA,
-             det_min=DET_MIN, quat_min=QUAT_MIN, fp64_conic: bool = False) -> Dict[str, np.ndarray]:
+             det_min=DET_MIN, quat_min=QUAT_MIN, fp64_conic: bool = False,
+             cond: Optional[Dict[str, np.ndarray]] = None) -> Dict[str, np.ndarray]:
     """FP32 per-Gaussian quantities that decide the instance keys.
 
     thr_scale multiplies the truncation threshold (used for the borderline
@@ -72,9 +90,12 @@ def record32(scene: Dict[str, torch.Tensor], cam, *, thr_scale: float = 1.0,
     relative amount.  fp64_conic: the precision form's determinant and 2x2
     inverse in float64 from the float32 entries (products exact, one rounding
     per subtraction and per division), the conic rounded to float32.
+    cond: ``cond_inputs32`` of conditional 4D Gaussians, whose mean and 3D
+    covariance replace those of the raw parameters and whose marginal factor
+    multiplies the opacity.
     """
     with np.errstate(all="ignore"):
-        mu = _np32(scene["means"])
+        mu = _np32(scene["means"]) if cond is None else cond["means"]
         ls = _np32(scene["log_scales"])
         q = _np32(scene["quats"])
         logit = _np32(scene["opacity_logits"])
@@ -101,6 +122,9 @@ def record32(scene: Dict[str, torch.Tensor], cam, *, thr_scale: float = 1.0,
         S = {(0, 0): sig(0, 0), (0, 1): sig(0, 1), (0, 2): sig(0, 2),
              (1, 1): sig(1, 1), (1, 2): sig(1, 2), (2, 2): sig(2, 2)}
         S[(1, 0)], S[(2, 0)], S[(2, 1)] = S[(0, 1)], S[(0, 2)], S[(1, 2)]
+        if cond is not None:
+            S = dict(cond["cov"])
+            qn = np.minimum(qn, cond["qn_r"])
 
         X = ((W[0, 0] * mu[0] + W[0, 1] * mu[1]) + W[0, 2] * mu[2]) + W[0, 3]
         Y = ((W[1, 0] * mu[0] + W[1, 1] * mu[1]) + W[1, 2] * mu[2]) + W[1, 3]
@@ -135,6 +159,8 @@ def record32(scene: Dict[str, torch.Tensor], cam, *, thr_scale: float = 1.0,
             cb = -h01 / deth
             cc = h00 / deth
         o = one / (one + np.exp(-logit))
+        if cond is not None:
+            o = o * cond["p"]
 
         lo, hi = f32(1.0 - cull_slack), f32(1.0 + cull_slack)
         det_ok = (det_d >= np.float64(det_min * lo)) if fp64_conic else (det >= det_min * lo)
@@ -269,10 +295,16 @@ def _sort_instances(gid, tid, depth, n_tiles_total):
 
 
 def keys_ref(scene: Dict[str, torch.Tensor], cam, tile: int = 16, thr_scale: float = 1.0,
-             cull_slack: float = 0.0, fp64_conic: bool = False) -> Dict[str, np.ndarray]:
+             cull_slack: float = 0.0, fp64_conic: bool = False, time: Optional[float] = None,
+             depth: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
     """Sorted instance keys (tile id), values (Gaussian index), tile ranges [tiles, 2],
-    per-Gaussian tile counts and the FP32 record they were derived from."""
-    rec = record32(scene, cam, thr_scale=thr_scale, cull_slack=cull_slack, fp64_conic=fp64_conic)
+    per-Gaussian tile counts and the FP32 record they were derived from.
+    time: conditional 4D Gaussians at that time; depth: FP32 depth keys for
+    the order (else the record's)."""
+    rec = record32(scene, cam, thr_scale=thr_scale, cull_slack=cull_slack, fp64_conic=fp64_conic,
+                   cond=cond_inputs32(scene, time) if "quats_r" in scene else None)
+    if depth is not None:
+        rec = dict(rec, depth=np.asarray(depth, dtype=np.float32))
     w, h = int(cam.width), int(cam.height)
     gid, tid = _instances(rec, w, h, tile)  # the extents already carry thr_scale
     tiles = ((w + tile - 1) // tile) * ((h + tile - 1) // tile)
@@ -284,24 +316,31 @@ def keys_ref(scene: Dict[str, torch.Tensor], cam, tile: int = 16, thr_scale: flo
             "tiles_y": (h + tile - 1) // tile}
 
 
-def keys_ref_banded(scene, cam, tile: int = 16, delta: float = 1e-3, fp64_conic: bool = False):
+def keys_ref_banded(scene, cam, tile: int = 16, delta: float = 1e-3, fp64_conic: bool = False,
+                    time: Optional[float] = None, depth: Optional[np.ndarray] = None):
     """Nominal instances plus the borderline pairs: those present with every
     threshold loosened by ``delta`` (relative) but absent with every threshold
     tightened by ``delta``.  Returns (nominal, borderline_pairs) where
     borderline_pairs is a set of (tile, gaussian) tuples."""
-    nom = keys_ref(scene, cam, tile, fp64_conic=fp64_conic)
-    loose = keys_ref(scene, cam, tile, thr_scale=1.0 + delta, cull_slack=delta, fp64_conic=fp64_conic)
-    tight = keys_ref(scene, cam, tile, thr_scale=1.0 - delta, cull_slack=-delta, fp64_conic=fp64_conic)
+    kw = dict(fp64_conic=fp64_conic, time=time, depth=depth)
+    nom = keys_ref(scene, cam, tile, **kw)
+    loose = keys_ref(scene, cam, tile, thr_scale=1.0 + delta, cull_slack=delta, **kw)
+    tight = keys_ref(scene, cam, tile, thr_scale=1.0 - delta, cull_slack=-delta, **kw)
     lo_pairs = set(zip(tight["keys"].tolist(), tight["vals"].tolist()))
     hi_pairs = set(zip(loose["keys"].tolist(), loose["vals"].tolist()))
     return nom, hi_pairs - lo_pairs
 
 
-def tile_lists_for(scene, cam, tiles, tile: int = 16, delta: Optional[float] = None):
+def tile_lists_for(scene, cam, tiles, tile: int = 16, delta: Optional[float] = None, time: Optional[float] = None,
+                   depth: Optional[np.ndarray] = None):
     """Reference list of Gaussian indices (canonical order) for a few tile ids,
     without materialising every instance -- for full-size spot checks.
-    With ``delta`` also returns the borderline Gaussians of each tile."""
-    rec = record32(scene, cam)
+    With ``delta`` also returns the borderline Gaussians of each tile.
+    time: conditional 4D Gaussians at that time; depth: FP32 depth keys for
+    the order (else the record's)."""
+    rec = record32(scene, cam, cond=cond_inputs32(scene, time) if "quats_r" in scene else None)
+    if depth is not None:
+        rec = dict(rec, depth=np.asarray(depth, dtype=np.float32))
     w, h = int(cam.width), int(cam.height)
     tiles_x = (w + tile - 1) // tile
     tx0, ty0, tx1, ty1, ne = tile_rect(rec, w, h, tile)

@@ -139,11 +139,15 @@ def _rows(scene: Dict[str, torch.Tensor]) -> Dict[str, torch.Tensor]:
 
 
 def preprocess64(p: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTINGS,
-                 sh_degree: int = 3, mca: bool = False) -> Dict[str, torch.Tensor]:
+                 sh_degree: int = 3, mca: bool = False, time: Optional[float] = None) -> Dict[str, torch.Tensor]:
     """Per-Gaussian projection in float64 (differentiable w.r.t. the row tensors in p).
 
     p holds row tensors: means [N,3], log_scales [N,3], quats [N,4],
-    opacity_logits [N], sh_dc [N,3], sh_rest [N,45].
+    opacity_logits [N], sh_dc [N,3], sh_rest [N,45].  Conditional 4D
+    Gaussians (Sec. 3.4; ``cond4d64``) also hold mean_t [N], log_scale_t [N]
+    and quats_r [N,4] (quats is then the left quaternion); they are rendered
+    at ``time`` as their conditional 3D Gaussians, the opacity times the
+    marginal factor.
     Returns mean2d [N,2], cov2d [N,2,2] (un-dilated), cov2d_dil, conic [N,3]
     (a, b, c of the inverse dilated matrix [[a, b], [b, c]]), opacity [N],
     rgb [N,3], colour before the clip, camera-space position, the cull mask
@@ -152,14 +156,23 @@ def preprocess64(p: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
     samples of ``fp32err.mca_deviations`` (key ``dev``).  Rows failing a
     cull test may hold non-finite values; callers select ``valid`` rows.
     """
-    mu = p["means"]
-    s = torch.exp(p["log_scales"])
     q = p["quats"]
     qn = torch.linalg.vector_norm(q, dim=-1)
-    qh = q / torch.where(qn > 0, qn, torch.ones_like(qn))[:, None]
-    R = quat_to_rotation64(qh)
-    M = R * s[:, None, :]
-    Sigma = M @ M.transpose(-1, -2)
+    four_d = "quats_r" in p
+    if four_d:
+        if time is None:
+            raise ValueError("conditional 4D Gaussians are rendered at a time")
+        from .cond4d64 import condition, rows4
+        # the guard of App. B.1 on both quaternions: the smaller norm decides
+        qn = torch.minimum(qn, torch.linalg.vector_norm(p["quats_r"], dim=-1))
+        mu, Sigma, p_t = condition(*rows4(p), float(time))
+    else:
+        mu = p["means"]
+        s = torch.exp(p["log_scales"])
+        qh = q / torch.where(qn > 0, qn, torch.ones_like(qn))[:, None]
+        R = quat_to_rotation64(qh)
+        M = R * s[:, None, :]
+        Sigma = M @ M.transpose(-1, -2)
 
     W3, t = _camera64(cam)
     mh = mu @ W3.T + t
@@ -184,6 +197,8 @@ def preprocess64(p: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
                          cov2d_dil[:, 0, 0] / safe_det], dim=-1)
 
     opacity = torch.sigmoid(p["opacity_logits"])
+    if four_d:
+        opacity = opacity * p_t
 
     campos = camera_center64(cam)
     dvec = mu - campos
@@ -215,7 +230,7 @@ def preprocess64(p: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
         idx = torch.nonzero(near_cull | ~torch.isfinite(kappa)).flatten()
         idx = idx[torch.isfinite(det2d[idx])]
         if len(idx):
-            d = _mca(p, idx, cam, st)
+            d = _mca(p, idx, cam, st, time)
             cull_border[idx] = ((torch.abs(qn[idx] - st.quat_min) <= lam * E.band_sigma(d["qn"]))
                                 | (torch.abs(z[idx] - float(cam.near)) <= lam * E.band_sigma(d["z"]))
                                 | (torch.abs(det2d[idx] - st.det_min) <= lam * E.band_sigma(d["det2d"]))
@@ -225,7 +240,7 @@ def preprocess64(p: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
         terms = Y[:, :, None] * coeffs
         col_sigma = E.U32 * torch.sqrt((4.0 * terms * terms).sum(dim=1) + colour * colour)
         clip_border = (torch.abs(colour) <= lam * col_sigma).any(dim=-1)
-        dev = _mca(p, torch.arange(n), cam, st) if mca else None
+        dev = _mca(p, torch.arange(n), cam, st, time) if mca else None
     return {
         "mean2d": mean2d, "cov2d": cov2d, "cov2d_dil": cov2d_dil, "conic": conic,
         "opacity": opacity, "rgb": rgb, "colour": colour, "cam_pos": mh, "det2d": det2d,
@@ -234,15 +249,19 @@ def preprocess64(p: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
     }
 
 
-def _mca(p: Dict[str, torch.Tensor], idx: torch.Tensor, cam, st: Settings, chunk: int = 32768):
+def _mca(p: Dict[str, torch.Tensor], idx: torch.Tensor, cam, st: Settings, time: Optional[float] = None,
+         chunk: int = 32768):
     """fp32err.mca_deviations of rows idx (in chunks), detached from autograd."""
     W3, t = _camera64(cam)
+    keys = ["means", "log_scales", "quats", "opacity_logits"]
+    if "quats_r" in p:
+        keys += ["mean_t", "log_scale_t", "quats_r"]
     outs = []
     for c0 in range(0, len(idx), chunk):
         sel = idx[c0:c0 + chunk]
-        rows = {k: p[k].detach().index_select(0, sel) for k in ("means", "log_scales", "quats", "opacity_logits")}
+        rows = {k: p[k].detach().index_select(0, sel) for k in keys}
         outs.append(E.mca_deviations(rows, W3, t, float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy),
-                                     st.dilation))
+                                     st.dilation, time=time))
     if not outs:
         return None
     return {k: torch.cat([o[k] for o in outs], dim=1) for k in outs[0]}
@@ -343,10 +362,15 @@ def composite64(px: torch.Tensor, py: torch.Tensor, mean2d: torch.Tensor,
     return C, T_run, last, border, nblend
 
 
-def _canonical_order(scene: Dict[str, torch.Tensor], cam, idx: np.ndarray) -> np.ndarray:
-    """Indices ``idx`` ordered by (FP32 depth key, index), the canonical order."""
+def _canonical_order(scene: Dict[str, torch.Tensor], cam, idx: np.ndarray,
+                     keys: Optional[np.ndarray] = None) -> np.ndarray:
+    """Indices ``idx`` ordered by (FP32 depth key, index), the canonical order.
+    keys: the FP32 depth of every Gaussian when given (else computed from the
+    means as the kernel does)."""
     from .keys32 import depth_key32  # same package; FP32 key spelled out there
-    keys = depth_key32(scene["means"], cam)[idx]
+    if keys is None:
+        keys = depth_key32(scene["means"], cam)
+    keys = np.asarray(keys, dtype=np.float32)[idx]
     return idx[np.lexsort((idx, keys))]
 
 
@@ -363,7 +387,8 @@ def rect_candidates64(mean2d: torch.Tensor, extent: torch.Tensor, box: Tuple[int
 def render64(scene: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTINGS, *,
              dl_dimage: Optional[torch.Tensor] = None, crop: Optional[Tuple[int, int, int, int]] = None,
              cull: bool = True, block_px: int = 16, sh_degree: int = 3,
-             depth_block: int = 256, mask_borderline: bool = False) -> Dict[str, object]:
+             depth_block: int = 256, mask_borderline: bool = False, time: Optional[float] = None,
+             order_keys: Optional[np.ndarray] = None) -> Dict[str, object]:
     """Render (and optionally differentiate) a scene in float64 on the CPU.
 
     scene: SoA float32 tensors (see ``synthetic``); cam: camera with
@@ -379,6 +404,10 @@ def render64(scene: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
     opacity-aware rectangle reaches it (exact: outside it alpha < tau_alpha,
     see the module docstring); False makes every Gaussian a candidate of every
     pixel.
+    time: the timestep of conditional 4D Gaussians (``cond4d64``).
+    order_keys: FP32 depth of every Gaussian for the canonical order (else the
+    FP32 camera z of the means, as the kernel computes it; for conditional 4D
+    Gaussians the float32 rounding of the float64 conditional depth).
     """
     x0, y0, x1, y1 = crop if crop is not None else (0, 0, int(cam.width), int(cam.height))
     h, w = y1 - y0, x1 - x0
@@ -387,9 +416,11 @@ def render64(scene: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
     N = rows["means"].shape[0]
 
     with torch.no_grad():
-        pre_all = preprocess64(rows, cam, st, sh_degree)
+        pre_all = preprocess64(rows, cam, st, sh_degree, time=time)
     valid_idx = torch.nonzero(pre_all["valid"]).flatten().numpy()
-    order = _canonical_order(scene, cam, valid_idx) if len(valid_idx) else valid_idx
+    if order_keys is None and "quats_r" in rows:
+        order_keys = pre_all["cam_pos"][:, 2].numpy().astype(np.float32)
+    order = _canonical_order(scene, cam, valid_idx, order_keys) if len(valid_idx) else valid_idx
     if cull and len(order):
         # Gaussians whose widened FP64 rectangle misses the crop have alpha < tau there.
         near = rect_candidates64(pre_all["mean2d"][order], pre_all["extent"][order], (x0, y0, x1, y1))
@@ -400,7 +431,7 @@ def render64(scene: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
     for k, v in rows.items():
         leaves[k] = v.clone().requires_grad_(want_grad)
     sub = {k: v.index_select(0, order_t) for k, v in leaves.items()}
-    pre = preprocess64(sub, cam, st, sh_degree, mca=True)
+    pre = preprocess64(sub, cam, st, sh_degree, mca=True, time=time)
     m2d, con, opa, rgb = pre["mean2d"], pre["conic"], pre["opacity"], pre["rgb"]
     lv = [t.detach().clone().requires_grad_(want_grad) for t in (m2d, con, opa, rgb)]
     devs = pre["dev"]
@@ -419,7 +450,7 @@ def render64(scene: Dict[str, torch.Tensor], cam, st: Settings = DEFAULT_SETTING
     cb = torch.nonzero(pre_all["cull_border"]).flatten()
     for gi in cb.tolist():
         with torch.no_grad():
-            one = preprocess64({k: v[gi:gi + 1] for k, v in rows.items()}, cam, st, sh_degree)
+            one = preprocess64({k: v[gi:gi + 1] for k, v in rows.items()}, cam, st, sh_degree, time=time)
             e2 = torch.sqrt(torch.clamp(2.0 * math.log(max(float(one["opacity"][0]), 1e-300) / st.tau_alpha)
                                         * torch.stack([one["cov2d_dil"][0, 0, 0], one["cov2d_dil"][0, 1, 1]]),
                                         min=0.0))

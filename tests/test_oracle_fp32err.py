@@ -25,10 +25,51 @@ from oracle.render64 import _rows
 F32 = np.float32
 
 
-def preprocess32(sc, cam):
-    """mean2d, conic (a, b, c), opacity in numpy float32, operation by operation."""
+def hamilton32(p, q):
+    """Quaternion product of float32 component lists (w, x, y, z)."""
+    return [p[0] * q[0] - p[1] * q[1] - p[2] * q[2] - p[3] * q[3],
+            p[0] * q[1] + p[1] * q[0] + p[2] * q[3] - p[3] * q[2],
+            p[0] * q[2] - p[1] * q[3] + p[2] * q[0] + p[3] * q[1],
+            p[0] * q[3] + p[1] * q[2] - p[2] * q[1] + p[3] * q[0]]
+
+
+def condition32(sc, t):
+    """Conditional 4D Gaussians at time t in numpy float32: the mean, the 3x3
+    covariance and the marginal factor (Sec. 3.4), written on its own with
+    quaternion products applied to the basis vectors."""
+    def unit(q):
+        qn = np.sqrt(((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3])
+        return [q[k] / qn for k in range(4)]
+    ql = unit(sc["quats"].numpy().astype(F32))
+    qr = unit(sc["quats_r"].numpy().astype(F32))
+    n = ql[0].shape[0]
+    z, o = np.zeros(n, F32), np.ones(n, F32)
+    basis = [[z, o, z, z], [z, z, o, z], [z, z, z, o], [o, z, z, z]]  # x, y, z, t as quaternions
+    cols = []
+    for e in basis:
+        im = hamilton32(hamilton32(ql, e), qr)
+        cols.append([im[1], im[2], im[3], im[0]])
+    R = [[cols[c][r] for c in range(4)] for r in range(4)]
+    s = [np.exp(v) for v in sc["log_scales"].numpy().astype(F32)] + [np.exp(sc["log_scale_t"].numpy().astype(F32))]
+    M = [[R[i][k] * s[k] for k in range(4)] for i in range(4)]
+    Sg = [[((M[i][0] * M[j][0] + M[i][1] * M[j][1]) + M[i][2] * M[j][2]) + M[i][3] * M[j][3] for j in range(4)]
+          for i in range(4)]
+    dt = F32(t) - sc["mean_t"].numpy().astype(F32)
+    mu = sc["means"].numpy().astype(F32)
+    mean = [mu[i] + Sg[i][3] * (dt / Sg[3][3]) for i in range(3)]
+    cov = [[Sg[i][j] - (Sg[i][3] * Sg[j][3]) / Sg[3][3] for j in range(3)] for i in range(3)]
+    p = np.exp(F32(-0.5) * (dt * dt) / Sg[3][3])
+    return np.stack(mean), cov, p
+
+
+def preprocess32(sc, cam, time=None):
+    """mean2d, conic (a, b, c), opacity in numpy float32, operation by operation
+    (conditional 4D Gaussians at ``time`` when the scene has them)."""
     W = np.asarray(cam.world_to_cam, dtype=F32)
     mu = sc["means"].numpy().astype(F32)
+    four_d = "quats_r" in sc
+    if four_d:
+        mu, cov4, p4 = condition32(sc, time)
     X = [(W[r, 0] * mu[0] + W[r, 1] * mu[1]) + W[r, 2] * mu[2] + W[r, 3] for r in range(3)]
     x, y, z = X
     mx = F32(cam.fx) * (x / z) + F32(cam.cx)
@@ -43,6 +84,8 @@ def preprocess32(sc, cam):
     s = np.exp(sc["log_scales"].numpy().astype(F32))
     M = [[R[i][j] * s[j] for j in range(3)] for i in range(3)]
     Sig = [[(M[i][0] * M[j][0] + M[i][1] * M[j][1]) + M[i][2] * M[j][2] for j in range(3)] for i in range(3)]
+    if four_d:
+        Sig = cov4
     fx, fy = F32(cam.fx), F32(cam.fy)
     J = [[fx / z, np.zeros_like(z), -(fx / z) * (x / z)], [np.zeros_like(z), fy / z, -(fy / z) * (y / z)]]
     T = [[(J[a][0] * W[0, k] + J[a][1] * W[1, k]) + J[a][2] * W[2, k] for k in range(3)] for a in range(2)]
@@ -51,6 +94,8 @@ def preprocess32(sc, cam):
     h00, h11, h01 = cov[0][0] + F32(0.3), cov[1][1] + F32(0.3), cov[0][1]
     det = h00 * h11 - h01 * h01
     o = one / (one + np.exp(-sc["opacity_logits"].numpy().astype(F32)))
+    if four_d:
+        o = o * p4
     return mx, my, h11 / det, -h01 / det, h00 / det, o
 
 
@@ -109,8 +154,39 @@ def test_mean2d_deviation_matches_its_roundings():
     assert float(ratio.max()) < 1.6
 
 
+def scene4d(n, seed):
+    """The workload's draws plus conditional 4D parameters: time means in [0, 1],
+    temporal log-scales N(-1, 0.3), right quaternions near the left ones'
+    conjugates (small mixing of space and time)."""
+    sc = S.make_scene(n, seed)
+    g = torch.Generator().manual_seed(seed + 11)
+    sc["mean_t"] = torch.rand(n, generator=g)
+    sc["log_scale_t"] = (torch.randn(n, generator=g) * 0.3 - 1.0)
+    conj = sc["quats"] * torch.tensor([1.0, -1.0, -1.0, -1.0])[:, None]
+    sc["quats_r"] = conj + 0.3 * torch.randn(4, n, generator=g)
+    return {k: v.float().contiguous() for k, v in sc.items()}
+
+
+@pytest.fixture(scope="module")
+def small4d():
+    sc, cam, t = scene4d(4_000, 8), S.identity_camera(128, 112, 130.0, cx=50.0, cy=70.0), 0.37
+    with torch.no_grad():
+        pre = O.preprocess64(_rows(sc), cam, mca=True, time=t)
+    return sc, cam, pre, preprocess32(sc, cam, time=t)
+
+
 def test_alpha_band_covers_float32_alpha(small):
-    sc, cam, pre, (mx, my, ca, cb, cc, o32) = small
+    _check_alpha_band(*small)
+
+
+def test_alpha_band_covers_float32_alpha_conditional_4d(small4d):
+    """The same for conditional 4D Gaussians (Sec. 3.4): the model's bands
+    include the float32 error of the conditioning."""
+    _check_alpha_band(*small4d)
+
+
+def _check_alpha_band(sc, cam, pre, f32vals):
+    mx, my, ca, cb, cc, o32 = f32vals
     v = pre["valid"].numpy()
     idx = np.nonzero(v)[0]
     m64 = pre["mean2d"].numpy()
