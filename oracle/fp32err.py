@@ -63,9 +63,10 @@ def mca_deviations(rows: Dict[str, torch.Tensor], W3: torch.Tensor, t: torch.Ten
     rotation and translation; fx, fy, cx, cy: intrinsics; dilation: the 2D
     filter variance.  Conditional 4D Gaussians (rows with mean_t,
     log_scale_t, quats_r; Sec. 3.4) are conditioned on ``time`` first: the
-    4D rotation from the two normalised quaternions, the 4D covariance, the
-    conditional mean and covariance and the marginal factor, one rounding per
-    operation.  Returns [K, N] tensors: mean2d x and y, conic a, b, c, opacity
+    4D rotation from the two normalised quaternions, M = R diag(s), and the
+    conditional mean, covariance and marginal factor in the projection form
+    the kernel evaluates (the covariance as N N^T with N the spatial rows of
+    M projected off the unit time row), one rounding per operation.  Returns [K, N] tensors: mean2d x and y, conic a, b, c, opacity
     (relative), quaternion norm (the smaller of two), camera z, det of the
     un-dilated Sigma2D.
     """
@@ -107,13 +108,18 @@ def mca_deviations(rows: Dict[str, torch.Tensor], W3: torch.Tensor, t: torch.Ten
         s4 = [r(torch.exp(ex(rows["log_scales"][:, j])), 2.0) for j in range(3)]
         s4.append(r(torch.exp(ex(rows["log_scale_t"])), 2.0))
         M4 = [[r(R4[i][k] * s4[k]) for k in range(4)] for i in range(4)]
-        S4 = [[dot(M4[i], M4[j]) for j in range(4)] for i in range(4)]
+        # projection form: u = m_t / |m_t|, h = M_xyz u, e = dt / |m_t|,
+        # N = M_xyz - h u^T; mean + h e, covariance N N^T, factor exp(-e^2 / 2)
+        nt = r(torch.sqrt(dot(M4[3], M4[3])))
+        inv = r(1.0 / nt)
+        u = [r(M4[3][k] * inv) for k in range(4)]
         dt = r(float(time) - ex(rows["mean_t"]))
-        ic = r(1.0 / S4[3][3])
-        wv = [r(S4[i][3] * ic) for i in range(3)]
-        mu = [r(mu[i] + r(wv[i] * dt)) for i in range(3)]
-        Sig4c = [[r(S4[i][j] - r(wv[i] * S4[j][3])) for j in range(3)] for i in range(3)]
-        p_t = r(torch.exp(-r(0.5 * r(r(dt * dt) * ic))), 2.0)
+        e_t = r(dt * inv)
+        h = [dot(M4[i], u) for i in range(3)]
+        N4 = [[r(M4[i][k] - r(h[i] * u[k])) for k in range(4)] for i in range(3)]
+        mu = [r(mu[i] + r(h[i] * e_t)) for i in range(3)]
+        Sig4c = [[dot(N4[i], N4[j]) for j in range(3)] for i in range(3)]
+        p_t = r(torch.exp(-r(0.5 * r(e_t * e_t))), 2.0)
     Wf = [[float(W3[i, j]) for j in range(3)] for i in range(3)]
     tf = [float(t[i]) for i in range(3)]
 

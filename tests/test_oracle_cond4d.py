@@ -146,3 +146,29 @@ def test_autograd_matches_central_finite_differences(seed):
             checked += 1
     assert set(r["grads"]) >= {"mean_t", "log_scale_t", "quats_r"}
     assert checked >= 65 * n - 4
+
+
+def test_projection_form_equals_the_schur_complement():
+    """The conditional covariance as the Gram matrix of the spatial rows of
+    M = R diag(s) projected off the unit time row u (N = M_xyz (I - u u^T),
+    Sigma_3|t = N N^T), the mean shift (M_xyz u) (t - mu_t) / |m_t| and the
+    factor exp(-((t - mu_t) / |m_t|)^2 / 2) equal the Schur-complement
+    definition: I - u u^T is idempotent, so N N^T = A - b b^T / c."""
+    n = 48
+    g = torch.Generator().manual_seed(11)
+    ql, qr = rand_quats(n, 12), rand_quats(n, 13)
+    ls4 = torch.randn(n, 4, generator=g, dtype=F64) * 0.8 - 1.0
+    mean4 = torch.randn(n, 4, generator=g, dtype=F64)
+    t = 0.3
+    mean3, cov3, p = C.condition(mean4, ls4, ql, qr, t)
+    M = C.rotation4(ql, qr) * torch.exp(ls4)[:, None, :]
+    m = M[:, 3, :]
+    norm = torch.linalg.vector_norm(m, dim=1)
+    u = m / norm[:, None]
+    along = (M[:, :3, :] * u[:, None, :]).sum(-1)
+    N = M[:, :3, :] - along[:, :, None] * u[:, None, :]
+    e = (t - mean4[:, 3]) / norm
+    scale = cov3.abs().amax(dim=(1, 2)) + (M[:, :3, :] ** 2).sum(-1).amax(-1)
+    assert float(((N @ N.transpose(1, 2) - cov3).abs().amax(dim=(1, 2)) / scale).max()) <= 1e-13
+    assert float((mean4[:, :3] + along * e[:, None] - mean3).abs().max()) <= 1e-12
+    assert float((torch.exp(-0.5 * e * e) - p).abs().max()) <= 1e-14

@@ -36,7 +36,9 @@ def hamilton32(p, q):
 def condition32(sc, t):
     """Conditional 4D Gaussians at time t in numpy float32: the mean, the 3x3
     covariance and the marginal factor (Sec. 3.4), written on its own with
-    quaternion products applied to the basis vectors."""
+    quaternion products applied to the basis vectors, and the covariance as
+    the Gram matrix of the spatial rows of M = R diag(s) with their
+    components along the time row removed (the form the kernel evaluates)."""
     def unit(q):
         qn = np.sqrt(((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3])
         return [q[k] / qn for k in range(4)]
@@ -52,13 +54,20 @@ def condition32(sc, t):
     R = [[cols[c][r] for c in range(4)] for r in range(4)]
     s = [np.exp(v) for v in sc["log_scales"].numpy().astype(F32)] + [np.exp(sc["log_scale_t"].numpy().astype(F32))]
     M = [[R[i][k] * s[k] for k in range(4)] for i in range(4)]
-    Sg = [[((M[i][0] * M[j][0] + M[i][1] * M[j][1]) + M[i][2] * M[j][2]) + M[i][3] * M[j][3] for j in range(4)]
-          for i in range(4)]
+    # the time row m of M: Sigma_tt = |m|^2; the spatial rows minus their
+    # components along m give the conditional covariance as a Gram matrix
+    m = M[3]
+    mm = ((m[0] * m[0] + m[1] * m[1]) + m[2] * m[2]) + m[3] * m[3]
+    norm = np.sqrt(mm)
+    unit = [m[k] / norm for k in range(4)]
+    along = [((M[i][0] * unit[0] + M[i][1] * unit[1]) + M[i][2] * unit[2]) + M[i][3] * unit[3] for i in range(3)]
+    perp = [[M[i][k] - along[i] * unit[k] for k in range(4)] for i in range(3)]
     dt = F32(t) - sc["mean_t"].numpy().astype(F32)
     mu = sc["means"].numpy().astype(F32)
-    mean = [mu[i] + Sg[i][3] * (dt / Sg[3][3]) for i in range(3)]
-    cov = [[Sg[i][j] - (Sg[i][3] * Sg[j][3]) / Sg[3][3] for j in range(3)] for i in range(3)]
-    p = np.exp(F32(-0.5) * (dt * dt) / Sg[3][3])
+    mean = [mu[i] + along[i] * (dt / norm) for i in range(3)]
+    cov = [[((perp[i][0] * perp[j][0] + perp[i][1] * perp[j][1]) + perp[i][2] * perp[j][2]) + perp[i][3] * perp[j][3]
+            for j in range(3)] for i in range(3)]
+    p = np.exp(F32(-0.5) * (dt / norm) * (dt / norm))
     return np.stack(mean), cov, p
 
 
