@@ -594,6 +594,39 @@ def run_dynamic(args, dev):
             "instances": br.last_stats["n_instances"], "roofline": roof}
 
 
+def run_dynamic_conditional(args, dev):
+    """Conditional 4D Gaussians (Sec. 3.4) at the dynamic workload's shape: 1M
+    Gaussians with a time mean, a temporal scale and a right quaternion, 8
+    timesteps t = k/7 at 1280x720 rendered as their conditional 3D Gaussians,
+    bfloat16 SH; the backward yields the 4D parameters' gradients and Adam
+    updates all of them."""
+    import paper_2602_09999_amd as P
+    from paper_2602_09999_amd import binding as B
+    scene = S.make_scene(DYN_N, seed=args.seed)
+    scene.update(S.make_cond4d(scene, seed=args.seed))
+    params = {k: v.to(dev) for k, v in scene.items()}
+    del scene
+    for k in ("sh_dc", "sh_rest"):
+        params[k] = params[k].bfloat16().contiguous()
+    cam = S.identity_camera(1280, 720, 1000.0)
+    times = S.timesteps(DYN_STEPS)
+    br = B.BatchRasterizer([cam] * DYN_STEPS, times=times)
+    lrs = dict(S.ADAM_LR, mean_t=S.ADAM_LR["means"], log_scale_t=S.ADAM_LR["log_scales"], quats_r=S.ADAM_LR["quats"])
+    opt = P.FusedAdam(params, lrs)
+    npix = sum(B.view_pixels([cam] * DYN_STEPS))
+    target = torch.rand(3 * npix, generator=torch.Generator().manual_seed(args.seed + 2)).to(dev)
+    dl = torch.empty(3 * npix, device=dev)
+    grads = {k: torch.empty_like(v) for k, v in params.items()}
+    step = batched_step_fn(br, params, opt, target, dl, grads, 0)
+    sec = time_steps(step, max(3, args.steps // 5), 2)
+    roof = adam_roofline(step, params)
+    log(f"dynamic (conditional 4D): {sec * 1e3:.2f} ms per step of {DYN_STEPS} timesteps; k_adam "
+        f"{roof['avg_launch_ms']:.3f} ms ({roof['frac']:.2f} of HBM peak)")
+    return {"workload": f"{DYN_N} conditional 4D Gaussians, {DYN_STEPS} timesteps, 1280x720, bf16 SH",
+            "ms_per_step": sec * 1e3, "steps_per_s": 1.0 / sec, "timesteps_per_s": DYN_STEPS / sec,
+            "instances": br.last_stats["n_instances"], "roofline": roof}
+
+
 def workload_counts(r, w, dev):
     """Instance and gradient counts of a finished run (outside any timed region)."""
     rz, last = r["rz"], r["last"]
@@ -774,6 +807,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_dynamic:
         out["dynamic"] = run_dynamic(args, dev)
+        torch.cuda.empty_cache()
+        out["dynamic_conditional"] = run_dynamic_conditional(args, dev)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         with_bf16 = any(results[v]["sh_bf16"] for v in results)

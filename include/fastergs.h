@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define FGS_ABI_VERSION 11
+#define FGS_ABI_VERSION 12
 
 typedef enum fgs_status {
   FGS_OK = 0,
@@ -75,9 +75,21 @@ typedef enum fgs_dtype { FGS_F32 = 0, FGS_BF16 = 1 } fgs_dtype;
  * and their gradients stored as bfloat16; everything else, including all
  * blending, transmittance and gradient accumulation, stays float32).
  * sh_degree in 0..3 (planes beyond the degree are not read). n may be 0.
- * Dynamic scenes (the batched entry points, one time per view): velocity and
- * accel [3][n] (both or neither; NULL = static) give the mean at time t as
- * (means + velocity t) + accel t^2 in float32.                            */
+ * Dynamic scenes (the batched entry points, one time per view), two models:
+ * - polynomial motion: velocity and accel [3][n] (both or neither; NULL =
+ *   static) give the mean at time t as (means + velocity t) + accel t^2 in
+ *   float32;
+ * - conditional 4D Gaussians (Sec. 3.4 "Extension to Dynamic Scenes"):
+ *   mean_t [n] (time of the mean), log_scale_t [n] (temporal log-scale) and
+ *   quats_r [4][n] (right-isoclinic quaternion; quats is then the left one),
+ *   all three or none, not together with velocity/accel.  The 4D rotation
+ *   maps (x, y, z, t), read as the quaternion t + xi + yj + zk, to
+ *   quats v quats_r (both normalised); Sigma4 = R diag(s^2) R^T; at time t a
+ *   Gaussian is rendered as its conditional 3D Gaussian (mean mu_xyz +
+ *   Sigma_xyz,t (t - mean_t) / Sigma_tt, covariance Sigma_xyz,xyz -
+ *   Sigma_xyz,t Sigma_t,xyz / Sigma_tt) with opacity sigmoid(logit) times
+ *   exp(-(t - mean_t)^2 / (2 Sigma_tt)); both quaternions are guarded
+ *   against degenerate norms.                                              */
 typedef struct fgs_gaussians {
   int64_t n;
   const float* means;
@@ -90,11 +102,15 @@ typedef struct fgs_gaussians {
   int32_t sh_degree;
   const float* velocity;
   const float* accel;
+  const float* mean_t;
+  const float* log_scale_t;
+  const float* quats_r;
 } fgs_gaussians;
 
 /* Gradient planes with the layout of fgs_gaussians (all written in full);
  * sh_dc and sh_rest have the element type of the SH coefficients; velocity
- * and accel are written for dynamic Gaussians (else unused). */
+ * and accel are written for polynomial motion, mean_t, log_scale_t and
+ * quats_r for conditional 4D Gaussians (else unused). */
 typedef struct fgs_gaussian_grads {
   float* means;
   float* log_scales;
@@ -104,6 +120,9 @@ typedef struct fgs_gaussian_grads {
   void* sh_rest;
   float* velocity;
   float* accel;
+  float* mean_t;
+  float* log_scale_t;
+  float* quats_r;
 } fgs_gaussian_grads;
 
 /* Pinhole camera of Eq. (1)-(2).  (host struct)

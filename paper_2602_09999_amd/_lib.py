@@ -24,13 +24,15 @@ FGS_SORT_NOALLOC_SCRATCH_BYTES = 17 << 19
 class Gaussians(ctypes.Structure):
     _fields_ = [("n", c_int64), ("means", c_void_p), ("log_scales", c_void_p), ("quats", c_void_p),
                 ("opacity_logits", c_void_p), ("sh_dc", c_void_p), ("sh_rest", c_void_p),
-                ("sh_dtype", c_int32), ("sh_degree", c_int32), ("velocity", c_void_p), ("accel", c_void_p)]
+                ("sh_dtype", c_int32), ("sh_degree", c_int32), ("velocity", c_void_p), ("accel", c_void_p),
+                ("mean_t", c_void_p), ("log_scale_t", c_void_p), ("quats_r", c_void_p)]
 
 
 class GaussianGrads(ctypes.Structure):
     _fields_ = [("means", c_void_p), ("log_scales", c_void_p), ("quats", c_void_p),
                 ("opacity_logits", c_void_p), ("sh_dc", c_void_p), ("sh_rest", c_void_p),
-                ("velocity", c_void_p), ("accel", c_void_p)]
+                ("velocity", c_void_p), ("accel", c_void_p), ("mean_t", c_void_p), ("log_scale_t", c_void_p),
+                ("quats_r", c_void_p)]
 
 
 class Camera(ctypes.Structure):
@@ -125,7 +127,7 @@ class FasterGSError(RuntimeError):
 
 
 # the structures above mirror include/fastergs.h at this ABI version
-ABI_VERSION = 11
+ABI_VERSION = 12
 
 
 def load(path: str = LIB_PATH) -> ctypes.CDLL:

@@ -100,10 +100,18 @@ def gaussians_struct(params: Dict[str, torch.Tensor], sh_degree: int = 3) -> L.G
         for name in ("velocity", "accel"):
             _check_tensor(params[name], name, shape=(3, n))
         g.velocity, g.accel = _ptr(params["velocity"]), _ptr(params["accel"])
+    if any(k in params for k in COND4D_NAMES):
+        for name in COND4D_NAMES:
+            _check_tensor(params[name], name, shape=(4, n) if name == "quats_r" else (n,))
+        g.mean_t, g.log_scale_t, g.quats_r = (_ptr(params[k]) for k in COND4D_NAMES)
     return g
 
 
 DYNAMIC_NAMES = ("velocity", "accel")
+# conditional 4D Gaussians (Sec. 3.4): time of the mean, temporal log-scale,
+# right-isoclinic quaternion (quats holds the left one)
+COND4D_NAMES = ("mean_t", "log_scale_t", "quats_r")
+COND4D_SHAPES = {"mean_t": 0, "log_scale_t": 0, "quats_r": 4}
 
 
 def _camera_array(cameras: Sequence) -> "ctypes.Array":
@@ -187,9 +195,10 @@ def rasterize_backward_batch(params: Dict[str, torch.Tensor], cameras: Sequence,
     _check_tensor(lasts, "lasts", dtype=torch.int32, shape=(npix,))
     shd = sh_dtype_of(params)
     gr = L.GaussianGrads()
-    names = PARAM_NAMES + (DYNAMIC_NAMES if "velocity" in params else ())
+    names = PARAM_NAMES + (DYNAMIC_NAMES if "velocity" in params else ()) + \
+        (COND4D_NAMES if "quats_r" in params else ())
     for name in names:
-        rows = PARAM_SHAPES.get(name, 3)
+        rows = PARAM_SHAPES.get(name, COND4D_SHAPES.get(name, 3))
         _check_tensor(grads[name], f"grads[{name}]", dtype=param_dtype(name, shd),
                       shape=(n,) if rows == 0 else (rows, n))
         setattr(gr, name, _ptr(grads[name]))

@@ -130,6 +130,11 @@ fgs_status check_gaussians(const fgs_gaussians* g) {
     return fail(FGS_ERR_INVALID_ARGUMENT, "a parameter pointer is NULL");
   if ((g->velocity == nullptr) != (g->accel == nullptr))
     return fail(FGS_ERR_INVALID_ARGUMENT, "velocity and accel are given together or not at all");
+  const int n4 = (g->mean_t != nullptr) + (g->log_scale_t != nullptr) + (g->quats_r != nullptr);
+  if (n4 != 0 && n4 != 3)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "mean_t, log_scale_t and quats_r are given together or not at all");
+  if (n4 == 3 && g->velocity != nullptr)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "conditional 4D Gaussians take no velocity or accel");
   return FGS_OK;
 }
 
@@ -257,6 +262,9 @@ GaussDev make_gauss(const fgs_gaussians* g) {
   d.sh_bf16 = g->sh_dtype == FGS_BF16 ? 1 : 0;
   d.velocity = g->velocity;
   d.accel = g->accel;
+  d.mean_t = g->mean_t;
+  d.log_scale_t = g->log_scale_t;
+  d.quats_r = g->quats_r;
   return d;
 }
 
@@ -326,7 +334,7 @@ fgs_status fgs_batch_workspace_layout(int64_t n, const fgs_camera* cams, int32_t
 fgs_status fgs_rasterize_forward(const fgs_gaussians* g, const fgs_camera* cam, const fgs_settings* st,
                                  void* workspace, size_t workspace_bytes, int64_t instance_capacity, float* image,
                                  float* t_final, uint32_t* last, fgs_forward_stats* stats, void* stream) {
-  if (g && (g->velocity || g->accel))
+  if (g && (g->velocity || g->accel || g->quats_r))
     return fail(FGS_ERR_INVALID_ARGUMENT, "dynamic Gaussians take fgs_rasterize_forward_batch with times");
   return fgs_rasterize_forward_batch(g, cam, nullptr, 1, st, workspace, workspace_bytes, instance_capacity, image,
                                      t_final, last, 0u, stats, stream);
@@ -510,6 +518,9 @@ static GradDev grad_dev(const fgs_gaussian_grads* grads) {
   gr.sh_rest = grads->sh_rest;
   gr.velocity = grads->velocity;
   gr.accel = grads->accel;
+  gr.mean_t = grads->mean_t;
+  gr.log_scale_t = grads->log_scale_t;
+  gr.quats_r = grads->quats_r;
   return gr;
 }
 
@@ -517,7 +528,7 @@ fgs_status fgs_rasterize_backward(const fgs_gaussians* g, const fgs_camera* cam,
                                   void* workspace, size_t workspace_bytes, int64_t instance_capacity,
                                   const float* image, const uint32_t* last, const float* dl_dimage,
                                   const fgs_gaussian_grads* grads, void* stream) {
-  if (g && (g->velocity || g->accel))
+  if (g && (g->velocity || g->accel || g->quats_r))
     return fail(FGS_ERR_INVALID_ARGUMENT, "dynamic Gaussians take fgs_rasterize_backward_batch with times");
   return fgs_rasterize_backward_batch(g, cam, nullptr, 1, st, workspace, workspace_bytes, instance_capacity, image,
                                       last, dl_dimage, grads, stream);
@@ -536,9 +547,11 @@ fgs_status fgs_rasterize_backward_batch(const fgs_gaussians* g, const fgs_camera
   if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits ||
                    !grads->sh_dc || !grads->sh_rest))
     return fail(FGS_ERR_INVALID_ARGUMENT, "a gradient pointer is NULL");
-  const bool dyn = g->velocity != nullptr;
+  const bool dyn = g->velocity != nullptr, cond4 = g->quats_r != nullptr;
   if (dyn && g->n > 0 && (!grads->velocity || !grads->accel))
     return fail(FGS_ERR_INVALID_ARGUMENT, "dynamic Gaussians need velocity and accel gradients");
+  if (cond4 && g->n > 0 && (!grads->mean_t || !grads->log_scale_t || !grads->quats_r))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "conditional 4D Gaussians need mean_t, log_scale_t and quats_r gradients");
   if (g->n == 0) return FGS_OK;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   const ViewSet vs = make_views(cams, n_views, st->tile, times);
@@ -546,7 +559,7 @@ fgs_status fgs_rasterize_backward_batch(const fgs_gaussians* g, const fgs_camera
   if (s != FGS_OK) return s;
   const GradDev gr = grad_dev(grads);
   const GaussDev gd = make_gauss(g);
-  if (n_views == 1 && !dyn) {
+  if (n_views == 1 && !dyn && !cond4) {
     FGS_TIMED("preprocess_backward", hs,
               launch_preprocess_backward(gd, vs.cam[0], at<float4>(workspace, L.rec), at<float>(workspace, L.accum),
                                          gr, hs),
@@ -577,7 +590,8 @@ fgs_status fgs_rasterize_backward_adam(const fgs_gaussians* g, const fgs_camera*
   fgs_status s = check_backward(g, cam, 1, st, workspace, workspace_bytes, instance_capacity, image, last, dl_dimage,
                                 &L);
   if (s != FGS_OK) return s;
-  if (g->velocity || g->accel) return fail(FGS_ERR_UNSUPPORTED, "the fused backward + Adam takes static Gaussians");
+  if (g->velocity || g->accel || g->quats_r)
+    return fail(FGS_ERR_UNSUPPORTED, "the fused backward + Adam takes static Gaussians");
   if (!opt) return fail(FGS_ERR_INVALID_ARGUMENT, "opt is NULL");
   s = check_adam_hyper(step, beta1, beta2, eps);
   if (s != FGS_OK) return s;

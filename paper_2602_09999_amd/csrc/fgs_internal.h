@@ -73,6 +73,11 @@ struct GaussDev {
   const float* logits;
   const void* sh_dc;
   const void* sh_rest;
+  // conditional 4D Gaussians (NULL: 3D): time of the mean, temporal
+  // log-scale, right-isoclinic quaternion [4][n] (quats is the left one)
+  const float* mean_t;
+  const float* log_scale_t;
+  const float* quats_r;
   uint32_t n;
   int32_t sh_coeffs;  // (degree + 1)^2
   int32_t sh_bf16;
@@ -87,6 +92,9 @@ struct GradDev {
   float* logits;
   void* sh_dc;  // element type of the SH parameters
   void* sh_rest;
+  float* mean_t;  // written for conditional 4D Gaussians
+  float* log_scale_t;
+  float* quats_r;
 };
 
 // bfloat16 <-> float32.  Widening is exact; narrowing rounds to nearest, ties
@@ -185,6 +193,122 @@ __device__ __forceinline__ bool tile_keep(float mx, float my, float a, float b, 
   const float inf = __builtin_huge_valf();
   const float q = fminf(out_x ? qX : inf, out_y ? qY : inf);
   return !(out_x || out_y) || q <= thr;
+}
+
+// Conditional 4D Gaussian at time t (Sec. 3.4 "Extension to Dynamic
+// Scenes").  The 4D rotation maps (x, y, z, t), read as the quaternion
+// t + xi + yj + zk, to ql v qr with both quaternions normalised: in (w, x,
+// y, z) coordinates the product L(ql) R(qr) of the left- and
+// right-multiplication matrices, then reordered to (x, y, z, t).
+// Sigma4 = M M^T with M = R diag(exp(ls4)); the conditional mean is
+// mu + Sigma_xyz,t (t - mean_t) / Sigma_tt, the covariance the Schur
+// complement Sigma_xyz,xyz - Sigma_xyz,t Sigma_t,xyz / Sigma_tt, and the
+// opacity factor exp(-(t - mean_t)^2 / (2 Sigma_tt)).
+//
+// Evaluated in a projection form: with m the time row of M (Sigma_tt =
+// |m|^2) and u = m / |m|, h = M_xyz u and e = (t - mean_t) / |m|, the mean
+// shift is h e, the factor exp(-e^2 / 2) and the covariance N N^T with
+// N = M_xyz - h u^T (M_xyz projected off u).  The Schur complement would
+// subtract two products of size |M_xyz|^2 and lose that much absolute
+// accuracy; N carries an error of order |M_xyz| only, so for a Gaussian
+// elongated along a direction that mixes space and time the conditional
+// covariance keeps about the square root of the relative error.  One
+// rounding per operation (contraction off).  S holds the covariance entries
+// 00, 01, 02, 11, 12, 22; qn is the smaller quaternion norm (the degenerate
+// guard takes both).
+struct Cond4 {
+  float mu[3];
+  float S[6];
+  float p;
+  float qn;
+};
+
+__device__ __forceinline__ void unit_quat(const float* q, float* u, float& qn) {
+#pragma clang fp contract(off)
+  qn = sqrtf(((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3]);
+  u[0] = q[0] / qn;
+  u[1] = q[1] / qn;
+  u[2] = q[2] / qn;
+  u[3] = q[3] / qn;
+}
+
+// L(a) and R(b) of quaternion products a v = L(a) v and v b = R(b) v, (w, x, y, z).
+__device__ __forceinline__ void quat_lr(const float* a, const float* b, float (&L)[4][4], float (&R)[4][4]) {
+  L[0][0] = a[0]; L[0][1] = -a[1]; L[0][2] = -a[2]; L[0][3] = -a[3];
+  L[1][0] = a[1]; L[1][1] = a[0];  L[1][2] = -a[3]; L[1][3] = a[2];
+  L[2][0] = a[2]; L[2][1] = a[3];  L[2][2] = a[0];  L[2][3] = -a[1];
+  L[3][0] = a[3]; L[3][1] = -a[2]; L[3][2] = a[1];  L[3][3] = a[0];
+  R[0][0] = b[0]; R[0][1] = -b[1]; R[0][2] = -b[2]; R[0][3] = -b[3];
+  R[1][0] = b[1]; R[1][1] = b[0];  R[1][2] = b[3];  R[1][3] = -b[2];
+  R[2][0] = b[2]; R[2][1] = -b[3]; R[2][2] = b[0];  R[2][3] = b[1];
+  R[3][0] = b[3]; R[3][1] = b[2];  R[3][2] = -b[1]; R[3][3] = b[0];
+}
+
+// 4D rotation in (x, y, z, t) order from unit quaternions a (left), b (right).
+__device__ __forceinline__ void rotation4(const float* a, const float* b, float (&R4)[4][4]) {
+#pragma clang fp contract(off)
+  float L[4][4], Rq[4][4];
+  quat_lr(a, b, L, Rq);
+  constexpr int pm[4] = {1, 2, 3, 0};  // x, y, z, t -> w, x, y, z index
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = pm[r], j = pm[c];
+      R4[r][c] = ((L[i][0] * Rq[0][j] + L[i][1] * Rq[1][j]) + L[i][2] * Rq[2][j]) + L[i][3] * Rq[3][j];
+    }
+}
+
+// Projection-form conditioning of M (rows x, y, z, t) at dt = t - mean_t:
+// h, e and the covariance entries as described above.
+__device__ __forceinline__ void condition_m(const float (&M)[4][4], float dt, float (&h)[3], float& e,
+                                            float (&S)[6]) {
+#pragma clang fp contract(off)
+  const float nt = sqrtf(((M[3][0] * M[3][0] + M[3][1] * M[3][1]) + M[3][2] * M[3][2]) + M[3][3] * M[3][3]);
+  const float inv = 1.0f / nt;
+  const float u[4] = {M[3][0] * inv, M[3][1] * inv, M[3][2] * inv, M[3][3] * inv};
+  e = dt * inv;
+  float N[3][4];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    h[r] = ((M[r][0] * u[0] + M[r][1] * u[1]) + M[r][2] * u[2]) + M[r][3] * u[3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) N[r][k] = M[r][k] - h[r] * u[k];
+  }
+  auto nn = [&](int r, int q) {
+    return ((N[r][0] * N[q][0] + N[r][1] * N[q][1]) + N[r][2] * N[q][2]) + N[r][3] * N[q][3];
+  };
+  S[0] = nn(0, 0);
+  S[1] = nn(0, 1);
+  S[2] = nn(0, 2);
+  S[3] = nn(1, 1);
+  S[4] = nn(1, 2);
+  S[5] = nn(2, 2);
+}
+
+__device__ __forceinline__ Cond4 condition4d(const float* ql, const float* qr, const float* ls4, float mean_t,
+                                             float t, float mu0, float mu1, float mu2) {
+#pragma clang fp contract(off)
+  Cond4 c;
+  float a[4], b[4], qna, qnb;
+  unit_quat(ql, a, qna);
+  unit_quat(qr, b, qnb);
+  float R4[4][4];
+  rotation4(a, b, R4);
+  const float s[4] = {expf(ls4[0]), expf(ls4[1]), expf(ls4[2]), expf(ls4[3])};
+  float M[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) M[r][k] = R4[r][k] * s[k];
+  float h[3], e;
+  condition_m(M, t - mean_t, h, e, c.S);
+  c.mu[0] = mu0 + h[0] * e;
+  c.mu[1] = mu1 + h[1] * e;
+  c.mu[2] = mu2 + h[2] * e;
+  c.p = expf(-(0.5f * (e * e)));
+  c.qn = fminf(qna, qnb);
+  return c;
 }
 
 // Decode the packed tile rectangle.

@@ -105,31 +105,50 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, ViewSet vs, S
     mu1 = (mu1 + g.velocity[n + i] * t) + g.accel[n + i] * tt;
     mu2 = (mu2 + g.velocity[2 * n + i] * t) + g.accel[2 * n + i] * tt;
   }
+  // conditional 4D Gaussians (uniform): the mean, covariance and opacity
+  // factor of the conditional 3D Gaussian at the view's time
+  const bool cond4 = g.quats_r != nullptr;
+  Cond4 c4;
+  if (cond4) {
+    const float ql[4] = {qw0, qx0, qy0, qz0};
+    const float qr[4] = {g.quats_r[i], g.quats_r[n + i], g.quats_r[2 * n + i], g.quats_r[3 * n + i]};
+    const float ls4[4] = {ls0, ls1, ls2, g.log_scale_t[i]};
+    c4 = condition4d(ql, qr, ls4, g.mean_t[i], vs.time[view], mu0, mu1, mu2);
+    mu0 = c4.mu[0];
+    mu1 = c4.mu[1];
+    mu2 = c4.mu[2];
+  }
   const float X = ((W[0] * mu0 + W[1] * mu1) + W[2] * mu2) + W[3];
   const float Yc = ((W[4] * mu0 + W[5] * mu1) + W[6] * mu2) + W[7];
   const float Z = ((W[8] * mu0 + W[9] * mu1) + W[10] * mu2) + W[11];
   if (in_range) depth_key[j] = __float_as_uint(Z);
 
   // activations: normalised quaternion, exp scales, sigmoid opacity
-  const float n2 = ((qw0 * qw0 + qx0 * qx0) + qy0 * qy0) + qz0 * qz0;
-  const float qn = sqrtf(n2);
-  const float w = qw0 / qn, x = qx0 / qn, y = qy0 / qn, z = qz0 / qn;
-  const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
-  const float wx = w * x, wy = w * y, wz = w * z;
-  const float r00 = 1.0f - 2.0f * (yy + zz), r01 = 2.0f * (xy - wz), r02 = 2.0f * (xz + wy);
-  const float r10 = 2.0f * (xy + wz), r11 = 1.0f - 2.0f * (xx + zz), r12 = 2.0f * (yz - wx);
-  const float r20 = 2.0f * (xz - wy), r21 = 2.0f * (yz + wx), r22 = 1.0f - 2.0f * (xx + yy);
-  const float s0 = expf(ls0), s1 = expf(ls1), s2 = expf(ls2);
-  const float m00 = r00 * s0, m01 = r01 * s1, m02 = r02 * s2;
-  const float m10 = r10 * s0, m11 = r11 * s1, m12 = r12 * s2;
-  const float m20 = r20 * s0, m21 = r21 * s1, m22 = r22 * s2;
-  // Sigma = M M^T
-  const float S00 = (m00 * m00 + m01 * m01) + m02 * m02;
-  const float S01 = (m00 * m10 + m01 * m11) + m02 * m12;
-  const float S02 = (m00 * m20 + m01 * m21) + m02 * m22;
-  const float S11 = (m10 * m10 + m11 * m11) + m12 * m12;
-  const float S12 = (m10 * m20 + m11 * m21) + m12 * m22;
-  const float S22 = (m20 * m20 + m21 * m21) + m22 * m22;
+  float qn, S00, S01, S02, S11, S12, S22;
+  if (cond4) {
+    qn = c4.qn;
+    S00 = c4.S[0]; S01 = c4.S[1]; S02 = c4.S[2]; S11 = c4.S[3]; S12 = c4.S[4]; S22 = c4.S[5];
+  } else {
+    const float n2 = ((qw0 * qw0 + qx0 * qx0) + qy0 * qy0) + qz0 * qz0;
+    qn = sqrtf(n2);
+    const float w = qw0 / qn, x = qx0 / qn, y = qy0 / qn, z = qz0 / qn;
+    const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
+    const float wx = w * x, wy = w * y, wz = w * z;
+    const float r00 = 1.0f - 2.0f * (yy + zz), r01 = 2.0f * (xy - wz), r02 = 2.0f * (xz + wy);
+    const float r10 = 2.0f * (xy + wz), r11 = 1.0f - 2.0f * (xx + zz), r12 = 2.0f * (yz - wx);
+    const float r20 = 2.0f * (xz - wy), r21 = 2.0f * (yz + wx), r22 = 1.0f - 2.0f * (xx + yy);
+    const float s0 = expf(ls0), s1 = expf(ls1), s2 = expf(ls2);
+    const float m00 = r00 * s0, m01 = r01 * s1, m02 = r02 * s2;
+    const float m10 = r10 * s0, m11 = r11 * s1, m12 = r12 * s2;
+    const float m20 = r20 * s0, m21 = r21 * s1, m22 = r22 * s2;
+    // Sigma = M M^T
+    S00 = (m00 * m00 + m01 * m01) + m02 * m02;
+    S01 = (m00 * m10 + m01 * m11) + m02 * m12;
+    S02 = (m00 * m20 + m01 * m21) + m02 * m22;
+    S11 = (m10 * m10 + m11 * m11) + m12 * m12;
+    S12 = (m10 * m20 + m11 * m21) + m12 * m22;
+    S22 = (m20 * m20 + m21 * m21) + m22 * m22;
+  }
 
   // Eq. (1): mean projection with the intrinsics
   const float iz = 1.0f / Z;
@@ -171,7 +190,8 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, ViewSet vs, S
     cc = h00 / deth;
     det_ok = det >= st.det_min;
   }
-  const float o = 1.0f / (1.0f + expf(-logit));
+  float o = 1.0f / (1.0f + expf(-logit));
+  if (cond4) o = o * c4.p;  // the marginal factor of the time
 
   bool ok = (qn >= st.quat_min) && (Z >= cam.near_z) && det_ok && (o > st.alpha_min);
   // opacity-aware extent: alpha reaches alpha_min out to d^T Sigma^-1 d = 2 ln(o / alpha_min)

@@ -108,17 +108,22 @@ __device__ __forceinline__ void plane_store4(void* const* base, int p, size_t n,
   }
 }
 
-// Gradient of the loss w.r.t. the 59 raw parameters of Gaussian i, from its
-// nine accumulated 2D gradients acc = dL/d(mu2D.x, mu2D.y, a, b, c, o, r, g, b).
-// Each gradient is handed to emit(p, value) as soon as it is known, with the
-// parameter index p a compile-time constant after unrolling.
-// The record of this (view, Gaussian) is rec[rj]; mu is the mean the view saw
-// (the means themselves, or mean(t) of a dynamic scene), and emit(0..2, .)
-// receives dL/dmu.
+// The part of the chain rule every covariance model shares: from the nine
+// accumulated 2D gradients acc = dL/d(mu2D.x, mu2D.y, a, b, c, o, r, g, b)
+// of Gaussian i (record rec[rj], mean mu, 3D covariance S) to dL/dmu (with
+// the colour's view-direction term), the symmetric matrix gradient dL/dS, and
+// the SH coefficients, handed to emit(11..58, value).  go = dL/d(opacity of
+// the record).
+struct SplatGrads {
+  float dmu[3];
+  float dS[3][3];
+  float go, o;
+};
+
 template <bool SHB, typename Emit>
-__device__ __forceinline__ void gaussian_grads(const GaussDev& g, const CamDev& cam, const float4* __restrict__ rec,
-                                               const float* acc, uint32_t i, size_t rj, const float* mu,
-                                               Emit&& emit) {
+__device__ __forceinline__ SplatGrads splat_grads(const GaussDev& g, const CamDev& cam, const float4* __restrict__ rec,
+                                                  const float* acc, uint32_t i, size_t rj, const float* mu,
+                                                  const float (&S)[3][3], Emit&& emit) {
 #pragma clang fp contract(on)
   const size_t n = g.n;
   const float gmx = acc[0], gmy = acc[1], ga = acc[2], gb = acc[3], gc = acc[4], go = acc[5];
@@ -134,23 +139,6 @@ __device__ __forceinline__ void gaussian_grads(const GaussDev& g, const CamDev& 
   const float X = W[0] * mu0 + W[1] * mu1 + W[2] * mu2 + W[3];
   const float Yc = W[4] * mu0 + W[5] * mu1 + W[6] * mu2 + W[7];
   const float Z = W[8] * mu0 + W[9] * mu1 + W[10] * mu2 + W[11];
-  const float qw0 = g.quats[i], qx0 = g.quats[n + i], qy0 = g.quats[2 * n + i], qz0 = g.quats[3 * n + i];
-  const float qn = sqrtf(qw0 * qw0 + qx0 * qx0 + qy0 * qy0 + qz0 * qz0);
-  const float iqn = 1.0f / qn;
-  const float w = qw0 * iqn, x = qx0 * iqn, y = qy0 * iqn, z = qz0 * iqn;
-  float R[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
-                   {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
-                   {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
-  const float s[3] = {expf(g.log_scales[i]), expf(g.log_scales[n + i]), expf(g.log_scales[2 * n + i])};
-  float M[3][3], S[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) M[a][b] = R[a][b] * s[b];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) S[a][b] = M[a][0] * M[b][0] + M[a][1] * M[b][1] + M[a][2] * M[b][2];
   const float iz = 1.0f / Z;
   const float u = X * iz, v = Yc * iz;
   const float j00 = cam.fx * iz, j11 = cam.fy * iz, j02 = -j00 * u, j12 = -j11 * v;
@@ -250,9 +238,54 @@ __device__ __forceinline__ void gaussian_grads(const GaussDev& g, const CamDev& 
     }
   }
   const float dot = ddx * gdx + ddy * gdy + ddz * gdz;
-  emit(0, dmu[0] + (gdx - ddx * dot) * il);
-  emit(1, dmu[1] + (gdy - ddy * dot) * il);
-  emit(2, dmu[2] + (gdz - ddz * dot) * il);
+  SplatGrads out;
+  out.dmu[0] = dmu[0] + (gdx - ddx * dot) * il;
+  out.dmu[1] = dmu[1] + (gdy - ddy * dot) * il;
+  out.dmu[2] = dmu[2] + (gdz - ddz * dot) * il;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) out.dS[a][b] = dS[a][b];
+  out.go = go;
+  out.o = o;
+  return out;
+
+}
+
+// Gradient of the loss w.r.t. the 59 raw parameters of a 3D Gaussian i:
+// Sigma = M M^T, M = R(q / |q|) diag(exp(log s)), opacity = sigmoid(logit).
+// Each gradient is handed to emit(p, value) as soon as it is known, with the
+// parameter index p a compile-time constant after unrolling.  mu is the mean
+// the view saw (the means themselves, or mean(t) of a dynamic scene), and
+// emit(0..2, .) receives dL/dmu.
+template <bool SHB, typename Emit>
+__device__ __forceinline__ void gaussian_grads(const GaussDev& g, const CamDev& cam, const float4* __restrict__ rec,
+                                               const float* acc, uint32_t i, size_t rj, const float* mu,
+                                               Emit&& emit) {
+#pragma clang fp contract(on)
+  const size_t n = g.n;
+  const float qw0 = g.quats[i], qx0 = g.quats[n + i], qy0 = g.quats[2 * n + i], qz0 = g.quats[3 * n + i];
+  const float qn = sqrtf(qw0 * qw0 + qx0 * qx0 + qy0 * qy0 + qz0 * qz0);
+  const float iqn = 1.0f / qn;
+  const float w = qw0 * iqn, x = qx0 * iqn, y = qy0 * iqn, z = qz0 * iqn;
+  float R[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
+                   {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
+                   {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
+  const float s[3] = {expf(g.log_scales[i]), expf(g.log_scales[n + i]), expf(g.log_scales[2 * n + i])};
+  float M[3][3], S[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) M[a][b] = R[a][b] * s[b];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) S[a][b] = M[a][0] * M[b][0] + M[a][1] * M[b][1] + M[a][2] * M[b][2];
+  const SplatGrads sg = splat_grads<SHB>(g, cam, rec, acc, i, rj, mu, S, emit);
+  emit(0, sg.dmu[0]);
+  emit(1, sg.dmu[1]);
+  emit(2, sg.dmu[2]);
+  const float(&dS)[3][3] = sg.dS;
 
   // ---- Sigma = M M^T, M = R diag(s)
   float dM[3][3];
@@ -284,7 +317,123 @@ __device__ __forceinline__ void gaussian_grads(const GaussDev& g, const CamDev& 
   emit(9, (dz - z * qdot) * iqn);
 
   // ---- opacity = sigmoid(logit)
-  emit(10, go * o * (1.f - o));
+  emit(10, sg.go * sg.o * (1.f - sg.o));
+}
+
+// Gradient of the loss w.r.t. the raw parameters of a conditional 4D
+// Gaussian i seen at time t (Sec. 3.4): planes 0..58 as for a 3D Gaussian
+// (means = the spatial mean, log_scales = the spatial log-scales, quats =
+// the left quaternion) and 59 = mean_t, 60 = log_scale_t, 61..64 = quats_r.
+// Forward: Sigma4 = M M^T, M = R4 diag(s), R4 from the two unit quaternions;
+// b = Sigma_xyz,t, c = Sigma_tt, dt = t - mean_t;
+// mean = mu + b dt / c, S = Sigma_xyz,xyz - b b^T / c, p = exp(-dt^2 / (2c)),
+// opacity = sigmoid(logit) p.  Chain (G = dL/dS, gm = dL/dmean, gp = dL/dp):
+//   dL/db = -2 G b / c + gm dt / c
+//   dL/dc = b^T G b / c^2 - (gm . b) dt / c^2 + gp p dt^2 / (2 c^2)
+//   dL/dmean_t = -(gm . b) / c + gp p dt / c
+//   dL/dSigma4: G on the spatial block, dL/db / 2 on each off-diagonal
+//   border, dL/dc in the corner; dL/dM = 2 dL/dSigma4 M
+//   R4 = L(a) R(b) (reordered): dL/dL = dP R^T, dL/dR = L^T dP.
+constexpr int kCond4Params = kParams + 6;
+
+template <bool SHB, typename Emit>
+__device__ __forceinline__ void gaussian_grads_cond4(const GaussDev& g, const CamDev& cam,
+                                                     const float4* __restrict__ rec, const float* acc, uint32_t i,
+                                                     size_t rj, float t, Emit&& emit) {
+#pragma clang fp contract(on)
+  const size_t n = g.n;
+  const float ql[4] = {g.quats[i], g.quats[n + i], g.quats[2 * n + i], g.quats[3 * n + i]};
+  const float qr[4] = {g.quats_r[i], g.quats_r[n + i], g.quats_r[2 * n + i], g.quats_r[3 * n + i]};
+  const float s[4] = {expf(g.log_scales[i]), expf(g.log_scales[n + i]), expf(g.log_scales[2 * n + i]),
+                      expf(g.log_scale_t[i])};
+  const float dt = t - g.mean_t[i];
+  const float logit = g.logits[i];
+  float a[4], b[4], qna, qnb;
+  unit_quat(ql, a, qna);
+  unit_quat(qr, b, qnb);
+  float L[4][4], Rq[4][4];
+  quat_lr(a, b, L, Rq);
+  float R4[4][4];
+  rotation4(a, b, R4);
+  float M[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) M[r][k] = R4[r][k] * s[k];
+  // the conditional Gaussian as the forward pass evaluates it
+  float h[3], e, S6[6];
+  condition_m(M, dt, h, e, S6);
+  const float mu[3] = {g.means[i] + h[0] * e, g.means[n + i] + h[1] * e, g.means[2 * n + i] + h[2] * e};
+  const float S[3][3] = {{S6[0], S6[1], S6[2]}, {S6[1], S6[3], S6[4]}, {S6[2], S6[4], S6[5]}};
+  const float p = expf(-0.5f * e * e);
+  // Sigma_xyz,t and Sigma_tt for the chain
+  auto sig = [&](int r) { return M[r][0] * M[3][0] + M[r][1] * M[3][1] + M[r][2] * M[3][2] + M[r][3] * M[3][3]; };
+  const float bv[3] = {sig(0), sig(1), sig(2)};
+  const float ic = 1.0f / sig(3);
+  const SplatGrads sg = splat_grads<SHB>(g, cam, rec, acc, i, rj, mu, S, emit);
+  const float os = 1.0f / (1.0f + expf(-logit));
+  const float gp = sg.go * os;
+  emit(10, sg.go * p * os * (1.f - os));
+  emit(0, sg.dmu[0]);
+  emit(1, sg.dmu[1]);
+  emit(2, sg.dmu[2]);
+  // ---- conditioning
+  float Gb[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) Gb[r] = sg.dS[r][0] * bv[0] + sg.dS[r][1] * bv[1] + sg.dS[r][2] * bv[2];
+  const float bGb = bv[0] * Gb[0] + bv[1] * Gb[1] + bv[2] * Gb[2];
+  const float gmb = sg.dmu[0] * bv[0] + sg.dmu[1] * bv[1] + sg.dmu[2] * bv[2];
+  const float gpp = gp * p;
+  float G4[4][4];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const float db = (-2.f * Gb[r] + sg.dmu[r] * dt) * ic;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) G4[r][q] = sg.dS[r][q];
+    G4[r][3] = 0.5f * db;
+    G4[3][r] = 0.5f * db;
+  }
+  G4[3][3] = (bGb - gmb * dt + 0.5f * gpp * dt * dt) * ic * ic;
+  emit(kParams, (-gmb + gpp * dt) * ic);  // mean_t
+  // ---- Sigma4 = M M^T, M = R4 diag(s)
+  float dM[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      dM[r][k] = 2.f * (G4[r][0] * M[0][k] + G4[r][1] * M[1][k] + G4[r][2] * M[2][k] + G4[r][3] * M[3][k]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float ds = dM[0][k] * R4[0][k] + dM[1][k] * R4[1][k] + dM[2][k] * R4[2][k] + dM[3][k] * R4[3][k];
+    emit(k < 3 ? 3 + k : kParams + 1, ds * s[k]);
+  }
+  // ---- R4 = L(a) R(b), reordered from (w, x, y, z) to (x, y, z, t)
+  constexpr int pm[4] = {1, 2, 3, 0};
+  float dP[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dP[pm[r]][pm[q]] = dM[r][q] * s[q];
+  float dL[4][4], dR[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      dL[r][q] = dP[r][0] * Rq[q][0] + dP[r][1] * Rq[q][1] + dP[r][2] * Rq[q][2] + dP[r][3] * Rq[q][3];
+      dR[r][q] = L[0][r] * dP[0][q] + L[1][r] * dP[1][q] + L[2][r] * dP[2][q] + L[3][r] * dP[3][q];
+    }
+  const float da[4] = {dL[0][0] + dL[1][1] + dL[2][2] + dL[3][3], -dL[0][1] + dL[1][0] - dL[2][3] + dL[3][2],
+                       -dL[0][2] + dL[1][3] + dL[2][0] - dL[3][1], -dL[0][3] - dL[1][2] + dL[2][1] + dL[3][0]};
+  const float db4[4] = {dR[0][0] + dR[1][1] + dR[2][2] + dR[3][3], -dR[0][1] + dR[1][0] + dR[2][3] - dR[3][2],
+                        -dR[0][2] - dR[1][3] + dR[2][0] + dR[3][1], -dR[0][3] + dR[1][2] - dR[2][1] + dR[3][0]};
+  // ---- normalisation of both quaternions
+  const float adot = a[0] * da[0] + a[1] * da[1] + a[2] * da[2] + a[3] * da[3];
+  const float bdot = b[0] * db4[0] + b[1] * db4[1] + b[2] * db4[2] + b[3] * db4[3];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    emit(6 + k, (da[k] - a[k] * adot) / qna);
+    emit(kParams + 2 + k, (db4[k] - b[k] * bdot) / qnb);
+  }
 }
 
 // The nine accumulators of Gaussians i0..i0+3 (zero past n; accum is
@@ -461,7 +610,7 @@ __global__ __launch_bounds__(kBlock) void k_touched_grads(GaussDev g, CamDev cam
 // Dynamic scenes (mean(t) = mu + v t + a t^2) also get dL/dvelocity =
 // sum_t t dL/dmean(t) and dL/daccel = sum_t t^2 dL/dmean(t).  One thread per
 // Gaussian; every gradient plane is written in full.
-template <bool SHB>
+template <bool SHB, bool C4>
 __global__ __launch_bounds__(kBlock) void k_preprocess_bwd_views(GaussDev g, ViewSet vs,
                                                                  const float4* __restrict__ rec,
                                                                  const float* __restrict__ accum, GradDev gr) {
@@ -470,9 +619,10 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd_views(GaussDev g, Vie
   if (i >= n) return;
   void* const out[6] = {gr.means, gr.log_scales, gr.quats, gr.logits, gr.sh_dc, gr.sh_rest};
   const bool dyn = g.velocity != nullptr;
-  float sum[kParams], dvel[3] = {0.f, 0.f, 0.f}, dacc[3] = {0.f, 0.f, 0.f};
+  constexpr int kSum = C4 ? kCond4Params : kParams;
+  float sum[kSum], dvel[3] = {0.f, 0.f, 0.f}, dacc[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-  for (int p = 0; p < kParams; ++p) sum[p] = 0.0f;
+  for (int p = 0; p < kSum; ++p) sum[p] = 0.0f;
   for (uint32_t v = 0; v < vs.n_views; ++v) {
     const size_t rj = (size_t)v * n + i;
     float a[9];
@@ -484,6 +634,10 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd_views(GaussDev g, Vie
     }
     if (!any) continue;
     const float t = vs.time[v], tt = t * t;
+    if (C4) {
+      gaussian_grads_cond4<SHB>(g, vs.cam[v], rec, a, i, rj, t, [&](int p, float val) { sum[p] += val; });
+      continue;
+    }
     float mu[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -500,6 +654,12 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd_views(GaussDev g, Vie
   }
 #pragma unroll
   for (int p = 0; p < kParams; ++p) plane_store<SHB>(out, p, n, i, sum[p]);
+  if (C4) {
+    gr.mean_t[i] = sum[kParams];
+    gr.log_scale_t[i] = sum[kParams + 1];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) gr.quats_r[k * n + i] = sum[kParams + 2 + k];
+  }
   if (dyn) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -513,10 +673,15 @@ hipError_t launch_preprocess_backward_views(const GaussDev& g, const ViewSet& vs
                                             const float* accum, const GradDev& gr, hipStream_t s) {
   if (g.n == 0) return hipSuccess;
   const uint32_t grid = ceil_div(g.n, kBlock);
-  if (g.sh_bf16)
-    k_preprocess_bwd_views<true><<<grid, kBlock, 0, s>>>(g, vs, rec, accum, gr);
+  const bool c4 = g.quats_r != nullptr;
+  if (g.sh_bf16 && c4)
+    k_preprocess_bwd_views<true, true><<<grid, kBlock, 0, s>>>(g, vs, rec, accum, gr);
+  else if (g.sh_bf16)
+    k_preprocess_bwd_views<true, false><<<grid, kBlock, 0, s>>>(g, vs, rec, accum, gr);
+  else if (c4)
+    k_preprocess_bwd_views<false, true><<<grid, kBlock, 0, s>>>(g, vs, rec, accum, gr);
   else
-    k_preprocess_bwd_views<false><<<grid, kBlock, 0, s>>>(g, vs, rec, accum, gr);
+    k_preprocess_bwd_views<false, false><<<grid, kBlock, 0, s>>>(g, vs, rec, accum, gr);
   return hipGetLastError();
 }
 

@@ -183,6 +183,27 @@ def make_motion(n: int, seed: int = 0, v_std: float = 0.1, a_std: float = 0.02) 
     return {"velocity": vel.to(torch.float32).contiguous(), "accel": acc.to(torch.float32).contiguous()}
 
 
+def make_cond4d(scene: Dict[str, torch.Tensor], seed: int = 0, t_range=(0.0, 1.0), log_scale_t_mean: float = -1.0,
+                log_scale_t_std: float = 0.3, mix: float = 0.3) -> Dict[str, torch.Tensor]:
+    """Extra planes of conditional 4D Gaussians for a scene: time of the mean
+    ~ U[t_range], temporal log-scale ~ N(mean, std), and a right quaternion
+    equal to the conjugate of the scene's (left) quaternion plus N(0, mix)
+    noise per component, so that space and time mix a little (a pure
+    conjugate would leave time unmixed).  float32: mean_t [n], log_scale_t
+    [n], quats_r [4][n]."""
+    n = count(scene)
+    g = torch.Generator(device="cpu")
+    g.manual_seed(int(seed) + 6_000_003)
+    f64 = torch.float64
+    lo, hi = t_range
+    mean_t = torch.rand(n, generator=g, dtype=f64) * (hi - lo) + lo
+    log_st = torch.randn(n, generator=g, dtype=f64) * log_scale_t_std + log_scale_t_mean
+    conj = scene["quats"].to(f64) * torch.tensor([1.0, -1.0, -1.0, -1.0], dtype=f64)[:, None]
+    quats_r = conj + torch.randn(4, n, generator=g, dtype=f64) * mix
+    return {"mean_t": mean_t.to(torch.float32), "log_scale_t": log_st.to(torch.float32),
+            "quats_r": quats_r.to(torch.float32).contiguous()}
+
+
 def timesteps(count: int):
     """t_k = k / (count - 1), k = 0 .. count-1 (times in [0, 1])."""
     return [k / (count - 1) if count > 1 else 0.0 for k in range(count)]
@@ -230,5 +251,5 @@ __all__ = [
     "Camera", "Workload", "WORKLOADS", "ADAM_LR", "PARAM_NAMES", "identity_camera",
     "look_at_camera", "make_scene", "workload_camera", "make_dl_dimage", "make_target",
     "uniform_sphere_cameras", "subset", "count", "bytes_per_gaussian", "scene_checksum", "make_motion",
-    "timesteps", "batch_scene", "make_adam_state",
+    "timesteps", "batch_scene", "make_adam_state", "make_cond4d",
 ]

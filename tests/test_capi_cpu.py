@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported_and_bound(lib):
     for name in names:
         assert hasattr(lib, name), name
         assert name in L.SIGNATURES, name
-    assert lib.fgs_abi_version() == 11 == L.ABI_VERSION
+    assert lib.fgs_abi_version() == 12 == L.ABI_VERSION
 
 
 def test_default_settings_match_the_paper(lib):
@@ -181,6 +181,25 @@ def test_invalid_arguments_are_rejected_without_launching(lib):
                                         None, fake, 4, ctypes.byref(stats), None)
     assert r == L.FGS_ERR_INVALID_ARGUMENT and b"mode" in lib.fgs_last_error()
     g.velocity = g.accel = None
+    # conditional 4D Gaussians: all three extra planes or none, not with velocity, batched calls only
+    g.mean_t = fake
+    r = lib.fgs_rasterize_forward_batch(ctypes.byref(g), cam1, None, 1, ctypes.byref(st), fake, 1 << 40, 0, fake,
+                                        None, fake, 0, ctypes.byref(stats), None)
+    assert r == L.FGS_ERR_INVALID_ARGUMENT and b"quats_r" in lib.fgs_last_error()
+    g.log_scale_t = g.quats_r = fake
+    r = lib.fgs_rasterize_forward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), fake, 1 << 30, 0, fake, None,
+                                  fake, ctypes.byref(stats), None)
+    assert r == L.FGS_ERR_INVALID_ARGUMENT and b"batch" in lib.fgs_last_error()
+    g.velocity = g.accel = fake
+    r = lib.fgs_rasterize_forward_batch(ctypes.byref(g), cam1, None, 1, ctypes.byref(st), fake, 1 << 40, 0, fake,
+                                        None, fake, 0, ctypes.byref(stats), None)
+    assert r == L.FGS_ERR_INVALID_ARGUMENT and b"no velocity" in lib.fgs_last_error()
+    g.velocity = g.accel = None
+    # the backward needs their gradients; the fused backward + Adam does not take them
+    r = lib.fgs_rasterize_backward_batch(ctypes.byref(g), cam1, None, 1, ctypes.byref(st), fake, 1 << 40, 0, fake,
+                                         fake, fake, ctypes.byref(gr), None)
+    assert r == L.FGS_ERR_INVALID_ARGUMENT
+    g.mean_t = g.log_scale_t = g.quats_r = None
     # fused backward + Adam: missing state, bad hyperparameters, non-finite lr
     mo = L.AdamMoments()
     r = lib.fgs_rasterize_backward_adam(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(st), fake, 1 << 30, 0, fake,

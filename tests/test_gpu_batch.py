@@ -134,6 +134,63 @@ def test_batch_matches_oracle_and_single_views(tile, views):
         assert e <= 1e-5, (name, e)
 
 
+def test_batched_workload_full_size_sampled():
+    """The 16-view workload at full size: 1.5M Gaussians around the origin, 16
+    cameras on the radius-5 sphere with seeded resolutions in 640-1920 x
+    480-1080, tile 16 (the benchmark's autotuner's choice).  On three views:
+    sampled tile lists bit-exact against the key reference off the borderline
+    band (entries of the right view, in canonical order), a 64x64 window at
+    the view centre against the FP64 oracle, and every gradient summed over
+    the three windows (the upstream gradient lives there only).  The
+    synchronisation-free forward, as the captured step runs it, gives the
+    same images bit for bit."""
+    n = 1_500_000
+    sc = S.batch_scene(n, 0)
+    cams = S.uniform_sphere_cameras(16, seed=0)
+    say("16-view workload", [(c.width, c.height) for c in cams])
+    params = to_gpu(sc)
+    br = B.BatchRasterizer(cams)
+    images, t_finals, lasts = br.forward(params)
+    images, t_finals = images.clone(), t_finals.clone()
+    imgs, tfs = br.split(images, 3), br.split(t_finals, 1)
+    keys, vals, ranges = sorted_instances(br)
+    say("  instances", len(keys), "global tiles", br.layout().total_tiles)
+    tiles_of = [((c.width + 15) // 16) * ((c.height + 15) // 16) for c in cams]
+    base = np.concatenate([[0], np.cumsum(tiles_of)])
+    rng = np.random.default_rng(4)
+    views = [0, 7, 15]
+    dls = [torch.zeros(3, c.height, c.width) for c in cams]
+    g_ref, exempt = None, []
+    for k in views:
+        cam = cams[k]
+        tx, ty = (cam.width + 15) // 16, (cam.height + 15) // 16
+        sample = sorted(set(rng.integers(0, tiles_of[k], 3).tolist()) | {(ty // 2) * tx + tx // 2})
+        lists = O.tile_lists_for(sc, cam, sample, delta=1e-3)
+        for tl in sample:
+            ref_list, band = lists[tl]
+            s0, e0 = ranges[base[k] + tl]
+            got = vals[s0:e0].astype(np.int64)
+            assert np.all(got // n == k), (k, tl)
+            got = (got % n).tolist()
+            assert [g for g in got if g not in band] == [g for g in ref_list.tolist() if g not in band], (k, tl)
+        say(f"  view {k}: tiles {sample} match ({sum(len(lists[t][0]) for t in sample)} entries)")
+        crop = (cam.width // 2 - 32, cam.height // 2 - 32, cam.width // 2 + 32, cam.height // 2 + 32)
+        x0, y0, x1, y1 = crop
+        ref = O.render64(sc, cam, crop=crop, mask_borderline=True, dl_dimage=S.make_dl_dimage(64, 64, seed=40 + k))
+        check_image(f"view {k} centre", imgs[k][:, y0:y1, x0:x1], ref, t_final=tfs[k][y0:y1, x0:x1])
+        dls[k][:, y0:y1, x0:x1] = ref["dl_used"].float()
+        g_ref = ref["grads"] if g_ref is None else {m: g_ref[m] + ref["grads"][m] for m in g_ref}
+        exempt.append(ref["clip_border"].numpy())
+    grads = br.backward(params, torch.cat([d.reshape(-1) for d in dls]).cuda())
+    torch.cuda.synchronize()
+    check_grads("16 views", grads, g_ref, exempt=np.concatenate(exempt))
+    br.ensure(n, int(br.last_stats["n_instances"] * 1.3))
+    images2, _, _ = br.forward(params, mode=L.FGS_FORWARD_NO_SYNC)
+    torch.cuda.synchronize()
+    assert int(br.counters().cpu()[7]) == 0
+    assert torch.equal(images2, images)
+
+
 def test_single_view_forward_without_synchronisation():
     sc, cam = S.make_scene(10_000, 0), S.workload_camera("c1")
     say("single-view no-sync forward")
@@ -162,9 +219,10 @@ def test_single_view_forward_without_synchronisation():
 def test_forward_without_synchronisation_skips_constant_depth_digits():
     """A scene spread over a very thin depth range: the visible depth keys
     agree in all bits from 16 up, so the synchronisation-free depth sort
-    (four passes over 31 bits) only copies in its last two passes, taking
-    the key range from the device.  Its results equal the synchronised
-    forward's, which sorts only the bits that vary."""
+    (four passes over 31 bits) skips its last two passes, taking the key
+    range from the device, and the duplication reads the sorted ids from the
+    buffer the device noted.  Its results equal the synchronised forward's,
+    which sorts only the bits that vary."""
     sc, cam = S.make_scene(8_000, 6, z_range=(3.0, 3.0005)), S.workload_camera("c1")
     say("no-sync forward, thin depth range")
     params = to_gpu(sc)
@@ -417,3 +475,82 @@ def test_dynamic_gaussians_match_oracle_and_chain_rule(case):
     bf = ("sh_dc", "sh_rest") if sh == "bf16" else ()
     check_grads(f"dynamic {case}", grads, want, names=list(want), exempt=np.concatenate(exempt), bf16_groups=bf,
                 rel_tol={k: 2.0 ** -8 for k in bf})
+
+
+COND4D = {
+    # n, timesteps, camera, comparison windows (None: whole frame)
+    "small": (3_000, 3, lambda: S.identity_camera(96, 72, 100.0, bg=(0.1, 0.2, 0.3)), None),
+    "720p": (200_000, 4, lambda: S.identity_camera(1280, 720, 1000.0), [(608, 328, 672, 392), (1076, 656, 1140, 720)]),
+}
+
+
+@pytest.mark.parametrize("case", list(COND4D))
+def test_conditional_4d_gaussians_match_oracle(case):
+    """Conditional 4D Gaussians (Sec. 3.4): every timestep is a view whose
+    Gaussians are the conditional 3D Gaussians at its time, with opacities
+    faded by the marginal factor.  Per timestep: the GPU's float32 depth keys
+    within 1e-5 relative of the oracle's float64 conditional depth; tile lists
+    against the key reference (whole frame: every list; 720p: sampled tiles)
+    in the order of the GPU's keys, exact off the borderline band; the image
+    against the FP64 oracle (rendered in that order); then every gradient,
+    including those of the time mean, the temporal log-scale and the right
+    quaternion, against the oracle's gradients summed over the timesteps."""
+    n, n_t, make_cam, windows = COND4D[case]
+    sc = S.make_scene(n, 8)
+    sc.update(S.make_cond4d(sc, 8))
+    cam = make_cam()
+    times = S.timesteps(n_t)
+    say("conditional 4D", case, n, "Gaussians", [round(t, 3) for t in times])
+    params = to_gpu(sc)
+    br = B.BatchRasterizer([cam] * n_t, times=times)
+    images, t_finals, lasts = br.forward(params)
+    imgs, tfs = br.split(images, 3), br.split(t_finals, 1)
+    keys, vals, ranges = sorted_instances(br)
+    dkeys = br.view("depth_key", n * n_t).cpu().numpy().view(np.float32).reshape(n_t, n)
+    ntl = br.view("n_tiles", n * n_t).cpu().numpy().reshape(n_t, n)
+    tiles_per_view = ranges.shape[0] // n_t
+    rng = np.random.default_rng(2)
+    rows = {k: (v.double().T.contiguous() if v.dim() == 2 else v.double()) for k, v in sc.items()}
+    dls, g_sum, exempt = [], None, []
+    for k, t in enumerate(times):
+        vis = ntl[k] != 0
+        with torch.no_grad():
+            z64 = O.preprocess64(rows, cam, time=t, sh_degree=0)["cam_pos"][:, 2].numpy()
+        rel = np.abs(dkeys[k][vis].astype(np.float64) - z64[vis]) / np.abs(z64[vis])
+        say(f"  t={t:.3f}: visible {int(vis.sum())}, depth key max rel err {rel.max():.2e}")
+        assert rel.max() <= 1e-5
+        lo = int(np.searchsorted(keys, k * tiles_per_view))
+        hi = int(np.searchsorted(keys, (k + 1) * tiles_per_view))
+        kv = vals[lo:hi].astype(np.int64)
+        assert np.all(kv // n == k)
+        view_ranges = ranges[k * tiles_per_view:(k + 1) * tiles_per_view].astype(np.int64)
+        if windows is None:
+            nom, border = O.keys_ref_banded(sc, cam, time=t, depth=dkeys[k])
+            loc_ranges = view_ranges - lo
+            loc_ranges[view_ranges[:, 1] == 0] = 0
+            flips = compare_lists(keys[lo:hi] - k * tiles_per_view, (kv % n).astype(np.uint32),
+                                  loc_ranges.astype(np.uint32), nom, border, depth=dkeys[k])
+            assert flips <= len(border)
+            crop = None
+        else:
+            sample = sorted(set(rng.integers(0, tiles_per_view, 4).tolist()) | {tiles_per_view // 2})
+            lists = O.tile_lists_for(sc, cam, sample, delta=1e-3, time=t, depth=dkeys[k])
+            for tl in sample:
+                ref_list, band = lists[tl]
+                s0, e0 = view_ranges[tl]
+                got = [int(g) % n for g in vals[s0:e0].tolist()]
+                assert [g for g in got if g not in band] == [g for g in ref_list.tolist() if g not in band], (k, tl)
+            crop = windows[k % len(windows)]
+        x0, y0, x1, y1 = crop if crop is not None else (0, 0, cam.width, cam.height)
+        ref = O.render64(sc, cam, crop=crop, time=t, order_keys=dkeys[k], mask_borderline=True,
+                         dl_dimage=S.make_dl_dimage(y1 - y0, x1 - x0, seed=50 + k))
+        check_image(f"t={t:.3f}", imgs[k][:, y0:y1, x0:x1], ref, t_final=tfs[k][y0:y1, x0:x1])
+        dl = torch.zeros(3, cam.height, cam.width)
+        dl[:, y0:y1, x0:x1] = ref["dl_used"].float()
+        dls.append(dl)
+        exempt.append(ref["clip_border"].numpy())
+        g_sum = ref["grads"] if g_sum is None else {m: g_sum[m] + ref["grads"][m] for m in g_sum}
+    grads = br.backward(params, torch.cat([d.reshape(-1) for d in dls]).cuda())
+    torch.cuda.synchronize()
+    assert set(g_sum) >= set(B.PARAM_NAMES) | set(B.COND4D_NAMES)
+    check_grads(f"conditional 4D {case}", grads, g_sum, names=list(g_sum), exempt=np.concatenate(exempt))
