@@ -52,6 +52,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-view batched step")
     ap.add_argument("--no-dynamic", action="store_true", help="skip the dynamic (4D) step")
+    ap.add_argument("--batched-tile", type=int, default=0, choices=[0, 8, 16, 32],
+                    help="tile size of the batched step (0: the autotuner's choice of tile and schedule)")
+    ap.add_argument("--batched-schedule", default="grid", choices=["grid", "queue"],
+                    help="blend schedule of the batched step with --batched-tile: one workgroup per tile, or "
+                         "persistent waves over per-XCD tile queues")
+    ap.add_argument("--form", default="step", choices=["step", "batched", "dynamic", "conditional"],
+                    help="step: the full report; otherwise time only that form and print its block "
+                         "(for kernel traces of one form)")
     ap.add_argument("--dist-steps", type=int, default=200,
                     help="steps timed one by one (events around each) for the median and p10/p90")
     ap.add_argument("--split-reps", type=int, default=3,
@@ -232,6 +240,18 @@ def bf16_ulps(got: torch.Tensor, ref: torch.Tensor):
     return {"max_bf16_ulps": float(((got.double() - rb).abs() / ulp).max())}
 
 
+def f32_ulps(got: torch.Tensor, ref: torch.Tensor):
+    """Largest distance of float32-stored values from the float32 rounding of
+    the float64 reference, in units of the reference's float32 ulp: an update
+    far smaller than the parameter is resolved only to the parameter's ulp, so
+    its relative error says little on its own."""
+    r = ref.double()
+    rf = r.float().double()
+    e = torch.floor(torch.log2(torch.clamp(r.abs(), min=1e-38)))
+    ulp = torch.pow(2.0, e - 23)
+    return float(((got.double() - rf).abs() / ulp).max())
+
+
 def unpermute(t: torch.Tensor, perm: torch.Tensor) -> torch.Tensor:
     """Gaussian axis (last) back from z-order: out[..., perm[i]] = t[..., i]."""
     out = torch.empty_like(t)
@@ -298,13 +318,15 @@ def oracle_errors(refs, scene, workload: str, dev, with_bf16: bool):
                 if pc[k].dtype == torch.bfloat16:
                     upd[k] = bf16_ulps(p_gpu, p_ref)  # stored in bfloat16: the step is rounded to it
                 else:
-                    upd[k] = err_stats(p_gpu - p0, p_ref - p0.double())  # the update of every parameter
+                    # the update of every parameter, and the stored parameter in float32 ulps
+                    upd[k] = dict(err_stats(p_gpu - p0, p_ref - p0.double()), max_f32_ulps=f32_ulps(p_gpu, p_ref))
             e["fused_adam_update"] = upd
             res[where] = e
+            ulps = [v.get("max_f32_ulps", v.get("max_bf16_ulps")) for v in upd.values()]
             log(f"oracle error {sh} {where}: image max abs {e['image']['max_abs']:.2e} "
                 f"({e['borderline_pixels_excluded']} borderline px), worst gradient max rel "
-                f"{max(v['max_rel'] for v in e['gradients'].values()):.2e}, worst update max rel "
-                f"{max(v['max_rel'] for v in upd.values() if 'max_rel' in v):.2e}")
+                f"{max(v['max_rel'] for v in e['gradients'].values()):.2e}, updated parameters within "
+                f"{max(ulps):.0f} ulp of the stored type")
         out[sh] = res
         del params, rz
         torch.cuda.empty_cache()
@@ -510,25 +532,31 @@ def time_steps(step, steps, warmup):
 def run_batched(args, dev):
     """Several views per step: 1.5M Gaussians around the origin, 16 cameras on
     the radius-5 sphere with seeded uneven resolutions (640-1920 x 480-1080,
-    f = width); tile size from the autotuner; the step timed eagerly and as a
-    captured graph replayed (synchronisation-free forward, device step count)."""
+    f = width); tile size from the autotuner (or --batched-tile); the step
+    timed eagerly and as a captured graph replayed (synchronisation-free
+    forward, device step count)."""
     import paper_2602_09999_amd as P
     from paper_2602_09999_amd import _lib as L
     from paper_2602_09999_amd import binding as B
-    from paper_2602_09999_amd.autotune import TileAutotuner
+    from paper_2602_09999_amd.autotune import Autotuner, settings_for
     scene = S.batch_scene(BATCH_N, seed=args.seed)
     cams = S.uniform_sphere_cameras(BATCH_VIEWS, seed=args.seed)
     params = {k: v.to(dev) for k, v in scene.items()}
     del scene
-    tuner = TileAutotuner(reps=2)
-    tile = tuner.choose(params, cams)
-    tile_ms = next(iter(tuner.cache.values()))["ms"]
-    st = B.default_settings(tile=tile)
+    if args.batched_tile:
+        config, tune_ms = {"tile": args.batched_tile, "schedule": args.batched_schedule}, None
+    else:
+        tuner = Autotuner(reps=2)
+        config = tuner.choose(params, cams)
+        tune_ms = next(iter(tuner.cache.values()))["ms"]
+    tile = config["tile"]
+    st = settings_for(config)
     npix = sum(B.view_pixels(cams))
     target = torch.rand(3 * npix, generator=torch.Generator().manual_seed(args.seed)).to(dev)
     dl = torch.empty(3 * npix, device=dev)
     out = {"workload": f"{BATCH_N} Gaussians, {BATCH_VIEWS} views on a radius-5 sphere, "
-                       f"{npix} pixels in all", "tile": tile, "autotune_ms_per_fwd_bwd": tile_ms}
+                       f"{npix} pixels in all", "tile": tile, "schedule": config["schedule"],
+           "autotune_ms_per_fwd_bwd": tune_ms}
     for mode_name, graph in (("eager", False), ("graph", True)):
         br = B.BatchRasterizer(cams, settings=st)
         opt = P.FusedAdam(params, S.ADAM_LR, device_step=graph)
@@ -556,7 +584,8 @@ def run_batched(args, dev):
         out[f"{mode_name}_ms_per_step"] = sec * 1e3
         out[f"{mode_name}_steps_per_s"] = 1.0 / sec
         out[f"{mode_name}_views_per_s"] = BATCH_VIEWS / sec
-        log(f"batched {mode_name}: {sec * 1e3:.2f} ms per step of {BATCH_VIEWS} views (tile {tile})")
+        log(f"batched {mode_name}: {sec * 1e3:.2f} ms per step of {BATCH_VIEWS} views (tile {tile}, "
+            f"{config['schedule']} schedule)")
         del br, opt, grads
         torch.cuda.empty_cache()
     return out
@@ -656,6 +685,11 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(2)
+    if args.form != "step":
+        dev = torch.device("cuda", 0)
+        run = {"batched": run_batched, "dynamic": run_dynamic, "conditional": run_dynamic_conditional}[args.form]
+        print(json.dumps({"form": args.form, args.form: run(args, dev)}))
+        return
     w = S.WORKLOADS[args.workload]
     log(f"workload {w.name}: {w.description}")
     scene = S.make_scene(w.n, seed=args.seed)

@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define FGS_ABI_VERSION 12
+#define FGS_ABI_VERSION 13
 
 typedef enum fgs_status {
   FGS_OK = 0,
@@ -59,6 +59,12 @@ typedef enum fgs_dtype { FGS_F32 = 0, FGS_BF16 = 1 } fgs_dtype;
  *   bounded wait runs out.  Same results, much slower; for tests of that
  *   path. */
 #define FGS_FLAG_LOOKBACK_FALLBACK 2u
+/* FGS_FLAG_BLEND_QUEUE: the blend kernels (forward and backward) run as
+ *   persistent waves, as many as the device holds at once, that take tiles
+ *   from one queue per XCD (each XCD owns a band of consecutive tiles)
+ *   instead of one workgroup per tile.  Same results; a scheduling choice
+ *   for workloads with many more tiles than the device holds waves. */
+#define FGS_FLAG_BLEND_QUEUE 4u
 
 /* The Gaussian parameters of Sec. 2.1 ("3D Gaussian Splatting"): mean mu,
  * log-scales (scale = exp, "Activation Functions"), rotation quaternion
@@ -163,6 +169,10 @@ typedef struct fgs_forward_stats {
   int64_t n_visible;    /* Gaussians with at least one tile instance        */
   int64_t n_instances;  /* (tile, Gaussian) instances I                     */
   int64_t tiles_x, tiles_y;
+  int64_t depth_key_bits; /* bits the depth sort needs: the visible depth
+                             keys are sorted as key - min key, so 32 -
+                             clz(max key - min key), 0 when all are equal
+                             (see FGS_FORWARD_DEPTH_BITS)                  */
 } fgs_forward_stats;
 
 /* Byte offsets of the workspace regions (host struct), for inspection.
@@ -179,8 +189,10 @@ typedef struct fgs_forward_stats {
  *                           visible depth key, [3] index of the ping-pong buffer
  *                           holding the depth-sorted visible ids, [4..5] the
  *                           instance count I (uint64), [6] min(I, capacity),
- *                           [7] 1 when I exceeded the capacity, [8] the
- *                           Gaussians with a gradient (fused backward)
+ *                           [7] bit 0: I exceeded the capacity, bit 1: the
+ *                           depth keys need more than FGS_FORWARD_DEPTH_BITS,
+ *                           [8] the Gaussians with a gradient (fused backward),
+ *                           [10..11] {0, max - min visible depth key}
  * With several views, the per-Gaussian regions (rec, n_tiles, depth_key,
  * vis_*, accum) hold n_views * n entries, entry v * n + i for view v.
  *   vis_ids    uint32[n] x2 ping-pong (see counters[3])
@@ -204,13 +216,15 @@ typedef struct fgs_forward_stats {
  *                           Gaussian 4k+j received a gradient
  *   touched_list uint32[n]  fused: the marked Gaussians (count in counters[8])
  *   slot_of    uint32[n]    fused: slot s of a marked Gaussian i (list[s] = i)
- *   sparse_grads float[59][n]  fused: plane p's gradient of list[s] at [p][s] */
+ *   sparse_grads float[59][n]  fused: plane p's gradient of list[s] at [p][s]
+ *   queues     uint32[256]  FGS_FLAG_BLEND_QUEUE: the eight per-XCD tile
+ *                           counters, 32 words apart */
 typedef struct fgs_layout {
   size_t rec, n_tiles, depth_key, counters;
   size_t vis_keys[2], vis_ids[2];
   size_t dup_scan;
   size_t inst_keys[2], inst_vals[2];
-  size_t ranges, accum, marks, touched, touched_list, slot_of, sparse_grads, scratch, total;
+  size_t ranges, accum, marks, touched, touched_list, slot_of, sparse_grads, queues, scratch, total;
   int32_t inst_final;
   int32_t inst_key_bytes;        /* 2 or 4: width of the inst_keys entries */
   int32_t tiles_x, tiles_y;      /* tile grid of view 0 */
@@ -423,12 +437,25 @@ fgs_status fgs_sort_pairs_noalloc(void* keys, uint32_t* vals, int64_t n, int32_t
  * mode FGS_FORWARD_NO_SYNC: the forward call never synchronises the stream,
  * so the whole step can be captured into a graph; every launch is sized by
  * the capacities and reads the counts from the workspace counters, *stats is
- * not filled (n_visible = n_instances = -1), and an instance count above the
- * capacity sets counters[7] (the image is then incomplete: grow the
- * capacity, re-capture and run again).  Without it the call behaves like
- * fgs_rasterize_forward (one synchronisation, FGS_ERR_CAPACITY). */
+ * not filled (n_visible = n_instances = depth_key_bits = -1), and an instance
+ * count above the capacity sets bit 0 of counters[7] (the image is then
+ * incomplete: grow the capacity, re-capture and run again).  Without it the
+ * call behaves like fgs_rasterize_forward (one synchronisation,
+ * FGS_ERR_CAPACITY).
+ * The depth sort orders the visible keys minus the smallest (same order and
+ * ties: keys are the bits of positive floats); the host-synchronised call
+ * sorts the bits of max - min only.
+ * mode | FGS_FORWARD_DEPTH_BITS(b), 1 <= b <= 31, only with
+ * FGS_FORWARD_NO_SYNC: max - min is taken to fit in b bits (the
+ * depth_key_bits a synchronised call reported) and the depth sort covers
+ * those (without it all 31, up to one more radix pass; trailing passes whose
+ * digit is the same in every key find that on the device and do no work, at
+ * the cost of their launches).  A wider span sets bit 1 of counters[7]: the
+ * depth order, and so the image, is then wrong; run a synchronised call,
+ * re-capture with its depth_key_bits and run again. */
 #define FGS_MAX_VIEWS 16
 #define FGS_FORWARD_NO_SYNC 1u
+#define FGS_FORWARD_DEPTH_BITS(b) ((uint32_t)(b) << 8)
 fgs_status fgs_batch_workspace_size(int64_t n, const fgs_camera* cams, int32_t n_views, const fgs_settings* st,
                                     int64_t instance_capacity, size_t* bytes);
 fgs_status fgs_batch_workspace_layout(int64_t n, const fgs_camera* cams, int32_t n_views, const fgs_settings* st,

@@ -16,7 +16,12 @@ FGS_OK, FGS_ERR_INVALID_ARGUMENT, FGS_ERR_CAPACITY, FGS_ERR_HIP, FGS_ERR_UNSUPPO
 FGS_F32, FGS_BF16 = 0, 1
 FGS_MAX_VIEWS = 16
 FGS_FORWARD_NO_SYNC = 1
-FGS_FLAG_FP64_CONIC, FGS_FLAG_LOOKBACK_FALLBACK = 1, 2
+
+
+def FGS_FORWARD_DEPTH_BITS(b: int) -> int:
+    """Mode bits: with FGS_FORWARD_NO_SYNC, sort the depth keys' low b bits only."""
+    return int(b) << 8
+FGS_FLAG_FP64_CONIC, FGS_FLAG_LOOKBACK_FALLBACK, FGS_FLAG_BLEND_QUEUE = 1, 2, 4
 FGS_SORT_NOALLOC_MAX_PAIRS = 1 << 20
 FGS_SORT_NOALLOC_SCRATCH_BYTES = 17 << 19
 
@@ -47,7 +52,8 @@ class Settings(ctypes.Structure):
 
 
 class ForwardStats(ctypes.Structure):
-    _fields_ = [("n_visible", c_int64), ("n_instances", c_int64), ("tiles_x", c_int64), ("tiles_y", c_int64)]
+    _fields_ = [("n_visible", c_int64), ("n_instances", c_int64), ("tiles_x", c_int64), ("tiles_y", c_int64),
+                ("depth_key_bits", c_int64)]
 
 
 class Layout(ctypes.Structure):
@@ -55,7 +61,8 @@ class Layout(ctypes.Structure):
                 ("counters", c_size_t), ("vis_keys", c_size_t * 2), ("vis_ids", c_size_t * 2),
                 ("dup_scan", c_size_t), ("inst_keys", c_size_t * 2), ("inst_vals", c_size_t * 2),
                 ("ranges", c_size_t), ("accum", c_size_t), ("marks", c_size_t), ("touched", c_size_t),
-                ("touched_list", c_size_t), ("slot_of", c_size_t), ("sparse_grads", c_size_t), ("scratch", c_size_t),
+                ("touched_list", c_size_t), ("slot_of", c_size_t), ("sparse_grads", c_size_t), ("queues", c_size_t),
+                ("scratch", c_size_t),
                 ("total", c_size_t),
                 ("inst_final", c_int32), ("inst_key_bytes", c_int32), ("tiles_x", c_int32), ("tiles_y", c_int32),
                 ("instance_capacity", c_int64), ("n_views", c_int64), ("total_tiles", c_int64)]
@@ -127,7 +134,7 @@ class FasterGSError(RuntimeError):
 
 
 # the structures above mirror include/fastergs.h at this ABI version
-ABI_VERSION = 12
+ABI_VERSION = 13
 
 
 def load(path: str = LIB_PATH) -> ctypes.CDLL:

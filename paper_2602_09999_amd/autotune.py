@@ -1,11 +1,16 @@
-"""Tile-size autotuner: picks 8, 16 or 32 pixel tiles for a workload by timing
-rasterizer steps, and caches the choice per (Gaussian-count bucket,
+"""Autotuner over the rasterizer's tiling and scheduling: the tile size (8, 16
+or 32 pixels) and the blend schedule (one workgroup per tile, or persistent
+waves taking tiles from per-XCD queues, FGS_FLAG_BLEND_QUEUE), chosen for a
+workload by timing rasterizer steps and cached per (Gaussian-count bucket,
 pixel-count bucket, view count).
 
 The timing runs the library's forward and backward passes (HIP events on the
-current stream); the choice only changes how the image is cut into tiles, not
-the result (every tile size gives the same image up to the float32 rounding
-of borderline fragments).
+current stream).  The search is coordinate-wise: every tile size with the
+one-workgroup-per-tile schedule, then the other schedules at the fastest
+tile size.  Neither choice changes the result: every tile size gives the
+same image up to the float32 rounding of borderline fragments, and both
+schedules run the same per-tile code (the backward's gradient sums differ
+only in the order of their float atomics).
 """
 from __future__ import annotations
 
@@ -16,28 +21,50 @@ from typing import Callable, Dict, Iterable, Optional, Sequence, Tuple
 
 import torch
 
+from . import _lib as L
 from . import binding as B
 
 CANDIDATES = (8, 16, 32)
+SCHEDULES = ("grid", "queue")
 
 
 def bucket(n: int, cameras: Sequence) -> Tuple[int, int, int]:
     """(round(log2 N), round(log2 total pixels), views): workloads in one bucket
-    share a tile size."""
+    share a configuration."""
     pixels = sum(int(c.width) * int(c.height) for c in cameras)
     return (int(round(math.log2(max(n, 1)))), int(round(math.log2(max(pixels, 1)))), len(cameras))
 
 
-class TileAutotuner:
-    """choose(params, cameras) -> tile size.  ``measure(tile) -> ms`` may be
-    given to replace the timed steps (tests); ``cache_path`` persists choices
-    as JSON."""
+def settings_for(config: Dict[str, object], base=None) -> L.Settings:
+    """Settings with the configuration's tile size and blend schedule (other
+    fields from ``base``, else the defaults)."""
+    st = B.default_settings() if base is None else base
+    st = B.default_settings(**{f: getattr(st, f) for f, _ in st._fields_})
+    st.tile = int(config["tile"])
+    if config.get("schedule", "grid") == "queue":
+        st.flags |= L.FGS_FLAG_BLEND_QUEUE
+    else:
+        st.flags &= ~L.FGS_FLAG_BLEND_QUEUE
+    return st
 
-    def __init__(self, candidates: Iterable[int] = CANDIDATES, reps: int = 3, cache_path: Optional[str] = None):
+
+class Autotuner:
+    """choose(params, cameras) -> {"tile": t, "schedule": s}.  ``measure(config)
+    -> ms`` may be given to replace the timed steps (tests); ``cache_path``
+    persists choices as JSON."""
+
+    def __init__(self, candidates: Iterable[int] = CANDIDATES, schedules: Iterable[str] = SCHEDULES, reps: int = 3,
+                 cache_path: Optional[str] = None):
         self.candidates = tuple(int(t) for t in candidates)
         for t in self.candidates:
             if t not in CANDIDATES:
                 raise ValueError(f"tile {t} not in {CANDIDATES}")
+        self.schedules = tuple(schedules)
+        for s in self.schedules:
+            if s not in SCHEDULES:
+                raise ValueError(f"schedule {s!r} not in {SCHEDULES}")
+        if "grid" not in self.schedules:
+            raise ValueError("the one-workgroup-per-tile schedule ('grid') is the search's starting point")
         self.reps = int(reps)
         self.cache_path = cache_path
         self.cache: Dict[str, Dict[str, object]] = {}
@@ -49,13 +76,14 @@ class TileAutotuner:
     def _key(k: Tuple[int, int, int]) -> str:
         return f"{k[0]}:{k[1]}:{k[2]}"
 
-    def time_steps(self, params: Dict[str, torch.Tensor], cameras: Sequence, tile: int,
+    @staticmethod
+    def _name(config: Dict[str, object]) -> str:
+        return f"{config['tile']}/{config['schedule']}"
+
+    def time_steps(self, params: Dict[str, torch.Tensor], cameras: Sequence, config: Dict[str, object],
                    times: Optional[Sequence[float]] = None, settings=None) -> float:
-        """Mean ms of a forward + backward pass over the views at this tile size."""
-        st = B.default_settings() if settings is None else settings
-        st = B.default_settings(**{f: getattr(st, f) for f, _ in st._fields_})
-        st.tile = int(tile)
-        br = B.BatchRasterizer(cameras, settings=st, times=times)
+        """Mean ms of a forward + backward pass over the views in this configuration."""
+        br = B.BatchRasterizer(cameras, settings=settings_for(config, settings), times=times)
         npix = sum(B.view_pixels(cameras))
         dl = torch.full((3 * npix,), 1e-3, device=br.device)
         grads = {k: torch.empty_like(v) for k, v in params.items()}
@@ -72,18 +100,38 @@ class TileAutotuner:
         return start.elapsed_time(stop) / self.reps
 
     def choose(self, params: Dict[str, torch.Tensor], cameras: Sequence, times: Optional[Sequence[float]] = None,
-               settings=None, measure: Optional[Callable[[int], float]] = None) -> int:
+               settings=None, measure: Optional[Callable[[Dict[str, object]], float]] = None) -> Dict[str, object]:
         n = int(params["opacity_logits"].shape[0])
         key = self._key(bucket(n, cameras))
         if key in self.cache:
-            return int(self.cache[key]["tile"])
-        timings = {}
-        for t in self.candidates:
-            timings[t] = float(measure(t) if measure is not None
-                               else self.time_steps(params, cameras, t, times, settings))
-        best = min(timings, key=lambda t: (timings[t], t))
-        self.cache[key] = {"tile": best, "ms": {str(t): v for t, v in timings.items()}}
+            c = self.cache[key]
+            return {"tile": int(c["tile"]), "schedule": str(c["schedule"])}
+        timings: Dict[str, float] = {}
+
+        def run(config):
+            ms = float(measure(config) if measure is not None
+                       else self.time_steps(params, cameras, config, times, settings))
+            timings[self._name(config)] = ms
+            return ms
+
+        # tile sizes with one workgroup per tile; equal times: the smaller tile
+        tile_ms = {t: run({"tile": t, "schedule": "grid"}) for t in self.candidates}
+        best = {"tile": min(tile_ms, key=lambda t: (tile_ms[t], t)), "schedule": "grid"}
+        best_ms = tile_ms[best["tile"]]
+        # the other schedules at that tile size (kept only when faster)
+        for s in self.schedules:
+            if s == "grid":
+                continue
+            config = {"tile": best["tile"], "schedule": s}
+            ms = run(config)
+            if ms < best_ms:
+                best, best_ms = config, ms
+        self.cache[key] = dict(best, ms=timings)
         if self.cache_path:
             with open(self.cache_path, "w") as f:
                 json.dump(self.cache, f, indent=1)
-        return best
+        return dict(best)
+
+
+# the tile-size-only name of earlier releases
+TileAutotuner = Autotuner

@@ -173,7 +173,8 @@ def rasterize_forward_batch(params: Dict[str, torch.Tensor], cameras: Sequence, 
         ctypes.byref(g), _camera_array(cameras), _times_array(times, len(cameras)), len(cameras), ctypes.byref(st),
         _ptr(workspace), workspace.numel(), int(instance_capacity), _ptr(images), _ptr(t_finals), _ptr(lasts),
         int(mode), ctypes.byref(stats), _stream_handle(stream))
-    out = {"status": int(status), "n_visible": int(stats.n_visible), "n_instances": int(stats.n_instances)}
+    out = {"status": int(status), "n_visible": int(stats.n_visible), "n_instances": int(stats.n_instances),
+           "depth_key_bits": int(stats.depth_key_bits)}
     if status == L.FGS_ERR_CAPACITY and not raise_on_capacity:
         return out
     L.check(status, "fgs_rasterize_forward_batch")
@@ -246,7 +247,7 @@ def rasterize_forward(params: Dict[str, torch.Tensor], camera, settings: Optiona
         int(instance_capacity), _ptr(image), _ptr(t_final), _ptr(last), ctypes.byref(stats),
         _stream_handle(stream))
     out = {"status": int(status), "n_visible": int(stats.n_visible), "n_instances": int(stats.n_instances),
-           "tiles_x": int(stats.tiles_x), "tiles_y": int(stats.tiles_y)}
+           "tiles_x": int(stats.tiles_x), "tiles_y": int(stats.tiles_y), "depth_key_bits": int(stats.depth_key_bits)}
     if status == L.FGS_ERR_CAPACITY and not raise_on_capacity:
         return out
     L.check(status, "fgs_rasterize_forward")
@@ -462,6 +463,13 @@ def apply_zorder(params: Dict[str, torch.Tensor], optimizer=None, *, stream=None
     return perm
 
 
+def no_sync_mode(sync_stats: Dict[str, int]) -> int:
+    """FGS_FORWARD_NO_SYNC with the depth-key bits a synchronised forward
+    reported (none when it found at most one visible key value)."""
+    bits = int(sync_stats.get("depth_key_bits", 0))
+    return L.FGS_FORWARD_NO_SYNC | (L.FGS_FORWARD_DEPTH_BITS(bits) if 1 <= bits <= 31 else 0)
+
+
 class Rasterizer:
     """Owns a workspace for one camera and grows it when the instance count
     exceeds its capacity.  forward() and backward() call the C ABI."""
@@ -494,8 +502,10 @@ class Rasterizer:
                 sync: bool = True):
         """sync=False (once a synchronised forward has sized the workspace for
         this Gaussian count): the host never waits for the GPU; launches are
-        sized by the capacity and read the counts on the device.  An instance
-        count beyond the capacity then only sets a flag, see overflowed()."""
+        sized by the capacity and read the counts on the device, and the depth
+        sort covers the key bits the synchronised forward found varying.  An
+        instance count beyond the capacity, or depth keys varying in more bits,
+        then only set a flag, see overflowed()."""
         n = int(params["opacity_logits"].shape[0])
         h, w = int(self.camera.height), int(self.camera.width)
         if image is None:
@@ -506,8 +516,8 @@ class Rasterizer:
             t_final = torch.empty(h, w, dtype=torch.float32, device=self.device)
         if not sync and self.workspace is not None and n == self.n:
             rasterize_forward_batch(params, [self.camera], None, self.settings, self.workspace, self.capacity,
-                                    image.view(-1), t_final.view(-1), last.view(-1), mode=L.FGS_FORWARD_NO_SYNC,
-                                    sh_degree=self.sh_degree, stream=stream)
+                                    image.view(-1), t_final.view(-1), last.view(-1),
+                                    mode=no_sync_mode(self.last_stats), sh_degree=self.sh_degree, stream=stream)
             return image, t_final, last
         self._ensure(n, max(self.capacity, 1024) if n == self.n else max(1024, 16 * n))
         for _ in range(3):
@@ -538,8 +548,9 @@ class Rasterizer:
                                 sh_degree=self.sh_degree, stream=stream)
 
     def overflowed(self) -> bool:
-        """Whether the last forward found more instances than the capacity (its
-        result is then incomplete); reads the device counters, so it waits for
+        """Whether the last forward found more instances than the capacity, or
+        depth keys varying above the bits it sorted (its result is then
+        incomplete or misordered); reads the device counters, so it waits for
         the GPU."""
         return bool(int(self.view("counters", 8)[7].item()))
 
@@ -605,14 +616,20 @@ class BatchRasterizer:
         return out
 
     def forward(self, params: Dict[str, torch.Tensor], *, mode: int = 0, stream=None):
+        """mode=FGS_FORWARD_NO_SYNC (once a synchronised forward has run): the
+        depth sort covers the key bits that forward found varying, unless mode
+        names its own FGS_FORWARD_DEPTH_BITS."""
         n = int(params["opacity_logits"].shape[0])
+        if mode == L.FGS_FORWARD_NO_SYNC:
+            mode = no_sync_mode(self.last_stats)
         self.ensure(n, max(self.capacity, 1024) if n == self.n else max(1024, 16 * n * len(self.cameras)))
         for _ in range(3):
             st = rasterize_forward_batch(params, self.cameras, self.times, self.settings, self.workspace,
                                          self.capacity, self.images, self.t_finals, self.lasts, mode=mode,
                                          sh_degree=self.sh_degree, stream=stream, raise_on_capacity=False)
             if st["status"] == L.FGS_OK:
-                self.last_stats = st
+                if not mode & L.FGS_FORWARD_NO_SYNC:  # the counts of a synchronised call
+                    self.last_stats = st
                 return self.images, self.t_finals, self.lasts
             self.ensure(n, int(st["n_instances"] * self.headroom) + 1024)
         raise RuntimeError("instance capacity could not be satisfied")

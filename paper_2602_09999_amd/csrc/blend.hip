@@ -40,9 +40,13 @@ __device__ __forceinline__ TileView tile_view(const ViewSet& vs, uint32_t gt) {
 }
 
 // A batch of up to 64 consecutive list entries: lane i holds entry base + i.
+// The record words are native 4-vectors: with the HIP float4 wrapper the
+// prefetched batch was kept in scratch memory (the wrapper's union defeats
+// the promotion of the struct to registers).
+typedef float rec4 __attribute__((ext_vector_type(4)));
 struct Batch {
   uint32_t gid;
-  float4 r0, r1, r2;  // splat record: {mu2D, o, -}, {a, b, c, -}, {r, g, b, flags}
+  rec4 r0, r1, r2;  // splat record: {mu2D, o, -}, {a, b, c, -}, {r, g, b, flags}
 };
 
 __device__ __forceinline__ void load_batch(const uint32_t* __restrict__ vals, const float4* __restrict__ rec,
@@ -50,9 +54,10 @@ __device__ __forceinline__ void load_batch(const uint32_t* __restrict__ vals, co
   const uint32_t j = base + (uint32_t)lane;
   if (j < end) {
     b.gid = vals[j];
-    b.r0 = rec[kRecWords * (size_t)b.gid + 0];
-    b.r1 = rec[kRecWords * (size_t)b.gid + 1];
-    b.r2 = rec[kRecWords * (size_t)b.gid + 2];
+    const rec4* r = reinterpret_cast<const rec4*>(rec) + kRecWords * (size_t)b.gid;
+    b.r0 = r[0];
+    b.r1 = r[1];
+    b.r2 = r[2];
   }
 }
 
@@ -70,9 +75,9 @@ struct BatchLds {
 constexpr float kHalfLog2e = 0.72134752044448170368f;  // log2(e) / 2
 
 __device__ __forceinline__ void stage_batch(const Batch& b, BatchLds& L, int lane) {
-  L.r0[lane] = b.r0;
-  L.r1[lane] = b.r1;
-  L.r2[lane] = b.r2;
+  L.r0[lane] = make_float4(b.r0.x, b.r0.y, b.r0.z, b.r0.w);
+  L.r1[lane] = make_float4(b.r1.x, b.r1.y, b.r1.z, b.r1.w);
+  L.r2[lane] = make_float4(b.r2.x, b.r2.y, b.r2.z, b.r2.w);
   L.q[lane] = make_float4(-kHalfLog2e * b.r1.x, -2.0f * kHalfLog2e * b.r1.y, -kHalfLog2e * b.r1.z, 0.0f);
   L.gid[lane] = b.gid;
 }
@@ -108,16 +113,14 @@ __device__ __forceinline__ float pixel_alpha(const Splat& s, float ax, float bx,
   return __builtin_amdgcn_fmed3f(s.o * G, 0.0f, alpha_max);
 }
 
-// Grid: one wave per global tile of all views.  images: the views' [3][H][W]
+// Global tile gt of all views, by one wave.  images: the views' [3][H][W]
 // blocks one after another; t_finals and lasts likewise with one plane.
 template <int TILE>
-__global__ __launch_bounds__(kWave) void k_blend_fwd(const uint2* __restrict__ ranges,
-                                                     const uint32_t* __restrict__ vals,
-                                                     const float4* __restrict__ rec, ViewSet vs, SetDev st,
-                                                     float* __restrict__ images, float* __restrict__ t_finals,
-                                                     uint32_t* __restrict__ lasts) {
+__device__ __forceinline__ void blend_fwd_tile(uint32_t gt, const uint2* __restrict__ ranges,
+                                               const uint32_t* __restrict__ vals, const float4* __restrict__ rec,
+                                               const ViewSet& vs, const SetDev& st, float* __restrict__ images,
+                                               float* __restrict__ t_finals, uint32_t* __restrict__ lasts) {
   constexpr int kRows = TileShape<TILE>::kRows, kStep = TileShape<TILE>::kStep;
-  const uint32_t gt = xcd_tile(blockIdx.x, gridDim.x);
   const TileView tv = tile_view(vs, gt);
   const CamDev& cam = vs.cam[tv.view];
   float* __restrict__ image = images + 3 * tv.pix0;
@@ -195,18 +198,86 @@ __global__ __launch_bounds__(kWave) void k_blend_fwd(const uint2* __restrict__ r
   }
 }
 
+// Tile queues (persistent waves): XCD x owns the same band of tiles as in
+// xcd_tile, and the waves running on it take the band's tiles in order from
+// counter x (one 128-byte line each, zero before the launch), so a wave that
+// finishes a short tile takes the next one instead of the hardware
+// dispatcher starting a new workgroup.  Every wave stops at the first
+// number past its band: no wave waits on another.
+__device__ __forceinline__ void xcd_band(uint32_t xcd, uint32_t nb, uint32_t& start, uint32_t& count) {
+  const uint32_t base = nb / kNumXcd, rem = nb % kNumXcd;
+  start = xcd * base + (xcd < rem ? xcd : rem);
+  count = base + (xcd < rem ? 1u : 0u);
+}
+__device__ __forceinline__ uint32_t queue_take(uint32_t* q) {
+  uint32_t t = 0;
+  if (threadIdx.x == 0) t = atomicAdd(q, 1u);
+  return (uint32_t)__shfl((int)t, 0, kWave);
+}
+
+// Grid: one wave per global tile of all views (XCD-banded order).
+template <int TILE>
+__global__ __launch_bounds__(kWave) void k_blend_fwd(const uint2* __restrict__ ranges,
+                                                     const uint32_t* __restrict__ vals,
+                                                     const float4* __restrict__ rec, ViewSet vs, SetDev st,
+                                                     float* __restrict__ images, float* __restrict__ t_finals,
+                                                     uint32_t* __restrict__ lasts) {
+  blend_fwd_tile<TILE>(xcd_tile(blockIdx.x, gridDim.x), ranges, vals, rec, vs, st, images, t_finals, lasts);
+}
+
+// Persistent waves over the tile queues (a multiple of 8 workgroups).
+template <int TILE>
+__global__ __launch_bounds__(kWave) void k_blend_fwd_queue(const uint2* __restrict__ ranges,
+                                                           const uint32_t* __restrict__ vals,
+                                                           const float4* __restrict__ rec, ViewSet vs, SetDev st,
+                                                           float* __restrict__ images, float* __restrict__ t_finals,
+                                                           uint32_t* __restrict__ lasts, uint32_t* __restrict__ queues) {
+  const uint32_t xcd = blockIdx.x % kNumXcd;
+  uint32_t start, count;
+  xcd_band(xcd, vs.tile_base[vs.n_views], start, count);
+  for (uint32_t t = queue_take(queues + kQueueStride * xcd); t < count; t = queue_take(queues + kQueueStride * xcd))
+    blend_fwd_tile<TILE>(start + t, ranges, vals, rec, vs, st, images, t_finals, lasts);
+}
+
+// Workgroups of a persistent launch of `kernel` (one wave each): as many as
+// the chip holds at once, a multiple of the XCD count, at most `tiles`
+// rounded up to it.
+template <typename K>
+static uint32_t queue_grid(K kernel, uint32_t tiles) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave, 0) != hipSuccess || cus <= 0 ||
+      per_cu <= 0)
+    return 0;
+  const uint64_t want = std::min<uint64_t>((uint64_t)cus * (uint64_t)per_cu, (uint64_t)tiles + kNumXcd - 1);
+  return (uint32_t)std::max<uint64_t>(kNumXcd, want / kNumXcd * kNumXcd);
+}
+
+template <int TILE>
+static hipError_t blend_forward_t(const uint2* ranges, const uint32_t* vals, const float4* rec, const ViewSet& vs,
+                                  const SetDev& st, float* images, float* t_finals, uint32_t* lasts,
+                                  uint32_t* queues, uint32_t tiles, hipStream_t s) {
+  if (queues == nullptr) {
+    k_blend_fwd<TILE><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, t_finals, lasts);
+    return hipGetLastError();
+  }
+  const uint32_t grid = queue_grid(k_blend_fwd_queue<TILE>, tiles);
+  if (grid == 0) return hipErrorInvalidConfiguration;
+  hipError_t e = launch_fill_u32(queues, 0u, kQueueWords, s);
+  if (e != hipSuccess) return e;
+  k_blend_fwd_queue<TILE><<<grid, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, t_finals, lasts, queues);
+  return hipGetLastError();
+}
+
 hipError_t launch_blend_forward(const uint2* ranges, const uint32_t* vals, const float4* rec, const ViewSet& vs,
                                 const SetDev& st, int tile, float* images, float* t_finals, uint32_t* lasts,
-                                hipStream_t s) {
+                                uint32_t* queues, hipStream_t s) {
   const uint32_t tiles = vs.tile_base[vs.n_views];
   if (tiles == 0) return hipSuccess;
-  if (tile == 8)
-    k_blend_fwd<8><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, t_finals, lasts);
-  else if (tile == 32)
-    k_blend_fwd<32><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, t_finals, lasts);
-  else
-    k_blend_fwd<16><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, t_finals, lasts);
-  return hipGetLastError();
+  if (tile == 8) return blend_forward_t<8>(ranges, vals, rec, vs, st, images, t_finals, lasts, queues, tiles, s);
+  if (tile == 32) return blend_forward_t<32>(ranges, vals, rec, vs, st, images, t_finals, lasts, queues, tiles, s);
+  return blend_forward_t<16>(ranges, vals, rec, vs, st, images, t_finals, lasts, queues, tiles, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -269,19 +340,16 @@ __device__ __forceinline__ float wave_reduce1(float x) {
 
 constexpr int kGrad = 9;  // dL/d(mu2D.x, mu2D.y, a, b, c, opacity, r, g, b)
 
-// accum: [n][9] with n the (view, Gaussian) index range of the record.
+// Global tile gt, by one wave.  accum: [n][9] with n the (view, Gaussian)
+// index range of the record.
 template <int TILE>
-__global__ __launch_bounds__(kWave) void k_blend_bwd(const uint2* __restrict__ ranges,
-                                                     const uint32_t* __restrict__ vals,
-                                                     const float4* __restrict__ rec, ViewSet vs, SetDev st,
-                                                     const float* __restrict__ images,
-                                                     const uint32_t* __restrict__ lasts,
-                                                     const float* __restrict__ dl_dimages,
-                                                     float* __restrict__ accum, uint8_t* __restrict__ marks,
-                                                     uint32_t* __restrict__ reset_word, uint32_t n) {
+__device__ __forceinline__ void blend_bwd_tile(uint32_t gt, const uint2* __restrict__ ranges,
+                                               const uint32_t* __restrict__ vals, const float4* __restrict__ rec,
+                                               const ViewSet& vs, const SetDev& st, const float* __restrict__ images,
+                                               const uint32_t* __restrict__ lasts,
+                                               const float* __restrict__ dl_dimages, float* __restrict__ accum,
+                                               uint8_t* __restrict__ marks) {
   constexpr int kRows = TileShape<TILE>::kRows, kStep = TileShape<TILE>::kStep;
-  if (reset_word != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *reset_word = 0u;
-  const uint32_t gt = xcd_tile(blockIdx.x, gridDim.x);
   const TileView tv = tile_view(vs, gt);
   const CamDev& cam = vs.cam[tv.view];
   const float* __restrict__ image = images + 3 * tv.pix0;
@@ -411,22 +479,74 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const uint2* __restrict__ r
   }
 }
 
+// Grid: one wave per global tile (XCD-banded order); the first workgroup
+// also zeroes *reset_word when given.
+template <int TILE>
+__global__ __launch_bounds__(kWave) void k_blend_bwd(const uint2* __restrict__ ranges,
+                                                     const uint32_t* __restrict__ vals,
+                                                     const float4* __restrict__ rec, ViewSet vs, SetDev st,
+                                                     const float* __restrict__ images,
+                                                     const uint32_t* __restrict__ lasts,
+                                                     const float* __restrict__ dl_dimages,
+                                                     float* __restrict__ accum, uint8_t* __restrict__ marks,
+                                                     uint32_t* __restrict__ reset_word) {
+  if (reset_word != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *reset_word = 0u;
+  blend_bwd_tile<TILE>(xcd_tile(blockIdx.x, gridDim.x), ranges, vals, rec, vs, st, images, lasts, dl_dimages,
+                       accum, marks);
+}
+
+// Persistent waves over the tile queues.
+template <int TILE>
+__global__ __launch_bounds__(kWave) void k_blend_bwd_queue(const uint2* __restrict__ ranges,
+                                                           const uint32_t* __restrict__ vals,
+                                                           const float4* __restrict__ rec, ViewSet vs, SetDev st,
+                                                           const float* __restrict__ images,
+                                                           const uint32_t* __restrict__ lasts,
+                                                           const float* __restrict__ dl_dimages,
+                                                           float* __restrict__ accum, uint8_t* __restrict__ marks,
+                                                           uint32_t* __restrict__ reset_word,
+                                                           uint32_t* __restrict__ queues) {
+  if (reset_word != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *reset_word = 0u;
+  const uint32_t xcd = blockIdx.x % kNumXcd;
+  uint32_t start, count;
+  xcd_band(xcd, vs.tile_base[vs.n_views], start, count);
+  for (uint32_t t = queue_take(queues + kQueueStride * xcd); t < count; t = queue_take(queues + kQueueStride * xcd))
+    blend_bwd_tile<TILE>(start + t, ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, marks);
+}
+
+template <int TILE>
+static hipError_t blend_backward_t(const uint2* ranges, const uint32_t* vals, const float4* rec, const ViewSet& vs,
+                                   const SetDev& st, const float* images, const uint32_t* lasts,
+                                   const float* dl_dimages, float* accum, uint8_t* marks, uint32_t* reset_word,
+                                   uint32_t* queues, uint32_t tiles, hipStream_t s) {
+  if (queues == nullptr) {
+    k_blend_bwd<TILE><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, marks,
+                                              reset_word);
+    return hipGetLastError();
+  }
+  const uint32_t grid = queue_grid(k_blend_bwd_queue<TILE>, tiles);
+  if (grid == 0) return hipErrorInvalidConfiguration;
+  hipError_t e = launch_fill_u32(queues, 0u, kQueueWords, s);
+  if (e != hipSuccess) return e;
+  k_blend_bwd_queue<TILE><<<grid, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum,
+                                                 marks, reset_word, queues);
+  return hipGetLastError();
+}
+
 hipError_t launch_blend_backward(const uint2* ranges, const uint32_t* vals, const float4* rec, const ViewSet& vs,
                                  const SetDev& st, int tile, const float* images, const uint32_t* lasts,
                                  const float* dl_dimages, float* accum, uint8_t* marks, uint32_t* reset_word,
-                                 uint32_t n, hipStream_t s) {
+                                 uint32_t n, uint32_t* queues, hipStream_t s) {
   const uint32_t tiles = vs.tile_base[vs.n_views];
   if (tiles == 0 || n == 0) return hipSuccess;
   if (tile == 8)
-    k_blend_bwd<8><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, marks,
-                                                     reset_word, n);
-  else if (tile == 32)
-    k_blend_bwd<32><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, marks,
-                                                     reset_word, n);
-  else
-    k_blend_bwd<16><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, marks,
-                                                     reset_word, n);
-  return hipGetLastError();
+    return blend_backward_t<8>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, marks, reset_word,
+                               queues, tiles, s);
+  if (tile == 32)
+    return blend_backward_t<32>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, marks, reset_word,
+                                queues, tiles, s);
+  return blend_backward_t<16>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, marks, reset_word, queues,
+                              tiles, s);
 }
 
 }  // namespace fgs

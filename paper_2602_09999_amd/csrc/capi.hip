@@ -104,7 +104,7 @@ fgs_status check_settings(const fgs_settings* st) {
   if (!st) return fail(FGS_ERR_INVALID_ARGUMENT, "settings is NULL");
   if (st->tile != 8 && st->tile != 16 && st->tile != 32)
     return fail(FGS_ERR_INVALID_ARGUMENT, "tile must be 8, 16 or 32 (got %d)", st->tile);
-  if (st->flags & ~(uint32_t)(FGS_FLAG_FP64_CONIC | FGS_FLAG_LOOKBACK_FALLBACK))
+  if (st->flags & ~(uint32_t)(FGS_FLAG_FP64_CONIC | FGS_FLAG_LOOKBACK_FALLBACK | FGS_FLAG_BLEND_QUEUE))
     return fail(FGS_ERR_INVALID_ARGUMENT, "unknown bits in settings.flags 0x%x", st->flags);
   // alpha_max < 1: the backward divides by 1 - alpha (App. B.1's front-to-back
   // gradient), which the cap keeps at least 1 - alpha_max away from zero
@@ -192,6 +192,7 @@ fgs_status make_layout(int64_t n, const fgs_camera* cams, int32_t n_views, const
   L->touched_list = take(un * 4);
   L->slot_of = take(un * 4);
   L->sparse_grads = take(un * 59 * 4);
+  L->queues = take(kQueueWords * 4);
   size_t words = radix_scratch_words(vn);
   words = std::max(words, radix_scratch_words(uc));
   words = std::max(words, stats_scratch_words((uint32_t)((size_t)n_views * ((un + kBlock - 1) / kBlock))));
@@ -273,6 +274,11 @@ T* at(void* base, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(base) + off);
 }
 
+// The blend's tile queues when the settings ask for them, else NULL.
+uint32_t* blend_queues(const fgs_settings* st, void* workspace, const fgs_layout& L) {
+  return (st->flags & FGS_FLAG_BLEND_QUEUE) ? at<uint32_t>(workspace, L.queues) : nullptr;
+}
+
 }  // namespace
 
 extern "C" {
@@ -350,8 +356,13 @@ fgs_status fgs_rasterize_forward_batch(const fgs_gaussians* g, const fgs_camera*
   fgs_layout L;
   s = make_layout(g->n, cams, n_views, st, instance_capacity, &L);
   if (s != FGS_OK) return s;
-  if (mode & ~(uint32_t)FGS_FORWARD_NO_SYNC) return fail(FGS_ERR_INVALID_ARGUMENT, "unknown mode bits 0x%x", mode);
+  if (mode & ~(uint32_t)(FGS_FORWARD_NO_SYNC | FGS_FORWARD_DEPTH_BITS(0x3f)))
+    return fail(FGS_ERR_INVALID_ARGUMENT, "unknown mode bits 0x%x", mode);
   const bool no_sync = (mode & FGS_FORWARD_NO_SYNC) != 0;
+  const int depth_hint = (int)((mode >> 8) & 0x3fu);
+  if (depth_hint > 31) return fail(FGS_ERR_INVALID_ARGUMENT, "FGS_FORWARD_DEPTH_BITS(%d) not in 1..31", depth_hint);
+  if (depth_hint && !no_sync)
+    return fail(FGS_ERR_INVALID_ARGUMENT, "FGS_FORWARD_DEPTH_BITS goes with FGS_FORWARD_NO_SYNC");
   if (!workspace) return fail(FGS_ERR_INVALID_ARGUMENT, "workspace is NULL");
   if (workspace_bytes < L.total)
     return fail(FGS_ERR_INVALID_ARGUMENT, "workspace holds %zu bytes, %zu needed", workspace_bytes, L.total);
@@ -391,7 +402,11 @@ fgs_status fgs_rasterize_forward_batch(const fgs_gaussians* g, const fgs_camera*
     uint4* partials = reinterpret_cast<uint4*>(scratch);  // free until the compaction scan
     FGS_TIMED("preprocess", hs, launch_preprocess(gd, vs, sd, st->tile, rec, n_tiles, depth_key, partials, hs),
               "preprocess");
-    FGS_HIP(launch_stats(partials, (uint32_t)n_views * ceil_div(n, kBlock), (uint64_t)cap, counters, hs), "stats");
+    // without a host synchronisation the depth sort covers the hinted bits
+    // (all 31 without a hint); keys differing above them are flagged
+    FGS_HIP(launch_stats(partials, (uint32_t)n_views * ceil_div(n, kBlock), (uint64_t)cap,
+                         no_sync ? (depth_hint ? depth_hint : 31) : 32, counters, hs),
+            "stats");
     if (!no_sync) {
       FGS_HIP(hipMemcpyAsync(stats_host, counters, sizeof(stats_host), hipMemcpyDeviceToHost, hs), "stats copy");
       FGS_HIP(hipStreamSynchronize(hs), "stats sync");
@@ -401,17 +416,18 @@ fgs_status fgs_rasterize_forward_batch(const fgs_gaussians* g, const fgs_camera*
   }
   uint32_t nvis = vn;  // capacity of the visible list
   uint64_t inst64 = cap;
-  int depth_bits = 31;  // z > 0: the sign bit of every key is 0
+  int depth_bits = depth_hint ? depth_hint : 31;  // z > 0: the sign bit of every key is 0
   if (!no_sync) {
     nvis = stats_host[kStatVisible];
     std::memcpy(&inst64, stats_host + kStatInstances, sizeof(inst64));
-    const uint32_t diff = stats_host[kStatKeyMin] ^ stats_host[kStatKeyMax];
-    depth_bits = diff ? 32 - __builtin_clz(diff) : 0;
+    const uint32_t span = stats_host[kStatKeyMax] - stats_host[kStatKeyMin];  // of the offset keys
+    depth_bits = span ? 32 - __builtin_clz(span) : 0;
     if (stats) {
       stats->n_visible = nvis;
       stats->n_instances = (int64_t)inst64;
       stats->tiles_x = L.tiles_x;
       stats->tiles_y = L.tiles_y;
+      stats->depth_key_bits = nvis > 0 ? depth_bits : 0;
     }
     if (inst64 > (uint64_t)instance_capacity)
       return fail(FGS_ERR_CAPACITY, "%llu instances exceed the capacity of %lld", (unsigned long long)inst64,
@@ -421,6 +437,7 @@ fgs_status fgs_rasterize_forward_batch(const fgs_gaussians* g, const fgs_camera*
     stats->n_instances = -1;
     stats->tiles_x = L.tiles_x;
     stats->tiles_y = L.tiles_y;
+    stats->depth_key_bits = -1;
   }
   const uint32_t* d_vis = counters + kStatVisible;
   const uint32_t* d_sorted = no_sync ? counters + kStatSortCount : nullptr;
@@ -430,18 +447,23 @@ fgs_status fgs_rasterize_forward_batch(const fgs_gaussians* g, const fgs_camera*
   if (nvis > 0) {
     // visible compaction (block offsets from the statistics, index order kept) and the depth
     // sort over the key bits that vary among the visible entries
+    // (the compacted keys are offset by the smallest visible key: they span [0, max - min])
+    // (and the compaction clears the look-back words and the tile ranges)
     FGS_HIP(launch_compact_visible(n_tiles, depth_key, n, (uint32_t)n_views, reinterpret_cast<uint4*>(scratch),
-                                   vis_keys[0], vis_ids[0], dup_scan, dup_scan_words(vn), hs),
+                                   counters + kStatKeyMin, vis_keys[0], vis_ids[0], dup_scan, dup_scan_words(vn),
+                                   reinterpret_cast<uint32_t*>(ranges), (size_t)tiles * 2, hs),
             "compact");
-    // with the device's key range, trailing passes whose digit every visible key shares are
+    // with the device's key span, trailing passes whose digit every visible key shares are
     // skipped, and the buffer holding the sorted ids is noted in counters[kStatDepthBuf]
     // (0, set by the statistics, when no pass runs)
     FGS_HIP(radix_sort_pairs(vis_keys, vis_ids, nvis, no_sync ? d_vis : nullptr, 0, depth_bits, scratch, &vis_final,
-                             hs, counters + kStatKeyMin, false, counters + kStatDepthBuf),
+                             hs, counters + kStatKeySpan, false, counters + kStatDepthBuf),
             "depth sort");
   }
 
-  FGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, (uint64_t)tiles * 2, hs), "ranges clear");
+  if (nvis == 0) {  // no compaction ran to clear the tile ranges
+    FGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, (uint64_t)tiles * 2, hs), "ranges clear");
+  }
   if (inst > 0 && nvis > 0) {
     const uint32_t* depth_ids[2] = {vis_ids[0], vis_ids[1]};
     FGS_TIMED("duplicate", hs,
@@ -464,7 +486,8 @@ fgs_status fgs_rasterize_forward_batch(const fgs_gaussians* g, const fgs_camera*
     FGS_HIP(launch_tile_ranges(ikeys[inst_final], key_bytes, inst, d_sorted, tiles, ranges, hs), "tile ranges");
   }
   FGS_TIMED("blend_forward", hs,
-            launch_blend_forward(ranges, ivals[L.inst_final], rec, vs, sd, st->tile, images, t_finals, lasts, hs),
+            launch_blend_forward(ranges, ivals[L.inst_final], rec, vs, sd, st->tile, images, t_finals, lasts,
+                                 blend_queues(st, workspace, L), hs),
             "blend");
   return FGS_OK;
 }
@@ -503,7 +526,7 @@ static fgs_status blend_backward(const fgs_gaussians* g, const ViewSet& vs, cons
   FGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(accum), 0u, clear_words, hs), "accum clear");
   FGS_TIMED("blend_backward", hs,
             launch_blend_backward(ranges, ivals, rec, vs, sd, st->tile, images, lasts, dl_dimages, accum, marks,
-                                  reset_word, vn, hs),
+                                  reset_word, vn, blend_queues(st, workspace, L), hs),
             "blend bwd");
   return FGS_OK;
 }

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <stdint.h>
 
 #include "../../include/fastergs.h"
@@ -553,6 +554,7 @@ constexpr int kStatInstances = 4;  // instance count I, uint64 at words 4-5
 constexpr int kStatSortCount = 6;  // min(I, instance capacity): instances written and sorted
 constexpr int kStatOverflow = 7;   // 1 when I exceeds the instance capacity
 constexpr int kStatTouched = 8;    // fused backward: Gaussians that received a gradient
+constexpr int kStatKeySpan = 10;   // {0, max - min key}: the range of the compacted depth keys (words 10-11)
 // Z-order: scratch bytes for n Gaussians; perm[k] = index of the Gaussian at
 // position k of the Morton order of the means [3][n]; gather of `planes`
 // planes of n elements of 2 or 4 bytes: dst[p][k] = src[p][perm[k]].
@@ -560,20 +562,25 @@ size_t zorder_scratch_bytes(uint64_t n);
 hipError_t launch_zorder(const float* means, uint32_t n, void* scratch, uint32_t* perm, hipStream_t s);
 hipError_t launch_permute(const void* src, void* dst, uint32_t n, int planes, int elem_bytes,
                           const uint32_t* perm, hipStream_t s);
-// Reduces the preprocess partials of nb blocks into the counter words,
-// including min(I, cap) and the overflow flag.
 // Reduces the preprocess's per-block partials {visible, instances, key min,
-// key max} into the counters and replaces each block's visible count by its
-// exclusive prefix (the block's first compacted position).
+// key max} into the counters, including min(I, cap), the span {0, max key -
+// min key} of the compacted (offset) depth keys and the overflow flags (bit
+// 0: I > cap; bit 1: the span needs more than depth_bits bits, never set for
+// depth_bits = 32), and replaces each block's visible count by its exclusive
+// prefix (the block's first compacted position).
 // partials sits at the start of a scratch of stats_scratch_words(nb) words.
-hipError_t launch_stats(uint4* partials, uint32_t nb, uint64_t cap, uint32_t* counters, hipStream_t s);
+hipError_t launch_stats(uint4* partials, uint32_t nb, uint64_t cap, int depth_bits, uint32_t* counters,
+                        hipStream_t s);
 size_t stats_scratch_words(uint32_t nb);
 // n: Gaussians per view; entries j = v n + i of n_views views; partials as
-// left by launch_stats (nb = n_views * ceil(n / 256)).  Also zeroes
-// clear[0 .. clear_words) (the duplication's look-back words).
+// left by launch_stats (nb = n_views * ceil(n / 256)).  The compacted keys
+// are the depth keys minus *key_min (device: the smallest visible key).
+// Also zeroes clear[0 .. clear_words) and clear2[0 .. clear2_words) (the
+// duplication's look-back words and the tile ranges).
 hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth_key, uint32_t n, uint32_t n_views,
-                                  uint4* partials, uint32_t* vis_keys, uint32_t* vis_ids, uint32_t* clear,
-                                  size_t clear_words, hipStream_t s);
+                                  uint4* partials, const uint32_t* key_min, uint32_t* vis_keys, uint32_t* vis_ids,
+                                  uint32_t* clear, size_t clear_words, uint32_t* clear2, size_t clear2_words,
+                                  hipStream_t s);
 // Tile keys are written as uint16 (key_bytes 2: every global tile id and the
 // out-of-range id `tiles` fit) or uint32 (key_bytes 4).  Each visible entry's
 // first slot is found by the kernel (decoupled look-back over its workgroups
@@ -590,18 +597,25 @@ hipError_t launch_duplicate(const uint32_t* const vis_ids[2], const uint32_t* wh
 // Ranges of the first min(*d_count, n) (or n) sorted keys.
 hipError_t launch_tile_ranges(const void* keys, int key_bytes, uint32_t n, const uint32_t* d_count, uint32_t tiles,
                               uint2* ranges, hipStream_t s);
+// Tile queues of the persistent blend: one counter per XCD, kQueueStride
+// words (128 bytes) apart, in a region of kQueueWords words.
+constexpr uint32_t kQueueStride = 32;
+constexpr uint32_t kQueueWords = kQueueStride * kNumXcd;
 // One wave per global tile of all views (tile size 8, 16 or 32); images,
-// t_finals, lasts and dl_dimages hold the views one after another.
+// t_finals, lasts and dl_dimages hold the views one after another.  queues
+// (kQueueWords device words, or NULL): persistent waves take the tiles from
+// per-XCD queues instead of one workgroup per tile (the launch zeroes them).
 hipError_t launch_blend_forward(const uint2* ranges, const uint32_t* vals, const float4* rec, const ViewSet& vs,
                                 const SetDev& st, int tile, float* images, float* t_finals, uint32_t* lasts,
-                                hipStream_t s);
+                                uint32_t* queues, hipStream_t s);
 // Adds each fragment's nine gradient sums to its entry's accumulator row and
 // sets the entry's byte in `marks` when it adds a nonzero value; accum and
-// marks start at zero.  reset_word (optional) is set to 0 by the launch.
+// marks start at zero.  reset_word (optional) is set to 0 by the launch;
+// queues as in the forward.
 hipError_t launch_blend_backward(const uint2* ranges, const uint32_t* vals, const float4* rec, const ViewSet& vs,
                                  const SetDev& st, int tile, const float* images, const uint32_t* lasts,
                                  const float* dl_dimages, float* accum, uint8_t* marks, uint32_t* reset_word,
-                                 uint32_t n, hipStream_t s);
+                                 uint32_t n, uint32_t* queues, hipStream_t s);
 hipError_t launch_preprocess_backward(const GaussDev& g, const CamDev& cam, const float4* rec, const float* accum,
                                       const GradDev& gr, hipStream_t s);
 // Several views / timesteps: gradients summed over the views (accum is

@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_stats_group(uint4* __restrict__ part
 }
 
 __global__ __launch_bounds__(kBlock) void k_stats_final(const StatsGroup* __restrict__ groups, uint32_t ng,
-                                                        uint64_t cap, uint32_t* __restrict__ c,
+                                                        uint64_t cap, int depth_bits, uint32_t* __restrict__ c,
                                                         uint32_t* __restrict__ group_start) {
   __shared__ uint32_t s_lds[kBlock / kWave];
   __shared__ uint32_t s_min[kBlock / kWave], s_max[kBlock / kWave];
@@ -361,7 +361,12 @@ __global__ __launch_bounds__(kBlock) void k_stats_final(const StatsGroup* __rest
     c[kStatDepthBuf] = 0u;
     reinterpret_cast<unsigned long long*>(c + kStatInstances)[0] = sum;
     c[kStatSortCount] = (uint32_t)(sum < cap ? sum : cap);
-    c[kStatOverflow] = sum > cap ? 1u : 0u;
+    // the compacted keys are offset by the smallest: they span [0, kmax - kmin]
+    const uint32_t span = carry > 0 ? kmax - kmin : 0u;
+    c[kStatKeySpan] = 0u;
+    c[kStatKeySpan + 1] = span;
+    const bool depth_over = depth_bits < 32 && (span >> depth_bits) != 0u;
+    c[kStatOverflow] = (sum > cap ? 1u : 0u) | (depth_over ? 2u : 0u);
   }
 }
 
@@ -379,33 +384,41 @@ static uint32_t* stats_group_start(uint4* partials, uint32_t nb) {
   return reinterpret_cast<uint32_t*>(partials) + 4 * (size_t)nb + round_up64(sizeof(StatsGroup) / 4 * ng);
 }
 
-hipError_t launch_stats(uint4* partials, uint32_t nb, uint64_t cap, uint32_t* counters, hipStream_t s) {
+hipError_t launch_stats(uint4* partials, uint32_t nb, uint64_t cap, int depth_bits, uint32_t* counters,
+                        hipStream_t s) {
   const uint32_t ng = ceil_div(nb, kBlock);
   k_stats_group<<<ng, kBlock, 0, s>>>(partials, nb, stats_groups(partials, nb));
-  k_stats_final<<<1, kBlock, 0, s>>>(stats_groups(partials, nb), ng, cap, counters,
+  k_stats_final<<<1, kBlock, 0, s>>>(stats_groups(partials, nb), ng, cap, depth_bits, counters,
                                      stats_group_start(partials, nb));
   return hipGetLastError();
 }
 
-// Writes (depth key, entry index) of every entry with at least one instance,
-// in index order (which the stable depth sort turns into the (depth, index)
-// tie-break).  Same grid as the preprocess: block (b, v), preprocess block
-// q = v * gridDim.x + b, takes entries v n + [256 b, 256 b + 256), starts at
-// its group's start plus its prefix within the group, and ranks its visible
+// Writes (depth key - smallest visible key, entry index) of every entry with
+// at least one instance, in index order (which the stable depth sort turns
+// into the (depth, index) tie-break).  The keys are the bits of positive
+// floats, which order like the floats, so subtracting the smallest keeps the
+// order and the ties, and leaves keys in [0, max - min]: depths crossing a
+// power of two differ in exponent bits up to bit 30, but rarely in more than
+// 24 bits of offset, which the sort then takes in three passes instead of
+// four.  Same grid as the preprocess: block (b, v), preprocess block q = v *
+// gridDim.x + b, takes entries v n + [256 b, 256 b + 256), starts at its
+// group's start plus its prefix within the group, and ranks its visible
 // entries with ballots.
 __global__ __launch_bounds__(kBlock) void k_compact(const uint32_t* __restrict__ n_tiles,
                                                     const uint32_t* __restrict__ depth_key, uint32_t n,
                                                     const uint4* __restrict__ partials,
                                                     const uint32_t* __restrict__ group_start,
+                                                    const uint32_t* __restrict__ key_min,
                                                     uint32_t* __restrict__ vis_keys,
                                                     uint32_t* __restrict__ vis_ids,
-                                                    uint32_t* __restrict__ clear, size_t clear_words) {
+                                                    uint32_t* __restrict__ clear, size_t clear_words,
+                                                    uint32_t* __restrict__ clear2, size_t clear2_words) {
   __shared__ uint32_t s_w[kBlock / kWave];
-  {  // also clears the duplication's look-back words (and flag) for this forward
+  {  // also clears the duplication's look-back words (and flag) and the tile ranges for this forward
     const size_t nthreads = (size_t)gridDim.x * gridDim.y * kBlock;
-    for (size_t w = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * kBlock + threadIdx.x; w < clear_words;
-         w += nthreads)
-      clear[w] = 0u;
+    const size_t t0 = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * kBlock + threadIdx.x;
+    for (size_t w = t0; w < clear_words; w += nthreads) clear[w] = 0u;
+    for (size_t w = t0; w < clear2_words; w += nthreads) clear2[w] = 0u;
   }
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
   const size_t j = (size_t)blockIdx.y * n + i;
@@ -421,19 +434,20 @@ __global__ __launch_bounds__(kBlock) void k_compact(const uint32_t* __restrict__
   if (vis) {
     const size_t q = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
     const uint32_t p = group_start[q / kBlock] + partials[q].x + pre + below;
-    vis_keys[p] = depth_key[j];
+    vis_keys[p] = depth_key[j] - *key_min;
     vis_ids[p] = (uint32_t)j;
   }
 }
 
 hipError_t launch_compact_visible(const uint32_t* n_tiles, const uint32_t* depth_key, uint32_t n, uint32_t n_views,
-                                  uint4* partials, uint32_t* vis_keys, uint32_t* vis_ids, uint32_t* clear,
-                                  size_t clear_words, hipStream_t s) {
+                                  uint4* partials, const uint32_t* key_min, uint32_t* vis_keys, uint32_t* vis_ids,
+                                  uint32_t* clear, size_t clear_words, uint32_t* clear2, size_t clear2_words,
+                                  hipStream_t s) {
   if (n == 0 || n_views == 0) return hipSuccess;
   const dim3 grid(ceil_div(n, kBlock), n_views);
   const uint32_t nb = grid.x * n_views;
-  k_compact<<<grid, kBlock, 0, s>>>(n_tiles, depth_key, n, partials, stats_group_start(partials, nb), vis_keys,
-                                    vis_ids, clear, clear_words);
+  k_compact<<<grid, kBlock, 0, s>>>(n_tiles, depth_key, n, partials, stats_group_start(partials, nb), key_min,
+                                    vis_keys, vis_ids, clear, clear_words, clear2, clear2_words);
   return hipGetLastError();
 }
 

@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported_and_bound(lib):
     for name in names:
         assert hasattr(lib, name), name
         assert name in L.SIGNATURES, name
-    assert lib.fgs_abi_version() == 12 == L.ABI_VERSION
+    assert lib.fgs_abi_version() == 13 == L.ABI_VERSION
 
 
 def test_default_settings_match_the_paper(lib):
@@ -66,11 +66,11 @@ def test_workspace_size_and_layout(lib):
     lay = B.workspace_layout(10_000, cam, instance_capacity=100_000)
     offs = [lay.rec, lay.n_tiles, lay.depth_key, lay.counters, lay.vis_keys[0], lay.vis_ids[0],
             lay.dup_scan, lay.inst_keys[0], lay.inst_vals[0], lay.ranges, lay.accum, lay.marks, lay.touched,
-            lay.touched_list, lay.slot_of, lay.sparse_grads, lay.scratch]
+            lay.touched_list, lay.slot_of, lay.sparse_grads, lay.queues, lay.scratch]
     assert lay.marks - lay.accum >= 9 * 4 * 10_000 and lay.touched - lay.marks >= 10_000
     assert lay.touched_list - lay.touched >= (10_000 + 3) // 4
     assert lay.slot_of - lay.touched_list >= 4 * 10_000 and lay.sparse_grads - lay.slot_of >= 4 * 10_000
-    assert lay.scratch - lay.sparse_grads >= 59 * 4 * 10_000
+    assert lay.queues - lay.sparse_grads >= 59 * 4 * 10_000 and lay.scratch - lay.queues >= 1024
     assert all(o % 256 == 0 for o in offs)
     assert lay.total == a and lay.tiles_x == 16 and lay.tiles_y == 16
     assert lay.inst_final == 1  # 256 tiles -> 8 key bits -> one radix pass
@@ -114,7 +114,7 @@ def test_invalid_arguments_are_rejected_without_launching(lib):
     assert size.value > 3 * one.value // 2
     st7 = B.default_settings(tile=7)
     assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(st7), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
-    stf = B.default_settings(flags=4)  # only bits 0 and 1 are defined
+    stf = B.default_settings(flags=8)  # only bits 0, 1 and 2 are defined
     assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(stf), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
     for flags in (L.FGS_FLAG_FP64_CONIC, L.FGS_FLAG_LOOKBACK_FALLBACK, 3):
         st1 = B.default_settings(flags=flags)
@@ -180,6 +180,13 @@ def test_invalid_arguments_are_rejected_without_launching(lib):
     r = lib.fgs_rasterize_forward_batch(ctypes.byref(g), cams2, None, 2, ctypes.byref(st), fake, 1 << 40, 0, fake,
                                         None, fake, 4, ctypes.byref(stats), None)
     assert r == L.FGS_ERR_INVALID_ARGUMENT and b"mode" in lib.fgs_last_error()
+    # depth-bit hints: 1..31, only without synchronisation
+    for mode, msg in ((L.FGS_FORWARD_DEPTH_BITS(20), b"NO_SYNC"),
+                      (L.FGS_FORWARD_NO_SYNC | L.FGS_FORWARD_DEPTH_BITS(32), b"1..31"),
+                      (L.FGS_FORWARD_NO_SYNC | L.FGS_FORWARD_DEPTH_BITS(64), b"mode bits")):
+        r = lib.fgs_rasterize_forward_batch(ctypes.byref(g), cams2, None, 2, ctypes.byref(st), fake, 1 << 40, 0,
+                                            fake, None, fake, mode, ctypes.byref(stats), None)
+        assert r == L.FGS_ERR_INVALID_ARGUMENT and msg in lib.fgs_last_error(), (mode, lib.fgs_last_error())
     g.velocity = g.accel = None
     # conditional 4D Gaussians: all three extra planes or none, not with velocity, batched calls only
     g.mean_t = fake

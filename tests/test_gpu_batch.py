@@ -217,12 +217,14 @@ def test_single_view_forward_without_synchronisation():
 
 
 def test_forward_without_synchronisation_skips_constant_depth_digits():
-    """A scene spread over a very thin depth range: the visible depth keys
-    agree in all bits from 16 up, so the synchronisation-free depth sort
-    (four passes over 31 bits) skips its last two passes, taking the key
-    range from the device, and the duplication reads the sorted ids from the
-    buffer the device noted.  Its results equal the synchronised forward's,
-    which sorts only the bits that vary."""
+    """A scene spread over a very thin depth range: the visible depth keys,
+    offset by the smallest, span fewer than 2^16.  Without a depth-bits hint
+    the synchronisation-free depth sort (four passes over 31 bits) skips its
+    last two passes, taking the span from the device, and the duplication
+    reads the sorted ids from the buffer the device noted; with the bits the
+    synchronised forward reported (FGS_FORWARD_DEPTH_BITS, what the
+    Rasterizer passes) it sorts only those.  Both equal the synchronised
+    forward.  A hint four bits short sets bit 1 of the overflow word."""
     sc, cam = S.make_scene(8_000, 6, z_range=(3.0, 3.0005)), S.workload_camera("c1")
     say("no-sync forward, thin depth range")
     params = to_gpu(sc)
@@ -231,13 +233,26 @@ def test_forward_without_synchronisation_skips_constant_depth_digits():
     keys, vals, ranges = sorted_instances(rz)
     c = rz.view("counters", 16).cpu().numpy().view(np.uint32)
     kmin, kmax = int(c[1]), int(c[2])
-    say("  visible", rz.last_stats["n_visible"], "depth keys differ in bits", hex(kmin ^ kmax))
-    assert rz.last_stats["n_visible"] > 256 and (kmin ^ kmax) >> 16 == 0 and (kmin ^ kmax) >> 8 != 0
-    img2, tf2, last2 = rz.forward(params, sync=False)
-    assert not rz.overflowed()
-    assert torch.equal(img2, img) and torch.equal(tf2, tf) and torch.equal(last2, last)
-    keys2, vals2, ranges2 = sorted_instances(rz)
-    assert np.array_equal(keys2, keys) and np.array_equal(vals2, vals) and np.array_equal(ranges2, ranges)
+    say("  visible", rz.last_stats["n_visible"], "depth key span", hex(kmax - kmin))
+    assert rz.last_stats["n_visible"] > 256 and (kmax - kmin) >> 16 == 0 and (kmax - kmin) >> 8 != 0
+    assert np.array_equal(c[10:12], [0, kmax - kmin])
+    bits = rz.last_stats["depth_key_bits"]
+    assert bits == (kmax - kmin).bit_length()
+    say("  depth_key_bits", bits)
+    for label, mode in (("hint", B.no_sync_mode(rz.last_stats)), ("no hint", L.FGS_FORWARD_NO_SYNC)):
+        img2, tf2, last2 = torch.empty_like(img), torch.empty_like(tf), torch.empty_like(last)
+        B.rasterize_forward_batch(params, [cam], None, rz.settings, rz.workspace, rz.capacity, img2.view(-1),
+                                  tf2.view(-1), last2.view(-1), mode=mode)
+        assert not rz.overflowed(), label
+        assert torch.equal(img2, img) and torch.equal(tf2, tf) and torch.equal(last2, last), label
+        keys2, vals2, ranges2 = sorted_instances(rz)
+        assert np.array_equal(keys2, keys) and np.array_equal(vals2, vals) and np.array_equal(ranges2, ranges)
+    img2, tf2, last2 = torch.empty_like(img), torch.empty_like(tf), torch.empty_like(last)
+    B.rasterize_forward_batch(params, [cam], None, rz.settings, rz.workspace, rz.capacity, img2.view(-1),
+                              tf2.view(-1), last2.view(-1),
+                              mode=L.FGS_FORWARD_NO_SYNC | L.FGS_FORWARD_DEPTH_BITS(bits - 4))
+    torch.cuda.synchronize()
+    assert int(rz.view("counters", 8).cpu()[7]) == 2
 
 
 def test_batch_without_synchronisation_and_overflow_flag():
@@ -554,3 +569,35 @@ def test_conditional_4d_gaussians_match_oracle(case):
     torch.cuda.synchronize()
     assert set(g_sum) >= set(B.PARAM_NAMES) | set(B.COND4D_NAMES)
     check_grads(f"conditional 4D {case}", grads, g_sum, names=list(g_sum), exempt=np.concatenate(exempt))
+
+
+@pytest.mark.parametrize("case", ["views", "c1"])
+def test_blend_queue_schedule_matches_one_workgroup_per_tile(case):
+    """FGS_FLAG_BLEND_QUEUE runs the blend's per-tile code as persistent waves
+    that take tiles from one queue per XCD: images, T and last ids
+    bit-identical to one workgroup per tile, gradients equal up to the order
+    of their float atomics (relative L2 <= 1e-6 per group); run twice, since
+    every launch restarts its queues (several views, and one view)."""
+    if case == "views":
+        sc, cams = S.batch_scene(20_000, 4), small_views()
+    else:
+        sc, cams = S.make_scene(10_000, 0), [S.workload_camera("c1")]
+    say("blend queue", case)
+    params = to_gpu(sc)
+    npix = sum(B.view_pixels(cams))
+    dl = torch.randn(3 * npix, generator=torch.Generator().manual_seed(7)).mul_(1e-3).cuda()
+    out = {}
+    for sched, flags in (("grid", 0), ("queue", L.FGS_FLAG_BLEND_QUEUE)):
+        br = B.BatchRasterizer(cams, settings=B.default_settings(flags=flags))
+        for rep in range(2):
+            imgs, tfs, lasts = (t.clone() for t in br.forward(params))
+            grads = {k: v.clone() for k, v in br.backward(params, dl).items()}
+            torch.cuda.synchronize()
+            out[(sched, rep)] = (imgs, tfs, lasts, grads)
+    for rep in range(2):
+        gi, gt, gl, gg = out[("grid", 0)]
+        qi, qt, ql, qg = out[("queue", rep)]
+        assert torch.equal(qi, gi) and torch.equal(qt, gt) and torch.equal(ql, gl), rep
+        worst = max(rel_l2(qg[k], gg[k]) for k in B.PARAM_NAMES)
+        say(f"  rep {rep}: images equal, worst gradient rel L2 {worst:.2e}")
+        assert worst <= 1e-6
