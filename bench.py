@@ -53,10 +53,12 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-view batched step")
     ap.add_argument("--no-dynamic", action="store_true", help="skip the dynamic (4D) step")
     ap.add_argument("--batched-tile", type=int, default=0, choices=[0, 8, 16, 32],
-                    help="tile size of the batched step (0: the autotuner's choice of tile and schedule)")
+                    help="tile size of the batched step (0: the autotuner's choice of tile, schedule and sort block)")
     ap.add_argument("--batched-schedule", default="grid", choices=["grid", "queue"],
                     help="blend schedule of the batched step with --batched-tile: one workgroup per tile, or "
                          "persistent waves over per-XCD tile queues")
+    ap.add_argument("--batched-sort-block", type=int, default=4096, choices=[4096, 8192],
+                    help="pairs per block of the batched step's tile sort with --batched-tile")
     ap.add_argument("--form", default="step", choices=["step", "batched", "dynamic", "conditional"],
                     help="step: the full report; otherwise time only that form and print its block "
                          "(for kernel traces of one form)")
@@ -240,16 +242,19 @@ def bf16_ulps(got: torch.Tensor, ref: torch.Tensor):
     return {"max_bf16_ulps": float(((got.double() - rb).abs() / ulp).max())}
 
 
-def f32_ulps(got: torch.Tensor, ref: torch.Tensor):
-    """Largest distance of float32-stored values from the float32 rounding of
-    the float64 reference, in units of the reference's float32 ulp: an update
-    far smaller than the parameter is resolved only to the parameter's ulp, so
-    its relative error says little on its own."""
-    r = ref.double()
-    rf = r.float().double()
-    e = torch.floor(torch.log2(torch.clamp(r.abs(), min=1e-38)))
-    ulp = torch.pow(2.0, e - 23)
-    return float(((got.double() - rf).abs() / ulp).max())
+def update_error_beyond_rounding(p_gpu: torch.Tensor, p0: torch.Tensor, p_ref: torch.Tensor):
+    """The float32 update's error beyond the rounding of the stored parameter:
+    max(0, |p_gpu - p_ref| - ulp(p_ref) / 2) relative to max(|update|, the
+    RMS of the nonzero updates), p_ref the float64 reference.  An update far
+    smaller than the parameter is resolved only to the parameter's ulp, which
+    no implementation can beat; what is left is the update's own error."""
+    r = p_ref.double()
+    upd = r - p0.double()
+    half_ulp = 0.5 * torch.pow(2.0, torch.floor(torch.log2(torch.clamp(r.abs(), min=1e-38))) - 23)
+    excess = torch.clamp((p_gpu.double() - r).abs() - half_ulp, min=0.0)
+    live = upd[upd != 0]
+    rms = float(torch.sqrt((live ** 2).mean())) if live.numel() else 0.0
+    return float((excess / torch.clamp(upd.abs(), min=max(rms, 1e-300))).max())
 
 
 def unpermute(t: torch.Tensor, perm: torch.Tensor) -> torch.Tensor:
@@ -318,15 +323,18 @@ def oracle_errors(refs, scene, workload: str, dev, with_bf16: bool):
                 if pc[k].dtype == torch.bfloat16:
                     upd[k] = bf16_ulps(p_gpu, p_ref)  # stored in bfloat16: the step is rounded to it
                 else:
-                    # the update of every parameter, and the stored parameter in float32 ulps
-                    upd[k] = dict(err_stats(p_gpu - p0, p_ref - p0.double()), max_f32_ulps=f32_ulps(p_gpu, p_ref))
+                    # the update of every parameter, and its error beyond the float32 rounding of the parameter
+                    upd[k] = dict(err_stats(p_gpu - p0, p_ref - p0.double()),
+                                  max_rel_beyond_rounding=update_error_beyond_rounding(p_gpu, p0, p_ref))
             e["fused_adam_update"] = upd
             res[where] = e
-            ulps = [v.get("max_f32_ulps", v.get("max_bf16_ulps")) for v in upd.values()]
+            f32u = [v["max_rel_beyond_rounding"] for v in upd.values() if "max_rel_beyond_rounding" in v]
+            bf16u = [v["max_bf16_ulps"] for v in upd.values() if "max_bf16_ulps" in v]
             log(f"oracle error {sh} {where}: image max abs {e['image']['max_abs']:.2e} "
                 f"({e['borderline_pixels_excluded']} borderline px), worst gradient max rel "
-                f"{max(v['max_rel'] for v in e['gradients'].values()):.2e}, updated parameters within "
-                f"{max(ulps):.0f} ulp of the stored type")
+                f"{max(v['max_rel'] for v in e['gradients'].values()):.2e}, float32 updates max rel "
+                f"{max(f32u):.2e} beyond the parameters' rounding"
+                + (f", bfloat16 parameters within {max(bf16u):.0f} bf16 ulp" if bf16u else ""))
         out[sh] = res
         del params, rz
         torch.cuda.empty_cache()
@@ -532,9 +540,9 @@ def time_steps(step, steps, warmup):
 def run_batched(args, dev):
     """Several views per step: 1.5M Gaussians around the origin, 16 cameras on
     the radius-5 sphere with seeded uneven resolutions (640-1920 x 480-1080,
-    f = width); tile size from the autotuner (or --batched-tile); the step
-    timed eagerly and as a captured graph replayed (synchronisation-free
-    forward, device step count)."""
+    f = width); tile size, blend schedule and sort block from the autotuner
+    (or --batched-tile and its options); the step timed eagerly and as a
+    captured graph replayed (synchronisation-free forward, device step count)."""
     import paper_2602_09999_amd as P
     from paper_2602_09999_amd import _lib as L
     from paper_2602_09999_amd import binding as B
@@ -544,7 +552,8 @@ def run_batched(args, dev):
     params = {k: v.to(dev) for k, v in scene.items()}
     del scene
     if args.batched_tile:
-        config, tune_ms = {"tile": args.batched_tile, "schedule": args.batched_schedule}, None
+        config = {"tile": args.batched_tile, "schedule": args.batched_schedule, "sort_block": args.batched_sort_block}
+        tune_ms = None
     else:
         tuner = Autotuner(reps=2)
         config = tuner.choose(params, cams)
@@ -556,7 +565,7 @@ def run_batched(args, dev):
     dl = torch.empty(3 * npix, device=dev)
     out = {"workload": f"{BATCH_N} Gaussians, {BATCH_VIEWS} views on a radius-5 sphere, "
                        f"{npix} pixels in all", "tile": tile, "schedule": config["schedule"],
-           "autotune_ms_per_fwd_bwd": tune_ms}
+           "sort_block": config["sort_block"], "autotune_ms_per_fwd_bwd": tune_ms}
     for mode_name, graph in (("eager", False), ("graph", True)):
         br = B.BatchRasterizer(cams, settings=st)
         opt = P.FusedAdam(params, S.ADAM_LR, device_step=graph)
@@ -585,7 +594,7 @@ def run_batched(args, dev):
         out[f"{mode_name}_steps_per_s"] = 1.0 / sec
         out[f"{mode_name}_views_per_s"] = BATCH_VIEWS / sec
         log(f"batched {mode_name}: {sec * 1e3:.2f} ms per step of {BATCH_VIEWS} views (tile {tile}, "
-            f"{config['schedule']} schedule)")
+            f"{config['schedule']} schedule, sort blocks of {config['sort_block']})")
         del br, opt, grads
         torch.cuda.empty_cache()
     return out

@@ -65,6 +65,11 @@ typedef enum fgs_dtype { FGS_F32 = 0, FGS_BF16 = 1 } fgs_dtype;
  *   instead of one workgroup per tile.  Same results; a scheduling choice
  *   for workloads with many more tiles than the device holds waves. */
 #define FGS_FLAG_BLEND_QUEUE 4u
+/* FGS_FLAG_SORT_LARGE_BLOCKS: the tile sort ranks and scatters blocks of
+ *   8192 pairs instead of 4096 (longer digit runs per block to write out,
+ *   fewer waves per SIMD).  Same results; a blocking choice for the
+ *   autotuner (it pays off for many instances over wide digits). */
+#define FGS_FLAG_SORT_LARGE_BLOCKS 8u
 
 /* The Gaussian parameters of Sec. 2.1 ("3D Gaussian Splatting"): mean mu,
  * log-scales (scale = exp, "Activation Functions"), rotation quaternion

@@ -1,16 +1,18 @@
-"""Autotuner over the rasterizer's tiling and scheduling: the tile size (8, 16
-or 32 pixels) and the blend schedule (one workgroup per tile, or persistent
-waves taking tiles from per-XCD queues, FGS_FLAG_BLEND_QUEUE), chosen for a
-workload by timing rasterizer steps and cached per (Gaussian-count bucket,
-pixel-count bucket, view count).
+"""Autotuner over the rasterizer's tiling, scheduling and blocking: the tile
+size (8, 16 or 32 pixels), the blend schedule (one workgroup per tile, or
+persistent waves taking tiles from per-XCD queues, FGS_FLAG_BLEND_QUEUE) and
+the tile sort's block (4096 or 8192 pairs, FGS_FLAG_SORT_LARGE_BLOCKS),
+chosen for a workload by timing rasterizer steps and cached per
+(Gaussian-count bucket, pixel-count bucket, view count).
 
 The timing runs the library's forward and backward passes (HIP events on the
 current stream).  The search is coordinate-wise: every tile size with the
-one-workgroup-per-tile schedule, then the other schedules at the fastest
-tile size.  Neither choice changes the result: every tile size gives the
-same image up to the float32 rounding of borderline fragments, and both
-schedules run the same per-tile code (the backward's gradient sums differ
-only in the order of their float atomics).
+default schedule and block, then the other schedules at the fastest tile
+size, then the other sort blocks at the fastest (tile, schedule).  No choice
+changes the result: every tile size gives the same image up to the float32
+rounding of borderline fragments, both schedules run the same per-tile code
+(the backward's gradient sums differ only in the order of their float
+atomics), and both blockings sort stably to the same order.
 """
 from __future__ import annotations
 
@@ -26,6 +28,7 @@ from . import binding as B
 
 CANDIDATES = (8, 16, 32)
 SCHEDULES = ("grid", "queue")
+SORT_BLOCKS = (4096, 8192)
 
 
 def bucket(n: int, cameras: Sequence) -> Tuple[int, int, int]:
@@ -36,8 +39,8 @@ def bucket(n: int, cameras: Sequence) -> Tuple[int, int, int]:
 
 
 def settings_for(config: Dict[str, object], base=None) -> L.Settings:
-    """Settings with the configuration's tile size and blend schedule (other
-    fields from ``base``, else the defaults)."""
+    """Settings with the configuration's tile size, blend schedule and sort
+    block (other fields from ``base``, else the defaults)."""
     st = B.default_settings() if base is None else base
     st = B.default_settings(**{f: getattr(st, f) for f, _ in st._fields_})
     st.tile = int(config["tile"])
@@ -45,16 +48,20 @@ def settings_for(config: Dict[str, object], base=None) -> L.Settings:
         st.flags |= L.FGS_FLAG_BLEND_QUEUE
     else:
         st.flags &= ~L.FGS_FLAG_BLEND_QUEUE
+    if int(config.get("sort_block", SORT_BLOCKS[0])) == 8192:
+        st.flags |= L.FGS_FLAG_SORT_LARGE_BLOCKS
+    else:
+        st.flags &= ~L.FGS_FLAG_SORT_LARGE_BLOCKS
     return st
 
 
 class Autotuner:
-    """choose(params, cameras) -> {"tile": t, "schedule": s}.  ``measure(config)
-    -> ms`` may be given to replace the timed steps (tests); ``cache_path``
-    persists choices as JSON."""
+    """choose(params, cameras) -> {"tile": t, "schedule": s, "sort_block": b}.
+    ``measure(config) -> ms`` may be given to replace the timed steps (tests);
+    ``cache_path`` persists choices as JSON."""
 
-    def __init__(self, candidates: Iterable[int] = CANDIDATES, schedules: Iterable[str] = SCHEDULES, reps: int = 3,
-                 cache_path: Optional[str] = None):
+    def __init__(self, candidates: Iterable[int] = CANDIDATES, schedules: Iterable[str] = SCHEDULES,
+                 sort_blocks: Iterable[int] = SORT_BLOCKS, reps: int = 3, cache_path: Optional[str] = None):
         self.candidates = tuple(int(t) for t in candidates)
         for t in self.candidates:
             if t not in CANDIDATES:
@@ -65,6 +72,12 @@ class Autotuner:
                 raise ValueError(f"schedule {s!r} not in {SCHEDULES}")
         if "grid" not in self.schedules:
             raise ValueError("the one-workgroup-per-tile schedule ('grid') is the search's starting point")
+        self.sort_blocks = tuple(int(b) for b in sort_blocks)
+        for b in self.sort_blocks:
+            if b not in SORT_BLOCKS:
+                raise ValueError(f"sort block {b} not in {SORT_BLOCKS}")
+        if SORT_BLOCKS[0] not in self.sort_blocks:
+            raise ValueError(f"the default sort block ({SORT_BLOCKS[0]}) is the search's starting point")
         self.reps = int(reps)
         self.cache_path = cache_path
         self.cache: Dict[str, Dict[str, object]] = {}
@@ -78,7 +91,7 @@ class Autotuner:
 
     @staticmethod
     def _name(config: Dict[str, object]) -> str:
-        return f"{config['tile']}/{config['schedule']}"
+        return f"{config['tile']}/{config['schedule']}/{config['sort_block']}"
 
     def time_steps(self, params: Dict[str, torch.Tensor], cameras: Sequence, config: Dict[str, object],
                    times: Optional[Sequence[float]] = None, settings=None) -> float:
@@ -105,7 +118,7 @@ class Autotuner:
         key = self._key(bucket(n, cameras))
         if key in self.cache:
             c = self.cache[key]
-            return {"tile": int(c["tile"]), "schedule": str(c["schedule"])}
+            return {"tile": int(c["tile"]), "schedule": str(c["schedule"]), "sort_block": int(c["sort_block"])}
         timings: Dict[str, float] = {}
 
         def run(config):
@@ -114,15 +127,25 @@ class Autotuner:
             timings[self._name(config)] = ms
             return ms
 
-        # tile sizes with one workgroup per tile; equal times: the smaller tile
-        tile_ms = {t: run({"tile": t, "schedule": "grid"}) for t in self.candidates}
-        best = {"tile": min(tile_ms, key=lambda t: (tile_ms[t], t)), "schedule": "grid"}
+        # tile sizes with one workgroup per tile and the default sort block;
+        # equal times: the smaller tile
+        b0 = SORT_BLOCKS[0]
+        tile_ms = {t: run({"tile": t, "schedule": "grid", "sort_block": b0}) for t in self.candidates}
+        best = {"tile": min(tile_ms, key=lambda t: (tile_ms[t], t)), "schedule": "grid", "sort_block": b0}
         best_ms = tile_ms[best["tile"]]
-        # the other schedules at that tile size (kept only when faster)
+        # the other schedules at that tile size, then the other sort blocks
+        # (each kept only when faster)
         for s in self.schedules:
             if s == "grid":
                 continue
-            config = {"tile": best["tile"], "schedule": s}
+            config = dict(best, schedule=s)
+            ms = run(config)
+            if ms < best_ms:
+                best, best_ms = config, ms
+        for b in self.sort_blocks:
+            if b == b0:
+                continue
+            config = dict(best, sort_block=b)
             ms = run(config)
             if ms < best_ms:
                 best, best_ms = config, ms

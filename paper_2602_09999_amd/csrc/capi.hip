@@ -104,7 +104,8 @@ fgs_status check_settings(const fgs_settings* st) {
   if (!st) return fail(FGS_ERR_INVALID_ARGUMENT, "settings is NULL");
   if (st->tile != 8 && st->tile != 16 && st->tile != 32)
     return fail(FGS_ERR_INVALID_ARGUMENT, "tile must be 8, 16 or 32 (got %d)", st->tile);
-  if (st->flags & ~(uint32_t)(FGS_FLAG_FP64_CONIC | FGS_FLAG_LOOKBACK_FALLBACK | FGS_FLAG_BLEND_QUEUE))
+  if (st->flags &
+      ~(uint32_t)(FGS_FLAG_FP64_CONIC | FGS_FLAG_LOOKBACK_FALLBACK | FGS_FLAG_BLEND_QUEUE | FGS_FLAG_SORT_LARGE_BLOCKS))
     return fail(FGS_ERR_INVALID_ARGUMENT, "unknown bits in settings.flags 0x%x", st->flags);
   // alpha_max < 1: the backward divides by 1 - alpha (App. B.1's front-to-back
   // gradient), which the cap keeps at least 1 - alpha_max away from zero
@@ -473,13 +474,17 @@ fgs_status fgs_rasterize_forward_batch(const fgs_gaussians* g, const fgs_camera*
               "duplicate");
     int inst_final = 0;
     const int bits = tile_key_bits(tiles);
+    const bool large_blocks = (st->flags & FGS_FLAG_SORT_LARGE_BLOCKS) != 0;
     if (key_bytes == 2) {
       uint16_t* k16[2] = {static_cast<uint16_t*>(ikeys[0]), static_cast<uint16_t*>(ikeys[1])};
-      FGS_TIMED("tile_sort", hs, radix_sort_pairs16(k16, ivals, inst, d_sorted, 0, bits, scratch, &inst_final, hs),
+      FGS_TIMED("tile_sort", hs,
+                radix_sort_pairs16(k16, ivals, inst, d_sorted, 0, bits, scratch, &inst_final, hs, large_blocks),
                 "tile sort");
     } else {
       uint32_t* k32[2] = {static_cast<uint32_t*>(ikeys[0]), static_cast<uint32_t*>(ikeys[1])};
-      FGS_TIMED("tile_sort", hs, radix_sort_pairs(k32, ivals, inst, d_sorted, 0, bits, scratch, &inst_final, hs),
+      FGS_TIMED("tile_sort", hs,
+                radix_sort_pairs(k32, ivals, inst, d_sorted, 0, bits, scratch, &inst_final, hs, nullptr, true,
+                                 nullptr, large_blocks),
                 "tile sort");
     }
     if (inst_final != L.inst_final) return fail(FGS_ERR_HIP, "internal: tile sort buffer mismatch");

@@ -18,6 +18,7 @@ constexpr int kWave = 64;
 #define FGS_SORT32_ITEMS 16
 #endif
 constexpr int kScanItems = FGS_SORT32_ITEMS;
+constexpr int kSortItemsLarge = 32;  // pairs per thread of a sort's large blocks (8192 pairs)
 // pairs per thread of the 16-bit-key sort (a build-time tuning constant)
 #ifndef FGS_SORT16_ITEMS
 #define FGS_SORT16_ITEMS 16
@@ -524,13 +525,16 @@ size_t radix_scratch_words(uint64_t n);
 // the buffer holding the result is written to the device word final_word
 // (required then; *final_buf is -1).  keep_keys = false: the last pass writes
 // the values only (the sorted keys are not needed).
+// large_blocks: blocks of kBlock * kSortItemsLarge pairs instead of the
+// default shape (longer digit runs per block, fewer waves per SIMD).
 hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
                             int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s,
                             const uint32_t* d_range = nullptr, bool keep_keys = true,
-                            uint32_t* final_word = nullptr);
+                            uint32_t* final_word = nullptr, bool large_blocks = false);
 // The same for 16-bit keys (begin_bit < end_bit <= 16).
 hipError_t radix_sort_pairs16(uint16_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
-                              int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s);
+                              int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s,
+                              bool large_blocks = false);
 
 // Per-Gaussian splat record: four float4 (64 bytes, so a gather of any three
 // of them touches one cache line):

@@ -380,6 +380,8 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT* __restrict__
 // Pairs per block of the sorts (kBlock times the items per thread): smaller
 // blocks mean more histogram entries and shorter digit runs per block to
 // write out, larger ones fewer waves per SIMD (more registers and LDS).
+// The default shapes, and the large blocks (kSortItemsLarge per thread) a
+// caller may choose for the sort of many pairs over wide digits.
 template <typename KT>
 struct SortShape;
 template <>
@@ -405,12 +407,11 @@ size_t radix_scratch_words(uint64_t n) {
   return round_words((uint64_t)kRadix * nb) + round_words(kRadix) + scan_scratch_words((uint64_t)kRadix * nb);
 }
 
-template <int RB, typename KT>
+template <int RB, typename KT, int kItems>
 static hipError_t radix_pass(const KT* keys_in, const uint32_t* vals_in, KT* keys_out, uint32_t* vals_out,
                              uint32_t n, const uint32_t* d_count, const uint32_t* d_range, int shift,
                              uint32_t* hist, uint32_t* totals, uint32_t* scan_scratch, uint32_t nb,
                              uint32_t* final_word, uint32_t final_if_run, hipStream_t s) {
-  constexpr int kItems = SortShape<KT>::kItems;
   k_radix_hist<RB, KT, kItems><<<nb, kBlock, 0, s>>>(keys_in, n, d_count, shift, d_range, hist, nb, final_word,
                                                      final_if_run);
   const uint32_t* digit_totals = totals;
@@ -426,7 +427,7 @@ static hipError_t radix_pass(const KT* keys_in, const uint32_t* vals_in, KT* key
   return hipGetLastError();
 }
 
-template <typename KT>
+template <typename KT, int kItems>
 static hipError_t radix_sort_impl(KT* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
                                   const uint32_t* d_range, int begin_bit, int end_bit, bool keep_keys,
                                   uint32_t* scratch, int* final_buf, uint32_t* final_word, hipStream_t s) {
@@ -435,7 +436,7 @@ static hipError_t radix_sort_impl(KT* keys[2], uint32_t* vals[2], uint32_t n, co
     *final_buf = 0;
     return hipSuccess;
   }
-  const uint32_t nb = ceil_div(n, (uint64_t)kBlock * SortShape<KT>::kItems);
+  const uint32_t nb = ceil_div(n, (uint64_t)kBlock * kItems);
   uint32_t* hist = scratch;
   uint32_t* totals = scratch + round_words((size_t)kRadix * nb);
   uint32_t* scan_scratch = totals + round_words(kRadix);
@@ -454,8 +455,8 @@ static hipError_t radix_sort_impl(KT* keys[2], uint32_t* vals[2], uint32_t n, co
     const uint32_t fin = (uint32_t)(cur ^ 1);
     hipError_t e = hipSuccess;
 #define FGS_RADIX_PASS(RB_)                                                                                     \
-  e = radix_pass<RB_, KT>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, d_range, shift, hist, totals, \
-                          scan_scratch, nb, final_word, fin, s)
+  e = radix_pass<RB_, KT, kItems>(keys[cur], vals[cur], kout, vals[cur ^ 1], n, d_count, d_range, shift, hist,    \
+                                  totals, scan_scratch, nb, final_word, fin, s)
     switch (rb) {
       case 1: FGS_RADIX_PASS(1); break;
       case 2: FGS_RADIX_PASS(2); break;
@@ -479,18 +480,25 @@ static hipError_t radix_sort_impl(KT* keys[2], uint32_t* vals[2], uint32_t n, co
 
 hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
                             int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s,
-                            const uint32_t* d_range, bool keep_keys, uint32_t* final_word) {
+                            const uint32_t* d_range, bool keep_keys, uint32_t* final_word, bool large_blocks) {
   if ((uint64_t)n >= (uint64_t)kMaxSortPairs || (d_range != nullptr && final_word == nullptr))
     return hipErrorInvalidValue;
-  return radix_sort_impl<uint32_t>(keys, vals, n, d_count, d_range, begin_bit, end_bit, keep_keys, scratch,
-                                   final_buf, final_word, s);
+  if (large_blocks)
+    return radix_sort_impl<uint32_t, kSortItemsLarge>(keys, vals, n, d_count, d_range, begin_bit, end_bit, keep_keys,
+                                                      scratch, final_buf, final_word, s);
+  return radix_sort_impl<uint32_t, SortShape<uint32_t>::kItems>(keys, vals, n, d_count, d_range, begin_bit, end_bit,
+                                                                keep_keys, scratch, final_buf, final_word, s);
 }
 
 hipError_t radix_sort_pairs16(uint16_t* keys[2], uint32_t* vals[2], uint32_t n, const uint32_t* d_count,
-                              int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s) {
+                              int begin_bit, int end_bit, uint32_t* scratch, int* final_buf, hipStream_t s,
+                              bool large_blocks) {
   if ((uint64_t)n >= (uint64_t)kMaxSortPairs) return hipErrorInvalidValue;
-  return radix_sort_impl<uint16_t>(keys, vals, n, d_count, nullptr, begin_bit, end_bit, true, scratch, final_buf,
-                                   nullptr, s);
+  if (large_blocks)
+    return radix_sort_impl<uint16_t, kSortItemsLarge>(keys, vals, n, d_count, nullptr, begin_bit, end_bit, true,
+                                                      scratch, final_buf, nullptr, s);
+  return radix_sort_impl<uint16_t, SortShape<uint16_t>::kItems>(keys, vals, n, d_count, nullptr, begin_bit, end_bit,
+                                                                true, scratch, final_buf, nullptr, s);
 }
 
 }  // namespace fgs

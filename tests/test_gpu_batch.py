@@ -571,33 +571,40 @@ def test_conditional_4d_gaussians_match_oracle(case):
     check_grads(f"conditional 4D {case}", grads, g_sum, names=list(g_sum), exempt=np.concatenate(exempt))
 
 
+@pytest.mark.parametrize("option", ["queue", "sort8192"])
 @pytest.mark.parametrize("case", ["views", "c1"])
-def test_blend_queue_schedule_matches_one_workgroup_per_tile(case):
-    """FGS_FLAG_BLEND_QUEUE runs the blend's per-tile code as persistent waves
-    that take tiles from one queue per XCD: images, T and last ids
-    bit-identical to one workgroup per tile, gradients equal up to the order
-    of their float atomics (relative L2 <= 1e-6 per group); run twice, since
-    every launch restarts its queues (several views, and one view)."""
+def test_schedule_and_blocking_options_match_the_defaults(case, option):
+    """The autotuner's options change no result.  FGS_FLAG_BLEND_QUEUE runs the
+    blend's per-tile code as persistent waves that take tiles from one queue
+    per XCD; FGS_FLAG_SORT_LARGE_BLOCKS sorts the instances in blocks of 8192
+    pairs.  Sorted instances, images, T and last ids are bit-identical to the
+    defaults, gradients equal up to the order of their float atomics
+    (relative L2 <= 1e-6 per group); run twice (the queues restart every
+    launch), for several views and for one."""
     if case == "views":
         sc, cams = S.batch_scene(20_000, 4), small_views()
     else:
         sc, cams = S.make_scene(10_000, 0), [S.workload_camera("c1")]
-    say("blend queue", case)
+    flag = L.FGS_FLAG_BLEND_QUEUE if option == "queue" else L.FGS_FLAG_SORT_LARGE_BLOCKS
+    say("option", option, case)
     params = to_gpu(sc)
     npix = sum(B.view_pixels(cams))
     dl = torch.randn(3 * npix, generator=torch.Generator().manual_seed(7)).mul_(1e-3).cuda()
     out = {}
-    for sched, flags in (("grid", 0), ("queue", L.FGS_FLAG_BLEND_QUEUE)):
+    for sched, flags in (("default", 0), (option, flag)):
         br = B.BatchRasterizer(cams, settings=B.default_settings(flags=flags))
         for rep in range(2):
             imgs, tfs, lasts = (t.clone() for t in br.forward(params))
+            torch.cuda.synchronize()
+            inst = sorted_instances(br)
             grads = {k: v.clone() for k, v in br.backward(params, dl).items()}
             torch.cuda.synchronize()
-            out[(sched, rep)] = (imgs, tfs, lasts, grads)
+            out[(sched, rep)] = (imgs, tfs, lasts, grads, inst)
     for rep in range(2):
-        gi, gt, gl, gg = out[("grid", 0)]
-        qi, qt, ql, qg = out[("queue", rep)]
+        gi, gt, gl, gg, ginst = out[("default", 0)]
+        qi, qt, ql, qg, qinst = out[(option, rep)]
+        assert all(np.array_equal(a, b) for a, b in zip(qinst, ginst)), rep
         assert torch.equal(qi, gi) and torch.equal(qt, gt) and torch.equal(ql, gl), rep
         worst = max(rel_l2(qg[k], gg[k]) for k in B.PARAM_NAMES)
-        say(f"  rep {rep}: images equal, worst gradient rel L2 {worst:.2e}")
+        say(f"  rep {rep}: instances and images equal, worst gradient rel L2 {worst:.2e}")
         assert worst <= 1e-6
