@@ -595,7 +595,7 @@ fgs_status fgs_rasterize_backward_batch(const fgs_gaussians* g, const fgs_camera
   } else {
     FGS_TIMED("preprocess_backward", hs,
               launch_preprocess_backward_views(gd, vs, at<float4>(workspace, L.rec), at<float>(workspace, L.accum),
-                                               gr, hs),
+                                               at<uint8_t>(workspace, L.marks), gr, hs),
               "preprocess bwd (views)");
   }
   return FGS_OK;

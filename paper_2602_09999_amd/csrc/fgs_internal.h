@@ -421,6 +421,28 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// One step of a load-balanced walk over a wave's list of items, where lane l
+// owns the run [start, start + len) of the list (runs in lane order): the
+// lane owning position c0 + lane.  The owner of each run that starts in (or
+// runs into) the step claims the run's first position in owner_at with the
+// step's tag; position q belongs to the last claim at or below q.  claims /
+// first: whether this lane's run meets the step, and its first position in
+// the step.  owner_at must hold no tag of this step beforehand (tags grow by
+// 0x100 per step and owner_at starts at 0xffffffff).
+__device__ __forceinline__ int wave_run_owner(uint32_t start, uint32_t len, uint32_t c0, uint32_t tag,
+                                              lds_volatile_u32* owner_at, uint64_t upto, bool& claims,
+                                              uint32_t& first) {
+  const int lane = threadIdx.x & (kWave - 1);
+  claims = len > 0 && start < c0 + kWave && start + len > c0;
+  first = start > c0 ? start - c0 : 0u;
+  if (claims) owner_at[first] = tag | (uint32_t)lane;
+  const uint32_t mine = owner_at[lane];
+  const uint64_t claimed = __ballot((mine & ~0xffu) == tag);
+  const uint64_t m = claimed & upto;
+  const int src_slot = m ? 63 - __clzll(m) : 0;
+  return (int)(owner_at[src_slot] & 0xffu);
+}
+
 // emit(owner, const OwnerRec&, rank among the wave's kept tiles, tx, ty, keep)
 // is called by every lane at every step (uniform control flow); LDS the
 // caller wrote before the call is visible to all lanes inside emit.
@@ -453,15 +475,9 @@ __device__ __forceinline__ uint32_t wave_tile_walk(const CandLane& me, WalkLds& 
   owner_at[lane] = 0xffffffffu;  // no step tag matches
   wave_lds_sync();
   for (uint32_t c0 = 0; c0 < total; c0 += kWave, tag += 0x100u) {
-    // the Gaussian whose candidates start in (or run into) this step claims its first slot
-    const bool claims = me.cand > 0 && cstart < c0 + kWave && cstart + me.cand > c0;
-    const uint32_t slot = cstart > c0 ? cstart - c0 : 0u;
-    if (claims) owner_at[slot] = tag | (uint32_t)lane;
-    const uint32_t mine = owner_at[lane];
-    const uint64_t claimed = __ballot((mine & ~0xffu) == tag);
-    const uint64_t m = claimed & upto;
-    const int src_slot = m ? 63 - __clzll(m) : 0;
-    const int owner = (int)(owner_at[src_slot] & 0xffu);
+    bool claims;
+    uint32_t slot;
+    const int owner = wave_run_owner(cstart, me.cand, c0, tag, owner_at, upto, claims, slot);
     const uint32_t pos = c0 + (uint32_t)lane;
     const bool valid = pos < total;
     const OwnerRec o = L.own[owner];
@@ -624,8 +640,11 @@ hipError_t launch_preprocess_backward(const GaussDev& g, const CamDev& cam, cons
                                       const GradDev& gr, hipStream_t s);
 // Several views / timesteps: gradients summed over the views (accum is
 // [n_views n][9]); dynamic Gaussians also get dL/dvelocity and dL/daccel.
+// marks: the blend backward's byte per entry (nonzero: the entry's
+// accumulator row received a value); only marked entries are chained.
 hipError_t launch_preprocess_backward_views(const GaussDev& g, const ViewSet& vs, const float4* rec,
-                                            const float* accum, const GradDev& gr, hipStream_t s);
+                                            const float* accum, const uint8_t* marks, const GradDev& gr,
+                                            hipStream_t s);
 // Fused backward + Adam, first part: marks the Gaussians with a gradient in
 // `touched` (4 bits per byte), lists them (count in *counter, cleared here),
 // gives Gaussian list[s] slot s (slot_of) and writes its 59 raw-parameter

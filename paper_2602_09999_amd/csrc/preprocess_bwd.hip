@@ -608,50 +608,97 @@ __global__ __launch_bounds__(kBlock) void k_touched_grads(GaussDev g, CamDev cam
 // Several views (or timesteps): Gaussian i sums, over the views that gave it
 // a gradient, the chain rule through view v's camera and record j = v n + i.
 // Dynamic scenes (mean(t) = mu + v t + a t^2) also get dL/dvelocity =
-// sum_t t dL/dmean(t) and dL/daccel = sum_t t^2 dL/dmean(t).  One thread per
-// Gaussian; every gradient plane is written in full.
+// sum_t t dL/dmean(t) and dL/daccel = sum_t t^2 dL/dmean(t).  Every gradient
+// plane is written in full.
+//
+// One wave per 64 Gaussians.  The entries with a nonzero accumulator row are
+// the ones the blend backward marked; the wave walks its Gaussians' marked
+// entries 64 at a time (load-balanced, each Gaussian's in view order), so
+// every lane evaluates the chain rule of a real entry, where a lane per
+// Gaussian would leave most lanes idle whenever a view is needed by only a
+// few Gaussians of the wave.  A step's gradients pass through LDS, one row
+// per lane; the lane of each Gaussian then adds the rows of its entries in
+// view order (the same additions, in the same order, as a loop over its
+// views) and writes the sums once at the end.
 template <bool SHB, bool C4>
-__global__ __launch_bounds__(kBlock) void k_preprocess_bwd_views(GaussDev g, ViewSet vs,
-                                                                 const float4* __restrict__ rec,
-                                                                 const float* __restrict__ accum, GradDev gr) {
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(kWave) void k_preprocess_bwd_views(GaussDev g, ViewSet vs,
+                                                                const float4* __restrict__ rec,
+                                                                const float* __restrict__ accum,
+                                                                const uint8_t* __restrict__ marks, GradDev gr) {
+  constexpr int kSum = C4 ? kCond4Params : kParams;
+  constexpr int kRow = C4 ? kSum : kSum + 6;  // + t dL/dmean(t) and t^2 dL/dmean(t) of a dynamic scene
+  __shared__ float s_row[kWave][kRow + 1];
+  __shared__ uint32_t s_owner_at[kWave];
+  const int lane = threadIdx.x;
   const size_t n = g.n;
+  const uint32_t i = blockIdx.x * kWave + (uint32_t)lane;
+  const bool dyn = g.velocity != nullptr;
+  // this lane's Gaussian's marked views and its run in the wave's list
+  uint32_t vmask = 0;
+  if (i < n)
+    for (uint32_t v = 0; v < vs.n_views; ++v) vmask |= marks[(size_t)v * n + i] ? (1u << v) : 0u;
+  const uint32_t cnt = (uint32_t)__popc(vmask);
+  const uint32_t incl = wave_inclusive_scan(cnt, lane);
+  const uint32_t start = incl - cnt;
+  const uint32_t total = __shfl(incl, kWave - 1, kWave);
+  const uint64_t upto = ((lane == 0) ? 0ull : (~0ull >> (64 - lane))) | (1ull << lane);
+  float sum[kRow];
+#pragma unroll
+  for (int p = 0; p < kRow; ++p) sum[p] = 0.0f;
+  lds_volatile_u32* owner_at = lds_volatile(s_owner_at);
+  owner_at[lane] = 0xffffffffu;  // no step tag matches
+  wave_lds_sync();
+  float* row = s_row[lane];
+  uint32_t tag = 0;
+  for (uint32_t c0 = 0; c0 < total; c0 += kWave, tag += 0x100u) {
+    bool claims;
+    uint32_t first;
+    const int owner = wave_run_owner(start, cnt, c0, tag, owner_at, upto, claims, first);
+    const uint32_t pos = c0 + (uint32_t)lane;
+    const uint32_t o_start = (uint32_t)__shfl((int)start, owner, kWave);
+    const uint32_t o_mask = (uint32_t)__shfl((int)vmask, owner, kWave);
+    if (pos < total) {
+      // the owner's (pos - o_start)-th marked view
+      uint32_t m = o_mask;
+      for (uint32_t k = pos - o_start; k > 0; --k) m &= m - 1u;
+      const uint32_t v = (uint32_t)__builtin_ctz(m);
+      const uint32_t gi = blockIdx.x * kWave + (uint32_t)owner;
+      const size_t rj = (size_t)v * n + gi;
+      float a[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) a[q] = accum[rj * 9 + q];
+      const float t = vs.time[v], tt = t * t;
+      if (C4) {
+        gaussian_grads_cond4<SHB>(g, vs.cam[v], rec, a, gi, rj, t, [&](int p, float val) { row[p] = val; });
+      } else {
+        float mu[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          mu[k] = g.means[k * n + gi];
+          if (dyn) mu[k] = (mu[k] + g.velocity[k * n + gi] * t) + g.accel[k * n + gi] * tt;
+        }
+        gaussian_grads<SHB>(g, vs.cam[v], rec, a, gi, rj, mu, [&](int p, float val) {
+          row[p] = val;
+          if (p < 3) {
+            row[kSum + p] = t * val;
+            row[kSum + 3 + p] = tt * val;
+          }
+        });
+      }
+    }
+    wave_lds_sync();
+    // the lane of each Gaussian with entries in this step adds their rows
+    if (claims) {
+      const uint32_t hi = min(start + cnt - c0, (uint32_t)kWave);  // exclusive
+      for (uint32_t q = first; q < hi; ++q) {
+#pragma unroll
+        for (int p = 0; p < kRow; ++p) sum[p] += s_row[q][p];
+      }
+    }
+    wave_lds_sync();  // the rows are read before the next step writes them
+  }
   if (i >= n) return;
   void* const out[6] = {gr.means, gr.log_scales, gr.quats, gr.logits, gr.sh_dc, gr.sh_rest};
-  const bool dyn = g.velocity != nullptr;
-  constexpr int kSum = C4 ? kCond4Params : kParams;
-  float sum[kSum], dvel[3] = {0.f, 0.f, 0.f}, dacc[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-  for (int p = 0; p < kSum; ++p) sum[p] = 0.0f;
-  for (uint32_t v = 0; v < vs.n_views; ++v) {
-    const size_t rj = (size_t)v * n + i;
-    float a[9];
-    bool any = false;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      a[q] = accum[rj * 9 + q];
-      any |= a[q] != 0.0f;
-    }
-    if (!any) continue;
-    const float t = vs.time[v], tt = t * t;
-    if (C4) {
-      gaussian_grads_cond4<SHB>(g, vs.cam[v], rec, a, i, rj, t, [&](int p, float val) { sum[p] += val; });
-      continue;
-    }
-    float mu[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      mu[k] = g.means[k * n + i];
-      if (dyn) mu[k] = (mu[k] + g.velocity[k * n + i] * t) + g.accel[k * n + i] * tt;
-    }
-    gaussian_grads<SHB>(g, vs.cam[v], rec, a, i, rj, mu, [&](int p, float val) {
-      sum[p] += val;
-      if (p < 3) {
-        dvel[p] = fmaf(t, val, dvel[p]);
-        dacc[p] = fmaf(tt, val, dacc[p]);
-      }
-    });
-  }
 #pragma unroll
   for (int p = 0; p < kParams; ++p) plane_store<SHB>(out, p, n, i, sum[p]);
   if (C4) {
@@ -663,25 +710,26 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd_views(GaussDev g, Vie
   if (dyn) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      gr.velocity[k * n + i] = dvel[k];
-      gr.accel[k * n + i] = dacc[k];
+      gr.velocity[k * n + i] = sum[kSum + k];
+      gr.accel[k * n + i] = sum[kSum + 3 + k];
     }
   }
 }
 
 hipError_t launch_preprocess_backward_views(const GaussDev& g, const ViewSet& vs, const float4* rec,
-                                            const float* accum, const GradDev& gr, hipStream_t s) {
+                                            const float* accum, const uint8_t* marks, const GradDev& gr,
+                                            hipStream_t s) {
   if (g.n == 0) return hipSuccess;
-  const uint32_t grid = ceil_div(g.n, kBlock);
+  const uint32_t grid = ceil_div(g.n, kWave);
   const bool c4 = g.quats_r != nullptr;
   if (g.sh_bf16 && c4)
-    k_preprocess_bwd_views<true, true><<<grid, kBlock, 0, s>>>(g, vs, rec, accum, gr);
+    k_preprocess_bwd_views<true, true><<<grid, kWave, 0, s>>>(g, vs, rec, accum, marks, gr);
   else if (g.sh_bf16)
-    k_preprocess_bwd_views<true, false><<<grid, kBlock, 0, s>>>(g, vs, rec, accum, gr);
+    k_preprocess_bwd_views<true, false><<<grid, kWave, 0, s>>>(g, vs, rec, accum, marks, gr);
   else if (c4)
-    k_preprocess_bwd_views<false, true><<<grid, kBlock, 0, s>>>(g, vs, rec, accum, gr);
+    k_preprocess_bwd_views<false, true><<<grid, kWave, 0, s>>>(g, vs, rec, accum, marks, gr);
   else
-    k_preprocess_bwd_views<false, false><<<grid, kBlock, 0, s>>>(g, vs, rec, accum, gr);
+    k_preprocess_bwd_views<false, false><<<grid, kWave, 0, s>>>(g, vs, rec, accum, marks, gr);
   return hipGetLastError();
 }
 

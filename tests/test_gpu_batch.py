@@ -572,19 +572,26 @@ def test_conditional_4d_gaussians_match_oracle(case):
 
 
 @pytest.mark.parametrize("option", ["queue", "sort8192"])
-@pytest.mark.parametrize("case", ["views", "c1"])
+@pytest.mark.parametrize("case", ["views", "c1", "wide"])
 def test_schedule_and_blocking_options_match_the_defaults(case, option):
     """The autotuner's options change no result.  FGS_FLAG_BLEND_QUEUE runs the
     blend's per-tile code as persistent waves that take tiles from one queue
     per XCD; FGS_FLAG_SORT_LARGE_BLOCKS sorts the instances in blocks of 8192
     pairs.  Sorted instances, images, T and last ids are bit-identical to the
     defaults, gradients equal up to the order of their float atomics
-    (relative L2 <= 1e-6 per group); run twice (the queues restart every
-    launch), for several views and for one."""
+    (relative L2 <= 1e-5 per group: float32 sums of up to a few hundred
+    terms per Gaussian in another order, two runs of the defaults differ as
+    much); run twice (the queues restart every
+    launch), for several views, for one, and for 8x8 tiles of three 1920x1080
+    views (129600 tiles: 32-bit tile keys)."""
+    tile = 16
     if case == "views":
         sc, cams = S.batch_scene(20_000, 4), small_views()
-    else:
+    elif case == "c1":
         sc, cams = S.make_scene(10_000, 0), [S.workload_camera("c1")]
+    else:
+        sc, tile = S.make_scene(40_000, 9), 8
+        cams = [S.identity_camera(1920, 1080, 1500.0, bg=(0.2, 0.3, 0.4))] * 3
     flag = L.FGS_FLAG_BLEND_QUEUE if option == "queue" else L.FGS_FLAG_SORT_LARGE_BLOCKS
     say("option", option, case)
     params = to_gpu(sc)
@@ -592,14 +599,17 @@ def test_schedule_and_blocking_options_match_the_defaults(case, option):
     dl = torch.randn(3 * npix, generator=torch.Generator().manual_seed(7)).mul_(1e-3).cuda()
     out = {}
     for sched, flags in (("default", 0), (option, flag)):
-        br = B.BatchRasterizer(cams, settings=B.default_settings(flags=flags))
+        br = B.BatchRasterizer(cams, settings=B.default_settings(flags=flags, tile=tile))
         for rep in range(2):
             imgs, tfs, lasts = (t.clone() for t in br.forward(params))
             torch.cuda.synchronize()
+            assert br.layout().inst_key_bytes == (4 if case == "wide" else 2)
             inst = sorted_instances(br)
             grads = {k: v.clone() for k, v in br.backward(params, dl).items()}
             torch.cuda.synchronize()
             out[(sched, rep)] = (imgs, tfs, lasts, grads, inst)
+    noise = max(rel_l2(out[("default", 1)][3][k], out[("default", 0)][3][k]) for k in B.PARAM_NAMES)
+    say(f"  two runs of the defaults: worst gradient rel L2 {noise:.2e}")
     for rep in range(2):
         gi, gt, gl, gg, ginst = out[("default", 0)]
         qi, qt, ql, qg, qinst = out[(option, rep)]
@@ -607,4 +617,4 @@ def test_schedule_and_blocking_options_match_the_defaults(case, option):
         assert torch.equal(qi, gi) and torch.equal(qt, gt) and torch.equal(ql, gl), rep
         worst = max(rel_l2(qg[k], gg[k]) for k in B.PARAM_NAMES)
         say(f"  rep {rep}: instances and images equal, worst gradient rel L2 {worst:.2e}")
-        assert worst <= 1e-6
+        assert worst <= 1e-5
