@@ -70,6 +70,16 @@ typedef enum fgs_dtype { FGS_F32 = 0, FGS_BF16 = 1 } fgs_dtype;
  *   fewer waves per SIMD).  Same results; a blocking choice for the
  *   autotuner (it pays off for many instances over wide digits). */
 #define FGS_FLAG_SORT_LARGE_BLOCKS 8u
+/* FGS_FLAG_KEEP_ACCUM_ZERO: for a caller that keeps its workspace for this
+ *   library alone between calls (it writes no byte of it and hands its memory
+ *   to no other use).  A backward pass whose chain rule reads the
+ *   accumulators (fgs_rasterize_backward_adam, and every backward over
+ *   several views) then clears each row and mark it reads, leaving accum and
+ *   marks all zero, and records that in counters[12..13]; the next backward
+ *   on the same layout skips their clear (n_views * n * 37 bytes).  Before
+ *   the first call on a new workspace, or after its memory served anything
+ *   else, zero counters[12..13] (or the whole workspace).  Same results. */
+#define FGS_FLAG_KEEP_ACCUM_ZERO 16u
 
 /* The Gaussian parameters of Sec. 2.1 ("3D Gaussian Splatting"): mean mu,
  * log-scales (scale = exp, "Activation Functions"), rotation quaternion
@@ -197,7 +207,10 @@ typedef struct fgs_forward_stats {
  *                           [7] bit 0: I exceeded the capacity, bit 1: the
  *                           depth keys need more than FGS_FORWARD_DEPTH_BITS,
  *                           [8] the Gaussians with a gradient (fused backward),
- *                           [10..11] {0, max - min visible depth key}
+ *                           [10..11] {0, max - min visible depth key},
+ *                           [12..13] FGS_FLAG_KEEP_ACCUM_ZERO: a marker and
+ *                           a tag of the layout while accum and marks are
+ *                           known to be zero (any other value: not known)
  * With several views, the per-Gaussian regions (rec, n_tiles, depth_key,
  * vis_*, accum) hold n_views * n entries, entry v * n + i for view v.
  *   vis_ids    uint32[n] x2 ping-pong (see counters[3])

@@ -22,6 +22,7 @@ def FGS_FORWARD_DEPTH_BITS(b: int) -> int:
     """Mode bits: with FGS_FORWARD_NO_SYNC, sort the depth keys' low b bits only."""
     return int(b) << 8
 FGS_FLAG_FP64_CONIC, FGS_FLAG_LOOKBACK_FALLBACK, FGS_FLAG_BLEND_QUEUE, FGS_FLAG_SORT_LARGE_BLOCKS = 1, 2, 4, 8
+FGS_FLAG_KEEP_ACCUM_ZERO = 16
 FGS_SORT_NOALLOC_MAX_PAIRS = 1 << 20
 FGS_SORT_NOALLOC_SCRATCH_BYTES = 17 << 19
 

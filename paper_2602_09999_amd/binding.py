@@ -470,14 +470,35 @@ def no_sync_mode(sync_stats: Dict[str, int]) -> int:
     return L.FGS_FORWARD_NO_SYNC | (L.FGS_FORWARD_DEPTH_BITS(bits) if 1 <= bits <= 31 else 0)
 
 
+def owned_workspace_settings(settings: Optional[L.Settings], keep_accum_zero: bool) -> L.Settings:
+    """A copy of ``settings`` (default: the library's) for a workspace the
+    caller owns: with FGS_FLAG_KEEP_ACCUM_ZERO set when ``keep_accum_zero``."""
+    st = default_settings() if settings is None else settings
+    st = default_settings(**{f: getattr(st, f) for f, _ in st._fields_})
+    if keep_accum_zero:
+        st.flags |= L.FGS_FLAG_KEEP_ACCUM_ZERO
+    return st
+
+
+def new_workspace(size: int, layout: L.Layout, device) -> torch.Tensor:
+    """An uninitialised workspace whose accumulator state reads "not known to
+    be zero" (counters[12..13] cleared)."""
+    ws = torch.empty(size, dtype=torch.uint8, device=device)
+    ws[layout.counters + 48:layout.counters + 56].zero_()
+    return ws
+
+
 class Rasterizer:
     """Owns a workspace for one camera and grows it when the instance count
-    exceeds its capacity.  forward() and backward() call the C ABI."""
+    exceeds its capacity.  forward() and backward() call the C ABI.  The
+    workspace is kept for the library alone, so by default the backward
+    leaves its accumulators zero for the next one (FGS_FLAG_KEEP_ACCUM_ZERO)
+    instead of clearing them at each call."""
 
     def __init__(self, camera, settings: Optional[L.Settings] = None, sh_degree: int = 3,
-                 device: Optional[torch.device] = None, headroom: float = 1.25):
+                 device: Optional[torch.device] = None, headroom: float = 1.25, keep_accum_zero: bool = True):
         self.camera = camera
-        self.settings = settings or default_settings()
+        self.settings = owned_workspace_settings(settings, keep_accum_zero)
         self.sh_degree = sh_degree
         self.device = device or torch.device("cuda", torch.cuda.current_device())
         self.headroom = headroom
@@ -491,7 +512,7 @@ class Rasterizer:
             return
         capacity = max(capacity, self.capacity if n == self.n else 0)
         size = workspace_size(n, self.camera, self.settings, capacity)
-        self.workspace = torch.empty(size, dtype=torch.uint8, device=self.device)
+        self.workspace = new_workspace(size, workspace_layout(n, self.camera, self.settings, capacity), self.device)
         self.capacity, self.n = capacity, n
 
     def layout(self) -> L.Layout:
@@ -573,16 +594,18 @@ class Rasterizer:
 class BatchRasterizer:
     """Several views (or timesteps) per call: owns the workspace and the
     concatenated outputs.  forward() returns per-view (image [3,H,W], t_final,
-    last) views of those buffers; backward() the gradients summed over views."""
+    last) views of those buffers; backward() the gradients summed over views.
+    As with Rasterizer, the accumulators are kept zero between backward passes
+    by default (FGS_FLAG_KEEP_ACCUM_ZERO)."""
 
     def __init__(self, cameras: Sequence, settings: Optional[L.Settings] = None,
                  times: Optional[Sequence[float]] = None, sh_degree: int = 3,
-                 device: Optional[torch.device] = None, headroom: float = 1.25):
+                 device: Optional[torch.device] = None, headroom: float = 1.25, keep_accum_zero: bool = True):
         if not 1 <= len(cameras) <= L.FGS_MAX_VIEWS:
             raise ValueError(f"1..{L.FGS_MAX_VIEWS} views")
         self.cameras = list(cameras)
         self.times = None if times is None else [float(t) for t in times]
-        self.settings = settings or default_settings()
+        self.settings = owned_workspace_settings(settings, keep_accum_zero)
         self.sh_degree = sh_degree
         self.device = device or torch.device("cuda", torch.cuda.current_device())
         self.headroom = headroom
@@ -600,7 +623,8 @@ class BatchRasterizer:
             return
         capacity = max(capacity, self.capacity if n == self.n else 0)
         size = batch_workspace_size(n, self.cameras, self.settings, capacity)
-        self.workspace = torch.empty(size, dtype=torch.uint8, device=self.device)
+        self.workspace = new_workspace(size, batch_workspace_layout(n, self.cameras, self.settings, capacity),
+                                       self.device)
         self.capacity, self.n = capacity, n
 
     def layout(self) -> L.Layout:

@@ -480,7 +480,8 @@ __device__ __forceinline__ void blend_bwd_tile(uint32_t gt, const uint2* __restr
 }
 
 // Grid: one wave per global tile (XCD-banded order); the first workgroup
-// also zeroes *reset_word when given.
+// also zeroes *reset_word when given, and *dirty_word (the accumulator is no
+// longer known to be zero).
 template <int TILE>
 __global__ __launch_bounds__(kWave) void k_blend_bwd(const uint2* __restrict__ ranges,
                                                      const uint32_t* __restrict__ vals,
@@ -489,8 +490,12 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd(const uint2* __restrict__ r
                                                      const uint32_t* __restrict__ lasts,
                                                      const float* __restrict__ dl_dimages,
                                                      float* __restrict__ accum, uint8_t* __restrict__ marks,
-                                                     uint32_t* __restrict__ reset_word) {
-  if (reset_word != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *reset_word = 0u;
+                                                     uint32_t* __restrict__ reset_word,
+                                                     uint32_t* __restrict__ dirty_word) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (reset_word != nullptr) *reset_word = 0u;
+    *dirty_word = 0u;
+  }
   blend_bwd_tile<TILE>(xcd_tile(blockIdx.x, gridDim.x), ranges, vals, rec, vs, st, images, lasts, dl_dimages,
                        accum, marks);
 }
@@ -505,8 +510,12 @@ __global__ __launch_bounds__(kWave) void k_blend_bwd_queue(const uint2* __restri
                                                            const float* __restrict__ dl_dimages,
                                                            float* __restrict__ accum, uint8_t* __restrict__ marks,
                                                            uint32_t* __restrict__ reset_word,
+                                                           uint32_t* __restrict__ dirty_word,
                                                            uint32_t* __restrict__ queues) {
-  if (reset_word != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *reset_word = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (reset_word != nullptr) *reset_word = 0u;
+    *dirty_word = 0u;
+  }
   const uint32_t xcd = blockIdx.x % kNumXcd;
   uint32_t start, count;
   xcd_band(xcd, vs.tile_base[vs.n_views], start, count);
@@ -518,10 +527,10 @@ template <int TILE>
 static hipError_t blend_backward_t(const uint2* ranges, const uint32_t* vals, const float4* rec, const ViewSet& vs,
                                    const SetDev& st, const float* images, const uint32_t* lasts,
                                    const float* dl_dimages, float* accum, uint8_t* marks, uint32_t* reset_word,
-                                   uint32_t* queues, uint32_t tiles, hipStream_t s) {
+                                   uint32_t* dirty_word, uint32_t* queues, uint32_t tiles, hipStream_t s) {
   if (queues == nullptr) {
     k_blend_bwd<TILE><<<tiles, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, marks,
-                                              reset_word);
+                                              reset_word, dirty_word);
     return hipGetLastError();
   }
   const uint32_t grid = queue_grid(k_blend_bwd_queue<TILE>, tiles);
@@ -529,24 +538,24 @@ static hipError_t blend_backward_t(const uint2* ranges, const uint32_t* vals, co
   hipError_t e = launch_fill_u32(queues, 0u, kQueueWords, s);
   if (e != hipSuccess) return e;
   k_blend_bwd_queue<TILE><<<grid, kWave, 0, s>>>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum,
-                                                 marks, reset_word, queues);
+                                                 marks, reset_word, dirty_word, queues);
   return hipGetLastError();
 }
 
 hipError_t launch_blend_backward(const uint2* ranges, const uint32_t* vals, const float4* rec, const ViewSet& vs,
                                  const SetDev& st, int tile, const float* images, const uint32_t* lasts,
                                  const float* dl_dimages, float* accum, uint8_t* marks, uint32_t* reset_word,
-                                 uint32_t n, uint32_t* queues, hipStream_t s) {
+                                 uint32_t* dirty_word, uint32_t n, uint32_t* queues, hipStream_t s) {
   const uint32_t tiles = vs.tile_base[vs.n_views];
   if (tiles == 0 || n == 0) return hipSuccess;
   if (tile == 8)
     return blend_backward_t<8>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, marks, reset_word,
-                               queues, tiles, s);
+                               dirty_word, queues, tiles, s);
   if (tile == 32)
     return blend_backward_t<32>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, marks, reset_word,
-                                queues, tiles, s);
-  return blend_backward_t<16>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, marks, reset_word, queues,
-                              tiles, s);
+                                dirty_word, queues, tiles, s);
+  return blend_backward_t<16>(ranges, vals, rec, vs, st, images, lasts, dl_dimages, accum, marks, reset_word,
+                              dirty_word, queues, tiles, s);
 }
 
 }  // namespace fgs

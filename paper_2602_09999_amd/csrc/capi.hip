@@ -105,7 +105,8 @@ fgs_status check_settings(const fgs_settings* st) {
   if (st->tile != 8 && st->tile != 16 && st->tile != 32)
     return fail(FGS_ERR_INVALID_ARGUMENT, "tile must be 8, 16 or 32 (got %d)", st->tile);
   if (st->flags &
-      ~(uint32_t)(FGS_FLAG_FP64_CONIC | FGS_FLAG_LOOKBACK_FALLBACK | FGS_FLAG_BLEND_QUEUE | FGS_FLAG_SORT_LARGE_BLOCKS))
+      ~(uint32_t)(FGS_FLAG_FP64_CONIC | FGS_FLAG_LOOKBACK_FALLBACK | FGS_FLAG_BLEND_QUEUE | FGS_FLAG_SORT_LARGE_BLOCKS |
+                  FGS_FLAG_KEEP_ACCUM_ZERO))
     return fail(FGS_ERR_INVALID_ARGUMENT, "unknown bits in settings.flags 0x%x", st->flags);
   // alpha_max < 1: the backward divides by 1 - alpha (App. B.1's front-to-back
   // gradient), which the cap keeps at least 1 - alpha_max away from zero
@@ -514,8 +515,23 @@ static fgs_status check_backward(const fgs_gaussians* g, const fgs_camera* cams,
   return FGS_OK;
 }
 
-// Clears the accumulators and runs the blend backward over all views'
-// tiles (per-(view, Gaussian) 2D gradients into accum[n_views n][9]).
+// The tag of a layout's accumulator state (the pair kStatAccumClean holds
+// {kAccumClean, tag} while accum and marks are known to be zero): the
+// accumulators' place and extent.
+static uint32_t accum_tag(const fgs_layout& L, uint64_t vn) {
+  uint64_t h = (uint64_t)L.total * 0x9e3779b97f4a7c15ull ^ (uint64_t)L.accum * 0xc2b2ae3d27d4eb4full ^
+               (uint64_t)L.marks * 0x165667b19e3779f9ull ^ vn;
+  h ^= h >> 29;
+  h *= 0xbf58476d1ce4e5b9ull;
+  return (uint32_t)(h ^ (h >> 32)) | 1u;
+}
+
+static bool keep_accum_zero(const fgs_settings* st) { return (st->flags & FGS_FLAG_KEEP_ACCUM_ZERO) != 0; }
+
+// Clears the accumulators (with FGS_FLAG_KEEP_ACCUM_ZERO: unless they are
+// known to be zero) and runs the blend backward over all views' tiles
+// (per-(view, Gaussian) 2D gradients into accum[n_views n][9]); the
+// accumulators are then no longer known to be zero.
 static fgs_status blend_backward(const fgs_gaussians* g, const ViewSet& vs, const fgs_settings* st, void* workspace,
                                  const fgs_layout& L, const float* images, const uint32_t* lasts,
                                  const float* dl_dimages, hipStream_t hs, uint32_t* reset_word = nullptr) {
@@ -526,13 +542,27 @@ static fgs_status blend_backward(const fgs_gaussians* g, const ViewSet& vs, cons
   uint32_t* ivals = at<uint32_t>(workspace, L.inst_vals[L.inst_final]);
   float* accum = at<float>(workspace, L.accum);
   uint8_t* marks = at<uint8_t>(workspace, L.marks);
-  // accum and the marks after it, one fill
+  uint32_t* clean = at<uint32_t>(workspace, L.counters) + kStatAccumClean;
+  // accum and the marks after it, one clear (skipped on the device when the
+  // last backward on this layout left them zero)
   const uint64_t clear_words = (L.marks - L.accum) / 4 + ((uint64_t)vn + 3) / 4;
-  FGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(accum), 0u, clear_words, hs), "accum clear");
+  if (keep_accum_zero(st))
+    FGS_HIP(launch_clear_unless(reinterpret_cast<uint32_t*>(accum), clear_words, clean, accum_tag(L, vn), hs),
+            "accum clear");
+  else
+    FGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(accum), 0u, clear_words, hs), "accum clear");
   FGS_TIMED("blend_backward", hs,
             launch_blend_backward(ranges, ivals, rec, vs, sd, st->tile, images, lasts, dl_dimages, accum, marks,
-                                  reset_word, vn, blend_queues(st, workspace, L), hs),
+                                  reset_word, clean, vn, blend_queues(st, workspace, L), hs),
             "blend bwd");
+  return FGS_OK;
+}
+
+// After a backward whose chain rule cleared every row and mark it read: the
+// accumulators are known to be zero again.
+static fgs_status note_accum_clean(void* workspace, const fgs_layout& L, uint64_t vn, hipStream_t hs) {
+  uint32_t* clean = at<uint32_t>(workspace, L.counters) + kStatAccumClean;
+  FGS_HIP(launch_fill_u32(clean, kAccumClean, 1, hs, clean + 1, accum_tag(L, vn)), "accum state");
   return FGS_OK;
 }
 
@@ -595,8 +625,9 @@ fgs_status fgs_rasterize_backward_batch(const fgs_gaussians* g, const fgs_camera
   } else {
     FGS_TIMED("preprocess_backward", hs,
               launch_preprocess_backward_views(gd, vs, at<float4>(workspace, L.rec), at<float>(workspace, L.accum),
-                                               at<uint8_t>(workspace, L.marks), gr, hs),
+                                               at<uint8_t>(workspace, L.marks), gr, keep_accum_zero(st), hs),
               "preprocess bwd (views)");
+    if (keep_accum_zero(st)) return note_accum_clean(workspace, L, (uint64_t)g->n * n_views, hs);
   }
   return FGS_OK;
 }
@@ -644,8 +675,13 @@ fgs_status fgs_rasterize_backward_adam(const fgs_gaussians* g, const fgs_camera*
   FGS_TIMED("touched_gradients", hs,
             launch_touched_gradients(gd, vs.cam[0], at<float4>(workspace, L.rec), at<float>(workspace, L.accum),
                                      at<uint8_t>(workspace, L.marks), touched, touch_count,
-                                     at<uint32_t>(workspace, L.touched_list), slot_of, sparse, hs),
+                                     at<uint32_t>(workspace, L.touched_list), slot_of, sparse, keep_accum_zero(st),
+                                     hs),
             "touched gradients");
+  if (keep_accum_zero(st)) {
+    s = note_accum_clean(workspace, L, (uint64_t)g->n, hs);
+    if (s != FGS_OK) return s;
+  }
   FGS_TIMED("adam_sparse", hs,
             launch_adam_sparse(params, opt->exp_avg, opt->exp_avg_sq, opt->lr, gd.sh_bf16 != 0, gd.n, touched,
                                slot_of, sparse, step, beta1, beta2, eps, hs),

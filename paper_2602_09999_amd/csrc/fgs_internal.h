@@ -525,6 +525,14 @@ inline uint64_t round_up64(uint64_t w) { return (w + 63) & ~uint64_t(63); }
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s, uint32_t* word = nullptr,
                            uint32_t word_v = 0u);
 
+// The backward's gradient accumulator and marks are known to be zero when
+// the counter pair [kStatAccumClean, +1] reads {kAccumClean, the layout's
+// tag}; the blend backward breaks the pair before it adds, and the backwards
+// that zero every row they read restore it at their end.
+constexpr uint32_t kAccumClean = 0x5a3c0f81u;
+// p[0..n) = 0 (p 16-byte aligned) unless flag[0..2) = {kAccumClean, tag}.
+hipError_t launch_clear_unless(uint32_t* p, uint64_t n, const uint32_t* flag, uint32_t tag, hipStream_t s);
+
 // Scratch words needed by scan_u32 for n items.
 size_t scan_scratch_words(uint64_t n);
 // Exclusive scan of in[0..n) into out (which may alias in); writes the grand
@@ -575,6 +583,7 @@ constexpr int kStatSortCount = 6;  // min(I, instance capacity): instances writt
 constexpr int kStatOverflow = 7;   // 1 when I exceeds the instance capacity
 constexpr int kStatTouched = 8;    // fused backward: Gaussians that received a gradient
 constexpr int kStatKeySpan = 10;   // {0, max - min key}: the range of the compacted depth keys (words 10-11)
+constexpr int kStatAccumClean = 12;  // {kAccumClean, layout tag} while accum and marks are all zero (words 12-13)
 // Z-order: scratch bytes for n Gaussians; perm[k] = index of the Gaussian at
 // position k of the Morton order of the means [3][n]; gather of `planes`
 // planes of n elements of 2 or 4 bytes: dst[p][k] = src[p][perm[k]].
@@ -630,29 +639,31 @@ hipError_t launch_blend_forward(const uint2* ranges, const uint32_t* vals, const
                                 uint32_t* queues, hipStream_t s);
 // Adds each fragment's nine gradient sums to its entry's accumulator row and
 // sets the entry's byte in `marks` when it adds a nonzero value; accum and
-// marks start at zero.  reset_word (optional) is set to 0 by the launch;
-// queues as in the forward.
+// marks start at zero.  reset_word (optional) and *dirty_word are set to 0
+// by the launch; queues as in the forward.
 hipError_t launch_blend_backward(const uint2* ranges, const uint32_t* vals, const float4* rec, const ViewSet& vs,
                                  const SetDev& st, int tile, const float* images, const uint32_t* lasts,
                                  const float* dl_dimages, float* accum, uint8_t* marks, uint32_t* reset_word,
-                                 uint32_t n, uint32_t* queues, hipStream_t s);
+                                 uint32_t* dirty_word, uint32_t n, uint32_t* queues, hipStream_t s);
 hipError_t launch_preprocess_backward(const GaussDev& g, const CamDev& cam, const float4* rec, const float* accum,
                                       const GradDev& gr, hipStream_t s);
 // Several views / timesteps: gradients summed over the views (accum is
 // [n_views n][9]); dynamic Gaussians also get dL/dvelocity and dL/daccel.
 // marks: the blend backward's byte per entry (nonzero: the entry's
-// accumulator row received a value); only marked entries are chained.
-hipError_t launch_preprocess_backward_views(const GaussDev& g, const ViewSet& vs, const float4* rec,
-                                            const float* accum, const uint8_t* marks, const GradDev& gr,
-                                            hipStream_t s);
+// accumulator row received a value); only marked entries are chained, and
+// with rezero their marks and rows are cleared (accum and marks are all zero
+// after).
+hipError_t launch_preprocess_backward_views(const GaussDev& g, const ViewSet& vs, const float4* rec, float* accum,
+                                            uint8_t* marks, const GradDev& gr, bool rezero, hipStream_t s);
 // Fused backward + Adam, first part: marks the Gaussians with a gradient in
 // `touched` (4 bits per byte), lists them (count in *counter, cleared here),
 // gives Gaussian list[s] slot s (slot_of) and writes its 59 raw-parameter
-// gradients to grads[p][s] (grads: float [59][n]).
+// gradients to grads[p][s] (grads: float [59][n]); with rezero the marks and
+// rows it reads are cleared (accum and marks are all zero after).
 // *counter must be 0 on entry (the blend backward's reset_word).
-hipError_t launch_touched_gradients(const GaussDev& g, const CamDev& cam, const float4* rec, const float* accum,
-                                    const uint8_t* marks, uint8_t* touched, uint32_t* counter, uint32_t* list,
-                                    uint32_t* slot_of, float* grads, hipStream_t s);
+hipError_t launch_touched_gradients(const GaussDev& g, const CamDev& cam, const float4* rec, float* accum,
+                                    uint8_t* marks, uint8_t* touched, uint32_t* counter, uint32_t* list,
+                                    uint32_t* slot_of, float* grads, bool rezero, hipStream_t s);
 // Second part: Adam on every parameter of the six groups (means, log_scales,
 // quats, logits, sh_dc, sh_rest; planes of length n), with the gradient of
 // the marked Gaussians from their slots and zero for all others.

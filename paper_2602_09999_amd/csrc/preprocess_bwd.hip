@@ -532,11 +532,11 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(GaussDev g, CamDev ca
 //   k_adam_sparse    one streaming Adam pass over every parameter, which
 //                    takes a marked Gaussian's gradient from its slot and
 //                    zero for all others (adam_loss.hip).
-__global__ __launch_bounds__(kBlock) void k_touched_list(const uint8_t* __restrict__ marks, uint32_t n,
+__global__ __launch_bounds__(kBlock) void k_touched_list(uint8_t* __restrict__ marks, uint32_t n,
                                                          uint8_t* __restrict__ touched,
                                                          uint32_t* __restrict__ counter,
                                                          uint32_t* __restrict__ list,
-                                                         uint32_t* __restrict__ slot_of) {
+                                                         uint32_t* __restrict__ slot_of, bool rezero) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t i0 = (blockIdx.x * kBlock + threadIdx.x) * 4u;
   if ((blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1u))) * 4u >= n) return;  // whole wave past the end
@@ -545,8 +545,11 @@ __global__ __launch_bounds__(kBlock) void k_touched_list(const uint8_t* __restri
     uint32_t m4 = 0;  // the four mark bytes (the region is 256-byte aligned, i0 a multiple of 4)
     if (i0 + 4 <= n) {
       m4 = *reinterpret_cast<const uint32_t*>(marks + i0);
+      if (rezero && m4) *reinterpret_cast<uint32_t*>(marks + i0) = 0u;  // read: cleared for the next backward
     } else {
       for (uint32_t j = 0; i0 + j < n; ++j) m4 |= (uint32_t)marks[i0 + j] << (8 * j);
+      if (rezero)
+        for (uint32_t j = 0; i0 + j < n; ++j) marks[i0 + j] = 0u;
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) mask |= ((m4 >> (8 * j)) & 0xffu) ? (1u << j) : 0u;
@@ -579,10 +582,10 @@ __global__ __launch_bounds__(kBlock) void k_touched_list(const uint8_t* __restri
 // list is done).  A bfloat16 SH gradient is rounded as a stored one would be.
 template <bool SHB>
 __global__ __launch_bounds__(kBlock) void k_touched_grads(GaussDev g, CamDev cam, const float4* __restrict__ rec,
-                                                          const float* __restrict__ accum,
+                                                          float* __restrict__ accum,
                                                           const uint32_t* __restrict__ counter,
                                                           const uint32_t* __restrict__ list,
-                                                          float* __restrict__ grads) {
+                                                          float* __restrict__ grads, bool rezero) {
   const size_t n = g.n;
   const uint32_t count = min(*counter, (uint32_t)n);
   for (uint32_t slot = blockIdx.x * kBlock + threadIdx.x; slot < count; slot += gridDim.x * kBlock) {
@@ -602,6 +605,10 @@ __global__ __launch_bounds__(kBlock) void k_touched_grads(GaussDev g, CamDev cam
     });
 #pragma unroll
     for (int p = 0; p < kParams; ++p) grads[(size_t)p * n + slot] = out[p];
+    if (rezero) {  // read: cleared for the next backward
+#pragma unroll
+      for (int q = 0; q < 9; ++q) accum[(size_t)i * 9 + q] = 0.0f;
+    }
   }
 }
 
@@ -623,8 +630,9 @@ __global__ __launch_bounds__(kBlock) void k_touched_grads(GaussDev g, CamDev cam
 template <bool SHB, bool C4>
 __global__ __launch_bounds__(kWave) void k_preprocess_bwd_views(GaussDev g, ViewSet vs,
                                                                 const float4* __restrict__ rec,
-                                                                const float* __restrict__ accum,
-                                                                const uint8_t* __restrict__ marks, GradDev gr) {
+                                                                float* __restrict__ accum,
+                                                                uint8_t* __restrict__ marks, GradDev gr,
+                                                                bool rezero) {
   constexpr int kSum = C4 ? kCond4Params : kParams;
   constexpr int kRow = C4 ? kSum : kSum + 6;  // + t dL/dmean(t) and t^2 dL/dmean(t) of a dynamic scene
   __shared__ float s_row[kWave][kRow + 1];
@@ -637,6 +645,9 @@ __global__ __launch_bounds__(kWave) void k_preprocess_bwd_views(GaussDev g, View
   uint32_t vmask = 0;
   if (i < n)
     for (uint32_t v = 0; v < vs.n_views; ++v) vmask |= marks[(size_t)v * n + i] ? (1u << v) : 0u;
+  // rezero: the marks and rows read here are cleared for the next backward
+  if (rezero)
+    for (uint32_t m = vmask; m != 0u; m &= m - 1u) marks[(size_t)__builtin_ctz(m) * n + i] = 0u;
   const uint32_t cnt = (uint32_t)__popc(vmask);
   const uint32_t incl = wave_inclusive_scan(cnt, lane);
   const uint32_t start = incl - cnt;
@@ -667,6 +678,10 @@ __global__ __launch_bounds__(kWave) void k_preprocess_bwd_views(GaussDev g, View
       float a[9];
 #pragma unroll
       for (int q = 0; q < 9; ++q) a[q] = accum[rj * 9 + q];
+      if (rezero) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) accum[rj * 9 + q] = 0.0f;
+      }
       const float t = vs.time[v], tt = t * t;
       if (C4) {
         gaussian_grads_cond4<SHB>(g, vs.cam[v], rec, a, gi, rj, t, [&](int p, float val) { row[p] = val; });
@@ -716,20 +731,19 @@ __global__ __launch_bounds__(kWave) void k_preprocess_bwd_views(GaussDev g, View
   }
 }
 
-hipError_t launch_preprocess_backward_views(const GaussDev& g, const ViewSet& vs, const float4* rec,
-                                            const float* accum, const uint8_t* marks, const GradDev& gr,
-                                            hipStream_t s) {
+hipError_t launch_preprocess_backward_views(const GaussDev& g, const ViewSet& vs, const float4* rec, float* accum,
+                                            uint8_t* marks, const GradDev& gr, bool rezero, hipStream_t s) {
   if (g.n == 0) return hipSuccess;
   const uint32_t grid = ceil_div(g.n, kWave);
   const bool c4 = g.quats_r != nullptr;
   if (g.sh_bf16 && c4)
-    k_preprocess_bwd_views<true, true><<<grid, kWave, 0, s>>>(g, vs, rec, accum, marks, gr);
+    k_preprocess_bwd_views<true, true><<<grid, kWave, 0, s>>>(g, vs, rec, accum, marks, gr, rezero);
   else if (g.sh_bf16)
-    k_preprocess_bwd_views<true, false><<<grid, kWave, 0, s>>>(g, vs, rec, accum, marks, gr);
+    k_preprocess_bwd_views<true, false><<<grid, kWave, 0, s>>>(g, vs, rec, accum, marks, gr, rezero);
   else if (c4)
-    k_preprocess_bwd_views<false, true><<<grid, kWave, 0, s>>>(g, vs, rec, accum, marks, gr);
+    k_preprocess_bwd_views<false, true><<<grid, kWave, 0, s>>>(g, vs, rec, accum, marks, gr, rezero);
   else
-    k_preprocess_bwd_views<false, false><<<grid, kWave, 0, s>>>(g, vs, rec, accum, marks, gr);
+    k_preprocess_bwd_views<false, false><<<grid, kWave, 0, s>>>(g, vs, rec, accum, marks, gr, rezero);
   return hipGetLastError();
 }
 
@@ -756,17 +770,18 @@ hipError_t launch_preprocess_backward(const GaussDev& g, const CamDev& cam, cons
   return hipGetLastError();
 }
 
-hipError_t launch_touched_gradients(const GaussDev& g, const CamDev& cam, const float4* rec, const float* accum,
-                                    const uint8_t* marks, uint8_t* touched, uint32_t* counter, uint32_t* list,
-                                    uint32_t* slot_of, float* grads, hipStream_t s) {
+hipError_t launch_touched_gradients(const GaussDev& g, const CamDev& cam, const float4* rec, float* accum,
+                                    uint8_t* marks, uint8_t* touched, uint32_t* counter, uint32_t* list,
+                                    uint32_t* slot_of, float* grads, bool rezero, hipStream_t s) {
   if (g.n == 0) return hipSuccess;
   if ((uintptr_t)marks % 4) return hipErrorInvalidValue;
-  k_touched_list<<<ceil_div(ceil_div(g.n, 4), kBlock), kBlock, 0, s>>>(marks, g.n, touched, counter, list, slot_of);
+  k_touched_list<<<ceil_div(ceil_div(g.n, 4), kBlock), kBlock, 0, s>>>(marks, g.n, touched, counter, list, slot_of,
+                                                                        rezero);
   const uint32_t grid = std::min<uint32_t>(ceil_div(g.n, kBlock), 2048u);
   if (g.sh_bf16)
-    k_touched_grads<true><<<grid, kBlock, 0, s>>>(g, cam, rec, accum, counter, list, grads);
+    k_touched_grads<true><<<grid, kBlock, 0, s>>>(g, cam, rec, accum, counter, list, grads, rezero);
   else
-    k_touched_grads<false><<<grid, kBlock, 0, s>>>(g, cam, rec, accum, counter, list, grads);
+    k_touched_grads<false><<<grid, kBlock, 0, s>>>(g, cam, rec, accum, counter, list, grads, rezero);
   return hipGetLastError();
 }
 

@@ -35,6 +35,29 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s, u
   return hipGetLastError();
 }
 
+// p[0..n) = 0 unless the pair flag[0..2) reads {kAccumClean, tag}: every
+// block checks the pair first, so a known-zero region costs one launch of a
+// few blocks.  A fixed grid of at most kClearBlocks blocks strides over the
+// region, 16 bytes per thread and step (p is 256-byte aligned).
+constexpr uint32_t kClearBlocks = 2048;
+__global__ __launch_bounds__(kBlock) void k_clear_unless(uint32_t* __restrict__ p, uint64_t n,
+                                                         const uint32_t* __restrict__ flag, uint32_t tag) {
+  if (flag[0] == kAccumClean && flag[1] == tag) return;  // uniform
+  const uint64_t n4 = n / 4, stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n4; i += stride)
+    reinterpret_cast<uint4*>(p)[i] = make_uint4(0u, 0u, 0u, 0u);
+  for (uint64_t i = n4 * 4 + (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
+hipError_t launch_clear_unless(uint32_t* p, uint64_t n, const uint32_t* flag, uint32_t tag, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if ((uintptr_t)p % 16) return hipErrorInvalidValue;
+  const uint64_t want = (n / 4 + kBlock - 1) / kBlock;
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, kClearBlocks));
+  k_clear_unless<<<grid, kBlock, 0, s>>>(p, n, flag, tag);
+  return hipGetLastError();
+}
+
 // Flat exclusive scan: a thread owns 4 consecutive items (one 16-byte access),
 // so a workgroup covers kFlatTile items with a single workgroup scan.  Up to
 // kFlatDirect blocks, each block of the down-sweep adds up the partial sums

@@ -114,9 +114,9 @@ def test_invalid_arguments_are_rejected_without_launching(lib):
     assert size.value > 3 * one.value // 2
     st7 = B.default_settings(tile=7)
     assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(st7), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
-    stf = B.default_settings(flags=16)  # only bits 0-3 are defined
+    stf = B.default_settings(flags=32)  # only bits 0-4 are defined
     assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(stf), 0, ctypes.byref(size)) == L.FGS_ERR_INVALID_ARGUMENT
-    for flags in (L.FGS_FLAG_FP64_CONIC, L.FGS_FLAG_LOOKBACK_FALLBACK, 3):
+    for flags in (L.FGS_FLAG_FP64_CONIC, L.FGS_FLAG_LOOKBACK_FALLBACK, 3, L.FGS_FLAG_KEEP_ACCUM_ZERO, 31):
         st1 = B.default_settings(flags=flags)
         assert lib.fgs_workspace_size(10, ctypes.byref(cam), ctypes.byref(st1), 0, ctypes.byref(size)) == L.FGS_OK
     stb = B.default_settings(alpha_min=0.995)

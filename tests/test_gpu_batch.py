@@ -618,3 +618,77 @@ def test_schedule_and_blocking_options_match_the_defaults(case, option):
         worst = max(rel_l2(qg[k], gg[k]) for k in B.PARAM_NAMES)
         say(f"  rep {rep}: instances and images equal, worst gradient rel L2 {worst:.2e}")
         assert worst <= 1e-5
+
+
+def accum_state(rz, vn):
+    """(accum and marks all zero, the counters' accumulator-state words)."""
+    acc = rz.view("accum", 9 * vn, dtype=torch.float32)
+    marks = rz.view("marks", vn, dtype=torch.uint8)
+    words = rz.view("counters", 14)[12:14].cpu().numpy().view(np.uint32)
+    return bool((acc == 0).all().item() and (marks == 0).all().item()), (int(words[0]), int(words[1]))
+
+
+ACCUM_CLEAN = 0x5A3C0F81
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("form", ["views", "dynamic", "cond4d", "fused"])
+def test_accumulators_kept_zero_between_backwards(form):
+    """FGS_FLAG_KEEP_ACCUM_ZERO (the binding's default for the workspaces it
+    owns): the chain rule clears every accumulator row and mark it reads and
+    the next backward skips the clear.  Three backward passes in a row (with
+    changing image gradients; fused: three training steps) equal those of a
+    rasterizer that clears at every call, up to the order of the float atomics
+    (relative L2 <= 1e-5); after each, accum and marks are all zero and the
+    state words read {marker, tag}; without the flag the state words stay
+    cleared.  The fused form compares Adam's first moment after one step
+    from fresh moments, (1 - beta1) times the gradient."""
+    if form == "fused":
+        sc, cams = S.make_scene(30_000, 3), [S.workload_camera("c1")]
+    else:
+        sc, cams = S.batch_scene(20_000, 4), small_views()
+    n = int(sc["opacity_logits"].shape[0])
+    times = None
+    if form == "dynamic":
+        sc.update(S.make_motion(n, 4))
+        times = S.timesteps(len(cams))
+    elif form == "cond4d":
+        sc.update(S.make_cond4d(sc, 4))
+        times = S.timesteps(len(cams))
+    say("keep accum zero", form, n, "Gaussians", len(cams), "views")
+    npix = sum(B.view_pixels(cams))
+    dls = [torch.randn(3 * npix, generator=torch.Generator().manual_seed(s)).mul_(1e-3).cuda() for s in (1, 2, 1)]
+    vn = n * len(cams)
+    out = {}
+    for keep in (False, True):
+        params = to_gpu(sc)
+        if form == "fused":
+            rz = B.Rasterizer(cams[0], keep_accum_zero=keep)
+            res = []
+            for call, dl in enumerate(dls):
+                params = to_gpu(sc)
+                opt = FusedAdam(params, S.ADAM_LR)
+                image, _, last = rz.forward(params)
+                rz.backward_adam(params, image, last, dl.view_as(image), opt)
+                torch.cuda.synchronize()
+                res.append({k: v.clone() for k, v in opt.exp_avg.items()})
+                zero, words = accum_state(rz, vn)
+                say(f"  keep={keep} step {call}: accum and marks zero {zero}, state words {words[0]:#x}")
+                assert (zero and words[0] == ACCUM_CLEAN) if keep else words == (0, 0)
+        else:
+            br = B.BatchRasterizer(cams, times=times, keep_accum_zero=keep)
+            br.forward(params)
+            res = []
+            for call, dl in enumerate(dls):
+                res.append({k: v.clone() for k, v in br.backward(params, dl).items()})
+                torch.cuda.synchronize()
+                zero, words = accum_state(br, vn)
+                say(f"  keep={keep} backward {call}: accum and marks zero {zero}, state words {words[0]:#x}")
+                assert (zero and words[0] == ACCUM_CLEAN) if keep else words == (0, 0)
+        out[keep] = res
+    for call in range(3):
+        worst = max(rel_l2(out[True][call][k], out[False][call][k]) for k in out[True][call])
+        say(f"  call {call}: worst rel L2 against clearing at every call {worst:.2e}")
+        assert worst <= 1e-5
+    # the same image gradient twice: the same gradients
+    assert max(rel_l2(out[True][2][k], out[True][0][k]) for k in out[True][0]) <= 1e-5

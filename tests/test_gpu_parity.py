@@ -358,16 +358,20 @@ def test_full_size_sampled_parity(name, sh):
     assert not rz.overflowed() and rz.lookback_slow_count() == 0
     assert torch.equal(img2, image) and torch.equal(tf2, t_final) and torch.equal(last2, last)
     # the fused path lists the Gaussians the blend backward marked: exactly
-    # those whose accumulator row is nonzero
+    # those whose accumulator row is nonzero (counted after the separate
+    # backward, which leaves the rows in place; the fused one, kept for the
+    # library alone, clears every row it reads)
     dl = S.make_dl_dimage(w.height, w.width, seed=4).cuda()
+    rz.backward(params, img2, last2, dl)
+    rows = rz.view("accum", 9 * w.n, dtype=torch.float32).view(w.n, 9)
+    n_rows = int(rows.ne(0).any(1).sum().item())
     opt = FusedAdam(params, S.ADAM_LR)
     rz.backward_adam(params, img2, last2, dl, opt)
     torch.cuda.synchronize()
-    rows = rz.view("accum", 9 * w.n, dtype=torch.float32).view(w.n, 9)
-    n_rows = int(rows.ne(0).any(1).sum().item())
     n_listed = int(rz.view("counters", 16)[8].item())
-    say("  Gaussians with a gradient", n_listed)
+    say("  Gaussians with a gradient", n_listed, "nonzero rows", n_rows)
     assert n_listed == n_rows > 0
+    assert int(rows.ne(0).sum().item()) == 0
 
 
 FUSED_CASES = {"c1": ("c1", None), "c3_centre": ("c3", "centre"), "c3_edge": ("c3", "edge")}
