@@ -11,7 +11,8 @@
  *    per thread, the last error message (fgs_last_error) and the armed
  *    timing hook (fgs_time_next_launch); per device, the static scratch
  *    array of fgs_sort_pairs_noalloc and its looked-up address.  Nothing
- *    else survives a call outside the caller's buffers.
+ *    else survives a call outside the caller's buffers (in the workspace,
+ *    with FGS_FLAG_KEEP_ACCUM_ZERO: whether its accumulators are zero).
  *  - Work is enqueued asynchronously on `stream` (a hipStream_t, NULL = the
  *    default stream).  fgs_rasterize_forward alone synchronises `stream` once
  *    to read the instance count (see there).
