@@ -247,7 +247,11 @@ __device__ __forceinline__ int group_first_plane(int g) {
 
 __global__ __launch_bounds__(kBlock) void k_adam_sparse(SparseAdamArgs a, const uint8_t* __restrict__ touched,
                                                         const uint32_t* __restrict__ slot_of,
-                                                        const float* __restrict__ grads) {
+                                                        const float* __restrict__ grads,
+                                                        uint32_t* __restrict__ state_word, uint32_t state_tag) {
+  // the chain rule before this launch left the accumulators zero: record it
+  if (state_word != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+    *reinterpret_cast<uint2*>(state_word) = make_uint2(kAccumClean, state_tag);
   const int plane = blockIdx.y;
   const int gi = plane_group(plane);
   const size_t n = a.n;
@@ -311,8 +315,9 @@ __global__ __launch_bounds__(kBlock) void k_adam_sparse(SparseAdamArgs a, const 
 hipError_t launch_adam_sparse(void* const params[6], float* const exp_avg[6], float* const exp_avg_sq[6],
                               const float lr[6], bool sh_bf16, uint64_t n, const uint8_t* touched,
                               const uint32_t* slot_of, const float* grads, int64_t step, double beta1, double beta2,
-                              double eps, hipStream_t s) {
+                              double eps, uint32_t* state_word, uint32_t state_tag, hipStream_t s) {
   if (n == 0) return hipSuccess;
+  if ((uintptr_t)state_word % 8) return hipErrorInvalidValue;
   SparseAdamArgs a = {};
   double bc1 = 1.0;
   a.c = adam_coef(step, beta1, beta2, eps, &bc1);
@@ -330,7 +335,7 @@ hipError_t launch_adam_sparse(void* const params[6], float* const exp_avg[6], fl
   }
   a.vec = vec ? 1 : 0;
   const dim3 grid(ceil_div(ceil_div(n, 4), kBlock), 59);
-  k_adam_sparse<<<grid, kBlock, 0, s>>>(a, touched, slot_of, grads);
+  k_adam_sparse<<<grid, kBlock, 0, s>>>(a, touched, slot_of, grads, state_word, state_tag);
   return hipGetLastError();
 }
 

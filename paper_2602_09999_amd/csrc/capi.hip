@@ -678,13 +678,12 @@ fgs_status fgs_rasterize_backward_adam(const fgs_gaussians* g, const fgs_camera*
                                      at<uint32_t>(workspace, L.touched_list), slot_of, sparse, keep_accum_zero(st),
                                      hs),
             "touched gradients");
-  if (keep_accum_zero(st)) {
-    s = note_accum_clean(workspace, L, (uint64_t)g->n, hs);
-    if (s != FGS_OK) return s;
-  }
+  // with FGS_FLAG_KEEP_ACCUM_ZERO the Adam launch also records that the
+  // accumulators are zero again
+  uint32_t* clean = keep_accum_zero(st) ? at<uint32_t>(workspace, L.counters) + kStatAccumClean : nullptr;
   FGS_TIMED("adam_sparse", hs,
             launch_adam_sparse(params, opt->exp_avg, opt->exp_avg_sq, opt->lr, gd.sh_bf16 != 0, gd.n, touched,
-                               slot_of, sparse, step, beta1, beta2, eps, hs),
+                               slot_of, sparse, step, beta1, beta2, eps, clean, accum_tag(L, (uint64_t)g->n), hs),
             "adam (sparse gradients)");
   return FGS_OK;
 }

@@ -666,11 +666,13 @@ hipError_t launch_touched_gradients(const GaussDev& g, const CamDev& cam, const 
                                     uint32_t* slot_of, float* grads, bool rezero, hipStream_t s);
 // Second part: Adam on every parameter of the six groups (means, log_scales,
 // quats, logits, sh_dc, sh_rest; planes of length n), with the gradient of
-// the marked Gaussians from their slots and zero for all others.
+// the marked Gaussians from their slots and zero for all others.  With
+// state_word (8-byte aligned), the pair {kAccumClean, state_tag} is written
+// there (the accumulator state after a chain rule that cleared what it read).
 hipError_t launch_adam_sparse(void* const params[6], float* const exp_avg[6], float* const exp_avg_sq[6],
                               const float lr[6], bool sh_bf16, uint64_t n, const uint8_t* touched,
                               const uint32_t* slot_of, const float* grads, int64_t step, double beta1, double beta2,
-                              double eps, hipStream_t s);
+                              double eps, uint32_t* state_word, uint32_t state_tag, hipStream_t s);
 // step >= 1: host step count; step == 0: advance the device step counter in
 // dev_state (256 bytes, first an int64 t) and use it.
 hipError_t launch_adam(const fgs_adam_group* groups, int n_groups, int64_t step, double beta1, double beta2,
