@@ -692,3 +692,35 @@ def test_accumulators_kept_zero_between_backwards(form):
         assert worst <= 1e-5
     # the same image gradient twice: the same gradients
     assert max(rel_l2(out[True][2][k], out[True][0][k]) for k in out[True][0]) <= 1e-5
+
+
+@pytest.mark.gpu
+def test_accumulators_state_survives_a_workspace_regrow():
+    """A forward whose instances outgrow the capacity allocates a new workspace,
+    whose accumulator state words start cleared: the backward after it clears
+    the new accumulators and matches a rasterizer that clears at every call."""
+    sc, cams = S.batch_scene(20_000, 4), small_views()
+    npix = sum(B.view_pixels(cams))
+    dl = torch.randn(3 * npix, generator=torch.Generator().manual_seed(3)).mul_(1e-3).cuda()
+    big = dict(sc, log_scales=sc["log_scales"] + 0.7)  # larger splats: more instances
+    out = {}
+    for keep in (True, False):
+        br = B.BatchRasterizer(cams, keep_accum_zero=keep, headroom=1.0)
+        br.ensure(20_000, 1024)  # a small workspace: the first forward regrows it too
+        params = to_gpu(sc)
+        br.forward(params)
+        br.backward(params, dl)
+        ws0, cap0 = br.workspace.data_ptr(), br.capacity
+        params = to_gpu(big)
+        br.forward(params)
+        grown = br.capacity > cap0
+        out[keep] = {k: v.clone() for k, v in br.backward(params, dl).items()}
+        torch.cuda.synchronize()
+        if keep:
+            zero, words = accum_state(br, 20_000 * len(cams))
+            say(f"  capacity {cap0} -> {br.capacity} (new workspace {br.workspace.data_ptr() != ws0}); "
+                f"accum zero {zero}, state {words[0]:#x}")
+            assert grown and zero and words[0] == ACCUM_CLEAN
+    worst = max(rel_l2(out[True][k], out[False][k]) for k in out[True])
+    say(f"  worst rel L2 against clearing at every call {worst:.2e}")
+    assert worst <= 1e-5
