@@ -81,12 +81,19 @@ template <bool SHB>
 __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, ViewSet vs, SetDev st, int tile,
                                                        float4* __restrict__ rec, uint32_t* __restrict__ n_tiles,
                                                        uint4* __restrict__ partials,
-                                                       uint32_t* __restrict__ depth_key) {
+                                                       uint32_t* __restrict__ depth_key, uint32_t chunks) {
 #pragma clang fp contract(off)
   __shared__ WalkLds s_walk[kBlock / kWave];
-  const uint32_t view = blockIdx.y;
+  // Workgroup b takes chunk (b mod 8) + 8 (b div 8 n_views) of the Gaussians
+  // in view (b div 8) mod n_views: workgroups are dealt to the eight XCDs in
+  // turn, so the views of one chunk run on one XCD one after another and
+  // read its parameters from that XCD's L2 (one view: chunk b).
+  const uint32_t b = blockIdx.x, nv = vs.n_views;
+  const uint32_t view = (b / kNumXcd) % nv;
+  const uint32_t chunk = b % kNumXcd + kNumXcd * (b / (kNumXcd * nv));
+  if (chunk >= chunks) return;  // the last group's missing chunks (uniform)
   const CamDev& cam = vs.cam[view];
-  const uint32_t i0 = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t i0 = chunk * kBlock + threadIdx.x;
   const bool in_range = i0 < g.n;
   const uint32_t i = in_range ? i0 : g.n - 1;  // lanes past the end mirror the last Gaussian, then drop it
   const size_t n = g.n;
@@ -259,18 +266,20 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(GaussDev g, ViewSet vs, S
       const uint4 u = s_part[w];
       t = make_uint4(t.x + u.x, t.y + u.y, min(t.z, u.z), max(t.w, u.w));
     }
-    partials[(size_t)view * gridDim.x + blockIdx.x] = t;
+    partials[(size_t)view * chunks + chunk] = t;
   }
 }
 
 hipError_t launch_preprocess(const GaussDev& g, const ViewSet& vs, const SetDev& st, int tile, float4* rec,
                              uint32_t* n_tiles, uint32_t* depth_key, uint4* partials, hipStream_t s) {
   if (g.n == 0 || vs.n_views == 0) return hipSuccess;
-  const dim3 grid(ceil_div(g.n, kBlock), vs.n_views);
+  // chunks of kBlock Gaussians; groups of kNumXcd chunks times the views
+  const uint32_t chunks = ceil_div(g.n, kBlock);
+  const uint32_t grid = ceil_div(chunks, kNumXcd) * kNumXcd * vs.n_views;
   if (g.sh_bf16)
-    k_preprocess<true><<<grid, kBlock, 0, s>>>(g, vs, st, tile, rec, n_tiles, partials, depth_key);
+    k_preprocess<true><<<grid, kBlock, 0, s>>>(g, vs, st, tile, rec, n_tiles, partials, depth_key, chunks);
   else
-    k_preprocess<false><<<grid, kBlock, 0, s>>>(g, vs, st, tile, rec, n_tiles, partials, depth_key);
+    k_preprocess<false><<<grid, kBlock, 0, s>>>(g, vs, st, tile, rec, n_tiles, partials, depth_key, chunks);
   return hipGetLastError();
 }
 
