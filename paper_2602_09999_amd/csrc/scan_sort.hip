@@ -170,6 +170,15 @@ __device__ __forceinline__ bool pass_is_constant(const uint32_t* __restrict__ d_
   return d_range != nullptr && ((d_range[0] ^ d_range[1]) >> shift) == 0u;
 }
 
+// The chunk of the pairs that workgroup blockIdx.x of a pass takes: the
+// workgroups below the number of chunks holding pairs share those chunks out
+// in one contiguous band per XCD (xcd_tile); the others, past the count, keep
+// their own index (its histogram column is zero, its scatter does nothing).
+__device__ __forceinline__ uint32_t radix_chunk(uint32_t count, uint32_t tile) {
+  const uint32_t used = (uint32_t)(((uint64_t)count + tile - 1) / tile);
+  return blockIdx.x < used ? xcd_tile(blockIdx.x, used) : blockIdx.x;
+}
+
 // fourth word of a raw buffer descriptor on gfx9-family GPUs (32-bit data format)
 constexpr int kBufferWord3 = 0x00020000;
 
@@ -203,7 +212,8 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const KT* __restrict__ ke
   for (int i = threadIdx.x; i < kSub * R; i += kBlock) (&h[0][0])[i] = 0;
   __syncthreads();
   const uint32_t count = d_count ? min(*d_count, n) : n;
-  const uint32_t base = blockIdx.x * (uint32_t)(kBlock * ITEMS);
+  const uint32_t blk = radix_chunk(count, (uint32_t)(kBlock * ITEMS));  // see k_radix_scatter
+  const uint32_t base = blk * (uint32_t)(kBlock * ITEMS);
   uint32_t* hw = h[(threadIdx.x / kWave) * kSplit + (threadIdx.x & (kSplit - 1))];
 #pragma unroll
   for (int k = 0; k < ITEMS / V; ++k) {
@@ -222,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const KT* __restrict__ ke
     uint32_t t = 0;
 #pragma unroll
     for (int w = 0; w < kSub; ++w) t += h[w][d];
-    hist[(size_t)d * nb + blockIdx.x] = t;
+    hist[(size_t)d * nb + blk] = t;
   }
 }
 
@@ -269,7 +279,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT* __restrict__
   __shared__ uint32_t s_val[kTile];
   __shared__ uint32_t scan_lds[kBlock / kWave];
   const uint32_t count = d_count ? min(*d_count, n) : n;
-  const uint32_t base = blockIdx.x * kTile;
+  // Chunk blk of the pairs: each XCD takes a contiguous band of the chunks
+  // that hold pairs (workgroups are dealt to the XCDs in turn), so the runs
+  // that consecutive chunks write for one digit, which meet inside cache
+  // lines, are merged in one L2 instead of leaving partial lines from two.
+  const uint32_t blk = radix_chunk(count, kTile);
+  const uint32_t base = blk * kTile;
   if (base >= count) return;  // uniform for the whole workgroup
   const uint32_t in_block = min(kTile, count - base);
   // uniform: the pass keeps the order.  Constant passes come last (a digit
@@ -309,7 +324,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT* __restrict__
   // global start of this block's run of digit t: with per-digit scans, the
   // digit start (scan of the totals) + the blocks before this one; with a flat
   // scan of the digit-major histogram (totals == NULL), the entry itself
-  uint32_t gbase = digit_thread ? hist_scan[(size_t)threadIdx.x * nb + blockIdx.x] : 0u;
+  uint32_t gbase = digit_thread ? hist_scan[(size_t)threadIdx.x * nb + blk] : 0u;
   if (totals) {  // uniform
     uint32_t tot;
     const uint32_t dstart = block_exclusive_scan(digit_thread ? totals[threadIdx.x] : 0u, scan_lds, &tot);
