@@ -724,3 +724,24 @@ def test_accumulators_state_survives_a_workspace_regrow():
     worst = max(rel_l2(out[True][k], out[False][k]) for k in out[True])
     say(f"  worst rel L2 against clearing at every call {worst:.2e}")
     assert worst <= 1e-5
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n", [3, 200])
+def test_forward_without_synchronisation_few_pairs_in_a_large_capacity(n):
+    """The radix passes band the chunks that hold pairs (read on the device)
+    over the XCDs and leave the grid's other workgroups on their own empty
+    chunks: a sync-free forward whose few instances fill fewer chunks than
+    there are XCDs, in a workspace sized for far more, equals the synchronised
+    forward bit for bit."""
+    sc, cam = S.make_scene(n, 5), S.workload_camera("c1")
+    params = to_gpu(sc)
+    rz = B.Rasterizer(cam)
+    rz._ensure(n, 200_000)  # 49 sort chunks of 4096 pairs
+    img, tf, last = (t.clone() for t in rz.forward(params))
+    need = rz.last_stats["n_instances"]
+    img2, tf2, last2 = rz.forward(params, sync=False)
+    torch.cuda.synchronize()
+    say(f"  {n} Gaussians: {need} instances in a capacity of {rz.capacity}")
+    assert need < 8 * 4096 and not rz.overflowed()
+    assert torch.equal(img2, img) and torch.equal(tf2, tf) and torch.equal(last2, last)
