@@ -658,8 +658,8 @@ hipError_t launch_duplicate(const uint32_t* const vis_ids[2], const uint32_t* wh
 }
 
 // Start and end of each tile's run in the sorted keys; a run boundary is where
-// a key differs from its neighbour.  Each thread takes V consecutive keys (32
-// bytes, two 16-byte loads; the key buffer is 256-byte aligned); the keys
+// a key differs from its neighbour.  Each thread takes V consecutive keys (64
+// bytes, four 16-byte loads; the key buffer is 256-byte aligned); the keys
 // just before and after its V come from the neighbouring lanes by shuffle,
 // and only the wave's first and last lane read them from memory.
 template <typename KT>
@@ -667,7 +667,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_ranges(const KT* __restrict__ k
                                                         const uint32_t* __restrict__ d_count, uint32_t tiles,
                                                         uint2* __restrict__ ranges) {
   constexpr int H = 16 / (int)sizeof(KT);  // keys per 16-byte load
-  constexpr int V = 2 * H;
+  constexpr int kLoads = 4;
+  constexpr int V = kLoads * H;
   constexpr uint32_t kNone = 0xffffffffu;  // differs from every key
   const uint32_t count = d_count ? min(*d_count, n) : n;
   const int lane = threadIdx.x & (kWave - 1);
@@ -676,13 +677,13 @@ __global__ __launch_bounds__(kBlock) void k_tile_ranges(const KT* __restrict__ k
   uint32_t k[V];
   if (i0 + V <= count) {
     struct alignas(16) Vec { KT k[H]; };
-    const Vec a = reinterpret_cast<const Vec*>(keys + i0)[0];
-    const Vec b = reinterpret_cast<const Vec*>(keys + i0)[1];
+    Vec a[kLoads];
 #pragma unroll
-    for (int j = 0; j < H; ++j) {
-      k[j] = a.k[j];
-      k[H + j] = b.k[j];
-    }
+    for (int l = 0; l < kLoads; ++l) a[l] = reinterpret_cast<const Vec*>(keys + i0)[l];
+#pragma unroll
+    for (int l = 0; l < kLoads; ++l)
+#pragma unroll
+      for (int j = 0; j < H; ++j) k[l * H + j] = a[l].k[j];
   } else {
 #pragma unroll
     for (int j = 0; j < V; ++j) k[j] = (i0 + j < count) ? (uint32_t)keys[i0 + j] : kNone;
@@ -706,12 +707,12 @@ __global__ __launch_bounds__(kBlock) void k_tile_ranges(const KT* __restrict__ k
 hipError_t launch_tile_ranges(const void* keys, int key_bytes, uint32_t n, const uint32_t* d_count, uint32_t tiles,
                               uint2* ranges, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  // 32 bytes of keys per thread
+  // 64 bytes of keys per thread
   if (key_bytes == 2)
-    k_tile_ranges<uint16_t><<<ceil_div(ceil_div(n, 16), kBlock), kBlock, 0, s>>>(
+    k_tile_ranges<uint16_t><<<ceil_div(ceil_div(n, 32), kBlock), kBlock, 0, s>>>(
         static_cast<const uint16_t*>(keys), n, d_count, tiles, ranges);
   else
-    k_tile_ranges<uint32_t><<<ceil_div(ceil_div(n, 8), kBlock), kBlock, 0, s>>>(
+    k_tile_ranges<uint32_t><<<ceil_div(ceil_div(n, 16), kBlock), kBlock, 0, s>>>(
         static_cast<const uint32_t*>(keys), n, d_count, tiles, ranges);
   return hipGetLastError();
 }
