@@ -69,7 +69,7 @@ typedef enum fgs_dtype { FGS_F32 = 0, FGS_BF16 = 1 } fgs_dtype;
 /* FGS_FLAG_SORT_LARGE_BLOCKS: the tile sort ranks and scatters blocks of
  *   8192 pairs instead of 4096 (longer digit runs per block to write out,
  *   fewer waves per SIMD).  Same results; a blocking choice for the
- *   autotuner (it pays off for many instances over wide digits). */
+ *   autotuner, which times both on the workload. */
 #define FGS_FLAG_SORT_LARGE_BLOCKS 8u
 /* FGS_FLAG_KEEP_ACCUM_ZERO: for a caller that keeps its workspace for this
  *   library alone between calls (it writes no byte of it and hands its memory
