@@ -173,7 +173,8 @@ __device__ __forceinline__ bool pass_is_constant(const uint32_t* __restrict__ d_
 // The chunk of the pairs that workgroup blockIdx.x of a pass takes: the
 // workgroups below the number of chunks holding pairs share those chunks out
 // in one contiguous band per XCD (xcd_tile); the others, past the count, keep
-// their own index (its histogram column is zero, its scatter does nothing).
+// their own index (the histogram zeroes those columns, the scatter does
+// nothing for them).
 __device__ __forceinline__ uint32_t radix_chunk(uint32_t count, uint32_t tile) {
   const uint32_t used = (uint32_t)(((uint64_t)count + tile - 1) / tile);
   return blockIdx.x < used ? xcd_tile(blockIdx.x, used) : blockIdx.x;
@@ -202,6 +203,17 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const KT* __restrict__ ke
   // a pass that runs notes the buffer its scatter writes: the last one to run
   // leaves the buffer holding the result
   if (final_word != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *final_word = final_if_run;
+  const uint32_t count = d_count ? min(*d_count, n) : n;
+  const uint32_t used = (uint32_t)(((uint64_t)count + kBlock * ITEMS - 1) / (kBlock * ITEMS));
+  if (blockIdx.x >= used) {
+    // the chunks past the count (a grid sized by a capacity) have zero
+    // columns: these workgroups zero the entries (d, used .. nb) together,
+    // row by row, so that consecutive threads write consecutive words
+    const uint32_t m = nb - used;
+    const uint64_t idx = (uint64_t)(blockIdx.x - used) * kBlock + threadIdx.x;
+    if (idx < (uint64_t)R * m) hist[(size_t)(idx / m) * nb + used + (uint32_t)(idx % m)] = 0u;
+    return;  // uniform for the whole workgroup
+  }
   // kSplit histograms per wave (lane l adds to histogram l mod kSplit), so
   // that fewer lanes of one instruction add to the same counter.  With few
   // digits the collisions cost most and the extra counters least (measured at
@@ -211,7 +223,6 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const KT* __restrict__ ke
   __shared__ uint32_t h[kSub][R];
   for (int i = threadIdx.x; i < kSub * R; i += kBlock) (&h[0][0])[i] = 0;
   __syncthreads();
-  const uint32_t count = d_count ? min(*d_count, n) : n;
   const uint32_t blk = radix_chunk(count, (uint32_t)(kBlock * ITEMS));  // see k_radix_scatter
   const uint32_t base = blk * (uint32_t)(kBlock * ITEMS);
   uint32_t* hw = h[(threadIdx.x / kWave) * kSplit + (threadIdx.x & (kSplit - 1))];
